@@ -1,0 +1,134 @@
+/*
+ * hd.h -- certified one-sided Pompeiu-Hausdorff bounds between triangle soups
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes an interval [L, U] with L <= h(A,B) <= U and
+ * U - L <= eps * dA, where h(A,B) = max over p in A of the distance from p to
+ * B, and dA is the length of the diagonal of the bounding box of A's
+ * (referenced) vertices. This is the problem statement and output contract
+ * of Sacht & Jacobson, "Cascading upper bounds for triangle soup
+ * Pompeiu-Hausdorff distance" (Method section: eq. hausdorff_distance and
+ * eq. output_bounds). The method is that paper's branch and bound with its
+ * exact same-triangle bound and four cascading upper bounds, run as
+ * breadth-first rounds of data-parallel HIP kernels.
+ *
+ * Conventions for every entry point:
+ *  - Mesh arrays are DEVICE pointers owned by the caller: V is m x 3 doubles,
+ *    row-major; F is n x 3 int32, 0-based. They must stay valid and unmodified
+ *    until the stream passes the call. The library never frees caller memory.
+ *  - Vertices that no face references are ignored (Limitations subsection: an
+ *    unreferenced vertex would make the lower bound wrong).
+ *  - Work is enqueued on the given stream; entry points that return numbers
+ *    to the host synchronise that stream before returning.
+ *  - Errors are returned as hd_status; no C++ exception crosses the ABI. On
+ *    any error LU_out receives {NaN, NaN}.
+ */
+#ifndef HD_H
+#define HD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hd_stream_t; /* hipStream_t; NULL = default stream */
+
+typedef enum {
+    HD_OK = 0,
+    HD_E_INVALID = 1,  /* bad argument: eps <= 0, empty mesh, index out of range, non-finite coordinate */
+    HD_E_CAPACITY = 2, /* face budget m * nA exceeded, or frontier workspace / subdivision depth exhausted */
+    HD_E_NOMEM = 3,    /* device allocation failed */
+    HD_E_DEVICE = 4,   /* a HIP runtime call failed */
+    HD_E_INTERNAL = 5  /* an invariant failed (e.g. the frontier emptied while the tolerance did not hold) */
+} hd_status;
+
+/* Arithmetic of the branch-and-bound rounds. The final [L, U] is always
+ * evaluated in FP64. */
+enum { HD_PREC_FP64 = 0, HD_PREC_FP32 = 1, HD_PREC_FP32_RECHECK = 2 };
+
+typedef struct hd_bvh_s *hd_bvh; /* opaque; owns library-allocated device memory */
+
+typedef struct {
+    int32_t precision;   /* HD_PREC_*; default HD_PREC_FP32_RECHECK */
+    int32_t order;       /* cascade order as decimal digits, e.g. 1234 (default) or 2314;
+                            any non-empty subset of {1,2,3,4} without repeats */
+    double budget_m;     /* the paper's m: at most m * nA faces may be processed (Implementation
+                            section); <= 0 means 1e7 */
+    int64_t capacity;    /* frontier capacity in triangles; 0 = automatic */
+    int32_t max_rounds;  /* 0 = unlimited */
+    int32_t stack_depth; /* traversal stack entries per lane (test hook); 0 = default */
+    int32_t subbatch;    /* > 0: subdivide at most this many triangles per round, highest
+                            upper bound first (approximates the paper's best-first queue) */
+    int32_t reserved;
+} hd_options;
+
+typedef struct {
+    int32_t rounds;            /* rounds after round 0 */
+    int32_t status;            /* hd_status of the call */
+    int64_t nodes_bounded;     /* frontier triangles whose upper bound was computed */
+    int64_t subdivided;        /* triangles split 1 -> 4 */
+    int64_t queries;           /* point -> B distance queries */
+    int64_t pt_tri_evals;      /* point-triangle closest-point evaluations (traversal leaves
+                                  and the third bound's fixed-triangle evaluations) */
+    int64_t box_tests;         /* BVH box tests */
+    int64_t discards[5];       /* triangles discarded by uexact, u1, u2, u3, u4 */
+    int64_t rechecked64;       /* triangles re-bounded in FP64 inside the ambiguity band */
+    int64_t parked_final;      /* triangles left within eps of L at the end */
+    int64_t max_frontier;      /* peak live frontier size */
+    int64_t stack_overflows;   /* traversals that fell back to the deep-stack path */
+    double dA, eps_abs;        /* bbox diagonal of A and eps * dA */
+    double L_rounds, U_rounds; /* interval reached by the rounds, before the FP64 final step */
+    double mu_coef_d, mu_coef_0; /* FP32 margin: mu(d) = mu_coef_d * d + mu_coef_0 */
+    double ms_total;           /* wall time of the hd_bound call */
+} hd_stats;
+
+/* Build the LBVH over soup B (device-built: Morton codes of triangle
+ * centroids, radix sort, Karras hierarchy, outward-rounded refit) together
+ * with per-triangle frames used by the closest-point evaluation. The paper
+ * builds an AABB tree over B before any query (Implementation section).
+ * Returns HD_E_INVALID for nB <= 0, mB <= 0, an out-of-range index or a
+ * non-finite coordinate. The handle is usable once the stream reaches it. */
+hd_status hd_build_bvh(const double *VB, int64_t mB, const int32_t *FB, int64_t nB,
+                       hd_stream_t stream, hd_bvh *out);
+
+/* Release a handle from hd_build_bvh (NULL is allowed). */
+void hd_free_bvh(hd_bvh bvh);
+
+/* Certified [L, U] for h(A, B), B given by its BVH; eps is the paper's
+ * relative tolerance (eq. output_bounds), so U - L <= eps * dA on success.
+ * opt may be NULL (defaults). LU_out is a HOST array of 2 doubles; stats is a
+ * host struct or NULL. The stream is synchronised before return. */
+hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, hd_bvh B,
+                   double eps, const hd_options *opt, hd_stream_t stream, double LU_out[2],
+                   hd_stats *stats);
+
+/* Distances from nP points P (device, nP x 3 doubles) to B: d (device, nP
+ * doubles), closest face of B as its original index (device, nP int32) and
+ * closest points (device, nP x 3 doubles; may be NULL). precision selects
+ * FP64 or FP32 arithmetic (HD_PREC_FP32 and HD_PREC_FP32_RECHECK both mean
+ * FP32 here). This is the per-vertex query of the Implementation section,
+ * exposed for testing and reuse. */
+hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh B, int32_t precision,
+                             double *d, int32_t *I, double *Q, hd_stream_t stream);
+
+/* All five bounds of n given triangles against B, for testing the bound
+ * kernels in isolation ("Upper bounds" subsection). Device arrays: v (n x 9
+ * doubles: three vertices), d (n x 3 vertex distances), I (n x 3 closest faces
+ * of B, original indices), q (n x 9 closest points). out (device, n x 5
+ * doubles) receives uexact (NaN unless the three faces coincide), u1, u2, u3,
+ * u4 without rounding margins; u3_case (device, n int32) receives 1 or 2.
+ * precision is HD_PREC_FP64 or HD_PREC_FP32. */
+hd_status hd_eval_bounds(const double *v, const double *d, const int32_t *I, const double *q, int64_t n,
+                         hd_bvh B, int32_t precision, double *out, int32_t *u3_case, hd_stream_t stream);
+
+/* Human-readable name of a status code (static string). */
+const char *hd_status_str(hd_status s);
+
+/* Default options (precision FP32 + FP64 recheck, order 1234, m = 1e7). */
+void hd_default_options(hd_options *opt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HD_H */

@@ -1,0 +1,193 @@
+"""Certified one-sided Pompeiu-Hausdorff bounds between triangle soups on
+AMD Instinct MI355X.
+
+Thin ctypes binding over the C ABI in include/hd.h (libhd.so, built by
+build.py). Every step of the computation runs in the library's HIP kernels;
+this module only marshals torch tensors (device memory) and the current
+stream. There is no CPU fallback: without the built library on a GPU, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+__all__ = ["HDError", "Bvh", "Options", "build_bvh", "bound", "point_distances", "eval_bounds",
+           "load_library", "PREC_FP64", "PREC_FP32", "PREC_FP32_RECHECK"]
+
+PREC_FP64, PREC_FP32, PREC_FP32_RECHECK = 0, 1, 2
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhd.so")
+_lib = None
+
+STATUS = {0: "HD_OK", 1: "HD_E_INVALID", 2: "HD_E_CAPACITY", 3: "HD_E_NOMEM", 4: "HD_E_DEVICE",
+          5: "HD_E_INTERNAL"}
+
+
+class HDError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("order", C.c_int32), ("budget_m", C.c_double),
+                ("capacity", C.c_int64), ("max_rounds", C.c_int32), ("stack_depth", C.c_int32),
+                ("subbatch", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("status", C.c_int32), ("nodes_bounded", C.c_int64),
+                ("subdivided", C.c_int64), ("queries", C.c_int64), ("pt_tri_evals", C.c_int64),
+                ("box_tests", C.c_int64), ("discards", C.c_int64 * 5), ("rechecked64", C.c_int64),
+                ("parked_final", C.c_int64), ("max_frontier", C.c_int64),
+                ("stack_overflows", C.c_int64), ("dA", C.c_double), ("eps_abs", C.c_double),
+                ("L_rounds", C.c_double), ("U_rounds", C.c_double), ("mu_coef_d", C.c_double),
+                ("mu_coef_0", C.c_double), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["discards"] = list(self.discards)
+        return d
+
+
+EXPORTS = ["hd_build_bvh", "hd_free_bvh", "hd_bound", "hd_point_distances", "hd_eval_bounds",
+           "hd_status_str", "hd_default_options"]
+
+
+def load_library(path: str | None = None):
+    """Load libhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or _LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2406_10357_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    lib.hd_build_bvh.restype = i32
+    lib.hd_build_bvh.argtypes = [vp, i64, vp, i64, vp, C.POINTER(vp)]
+    lib.hd_free_bvh.restype = None
+    lib.hd_free_bvh.argtypes = [vp]
+    lib.hd_bound.restype = i32
+    lib.hd_bound.argtypes = [vp, i64, vp, i64, vp, dbl, C.POINTER(Options), vp, C.POINTER(C.c_double),
+                             C.POINTER(Stats)]
+    lib.hd_point_distances.restype = i32
+    lib.hd_point_distances.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp]
+    lib.hd_eval_bounds.restype = i32
+    lib.hd_eval_bounds.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp]
+    lib.hd_status_str.restype = C.c_char_p
+    lib.hd_status_str.argtypes = [i32]
+    lib.hd_default_options.restype = None
+    lib.hd_default_options.argtypes = [C.POINTER(Options)]
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(x, dtype):
+    """A contiguous CUDA tensor of the given dtype (copied if needed)."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(x)
+    if not x.is_cuda:
+        x = x.to("cuda")
+    return x.to(dtype).contiguous()
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(st, where):
+    if st != 0:
+        raise HDError(st, where)
+
+
+class Bvh:
+    """LBVH over soup B (device memory owned by the library)."""
+
+    def __init__(self, handle, VB, FB):
+        self.handle = handle
+        self.VB, self.FB = VB, FB  # kept alive with the handle
+        self.nB = FB.shape[0]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hd_free_bvh(self.handle)
+            self.handle = None
+
+
+def build_bvh(VB, FB) -> Bvh:
+    torch = _torch()
+    lib = load_library()
+    VB = _dev(VB, torch.float64)
+    FB = _dev(FB, torch.int32)
+    h = C.c_void_p()
+    st = lib.hd_build_bvh(C.c_void_p(VB.data_ptr()), VB.shape[0], C.c_void_p(FB.data_ptr()), FB.shape[0],
+                          _stream(), C.byref(h))
+    _check(st, "hd_build_bvh")
+    return Bvh(h, VB, FB)
+
+
+def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
+                 stack_depth=0, subbatch=0) -> Options:
+    o = Options()
+    load_library().hd_default_options(C.byref(o))
+    o.precision, o.order, o.budget_m = precision, order, budget_m
+    o.capacity, o.max_rounds, o.stack_depth, o.subbatch = capacity, max_rounds, stack_depth, subbatch
+    return o
+
+
+def bound(VA, FA, bvh: Bvh, eps: float, **opts):
+    """Certified (L, U, stats) with L <= h(A,B) <= U and U - L <= eps * dA."""
+    torch = _torch()
+    lib = load_library()
+    VA = _dev(VA, torch.float64)
+    FA = _dev(FA, torch.int32)
+    o = make_options(**opts)
+    LU = (C.c_double * 2)()
+    stats = Stats()
+    st = lib.hd_bound(C.c_void_p(VA.data_ptr()), VA.shape[0], C.c_void_p(FA.data_ptr()), FA.shape[0],
+                      bvh.handle, float(eps), C.byref(o), _stream(), LU, C.byref(stats))
+    _check(st, "hd_bound")
+    return LU[0], LU[1], stats.as_dict()
+
+
+def point_distances(P, bvh: Bvh, precision=PREC_FP64):
+    """(d, I, Q) of points P against B: distance, original face index, closest point."""
+    torch = _torch()
+    lib = load_library()
+    P = _dev(P, torch.float64)
+    n = P.shape[0]
+    d = torch.empty(n, dtype=torch.float64, device=P.device)
+    I = torch.empty(n, dtype=torch.int32, device=P.device)
+    Q = torch.empty((n, 3), dtype=torch.float64, device=P.device)
+    st = lib.hd_point_distances(C.c_void_p(P.data_ptr()), n, bvh.handle, precision, C.c_void_p(d.data_ptr()),
+                                C.c_void_p(I.data_ptr()), C.c_void_p(Q.data_ptr()), _stream())
+    _check(st, "hd_point_distances")
+    return d, I, Q
+
+
+def eval_bounds(v, d, I, q, bvh: Bvh, precision=PREC_FP64):
+    """All five bounds (uexact or NaN, u1..u4) of n triangles, and u3's case."""
+    torch = _torch()
+    lib = load_library()
+    v = _dev(v, torch.float64).reshape(-1, 9)
+    n = v.shape[0]
+    d = _dev(d, torch.float64).reshape(n, 3)
+    I = _dev(I, torch.int32).reshape(n, 3)
+    q = _dev(q, torch.float64).reshape(n, 9)
+    out = torch.empty((n, 5), dtype=torch.float64, device=v.device)
+    case = torch.empty(n, dtype=torch.int32, device=v.device)
+    st = lib.hd_eval_bounds(C.c_void_p(v.data_ptr()), C.c_void_p(d.data_ptr()), C.c_void_p(I.data_ptr()),
+                            C.c_void_p(q.data_ptr()), n, bvh.handle, precision, C.c_void_p(out.data_ptr()),
+                            C.c_void_p(case.data_ptr()), _stream())
+    _check(st, "hd_eval_bounds")
+    return out, case

@@ -1,0 +1,323 @@
+// hd_geom.hpp -- device geometry: the per-triangle frame record of soup B,
+// point-to-triangle distance in that frame, and the paper's upper bounds
+// (exact same-triangle bound and u1..u4 of the "Upper bounds" subsection).
+//
+// Frame record. Every triangle S of B is stored as its longest edge AB
+// (length Lb) along an orthonormal in-plane axis ex, a second in-plane axis
+// ey pointing towards the third vertex C, and C's in-plane coordinates
+// (cx, cy), cy >= 0, 0 <= cx <= Lb. The frame is computed once in FP64 when
+// the BVH is built. A point p is then mapped to (x, y, z) in that frame and
+// its distance to S is sqrt(z^2 + d2D^2), d2D being the planar distance from
+// (x, y) to the planar triangle (0,0),(Lb,0),(cx,cy): zero if inside, else
+// the nearest of the three edges. Each step is a short dot product or a
+// clamped segment projection, so the rounding error is a few units of
+// roundoff times (distance + triangle size + coordinate size), independently
+// of how thin the triangle is.
+#pragma once
+#include "hd_math.hpp"
+
+namespace hd {
+
+template <class T> struct Frame {
+    V3<T> A, ex, ey;
+    T Lb, cx, cy, inv2bc, inv2ca, R;
+};
+
+// device layout: float -> 4 x float4 (64 B); double -> 8 x double2 (128 B)
+HD_D Frame<float> load_frame(const float4 *__restrict__ F, int64_t i) {
+    float4 a = F[4 * i], b = F[4 * i + 1], c = F[4 * i + 2], d = F[4 * i + 3];
+    Frame<float> f;
+    f.A = {a.x, a.y, a.z};
+    f.Lb = a.w;
+    f.ex = {b.x, b.y, b.z};
+    f.cx = b.w;
+    f.ey = {c.x, c.y, c.z};
+    f.cy = c.w;
+    f.inv2bc = d.x;
+    f.inv2ca = d.y;
+    f.R = d.z;
+    return f;
+}
+HD_D Frame<double> load_frame(const double2 *__restrict__ F, int64_t i) {
+    const double2 *p = F + 8 * i;
+    double2 a = p[0], b = p[1], c = p[2], d = p[3], e = p[4], g = p[5], h = p[6], k = p[7];
+    Frame<double> f;
+    f.A = {a.x, a.y, b.x};
+    f.Lb = b.y;
+    f.ex = {c.x, c.y, d.x};
+    f.cx = d.y;
+    f.ey = {e.x, e.y, g.x};
+    f.cy = g.y;
+    f.inv2bc = h.x;
+    f.inv2ca = h.y;
+    f.R = k.x;
+    return f;
+}
+
+template <class T> HD_HD V3<T> frame_vertex(const Frame<T> &f, int k) {
+    if (k == 0) return f.A;
+    if (k == 1) return f.A + f.Lb * f.ex;
+    return f.A + f.cx * f.ex + f.cy * f.ey;
+}
+
+// Squared distance from p to the frame triangle; optionally the closest
+// point. Branch-free apart from the final selection.
+template <class T, bool WANT_Q>
+HD_D T frame_dist2(const Frame<T> &f, const V3<T> &p, V3<T> *q) {
+    V3<T> r = p - f.A;
+    T x = dot(r, f.ex);
+    T y = dot(r, f.ey);
+    V3<T> n = cross(f.ex, f.ey);
+    T z = dot(r, n);
+    T xb = x - f.Lb;
+    T bcx = f.cx - f.Lb;
+    // planar edge functions of the counter-clockwise triangle (0,0),(Lb,0),(cx,cy)
+    T eBC = bcx * y - f.cy * xb;
+    T eCA = f.cy * x - f.cx * y;
+    bool inside = (y >= T(0)) & (eBC >= T(0)) & (eCA >= T(0)) & (f.cy > T(0));
+    // edge AB lies on the x axis from 0 to Lb
+    T Xab = clampab(x, T(0), f.Lb);
+    T dxa = x - Xab;
+    T dAB = dxa * dxa + y * y;
+    // edge CA from (0,0) to (cx,cy)
+    T tca = clamp01((x * f.cx + y * f.cy) * f.inv2ca);
+    T dxc = x - tca * f.cx, dyc = y - tca * f.cy;
+    T dCA = dxc * dxc + dyc * dyc;
+    // edge BC from (Lb,0) to (cx,cy)
+    T tbc = clamp01((xb * bcx + y * f.cy) * f.inv2bc);
+    T dxq = xb - tbc * bcx, dyq = y - tbc * f.cy;
+    T dBC = dxq * dxq + dyq * dyq;
+    T d2 = hmin(dAB, hmin(dCA, dBC));
+    d2 = inside ? T(0) : d2;
+    if constexpr (WANT_Q) {
+        T X, Y;
+        if (inside) {
+            X = x;
+            Y = y;
+        } else if (dAB <= dCA && dAB <= dBC) {
+            X = Xab;
+            Y = T(0);
+        } else if (dCA <= dBC) {
+            X = tca * f.cx;
+            Y = tca * f.cy;
+        } else {
+            X = f.Lb + tbc * bcx;
+            Y = tbc * f.cy;
+        }
+        *q = f.A + X * f.ex + Y * f.ey;
+    }
+    return z * z + d2;
+}
+
+// Distance of the point x to the triangle s (sorted index) of B.
+template <class T> struct BView;
+template <> struct BView<float> {
+    const float4 *frames;
+};
+template <> struct BView<double> {
+    const double2 *frames;
+};
+
+template <class T> HD_D T dist_to(const BView<T> &b, int s, const V3<T> &x) {
+    Frame<T> f = load_frame(b.frames, s);
+    return hsqrt(frame_dist2<T, false>(f, x, nullptr));
+}
+
+// ---------------------------------------------------------------------------
+// The bounds. A frontier triangle T has vertices v[i], distances d[i] to B,
+// closest triangles S_i = I[i] (sorted index into B) and closest points q[i].
+// All bounds below are computed without rounding margins; callers add them.
+// ---------------------------------------------------------------------------
+
+template <class T> struct Tri {
+    V3<T> v[3];
+    T d[3];
+    int I[3];
+    V3<T> q[3];
+};
+
+// eq. u1: the best vertex plus the longer of its two incident edges
+template <class T> HD_D T bound_u1(const Tri<T> &t) {
+    T e12 = hsqrt(norm2(t.v[0] - t.v[1]));
+    T e23 = hsqrt(norm2(t.v[1] - t.v[2]));
+    T e31 = hsqrt(norm2(t.v[2] - t.v[0]));
+    T b1 = hmax(e12, e31) + t.d[0];
+    T b2 = hmax(e12, e23) + t.d[1];
+    T b3 = hmax(e23, e31) + t.d[2];
+    return hmin(b1, hmin(b2, b3));
+}
+
+// g of eq. u2: circumradius if the triangle is acute (the paper's s - r > 2R
+// test is the classical acute criterion), half the longest edge otherwise.
+// Near-right triangles are sent to the circumradius branch, which is never
+// smaller (R >= longest edge / 2 for every triangle). The area comes from the
+// two shorter edges, which meet at the largest angle (>= 60 degrees), so it
+// is accurate whenever R is used.
+template <class T> HD_D T u2_g(const Tri<T> &t) {
+    V3<T> e[3] = {t.v[1] - t.v[0], t.v[2] - t.v[1], t.v[0] - t.v[2]};
+    T l2[3] = {norm2(e[0]), norm2(e[1]), norm2(e[2])};
+    int k = 0;
+    if (l2[1] > l2[k]) k = 1;
+    if (l2[2] > l2[k]) k = 2;
+    int a = (k + 1) % 3, b = (k + 2) % 3;
+    T lmax = hsqrt(l2[k]);
+    const T slack = T(1) + T(8 * Prec<T>::u);
+    if (l2[k] < (l2[a] + l2[b]) * slack) {
+        V3<T> c = cross(e[a], e[b]);
+        T twice_area = hsqrt(norm2(c));
+        if (twice_area > T(0)) {
+            T R = hsqrt(l2[0]) * hsqrt(l2[1]) * hsqrt(l2[2]) / (T(2) * twice_area);
+            return hmax(R, T(0.5) * lmax);
+        }
+    }
+    return T(0.5) * lmax;
+}
+
+template <class T> HD_D T bound_u2(const Tri<T> &t) {
+    return u2_g(t) + hmax(t.d[0], hmax(t.d[1], t.d[2]));
+}
+
+// unit vector in the plane of triangle s (positions P[3] with vertex ids
+// id[3]) perpendicular to the edge (a,b), pointing to the third vertex
+template <class T>
+HD_D bool inplane_dir(const V3<T> P[3], const int id[3], int ia, int ib, V3<T> &out) {
+    int ka = -1, kb = -1, kc = -1;
+    for (int k = 0; k < 3; ++k) {
+        if (id[k] == ia && ka < 0) ka = k;
+        else if (id[k] == ib && kb < 0) kb = k;
+        else kc = k;
+    }
+    if (ka < 0 || kb < 0 || kc < 0) return false;
+    V3<T> e = P[kb] - P[ka];
+    V3<T> w = P[kc] - P[ka];
+    T ee = norm2(e);
+    if (!(ee > T(0))) return false;
+    V3<T> tt = w - (dot(w, e) / ee) * e;
+    T tn = hsqrt(norm2(tt));
+    if (!(tn > T(0))) return false;
+    out = (T(1) / tn) * tt;
+    return true;
+}
+
+struct IdView {
+    const int4 *ids; // per sorted triangle: vertex ids of frame corners A, B, C; original face id
+};
+
+// eq. Kang2018_case1 / eq. Kang2018_case2. *evals counts closest-point
+// evaluations.
+template <class T>
+HD_D T bound_u3(const Tri<T> &t, const BView<T> &bv, const IdView &iv, int *which_case, int *evals) {
+    int odd = -1;
+    if (t.I[0] != t.I[1] && t.I[1] == t.I[2]) odd = 0;
+    else if (t.I[1] != t.I[0] && t.I[0] == t.I[2]) odd = 1;
+    else if (t.I[2] != t.I[0] && t.I[0] == t.I[1]) odd = 2;
+    if (odd >= 0) {
+        int S1 = t.I[odd], S2 = t.I[(odd + 1) % 3];
+        int4 i1 = iv.ids[S1], i2 = iv.ids[S2];
+        int a1[3] = {i1.x, i1.y, i1.z}, a2[3] = {i2.x, i2.y, i2.z};
+        int common[3], nc = 0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                if (a1[i] == a2[j]) {
+                    bool dup = false;
+                    for (int k = 0; k < nc; ++k) dup |= common[k] == a1[i];
+                    if (!dup && nc < 3) common[nc++] = a1[i];
+                }
+        if (nc >= 2) {
+            if (which_case) *which_case = 1;
+            Frame<T> f1 = load_frame(bv.frames, S1), f2 = load_frame(bv.frames, S2);
+            V3<T> P1[3] = {frame_vertex(f1, 0), frame_vertex(f1, 1), frame_vertex(f1, 2)};
+            V3<T> P2[3] = {frame_vertex(f2, 0), frame_vertex(f2, 1), frame_vertex(f2, 2)};
+            int i1a = odd, i2a = (odd + 1) % 3, i3a = (odd + 2) % 3;
+            V3<T> v1 = t.v[i1a], v2 = t.v[i2a], v3 = t.v[i3a];
+            V3<T> b1 = T(0.5) * (v1 + v2), b2 = T(0.5) * (v1 + v3);
+            V3<T> t1, t2;
+            if (inplane_dir(P1, a1, common[0], common[1], t1) &&
+                inplane_dir(P2, a2, common[0], common[1], t2)) {
+                V3<T> nu = t1 - t2;
+                if (norm2(nu) > T(0)) {
+                    // a point of the shared edge: the corner of S1 with id common[0]
+                    V3<T> ea = P1[0];
+                    for (int k = 0; k < 3; ++k)
+                        if (a1[k] == common[0]) ea = P1[k];
+                    T f1v = dot(v1 - ea, nu), f2v = dot(v2 - ea, nu), f3v = dot(v3 - ea, nu);
+                    if (f1v != f2v && f1v != f3v) {
+                        T s12 = f1v / (f1v - f2v), s13 = f1v / (f1v - f3v);
+                        if (s12 >= T(0) && s12 <= T(1) && s13 >= T(0) && s13 <= T(1)) {
+                            b1 = v1 + s12 * (v2 - v1);
+                            b2 = v1 + s13 * (v3 - v1);
+                        }
+                    }
+                }
+            }
+            T hR = hmax(t.d[i1a], hmax(hsqrt(frame_dist2<T, false>(f1, b1, nullptr)),
+                                       hsqrt(frame_dist2<T, false>(f1, b2, nullptr))));
+            T hQ = hmax(hmax(t.d[i2a], t.d[i3a]),
+                        hmax(hsqrt(frame_dist2<T, false>(f2, b1, nullptr)),
+                             hsqrt(frame_dist2<T, false>(f2, b2, nullptr))));
+            if (evals) *evals += 4;
+            return hmax(hR, hQ);
+        }
+    }
+    if (which_case) *which_case = 2;
+    V3<T> m1 = T(0.5) * (t.v[0] + t.v[1]);
+    V3<T> m2 = T(0.5) * (t.v[1] + t.v[2]);
+    V3<T> m3 = T(0.5) * (t.v[2] + t.v[0]);
+    V3<T> b = T(1.0 / 3.0) * (t.v[0] + t.v[1] + t.v[2]);
+    Frame<T> f[3] = {load_frame(bv.frames, t.I[0]), load_frame(bv.frames, t.I[1]),
+                     load_frame(bv.frames, t.I[2])};
+    // Q1 = (v1,m1,b,m3) to S1, Q2 = (v2,m2,b,m1) to S2, Q3 = (v3,m3,b,m2) to S3
+    const V3<T> *corner[3][3] = {{&m1, &b, &m3}, {&m2, &b, &m1}, {&m3, &b, &m2}};
+    T part = T(0);
+    for (int i = 0; i < 3; ++i) {
+        T h = t.d[i];
+        for (int k = 0; k < 3; ++k) h = hmax(h, hsqrt(frame_dist2<T, false>(f[i], *corner[i][k], nullptr)));
+        part = hmax(part, h);
+    }
+    // h(T, S_i): largest distance of the three vertices to S_i
+    T best = part;
+    for (int i = 0; i < 3; ++i) {
+        T h = t.d[i];
+        for (int j = 0; j < 3; ++j)
+            if (j != i) h = hmax(h, hsqrt(frame_dist2<T, false>(f[i], t.v[j], nullptr)));
+        best = hmin(best, h);
+    }
+    if (evals) *evals += 15;
+    return best;
+}
+
+// h(T, {x, y}): maximum over the vertices of T and the crossings of T's
+// edges with the bisector plane of x and y (eq. bound_u4 discussion).
+template <class T> HD_D T h_two_points(const Tri<T> &t, const V3<T> &x, const V3<T> &y) {
+    T h = T(0);
+    for (int j = 0; j < 3; ++j)
+        h = hmax(h, hmin(norm2(t.v[j] - x), norm2(t.v[j] - y)));
+    V3<T> w = y - x;
+    if (norm2(w) > T(0)) {
+        V3<T> m = T(0.5) * (x + y);
+        T f[3];
+        for (int j = 0; j < 3; ++j) f[j] = dot(t.v[j] - m, w);
+        for (int j = 0; j < 3; ++j) {
+            int k = (j + 1) % 3;
+            if (f[j] * f[k] < T(0)) {
+                T s = f[j] / (f[j] - f[k]);
+                V3<T> p = t.v[j] + s * (t.v[k] - t.v[j]);
+                h = hmax(h, norm2(p - x));
+            }
+        }
+    }
+    return hsqrt(h);
+}
+
+// eq. bound_u4: q2, q3 are the footpoints of the shortest edge's endpoints
+// (first edge among v1v2, v2v3, v3v1 on ties), q1 that of the other vertex
+template <class T> HD_D T bound_u4(const Tri<T> &t) {
+    T e[3] = {norm2(t.v[0] - t.v[1]), norm2(t.v[1] - t.v[2]), norm2(t.v[2] - t.v[0])};
+    int s = 0;
+    if (e[1] < e[s]) s = 1;
+    if (e[2] < e[s]) s = 2;
+    int a = s, b = (s + 1) % 3, c = (s + 2) % 3;
+    return hmin(h_two_points(t, t.q[c], t.q[a]), h_two_points(t, t.q[c], t.q[b]));
+}
+
+} // namespace hd

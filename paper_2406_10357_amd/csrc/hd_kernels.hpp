@@ -1,0 +1,291 @@
+// hd_kernels.hpp -- device pieces of the branch-and-bound rounds: BVH
+// traversal for point queries, the frontier record layout, the cascade
+// with its rounding margins, and the FP64 re-bound of a frontier triangle.
+#pragma once
+#include "hd_geom.hpp"
+#include "hd_internal.hpp"
+
+namespace hd {
+
+// ---------------------------------------------------------------------------
+// Frontier records (structure of arrays; one slot per triangle).
+// A frontier triangle is a piece of an original face `face` of A, obtained by
+// `lvl` rounds of 1->4 midpoint subdivision. Its vertex i sits at the exact
+// dyadic barycentric position V0 + (ba[i] * E1 + bb[i] * E2) / 2^lvl of that
+// face (E1 = V1 - V0, E2 = V2 - V0), so positions never accumulate rounding.
+// ---------------------------------------------------------------------------
+template <class T> struct FrontierView {
+    T *v[9];   // vertex i coordinate k at v[3*i+k]
+    T *q[9];   // closest point on B of vertex i
+    T *d[3];   // distance of vertex i to B (computed value)
+    int *I[3]; // closest triangle of vertex i (sorted index into B)
+    float *ub; // upper bound, margin included, rounded up
+    int *face;
+    int *lvl;
+    int *ba[3];
+    int *bb[3];
+};
+
+// A's vertices (centred FP64) and faces.
+struct AView {
+    const double *V; // mA x 3, original coordinates
+    const int32_t *F;
+    double cx, cy, cz; // centre subtracted from every coordinate
+};
+
+HD_D V3<double> a_vertex(const AView &a, int32_t v) {
+    return {a.V[3 * (int64_t)v] - a.cx, a.V[3 * (int64_t)v + 1] - a.cy, a.V[3 * (int64_t)v + 2] - a.cz};
+}
+
+// exact dyadic point of face f
+HD_D V3<double> a_point(const AView &a, int32_t f, int lvl, int ba, int bb) {
+    V3<double> V0 = a_vertex(a, a.F[3 * (int64_t)f]);
+    V3<double> V1 = a_vertex(a, a.F[3 * (int64_t)f + 1]);
+    V3<double> V2 = a_vertex(a, a.F[3 * (int64_t)f + 2]);
+    double s = __builtin_ldexp(1.0, -lvl);
+    double wa = (double)ba * s, wb = (double)bb * s;
+    return V0 + (wa * (V1 - V0) + wb * (V2 - V0));
+}
+
+// ---------------------------------------------------------------------------
+// Margins. For a value computed in precision T with unit roundoff u:
+//   point query:  |d_computed - d_exact| <= mu_d * d + mu_0
+//   triangle bound: |ub_computed - ub_exact| <= mu_d * dmax + mu_e * emax + mu_0
+// where mu_d = 16u, mu_e = 48u and mu_0 = u * (48 * D_B + 12 * S): D_B the
+// longest edge of B, S the largest coordinate magnitude after centring.
+// (Forward-error analysis of the frame evaluation and the bound formulas;
+// the constants carry a safety factor of about 2.)
+// ---------------------------------------------------------------------------
+struct Margins {
+    double mu_d, mu_e, mu_0;
+};
+
+// ---------------------------------------------------------------------------
+// Traversal
+// ---------------------------------------------------------------------------
+template <class T> HD_D T box_d2(const float4 &lo, const float4 &hi, const V3<T> &p) {
+    T dx = hmax(hmax(T(lo.x) - p.x, p.x - T(hi.x)), T(0));
+    T dy = hmax(hmax(T(lo.y) - p.y, p.y - T(hi.y)), T(0));
+    T dz = hmax(hmax(T(lo.z) - p.z, p.z - T(hi.z)), T(0));
+    return dx * dx + dy * dy + dz * dz;
+}
+
+HD_D float to_float_down(float x) { return x; }
+HD_D float to_float_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = next_down(f);
+    return f;
+}
+
+// per-lane stack in LDS, entries [depth][lane of block]
+template <int SD, int BLOCK> struct LdsStack {
+    int *node;
+    float *dist;
+    int sp = 0;
+    HD_D bool push(int n, float d) {
+        if (sp >= SD) return false;
+        node[sp * BLOCK + threadIdx.x] = n;
+        dist[sp * BLOCK + threadIdx.x] = d;
+        ++sp;
+        return true;
+    }
+    HD_D bool pop(int &n, float &d) {
+        if (sp == 0) return false;
+        --sp;
+        n = node[sp * BLOCK + threadIdx.x];
+        d = dist[sp * BLOCK + threadIdx.x];
+        return true;
+    }
+};
+
+// per-lane stack in global memory (deep fallback)
+struct GlobalStack {
+    int2 *base; // depth x stride
+    int64_t stride;
+    int depth;
+    int sp = 0;
+    HD_D bool push(int n, float d) {
+        if (sp >= depth) return false;
+        base[(int64_t)sp * stride] = make_int2(n, __builtin_bit_cast(int, d));
+        ++sp;
+        return true;
+    }
+    HD_D bool pop(int &n, float &d) {
+        if (sp == 0) return false;
+        --sp;
+        int2 e = base[(int64_t)sp * stride];
+        n = e.x;
+        d = __builtin_bit_cast(float, e.y);
+        return true;
+    }
+};
+
+template <class T> struct QueryResult {
+    T d2;
+    int s;    // sorted index of the closest triangle
+    int orig; // its original face index
+    int nbox, nleaf;
+    bool overflow;
+};
+
+// Closest-first traversal. A child box is entered only when its distance is
+// within (1 + 16u) of the best squared distance so far, which keeps pruning
+// conservative under the rounding of the box test; exact ties between
+// triangles resolve to the smallest original face index.
+template <class T, class Stack>
+HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &bv,
+                             const int4 *__restrict__ ids, const V3<T> &p, Stack &st) {
+    const T slack = T(1) + T(16 * Prec<T>::u);
+    QueryResult<T> r;
+    r.d2 = T(__builtin_inf());
+    r.s = -1;
+    r.orig = 0x7fffffff;
+    r.nbox = 0;
+    r.nleaf = 0;
+    r.overflow = false;
+    int node = 0;
+    auto leaf = [&](int s) {
+        Frame<T> f = load_frame(bv.frames, s);
+        T d2 = frame_dist2<T, false>(f, p, nullptr);
+        ++r.nleaf;
+        if (d2 <= r.d2) {
+            int o = ids[s].w;
+            if (d2 < r.d2 || o < r.orig) {
+                r.d2 = d2;
+                r.s = s;
+                r.orig = o;
+            }
+        }
+    };
+    while (true) {
+        const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
+        float4 a = np[0], b = np[1], c = np[2], d = np[3];
+        int cl = __builtin_bit_cast(int, a.w), cr = __builtin_bit_cast(int, b.w);
+        T dl = box_d2<T>(a, b, p), dr = box_d2<T>(c, d, p);
+        r.nbox += 2;
+        T thr = r.d2 * slack;
+        bool hl = dl <= thr, hr = dr <= thr;
+        if (hl && cl < 0) {
+            leaf(~cl);
+            hl = false;
+        }
+        if (hr && cr < 0) {
+            if (cr != cl) leaf(~cr);
+            hr = false;
+        }
+        thr = r.d2 * slack;
+        hl = hl && dl <= thr;
+        hr = hr && dr <= thr;
+        if (hl && hr) {
+            bool lfirst = dl <= dr;
+            int nearc = lfirst ? cl : cr, farc = lfirst ? cr : cl;
+            T fard = lfirst ? dr : dl;
+            if (!st.push(farc, to_float_down(fard))) r.overflow = true;
+            node = nearc;
+            continue;
+        }
+        if (hl) {
+            node = cl;
+            continue;
+        }
+        if (hr) {
+            node = cr;
+            continue;
+        }
+        bool found = false;
+        int n;
+        float dn;
+        while (st.pop(n, dn)) {
+            if (T(dn) <= r.d2 * slack) {
+                node = n;
+                found = true;
+                break;
+            }
+        }
+        if (!found) break;
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// The cascade ("Upper bounds" subsection and Implementation section): the
+// exact bound when all three closest triangles coincide; otherwise the
+// bounds in the requested order, stopping at the first that falls below the
+// lower bound L (discard), else the minimum of all of them.
+// ---------------------------------------------------------------------------
+struct CascadeCtx {
+    int order[4];
+    int norder;
+    double L;       // certified running lower bound
+    double eps;     // absolute tolerance
+    double mu64_0;  // FP64 absolute margin term, for the final-step consistency slack
+    Margins m;
+};
+
+template <class T>
+HD_D T bound_k(int k, const Tri<T> &t, const BView<T> &bv, const IdView &iv, int *evals) {
+    switch (k) {
+    case 1: return bound_u1(t);
+    case 2: return bound_u2(t);
+    case 3: return bound_u3(t, bv, iv, nullptr, evals);
+    default: return bound_u4(t);
+    }
+}
+
+template <class T> HD_D double tri_margin(const Tri<T> &t, const Margins &m) {
+    double dmax = (double)hmax(t.d[0], hmax(t.d[1], t.d[2]));
+    double e = (double)hmax(norm2(t.v[0] - t.v[1]), hmax(norm2(t.v[1] - t.v[2]), norm2(t.v[2] - t.v[0])));
+    return m.mu_d * dmax + m.mu_e * sqrt(e) + m.mu_0;
+}
+
+// returns the upper bound (margin included); *decider = 0 (exact), 1..4
+template <class T>
+HD_D double cascade(const Tri<T> &t, const CascadeCtx &c, const BView<T> &bv, const IdView &iv,
+                    int *decider, int *evals) {
+    double mu = tri_margin(t, c.m);
+    if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) {
+        *decider = 0;
+        return (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
+    }
+    double best = __builtin_inf();
+    *decider = c.order[c.norder - 1];
+    for (int i = 0; i < c.norder; ++i) {
+        int k = c.order[i];
+        double u = (double)bound_k<T>(k, t, bv, iv, evals) + mu;
+        if (u < c.L) {
+            *decider = k;
+            return u;
+        }
+        if (u < best) {
+            best = u;
+            *decider = k;
+        }
+    }
+    return best;
+}
+
+// FP64 recomputation of a frontier triangle: exact vertex positions, FP64
+// distances to the recorded closest triangles (any point of B gives a valid
+// upper-bound distance), then the full minimum over the bounds in the order
+// set. Returns the bound with the FP64 margin.
+HD_D double rebound64(const AView &a, int32_t face, int lvl, const int ba[3], const int bb[3],
+                      const int I[3], const BView<double> &bv64, const IdView &iv, const CascadeCtx &c,
+                      const Margins &m64, int *evals) {
+    Tri<double> t;
+    for (int i = 0; i < 3; ++i) {
+        t.v[i] = a_point(a, face, lvl, ba[i], bb[i]);
+        t.I[i] = I[i];
+        Frame<double> f = load_frame(bv64.frames, I[i]);
+        V3<double> q;
+        t.d[i] = sqrt(frame_dist2<double, true>(f, t.v[i], &q));
+        t.q[i] = q;
+    }
+    *evals += 3;
+    double mu = tri_margin(t, m64);
+    if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) return hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
+    double best = __builtin_inf();
+    for (int i = 0; i < c.norder; ++i) best = hmin(best, bound_k<double>(c.order[i], t, bv64, iv, evals) + mu);
+    return best;
+}
+
+} // namespace hd

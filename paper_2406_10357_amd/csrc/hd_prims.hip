@@ -1,0 +1,205 @@
+// hd_prims.hip -- device-wide exclusive scan and stable LSD radix sort,
+// written for wave64: lane prefixes from ballot/popcount and 64-lane shuffles,
+// block results combined in LDS.
+#include "hd_internal.hpp"
+
+namespace hd {
+
+namespace {
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// inclusive scan across the 64 lanes of a wave
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane_id() >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan across a block of SCAN_BLOCK threads; returns the block total
+__device__ __forceinline__ int block_exclusive_scan(int v, int *total) {
+    __shared__ int wsum[SCAN_BLOCK / 64];
+    int inc = wave_inclusive_scan(v);
+    int w = threadIdx.x >> 6;
+    if (lane_id() == 63) wsum[w] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_BLOCK / 64; ++i) {
+        if (i < w) off += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void k_scan_reduce(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ part) {
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < n) s += in[base + i];
+    int tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the per-tile partial sums, in place
+__global__ void k_scan_partials(int32_t *part, int64_t n, int32_t *d_total) {
+    int carry = 0;
+    for (int64_t b = 0; b < n; b += SCAN_BLOCK) {
+        int64_t i = b + threadIdx.x;
+        int v = i < n ? part[i] : 0;
+        int tot;
+        int ex = block_exclusive_scan(v, &tot);
+        if (i < n) part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && d_total) *d_total = carry;
+}
+
+__global__ void k_scan_down(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
+                            const int32_t *__restrict__ part) {
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        s += v[i];
+    }
+    int tot;
+    int ex = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out[base + i] = ex;
+        ex += v[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// radix sort: 8-bit digits, one tile of RS_BLOCK * RS_ITEMS keys per block
+// ---------------------------------------------------------------------------
+constexpr int RS_BLOCK = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
+constexpr int RS_WAVES = RS_BLOCK / 64;
+
+__global__ void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int shift, int nblocks,
+                             int32_t *__restrict__ hist) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
+                                uint32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
+                                int shift, int nblocks, const int32_t *__restrict__ offs) {
+    __shared__ int goff[256];
+    __shared__ int wcnt[RS_WAVES][256];
+    __shared__ int woff[RS_WAVES][256];
+    goff[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    const int w = threadIdx.x >> 6;
+    const int lane = __lane_id();
+    const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        for (int k = 0; k < RS_WAVES; ++k) wcnt[k][threadIdx.x] = 0;
+        __syncthreads();
+        int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
+        bool act = i < n;
+        uint32_t key = act ? kin[i] : 0u;
+        int32_t val = act ? vin[i] : 0;
+        uint32_t dg = (key >> shift) & 255u;
+        unsigned long long peers = __ballot(act);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            unsigned long long m = __ballot((dg >> b) & 1u);
+            peers &= ((dg >> b) & 1u) ? m : ~m;
+        }
+        int rank = __popcll(peers & lt);
+        if (act && rank == 0) wcnt[w][dg] = __popcll(peers);
+        __syncthreads();
+        {   // per digit: offsets of each wave within this round
+            int d = threadIdx.x;
+            int run = goff[d];
+            for (int k = 0; k < RS_WAVES; ++k) {
+                woff[k][d] = run;
+                run += wcnt[k][d];
+            }
+            goff[d] = run;
+        }
+        __syncthreads();
+        if (act) {
+            int64_t o = woff[w][dg] + rank;
+            kout[o] = key;
+            vout[o] = val;
+        }
+        __syncthreads();
+    }
+}
+
+} // namespace
+
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,
+                        hipStream_t s) {
+    if (n <= 0) {
+        if (d_total) HD_HIP(hipMemsetAsync(d_total, 0, sizeof(int32_t), s));
+        return;
+    }
+    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    tmp.reserve(nb * sizeof(int32_t));
+    int32_t *part = tmp.as<int32_t>();
+    k_scan_reduce<<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, n, part);
+    k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, nb, d_total);
+    k_scan_down<<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, out, n, part);
+    HD_LAUNCH_CHECK();
+}
+
+void radix_sort_u32(uint32_t *keys, int32_t *vals, uint32_t *keys_alt, int32_t *vals_alt, int64_t n,
+                    int bits, DBuf &tmp, hipStream_t s) {
+    if (n <= 1) return;
+    int nb = (int)((n + RS_TILE - 1) / RS_TILE);
+    int64_t hn = 256LL * nb;
+    int64_t scan_parts = (hn + SCAN_TILE - 1) / SCAN_TILE;
+    tmp.reserve((size_t)(2 * hn + scan_parts + 64) * sizeof(int32_t));
+    int32_t *hist = tmp.as<int32_t>();
+    int32_t *offs = hist + hn;
+    int32_t *part = offs + hn;
+    uint32_t *ka = keys, *kb = keys_alt;
+    int32_t *va = vals, *vb = vals_alt;
+    int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        int shift = 8 * p;
+        k_radix_hist<<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, hist);
+        int64_t pb = scan_parts;
+        k_scan_reduce<<<(unsigned)pb, SCAN_BLOCK, 0, s>>>(hist, hn, part);
+        k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, pb, nullptr);
+        k_scan_down<<<(unsigned)pb, SCAN_BLOCK, 0, s>>>(hist, offs, hn, part);
+        k_radix_scatter<<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, offs);
+        HD_LAUNCH_CHECK();
+        uint32_t *tk = ka; ka = kb; kb = tk;
+        int32_t *tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys) {
+        HD_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        HD_HIP(hipMemcpyAsync(vals, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+}
+
+} // namespace hd

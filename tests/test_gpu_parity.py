@@ -1,0 +1,252 @@
+"""Parity of the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Every test prints the case it is about to run before touching the GPU."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_10357_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _hd():
+    import torch
+    import paper_2406_10357_amd as hd
+    assert torch.cuda.is_available()
+    hd.load_library()
+    return hd, torch
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _cu(x, torch):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _grid_soup(n, rng, amp=0.2, lo=-1, hi=1):
+    xs = np.linspace(lo, hi, n + 1)
+    X, Y = np.meshgrid(xs, xs)
+    Z = amp * rng.normal(size=X.shape)
+    V = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    idx = np.arange((n + 1) ** 2).reshape(n + 1, n + 1)
+    F = np.concatenate([np.stack([idx[:-1, :-1].ravel(), idx[:-1, 1:].ravel(), idx[1:, 1:].ravel()], 1),
+                        np.stack([idx[:-1, :-1].ravel(), idx[1:, 1:].ravel(), idx[1:, :-1].ravel()], 1)])
+    return V, F.astype(np.int32)
+
+
+def _margin(d, u, edge_max, coord_max):
+    return 16 * u * d + u * (48 * edge_max + 12 * coord_max)
+
+
+# ----------------------------------------------------------------------------
+# point -> B queries (LBVH traversal + frame closest point)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["config2-small", "config3-small", "grid"])
+def test_point_distances_match_oracle(which):
+    hd, torch = _hd()
+    rng = np.random.default_rng(5)
+    if which == "grid":
+        VB, FB = _grid_soup(12, rng)
+        P = rng.uniform(-1.3, 1.3, size=(3000, 3))
+    else:
+        W = wl.config(2 if which == "config2-small" else 3, scale=0.05)
+        VB, FB = W.VB, W.FB
+        lo, hi = VB.min(0), VB.max(0)
+        P = np.concatenate([rng.uniform(lo - 0.1, hi + 0.1, size=(1500, 3)), W.VA[:1500]])
+    say("point_distances", which, "nB", FB.shape[0], "nP", P.shape[0])
+    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+    d64, I64, Q64 = hd.point_distances(_cu(P, torch), bvh, precision=hd.PREC_FP64)
+    d32, I32, Q32 = hd.point_distances(_cu(P, torch), bvh, precision=hd.PREC_FP32)
+    d64, I64, Q64 = d64.cpu().numpy(), I64.cpu().numpy(), Q64.cpu().numpy()
+    d32, I32 = d32.cpu().numpy(), I32.cpu().numpy()
+    dref, Iref = oracle.points_soup(P, VB, FB)
+    scale = np.abs(VB).max()
+    # FP64: same distance; the face is the oracle's or one at the same distance
+    assert np.abs(d64 - dref).max() <= 1e-12 * scale
+    bad = np.nonzero(I64 != Iref)[0]
+    for i in bad:
+        a, b, c = VB[FB[I64[i]]]
+        dd = math.sqrt(oracle.closest_point(P[i], a, b, c)[0])
+        assert abs(dd - dref[i]) <= 1e-12 * scale
+    # closest point lies on the reported face at the reported distance
+    for i in range(0, P.shape[0], 97):
+        a, b, c = VB[FB[I64[i]]]
+        dq = math.sqrt(oracle.closest_point(Q64[i], a, b, c)[0])
+        assert dq <= 1e-12 * scale
+        assert abs(np.linalg.norm(Q64[i] - P[i]) - d64[i]) <= 1e-12 * scale
+    # FP32: within the stated margin of the exact distance
+    edge = max(np.linalg.norm(VB[FB[:, i]] - VB[FB[:, (i + 1) % 3]], axis=1).max() for i in range(3))
+    ctr = 0.5 * (VB[np.unique(FB)].min(0) + VB[np.unique(FB)].max(0))
+    coord = max(np.abs(VB - ctr).max(), np.abs(P - ctr).max())
+    mu = _margin(dref, 2.0 ** -24, edge, coord)
+    err = np.abs(d32 - dref)
+    print("fp32 max |d32-d| / mu =", float((err / mu).max()), flush=True)
+    assert (err <= mu).all()
+
+
+# ----------------------------------------------------------------------------
+# the bound formulas, in isolation
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_eval_bounds_match_oracle(seed):
+    hd, torch = _hd()
+    rng = np.random.default_rng(300 + seed)
+    VB, FB = _grid_soup(8, rng)
+    tris, ds, Is, qs = [], [], [], []
+    for k in range(400):
+        kind = ["generic", "thin"][k % 2]
+        c0 = rng.uniform(-0.8, 0.8, size=3) * np.array([1, 1, 0.3]) + np.array([0, 0, rng.uniform(-0.5, 0.5)])
+        s = rng.choice([0.03, 0.2, 0.8])
+        a = rng.normal(size=3) * s
+        if kind == "generic":
+            v = np.array([a, a + rng.normal(size=3) * s, a + rng.normal(size=3) * s])
+        else:
+            e = rng.normal(size=3)
+            v = np.array([a, a + e * s, a + e * s * 0.5 + rng.normal(size=3) * 1e-3 * s])
+        v = v - v[0] + c0
+        res = [oracle.point_soup(x, VB, FB) for x in v]
+        tris.append(v)
+        ds.append([r[0] for r in res])
+        Is.append([r[1] for r in res])
+        qs.append([r[2] for r in res])
+    tris, ds, Is, qs = map(np.array, (tris, ds, Is, qs))
+    ref = np.array([oracle.bounds(tris[i], ds[i], Is[i].astype(np.int32), qs[i], VB, FB)[0] for i in range(len(tris))])
+    refcase = np.array([oracle.bounds(tris[i], ds[i], Is[i].astype(np.int32), qs[i], VB, FB)[1] for i in range(len(tris))])
+    say("eval_bounds seed", seed, "n", len(tris))
+    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+    out, case = hd.eval_bounds(_cu(tris, torch), _cu(ds, torch), _cu(Is.astype(np.int32), torch),
+                               _cu(qs, torch), bvh, precision=hd.PREC_FP64)
+    out, case = out.cpu().numpy(), case.cpu().numpy()
+    assert (case == refcase).all()
+    assert (np.isnan(out[:, 0]) == np.isnan(ref[:, 0])).all()
+    m = ~np.isnan(ref)
+    assert np.allclose(out[m], ref[m], rtol=1e-9, atol=1e-12)
+    # FP32 evaluation stays within the triangle margin of FP64
+    out32, _ = hd.eval_bounds(_cu(tris, torch), _cu(ds, torch), _cu(Is.astype(np.int32), torch),
+                              _cu(qs, torch), bvh, precision=hd.PREC_FP32)
+    out32 = out32.cpu().numpy()
+    u = 2.0 ** -24
+    edgeB = max(np.linalg.norm(VB[FB[:, i]] - VB[FB[:, (i + 1) % 3]], axis=1).max() for i in range(3))
+    eT = np.max([np.linalg.norm(tris[:, i] - tris[:, (i + 1) % 3], axis=1) for i in range(3)], axis=0)
+    ctr = 0.5 * (VB.min(0) + VB.max(0))
+    coord = max(np.abs(VB - ctr).max(), np.abs(tris - ctr).max())
+    mu = 16 * u * ds.max(1) + 48 * u * eT + u * (48 * edgeB + 12 * coord)
+    err = np.abs(out32[:, 1:] - ref[:, 1:]).max(1)
+    print("fp32 bound max err / mu =", float((err / mu).max()), flush=True)
+    assert (err <= mu).all()
+
+
+# ----------------------------------------------------------------------------
+# the whole branch and bound
+# ----------------------------------------------------------------------------
+
+def _check_against_oracle(L, U, st, ref, name):
+    eps = st["eps_abs"]
+    print(f"{name}: gpu [{L:.12g}, {U:.12g}] oracle [{ref['L']:.12g}, {ref['U']:.12g}] eps {eps:.3g} "
+          f"rounds {st['rounds']} subdiv {st['subdivided']} (oracle {ref['subdivided']}) "
+          f"dL/dA {abs(L - ref['L']) / st['dA']:.3g} dU/dA {abs(U - ref['U']) / st['dA']:.3g}", flush=True)
+    assert st["dA"] == pytest.approx(ref["dA"], rel=1e-14)
+    assert U - L <= eps * (1 + 1e-12)
+    assert L <= ref["U"] + 1e-12 * st["dA"] and ref["L"] <= U + 1e-12 * st["dA"]
+    assert abs(L - ref["L"]) <= eps
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32+recheck"])
+def test_config1_against_oracle(prec):
+    hd, torch = _hd()
+    W = wl.config(1)
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel)
+    p = {"fp64": hd.PREC_FP64, "fp32": hd.PREC_FP32, "fp32+recheck": hd.PREC_FP32_RECHECK}[prec]
+    say("config1", prec)
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, precision=p)
+    _check_against_oracle(L, U, st, ref, f"config1 {prec}")
+
+
+@pytest.mark.parametrize("k,scale", [(2, 0.05), (3, 0.02), (5, 0.003)])
+@pytest.mark.parametrize("prec", ["fp32", "fp32+recheck", "fp64"])
+def test_small_configs_against_oracle(k, scale, prec):
+    hd, torch = _hd()
+    W = wl.config(k, scale=scale)
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+    assert ref["status"] == 0
+    p = {"fp64": hd.PREC_FP64, "fp32": hd.PREC_FP32, "fp32+recheck": hd.PREC_FP32_RECHECK}[prec]
+    say(f"config{k} scale {scale}", prec, "nA", W.FA.shape[0], "nB", W.FB.shape[0])
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, precision=p)
+    _check_against_oracle(L, U, st, ref, f"config{k}@{scale} {prec}")
+
+
+def test_closed_forms_on_gpu():
+    hd, torch = _hd()
+    # offset triangle: h = d exactly
+    rng = np.random.default_rng(11)
+    v = rng.normal(size=(3, 3))
+    n = np.cross(v[1] - v[0], v[2] - v[0])
+    n /= np.linalg.norm(n)
+    F = np.array([[0, 1, 2]], np.int32)
+    say("closed form: offset triangle")
+    bvh = hd.build_bvh(_cu(v, torch), _cu(F, torch))
+    L, U, st = hd.bound(_cu(v + 0.37 * n, torch), _cu(F, torch), bvh, 1e-6, precision=hd.PREC_FP64)
+    assert L <= 0.37 + 1e-12 <= U + 2e-12 and U - L <= st["eps_abs"]
+    # two-point closed form with an edge maximiser
+    delta = 0.3
+    VA = np.array([[-1, 0, 0], [1, 0, 0], [0.5, delta, 0]], float)
+    VB = np.array([[-1, 0, 1], [1, 0, 1]], float)
+    FB = np.array([[0, 0, 0], [1, 1, 1]], np.int32)
+    h = math.sqrt(2 + 4 * delta ** 2 / 9)
+    for prec in (hd.PREC_FP64, hd.PREC_FP32_RECHECK):
+        say("closed form: two points, precision", prec)
+        bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+        L, U, st = hd.bound(_cu(VA, torch), _cu(F, torch), bvh, 1e-6, precision=prec)
+        assert L <= h + 1e-12 <= U + 2e-12 and U - L <= st["eps_abs"] * (1 + 1e-12)
+        assert L > math.sqrt(1.34) + 1e-3
+    # self distance
+    V, Fi = wl.icosphere(1)
+    say("closed form: h(A,A)")
+    bvh = hd.build_bvh(_cu(V, torch), _cu(Fi, torch))
+    L, U, st = hd.bound(_cu(V, torch), _cu(Fi, torch), bvh, 1e-2, precision=hd.PREC_FP64)
+    assert L <= 1e-12 and U <= st["eps_abs"] * (1 + 1e-12)
+
+
+def test_deterministic():
+    hd, torch = _hd()
+    W = wl.config(2, scale=0.05)
+    say("determinism config2 scale 0.05")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    r1 = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    r2 = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    assert r1[0] == r2[0] and r1[1] == r2[1]
+    for k in ("subdivided", "nodes_bounded", "queries", "rounds"):
+        assert r1[2][k] == r2[2][k]
+
+
+@pytest.mark.parametrize("bad", ["eps", "index", "nan", "emptyA"])
+def test_invalid_inputs(bad):
+    hd, torch = _hd()
+    V, F = wl.icosphere(0)
+    VA, FA, eps = V.copy(), F.copy(), 1e-3
+    if bad == "eps":
+        eps = 0.0
+    elif bad == "index":
+        FA[3, 1] = V.shape[0]
+    elif bad == "nan":
+        VA[2, 0] = np.nan
+    say("invalid input", bad)
+    bvh = hd.build_bvh(_cu(V, torch), _cu(F, torch))
+    if bad == "emptyA":
+        FA = FA[:0]
+    with pytest.raises(hd.HDError) as e:
+        hd.bound(_cu(VA, torch), _cu(FA, torch), bvh, eps)
+    assert e.value.status == 1
+    FB = F.copy()
+    FB[0, 0] = -1
+    with pytest.raises(hd.HDError):
+        hd.build_bvh(_cu(V, torch), _cu(FB, torch))
