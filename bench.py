@@ -1,0 +1,158 @@
+"""Benchmark: milliseconds to an eps-certified [L, U] for h(A,B) on one MI355X.
+
+A step is one whole pass of the method on one resident input pair: build the
+LBVH over B, then the certified bound for A (the BVH build is inside the
+timed step, as in the paper's totals). Prints one JSON line.
+
+Default workload: the near-zero case, a displaced torus on a 160 x 160 grid
+(51,200 triangles) against a periodic Delaunay re-triangulation of the same
+surface from 20,000 random points (40,000 triangles), eps = 1e-5 * dA, FP32
+arithmetic with an FP64 recheck band and an FP64 final step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to eps-certified h(A,B) (ms), learned vs plain; point-tri dist evals/s"
+
+# Algorithmic FP32 operations per unit of work in the query kernel (counted from
+# the source of the frame evaluation and the box test; an FMA counts as 2).
+FLOP_PER_LEAF = 63       # one point-triangle distance in the triangle's frame
+FLOP_PER_BOX = 11        # one point-box squared distance
+FLOP_PER_QUERY = 70      # final closest point + square root per query
+PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X datasheet vector FP32
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", default="fp32+recheck", choices=["fp64", "fp32", "fp32+recheck"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(W, reps=3):
+    import oracle
+    times, res = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+        times.append((time.perf_counter() - t0) * 1e3)
+    return statistics.median(times), res
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build "
+              "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2406_10357_amd as hd
+    from paper_2406_10357_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    W = wl.config(a.config)
+    prec = {"fp64": hd.PREC_FP64, "fp32": hd.PREC_FP32, "fp32+recheck": hd.PREC_FP32_RECHECK}[a.precision]
+    VA = torch.from_numpy(W.VA).cuda()
+    FA = torch.from_numpy(W.FA).cuda()
+    VB = torch.from_numpy(W.VB).cuda()
+    FB = torch.from_numpy(W.FB).cuda()
+    torch.cuda.synchronize()
+
+    def step(profile=0):
+        bvh = hd.build_bvh(VB, FB)
+        return hd.bound(VA, FA, bvh, W.eps_rel, precision=prec, profile=profile)
+
+    for i in range(a.warmup):
+        step()
+        print(f"warmup {i + 1}/{a.warmup} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(a.steps):
+        results.append(step(profile=1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / a.steps
+    print(f"timed {a.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    L, U, st = results[-1]
+    q_ms = sum(r[2]["ms_query_kernels"] for r in results)
+    c_ms = sum(r[2]["ms_cascade_kernels"] for r in results)
+    q_leaf = sum(r[2]["query_leaf_evals"] for r in results)
+    q_box = sum(r[2]["query_box_tests"] for r in results)
+    q_n = sum(r[2]["queries"] for r in results)
+    q_launch = sum(r[2]["query_launches"] for r in results)
+    evals = sum(r[2]["pt_tri_evals"] for r in results)
+    flops = FLOP_PER_LEAF * q_leaf + FLOP_PER_BOX * q_box + FLOP_PER_QUERY * q_n
+    achieved = flops / (q_ms * 1e-3) / 1e12 if q_ms > 0 else None
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": W.name,
+            "nA": int(W.FA.shape[0]), "nB": int(W.FB.shape[0]),
+            "eps_rel": W.eps_rel, "precision": a.precision,
+            "variant": "plain cascade 1234, breadth-first rounds",
+        },
+        "result": {"L": L, "U": U, "dA": st["dA"], "eps_abs": st["eps_abs"], "rounds": st["rounds"],
+                   "subdivided": st["subdivided"], "nodes_bounded": st["nodes_bounded"],
+                   "queries": st["queries"], "pt_tri_evals": st["pt_tri_evals"],
+                   "discards": st["discards"], "rechecked64": st["rechecked64"],
+                   "parked_final": st["parked_final"]},
+        "evals_per_s": evals / ((q_ms + c_ms) * 1e-3) if q_ms + c_ms > 0 else None,
+        "learned_ms": None,
+        "roofline": {
+            "kernel": "k_query<float> (LBVH traversal + point-triangle distances)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_VECTOR,
+            "unit": "TFLOP/s",
+            "frac": (achieved / PEAK_FP32_VECTOR) if achieved else None,
+            "traffic": None,
+            "launches": q_launch,
+            "avg_launch_ms": q_ms / q_launch if q_launch else None,
+            "flops_per_launch": flops / q_launch if q_launch else None,
+        },
+    }
+    if not a.no_cpu_baseline:
+        print("timing the CPU oracle on the same workload ...", file=sys.stderr, flush=True)
+        cms, ref = cpu_baseline(W)
+        out["cpu_baseline"] = {"value": round(cms, 3), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": "the full workload, single-threaded FP64 oracle with its own AABB "
+                                         "tree, median of 3 runs (tree build included)"}
+        out["parity"] = {"oracle_L": ref["L"], "oracle_U": ref["U"],
+                         "overlap": bool(L <= ref["U"] and ref["L"] <= U),
+                         "dL_over_dA": abs(L - ref["L"]) / st["dA"], "dU_over_dA": abs(U - ref["U"]) / st["dA"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,7 +60,8 @@ typedef struct {
     int32_t stack_depth; /* traversal stack entries per lane (test hook); 0 = default */
     int32_t subbatch;    /* > 0: subdivide at most this many triangles per round, highest
                             upper bound first (approximates the paper's best-first queue) */
-    int32_t reserved;
+    int32_t profile;     /* 1: time the query and cascade kernels with HIP events on the
+                            call's stream (fills the ms_* kernel fields of hd_stats) */
 } hd_options;
 
 typedef struct {
@@ -81,6 +82,11 @@ typedef struct {
     double L_rounds, U_rounds; /* interval reached by the rounds, before the FP64 final step */
     double mu_coef_d, mu_coef_0; /* FP32 margin: mu(d) = mu_coef_d * d + mu_coef_0 */
     double ms_total;           /* wall time of the hd_bound call */
+    double ms_query_kernels;   /* profile = 1: summed duration of the point-query kernels */
+    double ms_cascade_kernels; /* profile = 1: summed duration of the bound/classify kernels */
+    int64_t query_launches, cascade_launches;
+    int64_t query_leaf_evals;  /* closest-point evaluations inside the query kernels */
+    int64_t query_box_tests;   /* box tests inside the query kernels */
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle

@@ -33,7 +33,7 @@ class HDError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("order", C.c_int32), ("budget_m", C.c_double),
                 ("capacity", C.c_int64), ("max_rounds", C.c_int32), ("stack_depth", C.c_int32),
-                ("subbatch", C.c_int32), ("reserved", C.c_int32)]
+                ("subbatch", C.c_int32), ("profile", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -43,7 +43,10 @@ class Stats(C.Structure):
                 ("parked_final", C.c_int64), ("max_frontier", C.c_int64),
                 ("stack_overflows", C.c_int64), ("dA", C.c_double), ("eps_abs", C.c_double),
                 ("L_rounds", C.c_double), ("U_rounds", C.c_double), ("mu_coef_d", C.c_double),
-                ("mu_coef_0", C.c_double), ("ms_total", C.c_double)]
+                ("mu_coef_0", C.c_double), ("ms_total", C.c_double),
+                ("ms_query_kernels", C.c_double), ("ms_cascade_kernels", C.c_double),
+                ("query_launches", C.c_int64), ("cascade_launches", C.c_int64),
+                ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -137,11 +140,12 @@ def build_bvh(VB, FB) -> Bvh:
 
 
 def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
-                 stack_depth=0, subbatch=0) -> Options:
+                 stack_depth=0, subbatch=0, profile=0) -> Options:
     o = Options()
     load_library().hd_default_options(C.byref(o))
     o.precision, o.order, o.budget_m = precision, order, budget_m
     o.capacity, o.max_rounds, o.stack_depth, o.subbatch = capacity, max_rounds, stack_depth, subbatch
+    o.profile = profile
     return o
 
 

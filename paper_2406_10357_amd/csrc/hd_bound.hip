@@ -32,7 +32,7 @@ constexpr int BLK = 256;
 struct DevState {
     unsigned long long queries, evals, boxes, bounded, subdivided;
     unsigned long long discards[5];
-    unsigned long long rechecked, overflows;
+    unsigned long long rechecked, overflows, q_leaves, q_boxes;
     unsigned long long Lord;      // ordered double: certified lower bound
     unsigned long long Uord;      // ordered double: upper bound of the final step
     unsigned long long round_key; // (ordered float of d_lo) << 32 | ~query index
@@ -41,6 +41,7 @@ struct DevState {
     unsigned long long coord_max; // ordered FP64
     int bad;
     int n_overflow;
+    int argmax_dirty;
     double argmax_pos[3];
     double L64;
 };
@@ -205,6 +206,8 @@ __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn in, int64_t n, QueryCf
     }
     wave_add(&st->boxes, nb);
     wave_add(&st->evals, nl);
+    wave_add(&st->q_leaves, nl);
+    wave_add(&st->q_boxes, nb);
     wave_add(&st->queries, nq);
 }
 
@@ -242,6 +245,7 @@ __global__ void k_argmax_update(QueryIn in, DevState *st) {
         st->argmax_pos[0] = p.x;
         st->argmax_pos[1] = p.y;
         st->argmax_pos[2] = p.z;
+        st->argmax_dirty = 1;
     }
     st->round_key = 0;
 }
@@ -391,6 +395,9 @@ __global__ void k_children(int64_t nsel, FrontierView<T> par, QueryOut<T> mq, Cl
                 cn[i].bb = par.bb[e][j] + par.bb[e2][j];
             }
         }
+        // dyadic coordinates are int32 numerators over 2^lvl: level 30 is the
+        // deepest representable one
+        if (par.lvl[j] >= 30) st->bad = 3;
         cls = bound_and_write<T>(cn, par.face[j], par.lvl[j] + 1, cfg, bv, fo, c, &decider, &evals, &rechecked);
         co.flag_act[c] = cls == 2;
         co.flag_park[c] = cls == 1;
@@ -484,11 +491,15 @@ __global__ void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> 
     wave_add(&st->evals, ev);
 }
 
-__global__ void k_final_L(const NodeRec *nodes, BView<double> bv64, const int4 *ids, Margins m64, DevState *st) {
+// FP64 distance of the best vertex found so far (when it changed): the lower
+// bound then carries the FP64 margin instead of the FP32 one, which the
+// recheck band needs to park triangles within eps of it
+__global__ void k_L64(const NodeRec *nodes, BView<double> bv64, const int4 *ids, Margins m64, DevState *st) {
     __shared__ int s_node[DEEP_STACK];
     __shared__ float s_dist[DEEP_STACK];
     if (threadIdx.x != 0) return;
-    if (st->best_key == 0) return;
+    if (st->best_key == 0 || !st->argmax_dirty) return;
+    st->argmax_dirty = 0;
     V3<double> p = {st->argmax_pos[0], st->argmax_pos[1], st->argmax_pos[2]};
     LdsStack<DEEP_STACK, 1> stk{s_node, s_dist, 0};
     QueryResult<double> r = traverse<double>(nodes, bv64, ids, p, stk);
@@ -638,6 +649,31 @@ struct Runner {
     DBuf st_mem;
     DevState *st;
     DBuf scan_tmp, sort_tmp, ovf_mem, deep_stack;
+    BView<double> bv64{};
+    Margins m64{};
+    // optional kernel timing with events on the call's stream
+    bool profile = false;
+    std::vector<hipEvent_t> qev, cev; // begin/end pairs
+    hipEvent_t mark(std::vector<hipEvent_t> &v) {
+        hipEvent_t e = nullptr;
+        if (!profile) return e;
+        HD_HIP(hipEventCreate(&e));
+        HD_HIP(hipEventRecord(e, s));
+        v.push_back(e);
+        return e;
+    }
+    static double sum_pairs(std::vector<hipEvent_t> &v) {
+        double ms = 0;
+        for (size_t i = 0; i + 1 < v.size(); i += 2) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, v[i], v[i + 1]) == hipSuccess) ms += t;
+        }
+        return ms;
+    }
+    ~Runner() {
+        for (auto e : qev) (void)hipEventDestroy(e);
+        for (auto e : cev) (void)hipEventDestroy(e);
+    }
 
     template <class T>
     void queries(const QueryIn &in, int64_t n, const QueryCfg &cfg, const BView<T> &bv, const QueryOut<T> &out,
@@ -645,8 +681,10 @@ struct Runner {
         if (n <= 0) return;
         ovf_mem.reserve((size_t)n * sizeof(int32_t));
         k_fill_i32<<<1, 1, 0, s>>>((int32_t *)&st->n_overflow, 1, 0);
+        mark(qev);
         k_query<T><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(in, n, cfg, bv, out, st, ovf_mem.as<int32_t>());
         HD_LAUNCH_CHECK();
+        mark(qev);
         int novf = 0;
         HD_HIP(hipMemcpyAsync(&novf, &st->n_overflow, sizeof(int), hipMemcpyDeviceToHost, s));
         HD_HIP(hipStreamSynchronize(s));
@@ -657,7 +695,10 @@ struct Runner {
                                                               deep_stack.as<int2>(), novf);
             HD_LAUNCH_CHECK();
         }
-        if (cfg.raise_L) k_argmax_update<<<1, 1, 0, s>>>(in, st);
+        if (cfg.raise_L) {
+            k_argmax_update<<<1, 1, 0, s>>>(in, st);
+            k_L64<<<1, 64, 0, s>>>(cfg.nodes, bv64, cfg.ids, m64, st);
+        }
         HD_LAUNCH_CHECK();
     }
 };
@@ -684,6 +725,7 @@ hd_status bound_impl(const double *VA, int64_t mA, const int32_t *FA, int64_t nA
     Runner R;
     R.s = s;
     R.b = B;
+    R.profile = opt.profile != 0;
     R.st_mem.reserve(sizeof(DevState));
     R.st = R.st_mem.as<DevState>();
     DevState *st = R.st;
@@ -723,6 +765,8 @@ hd_status bound_impl(const double *VA, int64_t mA, const int32_t *FA, int64_t nA
     Margins m64 = make_margins(Prec<double>::u, B, coord_max);
     cctx.m = m;
     cctx.mu64_0 = m64.mu_0;
+    R.bv64 = BView<double>{B->frames64.as<double2>()};
+    R.m64 = m64;
     S.mu_coef_d = m.mu_d;
     S.mu_coef_0 = m.mu_0;
 
@@ -792,9 +836,11 @@ hd_status bound_impl(const double *VA, int64_t mA, const int32_t *FA, int64_t nA
     cc.iv = iv;
 
     // ---- round 0: bound every face ------------------------------------------
+    R.mark(R.cev);
     k_faces_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, FA, vq.o, cc, bv, CH.v, CountOut{flag_act, flag_park},
                                                          st, st);
     HD_LAUNCH_CHECK();
+    R.mark(R.cev);
     int64_t nAct = compact<T>(R, CH.v, nA, flag_act, pos, d_total, ACT.v, 0);
     int64_t nPark = compact<T>(R, CH.v, nA, flag_park, pos, d_total, PARK.v, 0);
     vq.mem.release();
@@ -858,9 +904,11 @@ hd_status bound_impl(const double *VA, int64_t mA, const int32_t *FA, int64_t nA
         in.cz = B->center[2];
         R.queries<T>(in, 3 * K, qcfg, bv, mq.o, &S.stack_overflows);
         // children
+        R.mark(R.cev);
         k_children<T><<<grid_for(4 * K, BLK), BLK, 0, s>>>(K, ACT.v, mq.o, cc, bv, CH.v,
                                                             CountOut{flag_act, flag_park}, st, st);
         HD_LAUNCH_CHECK();
+        R.mark(R.cev);
         // new active list: unselected remainder, then active children
         int64_t rest = nAct - K;
         if (rest > 0) {
@@ -877,6 +925,17 @@ hd_status bound_impl(const double *VA, int64_t mA, const int32_t *FA, int64_t nA
         ++rounds;
         S.max_frontier = std::max<int64_t>(S.max_frontier, nAct + nPark);
         if (nAct > cap || nPark > cap) {
+            status = HD_E_INTERNAL;
+            break;
+        }
+        int bad = 0;
+        HD_HIP(hipMemcpyAsync(&bad, &st->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        HD_HIP(hipStreamSynchronize(s));
+        if (bad == 3) { // subdivision depth exhausted (tolerance below what the arithmetic resolves)
+            status = HD_E_CAPACITY;
+            break;
+        }
+        if (bad) {
             status = HD_E_INTERNAL;
             break;
         }
@@ -899,9 +958,8 @@ hd_status bound_impl(const double *VA, int64_t mA, const int32_t *FA, int64_t nA
     }
 
     if (status == HD_OK) {
-        // final FP64 step: L at the best vertex, U over every live triangle
-        k_final_L<<<1, 64, 0, s>>>(B->nodes.as<NodeRec>(), bv64, iv.ids, m64, st);
-        HD_LAUNCH_CHECK();
+        // final FP64 step: L was re-evaluated in FP64 at the best vertex after
+        // every query round; now U over every live triangle
         if (nPark > 0)
             k_final_U<T><<<grid_for(nPark, BLK), BLK, 0, s>>>(PARK.v, nPark, av, bv64, iv, cctx, m64, st);
         if (nAct > 0)
@@ -926,6 +984,15 @@ hd_status bound_impl(const double *VA, int64_t mA, const int32_t *FA, int64_t nA
     for (int k = 0; k < 5; ++k) S.discards[k] = (int64_t)hs.discards[k];
     S.rechecked64 = (int64_t)hs.rechecked;
     S.parked_final = nPark;
+    S.query_leaf_evals = (int64_t)hs.q_leaves;
+    S.query_box_tests = (int64_t)hs.q_boxes;
+    if (R.profile) {
+        HD_HIP(hipStreamSynchronize(s));
+        S.ms_query_kernels = Runner::sum_pairs(R.qev);
+        S.ms_cascade_kernels = Runner::sum_pairs(R.cev);
+        S.query_launches = (int64_t)R.qev.size() / 2;
+        S.cascade_launches = (int64_t)R.cev.size() / 2;
+    }
     S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = S;
     return status;
