@@ -98,7 +98,15 @@ typedef struct {
 hd_status hd_build_bvh(const double *VB, int64_t mB, const int32_t *FB, int64_t nB,
                        hd_stream_t stream, hd_bvh *out);
 
-/* Release a handle from hd_build_bvh (NULL is allowed). */
+/* One BVH over npairs soups B_p (host arrays of npairs device pointers and
+ * sizes): keys (pair id, Morton code) give every pair its own subtree, and
+ * the returned handle serves hd_bound_batched with the same pair order. The
+ * per-pair original face index is what the queries report. */
+hd_status hd_build_bvh_batched(int32_t npairs, const double *const *VB, const int64_t *mB,
+                               const int32_t *const *FB, const int64_t *nB, hd_stream_t stream,
+                               hd_bvh *out);
+
+/* Release a handle from hd_build_bvh or hd_build_bvh_batched (NULL is allowed). */
 void hd_free_bvh(hd_bvh bvh);
 
 /* Certified [L, U] for h(A, B), B given by its BVH; eps is the paper's
@@ -108,6 +116,21 @@ void hd_free_bvh(hd_bvh bvh);
 hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, hd_bvh B,
                    double eps, const hd_options *opt, hd_stream_t stream, double LU_out[2],
                    hd_stats *stats);
+
+/* Certified [L_p, U_p] for npairs independent pairs (A_p, B_p) in one call:
+ * the pairs share every kernel launch of every round (records carry their
+ * pair id; L, U, eps and the margins are per pair). A_p is given as host
+ * arrays of device pointers and sizes; B is a handle from
+ * hd_build_bvh_batched over the B_p in the same order. eps is a host array
+ * of npairs relative tolerances when eps_per_pair != 0, else one value.
+ * LU_out is a host array of 2 * npairs doubles (L_0, U_0, L_1, U_1, ...);
+ * stats (host, nullable) sums the counters over pairs and reports pair 0's
+ * dA and eps_abs. A pair whose vertices are all referenced by no face is
+ * HD_E_INVALID like an empty mesh. */
+hd_status hd_bound_batched(int32_t npairs, const double *const *VA, const int64_t *mA,
+                           const int32_t *const *FA, const int64_t *nA, hd_bvh B, const double *eps,
+                           int32_t eps_per_pair, const hd_options *opt, hd_stream_t stream,
+                           double *LU_out, hd_stats *stats);
 
 /* Distances from nP points P (device, nP x 3 doubles) to B: d (device, nP
  * doubles), closest face of B as its original index (device, nP int32) and

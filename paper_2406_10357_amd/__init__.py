@@ -12,7 +12,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-__all__ = ["HDError", "Bvh", "Options", "build_bvh", "bound", "point_distances", "eval_bounds",
+__all__ = ["HDError", "Bvh", "Options", "build_bvh", "bound", "build_bvh_batched", "bound_batched",
+           "point_distances", "eval_bounds",
            "load_library", "PREC_FP64", "PREC_FP32", "PREC_FP32_RECHECK"]
 
 PREC_FP64, PREC_FP32, PREC_FP32_RECHECK = 0, 1, 2
@@ -54,8 +55,8 @@ class Stats(C.Structure):
         return d
 
 
-EXPORTS = ["hd_build_bvh", "hd_free_bvh", "hd_bound", "hd_point_distances", "hd_eval_bounds",
-           "hd_status_str", "hd_default_options"]
+EXPORTS = ["hd_build_bvh", "hd_build_bvh_batched", "hd_free_bvh", "hd_bound", "hd_bound_batched",
+           "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options"]
 
 
 def load_library(path: str | None = None):
@@ -76,6 +77,12 @@ def load_library(path: str | None = None):
     lib.hd_bound.restype = i32
     lib.hd_bound.argtypes = [vp, i64, vp, i64, vp, dbl, C.POINTER(Options), vp, C.POINTER(C.c_double),
                              C.POINTER(Stats)]
+    pp = C.POINTER(C.c_void_p)
+    lib.hd_build_bvh_batched.restype = i32
+    lib.hd_build_bvh_batched.argtypes = [i32, pp, C.POINTER(i64), pp, C.POINTER(i64), vp, C.POINTER(vp)]
+    lib.hd_bound_batched.restype = i32
+    lib.hd_bound_batched.argtypes = [i32, pp, C.POINTER(i64), pp, C.POINTER(i64), vp, C.POINTER(C.c_double),
+                                     i32, C.POINTER(Options), vp, C.POINTER(C.c_double), C.POINTER(Stats)]
     lib.hd_point_distances.restype = i32
     lib.hd_point_distances.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp]
     lib.hd_eval_bounds.restype = i32
@@ -119,7 +126,7 @@ class Bvh:
     def __init__(self, handle, VB, FB):
         self.handle = handle
         self.VB, self.FB = VB, FB  # kept alive with the handle
-        self.nB = FB.shape[0]
+        self.nB = FB.shape[0] if hasattr(FB, "shape") else sum(f.shape[0] for f in FB)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -162,6 +169,49 @@ def bound(VA, FA, bvh: Bvh, eps: float, **opts):
                       bvh.handle, float(eps), C.byref(o), _stream(), LU, C.byref(stats))
     _check(st, "hd_bound")
     return LU[0], LU[1], stats.as_dict()
+
+
+def build_bvh_batched(soups) -> Bvh:
+    """One BVH over many soups B_p; soups is a list of (VB, FB)."""
+    torch = _torch()
+    lib = load_library()
+    Vs = [_dev(V, torch.float64) for V, _ in soups]
+    Fs = [_dev(F, torch.int32) for _, F in soups]
+    n = len(soups)
+    vptr = (C.c_void_p * n)(*[V.data_ptr() for V in Vs])
+    fptr = (C.c_void_p * n)(*[F.data_ptr() for F in Fs])
+    ms = (C.c_int64 * n)(*[V.shape[0] for V in Vs])
+    ns = (C.c_int64 * n)(*[F.shape[0] for F in Fs])
+    h = C.c_void_p()
+    st = lib.hd_build_bvh_batched(n, vptr, ms, fptr, ns, _stream(), C.byref(h))
+    _check(st, "hd_build_bvh_batched")
+    b = Bvh(h, Vs, Fs)
+    b.npairs = n
+    return b
+
+
+def bound_batched(meshes, bvh: Bvh, eps, **opts):
+    """Certified [L_p, U_p] for many pairs at once; meshes is a list of
+    (VA, FA) in the order of the soups given to build_bvh_batched; eps is one
+    value or one per pair. Returns (L list, U list, summed stats)."""
+    torch = _torch()
+    lib = load_library()
+    Vs = [_dev(V, torch.float64) for V, _ in meshes]
+    Fs = [_dev(F, torch.int32) for _, F in meshes]
+    n = len(meshes)
+    vptr = (C.c_void_p * n)(*[V.data_ptr() for V in Vs])
+    fptr = (C.c_void_p * n)(*[F.data_ptr() for F in Fs])
+    ms = (C.c_int64 * n)(*[V.shape[0] for V in Vs])
+    ns = (C.c_int64 * n)(*[F.shape[0] for F in Fs])
+    per = not isinstance(eps, (int, float))
+    ev = (C.c_double * (n if per else 1))(*([float(e) for e in eps] if per else [float(eps)]))
+    o = make_options(**opts)
+    LU = (C.c_double * (2 * n))()
+    stats = Stats()
+    st = lib.hd_bound_batched(n, vptr, ms, fptr, ns, bvh.handle, ev, 1 if per else 0, C.byref(o), _stream(),
+                              LU, C.byref(stats))
+    _check(st, "hd_bound_batched")
+    return [LU[2 * i] for i in range(n)], [LU[2 * i + 1] for i in range(n)], stats.as_dict()
 
 
 def point_distances(P, bvh: Bvh, precision=PREC_FP64):

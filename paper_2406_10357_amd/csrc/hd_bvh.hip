@@ -1,13 +1,24 @@
-// hd_bvh.hip -- device-built linear BVH over soup B.
+// hd_bvh.hip -- device-built linear BVH over one or more soups B_p.
 //
-// Morton codes of triangle centroids (30 bits), stable radix sort, the
-// binary radix tree of Karras (HPG 2012) with duplicate keys split by index,
-// and a bottom-up refit whose boxes are rounded outwards from the FP64
-// triangles, so that they contain both the FP64 and the FP32 geometry. Each
-// internal node stores the boxes of both children (64 B), so one load per
-// visited node gives the two distances a closest-first traversal needs.
-// Leaves are the triangles themselves, stored in Morton order as frame
-// records (see hd_geom.hpp) in FP32 and FP64.
+// Keys are (pair id << 32 | 30-bit Morton code of the centroid, normalised to
+// the pair's own centroid box), sorted by a stable radix sort. The binary
+// radix tree of Karras (HPG 2012) over the sorted keys, with duplicate keys
+// split by index, then contains one subtree per pair; a pair's traversal
+// starts at its subtree root. Boxes are rounded outwards from the FP64
+// triangles (in the pair's centred coordinates), so they contain both the
+// FP64 and the FP32 geometry. Each internal node stores the boxes of both
+// children (64 B), so one load per visited node gives both distances of a
+// closest-first traversal. Leaves are the triangles, stored in sorted order
+// as frame records (hd_geom.hpp) in FP32 and FP64.
+//
+// The refit avoids device-scope synchronisation, which on a multi-XCD part
+// costs an L2 write-back and invalidate per step: nodes whose leaf range lies
+// inside one 256-leaf tile are refit by that tile's workgroup (workgroup-scope
+// counters); the few nodes above the tiles are refit by a single workgroup,
+// in sweeps.
+#include <memory>
+#include <mutex>
+
 #include "hd_geom.hpp"
 #include "hd_internal.hpp"
 
@@ -16,6 +27,7 @@ namespace hd {
 namespace {
 
 constexpr int BLK = 256;
+constexpr int TILE = 256; // refit tile = refit workgroup
 
 __device__ __forceinline__ float round_down_f(double x) {
     float f = (float)x;
@@ -28,79 +40,153 @@ __device__ __forceinline__ float round_up_f(double x) {
     return f;
 }
 
-__device__ __forceinline__ void atomic_min_d(unsigned long long *a, double v) { atomicMin(a, d2ord(v)); }
-__device__ __forceinline__ void atomic_max_d(unsigned long long *a, double v) { atomicMax(a, d2ord(v)); }
-
-struct BuildState {
-    unsigned long long bbox[6];  // ordered FP64 lo xyz, hi xyz of B's vertices
-    unsigned long long cbox[6];  // ordered FP64 lo/hi of centroids (centred)
+struct PairAcc { // per-pair accumulators, ordered-double bits
+    unsigned long long bbox[6];
+    unsigned long long cbox[6];
     unsigned long long coord_max, edge_max;
-    int bad;
 };
 
-__global__ void k_init_state(BuildState *st) {
-    for (int k = 0; k < 3; ++k) {
-        st->bbox[k] = d2ord(__builtin_inf());
-        st->bbox[3 + k] = d2ord(-__builtin_inf());
-        st->cbox[k] = d2ord(__builtin_inf());
-        st->cbox[3 + k] = d2ord(-__builtin_inf());
+struct BuildState {
+    int bad;
+    int n_upper;
+};
+
+__global__ void k_init(PairAcc *acc, int npairs, BuildState *st) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        st->bad = 0;
+        st->n_upper = 0;
     }
-    st->coord_max = d2ord(0.0);
-    st->edge_max = d2ord(0.0);
-    st->bad = 0;
+    if (p >= npairs) return;
+    for (int k = 0; k < 3; ++k) {
+        acc[p].bbox[k] = d2ord(__builtin_inf());
+        acc[p].bbox[3 + k] = d2ord(-__builtin_inf());
+        acc[p].cbox[k] = d2ord(__builtin_inf());
+        acc[p].cbox[3 + k] = d2ord(-__builtin_inf());
+    }
+    acc[p].coord_max = d2ord(0.0);
+    acc[p].edge_max = d2ord(0.0);
 }
 
-// validate faces; bbox of referenced vertices (through the faces)
-__global__ void k_faces_check(const double *__restrict__ V, int64_t m, const int32_t *__restrict__ F,
-                              int64_t n, BuildState *st) {
+// pair of a global face index (faces of pair p are [foff[p], foff[p+1]))
+__device__ __forceinline__ int pair_of(const int64_t *__restrict__ foff, int npairs, int64_t f) {
+    int lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (foff[mid] <= f) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// one pair's device pointers
+struct PairSrc {
+    const double *V;
+    const int32_t *F;
+    int64_t m;
+};
+
+// true when every active lane of the wave holds the same value of p
+__device__ __forceinline__ bool uniform_pair(int p) {
+    int p0 = __shfl(p, __ffsll((unsigned long long)__ballot(1)) - 1, 64);
+    return __ballot(p != p0) == 0;
+}
+
+// min/max over a wave when every active lane has the same pair, else per lane
+__device__ __forceinline__ void acc_min(unsigned long long *a, double v, bool uni) {
+    if (uni) {
+        for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+        if (__lane_id() == 0) atomicMin(a, d2ord(v));
+    } else {
+        atomicMin(a, d2ord(v));
+    }
+}
+__device__ __forceinline__ void acc_max(unsigned long long *a, double v, bool uni) {
+    if (uni) {
+        for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        if (__lane_id() == 0) atomicMax(a, d2ord(v));
+    } else {
+        atomicMax(a, d2ord(v));
+    }
+}
+
+// validate faces and compute each pair's vertex box (through its faces).
+// Every lane of a launched wave takes part (inactive lanes carry neutral
+// values) so that the wave-wide reductions see 64 lanes.
+__global__ void k_faces_check(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs,
+                              int64_t n, PairAcc *acc, BuildState *st) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n) return;
+    bool valid = f < n;
+    int p = pair_of(foff, npairs, valid ? f : n - 1);
     double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
     double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
-    for (int j = 0; j < 3; ++j) {
-        int32_t v = F[3 * f + j];
-        if (v < 0 || v >= m) {
-            st->bad = 1;
-            return;
-        }
-        for (int k = 0; k < 3; ++k) {
-            double x = V[3 * (int64_t)v + k];
-            if (!__builtin_isfinite(x)) {
+    if (valid) {
+        PairSrc ps = src[p];
+        int64_t lf = f - foff[p];
+        for (int j = 0; j < 3; ++j) {
+            int32_t v = ps.F[3 * lf + j];
+            if (v < 0 || v >= ps.m) {
                 st->bad = 1;
-                return;
+                continue;
             }
-            lo[k] = fmin(lo[k], x);
-            hi[k] = fmax(hi[k], x);
+            for (int k = 0; k < 3; ++k) {
+                double x = ps.V[3 * (int64_t)v + k];
+                if (!__builtin_isfinite(x)) {
+                    st->bad = 1;
+                    continue;
+                }
+                lo[k] = fmin(lo[k], x);
+                hi[k] = fmax(hi[k], x);
+            }
         }
     }
+    bool uni = uniform_pair(p);
     for (int k = 0; k < 3; ++k) {
-        atomic_min_d(&st->bbox[k], lo[k]);
-        atomic_max_d(&st->bbox[3 + k], hi[k]);
+        acc_min(&acc[p].bbox[k], lo[k], uni);
+        acc_max(&acc[p].bbox[3 + k], hi[k], uni);
     }
 }
 
-__global__ void k_centroids(const double *__restrict__ V, const int32_t *__restrict__ F, int64_t n,
-                            double cx, double cy, double cz, double *__restrict__ cen, BuildState *st) {
+__global__ void k_pair_centres(const PairAcc *acc, int npairs, BvhPair *pairs) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    for (int k = 0; k < 3; ++k) pairs[p].ctr[k] = 0.5 * (ord2d(acc[p].bbox[k]) + ord2d(acc[p].bbox[3 + k]));
+}
+
+__global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs, int64_t n,
+                            const BvhPair *__restrict__ pairs, double *__restrict__ cen, int32_t *__restrict__ fpair,
+                            PairAcc *acc, const BuildState *st) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n) return;
+    bool valid = f < n && !st->bad;
+    int p = pair_of(foff, npairs, f < n ? f : n - 1);
     double c[3] = {0, 0, 0};
     double m = 0;
-    const double ctr[3] = {cx, cy, cz};
-    for (int j = 0; j < 3; ++j) {
-        int32_t v = F[3 * f + j];
+    double clo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
+    double chi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
+    if (valid) {
+        PairSrc ps = src[p];
+        int64_t lf = f - foff[p];
+        for (int j = 0; j < 3; ++j) {
+            int32_t v = ps.F[3 * lf + j];
+            for (int k = 0; k < 3; ++k) {
+                double x = ps.V[3 * (int64_t)v + k] - pairs[p].ctr[k];
+                c[k] += x;
+                m = fmax(m, fabs(x));
+            }
+        }
         for (int k = 0; k < 3; ++k) {
-            double x = V[3 * (int64_t)v + k] - ctr[k];
-            c[k] += x;
-            m = fmax(m, fabs(x));
+            c[k] /= 3.0;
+            cen[3 * f + k] = c[k];
+            clo[k] = chi[k] = c[k];
         }
     }
+    if (f < n) fpair[f] = p;
+    bool uni = uniform_pair(p);
     for (int k = 0; k < 3; ++k) {
-        c[k] /= 3.0;
-        cen[3 * f + k] = c[k];
-        atomic_min_d(&st->cbox[k], c[k]);
-        atomic_max_d(&st->cbox[3 + k], c[k]);
+        acc_min(&acc[p].cbox[k], clo[k], uni);
+        acc_max(&acc[p].cbox[3 + k], chi[k], uni);
     }
-    atomic_max_d(&st->coord_max, m);
+    acc_max(&acc[p].coord_max, m, uni);
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -112,33 +198,37 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     return x;
 }
 
-__global__ void k_morton(const double *__restrict__ cen, int64_t n, const BuildState *st,
-                         uint32_t *__restrict__ keys, int32_t *__restrict__ vals) {
+__global__ void k_morton(const double *__restrict__ cen, const int32_t *__restrict__ fpair, int64_t n,
+                         const PairAcc *acc, unsigned long long *__restrict__ keys, int32_t *__restrict__ vals) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n) return;
+    int p = fpair[f];
     uint32_t q[3];
     for (int k = 0; k < 3; ++k) {
-        double lo = ord2d(st->cbox[k]), hi = ord2d(st->cbox[3 + k]);
+        double lo = ord2d(acc[p].cbox[k]), hi = ord2d(acc[p].cbox[3 + k]);
         double ext = hi - lo;
         double t = ext > 0 ? (cen[3 * f + k] - lo) / ext : 0.5;
+        t = t == t ? t : 0.5;
         int v = (int)(t * 1023.0);
         q[k] = (uint32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
     }
-    keys[f] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    uint32_t mc = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    keys[f] = ((unsigned long long)p << 32) | mc;
     vals[f] = (int32_t)f;
 }
 
-__device__ __forceinline__ int delta(const uint32_t *__restrict__ keys, int64_t n, int64_t i, int64_t j) {
+__device__ __forceinline__ int delta(const unsigned long long *__restrict__ keys, int64_t n, int64_t i, int64_t j) {
     if (j < 0 || j >= n) return -1;
-    uint32_t a = keys[i], b = keys[j];
-    if (a == b) return 32 + __clz((uint32_t)(i ^ j));
-    return __clz(a ^ b);
+    unsigned long long a = keys[i], b = keys[j];
+    if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+    return __clzll(a ^ b);
 }
 
-// Karras 2012, one thread per internal node i in [0, n-2]
-__global__ void k_karras(const uint32_t *__restrict__ keys, int64_t n, int32_t *__restrict__ childL,
-                         int32_t *__restrict__ childR, int32_t *__restrict__ parentN,
-                         int32_t *__restrict__ parentL) {
+// Karras 2012, one thread per internal node i in [0, n-2]; also the node's
+// leaf range, and the list of nodes whose range spans more than one tile
+__global__ void k_karras(const unsigned long long *__restrict__ keys, int64_t n, int32_t *__restrict__ childL,
+                         int32_t *__restrict__ childR, int32_t *__restrict__ parentN, int32_t *__restrict__ parentL,
+                         int2 *__restrict__ range, int32_t *__restrict__ upper, BuildState *st) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
     int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
@@ -175,26 +265,30 @@ __global__ void k_karras(const uint32_t *__restrict__ keys, int64_t n, int32_t *
     }
     childL[i] = cl;
     childR[i] = cr;
+    range[i] = make_int2((int)lo, (int)hi);
+    if (lo / TILE != hi / TILE) upper[atomicAdd(&st->n_upper, 1)] = (int32_t)i;
 }
 
 // leaf data in sorted order: outward-rounded box, frame records, ids
-__global__ void k_leaves(const double *__restrict__ V, const int32_t *__restrict__ F,
-                         const int32_t *__restrict__ order, int64_t n, double ccx, double ccy,
-                         double ccz, float4 *__restrict__ lbox, float4 *__restrict__ fr32,
-                         double2 *__restrict__ fr64, int4 *__restrict__ ids, BuildState *st) {
+__global__ void k_leaves(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff,
+                         const int32_t *__restrict__ fpair, const int32_t *__restrict__ order, int64_t n,
+                         const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox, float4 *__restrict__ fr32,
+                         double2 *__restrict__ fr64, int4 *__restrict__ ids, PairAcc *acc, const BuildState *st) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || st->bad) return;
     int32_t f = order[i];
-    const double ctr[3] = {ccx, ccy, ccz};
+    int p = fpair[f];
+    PairSrc ps = src[p];
+    int64_t lf = f - foff[p];
     int32_t vid[3];
     V3<double> P[3];
     double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
     double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
     for (int j = 0; j < 3; ++j) {
-        vid[j] = F[3 * (int64_t)f + j];
+        vid[j] = ps.F[3 * lf + j];
         double c[3];
         for (int k = 0; k < 3; ++k) {
-            c[k] = V[3 * (int64_t)vid[j] + k] - ctr[k];
+            c[k] = ps.V[3 * (int64_t)vid[j] + k] - pairs[p].ctr[k];
             lo[k] = fmin(lo[k], c[k]);
             hi[k] = fmax(hi[k], c[k]);
         }
@@ -220,7 +314,6 @@ __global__ void k_leaves(const double *__restrict__ V, const int32_t *__restrict
     if (cy > 0) {
         ey = (1.0 / cy) * g;
     } else {
-        // any unit vector perpendicular to ex
         V3<double> ax = fabs(ex.x) <= fabs(ex.y) && fabs(ex.x) <= fabs(ex.z) ? mk(1.0, 0.0, 0.0)
                         : (fabs(ex.y) <= fabs(ex.z) ? mk(0.0, 1.0, 0.0) : mk(0.0, 0.0, 1.0));
         V3<double> t = cross(ex, ax);
@@ -234,21 +327,21 @@ __global__ void k_leaves(const double *__restrict__ V, const int32_t *__restrict
     fr32[4 * i + 1] = make_float4((float)ex.x, (float)ex.y, (float)ex.z, (float)cx);
     fr32[4 * i + 2] = make_float4((float)ey.x, (float)ey.y, (float)ey.z, (float)cy);
     fr32[4 * i + 3] = make_float4((float)ibc, (float)ica, (float)Lb, 0.f);
-    double2 *p = fr64 + 8 * i;
-    p[0] = make_double2(A.x, A.y);
-    p[1] = make_double2(A.z, Lb);
-    p[2] = make_double2(ex.x, ex.y);
-    p[3] = make_double2(ex.z, cx);
-    p[4] = make_double2(ey.x, ey.y);
-    p[5] = make_double2(ey.z, cy);
-    p[6] = make_double2(ibc, ica);
-    p[7] = make_double2(Lb, 0.0);
-    ids[i] = make_int4(vid[k], vid[(k + 1) % 3], vid[(k + 2) % 3], f);
-    atomic_max_d(&st->edge_max, Lb);
+    double2 *q = fr64 + 8 * i;
+    q[0] = make_double2(A.x, A.y);
+    q[1] = make_double2(A.z, Lb);
+    q[2] = make_double2(ex.x, ex.y);
+    q[3] = make_double2(ex.z, cx);
+    q[4] = make_double2(ey.x, ey.y);
+    q[5] = make_double2(ey.z, cy);
+    q[6] = make_double2(ibc, ica);
+    q[7] = make_double2(Lb, 0.0);
+    ids[i] = make_int4(vid[k], vid[(k + 1) % 3], vid[(k + 2) % 3], (int32_t)lf);
+    atomicMax(&acc[p].edge_max, d2ord(Lb));
 }
 
-__device__ __forceinline__ void load_box(const float4 *__restrict__ nbox, const float4 *__restrict__ lbox,
-                                         int32_t c, float4 &lo, float4 &hi) {
+__device__ __forceinline__ void load_box(const float4 *nbox, const float4 *__restrict__ lbox, int32_t c, float4 &lo,
+                                         float4 &hi) {
     if (c >= 0) {
         lo = nbox[2 * (int64_t)c];
         hi = nbox[2 * (int64_t)c + 1];
@@ -258,23 +351,73 @@ __device__ __forceinline__ void load_box(const float4 *__restrict__ nbox, const 
     }
 }
 
-// bottom-up union of child boxes; the second thread to reach a node builds it
-__global__ void k_refit(int64_t n, const int32_t *__restrict__ childL, const int32_t *__restrict__ childR,
-                        const int32_t *__restrict__ parentN, const int32_t *__restrict__ parentL,
-                        const float4 *__restrict__ lbox, float4 *nbox, int32_t *counter) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void union_box(const float4 *nbox, const float4 *__restrict__ lbox, int32_t cl, int32_t cr,
+                                          float4 *out) {
+    float4 l0, h0, l1, h1;
+    load_box(nbox, lbox, cl, l0, h0);
+    load_box(nbox, lbox, cr, l1, h1);
+    out[0] = make_float4(fminf(l0.x, l1.x), fminf(l0.y, l1.y), fminf(l0.z, l1.z), 0.f);
+    out[1] = make_float4(fmaxf(h0.x, h1.x), fmaxf(h0.y, h1.y), fmaxf(h0.z, h1.z), 0.f);
+}
+
+// nodes inside one tile: bottom-up, the second thread of the workgroup to
+// reach a node builds it (workgroup-scope counters)
+__global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *__restrict__ childL,
+                                                      const int32_t *__restrict__ childR,
+                                                      const int32_t *__restrict__ parentN,
+                                                      const int32_t *__restrict__ parentL,
+                                                      const int2 *__restrict__ range, const float4 *__restrict__ lbox,
+                                                      float4 *nbox, int32_t *counter) {
+    int64_t i = (int64_t)blockIdx.x * TILE + threadIdx.x;
     if (i >= n) return;
+    const int64_t t0 = (int64_t)blockIdx.x * TILE, t1 = t0 + TILE - 1;
     int32_t p = parentL[i];
     while (p >= 0) {
-        int old = __hip_atomic_fetch_add(&counter[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int2 r = range[p];
+        if (r.x < t0 || r.y > t1) return; // spans tiles: left to the upper pass
+        int old = __hip_atomic_fetch_add(&counter[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == 0) return;
-        float4 l0, h0, l1, h1;
-        load_box(nbox, lbox, childL[p], l0, h0);
-        load_box(nbox, lbox, childR[p], l1, h1);
-        nbox[2 * (int64_t)p] = make_float4(fminf(l0.x, l1.x), fminf(l0.y, l1.y), fminf(l0.z, l1.z), 0.f);
-        nbox[2 * (int64_t)p + 1] = make_float4(fmaxf(h0.x, h1.x), fmaxf(h0.y, h1.y), fmaxf(h0.z, h1.z), 0.f);
-        if (p == 0) return;
+        union_box(nbox, lbox, childL[p], childR[p], nbox + 2 * (int64_t)p);
         p = parentN[p];
+    }
+}
+
+// nodes spanning tiles: one workgroup, repeated sweeps until every node whose
+// children are ready has been built (the number of sweeps is the height of
+// the tree above the tiles)
+__global__ __launch_bounds__(1024) void k_refit_upper(const int32_t *__restrict__ upper, const BuildState *st,
+                                                      const int32_t *__restrict__ childL,
+                                                      const int32_t *__restrict__ childR,
+                                                      const int2 *__restrict__ range, const float4 *__restrict__ lbox,
+                                                      float4 *nbox, int32_t *done) {
+    __shared__ int changed;
+    const int nup = st->n_upper;
+    // done[u] = sweep that built u, plus one; a child counts as ready only if
+    // it was built in an earlier sweep, whose stores the barrier has published
+    int sweep = 0;
+    auto ready = [&](int32_t c) {
+        if (c < 0) return true;
+        int2 r = range[c];
+        if (r.x / TILE == r.y / TILE) return true;
+        int dc = done[c];
+        return dc != 0 && dc <= sweep;
+    };
+    for (;; ++sweep) {
+        __syncthreads();
+        if (threadIdx.x == 0) changed = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < nup; k += blockDim.x) {
+            int32_t u = upper[k];
+            if (done[u]) continue;
+            int32_t cl = childL[u], cr = childR[u];
+            if (ready(cl) && ready(cr)) {
+                union_box(nbox, lbox, cl, cr, nbox + 2 * (int64_t)u);
+                done[u] = sweep + 1;
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        if (!changed) break;
     }
 }
 
@@ -295,16 +438,22 @@ __global__ void k_node_records(int64_t ninternal, const int32_t *__restrict__ ch
     out[i] = r;
 }
 
-// a one-triangle soup: a root whose two children are the single leaf
-__global__ void k_single_root(const float4 *__restrict__ lbox, NodeRec *out) {
-    float4 lo = lbox[0], hi = lbox[1];
-    NodeRec r;
-    int32_t c = ~0;
-    r.a = make_float4(lo.x, lo.y, lo.z, __builtin_bit_cast(float, c));
-    r.b = make_float4(hi.x, hi.y, hi.z, __builtin_bit_cast(float, c));
-    r.c = make_float4(lo.x, lo.y, lo.z, 0.f);
-    r.d = make_float4(hi.x, hi.y, hi.z, 0.f);
-    out[0] = r;
+// root of each pair: the internal node whose leaf range is exactly the pair's
+__global__ void k_pair_roots(int64_t ninternal, const int2 *__restrict__ range, BvhPair *pairs, int npairs,
+                             const unsigned long long *__restrict__ keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninternal) return;
+    int2 r = range[i];
+    int p = (int)(keys[r.x] >> 32);
+    if (p < 0 || p >= npairs) return;
+    if (pairs[p].tri_begin == r.x && pairs[p].tri_end == (int64_t)r.y + 1) pairs[p].root = (int32_t)i;
+}
+
+__global__ void k_pair_finish(const PairAcc *acc, int npairs, BvhPair *pairs) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    pairs[p].coord_max = ord2d(acc[p].coord_max);
+    pairs[p].edge_max = ord2d(acc[p].edge_max);
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -312,23 +461,49 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// build scratch, reused between builds on the same device; kept until the
+// process ends (never destroyed: the HIP runtime may be gone by static
+// destruction). A build that finds it busy uses a private one.
+struct BuildScratch {
+    std::mutex mu;
+    DBuf mem, sort_tmp, src;
+};
+std::mutex g_scratch_mu;
+BuildScratch *g_scratch[64] = {};
+BuildScratch *scratch_for(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    BuildScratch *&b = g_scratch[dev & 63];
+    if (!b) b = new BuildScratch();
+    return b;
+}
+
 } // namespace
 
-Bvh *build_bvh(const double *VB, int64_t mB, const int32_t *FB, int64_t nB, hipStream_t s) {
-    if (nB <= 0 || mB <= 0 || !VB || !FB) throw Error{HD_E_INVALID, "empty soup B"};
-    if (nB >= (int64_t(1) << 30)) throw Error{HD_E_INVALID, "soup B too large (>= 2^30 faces)"};
+Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int32_t *const *FB, const int64_t *nBp,
+               hipStream_t s) {
+    if (npairs <= 0) throw Error{HD_E_INVALID, "no soup"};
+    std::vector<int64_t> foff(npairs + 1, 0);
+    for (int p = 0; p < npairs; ++p) {
+        if (nBp[p] <= 0 || mB[p] <= 0 || !VB[p] || !FB[p]) throw Error{HD_E_INVALID, "empty soup B"};
+        foff[p + 1] = foff[p] + nBp[p];
+    }
+    const int64_t n = foff[npairs];
+    if (n >= (int64_t(1) << 30)) throw Error{HD_E_INVALID, "soups B too large (>= 2^30 faces)"};
     Bvh *b = new Bvh();
     try {
         HD_HIP(hipGetDevice(&b->device));
-        b->nB = nB;
-        b->mB = mB;
+        BuildScratch *shared = scratch_for(b->device);
+        std::unique_lock<std::mutex> lk(shared->mu, std::try_to_lock);
+        std::unique_ptr<BuildScratch> priv;
+        if (!lk.owns_lock()) priv.reset(new BuildScratch());
+        BuildScratch &sc = lk.owns_lock() ? *shared : *priv;
+        b->npairs = npairs;
+        b->nB = n;
         hipEvent_t e0, e1;
         HD_HIP(hipEventCreate(&e0));
         HD_HIP(hipEventCreate(&e1));
         HD_HIP(hipEventRecord(e0, s));
-        const int64_t n = nB;
         const int64_t ni = n > 1 ? n - 1 : 1;
-        // scratch layout
         size_t off = 0;
         auto take = [&](size_t bytes) {
             size_t o = off;
@@ -336,78 +511,102 @@ Bvh *build_bvh(const double *VB, int64_t mB, const int32_t *FB, int64_t nB, hipS
             return o;
         };
         size_t o_state = take(sizeof(BuildState));
+        size_t o_acc = take(npairs * sizeof(PairAcc));
         size_t o_cen = take(n * 3 * sizeof(double));
-        size_t o_keys = take(n * sizeof(uint32_t));
+        size_t o_fpair = take(n * sizeof(int32_t));
+        size_t o_keys = take(n * sizeof(unsigned long long));
         size_t o_vals = take(n * sizeof(int32_t));
-        size_t o_keys2 = take(n * sizeof(uint32_t));
+        size_t o_keys2 = take(n * sizeof(unsigned long long));
         size_t o_vals2 = take(n * sizeof(int32_t));
         size_t o_cl = take(ni * sizeof(int32_t));
         size_t o_cr = take(ni * sizeof(int32_t));
         size_t o_pn = take(ni * sizeof(int32_t));
         size_t o_pl = take(n * sizeof(int32_t));
         size_t o_cnt = take(ni * sizeof(int32_t));
+        size_t o_range = take(ni * sizeof(int2));
+        size_t o_upper = take(ni * sizeof(int32_t));
         size_t o_lbox = take(n * 2 * sizeof(float4));
         size_t o_nbox = take(ni * 2 * sizeof(float4));
-        b->scratch.reserve(off);
-        char *base = b->scratch.as<char>();
+        sc.mem.reserve(off);
+        char *base = sc.mem.as<char>();
         BuildState *st = (BuildState *)(base + o_state);
+        PairAcc *acc = (PairAcc *)(base + o_acc);
         double *cen = (double *)(base + o_cen);
-        uint32_t *keys = (uint32_t *)(base + o_keys);
+        int32_t *fpair = (int32_t *)(base + o_fpair);
+        unsigned long long *keys = (unsigned long long *)(base + o_keys);
         int32_t *vals = (int32_t *)(base + o_vals);
-        uint32_t *keys2 = (uint32_t *)(base + o_keys2);
+        unsigned long long *keys2 = (unsigned long long *)(base + o_keys2);
         int32_t *vals2 = (int32_t *)(base + o_vals2);
         int32_t *cl = (int32_t *)(base + o_cl);
         int32_t *cr = (int32_t *)(base + o_cr);
         int32_t *pn = (int32_t *)(base + o_pn);
         int32_t *pl = (int32_t *)(base + o_pl);
         int32_t *cnt = (int32_t *)(base + o_cnt);
+        int2 *range = (int2 *)(base + o_range);
+        int32_t *upper = (int32_t *)(base + o_upper);
         float4 *lbox = (float4 *)(base + o_lbox);
         float4 *nbox = (float4 *)(base + o_nbox);
 
-        k_init_state<<<1, 1, 0, s>>>(st);
-        k_faces_check<<<grid_for(n, BLK), BLK, 0, s>>>(VB, mB, FB, n, st);
-        HD_LAUNCH_CHECK();
-        BuildState hs;
-        HD_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-        HD_HIP(hipStreamSynchronize(s));
-        if (hs.bad) throw Error{HD_E_INVALID, "soup B has an out-of-range index or a non-finite coordinate"};
-        for (int k = 0; k < 3; ++k) b->center[k] = 0.5 * (ord2d(hs.bbox[k]) + ord2d(hs.bbox[3 + k]));
+        // per-pair sources and face offsets
+        std::vector<PairSrc> hsrc(npairs);
+        for (int p = 0; p < npairs; ++p) hsrc[p] = PairSrc{VB[p], FB[p], mB[p]};
+        sc.src.reserve(npairs * sizeof(PairSrc) + (npairs + 1) * sizeof(int64_t) + 256);
+        PairSrc *dsrc = sc.src.as<PairSrc>();
+        int64_t *dfoff = (int64_t *)(dsrc + npairs);
+        HD_HIP(hipMemcpyAsync(dsrc, hsrc.data(), npairs * sizeof(PairSrc), hipMemcpyHostToDevice, s));
+        HD_HIP(hipMemcpyAsync(dfoff, foff.data(), (npairs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        b->hpairs.assign(npairs, BvhPair{});
+        for (int p = 0; p < npairs; ++p) {
+            b->hpairs[p].tri_begin = foff[p];
+            b->hpairs[p].tri_end = foff[p + 1];
+            b->hpairs[p].nB = (int32_t)nBp[p];
+            b->hpairs[p].root = nBp[p] == 1 ? ~(int32_t)foff[p] : -1;
+        }
+        b->pairs.reserve(npairs * sizeof(BvhPair));
+        BvhPair *dpairs = b->pairs.as<BvhPair>();
+        HD_HIP(hipMemcpyAsync(dpairs, b->hpairs.data(), npairs * sizeof(BvhPair), hipMemcpyHostToDevice, s));
 
-        k_centroids<<<grid_for(n, BLK), BLK, 0, s>>>(VB, FB, n, b->center[0], b->center[1], b->center[2],
-                                                     cen, st);
-        k_morton<<<grid_for(n, BLK), BLK, 0, s>>>(cen, n, st, keys, vals);
+        k_init<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, st);
+        k_faces_check<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, acc, st);
+        k_pair_centres<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs);
+        k_centroids<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, dpairs, cen, fpair, acc, st);
+        k_morton<<<grid_for(n, BLK), BLK, 0, s>>>(cen, fpair, n, acc, keys, vals);
         HD_LAUNCH_CHECK();
-        DBuf sort_tmp;
-        radix_sort_u32(keys, vals, keys2, vals2, n, 30, sort_tmp, s);
+        int pair_bits = 0;
+        while ((1 << pair_bits) < npairs) ++pair_bits;
+        radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, s);
 
         b->nodes.reserve(ni * sizeof(NodeRec));
         b->frames32.reserve(n * 4 * sizeof(float4));
         b->frames64.reserve(n * 8 * sizeof(double2));
         b->ids.reserve(n * sizeof(int4));
-        k_leaves<<<grid_for(n, BLK), BLK, 0, s>>>(VB, FB, vals, n, b->center[0], b->center[1], b->center[2],
-                                                  lbox, b->frames32.as<float4>(), b->frames64.as<double2>(),
-                                                  b->ids.as<int4>(), st);
+        k_leaves<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, fpair, vals, n, dpairs, lbox, b->frames32.as<float4>(),
+                                                  b->frames64.as<double2>(), b->ids.as<int4>(), acc, st);
         HD_LAUNCH_CHECK();
-        if (n == 1) {
-            k_single_root<<<1, 1, 0, s>>>(lbox, b->nodes.as<NodeRec>());
-        } else {
+        if (n > 1) {
             k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(pn, ni, -1);
             k_fill_i32<<<grid_for(n, BLK), BLK, 0, s>>>(pl, n, -1);
             k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(cnt, ni, 0);
-            k_karras<<<grid_for(ni, BLK), BLK, 0, s>>>(keys, n, cl, cr, pn, pl);
-            k_refit<<<grid_for(n, BLK), BLK, 0, s>>>(n, cl, cr, pn, pl, lbox, nbox, cnt);
+            k_karras<<<grid_for(ni, BLK), BLK, 0, s>>>(keys, n, cl, cr, pn, pl, range, upper, st);
+            k_refit_tiles<<<grid_for(n, TILE), TILE, 0, s>>>(n, cl, cr, pn, pl, range, lbox, nbox, cnt);
+            k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(cnt, ni, 0);
+            k_refit_upper<<<1, 1024, 0, s>>>(upper, st, cl, cr, range, lbox, nbox, cnt);
             k_node_records<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, cl, cr, nbox, lbox, b->nodes.as<NodeRec>());
+            k_pair_roots<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, range, dpairs, npairs, keys);
         }
+        k_pair_finish<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs);
         HD_LAUNCH_CHECK();
+        BuildState hs;
         HD_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        HD_HIP(hipMemcpyAsync(b->hpairs.data(), dpairs, npairs * sizeof(BvhPair), hipMemcpyDeviceToHost, s));
         HD_HIP(hipEventRecord(e1, s));
         HD_HIP(hipStreamSynchronize(s));
-        b->coord_max = ord2d(hs.coord_max);
-        b->edge_max = ord2d(hs.edge_max);
         HD_HIP(hipEventElapsedTime(&b->ms_build, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        b->scratch.release();
+        if (hs.bad) throw Error{HD_E_INVALID, "soup B has an out-of-range index or a non-finite coordinate"};
+        for (int p = 0; p < npairs; ++p)
+            if (b->hpairs[p].nB > 1 && b->hpairs[p].root < 0) throw Error{HD_E_INTERNAL, "pair subtree root not found"};
         return b;
     } catch (...) {
         delete b;

@@ -1,0 +1,1376 @@
+// hd_engine.hip -- the branch-and-bound rounds on the GPU, for one pair or
+// many pairs at once, and the C ABI.
+//
+// Round 0 queries every referenced vertex of A, raises the lower bound L of
+// its pair (a vertex distance is a lower bound of h: Branch and bound
+// subsection) and bounds every face of A with the cascade. Each later round
+// takes the active frontier (upper bound above L + eps), optionally the
+// sub-batch with the largest upper bounds (the paper's priority order),
+// splits every selected triangle 1->4 at its edge midpoints, queries the three
+// midpoints (seeded with the closest faces of the edge's endpoints), raises
+// L, bounds the four children and appends them to the active list (to split
+// again), the parked list (within eps of L: kept for U, never split) or drops
+// them (below L). The loop ends when no triangle is active; then every pair
+// has U - L <= eps (the paper's stopping rule). The final step re-evaluates
+// the parked triangles' bounds in FP64.
+//
+// All pairs of a batched call share the kernels: records carry their pair id
+// and every per-pair quantity (centre, BVH root, L, U, eps, margins) is read
+// from the pair table. One host read-back per round returns the list sizes.
+#include <math.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <functional>
+#include <mutex>
+
+#include "hd_kernels.hpp"
+
+namespace hd {
+
+namespace {
+
+constexpr int QBLOCK = 128;   // query kernel block
+constexpr int QSTACK = 24;    // LDS stack entries per lane
+constexpr int SMALL_STACK = 4; // test hook: tiny LDS stack, forces the deep path
+constexpr int DEEP_STACK = 256;
+constexpr int DEEP_SLOTS = 4096; // concurrent deep traversals
+constexpr int BLK = 256;
+constexpr int NW = BLK / 64;
+
+struct Ctl {
+    unsigned long long queries, evals, boxes, bounded, q_leaves, q_boxes, rechecked;
+    unsigned long long discards[5];
+    unsigned long long act_next, park_next; // append counters of the current round
+    int bad;        // 1 invalid input, 2 traversal deeper than the fallback stack, 3 depth exhausted
+    int n_overflow; // queries whose LDS stack overflowed this round
+};
+
+struct PairSrcA {
+    const double *V;
+    const int32_t *F;
+    int64_t m;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long long v) {
+    v = wave_sum_u64(v);
+    if (__lane_id() == 0 && v) atomicAdd(ctr, v);
+}
+
+__device__ __forceinline__ int pair_of(const int64_t *__restrict__ off, int npairs, int64_t x) {
+    int lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool wave_uniform(int p) {
+    int p0 = __shfl(p, __ffsll((unsigned long long)__ballot(1)) - 1, 64);
+    return __ballot(p != p0) == 0;
+}
+__device__ __forceinline__ void acc_min(unsigned long long *a, double v, bool uni) {
+    if (uni) {
+        for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+        if (__lane_id() == 0) atomicMin(a, d2ord(v));
+    } else {
+        atomicMin(a, d2ord(v));
+    }
+}
+__device__ __forceinline__ void acc_max(unsigned long long *a, double v, bool uni) {
+    if (uni) {
+        for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        if (__lane_id() == 0) atomicMax(a, d2ord(v));
+    } else {
+        atomicMax(a, d2ord(v));
+    }
+}
+
+template <class T> HD_HD const Margins &margins_of(const PairDev &p);
+template <> HD_HD const Margins &margins_of<float>(const PairDev &p) { return p.m32; }
+template <> HD_HD const Margins &margins_of<double>(const PairDev &p) { return p.m64; }
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_ctl_init(Ctl *c) { memset(c, 0, sizeof(Ctl)); }
+
+__global__ void k_round_setup(Ctl *c, unsigned long long act_base, unsigned long long park_base) {
+    c->n_overflow = 0;
+    c->act_next = act_base;
+    c->park_next = park_base;
+}
+
+__global__ void k_pairs_init(PairDev *pd, const BvhPair *__restrict__ bp, int npairs) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    PairDev d;
+    memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 3; ++k) {
+        d.ctr[k] = bp[p].ctr[k];
+        d.bbox[k] = d2ord(__builtin_inf());
+        d.bbox[3 + k] = d2ord(-__builtin_inf());
+    }
+    d.root = bp[p].root;
+    d.Lord = d2ord(0.0);
+    d.Uord = d2ord(0.0);
+    d.Urounds = d2ord(0.0);
+    d.coord_max = d2ord(0.0);
+    pd[p] = d;
+}
+
+// Validate A's faces, gather every pair's faces into one array with global
+// vertex ids (and the referenced vertices into one vertex array), mark the
+// referenced vertices, and accumulate each pair's bbox and coordinate range.
+__global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__restrict__ foff,
+                         const int64_t *__restrict__ voff, int npairs, int64_t n, int32_t *__restrict__ Fout,
+                         double *__restrict__ Vout, int32_t *__restrict__ fpair, int32_t *__restrict__ ref,
+                         PairDev *pd, Ctl *ctl) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = f < n;
+    int p = pair_of(foff, npairs, valid ? f : n - 1);
+    double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
+    double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
+    double cm = 0;
+    if (valid) {
+        PairSrcA s = src[p];
+        int64_t lf = f - foff[p];
+        fpair[f] = p;
+        for (int j = 0; j < 3; ++j) {
+            int32_t v = s.F[3 * lf + j];
+            if (v < 0 || v >= s.m) {
+                ctl->bad = 1;
+                Fout[3 * f + j] = (int32_t)voff[p];
+                continue;
+            }
+            int64_t vg = voff[p] + v;
+            Fout[3 * f + j] = (int32_t)vg;
+            ref[vg] = 1;
+            for (int k = 0; k < 3; ++k) {
+                double x = s.V[3 * (int64_t)v + k];
+                if (!__builtin_isfinite(x)) {
+                    ctl->bad = 1;
+                    x = 0;
+                }
+                Vout[3 * vg + k] = x;
+                lo[k] = fmin(lo[k], x);
+                hi[k] = fmax(hi[k], x);
+                cm = fmax(cm, fabs(x - pd[p].ctr[k]));
+            }
+        }
+    }
+    bool uni = wave_uniform(p);
+    for (int k = 0; k < 3; ++k) {
+        acc_min(&pd[p].bbox[k], lo[k], uni);
+        acc_max(&pd[p].bbox[3 + k], hi[k], uni);
+    }
+    acc_max(&pd[p].coord_max, cm, uni);
+}
+
+__device__ Margins make_margins(double u, double edge_max, double coord_max) {
+    Margins m;
+    m.mu_d = 16 * u;
+    m.mu_e = 48 * u;
+    m.mu_0 = u * (48 * edge_max + 12 * coord_max);
+    return m;
+}
+
+__global__ void k_pairs_post(PairDev *pd, const BvhPair *__restrict__ bp, int npairs, const double *__restrict__ eps,
+                             int eps_per_pair) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    double d2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        double e = ord2d(pd[p].bbox[3 + k]) - ord2d(pd[p].bbox[k]);
+        d2 += e * e;
+    }
+    double dA = sqrt(d2);
+    pd[p].dA = dA;
+    pd[p].eps_abs = eps[eps_per_pair ? p : 0] * dA;
+    double cm = fmax(ord2d(pd[p].coord_max), bp[p].coord_max);
+    pd[p].m32 = make_margins(Prec<float>::u, bp[p].edge_max, cm);
+    pd[p].m64 = make_margins(Prec<double>::u, bp[p].edge_max, cm);
+}
+
+// compact the referenced vertex ids (order preserving)
+__global__ void k_ref_scatter(const int32_t *__restrict__ ref, const int32_t *__restrict__ pos, int64_t m,
+                              int32_t *__restrict__ out) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < m && ref[v]) out[pos[v]] = (int32_t)v;
+}
+
+// ---------------------------------------------------------------------------
+// point queries
+// ---------------------------------------------------------------------------
+enum QMode { Q_POINTS = 0, Q_VERTICES = 1, Q_MIDPOINTS = 2 };
+
+template <class T> struct QueryOut {
+    T *d;
+    int *I;
+    T *q[3];
+    T *p[3];                 // query position (precision T), reused by the bound kernels
+    unsigned long long *key; // (d_lo, tag) key for the argmax (raise_L only)
+};
+
+template <class T> struct QueryIn {
+    int mode;
+    int npairs;
+    const double *P;         // Q_POINTS: n x 3, uncentred, pair 0
+    const int32_t *vids;     // Q_VERTICES: referenced vertex ids (global)
+    const int64_t *voff;     // Q_VERTICES: vertex offsets of the pairs
+    AView a;                 // Q_VERTICES / Q_MIDPOINTS
+    FrontierView<T> par;     // Q_MIDPOINTS: selected parents
+    const PairDev *pd;
+};
+
+struct QPoint {
+    V3<double> p;
+    int pair;
+    int64_t out;  // output slot
+    uint32_t tag; // argmax tie-break tag
+    int seed[2];  // candidate triangles (or -1)
+};
+
+template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
+    QPoint q;
+    q.seed[0] = q.seed[1] = -1;
+    if (in.mode == Q_POINTS) {
+        q.pair = 0;
+        const double *c = in.pd[0].ctr;
+        q.p = {in.P[3 * i] - c[0], in.P[3 * i + 1] - c[1], in.P[3 * i + 2] - c[2]};
+        q.out = i;
+        q.tag = 0;
+        return q;
+    }
+    if (in.mode == Q_VERTICES) {
+        int32_t v = in.vids[i];
+        q.pair = pair_of(in.voff, in.npairs, v);
+        q.p = a_vertex(in.a, q.pair, v);
+        q.out = v;
+        q.tag = mix32((uint32_t)v ^ 0x5bd1e995u);
+        return q;
+    }
+    int64_t j = i / 3;
+    int e = (int)(i - 3 * j);
+    int k = (e + 1) % 3;
+    int face = in.par.face[j], lvl = in.par.lvl[j] + 1;
+    int ba = in.par.ba[e][j] + in.par.ba[k][j], bb = in.par.bb[e][j] + in.par.bb[k][j];
+    q.pair = in.par.pair[j];
+    q.p = a_point(in.a, q.pair, face, lvl, ba, bb);
+    q.out = i;
+    q.tag = point_tag(face, lvl, ba, bb);
+    q.seed[0] = in.par.I[e][j];
+    q.seed[1] = in.par.I[k][j];
+    return q;
+}
+
+struct QueryCfg {
+    const NodeRec *nodes;
+    const int4 *ids;
+    int raise_L; // fold d - mu into the lower bound and the argmax key
+};
+
+template <class T>
+HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResult<T> &r, const QPoint &qp,
+                       const V3<T> &p, const QueryOut<T> &out, PairDev *pd) {
+    V3<T> q = p;
+    T d = T(__builtin_inf());
+    if (r.s >= 0) {
+        Frame<T> f = load_frame(bv.frames, r.s);
+        d = hsqrt(frame_dist2<T, true>(f, p, &q));
+    }
+    const int64_t o = qp.out;
+    out.d[o] = d;
+    out.I[o] = r.s < 0 ? 0 : r.s;
+    out.q[0][o] = q.x;
+    out.q[1][o] = q.y;
+    out.q[2][o] = q.z;
+    if (out.p[0]) {
+        out.p[0][o] = p.x;
+        out.p[1][o] = p.y;
+        out.p[2][o] = p.z;
+    }
+    if (cfg.raise_L) {
+        unsigned long long key = 0;
+        if (r.s >= 0) {
+            const Margins &m = margins_of<T>(pd[qp.pair]);
+            double dlo = (double)d - (m.mu_d * (double)d + m.mu_0);
+            if (dlo > 0) {
+                atomicMax(&pd[qp.pair].Lord, d2ord(dlo));
+                key = ((unsigned long long)f2ord(to_float_down(dlo)) << 32) | qp.tag;
+                atomicMax(&pd[qp.pair].round_key, key);
+            }
+        }
+        out.key[o] = key;
+    }
+}
+
+template <class T, int SD>
+__global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, int64_t n, QueryCfg cfg, BView<T> bv,
+                                                  QueryOut<T> out, PairDev *pd, Ctl *ctl, int32_t *ovf_list) {
+    __shared__ int s_node[SD * QBLOCK];
+    __shared__ float s_dist[SD * QBLOCK];
+    int64_t i = (int64_t)blockIdx.x * QBLOCK + threadIdx.x;
+    unsigned long long nb = 0, nl = 0, nq = 0;
+    if (i < n) {
+        QPoint qp = query_point(in, i);
+        V3<T> p = cvt<T>(qp.p);
+        QueryResult<T> r = empty_result<T>();
+        if (qp.seed[0] >= 0) visit_leaf(r, bv, cfg.ids, p, qp.seed[0]);
+        if (qp.seed[1] >= 0 && qp.seed[1] != qp.seed[0]) visit_leaf(r, bv, cfg.ids, p, qp.seed[1]);
+        LdsStack<SD, QBLOCK> stk{s_node, s_dist, 0};
+        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pd[qp.pair].root, stk, r);
+        nb = r.nbox;
+        nl = r.nleaf;
+        nq = 1;
+        if (r.overflow) {
+            int k = atomicAdd(&ctl->n_overflow, 1);
+            ovf_list[k] = (int32_t)i;
+        } else {
+            finish_query<T>(cfg, bv, r, qp, p, out, pd);
+        }
+    }
+    wave_add(&ctl->boxes, nb);
+    wave_add(&ctl->evals, nl);
+    wave_add(&ctl->q_leaves, nl);
+    wave_add(&ctl->q_boxes, nb);
+    wave_add(&ctl->queries, nq);
+}
+
+// queries whose LDS stack overflowed, redone with a deep stack in global
+// memory (grid-stride over the overflow list; exits at once when it is empty)
+template <class T>
+__global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<T> out, PairDev *pd, Ctl *ctl,
+                             const int32_t *ovf_list, int2 *stack_mem) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int novf = ctl->n_overflow;
+    unsigned long long nb = 0, nl = 0;
+    for (int k = tid; k < novf; k += DEEP_SLOTS) {
+        int64_t i = ovf_list[k];
+        QPoint qp = query_point(in, i);
+        V3<T> p = cvt<T>(qp.p);
+        QueryResult<T> r = empty_result<T>();
+        if (qp.seed[0] >= 0) visit_leaf(r, bv, cfg.ids, p, qp.seed[0]);
+        if (qp.seed[1] >= 0 && qp.seed[1] != qp.seed[0]) visit_leaf(r, bv, cfg.ids, p, qp.seed[1]);
+        GlobalStack stk{stack_mem + tid, DEEP_SLOTS, DEEP_STACK, 0};
+        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pd[qp.pair].root, stk, r);
+        nb += r.nbox;
+        nl += r.nleaf;
+        // a traversal deeper than the fallback stack fails the call; its
+        // (possibly suboptimal) result is still written so that later
+        // kernels read initialised indices
+        if (r.overflow) ctl->bad = 2;
+        finish_query<T>(cfg, bv, r, qp, p, out, pd);
+    }
+    wave_add(&ctl->boxes, nb);
+    wave_add(&ctl->evals, nl);
+}
+
+// after a query round: the query holding its pair's best key records its
+// exact position (keys are unique up to a tag collision of one point)
+template <class T>
+__global__ void k_argmax_finalize(QueryIn<T> in, int64_t n, const unsigned long long *__restrict__ keys,
+                                  PairDev *pd) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
+    unsigned long long key = keys[o];
+    if (key == 0) return;
+    QPoint qp = query_point(in, i);
+    PairDev &P = pd[qp.pair];
+    if (key == P.round_key && key > P.best_key) {
+        P.argmax_pos[0] = qp.p.x;
+        P.argmax_pos[1] = qp.p.y;
+        P.argmax_pos[2] = qp.p.z;
+        P.argmax_dirty = 1;
+    }
+}
+
+// FP64 distance of each pair's best vertex when it changed: the lower bound
+// then carries the FP64 margin instead of the FP32 one, which the recheck
+// band needs to park triangles within eps of it
+__global__ void k_L64(const NodeRec *nodes, BView<double> bv64, const int4 *ids, PairDev *pd, int npairs,
+                      int2 *stack_mem) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npairs) return;
+    PairDev &P = pd[p];
+    if (P.round_key > P.best_key) P.best_key = P.round_key;
+    P.round_key = 0;
+    if (!P.argmax_dirty) return;
+    P.argmax_dirty = 0;
+    V3<double> x = {P.argmax_pos[0], P.argmax_pos[1], P.argmax_pos[2]};
+    GlobalStack stk{stack_mem + p, npairs, DEEP_STACK, 0};
+    QueryResult<double> r = traverse<double>(nodes, bv64, ids, x, P.root, stk, empty_result<double>());
+    if (r.overflow || r.s < 0) return;
+    double d = sqrt(r.d2);
+    double dlo = d - (P.m64.mu_d * d + P.m64.mu_0);
+    P.L64 = dlo;
+    if (dlo > 0 && d2ord(dlo) > P.Lord) P.Lord = d2ord(dlo);
+}
+
+// ---------------------------------------------------------------------------
+// bounding children (or round-0 faces), classifying them and appending the
+// survivors to the active or parked list
+// ---------------------------------------------------------------------------
+struct ClassifyCfg {
+    CascadeCtx c;
+    int recheck; // FP32 + FP64 recheck of the ambiguity band
+    AView a;
+    BView<double> bv64;
+    IdView iv;
+    const PairDev *pd;
+};
+
+template <class T> struct Corner {
+    V3<T> v, q;
+    T d;
+    int I, ba, bb;
+};
+
+// returns the class (0 discard, 1 park, 2 active); *ub_out the bound
+template <class T>
+HD_D int classify(const Corner<T> cn[3], int pair, int face, int lvl, const ClassifyCfg &cc, const BView<T> &bv,
+                  float *ub_out, int *decider, int *evals, int *rechecked) {
+    Tri<T> t;
+    for (int i = 0; i < 3; ++i) {
+        t.v[i] = cn[i].v;
+        t.q[i] = cn[i].q;
+        t.d[i] = cn[i].d;
+        t.I[i] = cn[i].I;
+    }
+    const PairDev &P = cc.pd[pair];
+    const double L = ord2d(P.Lord), eps = P.eps_abs;
+    const Margins &m = margins_of<T>(P);
+    double ub = cascade<T>(t, L, cc.c, m, bv, cc.iv, decider, evals);
+    const double park_lim = eps * (1.0 - 1.0 / 1024.0 / 1024.0 / 1024.0);
+    if (cc.recheck) {
+        // the FP32 margin might hide a discard or a park: redo in FP64
+        double mu = tri_margin(t, m);
+        bool maybe_discard = ub >= L && ub - 2 * mu < L;
+        bool maybe_park = ub - L > park_lim && ub - 2 * mu - L <= park_lim;
+        if (maybe_discard || maybe_park) {
+            int ba[3] = {cn[0].ba, cn[1].ba, cn[2].ba}, bb[3] = {cn[0].bb, cn[1].bb, cn[2].bb};
+            double u64 = rebound64(cc.a, pair, face, lvl, ba, bb, t.I, cc.bv64, cc.iv, cc.c, P.m64, evals);
+            ub = hmin(ub, u64);
+            *rechecked += 1;
+        }
+    }
+    float ubf = (float)ub;
+    if ((double)ubf < ub) ubf = next_up(ubf);
+    *ub_out = ubf;
+    return ub < L ? 0 : (ub - L <= park_lim ? 1 : 2);
+}
+
+template <class T>
+HD_D void write_record(const FrontierView<T> &fo, int64_t o, const Corner<T> cn[3], float ub, int face, int lvl,
+                       int pair) {
+    for (int i = 0; i < 3; ++i) {
+        fo.v[3 * i][o] = cn[i].v.x;
+        fo.v[3 * i + 1][o] = cn[i].v.y;
+        fo.v[3 * i + 2][o] = cn[i].v.z;
+        fo.q[3 * i][o] = cn[i].q.x;
+        fo.q[3 * i + 1][o] = cn[i].q.y;
+        fo.q[3 * i + 2][o] = cn[i].q.z;
+        fo.d[i][o] = cn[i].d;
+        fo.I[i][o] = cn[i].I;
+        fo.ba[i][o] = cn[i].ba;
+        fo.bb[i][o] = cn[i].bb;
+    }
+    fo.ub[o] = ub;
+    fo.face[o] = face;
+    fo.lvl[o] = lvl;
+    fo.pair[o] = pair;
+}
+
+// block-aggregated append: one atomic per block and list; records of one
+// block stay in thread order
+struct Slots {
+    int64_t act, park;
+};
+__device__ Slots append_slots(bool act, bool park, Ctl *ctl) {
+    __shared__ int wa[NW], wp[NW];
+    __shared__ unsigned long long base_a, base_p;
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long ma = __ballot(act), mp = __ballot(park);
+    if (lane == 0) {
+        wa[w] = __popcll(ma);
+        wp[w] = __popcll(mp);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ta = 0, tp = 0;
+        for (int k = 0; k < NW; ++k) {
+            int a = wa[k], p = wp[k];
+            wa[k] = ta;
+            wp[k] = tp;
+            ta += a;
+            tp += p;
+        }
+        base_a = ta ? atomicAdd(&ctl->act_next, (unsigned long long)ta) : 0;
+        base_p = tp ? atomicAdd(&ctl->park_next, (unsigned long long)tp) : 0;
+    }
+    __syncthreads();
+    Slots s;
+    s.act = (int64_t)(base_a + wa[w] + __popcll(ma & lt));
+    s.park = (int64_t)(base_p + wp[w] + __popcll(mp & lt));
+    return s;
+}
+
+template <class T>
+HD_D void tally(Ctl *ctl, int cls, int decider, int evals, int rechecked, bool valid) {
+    unsigned long long dis[5] = {0, 0, 0, 0, 0};
+    if (valid && cls == 0) dis[decider] = 1;
+    for (int k = 0; k < 5; ++k) wave_add(&ctl->discards[k], dis[k]);
+    wave_add(&ctl->evals, valid ? (unsigned long long)evals : 0ull);
+    wave_add(&ctl->rechecked, valid ? (unsigned long long)rechecked : 0ull);
+    wave_add(&ctl->bounded, valid ? 1ull : 0ull);
+}
+
+// round 0: every face of A from the per-vertex query results
+template <class T>
+__global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__restrict__ F,
+                                                const int32_t *__restrict__ fpair, QueryOut<T> vq, ClassifyCfg cc,
+                                                BView<T> bv, FrontierView<T> act, FrontierView<T> park, Ctl *ctl) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = f < nA;
+    int cls = 0, decider = 0, evals = 0, rechecked = 0, pair = 0;
+    float ub = 0;
+    Corner<T> cn[3];
+    if (valid) {
+        pair = fpair[f];
+        for (int j = 0; j < 3; ++j) {
+            int32_t v = F[3 * f + j];
+            cn[j].v = {vq.p[0][v], vq.p[1][v], vq.p[2][v]};
+            cn[j].q = {vq.q[0][v], vq.q[1][v], vq.q[2][v]};
+            cn[j].d = vq.d[v];
+            cn[j].I = vq.I[v];
+            cn[j].ba = (j == 1);
+            cn[j].bb = (j == 2);
+        }
+        cls = classify<T>(cn, pair, (int)f, 0, cc, bv, &ub, &decider, &evals, &rechecked);
+    }
+    Slots sl = append_slots(valid && cls == 2, valid && cls == 1, ctl);
+    if (valid && cls == 2) write_record(act, sl.act, cn, ub, (int)f, 0, pair);
+    if (valid && cls == 1) write_record(park, sl.park, cn, ub, (int)f, 0, pair);
+    tally<T>(ctl, cls, decider, evals, rechecked, valid);
+}
+
+// round k: child c of selected parent c/4, from the parent's record and the
+// three midpoint query results (midpoint e joins parent vertices e and e+1)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_children(int64_t nsel, FrontierView<T> par, QueryOut<T> mq,
+                                                  ClassifyCfg cc, BView<T> bv, FrontierView<T> act,
+                                                  FrontierView<T> park, Ctl *ctl) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = c < 4 * nsel;
+    int cls = 0, decider = 0, evals = 0, rechecked = 0, pair = 0, face = 0, lvl = 0;
+    float ub = 0;
+    Corner<T> cn[3];
+    if (valid) {
+        int64_t j = c >> 2;
+        int kid = (int)(c & 3);
+        // corners: 0..2 parent vertices, 3..5 midpoints m01, m12, m20
+        const int kids[4][3] = {{0, 3, 5}, {3, 1, 4}, {5, 4, 2}, {3, 4, 5}};
+        for (int i = 0; i < 3; ++i) {
+            int s = kids[kid][i];
+            if (s < 3) {
+                cn[i].v = {par.v[3 * s][j], par.v[3 * s + 1][j], par.v[3 * s + 2][j]};
+                cn[i].q = {par.q[3 * s][j], par.q[3 * s + 1][j], par.q[3 * s + 2][j]};
+                cn[i].d = par.d[s][j];
+                cn[i].I = par.I[s][j];
+                cn[i].ba = 2 * par.ba[s][j];
+                cn[i].bb = 2 * par.bb[s][j];
+            } else {
+                int e = s - 3, e2 = (e + 1) % 3;
+                int64_t mi = 3 * j + e;
+                cn[i].v = {mq.p[0][mi], mq.p[1][mi], mq.p[2][mi]};
+                cn[i].q = {mq.q[0][mi], mq.q[1][mi], mq.q[2][mi]};
+                cn[i].d = mq.d[mi];
+                cn[i].I = mq.I[mi];
+                cn[i].ba = par.ba[e][j] + par.ba[e2][j];
+                cn[i].bb = par.bb[e][j] + par.bb[e2][j];
+            }
+        }
+        pair = par.pair[j];
+        face = par.face[j];
+        lvl = par.lvl[j] + 1;
+        // dyadic coordinates are int32 numerators over 2^lvl: level 30 is the
+        // deepest representable one
+        if (lvl > 30) ctl->bad = 3;
+        cls = classify<T>(cn, pair, face, lvl, cc, bv, &ub, &decider, &evals, &rechecked);
+    }
+    Slots sl = append_slots(valid && cls == 2, valid && cls == 1, ctl);
+    if (valid && cls == 2) write_record(act, sl.act, cn, ub, face, lvl, pair);
+    if (valid && cls == 1) write_record(park, sl.park, cn, ub, face, lvl, pair);
+    tally<T>(ctl, cls, decider, evals, rechecked, valid);
+}
+
+// ---------------------------------------------------------------------------
+// record movement and selection
+// ---------------------------------------------------------------------------
+template <class T>
+HD_D void copy_record(const FrontierView<T> &src, int64_t i, const FrontierView<T> &dst, int64_t o) {
+    for (int k = 0; k < 9; ++k) {
+        dst.v[k][o] = src.v[k][i];
+        dst.q[k][o] = src.q[k][i];
+    }
+    for (int k = 0; k < 3; ++k) {
+        dst.d[k][o] = src.d[k][i];
+        dst.I[k][o] = src.I[k][i];
+        dst.ba[k][o] = src.ba[k][i];
+        dst.bb[k][o] = src.bb[k][i];
+    }
+    dst.ub[o] = src.ub[i];
+    dst.face[o] = src.face[i];
+    dst.lvl[o] = src.lvl[i];
+    dst.pair[o] = src.pair[i];
+}
+
+// dst[o] = src[perm[o]] (perm null: src[off + o])
+template <class T>
+__global__ void k_gather(FrontierView<T> src, const int32_t *__restrict__ perm, int64_t off, int64_t n,
+                         FrontierView<T> dst) {
+    int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < n) copy_record(src, perm ? perm[o] : off + o, dst, o);
+}
+
+// selection keys: descending upper bound, ties by an order-independent tag
+template <class T>
+__global__ void k_sel_keys(FrontierView<T> fr, int64_t n, unsigned long long *__restrict__ keys,
+                           int32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t tag = point_tag(fr.face[i], fr.lvl[i], fr.ba[0][i] ^ (fr.ba[1][i] << 7) ^ (fr.ba[2][i] << 14),
+                             fr.bb[0][i] ^ (fr.bb[1][i] << 7) ^ (fr.bb[2][i] << 14));
+    keys[i] = ((unsigned long long)(~f2ord(fr.ub[i])) << 32) | tag;
+    vals[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// final FP64 step
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> bv64, IdView iv, CascadeCtx c,
+                          PairDev *pd, Ctl *ctl) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long ev = 0;
+    if (i < n) {
+        int pair = fr.pair[i];
+        int ba[3] = {fr.ba[0][i], fr.ba[1][i], fr.ba[2][i]};
+        int bb[3] = {fr.bb[0][i], fr.bb[1][i], fr.bb[2][i]};
+        int I[3] = {fr.I[0][i], fr.I[1][i], fr.I[2][i]};
+        int evals = 0;
+        double u64 = rebound64(a, pair, fr.face[i], fr.lvl[i], ba, bb, I, bv64, iv, c, pd[pair].m64, &evals);
+        double u32 = (double)fr.ub[i];
+        atomicMax(&pd[pair].Uord, d2ord(hmin(u64, u32)));
+        atomicMax(&pd[pair].Urounds, d2ord(u32));
+        ev = evals;
+    }
+    wave_add(&ctl->evals, ev);
+}
+
+// ---------------------------------------------------------------------------
+// test entry: all five bounds of given triangles
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_eval_bounds(const double *v, const double *d, const int32_t *Iorig, const double *q, int64_t n,
+                              const int32_t *inv_perm, int64_t nB, BView<T> bv, IdView iv, const PairDev *pd,
+                              double *out, int32_t *u3case) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < 3; ++k) {
+        int32_t f = Iorig[3 * i + k];
+        if (f < 0 || f >= nB) { // caller's face index out of range
+            for (int j = 0; j < 5; ++j) out[5 * i + j] = __builtin_nan("");
+            u3case[i] = 0;
+            return;
+        }
+    }
+    Tri<T> t;
+    const double *c = pd[0].ctr;
+    for (int k = 0; k < 3; ++k) {
+        t.v[k] = {T(v[9 * i + 3 * k] - c[0]), T(v[9 * i + 3 * k + 1] - c[1]), T(v[9 * i + 3 * k + 2] - c[2])};
+        t.q[k] = {T(q[9 * i + 3 * k] - c[0]), T(q[9 * i + 3 * k + 1] - c[1]), T(q[9 * i + 3 * k + 2] - c[2])};
+        t.d[k] = T(d[3 * i + k]);
+        t.I[k] = inv_perm[Iorig[3 * i + k]];
+    }
+    int ev = 0, cs = 0;
+    out[5 * i] = (t.I[0] == t.I[1] && t.I[1] == t.I[2]) ? (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) : __builtin_nan("");
+    out[5 * i + 1] = bound_u1(t);
+    out[5 * i + 2] = bound_u2(t);
+    out[5 * i + 3] = bound_u3(t, bv, iv, &cs, &ev);
+    out[5 * i + 4] = bound_u4(t);
+    u3case[i] = cs;
+}
+
+__global__ void k_inv_perm(const int4 *ids, int64_t n, int32_t *inv) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inv[ids[i].w] = (int32_t)i;
+}
+
+template <class T>
+__global__ void k_export_points(const QueryOut<T> r, int64_t n, const int4 *ids, const PairDev *pd, double *d,
+                                int32_t *I, double *Q) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *c = pd[0].ctr;
+    d[i] = (double)r.d[i];
+    I[i] = ids[r.I[i]].w;
+    if (Q) {
+        Q[3 * i] = (double)r.q[0][i] + c[0];
+        Q[3 * i + 1] = (double)r.q[1][i] + c[1];
+        Q[3 * i + 2] = (double)r.q[2][i] + c[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side: buffers
+// ---------------------------------------------------------------------------
+template <class T> struct FrontierBuf {
+    DBuf mem;
+    int64_t cap = 0;
+    FrontierView<T> v{};
+    static size_t per() { return 21 * sizeof(T) + 13 * sizeof(int32_t) + sizeof(float); }
+    void carve(char *p, int64_t c) {
+        auto take = [&](size_t sz) {
+            char *r = p;
+            p += ((size_t)c * sz + 255) & ~size_t(255);
+            return r;
+        };
+        for (int k = 0; k < 9; ++k) v.v[k] = (T *)take(sizeof(T));
+        for (int k = 0; k < 9; ++k) v.q[k] = (T *)take(sizeof(T));
+        for (int k = 0; k < 3; ++k) v.d[k] = (T *)take(sizeof(T));
+        for (int k = 0; k < 3; ++k) v.I[k] = (int *)take(4);
+        v.ub = (float *)take(4);
+        v.face = (int *)take(4);
+        v.lvl = (int *)take(4);
+        v.pair = (int *)take(4);
+        for (int k = 0; k < 3; ++k) v.ba[k] = (int *)take(4);
+        for (int k = 0; k < 3; ++k) v.bb[k] = (int *)take(4);
+    }
+    // grow to hold c records; the first `live` records are preserved
+    void ensure(int64_t c, int64_t live, hipStream_t s) {
+        if (c <= cap) return;
+        int64_t nc = std::max<int64_t>(c, cap + cap / 2);
+        DBuf nm;
+        nm.reserve((size_t)nc * per() + 40 * 256);
+        FrontierBuf<T> tmp;
+        tmp.carve(nm.as<char>(), nc);
+        if (live > 0)
+            k_gather<T><<<grid_for(live, BLK), BLK, 0, s>>>(v, nullptr, 0, live, tmp.v);
+        HD_LAUNCH_CHECK();
+        HD_HIP(hipStreamSynchronize(s));
+        mem.swap(nm);
+        cap = nc;
+        v = tmp.v;
+    }
+};
+
+template <class T> void swap_fb(FrontierBuf<T> &a, FrontierBuf<T> &b) {
+    a.mem.swap(b.mem);
+    std::swap(a.cap, b.cap);
+    std::swap(a.v, b.v);
+}
+
+template <class T> struct QBuf {
+    DBuf mem;
+    int64_t cap = 0;
+    QueryOut<T> o{};
+    void ensure(int64_t n) {
+        if (n <= cap) return;
+        int64_t nc = std::max<int64_t>(n, cap + cap / 2);
+        mem.reserve((size_t)nc * (sizeof(T) * 7 + 4 + 8) + 16 * 256);
+        char *p = mem.as<char>();
+        auto take = [&](size_t sz) {
+            char *r = p;
+            p += ((size_t)nc * sz + 255) & ~size_t(255);
+            return r;
+        };
+        o.d = (T *)take(sizeof(T));
+        o.I = (int *)take(4);
+        for (int k = 0; k < 3; ++k) o.q[k] = (T *)take(sizeof(T));
+        for (int k = 0; k < 3; ++k) o.p[k] = (T *)take(sizeof(T));
+        o.key = (unsigned long long *)take(8);
+        cap = nc;
+    }
+};
+
+// Buffers of the engine, kept between calls on one device (grow-only).
+template <class T> struct TypedWs {
+    FrontierBuf<T> act, act2, park;
+    QBuf<T> vq, mq;
+};
+struct Workspace {
+    std::mutex mu;
+    DBuf ctl, pd, src, offs, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
+    TypedWs<float> w32;
+    TypedWs<double> w64;
+    template <class T> TypedWs<T> &typed();
+};
+template <> TypedWs<float> &Workspace::typed<float>() { return w32; }
+template <> TypedWs<double> &Workspace::typed<double>() { return w64; }
+
+// one workspace per device, created on first use and kept until the process
+// ends (never destroyed: the HIP runtime may be gone by static destruction)
+std::mutex g_ws_mu;
+Workspace *g_ws[64] = {};
+Workspace *workspace_for(int dev) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace *&w = g_ws[dev & 63];
+    if (!w) w = new Workspace();
+    return w;
+}
+
+int parse_order(int32_t order, int out[4]) {
+    if (order <= 0) order = 1234;
+    int digits[8], n = 0;
+    while (order > 0 && n < 8) {
+        digits[n++] = order % 10;
+        order /= 10;
+    }
+    if (order > 0 || n > 4) return -1;
+    int used = 0;
+    for (int i = 0; i < n; ++i) {
+        int k = digits[n - 1 - i];
+        if (k < 1 || k > 4 || (used >> k) & 1) return -1;
+        used |= 1 << k;
+        out[i] = k;
+    }
+    return n;
+}
+
+struct Profiler {
+    hipStream_t s;
+    bool on = false;
+    std::vector<hipEvent_t> q, c; // begin/end pairs
+    void mark(std::vector<hipEvent_t> &v) {
+        if (!on) return;
+        hipEvent_t e;
+        HD_HIP(hipEventCreate(&e));
+        HD_HIP(hipEventRecord(e, s));
+        v.push_back(e);
+    }
+    static double sum(std::vector<hipEvent_t> &v) {
+        double ms = 0;
+        for (size_t i = 0; i + 1 < v.size(); i += 2) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, v[i], v[i + 1]) == hipSuccess) ms += t;
+        }
+        return ms;
+    }
+    ~Profiler() {
+        for (auto e : q) (void)hipEventDestroy(e);
+        for (auto e : c) (void)hipEventDestroy(e);
+    }
+};
+
+struct Input {
+    int npairs;
+    const double *const *VA;
+    const int64_t *mA;
+    const int32_t *const *FA;
+    const int64_t *nA;
+    const double *eps; // host: one value, or npairs values
+    int eps_per_pair;
+};
+
+// ---------------------------------------------------------------------------
+// the engine
+// ---------------------------------------------------------------------------
+template <class T>
+hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t s, Workspace &ws, double *LU,
+              hd_stats *stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int np = in.npairs;
+    if (np != B->npairs) throw Error{HD_E_INVALID, "pair count differs from the BVH's"};
+    hd_stats S;
+    std::memset(&S, 0, sizeof(S));
+    CascadeCtx cctx;
+    cctx.norder = parse_order(opt.order, cctx.order);
+    if (cctx.norder <= 0) throw Error{HD_E_INVALID, "bad cascade order"};
+    for (int p = 0; p < (in.eps_per_pair ? np : 1); ++p)
+        if (!(in.eps[p] > 0) || !std::isfinite(in.eps[p])) throw Error{HD_E_INVALID, "eps must be positive"};
+    std::vector<int64_t> foff(np + 1, 0), voff(np + 1, 0);
+    for (int p = 0; p < np; ++p) {
+        if (in.nA[p] <= 0 || in.mA[p] <= 0 || !in.VA[p] || !in.FA[p]) throw Error{HD_E_INVALID, "empty soup A"};
+        foff[p + 1] = foff[p] + in.nA[p];
+        voff[p + 1] = voff[p] + in.mA[p];
+    }
+    const int64_t nA = foff[np], mA = voff[np];
+    if (nA >= (int64_t(1) << 30) || mA >= (int64_t(1) << 31)) throw Error{HD_E_INVALID, "soup A too large"};
+
+    TypedWs<T> &tw = ws.typed<T>();
+    Profiler prof;
+    prof.s = s;
+    prof.on = opt.profile != 0;
+
+    // ---- small tables -----------------------------------------------------
+    ws.ctl.reserve(sizeof(Ctl));
+    Ctl *ctl = ws.ctl.as<Ctl>();
+    ws.pd.reserve(np * sizeof(PairDev));
+    PairDev *pd = ws.pd.as<PairDev>();
+    std::vector<PairSrcA> hsrc(np);
+    for (int p = 0; p < np; ++p) hsrc[p] = PairSrcA{in.VA[p], in.FA[p], in.mA[p]};
+    ws.src.reserve(np * sizeof(PairSrcA));
+    ws.offs.reserve((2 * (np + 1) + np) * sizeof(int64_t));
+    int64_t *dfoff = ws.offs.as<int64_t>();
+    int64_t *dvoff = dfoff + (np + 1);
+    double *deps = (double *)(dvoff + (np + 1));
+    HD_HIP(hipMemcpyAsync(ws.src.p, hsrc.data(), np * sizeof(PairSrcA), hipMemcpyHostToDevice, s));
+    HD_HIP(hipMemcpyAsync(dfoff, foff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HD_HIP(hipMemcpyAsync(dvoff, voff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HD_HIP(hipMemcpyAsync(deps, in.eps, (in.eps_per_pair ? np : 1) * sizeof(double), hipMemcpyHostToDevice, s));
+
+    // ---- ingest A ---------------------------------------------------------
+    ws.Vcat.reserve(mA * 3 * sizeof(double));
+    ws.Fcat.reserve(nA * 3 * sizeof(int32_t));
+    ws.fpair.reserve(nA * sizeof(int32_t));
+    ws.ref.reserve(2 * mA * sizeof(int32_t) + 512);
+    int32_t *ref = ws.ref.as<int32_t>();
+    int32_t *refpos = ref + ((mA + 63) / 64) * 64;
+    ws.small.reserve(4096);
+    int32_t *d_total = ws.small.as<int32_t>();
+    k_ctl_init<<<1, 1, 0, s>>>(ctl);
+    k_pairs_init<<<grid_for(np, 64), 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), np);
+    k_fill_i32<<<grid_for(mA, BLK), BLK, 0, s>>>(ref, mA, 0);
+    k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(ws.src.as<PairSrcA>(), dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
+                                              ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pd, ctl);
+    k_pairs_post<<<grid_for(np, 64), 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair);
+    scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
+    HD_LAUNCH_CHECK();
+    struct {
+        Ctl c;
+        int32_t nref;
+    } h0;
+    HD_HIP(hipMemcpyAsync(&h0.c, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HD_HIP(hipMemcpyAsync(&h0.nref, d_total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HD_HIP(hipStreamSynchronize(s));
+    if (h0.c.bad) throw Error{HD_E_INVALID, "soup A has an out-of-range index or a non-finite coordinate"};
+    const int64_t nref = h0.nref;
+    ws.vids.reserve(nref * sizeof(int32_t));
+    k_ref_scatter<<<grid_for(mA, BLK), BLK, 0, s>>>(ref, refpos, mA, ws.vids.as<int32_t>());
+
+    const BView<T> bv = [&] {
+        if constexpr (sizeof(T) == 4) return BView<float>{B->frames32.as<float4>()};
+        else return BView<double>{B->frames64.as<double2>()};
+    }();
+    const BView<double> bv64{B->frames64.as<double2>()};
+    const IdView iv{B->ids.as<int4>()};
+    const AView av{ws.Vcat.as<double>(), ws.Fcat.as<int32_t>(), pd};
+    const QueryCfg qcfg{B->nodes.as<NodeRec>(), B->ids.as<int4>(), 1};
+    ws.gstack.reserve((size_t)np * DEEP_STACK * sizeof(int2));
+    ws.deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
+    const bool small_stack = opt.stack_depth > 0 && opt.stack_depth < QSTACK;
+
+    auto run_queries = [&](const QueryIn<T> &qi, int64_t n, const QueryOut<T> &out) {
+        if (n <= 0) return;
+        ws.ovf.reserve((size_t)n * sizeof(int32_t));
+        prof.mark(prof.q);
+        if (small_stack)
+            k_query<T, SMALL_STACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pd, ctl,
+                                                                            ws.ovf.as<int32_t>());
+        else
+            k_query<T, QSTACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pd, ctl,
+                                                                       ws.ovf.as<int32_t>());
+        HD_LAUNCH_CHECK();
+        prof.mark(prof.q);
+        k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pd, ctl, ws.ovf.as<int32_t>(),
+                                                        ws.deep.as<int2>());
+        k_argmax_finalize<T><<<grid_for(n, BLK), BLK, 0, s>>>(qi, n, out.key, pd);
+        k_L64<<<grid_for(np, 64), 64, 0, s>>>(B->nodes.as<NodeRec>(), bv64, iv.ids, pd, np, ws.gstack.as<int2>());
+        HD_LAUNCH_CHECK();
+    };
+
+    // ---- round 0: vertex queries ------------------------------------------
+    tw.vq.ensure(mA);
+    {
+        QueryIn<T> qi{};
+        qi.mode = Q_VERTICES;
+        qi.npairs = np;
+        qi.vids = ws.vids.as<int32_t>();
+        qi.voff = dvoff;
+        qi.a = av;
+        qi.pd = pd;
+        k_round_setup<<<1, 1, 0, s>>>(ctl, 0, 0);
+        run_queries(qi, nref, tw.vq.o);
+    }
+
+    // ---- frontier buffers ---------------------------------------------------
+    int64_t cap0 = opt.capacity > 0 ? opt.capacity : std::max<int64_t>(int64_t(1) << 20, 4 * nA);
+    cap0 = std::max<int64_t>(cap0, nA);
+    tw.act.ensure(cap0, 0, s);
+    tw.act2.ensure(cap0, 0, s);
+    tw.park.ensure(cap0, 0, s);
+    const int64_t cap_limit = opt.capacity > 0 ? std::max<int64_t>(opt.capacity, nA) : (int64_t(1) << 30);
+
+    ClassifyCfg cc;
+    cc.c = cctx;
+    cc.recheck = (opt.precision == HD_PREC_FP32_RECHECK) && sizeof(T) == 4;
+    cc.a = av;
+    cc.bv64 = bv64;
+    cc.iv = iv;
+    cc.pd = pd;
+
+    // ---- round 0: bound every face ------------------------------------------
+    prof.mark(prof.c);
+    k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc, bv,
+                                                  tw.act.v, tw.park.v, ctl);
+    HD_LAUNCH_CHECK();
+    prof.mark(prof.c);
+    Ctl hc;
+    HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HD_HIP(hipStreamSynchronize(s));
+    int64_t nAct = (int64_t)hc.act_next, nPark = (int64_t)hc.park_next;
+
+    const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
+    double processed = (double)nA;
+    int64_t subdivided = 0;
+    int rounds = 0;
+    S.max_frontier = nAct + nPark;
+    hd_status status = HD_OK;
+    if (hc.bad == 2) status = HD_E_INTERNAL;
+    while (status == HD_OK && nAct > 0) {
+        if (opt.max_rounds > 0 && rounds >= opt.max_rounds) break;
+        // how many to split this round, growing the lists when allowed
+        int64_t K = nAct;
+        if (opt.subbatch > 0) K = std::min<int64_t>(K, opt.subbatch);
+        auto fits = [&](int64_t k) {
+            return nAct + 3 * k <= std::min(tw.act.cap, tw.act2.cap) && nPark + 4 * k <= tw.park.cap;
+        };
+        if (!fits(K)) {
+            int64_t need_act = std::min(cap_limit, nAct + 3 * K), need_park = std::min(cap_limit, nPark + 4 * K);
+            try {
+                tw.act.ensure(need_act, nAct, s);
+                tw.act2.ensure(need_act, 0, s);
+                tw.park.ensure(need_park, nPark, s);
+            } catch (const Error &e) {
+                if (e.st != HD_E_NOMEM) throw;
+            }
+            K = std::min<int64_t>(K, std::min((std::min(tw.act.cap, tw.act2.cap) - nAct) / 3,
+                                              (tw.park.cap - nPark) / 4));
+        }
+        if (K <= 0) {
+            status = HD_E_CAPACITY;
+            break;
+        }
+        if (processed + 4.0 * (double)K > budget) {
+            status = HD_E_CAPACITY;
+            break;
+        }
+        if (K < nAct) {
+            // largest upper bounds first (the paper's priority-queue order)
+            ws.sortbuf.reserve((size_t)nAct * 24 + 1024);
+            unsigned long long *keys = ws.sortbuf.as<unsigned long long>();
+            unsigned long long *keys2 = keys + nAct;
+            int32_t *vals = (int32_t *)(keys2 + nAct);
+            int32_t *vals2 = vals + nAct;
+            k_sel_keys<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, keys, vals);
+            radix_sort_u64(keys, vals, keys2, vals2, nAct, 64, ws.sort_tmp, s);
+            k_gather<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, vals, 0, nAct, tw.act2.v);
+            HD_LAUNCH_CHECK();
+            swap_fb(tw.act, tw.act2);
+        }
+        const int64_t rest = nAct - K;
+        k_round_setup<<<1, 1, 0, s>>>(ctl, (unsigned long long)rest, (unsigned long long)nPark);
+        // midpoints of the K selected parents
+        tw.mq.ensure(3 * K);
+        QueryIn<T> qi{};
+        qi.mode = Q_MIDPOINTS;
+        qi.npairs = np;
+        qi.a = av;
+        qi.par = tw.act.v;
+        qi.pd = pd;
+        run_queries(qi, 3 * K, tw.mq.o);
+        // the unselected remainder first, then the active children
+        if (rest > 0) k_gather<T><<<grid_for(rest, BLK), BLK, 0, s>>>(tw.act.v, nullptr, K, rest, tw.act2.v);
+        prof.mark(prof.c);
+        k_children<T><<<grid_for(4 * K, BLK), BLK, 0, s>>>(K, tw.act.v, tw.mq.o, cc, bv, tw.act2.v, tw.park.v, ctl);
+        HD_LAUNCH_CHECK();
+        prof.mark(prof.c);
+        HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HD_HIP(hipStreamSynchronize(s));
+        swap_fb(tw.act, tw.act2);
+        nAct = (int64_t)hc.act_next;
+        nPark = (int64_t)hc.park_next;
+        subdivided += K;
+        processed += 4.0 * (double)K;
+        ++rounds;
+        S.max_frontier = std::max<int64_t>(S.max_frontier, nAct + nPark);
+        if (hc.bad == 3) status = HD_E_CAPACITY; // depth exhausted: tolerance below what the arithmetic resolves
+        else if (hc.bad) status = HD_E_INTERNAL;
+    }
+
+    // ---- final FP64 step: U over every live triangle --------------------------
+    std::vector<PairDev> hp(np);
+    if (status == HD_OK) {
+        prof.mark(prof.c);
+        if (nPark > 0)
+            k_final_U<T><<<grid_for(nPark, BLK), BLK, 0, s>>>(tw.park.v, nPark, av, bv64, iv, cctx, pd, ctl);
+        if (nAct > 0)
+            k_final_U<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, av, bv64, iv, cctx, pd, ctl);
+        HD_LAUNCH_CHECK();
+        prof.mark(prof.c);
+    }
+    HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HD_HIP(hipMemcpyAsync(hp.data(), pd, np * sizeof(PairDev), hipMemcpyDeviceToHost, s));
+    HD_HIP(hipStreamSynchronize(s));
+    if (status == HD_OK && hc.bad == 2) status = HD_E_INTERNAL;
+    if (status == HD_OK) {
+        for (int p = 0; p < np; ++p) {
+            double L = ord2d(hp[p].Lord);
+            double U = std::max(L, ord2d(hp[p].Uord));
+            LU[2 * p] = L;
+            LU[2 * p + 1] = U;
+            if (nAct == 0 && U - L > hp[p].eps_abs) status = HD_E_INTERNAL;
+        }
+        if (nAct > 0 && opt.max_rounds <= 0) status = HD_E_INTERNAL;
+    }
+    S.rounds = rounds;
+    S.status = status;
+    S.nodes_bounded = (int64_t)hc.bounded;
+    S.subdivided = subdivided;
+    S.queries = (int64_t)hc.queries;
+    S.pt_tri_evals = (int64_t)hc.evals;
+    S.box_tests = (int64_t)hc.boxes;
+    for (int k = 0; k < 5; ++k) S.discards[k] = (int64_t)hc.discards[k];
+    S.rechecked64 = (int64_t)hc.rechecked;
+    S.parked_final = nPark;
+    S.query_leaf_evals = (int64_t)hc.q_leaves;
+    S.query_box_tests = (int64_t)hc.q_boxes;
+    S.dA = hp[0].dA;
+    S.eps_abs = hp[0].eps_abs;
+    S.mu_coef_d = margins_of<T>(hp[0]).mu_d;
+    S.mu_coef_0 = margins_of<T>(hp[0]).mu_0;
+    S.L_rounds = ord2d(hp[0].Lord);
+    S.U_rounds = std::max(S.L_rounds, ord2d(hp[0].Urounds));
+    if (prof.on) {
+        S.ms_query_kernels = Profiler::sum(prof.q);
+        S.ms_cascade_kernels = Profiler::sum(prof.c);
+        S.query_launches = (int64_t)prof.q.size() / 2;
+        S.cascade_launches = (int64_t)prof.c.size() / 2;
+    }
+    S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S;
+    return status;
+}
+
+} // namespace
+
+} // namespace hd
+
+// ============================================================================
+// C ABI
+// ============================================================================
+using namespace hd;
+
+static hd_status guard(const std::function<hd_status()> &fn) {
+    try {
+        return fn();
+    } catch (const Error &e) {
+        return e.st;
+    } catch (...) {
+        return HD_E_INTERNAL;
+    }
+}
+
+// the calling thread's device workspace, or a private one if another call
+// holds it
+struct WsLease {
+    Workspace *ws = nullptr;
+    Workspace *owned = nullptr;
+    std::unique_lock<std::mutex> lk;
+    WsLease() {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        Workspace *w = workspace_for(dev);
+        lk = std::unique_lock<std::mutex>(w->mu, std::try_to_lock);
+        if (lk.owns_lock()) {
+            ws = w;
+        } else {
+            owned = new Workspace();
+            ws = owned;
+        }
+    }
+    ~WsLease() { delete owned; }
+};
+
+static hd_status bound_any(const Input &in, hd_bvh Bh, const hd_options *opt, hd_stream_t stream, double *LU,
+                           hd_stats *stats) {
+    hd_options o;
+    hd_default_options(&o);
+    if (opt) o = *opt;
+    const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
+    return guard([&] {
+        WsLease lease;
+        std::vector<double> lu(2 * (size_t)in.npairs, NAN);
+        hd_status r;
+        if (o.precision == HD_PREC_FP64)
+            r = run<double>(in, B, o, (hipStream_t)stream, *lease.ws, lu.data(), stats);
+        else if (o.precision == HD_PREC_FP32 || o.precision == HD_PREC_FP32_RECHECK)
+            r = run<float>(in, B, o, (hipStream_t)stream, *lease.ws, lu.data(), stats);
+        else
+            return HD_E_INVALID;
+        if (r == HD_OK) std::copy(lu.begin(), lu.end(), LU);
+        return r;
+    });
+}
+
+extern "C" {
+
+const char *hd_status_str(hd_status s) {
+    switch (s) {
+    case HD_OK: return "ok";
+    case HD_E_INVALID: return "invalid argument";
+    case HD_E_CAPACITY: return "capacity, face budget or subdivision depth exceeded";
+    case HD_E_NOMEM: return "device allocation failed";
+    case HD_E_DEVICE: return "HIP runtime error";
+    case HD_E_INTERNAL: return "internal invariant failed";
+    }
+    return "unknown status";
+}
+
+void hd_default_options(hd_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = HD_PREC_FP32_RECHECK;
+    o->order = 1234;
+    o->budget_m = 1e7;
+}
+
+hd_status hd_build_bvh(const double *VB, int64_t mB, const int32_t *FB, int64_t nB, hd_stream_t stream,
+                       hd_bvh *out) {
+    return hd_build_bvh_batched(1, &VB, &mB, &FB, &nB, stream, out);
+}
+
+hd_status hd_build_bvh_batched(int32_t npairs, const double *const *VB, const int64_t *mB, const int32_t *const *FB,
+                               const int64_t *nB, hd_stream_t stream, hd_bvh *out) {
+    if (!out) return HD_E_INVALID;
+    *out = nullptr;
+    if (npairs <= 0 || !VB || !mB || !FB || !nB) return HD_E_INVALID;
+    return guard([&] {
+        Bvh *b = build_bvh(npairs, VB, mB, FB, nB, (hipStream_t)stream);
+        *out = reinterpret_cast<hd_bvh>(b);
+        return HD_OK;
+    });
+}
+
+void hd_free_bvh(hd_bvh b) { delete reinterpret_cast<Bvh *>(b); }
+
+hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, hd_bvh Bh, double eps,
+                   const hd_options *opt, hd_stream_t stream, double LU_out[2], hd_stats *stats) {
+    if (LU_out) LU_out[0] = LU_out[1] = NAN;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->status = HD_E_INVALID;
+    }
+    if (!LU_out || !Bh || !VA || !FA || mA <= 0 || nA <= 0) return HD_E_INVALID;
+    Input in{1, &VA, &mA, &FA, &nA, &eps, 0};
+    hd_status st = bound_any(in, Bh, opt, stream, LU_out, stats);
+    if (stats) stats->status = st;
+    return st;
+}
+
+hd_status hd_bound_batched(int32_t npairs, const double *const *VA, const int64_t *mA, const int32_t *const *FA,
+                           const int64_t *nA, hd_bvh Bh, const double *eps, int32_t eps_per_pair,
+                           const hd_options *opt, hd_stream_t stream, double *LU_out, hd_stats *stats) {
+    if (LU_out)
+        for (int p = 0; p < npairs; ++p) LU_out[2 * p] = LU_out[2 * p + 1] = NAN;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->status = HD_E_INVALID;
+    }
+    if (npairs <= 0 || !LU_out || !Bh || !VA || !mA || !FA || !nA || !eps) return HD_E_INVALID;
+    Input in{npairs, VA, mA, FA, nA, eps, eps_per_pair ? 1 : 0};
+    hd_status st = bound_any(in, Bh, opt, stream, LU_out, stats);
+    if (stats) stats->status = st;
+    return st;
+}
+
+hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, double *d, int32_t *I,
+                             double *Q, hd_stream_t stream) {
+    if (!Bh || nP < 0 || (nP > 0 && (!P || !d || !I))) return HD_E_INVALID;
+    if (nP == 0) return HD_OK;
+    const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
+    hipStream_t s = (hipStream_t)stream;
+    return guard([&] {
+        DBuf ctlb, pdb, ovf, deep;
+        ctlb.reserve(sizeof(Ctl));
+        pdb.reserve(sizeof(PairDev));
+        ovf.reserve((size_t)nP * sizeof(int32_t));
+        deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
+        Ctl *ctl = ctlb.as<Ctl>();
+        PairDev *pd = pdb.as<PairDev>();
+        k_ctl_init<<<1, 1, 0, s>>>(ctl);
+        k_pairs_init<<<1, 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), 1);
+        const QueryCfg cfg{B->nodes.as<NodeRec>(), B->ids.as<int4>(), 0};
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            QBuf<T> qb;
+            qb.ensure(nP);
+            QueryIn<T> qi{};
+            qi.mode = Q_POINTS;
+            qi.npairs = 1;
+            qi.P = P;
+            qi.pd = pd;
+            BView<T> bv;
+            if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
+            else bv = BView<double>{B->frames64.as<double2>()};
+            k_query<T, QSTACK><<<grid_for(nP, QBLOCK), QBLOCK, 0, s>>>(qi, nP, cfg, bv, qb.o, pd, ctl,
+                                                                        ovf.as<int32_t>());
+            k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pd, ctl, ovf.as<int32_t>(),
+                                                            deep.as<int2>());
+            k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pd, d, I, Q);
+            HD_LAUNCH_CHECK();
+            HD_HIP(hipStreamSynchronize(s));
+        };
+        if (precision == HD_PREC_FP64) go(double{});
+        else go(float{});
+        Ctl hc;
+        HD_HIP(hipMemcpy(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost));
+        if (hc.bad == 2) return HD_E_INTERNAL;
+        return HD_OK;
+    });
+}
+
+hd_status hd_eval_bounds(const double *v, const double *dd, const int32_t *I, const double *q, int64_t n, hd_bvh Bh,
+                         int32_t precision, double *out, int32_t *u3_case, hd_stream_t stream) {
+    if (!Bh || n < 0 || (n > 0 && (!v || !dd || !I || !q || !out || !u3_case))) return HD_E_INVALID;
+    if (n == 0) return HD_OK;
+    const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
+    hipStream_t s = (hipStream_t)stream;
+    return guard([&] {
+        DBuf inv, pdb;
+        inv.reserve((size_t)B->nB * sizeof(int32_t));
+        pdb.reserve(sizeof(PairDev));
+        PairDev *pd = pdb.as<PairDev>();
+        k_pairs_init<<<1, 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), 1);
+        k_inv_perm<<<grid_for(B->nB, BLK), BLK, 0, s>>>(B->ids.as<int4>(), B->nB, inv.as<int32_t>());
+        IdView iv{B->ids.as<int4>()};
+        if (precision == HD_PREC_FP64)
+            k_eval_bounds<double><<<grid_for(n, BLK), BLK, 0, s>>>(v, dd, I, q, n, inv.as<int32_t>(), B->nB,
+                                                                   BView<double>{B->frames64.as<double2>()}, iv, pd,
+                                                                   out, u3_case);
+        else
+            k_eval_bounds<float><<<grid_for(n, BLK), BLK, 0, s>>>(v, dd, I, q, n, inv.as<int32_t>(), B->nB,
+                                                                  BView<float>{B->frames32.as<float4>()}, iv, pd,
+                                                                  out, u3_case);
+        HD_LAUNCH_CHECK();
+        HD_HIP(hipStreamSynchronize(s));
+        return HD_OK;
+    });
+}
+
+} // extern "C"

@@ -1,6 +1,6 @@
 // hd_internal.hpp -- host-side declarations shared by the library's
-// translation units: the BVH handle, device-buffer helpers, error handling
-// and the data-parallel primitives (scan, radix sort).
+// translation units: the (multi-pair) BVH handle, device-buffer helpers,
+// error handling and the data-parallel primitives (scan, radix sort).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -51,42 +51,59 @@ struct DBuf {
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             p = nullptr;
+            (void)hipGetLastError();
             throw Error{HD_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
         }
         bytes = b;
     }
+    void swap(DBuf &o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
     template <class X> X *as() const { return static_cast<X *>(p); }
 };
 
-// Device-resident BVH over soup B with everything the queries and the
-// bounds need. Arrays indexed by "sorted index" follow the Morton order of
-// the leaves.
+// Per-pair BVH facts (device array, host copy).
+struct BvhPair {
+    double ctr[3];        // centre subtracted from this pair's coordinates
+    double coord_max;     // largest |coordinate| of the pair's B after centring
+    double edge_max;      // longest edge of the pair's B triangles
+    int64_t tri_begin;    // sorted-leaf range of the pair
+    int64_t tri_end;
+    int32_t root;         // >= 0 internal node, < 0 the single leaf ~root
+    int32_t nB;
+};
+
+// Device-resident BVH over one or more soups B_p (one subtree per pair).
+// Arrays indexed by "sorted index" follow the (pair, Morton) order.
 struct Bvh {
     int device = 0;
-    int64_t nB = 0, mB = 0;
-    double center[3] = {0, 0, 0}; // subtracted from every coordinate (A's too)
-    double coord_max = 0;         // max |coordinate| of B after centering
-    double edge_max = 0;          // longest edge of any B triangle
-    DBuf nodes;                   // (nB-1 or 1) x 64 B: child boxes + child refs
-    DBuf frames32;                // nB x 64 B
-    DBuf frames64;                // nB x 128 B
-    DBuf ids;                     // nB x int4: corner vertex ids (frame order), original face id
-    DBuf scratch;                 // build temporaries
+    int npairs = 0;
+    int64_t nB = 0;
+    DBuf nodes;    // internal nodes x 64 B: child boxes + child refs
+    DBuf frames32; // nB x 64 B
+    DBuf frames64; // nB x 128 B
+    DBuf ids;      // nB x int4: corner vertex ids (frame order), original face index in its pair
+    DBuf pairs;    // npairs x BvhPair
+    std::vector<BvhPair> hpairs;
     float ms_build = 0;
 };
 
 // --- primitives (hd_prims.hip) -------------------------------------------
-// Exclusive scan of n int32 values in place-out; returns nothing; total in
-// *d_total (device, may be null).
+// Exclusive scan of n int32 values; total in *d_total (device, may be null).
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,
                         hipStream_t s);
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
 // keys. Results land in keys/vals (the alt buffers are scratch).
 void radix_sort_u32(uint32_t *keys, int32_t *vals, uint32_t *keys_alt, int32_t *vals_alt, int64_t n,
                     int bits, DBuf &tmp, hipStream_t s);
+void radix_sort_u64(unsigned long long *keys, int32_t *vals, unsigned long long *keys_alt, int32_t *vals_alt,
+                    int64_t n, int bits, DBuf &tmp, hipStream_t s);
 
 // --- BVH (hd_bvh.hip) ------------------------------------------------------
-Bvh *build_bvh(const double *VB, int64_t mB, const int32_t *FB, int64_t nB, hipStream_t s);
+// VB[p], FB[p]: device pointers of pair p (host arrays of npairs pointers).
+Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int32_t *const *FB,
+               const int64_t *nB, hipStream_t s);
 
 // Node record: a = (lo_L.xyz, child_L), b = (hi_L.xyz, child_R),
 // c = (lo_R.xyz, 0), d = (hi_R.xyz, 0). A child >= 0 is an internal node,

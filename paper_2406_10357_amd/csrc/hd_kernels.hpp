@@ -1,11 +1,44 @@
-// hd_kernels.hpp -- device pieces of the branch-and-bound rounds: BVH
-// traversal for point queries, the frontier record layout, the cascade
-// with its rounding margins, and the FP64 re-bound of a frontier triangle.
+// hd_kernels.hpp -- device pieces of the branch-and-bound rounds: the
+// frontier record layout, BVH traversal for point queries, the cascade with
+// its rounding margins, and the FP64 re-bound of a frontier triangle.
 #pragma once
 #include "hd_geom.hpp"
 #include "hd_internal.hpp"
 
 namespace hd {
+
+// ---------------------------------------------------------------------------
+// Margins. For a value computed in precision T with unit roundoff u:
+//   point query:    |d_computed - d_exact| <= mu_d * d + mu_0
+//   triangle bound: |ub_computed - ub_exact| <= mu_d * dmax + mu_e * emax + mu_0
+// with mu_d = 16u, mu_e = 48u and mu_0 = u * (48 * D_B + 12 * S): D_B the
+// longest edge of B, S the largest coordinate magnitude after centring
+// (forward-error analysis of the frame evaluation and of the bound formulas,
+// with a safety factor of about 2).
+// ---------------------------------------------------------------------------
+struct Margins {
+    double mu_d, mu_e, mu_0;
+};
+
+// Per pair state of one call (device array).
+struct PairDev {
+    double ctr[3];   // centre subtracted from every coordinate of the pair
+    int32_t root;    // BVH subtree root (>= 0 node, < 0 leaf ~root)
+    int32_t status;
+    double eps_abs, dA;
+    Margins m32, m64;
+    unsigned long long Lord;      // ordered double: certified lower bound
+    unsigned long long Uord;      // ordered double: final upper bound
+    unsigned long long Urounds;   // ordered double: largest live bound of the rounds
+    unsigned long long round_key; // best (d_lo, tie hash) key of the current query round
+    unsigned long long best_key;  // best key so far
+    unsigned long long bbox[6];   // ordered FP64 bbox of A's referenced vertices
+    unsigned long long coord_max; // ordered FP64 largest |coordinate| of A after centring
+    double argmax_pos[3];         // centred FP64 position of the best vertex
+    int32_t argmax_dirty;
+    int32_t pad;
+    double L64;
+};
 
 // ---------------------------------------------------------------------------
 // Frontier records (structure of arrays; one slot per triangle).
@@ -22,43 +55,51 @@ template <class T> struct FrontierView {
     float *ub; // upper bound, margin included, rounded up
     int *face;
     int *lvl;
+    int *pair;
     int *ba[3];
     int *bb[3];
 };
 
-// A's vertices (centred FP64) and faces.
+// A's vertices and faces (all pairs concatenated; face indices are global).
 struct AView {
-    const double *V; // mA x 3, original coordinates
+    const double *V;
     const int32_t *F;
-    double cx, cy, cz; // centre subtracted from every coordinate
+    const PairDev *pd;
 };
 
-HD_D V3<double> a_vertex(const AView &a, int32_t v) {
-    return {a.V[3 * (int64_t)v] - a.cx, a.V[3 * (int64_t)v + 1] - a.cy, a.V[3 * (int64_t)v + 2] - a.cz};
+HD_D V3<double> a_vertex(const AView &a, int pair, int32_t v) {
+    const double *c = a.pd[pair].ctr;
+    return {a.V[3 * (int64_t)v] - c[0], a.V[3 * (int64_t)v + 1] - c[1], a.V[3 * (int64_t)v + 2] - c[2]};
 }
 
-// exact dyadic point of face f
-HD_D V3<double> a_point(const AView &a, int32_t f, int lvl, int ba, int bb) {
-    V3<double> V0 = a_vertex(a, a.F[3 * (int64_t)f]);
-    V3<double> V1 = a_vertex(a, a.F[3 * (int64_t)f + 1]);
-    V3<double> V2 = a_vertex(a, a.F[3 * (int64_t)f + 2]);
+// exact dyadic point of face f (centred coordinates of its pair)
+HD_D V3<double> a_point(const AView &a, int pair, int32_t f, int lvl, int ba, int bb) {
+    V3<double> V0 = a_vertex(a, pair, a.F[3 * (int64_t)f]);
+    V3<double> V1 = a_vertex(a, pair, a.F[3 * (int64_t)f + 1]);
+    V3<double> V2 = a_vertex(a, pair, a.F[3 * (int64_t)f + 2]);
     double s = __builtin_ldexp(1.0, -lvl);
     double wa = (double)ba * s, wb = (double)bb * s;
     return V0 + (wa * (V1 - V0) + wb * (V2 - V0));
 }
 
-// ---------------------------------------------------------------------------
-// Margins. For a value computed in precision T with unit roundoff u:
-//   point query:  |d_computed - d_exact| <= mu_d * d + mu_0
-//   triangle bound: |ub_computed - ub_exact| <= mu_d * dmax + mu_e * emax + mu_0
-// where mu_d = 16u, mu_e = 48u and mu_0 = u * (48 * D_B + 12 * S): D_B the
-// longest edge of B, S the largest coordinate magnitude after centring.
-// (Forward-error analysis of the frame evaluation and the bound formulas;
-// the constants carry a safety factor of about 2.)
-// ---------------------------------------------------------------------------
-struct Margins {
-    double mu_d, mu_e, mu_0;
-};
+// order-independent 32-bit tag of a dyadic point (reduced fraction), used to
+// break ties between equal keys the same way on every run
+HD_HD uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+HD_HD uint32_t point_tag(int32_t face, int lvl, int ba, int bb) {
+    while (lvl > 0 && ((ba | bb) & 1) == 0) {
+        ba >>= 1;
+        bb >>= 1;
+        --lvl;
+    }
+    return mix32((uint32_t)face * 0x9E3779B1u ^ mix32((uint32_t)ba * 0x85ebca6bu + (uint32_t)bb) ^ (uint32_t)lvl * 0xc2b2ae35u);
+}
 
 // ---------------------------------------------------------------------------
 // Traversal
@@ -128,14 +169,7 @@ template <class T> struct QueryResult {
     bool overflow;
 };
 
-// Closest-first traversal. A child box is entered only when its distance is
-// within (1 + 16u) of the best squared distance so far, which keeps pruning
-// conservative under the rounding of the box test; exact ties between
-// triangles resolve to the smallest original face index.
-template <class T, class Stack>
-HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &bv,
-                             const int4 *__restrict__ ids, const V3<T> &p, Stack &st) {
-    const T slack = T(1) + T(16 * Prec<T>::u);
+template <class T> HD_D QueryResult<T> empty_result() {
     QueryResult<T> r;
     r.d2 = T(__builtin_inf());
     r.s = -1;
@@ -143,20 +177,38 @@ HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &
     r.nbox = 0;
     r.nleaf = 0;
     r.overflow = false;
-    int node = 0;
-    auto leaf = [&](int s) {
-        Frame<T> f = load_frame(bv.frames, s);
-        T d2 = frame_dist2<T, false>(f, p, nullptr);
-        ++r.nleaf;
-        if (d2 <= r.d2) {
-            int o = ids[s].w;
-            if (d2 < r.d2 || o < r.orig) {
-                r.d2 = d2;
-                r.s = s;
-                r.orig = o;
-            }
+    return r;
+}
+
+// fold leaf s into the running result (exact ties: smallest original index)
+template <class T>
+HD_D void visit_leaf(QueryResult<T> &r, const BView<T> &bv, const int4 *__restrict__ ids, const V3<T> &p, int s) {
+    Frame<T> f = load_frame(bv.frames, s);
+    T d2 = frame_dist2<T, false>(f, p, nullptr);
+    ++r.nleaf;
+    if (d2 <= r.d2) {
+        int o = ids[s].w;
+        if (d2 < r.d2 || o < r.orig) {
+            r.d2 = d2;
+            r.s = s;
+            r.orig = o;
         }
-    };
+    }
+}
+
+// Closest-first traversal from `root`, starting from the result `r` (empty,
+// or seeded with candidate triangles). A child box is entered only when its
+// distance is within (1 + 16u) of the best squared distance so far, which
+// keeps pruning conservative under the rounding of the box test.
+template <class T, class Stack>
+HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
+                             const V3<T> &p, int root, Stack &st, QueryResult<T> r) {
+    const T slack = T(1) + T(16 * Prec<T>::u);
+    if (root < 0) {
+        visit_leaf(r, bv, ids, p, ~root);
+        return r;
+    }
+    int node = root;
     while (true) {
         const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
         float4 a = np[0], b = np[1], c = np[2], d = np[3];
@@ -166,11 +218,11 @@ HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &
         T thr = r.d2 * slack;
         bool hl = dl <= thr, hr = dr <= thr;
         if (hl && cl < 0) {
-            leaf(~cl);
+            visit_leaf(r, bv, ids, p, ~cl);
             hl = false;
         }
         if (hr && cr < 0) {
-            if (cr != cl) leaf(~cr);
+            visit_leaf(r, bv, ids, p, ~cr);
             hr = false;
         }
         thr = r.d2 * slack;
@@ -216,10 +268,6 @@ HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &
 struct CascadeCtx {
     int order[4];
     int norder;
-    double L;       // certified running lower bound
-    double eps;     // absolute tolerance
-    double mu64_0;  // FP64 absolute margin term, for the final-step consistency slack
-    Margins m;
 };
 
 template <class T>
@@ -238,11 +286,11 @@ template <class T> HD_D double tri_margin(const Tri<T> &t, const Margins &m) {
     return m.mu_d * dmax + m.mu_e * sqrt(e) + m.mu_0;
 }
 
-// returns the upper bound (margin included); *decider = 0 (exact), 1..4
+// upper bound with margin; *decider = 0 (exact), 1..4
 template <class T>
-HD_D double cascade(const Tri<T> &t, const CascadeCtx &c, const BView<T> &bv, const IdView &iv,
-                    int *decider, int *evals) {
-    double mu = tri_margin(t, c.m);
+HD_D double cascade(const Tri<T> &t, double L, const CascadeCtx &c, const Margins &m, const BView<T> &bv,
+                    const IdView &iv, int *decider, int *evals) {
+    double mu = tri_margin(t, m);
     if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) {
         *decider = 0;
         return (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
@@ -252,7 +300,7 @@ HD_D double cascade(const Tri<T> &t, const CascadeCtx &c, const BView<T> &bv, co
     for (int i = 0; i < c.norder; ++i) {
         int k = c.order[i];
         double u = (double)bound_k<T>(k, t, bv, iv, evals) + mu;
-        if (u < c.L) {
+        if (u < L) {
             *decider = k;
             return u;
         }
@@ -268,12 +316,12 @@ HD_D double cascade(const Tri<T> &t, const CascadeCtx &c, const BView<T> &bv, co
 // distances to the recorded closest triangles (any point of B gives a valid
 // upper-bound distance), then the full minimum over the bounds in the order
 // set. Returns the bound with the FP64 margin.
-HD_D double rebound64(const AView &a, int32_t face, int lvl, const int ba[3], const int bb[3],
+HD_D double rebound64(const AView &a, int pair, int32_t face, int lvl, const int ba[3], const int bb[3],
                       const int I[3], const BView<double> &bv64, const IdView &iv, const CascadeCtx &c,
                       const Margins &m64, int *evals) {
     Tri<double> t;
     for (int i = 0; i < 3; ++i) {
-        t.v[i] = a_point(a, face, lvl, ba[i], bb[i]);
+        t.v[i] = a_point(a, pair, face, lvl, ba[i], bb[i]);
         t.I[i] = I[i];
         Frame<double> f = load_frame(bv64.frames, I[i]);
         V3<double> q;

@@ -11,14 +11,12 @@ constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
 // inclusive scan across the 64 lanes of a wave
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         int t = __shfl_up(v, o, 64);
-        if (lane_id() >= o) v += t;
+        if ((int)__lane_id() >= o) v += t;
     }
     return v;
 }
@@ -28,7 +26,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *total) {
     __shared__ int wsum[SCAN_BLOCK / 64];
     int inc = wave_inclusive_scan(v);
     int w = threadIdx.x >> 6;
-    if (lane_id() == 63) wsum[w] = inc;
+    if (__lane_id() == 63) wsum[w] = inc;
     __syncthreads();
     int off = 0, tot = 0;
 #pragma unroll
@@ -85,6 +83,8 @@ __global__ void k_scan_down(const int32_t *__restrict__ in, int32_t *__restrict_
     }
 }
 
+__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+
 // ---------------------------------------------------------------------------
 // radix sort: 8-bit digits, one tile of RS_BLOCK * RS_ITEMS keys per block
 // ---------------------------------------------------------------------------
@@ -93,7 +93,8 @@ constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
 constexpr int RS_WAVES = RS_BLOCK / 64;
 
-__global__ void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int shift, int nblocks,
+template <class K>
+__global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift, int nblocks,
                              int32_t *__restrict__ hist) {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
@@ -101,15 +102,19 @@ __global__ void k_radix_hist(const uint32_t *__restrict__ keys, int64_t n, int s
     int64_t base = (int64_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ITEMS; ++r) {
         int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
-                                uint32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
-                                int shift, int nblocks, const int32_t *__restrict__ offs) {
+// Stable scatter: within a round of RS_BLOCK keys, a key's rank among equal
+// digits of its wave comes from eight ballots (one per digit bit); waves are
+// then ordered through per-digit counters in LDS.
+template <class K>
+__global__ void k_radix_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin, K *__restrict__ kout,
+                                int32_t *__restrict__ vout, int64_t n, int shift, int nblocks,
+                                const int32_t *__restrict__ offs) {
     __shared__ int goff[256];
     __shared__ int wcnt[RS_WAVES][256];
     __shared__ int woff[RS_WAVES][256];
@@ -123,9 +128,9 @@ __global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t 
         __syncthreads();
         int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
         bool act = i < n;
-        uint32_t key = act ? kin[i] : 0u;
+        K key = act ? kin[i] : K(0);
         int32_t val = act ? vin[i] : 0;
-        uint32_t dg = (key >> shift) & 255u;
+        uint32_t dg = (uint32_t)(key >> shift) & 255u;
         unsigned long long peers = __ballot(act);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -135,7 +140,7 @@ __global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t 
         int rank = __popcll(peers & lt);
         if (act && rank == 0) wcnt[w][dg] = __popcll(peers);
         __syncthreads();
-        {   // per digit: offsets of each wave within this round
+        {
             int d = threadIdx.x;
             int run = goff[d];
             for (int k = 0; k < RS_WAVES; ++k) {
@@ -154,12 +159,43 @@ __global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t 
     }
 }
 
+template <class K>
+void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int64_t n, int bits, DBuf &tmp,
+                     hipStream_t s) {
+    if (n <= 1) return;
+    int nb = (int)((n + RS_TILE - 1) / RS_TILE);
+    int64_t hn = 256LL * nb;
+    int64_t scan_parts = (hn + SCAN_TILE - 1) / SCAN_TILE;
+    tmp.reserve((size_t)(2 * hn + scan_parts + 64) * sizeof(int32_t));
+    int32_t *hist = tmp.as<int32_t>();
+    int32_t *offs = hist + hn;
+    int32_t *part = offs + hn;
+    K *ka = keys, *kb = keys_alt;
+    int32_t *va = vals, *vb = vals_alt;
+    int passes = (bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        int shift = 8 * p;
+        k_radix_hist<K><<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, hist);
+        k_scan_reduce<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, hn, part);
+        k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, scan_parts, nullptr);
+        k_scan_down<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, offs, hn, part);
+        k_radix_scatter<K><<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, offs);
+        HD_LAUNCH_CHECK();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        HD_HIP(hipMemcpyAsync(keys, ka, n * sizeof(K), hipMemcpyDeviceToDevice, s));
+        HD_HIP(hipMemcpyAsync(vals, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+}
+
 } // namespace
 
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,
                         hipStream_t s) {
     if (n <= 0) {
-        if (d_total) HD_HIP(hipMemsetAsync(d_total, 0, sizeof(int32_t), s));
+        if (d_total) k_zero_i32<<<1, 1, 0, s>>>(d_total);
         return;
     }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -171,35 +207,14 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_t
     HD_LAUNCH_CHECK();
 }
 
-void radix_sort_u32(uint32_t *keys, int32_t *vals, uint32_t *keys_alt, int32_t *vals_alt, int64_t n,
-                    int bits, DBuf &tmp, hipStream_t s) {
-    if (n <= 1) return;
-    int nb = (int)((n + RS_TILE - 1) / RS_TILE);
-    int64_t hn = 256LL * nb;
-    int64_t scan_parts = (hn + SCAN_TILE - 1) / SCAN_TILE;
-    tmp.reserve((size_t)(2 * hn + scan_parts + 64) * sizeof(int32_t));
-    int32_t *hist = tmp.as<int32_t>();
-    int32_t *offs = hist + hn;
-    int32_t *part = offs + hn;
-    uint32_t *ka = keys, *kb = keys_alt;
-    int32_t *va = vals, *vb = vals_alt;
-    int passes = (bits + 7) / 8;
-    for (int p = 0; p < passes; ++p) {
-        int shift = 8 * p;
-        k_radix_hist<<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, hist);
-        int64_t pb = scan_parts;
-        k_scan_reduce<<<(unsigned)pb, SCAN_BLOCK, 0, s>>>(hist, hn, part);
-        k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, pb, nullptr);
-        k_scan_down<<<(unsigned)pb, SCAN_BLOCK, 0, s>>>(hist, offs, hn, part);
-        k_radix_scatter<<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, offs);
-        HD_LAUNCH_CHECK();
-        uint32_t *tk = ka; ka = kb; kb = tk;
-        int32_t *tv = va; va = vb; vb = tv;
-    }
-    if (ka != keys) {
-        HD_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-        HD_HIP(hipMemcpyAsync(vals, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    }
+void radix_sort_u32(uint32_t *keys, int32_t *vals, uint32_t *keys_alt, int32_t *vals_alt, int64_t n, int bits,
+                    DBuf &tmp, hipStream_t s) {
+    radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s);
+}
+
+void radix_sort_u64(unsigned long long *keys, int32_t *vals, unsigned long long *keys_alt, int32_t *vals_alt,
+                    int64_t n, int bits, DBuf &tmp, hipStream_t s) {
+    radix_sort_impl<unsigned long long>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s);
 }
 
 } // namespace hd

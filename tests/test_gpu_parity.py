@@ -256,3 +256,95 @@ def test_invalid_inputs(bad):
     FB[0, 0] = -1
     with pytest.raises(hd.HDError):
         hd.build_bvh(_cu(V, torch), _cu(FB, torch))
+
+
+# ----------------------------------------------------------------------------
+# batched pairs, selection by sub-batch, fallbacks and errors
+# ----------------------------------------------------------------------------
+
+def _small_pairs(k=5):
+    out = []
+    for i in range(k):
+        rng = np.random.default_rng([9, i])
+        V, F = wl.icosphere(1 + i % 2)
+        VB = V + rng.normal(0, 0.01, size=V.shape) * (1 + i)
+        VA = V * (1.0 + 0.02 * i) + 0.1 * i
+        out.append((VA, F, VB + 0.1 * i, F.copy(), [1e-3, 3e-4, 1e-4][i % 3]))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32+recheck", "fp64"])
+def test_batched_pairs_against_oracle_and_single(prec):
+    hd, torch = _hd()
+    pairs = _small_pairs()
+    p = {"fp64": hd.PREC_FP64, "fp32+recheck": hd.PREC_FP32_RECHECK}[prec]
+    say("batched", len(pairs), "pairs", prec)
+    bvh = hd.build_bvh_batched([(_cu(VB, torch), _cu(FB, torch)) for _, _, VB, FB, _ in pairs])
+    Ls, Us, st = hd.bound_batched([(_cu(VA, torch), _cu(FA, torch)) for VA, FA, _, _, _ in pairs], bvh,
+                                  [e for *_, e in pairs], precision=p)
+    for i, (VA, FA, VB, FB, eps) in enumerate(pairs):
+        ref = oracle.bound(VA, FA, VB, FB, eps)
+        dA = ref["dA"]
+        print(f"pair {i}: gpu [{Ls[i]:.10g}, {Us[i]:.10g}] oracle [{ref['L']:.10g}, {ref['U']:.10g}]", flush=True)
+        assert Us[i] - Ls[i] <= eps * dA * (1 + 1e-12)
+        assert Ls[i] <= ref["U"] + 1e-12 * dA and ref["L"] <= Us[i] + 1e-12 * dA
+        assert abs(Ls[i] - ref["L"]) <= eps * dA
+        say("single pair", i)
+        b1 = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+        L1, U1, _ = hd.bound(_cu(VA, torch), _cu(FA, torch), b1, eps, precision=p)
+        assert L1 <= Us[i] + 1e-12 * dA and Ls[i] <= U1 + 1e-12 * dA
+
+
+def test_subbatch_selection_is_certified():
+    hd, torch = _hd()
+    W = wl.config(2, scale=0.05)
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+    say("sub-batch 64 on config2 scale 0.05")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, subbatch=64)
+    _check_against_oracle(L, U, st, ref, "config2 subbatch 64")
+    assert st["rounds"] > 5
+
+
+def test_small_capacity_still_certified():
+    hd, torch = _hd()
+    W = wl.config(2, scale=0.05)
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+    say("capacity = nA on config2 scale 0.05")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, capacity=int(W.FA.shape[0] * 2))
+    _check_against_oracle(L, U, st, ref, "config2 small capacity")
+
+
+def test_tiny_stack_falls_back_and_agrees():
+    hd, torch = _hd()
+    W = wl.config(2, scale=0.05)
+    say("tiny traversal stack on config2 scale 0.05")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    a = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    b = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, stack_depth=2)
+    assert a[0] == b[0] and a[1] == b[1]
+    assert a[2]["subdivided"] == b[2]["subdivided"]
+
+
+def test_face_budget_exceeded():
+    hd, torch = _hd()
+    W = wl.config(1)
+    say("budget m = 1.5 on config1")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    with pytest.raises(hd.HDError) as e:
+        hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, budget_m=1.5)
+    assert e.value.status == 2
+
+
+def test_cascade_order_invariance_on_gpu():
+    hd, torch = _hd()
+    W = wl.config(1)
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    ref = None
+    for order in (1234, 4321, 2314, 3142):
+        say("order", order)
+        L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, order=order)
+        key = (L, U, st["subdivided"], st["nodes_bounded"])
+        ref = ref or key
+        assert key == ref
