@@ -280,29 +280,29 @@ __global__ void k_leaves(const PairSrc *__restrict__ src, const int64_t *__restr
     int p = fpair[f];
     PairSrc ps = src[p];
     int64_t lf = f - foff[p];
-    int32_t vid[3];
-    V3<double> P[3];
-    double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
-    double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
-    for (int j = 0; j < 3; ++j) {
-        vid[j] = ps.F[3 * lf + j];
-        double c[3];
-        for (int k = 0; k < 3; ++k) {
-            c[k] = ps.V[3 * (int64_t)vid[j] + k] - pairs[p].ctr[k];
-            lo[k] = fmin(lo[k], c[k]);
-            hi[k] = fmax(hi[k], c[k]);
-        }
-        P[j] = {c[0], c[1], c[2]};
-    }
-    lbox[2 * i] = make_float4(round_down_f(lo[0]), round_down_f(lo[1]), round_down_f(lo[2]), 0.f);
-    lbox[2 * i + 1] = make_float4(round_up_f(hi[0]), round_up_f(hi[1]), round_up_f(hi[2]), 0.f);
+    // (no runtime-indexed private arrays here: they would be promoted to LDS)
+    const int32_t v0 = ps.F[3 * lf], v1 = ps.F[3 * lf + 1], v2 = ps.F[3 * lf + 2];
+    const double *c = pairs[p].ctr;
+    auto load = [&](int32_t v) {
+        return mk(ps.V[3 * (int64_t)v] - c[0], ps.V[3 * (int64_t)v + 1] - c[1], ps.V[3 * (int64_t)v + 2] - c[2]);
+    };
+    const V3<double> P0 = load(v0), P1 = load(v1), P2 = load(v2);
+    V3<double> lo = mk(fmin(P0.x, fmin(P1.x, P2.x)), fmin(P0.y, fmin(P1.y, P2.y)), fmin(P0.z, fmin(P1.z, P2.z)));
+    V3<double> hi = mk(fmax(P0.x, fmax(P1.x, P2.x)), fmax(P0.y, fmax(P1.y, P2.y)), fmax(P0.z, fmax(P1.z, P2.z)));
+    lbox[2 * i] = make_float4(round_down_f(lo.x), round_down_f(lo.y), round_down_f(lo.z), 0.f);
+    lbox[2 * i + 1] = make_float4(round_up_f(hi.x), round_up_f(hi.y), round_up_f(hi.z), 0.f);
 
-    // frame anchored on the longest edge (P[k], P[k+1])
-    double l2[3] = {norm2(P[1] - P[0]), norm2(P[2] - P[1]), norm2(P[0] - P[2])};
+    // frame anchored on the longest edge (P_k, P_k+1)
+    double l0 = norm2(P1 - P0), l1 = norm2(P2 - P1), l2 = norm2(P0 - P2);
     int k = 0;
-    if (l2[1] > l2[k]) k = 1;
-    if (l2[2] > l2[k]) k = 2;
-    V3<double> A = P[k], B = P[(k + 1) % 3], C = P[(k + 2) % 3];
+    if (l1 > l0) k = 1;
+    if (l2 > (k == 0 ? l0 : l1)) k = 2;
+    V3<double> A = k == 0 ? P0 : (k == 1 ? P1 : P2);
+    V3<double> B = k == 0 ? P1 : (k == 1 ? P2 : P0);
+    V3<double> C = k == 0 ? P2 : (k == 1 ? P0 : P1);
+    const int32_t iA = k == 0 ? v0 : (k == 1 ? v1 : v2);
+    const int32_t iB = k == 0 ? v1 : (k == 1 ? v2 : v0);
+    const int32_t iC = k == 0 ? v2 : (k == 1 ? v0 : v1);
     V3<double> e = B - A;
     double Lb = sqrt(norm2(e));
     V3<double> ex = Lb > 0 ? (1.0 / Lb) * e : mk(1.0, 0.0, 0.0);
@@ -336,7 +336,7 @@ __global__ void k_leaves(const PairSrc *__restrict__ src, const int64_t *__restr
     q[5] = make_double2(ey.z, cy);
     q[6] = make_double2(ibc, ica);
     q[7] = make_double2(Lb, 0.0);
-    ids[i] = make_int4(vid[k], vid[(k + 1) % 3], vid[(k + 2) % 3], (int32_t)lf);
+    ids[i] = make_int4(iA, iB, iC, (int32_t)lf);
     atomicMax(&acc[p].edge_max, d2ord(Lb));
 }
 

@@ -96,9 +96,34 @@ __device__ __forceinline__ void acc_max(unsigned long long *a, double v, bool un
     }
 }
 
-template <class T> HD_HD const Margins &margins_of(const PairDev &p);
-template <> HD_HD const Margins &margins_of<float>(const PairDev &p) { return p.m32; }
-template <> HD_HD const Margins &margins_of<double>(const PairDev &p) { return p.m64; }
+template <class T> HD_HD const Margins &margins_of(const PairConst &p);
+template <> HD_HD const Margins &margins_of<float>(const PairConst &p) { return p.m32; }
+template <> HD_HD const Margins &margins_of<double>(const PairConst &p) { return p.m64; }
+
+// atomicMax of (a, b) into pair `pair`'s L and round key: one atomic per wave
+// when every contributing lane has the same pair, else one per lane. All
+// lanes of the wave must call it; lanes with nothing to add pass zeros.
+__device__ void pair_max2(PairVar *pv, int pair, unsigned long long a, unsigned long long b) {
+    unsigned long long has = __ballot(a != 0 || b != 0);
+    if (!has) return;
+    int first = __ffsll(has) - 1;
+    int p0 = __shfl(pair, first, 64);
+    bool uni = __ballot((a != 0 || b != 0) && pair != p0) == 0;
+    if (uni) {
+        for (int o = 32; o >= 1; o >>= 1) {
+            unsigned long long ta = __shfl_xor(a, o, 64), tb = __shfl_xor(b, o, 64);
+            a = ta > a ? ta : a;
+            b = tb > b ? tb : b;
+        }
+        if (__lane_id() == 0) {
+            if (a) atomicMax(&pv[p0].Lord, a);
+            if (b) atomicMax(&pv[p0].round_key, b);
+        }
+    } else {
+        if (a) atomicMax(&pv[pair].Lord, a);
+        if (b) atomicMax(&pv[pair].round_key, b);
+    }
+}
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,22 +138,25 @@ __global__ void k_round_setup(Ctl *c, unsigned long long act_base, unsigned long
     c->park_next = park_base;
 }
 
-__global__ void k_pairs_init(PairDev *pd, const BvhPair *__restrict__ bp, int npairs) {
+__global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int npairs) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
-    PairDev d;
+    PairConst c;
+    memset(&c, 0, sizeof(c));
+    PairVar d;
     memset(&d, 0, sizeof(d));
     for (int k = 0; k < 3; ++k) {
-        d.ctr[k] = bp[p].ctr[k];
+        c.ctr[k] = bp[p].ctr[k];
         d.bbox[k] = d2ord(__builtin_inf());
         d.bbox[3 + k] = d2ord(-__builtin_inf());
     }
-    d.root = bp[p].root;
+    c.root = bp[p].root;
     d.Lord = d2ord(0.0);
     d.Uord = d2ord(0.0);
     d.Urounds = d2ord(0.0);
     d.coord_max = d2ord(0.0);
-    pd[p] = d;
+    pc[p] = c;
+    pv[p] = d;
 }
 
 // Validate A's faces, gather every pair's faces into one array with global
@@ -137,7 +165,7 @@ __global__ void k_pairs_init(PairDev *pd, const BvhPair *__restrict__ bp, int np
 __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__restrict__ foff,
                          const int64_t *__restrict__ voff, int npairs, int64_t n, int32_t *__restrict__ Fout,
                          double *__restrict__ Vout, int32_t *__restrict__ fpair, int32_t *__restrict__ ref,
-                         PairDev *pd, Ctl *ctl) {
+                         const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = f < n;
     int p = pair_of(foff, npairs, valid ? f : n - 1);
@@ -167,16 +195,16 @@ __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__rest
                 Vout[3 * vg + k] = x;
                 lo[k] = fmin(lo[k], x);
                 hi[k] = fmax(hi[k], x);
-                cm = fmax(cm, fabs(x - pd[p].ctr[k]));
+                cm = fmax(cm, fabs(x - pc[p].ctr[k]));
             }
         }
     }
     bool uni = wave_uniform(p);
     for (int k = 0; k < 3; ++k) {
-        acc_min(&pd[p].bbox[k], lo[k], uni);
-        acc_max(&pd[p].bbox[3 + k], hi[k], uni);
+        acc_min(&pv[p].bbox[k], lo[k], uni);
+        acc_max(&pv[p].bbox[3 + k], hi[k], uni);
     }
-    acc_max(&pd[p].coord_max, cm, uni);
+    acc_max(&pv[p].coord_max, cm, uni);
 }
 
 __device__ Margins make_margins(double u, double edge_max, double coord_max) {
@@ -187,21 +215,21 @@ __device__ Margins make_margins(double u, double edge_max, double coord_max) {
     return m;
 }
 
-__global__ void k_pairs_post(PairDev *pd, const BvhPair *__restrict__ bp, int npairs, const double *__restrict__ eps,
-                             int eps_per_pair) {
+__global__ void k_pairs_post(PairConst *pc, const PairVar *pv, const BvhPair *__restrict__ bp, int npairs,
+                             const double *__restrict__ eps, int eps_per_pair) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
     double d2 = 0;
     for (int k = 0; k < 3; ++k) {
-        double e = ord2d(pd[p].bbox[3 + k]) - ord2d(pd[p].bbox[k]);
+        double e = ord2d(pv[p].bbox[3 + k]) - ord2d(pv[p].bbox[k]);
         d2 += e * e;
     }
     double dA = sqrt(d2);
-    pd[p].dA = dA;
-    pd[p].eps_abs = eps[eps_per_pair ? p : 0] * dA;
-    double cm = fmax(ord2d(pd[p].coord_max), bp[p].coord_max);
-    pd[p].m32 = make_margins(Prec<float>::u, bp[p].edge_max, cm);
-    pd[p].m64 = make_margins(Prec<double>::u, bp[p].edge_max, cm);
+    pc[p].dA = dA;
+    pc[p].eps_abs = eps[eps_per_pair ? p : 0] * dA;
+    double cm = fmax(ord2d(pv[p].coord_max), bp[p].coord_max);
+    pc[p].m32 = make_margins(Prec<float>::u, bp[p].edge_max, cm);
+    pc[p].m64 = make_margins(Prec<double>::u, bp[p].edge_max, cm);
 }
 
 // compact the referenced vertex ids (order preserving)
@@ -232,7 +260,7 @@ template <class T> struct QueryIn {
     const int64_t *voff;     // Q_VERTICES: vertex offsets of the pairs
     AView a;                 // Q_VERTICES / Q_MIDPOINTS
     FrontierView<T> par;     // Q_MIDPOINTS: selected parents
-    const PairDev *pd;
+    const PairConst *pc;
 };
 
 struct QPoint {
@@ -248,7 +276,7 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
     q.seed[0] = q.seed[1] = -1;
     if (in.mode == Q_POINTS) {
         q.pair = 0;
-        const double *c = in.pd[0].ctr;
+        const double *c = in.pc[0].ctr;
         q.p = {in.P[3 * i] - c[0], in.P[3 * i + 1] - c[1], in.P[3 * i + 2] - c[2]};
         q.out = i;
         q.tag = 0;
@@ -282,9 +310,12 @@ struct QueryCfg {
     int raise_L; // fold d - mu into the lower bound and the argmax key
 };
 
+// writes the result; returns in *lord, *key what the pair's L and round key
+// must be raised to (0: nothing)
 template <class T>
 HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResult<T> &r, const QPoint &qp,
-                       const V3<T> &p, const QueryOut<T> &out, PairDev *pd) {
+                       const V3<T> &p, const QueryOut<T> &out, const PairConst *pc, unsigned long long *lord,
+                       unsigned long long *keyout) {
     V3<T> q = p;
     T d = T(__builtin_inf());
     if (r.s >= 0) {
@@ -302,36 +333,41 @@ HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResul
         out.p[1][o] = p.y;
         out.p[2][o] = p.z;
     }
+    *lord = 0;
+    *keyout = 0;
     if (cfg.raise_L) {
         unsigned long long key = 0;
         if (r.s >= 0) {
-            const Margins &m = margins_of<T>(pd[qp.pair]);
+            const Margins &m = margins_of<T>(pc[qp.pair]);
             double dlo = (double)d - (m.mu_d * (double)d + m.mu_0);
             if (dlo > 0) {
-                atomicMax(&pd[qp.pair].Lord, d2ord(dlo));
+                *lord = d2ord(dlo);
                 key = ((unsigned long long)f2ord(to_float_down(dlo)) << 32) | qp.tag;
-                atomicMax(&pd[qp.pair].round_key, key);
             }
         }
+        *keyout = key;
         out.key[o] = key;
     }
 }
 
 template <class T, int SD>
 __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, int64_t n, QueryCfg cfg, BView<T> bv,
-                                                  QueryOut<T> out, PairDev *pd, Ctl *ctl, int32_t *ovf_list) {
+                                                  QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
+                                                  Ctl *ctl, int32_t *ovf_list) {
     __shared__ int s_node[SD * QBLOCK];
     __shared__ float s_dist[SD * QBLOCK];
     int64_t i = (int64_t)blockIdx.x * QBLOCK + threadIdx.x;
-    unsigned long long nb = 0, nl = 0, nq = 0;
+    unsigned long long nb = 0, nl = 0, nq = 0, lord = 0, key = 0;
+    int pair = 0;
     if (i < n) {
         QPoint qp = query_point(in, i);
+        pair = qp.pair;
         V3<T> p = cvt<T>(qp.p);
         QueryResult<T> r = empty_result<T>();
         if (qp.seed[0] >= 0) visit_leaf(r, bv, cfg.ids, p, qp.seed[0]);
         if (qp.seed[1] >= 0 && qp.seed[1] != qp.seed[0]) visit_leaf(r, bv, cfg.ids, p, qp.seed[1]);
         LdsStack<SD, QBLOCK> stk{s_node, s_dist, 0};
-        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pd[qp.pair].root, stk, r);
+        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
         nb = r.nbox;
         nl = r.nleaf;
         nq = 1;
@@ -339,9 +375,10 @@ __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, int64_t n, Quer
             int k = atomicAdd(&ctl->n_overflow, 1);
             ovf_list[k] = (int32_t)i;
         } else {
-            finish_query<T>(cfg, bv, r, qp, p, out, pd);
+            finish_query<T>(cfg, bv, r, qp, p, out, pc, &lord, &key);
         }
     }
+    pair_max2(pv, pair, lord, key);
     wave_add(&ctl->boxes, nb);
     wave_add(&ctl->evals, nl);
     wave_add(&ctl->q_leaves, nl);
@@ -352,8 +389,9 @@ __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, int64_t n, Quer
 // queries whose LDS stack overflowed, redone with a deep stack in global
 // memory (grid-stride over the overflow list; exits at once when it is empty)
 template <class T>
-__global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<T> out, PairDev *pd, Ctl *ctl,
-                             const int32_t *ovf_list, int2 *stack_mem) {
+__global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<T> out,
+                             const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, const int32_t *ovf_list,
+                             int2 *stack_mem) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int novf = ctl->n_overflow;
     unsigned long long nb = 0, nl = 0;
@@ -365,14 +403,17 @@ __global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<
         if (qp.seed[0] >= 0) visit_leaf(r, bv, cfg.ids, p, qp.seed[0]);
         if (qp.seed[1] >= 0 && qp.seed[1] != qp.seed[0]) visit_leaf(r, bv, cfg.ids, p, qp.seed[1]);
         GlobalStack stk{stack_mem + tid, DEEP_SLOTS, DEEP_STACK, 0};
-        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pd[qp.pair].root, stk, r);
+        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
         nb += r.nbox;
         nl += r.nleaf;
         // a traversal deeper than the fallback stack fails the call; its
         // (possibly suboptimal) result is still written so that later
         // kernels read initialised indices
         if (r.overflow) ctl->bad = 2;
-        finish_query<T>(cfg, bv, r, qp, p, out, pd);
+        unsigned long long lord, key;
+        finish_query<T>(cfg, bv, r, qp, p, out, pc, &lord, &key);
+        if (lord) atomicMax(&pv[qp.pair].Lord, lord);
+        if (key) atomicMax(&pv[qp.pair].round_key, key);
     }
     wave_add(&ctl->boxes, nb);
     wave_add(&ctl->evals, nl);
@@ -382,14 +423,14 @@ __global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<
 // exact position (keys are unique up to a tag collision of one point)
 template <class T>
 __global__ void k_argmax_finalize(QueryIn<T> in, int64_t n, const unsigned long long *__restrict__ keys,
-                                  PairDev *pd) {
+                                  PairVar *pv) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
     unsigned long long key = keys[o];
     if (key == 0) return;
     QPoint qp = query_point(in, i);
-    PairDev &P = pd[qp.pair];
+    PairVar &P = pv[qp.pair];
     if (key == P.round_key && key > P.best_key) {
         P.argmax_pos[0] = qp.p.x;
         P.argmax_pos[1] = qp.p.y;
@@ -401,21 +442,22 @@ __global__ void k_argmax_finalize(QueryIn<T> in, int64_t n, const unsigned long 
 // FP64 distance of each pair's best vertex when it changed: the lower bound
 // then carries the FP64 margin instead of the FP32 one, which the recheck
 // band needs to park triangles within eps of it
-__global__ void k_L64(const NodeRec *nodes, BView<double> bv64, const int4 *ids, PairDev *pd, int npairs,
-                      int2 *stack_mem) {
+__global__ void k_L64(const NodeRec *nodes, BView<double> bv64, const int4 *ids, const PairConst *pc, PairVar *pv,
+                      int npairs, int2 *stack_mem) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
-    PairDev &P = pd[p];
+    PairVar &P = pv[p];
+    const PairConst &C = pc[p];
     if (P.round_key > P.best_key) P.best_key = P.round_key;
     P.round_key = 0;
     if (!P.argmax_dirty) return;
     P.argmax_dirty = 0;
     V3<double> x = {P.argmax_pos[0], P.argmax_pos[1], P.argmax_pos[2]};
     GlobalStack stk{stack_mem + p, npairs, DEEP_STACK, 0};
-    QueryResult<double> r = traverse<double>(nodes, bv64, ids, x, P.root, stk, empty_result<double>());
+    QueryResult<double> r = traverse<double>(nodes, bv64, ids, x, C.root, stk, empty_result<double>());
     if (r.overflow || r.s < 0) return;
     double d = sqrt(r.d2);
-    double dlo = d - (P.m64.mu_d * d + P.m64.mu_0);
+    double dlo = d - (C.m64.mu_d * d + C.m64.mu_0);
     P.L64 = dlo;
     if (dlo > 0 && d2ord(dlo) > P.Lord) P.Lord = d2ord(dlo);
 }
@@ -430,7 +472,8 @@ struct ClassifyCfg {
     AView a;
     BView<double> bv64;
     IdView iv;
-    const PairDev *pd;
+    const PairConst *pc;
+    const PairVar *pv;
 };
 
 template <class T> struct Corner {
@@ -450,8 +493,8 @@ HD_D int classify(const Corner<T> cn[3], int pair, int face, int lvl, const Clas
         t.d[i] = cn[i].d;
         t.I[i] = cn[i].I;
     }
-    const PairDev &P = cc.pd[pair];
-    const double L = ord2d(P.Lord), eps = P.eps_abs;
+    const PairConst &P = cc.pc[pair];
+    const double L = ord2d(cc.pv[pair].Lord), eps = P.eps_abs;
     const Margins &m = margins_of<T>(P);
     double ub = cascade<T>(t, L, cc.c, m, bv, cc.iv, decider, evals);
     const double park_lim = eps * (1.0 - 1.0 / 1024.0 / 1024.0 / 1024.0);
@@ -664,7 +707,7 @@ __global__ void k_sel_keys(FrontierView<T> fr, int64_t n, unsigned long long *__
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> bv64, IdView iv, CascadeCtx c,
-                          PairDev *pd, Ctl *ctl) {
+                          const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long ev = 0;
     if (i < n) {
@@ -673,10 +716,10 @@ __global__ void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> 
         int bb[3] = {fr.bb[0][i], fr.bb[1][i], fr.bb[2][i]};
         int I[3] = {fr.I[0][i], fr.I[1][i], fr.I[2][i]};
         int evals = 0;
-        double u64 = rebound64(a, pair, fr.face[i], fr.lvl[i], ba, bb, I, bv64, iv, c, pd[pair].m64, &evals);
+        double u64 = rebound64(a, pair, fr.face[i], fr.lvl[i], ba, bb, I, bv64, iv, c, pc[pair].m64, &evals);
         double u32 = (double)fr.ub[i];
-        atomicMax(&pd[pair].Uord, d2ord(hmin(u64, u32)));
-        atomicMax(&pd[pair].Urounds, d2ord(u32));
+        atomicMax(&pv[pair].Uord, d2ord(hmin(u64, u32)));
+        atomicMax(&pv[pair].Urounds, d2ord(u32));
         ev = evals;
     }
     wave_add(&ctl->evals, ev);
@@ -687,8 +730,8 @@ __global__ void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> 
 // ---------------------------------------------------------------------------
 template <class T>
 __global__ void k_eval_bounds(const double *v, const double *d, const int32_t *Iorig, const double *q, int64_t n,
-                              const int32_t *inv_perm, int64_t nB, BView<T> bv, IdView iv, const PairDev *pd,
-                              double *out, int32_t *u3case) {
+                              const int32_t *inv_perm, int64_t nB, BView<T> bv, IdView iv,
+                              const PairConst *pc, double *out, int32_t *u3case) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int k = 0; k < 3; ++k) {
@@ -700,7 +743,7 @@ __global__ void k_eval_bounds(const double *v, const double *d, const int32_t *I
         }
     }
     Tri<T> t;
-    const double *c = pd[0].ctr;
+    const double *c = pc[0].ctr;
     for (int k = 0; k < 3; ++k) {
         t.v[k] = {T(v[9 * i + 3 * k] - c[0]), T(v[9 * i + 3 * k + 1] - c[1]), T(v[9 * i + 3 * k + 2] - c[2])};
         t.q[k] = {T(q[9 * i + 3 * k] - c[0]), T(q[9 * i + 3 * k + 1] - c[1]), T(q[9 * i + 3 * k + 2] - c[2])};
@@ -722,11 +765,11 @@ __global__ void k_inv_perm(const int4 *ids, int64_t n, int32_t *inv) {
 }
 
 template <class T>
-__global__ void k_export_points(const QueryOut<T> r, int64_t n, const int4 *ids, const PairDev *pd, double *d,
+__global__ void k_export_points(const QueryOut<T> r, int64_t n, const int4 *ids, const PairConst *pc, double *d,
                                 int32_t *I, double *Q) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double *c = pd[0].ctr;
+    const double *c = pc[0].ctr;
     d[i] = (double)r.d[i];
     I[i] = ids[r.I[i]].w;
     if (Q) {
@@ -815,7 +858,7 @@ template <class T> struct TypedWs {
 };
 struct Workspace {
     std::mutex mu;
-    DBuf ctl, pd, src, offs, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
+    DBuf ctl, pc, pv, src, offs, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
     TypedWs<float> w32;
     TypedWs<double> w64;
     template <class T> TypedWs<T> &typed();
@@ -920,8 +963,10 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // ---- small tables -----------------------------------------------------
     ws.ctl.reserve(sizeof(Ctl));
     Ctl *ctl = ws.ctl.as<Ctl>();
-    ws.pd.reserve(np * sizeof(PairDev));
-    PairDev *pd = ws.pd.as<PairDev>();
+    ws.pc.reserve(np * sizeof(PairConst));
+    ws.pv.reserve(np * sizeof(PairVar));
+    PairConst *pc = ws.pc.as<PairConst>();
+    PairVar *pv = ws.pv.as<PairVar>();
     std::vector<PairSrcA> hsrc(np);
     for (int p = 0; p < np; ++p) hsrc[p] = PairSrcA{in.VA[p], in.FA[p], in.mA[p]};
     ws.src.reserve(np * sizeof(PairSrcA));
@@ -944,11 +989,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     ws.small.reserve(4096);
     int32_t *d_total = ws.small.as<int32_t>();
     k_ctl_init<<<1, 1, 0, s>>>(ctl);
-    k_pairs_init<<<grid_for(np, 64), 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), np);
+    k_pairs_init<<<grid_for(np, 64), 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), np);
     k_fill_i32<<<grid_for(mA, BLK), BLK, 0, s>>>(ref, mA, 0);
     k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(ws.src.as<PairSrcA>(), dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
-                                              ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pd, ctl);
-    k_pairs_post<<<grid_for(np, 64), 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair);
+                                              ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pv, ctl);
+    k_pairs_post<<<grid_for(np, 64), 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair);
     scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
     HD_LAUNCH_CHECK();
     struct {
@@ -969,7 +1014,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     }();
     const BView<double> bv64{B->frames64.as<double2>()};
     const IdView iv{B->ids.as<int4>()};
-    const AView av{ws.Vcat.as<double>(), ws.Fcat.as<int32_t>(), pd};
+    const AView av{ws.Vcat.as<double>(), ws.Fcat.as<int32_t>(), pc};
     const QueryCfg qcfg{B->nodes.as<NodeRec>(), B->ids.as<int4>(), 1};
     ws.gstack.reserve((size_t)np * DEEP_STACK * sizeof(int2));
     ws.deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
@@ -980,17 +1025,18 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         ws.ovf.reserve((size_t)n * sizeof(int32_t));
         prof.mark(prof.q);
         if (small_stack)
-            k_query<T, SMALL_STACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pd, ctl,
+            k_query<T, SMALL_STACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pc, pv, ctl,
                                                                             ws.ovf.as<int32_t>());
         else
-            k_query<T, QSTACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pd, ctl,
+            k_query<T, QSTACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pc, pv, ctl,
                                                                        ws.ovf.as<int32_t>());
         HD_LAUNCH_CHECK();
         prof.mark(prof.q);
-        k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pd, ctl, ws.ovf.as<int32_t>(),
+        k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                         ws.deep.as<int2>());
-        k_argmax_finalize<T><<<grid_for(n, BLK), BLK, 0, s>>>(qi, n, out.key, pd);
-        k_L64<<<grid_for(np, 64), 64, 0, s>>>(B->nodes.as<NodeRec>(), bv64, iv.ids, pd, np, ws.gstack.as<int2>());
+        k_argmax_finalize<T><<<grid_for(n, BLK), BLK, 0, s>>>(qi, n, out.key, pv);
+        k_L64<<<grid_for(np, 64), 64, 0, s>>>(B->nodes.as<NodeRec>(), bv64, iv.ids, pc, pv, np,
+                                               ws.gstack.as<int2>());
         HD_LAUNCH_CHECK();
     };
 
@@ -1003,7 +1049,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.vids = ws.vids.as<int32_t>();
         qi.voff = dvoff;
         qi.a = av;
-        qi.pd = pd;
+        qi.pc = pc;
         k_round_setup<<<1, 1, 0, s>>>(ctl, 0, 0);
         run_queries(qi, nref, tw.vq.o);
     }
@@ -1022,7 +1068,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cc.a = av;
     cc.bv64 = bv64;
     cc.iv = iv;
-    cc.pd = pd;
+    cc.pc = pc;
+    cc.pv = pv;
 
     // ---- round 0: bound every face ------------------------------------------
     prof.mark(prof.c);
@@ -1092,7 +1139,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.npairs = np;
         qi.a = av;
         qi.par = tw.act.v;
-        qi.pd = pd;
+        qi.pc = pc;
         run_queries(qi, 3 * K, tw.mq.o);
         // the unselected remainder first, then the active children
         if (rest > 0) k_gather<T><<<grid_for(rest, BLK), BLK, 0, s>>>(tw.act.v, nullptr, K, rest, tw.act2.v);
@@ -1114,18 +1161,20 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     }
 
     // ---- final FP64 step: U over every live triangle --------------------------
-    std::vector<PairDev> hp(np);
+    std::vector<PairConst> hc_(np);
+    std::vector<PairVar> hp(np);
     if (status == HD_OK) {
         prof.mark(prof.c);
         if (nPark > 0)
-            k_final_U<T><<<grid_for(nPark, BLK), BLK, 0, s>>>(tw.park.v, nPark, av, bv64, iv, cctx, pd, ctl);
+            k_final_U<T><<<grid_for(nPark, BLK), BLK, 0, s>>>(tw.park.v, nPark, av, bv64, iv, cctx, pc, pv, ctl);
         if (nAct > 0)
-            k_final_U<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, av, bv64, iv, cctx, pd, ctl);
+            k_final_U<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, av, bv64, iv, cctx, pc, pv, ctl);
         HD_LAUNCH_CHECK();
         prof.mark(prof.c);
     }
     HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HD_HIP(hipMemcpyAsync(hp.data(), pd, np * sizeof(PairDev), hipMemcpyDeviceToHost, s));
+    HD_HIP(hipMemcpyAsync(hp.data(), pv, np * sizeof(PairVar), hipMemcpyDeviceToHost, s));
+    HD_HIP(hipMemcpyAsync(hc_.data(), pc, np * sizeof(PairConst), hipMemcpyDeviceToHost, s));
     HD_HIP(hipStreamSynchronize(s));
     if (status == HD_OK && hc.bad == 2) status = HD_E_INTERNAL;
     if (status == HD_OK) {
@@ -1134,7 +1183,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             double U = std::max(L, ord2d(hp[p].Uord));
             LU[2 * p] = L;
             LU[2 * p + 1] = U;
-            if (nAct == 0 && U - L > hp[p].eps_abs) status = HD_E_INTERNAL;
+            if (nAct == 0 && U - L > hc_[p].eps_abs) status = HD_E_INTERNAL;
         }
         if (nAct > 0 && opt.max_rounds <= 0) status = HD_E_INTERNAL;
     }
@@ -1150,10 +1199,10 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     S.parked_final = nPark;
     S.query_leaf_evals = (int64_t)hc.q_leaves;
     S.query_box_tests = (int64_t)hc.q_boxes;
-    S.dA = hp[0].dA;
-    S.eps_abs = hp[0].eps_abs;
-    S.mu_coef_d = margins_of<T>(hp[0]).mu_d;
-    S.mu_coef_0 = margins_of<T>(hp[0]).mu_0;
+    S.dA = hc_[0].dA;
+    S.eps_abs = hc_[0].eps_abs;
+    S.mu_coef_d = margins_of<T>(hc_[0]).mu_d;
+    S.mu_coef_0 = margins_of<T>(hc_[0]).mu_0;
     S.L_rounds = ord2d(hp[0].Lord);
     S.U_rounds = std::max(S.L_rounds, ord2d(hp[0].Urounds));
     if (prof.on) {
@@ -1306,15 +1355,17 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
     const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
     hipStream_t s = (hipStream_t)stream;
     return guard([&] {
-        DBuf ctlb, pdb, ovf, deep;
+        DBuf ctlb, pcb, pvb, ovf, deep;
         ctlb.reserve(sizeof(Ctl));
-        pdb.reserve(sizeof(PairDev));
+        pcb.reserve(sizeof(PairConst));
+        pvb.reserve(sizeof(PairVar));
         ovf.reserve((size_t)nP * sizeof(int32_t));
         deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
         Ctl *ctl = ctlb.as<Ctl>();
-        PairDev *pd = pdb.as<PairDev>();
+        PairConst *pc = pcb.as<PairConst>();
+        PairVar *pv = pvb.as<PairVar>();
         k_ctl_init<<<1, 1, 0, s>>>(ctl);
-        k_pairs_init<<<1, 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), 1);
+        k_pairs_init<<<1, 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), 1);
         const QueryCfg cfg{B->nodes.as<NodeRec>(), B->ids.as<int4>(), 0};
         auto go = [&](auto tag) {
             using T = decltype(tag);
@@ -1324,15 +1375,15 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             qi.mode = Q_POINTS;
             qi.npairs = 1;
             qi.P = P;
-            qi.pd = pd;
+            qi.pc = pc;
             BView<T> bv;
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
-            k_query<T, QSTACK><<<grid_for(nP, QBLOCK), QBLOCK, 0, s>>>(qi, nP, cfg, bv, qb.o, pd, ctl,
+            k_query<T, QSTACK><<<grid_for(nP, QBLOCK), QBLOCK, 0, s>>>(qi, nP, cfg, bv, qb.o, pc, pv, ctl,
                                                                         ovf.as<int32_t>());
-            k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pd, ctl, ovf.as<int32_t>(),
+            k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(),
                                                             deep.as<int2>());
-            k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pd, d, I, Q);
+            k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q);
             HD_LAUNCH_CHECK();
             HD_HIP(hipStreamSynchronize(s));
         };
@@ -1352,20 +1403,21 @@ hd_status hd_eval_bounds(const double *v, const double *dd, const int32_t *I, co
     const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
     hipStream_t s = (hipStream_t)stream;
     return guard([&] {
-        DBuf inv, pdb;
+        DBuf inv, pcb, pvb;
         inv.reserve((size_t)B->nB * sizeof(int32_t));
-        pdb.reserve(sizeof(PairDev));
-        PairDev *pd = pdb.as<PairDev>();
-        k_pairs_init<<<1, 64, 0, s>>>(pd, B->pairs.as<BvhPair>(), 1);
+        pcb.reserve(sizeof(PairConst));
+        pvb.reserve(sizeof(PairVar));
+        PairConst *pc = pcb.as<PairConst>();
+        k_pairs_init<<<1, 64, 0, s>>>(pc, pvb.as<PairVar>(), B->pairs.as<BvhPair>(), 1);
         k_inv_perm<<<grid_for(B->nB, BLK), BLK, 0, s>>>(B->ids.as<int4>(), B->nB, inv.as<int32_t>());
         IdView iv{B->ids.as<int4>()};
         if (precision == HD_PREC_FP64)
             k_eval_bounds<double><<<grid_for(n, BLK), BLK, 0, s>>>(v, dd, I, q, n, inv.as<int32_t>(), B->nB,
-                                                                   BView<double>{B->frames64.as<double2>()}, iv, pd,
+                                                                   BView<double>{B->frames64.as<double2>()}, iv, pc,
                                                                    out, u3_case);
         else
             k_eval_bounds<float><<<grid_for(n, BLK), BLK, 0, s>>>(v, dd, I, q, n, inv.as<int32_t>(), B->nB,
-                                                                  BView<float>{B->frames32.as<float4>()}, iv, pd,
+                                                                  BView<float>{B->frames32.as<float4>()}, iv, pc,
                                                                   out, u3_case);
         HD_LAUNCH_CHECK();
         HD_HIP(hipStreamSynchronize(s));

@@ -20,17 +20,23 @@ struct Margins {
     double mu_d, mu_e, mu_0;
 };
 
-// Per pair state of one call (device array).
-struct PairDev {
-    double ctr[3];   // centre subtracted from every coordinate of the pair
-    int32_t root;    // BVH subtree root (>= 0 node, < 0 leaf ~root)
-    int32_t status;
+// Per pair state of one call, in two device arrays: constants read by every
+// thread (written once after ingest), and the fields that kernels update
+// with atomics. Keeping them on separate cache lines matters: a device-scope
+// atomic evicts its line from every XCD's L2, and the constants are read by
+// every query.
+struct PairConst {
+    double ctr[3];  // centre subtracted from every coordinate of the pair
+    int32_t root;   // BVH subtree root (>= 0 node, < 0 leaf ~root)
+    int32_t pad;
     double eps_abs, dA;
     Margins m32, m64;
+};
+struct alignas(128) PairVar {
     unsigned long long Lord;      // ordered double: certified lower bound
+    unsigned long long round_key; // best (d_lo, tie tag) key of the current query round
     unsigned long long Uord;      // ordered double: final upper bound
     unsigned long long Urounds;   // ordered double: largest live bound of the rounds
-    unsigned long long round_key; // best (d_lo, tie hash) key of the current query round
     unsigned long long best_key;  // best key so far
     unsigned long long bbox[6];   // ordered FP64 bbox of A's referenced vertices
     unsigned long long coord_max; // ordered FP64 largest |coordinate| of A after centring
@@ -64,11 +70,11 @@ template <class T> struct FrontierView {
 struct AView {
     const double *V;
     const int32_t *F;
-    const PairDev *pd;
+    const PairConst *pc;
 };
 
 HD_D V3<double> a_vertex(const AView &a, int pair, int32_t v) {
-    const double *c = a.pd[pair].ctr;
+    const double *c = a.pc[pair].ctr;
     return {a.V[3 * (int64_t)v] - c[0], a.V[3 * (int64_t)v + 1] - c[1], a.V[3 * (int64_t)v + 2] - c[2]};
 }
 
