@@ -21,6 +21,7 @@
 
 #include "hd_geom.hpp"
 #include "hd_internal.hpp"
+#include "hd_reduce.hpp"
 
 namespace hd {
 
@@ -140,11 +141,8 @@ __global__ void k_faces_check(const PairSrc *__restrict__ src, const int64_t *__
             }
         }
     }
-    bool uni = uniform_pair(p);
-    for (int k = 0; k < 3; ++k) {
-        acc_min(&acc[p].bbox[k], lo[k], uni);
-        acc_max(&acc[p].bbox[3 + k], hi[k], uni);
-    }
+    const double v[6] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
+    block_pair_minmax<6, 0x38u, BLK>(p, valid, v, [&](int q, int k) { return &acc[q].bbox[k]; });
 }
 
 __global__ void k_pair_centres(const PairAcc *acc, int npairs, BvhPair *pairs) {
@@ -181,12 +179,10 @@ __global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__re
         }
     }
     if (f < n) fpair[f] = p;
-    bool uni = uniform_pair(p);
-    for (int k = 0; k < 3; ++k) {
-        acc_min(&acc[p].cbox[k], clo[k], uni);
-        acc_max(&acc[p].cbox[3 + k], chi[k], uni);
-    }
-    acc_max(&acc[p].coord_max, m, uni);
+    const double v[7] = {clo[0], clo[1], clo[2], chi[0], chi[1], chi[2], m};
+    block_pair_minmax<7, 0x78u, BLK>(p, valid, v, [&](int q, int k) {
+        return k < 6 ? &acc[q].cbox[k] : &acc[q].coord_max;
+    });
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -269,15 +265,33 @@ __global__ void k_karras(const unsigned long long *__restrict__ keys, int64_t n,
     if (lo / TILE != hi / TILE) upper[atomicAdd(&st->n_upper, 1)] = (int32_t)i;
 }
 
-// leaf data in sorted order: outward-rounded box, frame records, ids
-__global__ void k_leaves(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff,
-                         const int32_t *__restrict__ fpair, const int32_t *__restrict__ order, int64_t n,
-                         const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox, float4 *__restrict__ fr32,
-                         double2 *__restrict__ fr64, int4 *__restrict__ ids, PairAcc *acc, const BuildState *st) {
+// leaf data in sorted order: outward-rounded box, frame records, ids; the
+// longest edge of each pair
+__device__ double build_leaf(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int p, int32_t f,
+                             const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox, float4 *__restrict__ fr32,
+                             double2 *__restrict__ fr64, int4 *__restrict__ ids, int64_t i);
+
+__global__ __launch_bounds__(BLK) void k_leaves(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff,
+                                                const int32_t *__restrict__ fpair, const int32_t *__restrict__ order,
+                                                int64_t n, const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox,
+                                                float4 *__restrict__ fr32, double2 *__restrict__ fr64,
+                                                int4 *__restrict__ ids, PairAcc *acc, const BuildState *st) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || st->bad) return;
-    int32_t f = order[i];
-    int p = fpair[f];
+    const bool valid = i < n && !st->bad;
+    int p = 0;
+    double Lb = 0;
+    if (valid) {
+        int32_t f = order[i];
+        p = fpair[f];
+        Lb = build_leaf(src, foff, p, f, pairs, lbox, fr32, fr64, ids, i);
+    }
+    const double v[1] = {Lb};
+    block_pair_minmax<1, 1u, BLK>(p, valid, v, [&](int q, int) { return &acc[q].edge_max; });
+}
+
+__device__ double build_leaf(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int p, int32_t f,
+                             const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox, float4 *__restrict__ fr32,
+                             double2 *__restrict__ fr64, int4 *__restrict__ ids, int64_t i) {
     PairSrc ps = src[p];
     int64_t lf = f - foff[p];
     // (no runtime-indexed private arrays here: they would be promoted to LDS)
@@ -337,7 +351,7 @@ __global__ void k_leaves(const PairSrc *__restrict__ src, const int64_t *__restr
     q[6] = make_double2(ibc, ica);
     q[7] = make_double2(Lb, 0.0);
     ids[i] = make_int4(iA, iB, iC, (int32_t)lf);
-    atomicMax(&acc[p].edge_max, d2ord(Lb));
+    return Lb;
 }
 
 __device__ __forceinline__ void load_box(const float4 *nbox, const float4 *__restrict__ lbox, int32_t c, float4 &lo,
@@ -382,42 +396,39 @@ __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *
     }
 }
 
-// nodes spanning tiles: one workgroup, repeated sweeps until every node whose
-// children are ready has been built (the number of sweeps is the height of
-// the tree above the tiles)
+// nodes spanning tiles: one workgroup climbs bottom-up. A node's counter
+// starts at the number of its children that are already complete (leaves and
+// tile-internal nodes); climbs start at nodes with two such children, and the
+// thread that brings a parent's counter to 2 builds it and climbs on
+// (workgroup-scope atomics: all threads share one CU).
 __global__ __launch_bounds__(1024) void k_refit_upper(const int32_t *__restrict__ upper, const BuildState *st,
                                                       const int32_t *__restrict__ childL,
                                                       const int32_t *__restrict__ childR,
+                                                      const int32_t *__restrict__ parentN,
                                                       const int2 *__restrict__ range, const float4 *__restrict__ lbox,
-                                                      float4 *nbox, int32_t *done) {
-    __shared__ int changed;
+                                                      float4 *nbox, int32_t *cnt) {
     const int nup = st->n_upper;
-    // done[u] = sweep that built u, plus one; a child counts as ready only if
-    // it was built in an earlier sweep, whose stores the barrier has published
-    int sweep = 0;
-    auto ready = [&](int32_t c) {
-        if (c < 0) return true;
+    auto complete = [&](int32_t c) {
+        if (c < 0) return 1;
         int2 r = range[c];
-        if (r.x / TILE == r.y / TILE) return true;
-        int dc = done[c];
-        return dc != 0 && dc <= sweep;
+        return r.x / TILE == r.y / TILE ? 1 : 0;
     };
-    for (;; ++sweep) {
-        __syncthreads();
-        if (threadIdx.x == 0) changed = 0;
-        __syncthreads();
-        for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-            int32_t u = upper[k];
-            if (done[u]) continue;
-            int32_t cl = childL[u], cr = childR[u];
-            if (ready(cl) && ready(cr)) {
-                union_box(nbox, lbox, cl, cr, nbox + 2 * (int64_t)u);
-                done[u] = sweep + 1;
-                changed = 1;
-            }
+    for (int k = threadIdx.x; k < nup; k += blockDim.x) {
+        int32_t u = upper[k];
+        cnt[u] = complete(childL[u]) + complete(childR[u]);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nup; k += blockDim.x) {
+        int32_t x = upper[k];
+        if (complete(childL[x]) + complete(childR[x]) != 2) continue;
+        while (true) {
+            union_box(nbox, lbox, childL[x], childR[x], nbox + 2 * (int64_t)x);
+            int32_t p = parentN[x];
+            if (p < 0) break;
+            int old = __hip_atomic_fetch_add(&cnt[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old + 1 < 2) break;
+            x = p;
         }
-        __syncthreads();
-        if (!changed) break;
     }
 }
 
@@ -590,7 +601,7 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
             k_karras<<<grid_for(ni, BLK), BLK, 0, s>>>(keys, n, cl, cr, pn, pl, range, upper, st);
             k_refit_tiles<<<grid_for(n, TILE), TILE, 0, s>>>(n, cl, cr, pn, pl, range, lbox, nbox, cnt);
             k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(cnt, ni, 0);
-            k_refit_upper<<<1, 1024, 0, s>>>(upper, st, cl, cr, range, lbox, nbox, cnt);
+            k_refit_upper<<<1, 1024, 0, s>>>(upper, st, cl, cr, pn, range, lbox, nbox, cnt);
             k_node_records<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, cl, cr, nbox, lbox, b->nodes.as<NodeRec>());
             k_pair_roots<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, range, dpairs, npairs, keys);
         }

@@ -26,13 +26,14 @@
 #include <mutex>
 
 #include "hd_kernels.hpp"
+#include "hd_reduce.hpp"
 
 namespace hd {
 
 namespace {
 
 constexpr int QBLOCK = 128;   // query kernel block
-constexpr int QSTACK = 24;    // LDS stack entries per lane
+constexpr int QSTACK = 16;    // LDS ring-stack entries per lane (16 KB per block)
 constexpr int SMALL_STACK = 4; // test hook: tiny LDS stack, forces the deep path
 constexpr int DEEP_STACK = 256;
 constexpr int DEEP_SLOTS = 4096; // concurrent deep traversals
@@ -43,6 +44,7 @@ struct Ctl {
     unsigned long long queries, evals, boxes, bounded, q_leaves, q_boxes, rechecked;
     unsigned long long discards[5];
     unsigned long long act_next, park_next; // append counters of the current round
+    unsigned long long b_next, c_next;      // records waiting for cascade stage B / C
     int bad;        // 1 invalid input, 2 traversal deeper than the fallback stack, 3 depth exhausted
     int n_overflow; // queries whose LDS stack overflowed this round
 };
@@ -136,6 +138,8 @@ __global__ void k_round_setup(Ctl *c, unsigned long long act_base, unsigned long
     c->n_overflow = 0;
     c->act_next = act_base;
     c->park_next = park_base;
+    c->b_next = 0;
+    c->c_next = 0;
 }
 
 __global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int npairs) {
@@ -199,12 +203,10 @@ __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__rest
             }
         }
     }
-    bool uni = wave_uniform(p);
-    for (int k = 0; k < 3; ++k) {
-        acc_min(&pv[p].bbox[k], lo[k], uni);
-        acc_max(&pv[p].bbox[3 + k], hi[k], uni);
-    }
-    acc_max(&pv[p].coord_max, cm, uni);
+    const double v[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], cm};
+    block_pair_minmax<7, 0x78u, BLK>(p, valid, v, [&](int q, int k) {
+        return k < 6 ? &pv[q].bbox[k] : &pv[q].coord_max;
+    });
 }
 
 __device__ Margins make_margins(double u, double edge_max, double coord_max) {
@@ -293,14 +295,14 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
     int64_t j = i / 3;
     int e = (int)(i - 3 * j);
     int k = (e + 1) % 3;
-    int face = in.par.face[j], lvl = in.par.lvl[j] + 1;
-    int ba = in.par.ba[e][j] + in.par.ba[k][j], bb = in.par.bb[e][j] + in.par.bb[k][j];
-    q.pair = in.par.pair[j];
+    int face = in.par.face()[j], lvl = in.par.lvl()[j] + 1;
+    int ba = in.par.ba(e)[j] + in.par.ba(k)[j], bb = in.par.bb(e)[j] + in.par.bb(k)[j];
+    q.pair = in.par.pair()[j];
     q.p = a_point(in.a, q.pair, face, lvl, ba, bb);
     q.out = i;
     q.tag = point_tag(face, lvl, ba, bb);
-    q.seed[0] = in.par.I[e][j];
-    q.seed[1] = in.par.I[k][j];
+    q.seed[0] = in.par.I(e)[j];
+    q.seed[1] = in.par.I(k)[j];
     return q;
 }
 
@@ -351,7 +353,7 @@ HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResul
 }
 
 template <class T, int SD>
-__global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, int64_t n, QueryCfg cfg, BView<T> bv,
+__global__ __launch_bounds__(QBLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_query(QueryIn<T> in, int64_t n, QueryCfg cfg, BView<T> bv,
                                                   QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
                                                   Ctl *ctl, int32_t *ovf_list) {
     __shared__ int s_node[SD * QBLOCK];
@@ -482,115 +484,219 @@ template <class T> struct Corner {
     int I, ba, bb;
 };
 
-// returns the class (0 discard, 1 park, 2 active); *ub_out the bound
-template <class T>
-HD_D int classify(const Corner<T> cn[3], int pair, int face, int lvl, const ClassifyCfg &cc, const BView<T> &bv,
-                  float *ub_out, int *decider, int *evals, int *rechecked) {
+// The cascade runs in three stages, each its own kernel, so that the
+// frequent cheap cases do not carry the registers of the expensive ones:
+//   A: the exact bound, then the bounds listed before u3 in the order;
+//   B: u3 and every bound after it (triangles A could not decide);
+//   C: the FP64 re-bound of triangles whose decision lies within the FP32
+//      margin (the recheck band).
+// The decision is the same as the one-pass cascade in the same order.
+enum { TO_DISCARD = -1, TO_ACT = 0, TO_PARK = 1, TO_B = 2, TO_C = 3 };
+
+template <class T> HD_D Tri<T> make_tri(const Corner<T> cn[3]) {
     Tri<T> t;
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
         t.v[i] = cn[i].v;
         t.q[i] = cn[i].q;
         t.d[i] = cn[i].d;
         t.I[i] = cn[i].I;
     }
-    const PairConst &P = cc.pc[pair];
-    const double L = ord2d(cc.pv[pair].Lord), eps = P.eps_abs;
-    const Margins &m = margins_of<T>(P);
-    double ub = cascade<T>(t, L, cc.c, m, bv, cc.iv, decider, evals);
-    const double park_lim = eps * (1.0 - 1.0 / 1024.0 / 1024.0 / 1024.0);
-    if (cc.recheck) {
-        // the FP32 margin might hide a discard or a park: redo in FP64
-        double mu = tri_margin(t, m);
+    return t;
+}
+
+HD_D double park_limit(double eps) { return eps * (1.0 - 1.0 / 1024.0 / 1024.0 / 1024.0); }
+
+// list for a final bound ub (margin mu included)
+HD_D int decide(double ub, double L, double eps, double mu, bool recheck) {
+    const double lim = park_limit(eps);
+    if (recheck) {
         bool maybe_discard = ub >= L && ub - 2 * mu < L;
-        bool maybe_park = ub - L > park_lim && ub - 2 * mu - L <= park_lim;
-        if (maybe_discard || maybe_park) {
-            int ba[3] = {cn[0].ba, cn[1].ba, cn[2].ba}, bb[3] = {cn[0].bb, cn[1].bb, cn[2].bb};
-            double u64 = rebound64(cc.a, pair, face, lvl, ba, bb, t.I, cc.bv64, cc.iv, cc.c, P.m64, evals);
-            ub = hmin(ub, u64);
-            *rechecked += 1;
+        bool maybe_park = ub - L > lim && ub - 2 * mu - L <= lim;
+        if (maybe_discard || maybe_park) return TO_C;
+    }
+    return ub < L ? TO_DISCARD : (ub - L <= lim ? TO_PARK : TO_ACT);
+}
+
+HD_D float round_up_to_float(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = next_up(f);
+    return f;
+}
+
+template <class T> HD_D T bound_cheap(int k, const Tri<T> &t) {
+    return k == 1 ? bound_u1(t) : (k == 2 ? bound_u2(t) : bound_u4(t));
+}
+
+// stage A; *carry receives the running minimum for stage B
+template <class T>
+HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double *carry, int *decider) {
+    const Tri<T> t = make_tri(cn);
+    const PairConst &P = cc.pc[pair];
+    const double L = ord2d(cc.pv[pair].Lord);
+    const double mu = tri_margin(t, margins_of<T>(P));
+    if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) {
+        *decider = 0;
+        double ub = (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
+        *carry = ub;
+        return decide(ub, L, P.eps_abs, mu, cc.recheck);
+    }
+    double best = __builtin_inf();
+    *decider = cc.c.order[cc.c.norder - 1];
+    for (int i = 0; i < cc.c.norder; ++i) {
+        int k = cc.c.order[i];
+        if (k == 3) {
+            *carry = best;
+            return TO_B;
+        }
+        double u = (double)bound_cheap<T>(k, t) + mu;
+        if (u < L) {
+            *decider = k;
+            *carry = u;
+            return TO_DISCARD;
+        }
+        if (u < best) {
+            best = u;
+            *decider = k;
         }
     }
-    float ubf = (float)ub;
-    if ((double)ubf < ub) ubf = next_up(ubf);
-    *ub_out = ubf;
-    return ub < L ? 0 : (ub - L <= park_lim ? 1 : 2);
+    *carry = best;
+    return decide(best, L, P.eps_abs, mu, cc.recheck);
+}
+
+// stage B: u3 and the bounds after it, from the running minimum `best`
+template <class T>
+HD_D int stage_b(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, const BView<T> &bv, double best,
+                 int best_k, double *carry, int *decider, int *evals) {
+    const Tri<T> t = make_tri(cn);
+    const PairConst &P = cc.pc[pair];
+    const double L = ord2d(cc.pv[pair].Lord);
+    const double mu = tri_margin(t, margins_of<T>(P));
+    int i3 = 0;
+    while (cc.c.order[i3] != 3) ++i3;
+    *decider = best_k;
+    for (int i = i3; i < cc.c.norder; ++i) {
+        int k = cc.c.order[i];
+        double u = (double)(k == 3 ? bound_u3(t, bv, cc.iv, nullptr, evals) : bound_cheap<T>(k, t)) + mu;
+        if (u < L) {
+            *decider = k;
+            *carry = u;
+            return TO_DISCARD;
+        }
+        if (u < best) {
+            best = u;
+            *decider = k;
+        }
+    }
+    *carry = best;
+    return decide(best, L, P.eps_abs, mu, cc.recheck);
 }
 
 template <class T>
 HD_D void write_record(const FrontierView<T> &fo, int64_t o, const Corner<T> cn[3], float ub, int face, int lvl,
                        int pair) {
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
-        fo.v[3 * i][o] = cn[i].v.x;
-        fo.v[3 * i + 1][o] = cn[i].v.y;
-        fo.v[3 * i + 2][o] = cn[i].v.z;
-        fo.q[3 * i][o] = cn[i].q.x;
-        fo.q[3 * i + 1][o] = cn[i].q.y;
-        fo.q[3 * i + 2][o] = cn[i].q.z;
-        fo.d[i][o] = cn[i].d;
-        fo.I[i][o] = cn[i].I;
-        fo.ba[i][o] = cn[i].ba;
-        fo.bb[i][o] = cn[i].bb;
+        fo.v(3 * i)[o] = cn[i].v.x;
+        fo.v(3 * i + 1)[o] = cn[i].v.y;
+        fo.v(3 * i + 2)[o] = cn[i].v.z;
+        fo.q(3 * i)[o] = cn[i].q.x;
+        fo.q(3 * i + 1)[o] = cn[i].q.y;
+        fo.q(3 * i + 2)[o] = cn[i].q.z;
+        fo.d(i)[o] = cn[i].d;
+        fo.I(i)[o] = cn[i].I;
+        fo.ba(i)[o] = cn[i].ba;
+        fo.bb(i)[o] = cn[i].bb;
     }
-    fo.ub[o] = ub;
-    fo.face[o] = face;
-    fo.lvl[o] = lvl;
-    fo.pair[o] = pair;
+    fo.ub()[o] = ub;
+    fo.face()[o] = face;
+    fo.lvl()[o] = lvl;
+    fo.pair()[o] = pair;
 }
 
-// block-aggregated append: one atomic per block and list; records of one
-// block stay in thread order
-struct Slots {
-    int64_t act, park;
-};
-__device__ Slots append_slots(bool act, bool park, Ctl *ctl) {
-    __shared__ int wa[NW], wp[NW];
-    __shared__ unsigned long long base_a, base_p;
+// Records waiting for stage B or C carry the index of the bound that gave
+// their running minimum in bits 8.. of the level field.
+HD_D int lvl_field(int list, int lvl, int decider) { return list >= TO_B ? lvl | (decider << 8) : lvl; }
+
+// Block-aggregated append to one of four lists (TO_ACT, TO_PARK, TO_B, TO_C;
+// anything else appends nothing): one atomic per block and list; records of
+// one block stay in thread order. Every thread of the block must call it.
+__device__ int64_t append_slot(int list, Ctl *ctl) {
+    __shared__ int wc[4][NW];
+    __shared__ unsigned long long base[4];
     const int w = threadIdx.x >> 6, lane = __lane_id();
     const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    unsigned long long ma = __ballot(act), mp = __ballot(park);
-    if (lane == 0) {
-        wa[w] = __popcll(ma);
-        wp[w] = __popcll(mp);
+    unsigned long long m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        m[k] = __ballot(list == k);
+        if (lane == 0) wc[k][w] = __popcll(m[k]);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int ta = 0, tp = 0;
-        for (int k = 0; k < NW; ++k) {
-            int a = wa[k], p = wp[k];
-            wa[k] = ta;
-            wp[k] = tp;
-            ta += a;
-            tp += p;
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        int tot = 0;
+        for (int j = 0; j < NW; ++j) {
+            int c = wc[k][j];
+            wc[k][j] = tot;
+            tot += c;
         }
-        base_a = ta ? atomicAdd(&ctl->act_next, (unsigned long long)ta) : 0;
-        base_p = tp ? atomicAdd(&ctl->park_next, (unsigned long long)tp) : 0;
+        unsigned long long *ctr = k == 0 ? &ctl->act_next : (k == 1 ? &ctl->park_next : (k == 2 ? &ctl->b_next : &ctl->c_next));
+        base[k] = tot ? atomicAdd(ctr, (unsigned long long)tot) : 0;
     }
     __syncthreads();
-    Slots s;
-    s.act = (int64_t)(base_a + wa[w] + __popcll(ma & lt));
-    s.park = (int64_t)(base_p + wp[w] + __popcll(mp & lt));
-    return s;
+    int64_t slot = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (list == k) slot = (int64_t)(base[k] + wc[k][w] + __popcll(m[k] & lt));
+    __syncthreads();
+    return slot;
 }
 
-template <class T>
-HD_D void tally(Ctl *ctl, int cls, int decider, int evals, int rechecked, bool valid) {
+HD_D void tally(Ctl *ctl, int list, int decider, int evals, int rechecked, bool valid, bool bounded) {
     unsigned long long dis[5] = {0, 0, 0, 0, 0};
-    if (valid && cls == 0) dis[decider] = 1;
+    if (valid && list == TO_DISCARD) dis[decider] = 1;
     for (int k = 0; k < 5; ++k) wave_add(&ctl->discards[k], dis[k]);
     wave_add(&ctl->evals, valid ? (unsigned long long)evals : 0ull);
     wave_add(&ctl->rechecked, valid ? (unsigned long long)rechecked : 0ull);
-    wave_add(&ctl->bounded, valid ? 1ull : 0ull);
+    wave_add(&ctl->bounded, valid && bounded ? 1ull : 0ull);
 }
 
-// round 0: every face of A from the per-vertex query results
+template <class T> struct Dest {
+    FrontierView<T> act, park, b, c;
+};
+
+// append a record to list `list` of d (nothing for TO_DISCARD)
+template <class T>
+HD_D void write_to(const Dest<T> &d, int list, int64_t o, const Corner<T> cn[3], float ub, int face, int lvl,
+                   int pair) {
+    if (list < 0) return;
+    const FrontierView<T> fo = list == TO_ACT ? d.act : (list == TO_PARK ? d.park : (list == TO_B ? d.b : d.c));
+    write_record(fo, o, cn, ub, face, lvl, pair);
+}
+
+// load a record's corners
+template <class T> HD_D void load_corners(const FrontierView<T> &f, int64_t j, Corner<T> cn[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        cn[i].v = {f.v(3 * i)[j], f.v(3 * i + 1)[j], f.v(3 * i + 2)[j]};
+        cn[i].q = {f.q(3 * i)[j], f.q(3 * i + 1)[j], f.q(3 * i + 2)[j]};
+        cn[i].d = f.d(i)[j];
+        cn[i].I = f.I(i)[j];
+        cn[i].ba = f.ba(i)[j];
+        cn[i].bb = f.bb(i)[j];
+    }
+}
+
+// round 0: every face of A from the per-vertex query results (stage A)
 template <class T>
 __global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__restrict__ F,
                                                 const int32_t *__restrict__ fpair, QueryOut<T> vq, ClassifyCfg cc,
-                                                BView<T> bv, FrontierView<T> act, FrontierView<T> park, Ctl *ctl) {
+                                                Dest<T> dst, Ctl *ctl) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = f < nA;
-    int cls = 0, decider = 0, evals = 0, rechecked = 0, pair = 0;
-    float ub = 0;
+    int list = TO_DISCARD, decider = 0, pair = 0;
+    double carry = 0;
     Corner<T> cn[3];
     if (valid) {
         pair = fpair[f];
@@ -603,62 +709,128 @@ __global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__res
             cn[j].ba = (j == 1);
             cn[j].bb = (j == 2);
         }
-        cls = classify<T>(cn, pair, (int)f, 0, cc, bv, &ub, &decider, &evals, &rechecked);
+        list = stage_a<T>(cn, pair, cc, &carry, &decider);
     }
-    Slots sl = append_slots(valid && cls == 2, valid && cls == 1, ctl);
-    if (valid && cls == 2) write_record(act, sl.act, cn, ub, (int)f, 0, pair);
-    if (valid && cls == 1) write_record(park, sl.park, cn, ub, (int)f, 0, pair);
-    tally<T>(ctl, cls, decider, evals, rechecked, valid);
+    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+    if (valid)
+        write_to(dst, list, slot, cn, round_up_to_float(carry), (int)f, lvl_field(list, 0, decider), pair);
+    tally(ctl, list, decider, 0, 0, valid, true);
 }
 
 // round k: child c of selected parent c/4, from the parent's record and the
 // three midpoint query results (midpoint e joins parent vertices e and e+1)
 template <class T>
 __global__ __launch_bounds__(BLK) void k_children(int64_t nsel, FrontierView<T> par, QueryOut<T> mq,
-                                                  ClassifyCfg cc, BView<T> bv, FrontierView<T> act,
-                                                  FrontierView<T> park, Ctl *ctl) {
+                                                  ClassifyCfg cc, Dest<T> dst, Ctl *ctl) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = c < 4 * nsel;
-    int cls = 0, decider = 0, evals = 0, rechecked = 0, pair = 0, face = 0, lvl = 0;
-    float ub = 0;
+    int list = TO_DISCARD, decider = 0, pair = 0, face = 0, lvl = 0;
+    double carry = 0;
     Corner<T> cn[3];
     if (valid) {
-        int64_t j = c >> 2;
-        int kid = (int)(c & 3);
-        // corners: 0..2 parent vertices, 3..5 midpoints m01, m12, m20
-        const int kids[4][3] = {{0, 3, 5}, {3, 1, 4}, {5, 4, 2}, {3, 4, 5}};
-        for (int i = 0; i < 3; ++i) {
-            int s = kids[kid][i];
-            if (s < 3) {
-                cn[i].v = {par.v[3 * s][j], par.v[3 * s + 1][j], par.v[3 * s + 2][j]};
-                cn[i].q = {par.q[3 * s][j], par.q[3 * s + 1][j], par.q[3 * s + 2][j]};
-                cn[i].d = par.d[s][j];
-                cn[i].I = par.I[s][j];
-                cn[i].ba = 2 * par.ba[s][j];
-                cn[i].bb = 2 * par.bb[s][j];
-            } else {
-                int e = s - 3, e2 = (e + 1) % 3;
-                int64_t mi = 3 * j + e;
-                cn[i].v = {mq.p[0][mi], mq.p[1][mi], mq.p[2][mi]};
-                cn[i].q = {mq.q[0][mi], mq.q[1][mi], mq.q[2][mi]};
-                cn[i].d = mq.d[mi];
-                cn[i].I = mq.I[mi];
-                cn[i].ba = par.ba[e][j] + par.ba[e2][j];
-                cn[i].bb = par.bb[e][j] + par.bb[e2][j];
-            }
+        const int64_t j = c >> 2;
+        const int kid = (int)(c & 3);
+        // corner s of the parent, or the midpoint of parent edge (e, e+1);
+        // every array index below is a compile-time constant, so the view's
+        // pointers stay in scalar registers
+        auto vert = [&](Corner<T> &o, auto S) {
+            constexpr int s = decltype(S)::value;
+            o.v = {par.v(3 * s)[j], par.v(3 * s + 1)[j], par.v(3 * s + 2)[j]};
+            o.q = {par.q(3 * s)[j], par.q(3 * s + 1)[j], par.q(3 * s + 2)[j]};
+            o.d = par.d(s)[j];
+            o.I = par.I(s)[j];
+            o.ba = 2 * par.ba(s)[j];
+            o.bb = 2 * par.bb(s)[j];
+        };
+        auto mid = [&](Corner<T> &o, auto E) {
+            constexpr int e = decltype(E)::value, e2 = (e + 1) % 3;
+            const int64_t mi = 3 * j + e;
+            o.v = {mq.p[0][mi], mq.p[1][mi], mq.p[2][mi]};
+            o.q = {mq.q[0][mi], mq.q[1][mi], mq.q[2][mi]};
+            o.d = mq.d[mi];
+            o.I = mq.I[mi];
+            o.ba = par.ba(e)[j] + par.ba(e2)[j];
+            o.bb = par.bb(e)[j] + par.bb(e2)[j];
+        };
+        using C0 = std::integral_constant<int, 0>;
+        using C1 = std::integral_constant<int, 1>;
+        using C2 = std::integral_constant<int, 2>;
+        // the four children, counter-clockwise like the parent:
+        // (v0, m01, m20), (m01, v1, m12), (m20, m12, v2), (m01, m12, m20)
+        if (kid == 0) {
+            vert(cn[0], C0{}); mid(cn[1], C0{}); mid(cn[2], C2{});
+        } else if (kid == 1) {
+            mid(cn[0], C0{}); vert(cn[1], C1{}); mid(cn[2], C1{});
+        } else if (kid == 2) {
+            mid(cn[0], C2{}); mid(cn[1], C1{}); vert(cn[2], C2{});
+        } else {
+            mid(cn[0], C0{}); mid(cn[1], C1{}); mid(cn[2], C2{});
         }
-        pair = par.pair[j];
-        face = par.face[j];
-        lvl = par.lvl[j] + 1;
+        pair = par.pair()[j];
+        face = par.face()[j];
+        lvl = par.lvl()[j] + 1;
         // dyadic coordinates are int32 numerators over 2^lvl: level 30 is the
         // deepest representable one
         if (lvl > 30) ctl->bad = 3;
-        cls = classify<T>(cn, pair, face, lvl, cc, bv, &ub, &decider, &evals, &rechecked);
+        list = stage_a<T>(cn, pair, cc, &carry, &decider);
     }
-    Slots sl = append_slots(valid && cls == 2, valid && cls == 1, ctl);
-    if (valid && cls == 2) write_record(act, sl.act, cn, ub, face, lvl, pair);
-    if (valid && cls == 1) write_record(park, sl.park, cn, ub, face, lvl, pair);
-    tally<T>(ctl, cls, decider, evals, rechecked, valid);
+    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+    if (valid)
+        write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
+    tally(ctl, list, decider, 0, 0, valid, true);
+}
+
+// stage B over the records stage A left undecided (count in ctl->b_next;
+// the grid covers an upper bound of it)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg cc, BView<T> bv, Dest<T> dst,
+                                                 Ctl *ctl) {
+    const int64_t n = (int64_t)ctl->b_next;
+    if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole block idle
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = j < n;
+    int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
+    double carry = 0;
+    Corner<T> cn[3];
+    if (valid) {
+        load_corners(in, j, cn);
+        pair = in.pair()[j];
+        face = in.face()[j];
+        lvl = in.lvl()[j] & 0xff;
+        list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+    }
+    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+    if (valid)
+        write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
+    tally(ctl, list, decider, evals, 0, valid, false);
+}
+
+// stage C: FP64 re-bound of the recheck band (count in ctl->c_next)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg cc, Dest<T> dst, Ctl *ctl) {
+    const int64_t n = (int64_t)ctl->c_next;
+    if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole block idle
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = j < n;
+    int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
+    double ub = 0;
+    Corner<T> cn[3];
+    if (valid) {
+        load_corners(in, j, cn);
+        pair = in.pair()[j];
+        face = in.face()[j];
+        lvl = in.lvl()[j] & 0xff;
+        decider = in.lvl()[j] >> 8;
+        const PairConst &P = cc.pc[pair];
+        int ba[3] = {cn[0].ba, cn[1].ba, cn[2].ba}, bb[3] = {cn[0].bb, cn[1].bb, cn[2].bb};
+        int I[3] = {cn[0].I, cn[1].I, cn[2].I};
+        double u64 = rebound64(cc.a, pair, face, lvl, ba, bb, I, cc.bv64, cc.iv, cc.c, P.m64, &evals);
+        ub = hmin((double)in.ub()[j], u64);
+        list = decide(ub, ord2d(cc.pv[pair].Lord), P.eps_abs, 0.0, false);
+    }
+    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+    if (valid) write_to(dst, list, slot, cn, round_up_to_float(ub), face, lvl, pair);
+    tally(ctl, list, decider, evals, 1, valid, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -666,20 +838,22 @@ __global__ __launch_bounds__(BLK) void k_children(int64_t nsel, FrontierView<T> 
 // ---------------------------------------------------------------------------
 template <class T>
 HD_D void copy_record(const FrontierView<T> &src, int64_t i, const FrontierView<T> &dst, int64_t o) {
+#pragma unroll
     for (int k = 0; k < 9; ++k) {
-        dst.v[k][o] = src.v[k][i];
-        dst.q[k][o] = src.q[k][i];
+        dst.v(k)[o] = src.v(k)[i];
+        dst.q(k)[o] = src.q(k)[i];
     }
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        dst.d[k][o] = src.d[k][i];
-        dst.I[k][o] = src.I[k][i];
-        dst.ba[k][o] = src.ba[k][i];
-        dst.bb[k][o] = src.bb[k][i];
+        dst.d(k)[o] = src.d(k)[i];
+        dst.I(k)[o] = src.I(k)[i];
+        dst.ba(k)[o] = src.ba(k)[i];
+        dst.bb(k)[o] = src.bb(k)[i];
     }
-    dst.ub[o] = src.ub[i];
-    dst.face[o] = src.face[i];
-    dst.lvl[o] = src.lvl[i];
-    dst.pair[o] = src.pair[i];
+    dst.ub()[o] = src.ub()[i];
+    dst.face()[o] = src.face()[i];
+    dst.lvl()[o] = src.lvl()[i];
+    dst.pair()[o] = src.pair()[i];
 }
 
 // dst[o] = src[perm[o]] (perm null: src[off + o])
@@ -696,9 +870,9 @@ __global__ void k_sel_keys(FrontierView<T> fr, int64_t n, unsigned long long *__
                            int32_t *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint32_t tag = point_tag(fr.face[i], fr.lvl[i], fr.ba[0][i] ^ (fr.ba[1][i] << 7) ^ (fr.ba[2][i] << 14),
-                             fr.bb[0][i] ^ (fr.bb[1][i] << 7) ^ (fr.bb[2][i] << 14));
-    keys[i] = ((unsigned long long)(~f2ord(fr.ub[i])) << 32) | tag;
+    uint32_t tag = point_tag(fr.face()[i], fr.lvl()[i], fr.ba(0)[i] ^ (fr.ba(1)[i] << 7) ^ (fr.ba(2)[i] << 14),
+                             fr.bb(0)[i] ^ (fr.bb(1)[i] << 7) ^ (fr.bb(2)[i] << 14));
+    keys[i] = ((unsigned long long)(~f2ord(fr.ub()[i])) << 32) | tag;
     vals[i] = (int32_t)i;
 }
 
@@ -706,18 +880,18 @@ __global__ void k_sel_keys(FrontierView<T> fr, int64_t n, unsigned long long *__
 // final FP64 step
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> bv64, IdView iv, CascadeCtx c,
+__global__ __launch_bounds__(BLK) void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> bv64, IdView iv, CascadeCtx c,
                           const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long ev = 0;
     if (i < n) {
-        int pair = fr.pair[i];
-        int ba[3] = {fr.ba[0][i], fr.ba[1][i], fr.ba[2][i]};
-        int bb[3] = {fr.bb[0][i], fr.bb[1][i], fr.bb[2][i]};
-        int I[3] = {fr.I[0][i], fr.I[1][i], fr.I[2][i]};
+        int pair = fr.pair()[i];
+        int ba[3] = {fr.ba(0)[i], fr.ba(1)[i], fr.ba(2)[i]};
+        int bb[3] = {fr.bb(0)[i], fr.bb(1)[i], fr.bb(2)[i]};
+        int I[3] = {fr.I(0)[i], fr.I(1)[i], fr.I(2)[i]};
         int evals = 0;
-        double u64 = rebound64(a, pair, fr.face[i], fr.lvl[i], ba, bb, I, bv64, iv, c, pc[pair].m64, &evals);
-        double u32 = (double)fr.ub[i];
+        double u64 = rebound64(a, pair, fr.face()[i], fr.lvl()[i], ba, bb, I, bv64, iv, c, pc[pair].m64, &evals);
+        double u32 = (double)fr.ub()[i];
         atomicMax(&pv[pair].Uord, d2ord(hmin(u64, u32)));
         atomicMax(&pv[pair].Urounds, d2ord(u32));
         ev = evals;
@@ -786,39 +960,23 @@ template <class T> struct FrontierBuf {
     DBuf mem;
     int64_t cap = 0;
     FrontierView<T> v{};
-    static size_t per() { return 21 * sizeof(T) + 13 * sizeof(int32_t) + sizeof(float); }
-    void carve(char *p, int64_t c) {
-        auto take = [&](size_t sz) {
-            char *r = p;
-            p += ((size_t)c * sz + 255) & ~size_t(255);
-            return r;
-        };
-        for (int k = 0; k < 9; ++k) v.v[k] = (T *)take(sizeof(T));
-        for (int k = 0; k < 9; ++k) v.q[k] = (T *)take(sizeof(T));
-        for (int k = 0; k < 3; ++k) v.d[k] = (T *)take(sizeof(T));
-        for (int k = 0; k < 3; ++k) v.I[k] = (int *)take(4);
-        v.ub = (float *)take(4);
-        v.face = (int *)take(4);
-        v.lvl = (int *)take(4);
-        v.pair = (int *)take(4);
-        for (int k = 0; k < 3; ++k) v.ba[k] = (int *)take(4);
-        for (int k = 0; k < 3; ++k) v.bb[k] = (int *)take(4);
-    }
+    // view over p for c records (c a multiple of 64)
+    static FrontierView<T> carve(char *p, int64_t c) { return FrontierView<T>{p, c}; }
     // grow to hold c records; the first `live` records are preserved
     void ensure(int64_t c, int64_t live, hipStream_t s) {
         if (c <= cap) return;
         int64_t nc = std::max<int64_t>(c, cap + cap / 2);
+        nc = (nc + 63) & ~int64_t(63);
         DBuf nm;
-        nm.reserve((size_t)nc * per() + 40 * 256);
-        FrontierBuf<T> tmp;
-        tmp.carve(nm.as<char>(), nc);
+        nm.reserve((size_t)nc * FrontierView<T>::bytes_per_record());
+        FrontierView<T> nv = carve(nm.as<char>(), nc);
         if (live > 0)
-            k_gather<T><<<grid_for(live, BLK), BLK, 0, s>>>(v, nullptr, 0, live, tmp.v);
+            k_gather<T><<<grid_for(live, BLK), BLK, 0, s>>>(v, nullptr, 0, live, nv);
         HD_LAUNCH_CHECK();
         HD_HIP(hipStreamSynchronize(s));
         mem.swap(nm);
         cap = nc;
-        v = tmp.v;
+        v = nv;
     }
 };
 
@@ -854,6 +1012,7 @@ template <class T> struct QBuf {
 // Buffers of the engine, kept between calls on one device (grow-only).
 template <class T> struct TypedWs {
     FrontierBuf<T> act, act2, park;
+    FrontierBuf<T> pend_b, pend_c; // records between cascade stages (one round's worth)
     QBuf<T> vq, mq;
 };
 struct Workspace {
@@ -1071,11 +1230,22 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cc.pc = pc;
     cc.pv = pv;
 
+    // stages B and C over what one round's stage A produced (at most n records)
+    auto later_stages = [&](int64_t n, const FrontierView<T> &act_out) {
+        Dest<T> d{act_out, tw.park.v, tw.pend_b.v, tw.pend_c.v};
+        k_stage_b<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
+        if (cc.recheck) k_stage_c<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl);
+        HD_LAUNCH_CHECK();
+    };
+
     // ---- round 0: bound every face ------------------------------------------
+    tw.pend_b.ensure(nA, 0, s);
+    if (cc.recheck) tw.pend_c.ensure(nA, 0, s);
     prof.mark(prof.c);
-    k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc, bv,
-                                                  tw.act.v, tw.park.v, ctl);
+    k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc,
+                                                  Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
     HD_LAUNCH_CHECK();
+    later_stages(nA, tw.act.v);
     prof.mark(prof.c);
     Ctl hc;
     HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -1143,9 +1313,14 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         run_queries(qi, 3 * K, tw.mq.o);
         // the unselected remainder first, then the active children
         if (rest > 0) k_gather<T><<<grid_for(rest, BLK), BLK, 0, s>>>(tw.act.v, nullptr, K, rest, tw.act2.v);
+        tw.pend_b.ensure(4 * K, 0, s);
+        if (cc.recheck) tw.pend_c.ensure(4 * K, 0, s);
         prof.mark(prof.c);
-        k_children<T><<<grid_for(4 * K, BLK), BLK, 0, s>>>(K, tw.act.v, tw.mq.o, cc, bv, tw.act2.v, tw.park.v, ctl);
+        k_children<T><<<grid_for(4 * K, BLK), BLK, 0, s>>>(K, tw.act.v, tw.mq.o, cc,
+                                                           Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
+                                                           ctl);
         HD_LAUNCH_CHECK();
+        later_stages(4 * K, tw.act2.v);
         prof.mark(prof.c);
         HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HD_HIP(hipStreamSynchronize(s));

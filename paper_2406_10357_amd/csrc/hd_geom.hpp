@@ -160,10 +160,11 @@ template <class T> HD_D T u2_g(const Tri<T> &t) {
     if (l2[1] > l2[k]) k = 1;
     if (l2[2] > l2[k]) k = 2;
     int a = (k + 1) % 3, b = (k + 2) % 3;
-    T lmax = hsqrt(l2[k]);
+    const T lk = pick3(l2[0], l2[1], l2[2], k);
+    T lmax = hsqrt(lk);
     const T slack = T(1) + T(8 * Prec<T>::u);
-    if (l2[k] < (l2[a] + l2[b]) * slack) {
-        V3<T> c = cross(e[a], e[b]);
+    if (lk < (pick3(l2[0], l2[1], l2[2], a) + pick3(l2[0], l2[1], l2[2], b)) * slack) {
+        V3<T> c = cross(pick3(e[0], e[1], e[2], a), pick3(e[0], e[1], e[2], b));
         T twice_area = hsqrt(norm2(c));
         if (twice_area > T(0)) {
             T R = hsqrt(l2[0]) * hsqrt(l2[1]) * hsqrt(l2[2]) / (T(2) * twice_area);
@@ -181,15 +182,24 @@ template <class T> HD_D T bound_u2(const Tri<T> &t) {
 // id[3]) perpendicular to the edge (a,b), pointing to the third vertex
 template <class T>
 HD_D bool inplane_dir(const V3<T> P[3], const int id[3], int ia, int ib, V3<T> &out) {
-    int ka = -1, kb = -1, kc = -1;
+    bool ha = false, hb = false, hc = false;
+    V3<T> pa = P[0], pb = P[0], pc = P[0];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (id[k] == ia && ka < 0) ka = k;
-        else if (id[k] == ib && kb < 0) kb = k;
-        else kc = k;
+        if (id[k] == ia && !ha) {
+            ha = true;
+            pa = P[k];
+        } else if (id[k] == ib && !hb) {
+            hb = true;
+            pb = P[k];
+        } else {
+            hc = true;
+            pc = P[k];
+        }
     }
-    if (ka < 0 || kb < 0 || kc < 0) return false;
-    V3<T> e = P[kb] - P[ka];
-    V3<T> w = P[kc] - P[ka];
+    if (!ha || !hb || !hc) return false;
+    V3<T> e = pb - pa;
+    V3<T> w = pc - pa;
     T ee = norm2(e);
     if (!(ee > T(0))) return false;
     V3<T> tt = w - (dot(w, e) / ee) * e;
@@ -212,34 +222,38 @@ HD_D T bound_u3(const Tri<T> &t, const BView<T> &bv, const IdView &iv, int *whic
     else if (t.I[1] != t.I[0] && t.I[0] == t.I[2]) odd = 1;
     else if (t.I[2] != t.I[0] && t.I[0] == t.I[1]) odd = 2;
     if (odd >= 0) {
-        int S1 = t.I[odd], S2 = t.I[(odd + 1) % 3];
+        // rotate so that the odd vertex comes first (selects, not indexing)
+        const int r1 = (odd + 1) % 3, r2 = (odd + 2) % 3;
+        const int S1 = pick3(t.I[0], t.I[1], t.I[2], odd), S2 = pick3(t.I[0], t.I[1], t.I[2], r1);
         int4 i1 = iv.ids[S1], i2 = iv.ids[S2];
         int a1[3] = {i1.x, i1.y, i1.z}, a2[3] = {i2.x, i2.y, i2.z};
-        int common[3], nc = 0;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j)
-                if (a1[i] == a2[j]) {
-                    bool dup = false;
-                    for (int k = 0; k < nc; ++k) dup |= common[k] == a1[i];
-                    if (!dup && nc < 3) common[nc++] = a1[i];
-                }
-        if (nc >= 2) {
+        // the first two distinct vertex ids of S1 that S2 shares, in S1's order
+        int c0 = -1, c1 = -1;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const bool shared = a1[i] == a2[0] || a1[i] == a2[1] || a1[i] == a2[2];
+            if (shared && c0 < 0) c0 = a1[i];
+            else if (shared && c1 < 0 && a1[i] != c0) c1 = a1[i];
+        }
+        if (c1 >= 0) {
             if (which_case) *which_case = 1;
             Frame<T> f1 = load_frame(bv.frames, S1), f2 = load_frame(bv.frames, S2);
             V3<T> P1[3] = {frame_vertex(f1, 0), frame_vertex(f1, 1), frame_vertex(f1, 2)};
             V3<T> P2[3] = {frame_vertex(f2, 0), frame_vertex(f2, 1), frame_vertex(f2, 2)};
-            int i1a = odd, i2a = (odd + 1) % 3, i3a = (odd + 2) % 3;
-            V3<T> v1 = t.v[i1a], v2 = t.v[i2a], v3 = t.v[i3a];
+            const V3<T> v1 = pick3(t.v[0], t.v[1], t.v[2], odd), v2 = pick3(t.v[0], t.v[1], t.v[2], r1),
+                        v3 = pick3(t.v[0], t.v[1], t.v[2], r2);
+            const T d1 = pick3(t.d[0], t.d[1], t.d[2], odd), d2 = pick3(t.d[0], t.d[1], t.d[2], r1),
+                    d3 = pick3(t.d[0], t.d[1], t.d[2], r2);
             V3<T> b1 = T(0.5) * (v1 + v2), b2 = T(0.5) * (v1 + v3);
             V3<T> t1, t2;
-            if (inplane_dir(P1, a1, common[0], common[1], t1) &&
-                inplane_dir(P2, a2, common[0], common[1], t2)) {
+            if (inplane_dir(P1, a1, c0, c1, t1) && inplane_dir(P2, a2, c0, c1, t2)) {
                 V3<T> nu = t1 - t2;
                 if (norm2(nu) > T(0)) {
-                    // a point of the shared edge: the corner of S1 with id common[0]
+                    // a point of the shared edge: the corner of S1 with id c0
                     V3<T> ea = P1[0];
+#pragma unroll
                     for (int k = 0; k < 3; ++k)
-                        if (a1[k] == common[0]) ea = P1[k];
+                        if (a1[k] == c0) ea = P1[k];
                     T f1v = dot(v1 - ea, nu), f2v = dot(v2 - ea, nu), f3v = dot(v3 - ea, nu);
                     if (f1v != f2v && f1v != f3v) {
                         T s12 = f1v / (f1v - f2v), s13 = f1v / (f1v - f3v);
@@ -250,9 +264,9 @@ HD_D T bound_u3(const Tri<T> &t, const BView<T> &bv, const IdView &iv, int *whic
                     }
                 }
             }
-            T hR = hmax(t.d[i1a], hmax(hsqrt(frame_dist2<T, false>(f1, b1, nullptr)),
-                                       hsqrt(frame_dist2<T, false>(f1, b2, nullptr))));
-            T hQ = hmax(hmax(t.d[i2a], t.d[i3a]),
+            T hR = hmax(d1, hmax(hsqrt(frame_dist2<T, false>(f1, b1, nullptr)),
+                                 hsqrt(frame_dist2<T, false>(f1, b2, nullptr))));
+            T hQ = hmax(hmax(d2, d3),
                         hmax(hsqrt(frame_dist2<T, false>(f2, b1, nullptr)),
                              hsqrt(frame_dist2<T, false>(f2, b2, nullptr))));
             if (evals) *evals += 4;
@@ -264,24 +278,24 @@ HD_D T bound_u3(const Tri<T> &t, const BView<T> &bv, const IdView &iv, int *whic
     V3<T> m2 = T(0.5) * (t.v[1] + t.v[2]);
     V3<T> m3 = T(0.5) * (t.v[2] + t.v[0]);
     V3<T> b = T(1.0 / 3.0) * (t.v[0] + t.v[1] + t.v[2]);
-    Frame<T> f[3] = {load_frame(bv.frames, t.I[0]), load_frame(bv.frames, t.I[1]),
-                     load_frame(bv.frames, t.I[2])};
-    // Q1 = (v1,m1,b,m3) to S1, Q2 = (v2,m2,b,m1) to S2, Q3 = (v3,m3,b,m2) to S3
+    // Q1 = (v1,m1,b,m3) to S1, Q2 = (v2,m2,b,m1) to S2, Q3 = (v3,m3,b,m2) to S3;
+    // alongside, h(T, S_i): the largest distance of T's vertices to S_i. One
+    // frame is live at a time.
     const V3<T> *corner[3][3] = {{&m1, &b, &m3}, {&m2, &b, &m1}, {&m3, &b, &m2}};
-    T part = T(0);
+    T part = T(0), whole = __builtin_inf();
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
-        T h = t.d[i];
-        for (int k = 0; k < 3; ++k) h = hmax(h, hsqrt(frame_dist2<T, false>(f[i], *corner[i][k], nullptr)));
-        part = hmax(part, h);
-    }
-    // h(T, S_i): largest distance of the three vertices to S_i
-    T best = part;
-    for (int i = 0; i < 3; ++i) {
-        T h = t.d[i];
+        const Frame<T> f = load_frame(bv.frames, t.I[i]);
+        T hq = t.d[i], ht = t.d[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) hq = hmax(hq, hsqrt(frame_dist2<T, false>(f, *corner[i][k], nullptr)));
+#pragma unroll
         for (int j = 0; j < 3; ++j)
-            if (j != i) h = hmax(h, hsqrt(frame_dist2<T, false>(f[i], t.v[j], nullptr)));
-        best = hmin(best, h);
+            if (j != i) ht = hmax(ht, hsqrt(frame_dist2<T, false>(f, t.v[j], nullptr)));
+        part = hmax(part, hq);
+        whole = hmin(whole, ht);
     }
+    const T best = hmin(part, whole);
     if (evals) *evals += 15;
     return best;
 }
@@ -316,8 +330,10 @@ template <class T> HD_D T bound_u4(const Tri<T> &t) {
     int s = 0;
     if (e[1] < e[s]) s = 1;
     if (e[2] < e[s]) s = 2;
-    int a = s, b = (s + 1) % 3, c = (s + 2) % 3;
-    return hmin(h_two_points(t, t.q[c], t.q[a]), h_two_points(t, t.q[c], t.q[b]));
+    V3<T> qa = t.q[0], qb = t.q[1], qc = t.q[2];
+    if (s == 1) { qa = t.q[1]; qb = t.q[2]; qc = t.q[0]; }
+    if (s == 2) { qa = t.q[2]; qb = t.q[0]; qc = t.q[1]; }
+    return hmin(h_two_points(t, qc, qa), h_two_points(t, qc, qb));
 }
 
 } // namespace hd

@@ -53,17 +53,25 @@ struct alignas(128) PairVar {
 // dyadic barycentric position V0 + (ba[i] * E1 + bb[i] * E2) / 2^lvl of that
 // face (E1 = V1 - V0, E2 = V2 - V0), so positions never accumulate rounding.
 // ---------------------------------------------------------------------------
+// One allocation of `cap` records, field by field (structure of arrays): 21
+// fields of T, then 13 fields of 4 bytes. A view is a base and a capacity, so
+// choosing among several lists per lane costs a few registers, not a table of
+// pointers.
 template <class T> struct FrontierView {
-    T *v[9];   // vertex i coordinate k at v[3*i+k]
-    T *q[9];   // closest point on B of vertex i
-    T *d[3];   // distance of vertex i to B (computed value)
-    int *I[3]; // closest triangle of vertex i (sorted index into B)
-    float *ub; // upper bound, margin included, rounded up
-    int *face;
-    int *lvl;
-    int *pair;
-    int *ba[3];
-    int *bb[3];
+    char *base;
+    int64_t cap; // a multiple of 64, so every field starts 256-byte aligned
+    HD_HD T *v(int k) const { return (T *)base + (int64_t)k * cap; }       // vertex i coordinate c at k = 3i+c
+    HD_HD T *q(int k) const { return (T *)base + (int64_t)(9 + k) * cap; } // closest point on B of vertex i
+    HD_HD T *d(int i) const { return (T *)base + (int64_t)(18 + i) * cap; } // computed distance of vertex i to B
+    HD_HD int *i32(int m) const { return (int *)((T *)base + 21 * cap) + (int64_t)m * cap; }
+    HD_HD int *I(int i) const { return i32(i); } // closest triangle of vertex i (sorted index into B)
+    HD_HD float *ub() const { return (float *)i32(3); } // upper bound, margin included, rounded up
+    HD_HD int *face() const { return i32(4); }
+    HD_HD int *lvl() const { return i32(5); }
+    HD_HD int *pair() const { return i32(6); }
+    HD_HD int *ba(int i) const { return i32(7 + i); } // dyadic barycentric numerators of vertex i
+    HD_HD int *bb(int i) const { return i32(10 + i); }
+    static constexpr size_t bytes_per_record() { return 21 * sizeof(T) + 13 * 4; }
 };
 
 // A's vertices and faces (all pairs concatenated; face indices are global).
@@ -124,25 +132,32 @@ HD_D float to_float_down(double x) {
     return f;
 }
 
-// per-lane stack in LDS, entries [depth][lane of block]
+// Per-lane short stack in LDS, entries [slot][lane of block], kept as a ring:
+// a push onto a full stack overwrites the oldest entry and reports the loss;
+// the traversal then restarts from the root once the stack runs empty, with
+// the best distance found so far (every subtree whose entry was lost is
+// still reachable from the root and is pruned or visited again).
 template <int SD, int BLOCK> struct LdsStack {
     int *node;
     float *dist;
-    int sp = 0;
+    int top = 0, cnt = 0;
     HD_D bool push(int n, float d) {
-        if (sp >= SD) return false;
-        node[sp * BLOCK + threadIdx.x] = n;
-        dist[sp * BLOCK + threadIdx.x] = d;
-        ++sp;
+        node[top * BLOCK + threadIdx.x] = n;
+        dist[top * BLOCK + threadIdx.x] = d;
+        top = top + 1 == SD ? 0 : top + 1;
+        if (cnt == SD) return false;
+        ++cnt;
         return true;
     }
     HD_D bool pop(int &n, float &d) {
-        if (sp == 0) return false;
-        --sp;
-        n = node[sp * BLOCK + threadIdx.x];
-        d = dist[sp * BLOCK + threadIdx.x];
+        if (cnt == 0) return false;
+        top = top == 0 ? SD - 1 : top - 1;
+        --cnt;
+        n = node[top * BLOCK + threadIdx.x];
+        d = dist[top * BLOCK + threadIdx.x];
         return true;
     }
+    HD_D void clear() { top = cnt = 0; }
 };
 
 // per-lane stack in global memory (deep fallback)
@@ -165,7 +180,12 @@ struct GlobalStack {
         d = __builtin_bit_cast(float, e.y);
         return true;
     }
+    HD_D void clear() { sp = 0; }
 };
+
+// traversal restarts allowed after stack losses before the query is handed
+// to the deep-stack path
+constexpr int MAX_RESTARTS = 3;
 
 template <class T> struct QueryResult {
     T d2;
@@ -215,6 +235,8 @@ HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &
         return r;
     }
     int node = root;
+    bool lost = false;
+    int restarts = 0;
     while (true) {
         const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
         float4 a = np[0], b = np[1], c = np[2], d = np[3];
@@ -238,7 +260,7 @@ HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &
             bool lfirst = dl <= dr;
             int nearc = lfirst ? cl : cr, farc = lfirst ? cr : cl;
             T fard = lfirst ? dr : dl;
-            if (!st.push(farc, to_float_down(fard))) r.overflow = true;
+            if (!st.push(farc, to_float_down(fard))) lost = true;
             node = nearc;
             continue;
         }
@@ -260,7 +282,17 @@ HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &
                 break;
             }
         }
-        if (!found) break;
+        if (!found) {
+            if (!lost) break;
+            // entries were dropped: visit the tree again with the bound found
+            if (++restarts > MAX_RESTARTS) {
+                r.overflow = true;
+                break;
+            }
+            lost = false;
+            st.clear();
+            node = root;
+        }
     }
     return r;
 }
@@ -337,9 +369,15 @@ HD_D double rebound64(const AView &a, int pair, int32_t face, int lvl, const int
     *evals += 3;
     double mu = tri_margin(t, m64);
     if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) return hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
+    // the minimum over the bounds in the set does not depend on their order
+    unsigned used = 0;
+    for (int i = 0; i < c.norder; ++i) used |= 1u << c.order[i];
     double best = __builtin_inf();
-    for (int i = 0; i < c.norder; ++i) best = hmin(best, bound_k<double>(c.order[i], t, bv64, iv, evals) + mu);
-    return best;
+    if (used & 2u) best = hmin(best, bound_u1(t));
+    if (used & 4u) best = hmin(best, bound_u2(t));
+    if (used & 16u) best = hmin(best, bound_u4(t));
+    if (used & 8u) best = hmin(best, bound_u3(t, bv64, iv, nullptr, evals));
+    return best + mu;
 }
 
 } // namespace hd

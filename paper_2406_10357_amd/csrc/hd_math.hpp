@@ -26,6 +26,15 @@ template <class T> HD_HD T norm2(V3<T> a) { return dot(a, a); }
 template <class T> HD_HD T hmin(T a, T b) { return a < b ? a : b; }
 template <class T> HD_HD T hmax(T a, T b) { return a > b ? a : b; }
 template <class T> HD_HD T clamp01(T t) { return hmin(hmax(t, T(0)), T(1)); }
+// a[k] for k in 0..2 as selects between values. A run-time index into a
+// register array (or a ?: between two array elements, which selects an
+// address) makes the compiler keep the array in private (scratch) memory.
+template <class X> HD_HD X pick3(X a0, X a1, X a2, int k) {
+    X r = a2;
+    if (k == 0) r = a0;
+    if (k == 1) r = a1;
+    return r;
+}
 template <class T> HD_HD T clampab(T t, T a, T b) { return hmin(hmax(t, a), b); }
 
 HD_D float hsqrt(float x) { return __builtin_sqrtf(x); }

@@ -1,0 +1,86 @@
+// hd_reduce.hpp -- per-pair min/max reductions over a workgroup.
+//
+// Device-scope atomics on one address serialise at the memory side (about
+// 10 ns each on a multi-XCD part), so a kernel where every thread folds a
+// value into its pair's slot would spend its time in atomics. Here a block
+// reduces in registers and LDS first: one atomic per value per block when the
+// whole block belongs to one pair (the common case, since a pair's elements
+// are contiguous), one per wave when a block straddles pairs, one per lane
+// only in a wave that itself mixes pairs.
+#pragma once
+#include "hd_math.hpp"
+
+namespace hd {
+
+// v[k] is reduced with max when bit k of MAXMASK is set, else with min.
+// Threads with valid == false must pass neutral values (+inf for min, -inf
+// for max, or anything with valid == false: they are masked out). addr(p, k)
+// returns the ordered-bits slot of value k of pair p. Every thread of the
+// block must call this (it contains barriers).
+template <int K, unsigned MAXMASK, int BLOCK, class Addr>
+__device__ __forceinline__ void block_pair_minmax(int p, bool valid, const double (&v)[K], Addr addr) {
+    constexpr int NW = BLOCK / 64;
+    __shared__ double sv[NW][K];
+    __shared__ int sp[NW];
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const unsigned long long vm = __ballot(valid);
+    int p0 = vm ? __shfl(p, __ffsll(vm) - 1, 64) : -1;
+    const bool wave_uni = __ballot(valid && p != p0) == 0;
+    double r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const bool mx = (MAXMASK >> k) & 1u;
+        double x = valid ? v[k] : (mx ? -__builtin_inf() : __builtin_inf());
+        if (wave_uni) {
+            for (int o = 32; o >= 1; o >>= 1) {
+                double y = __shfl_xor(x, o, 64);
+                x = mx ? fmax(x, y) : fmin(x, y);
+            }
+        } else if (valid) {
+            unsigned long long *a = addr(p, k);
+            if (mx) atomicMax(a, d2ord(x));
+            else atomicMin(a, d2ord(x));
+        }
+        r[k] = x;
+    }
+    if (lane == 0) {
+        sp[w] = (vm && wave_uni) ? p0 : -1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) sv[w][k] = r[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int q = -1;
+        bool uni = true;
+        for (int i = 0; i < NW; ++i) {
+            if (sp[i] < 0) continue;
+            if (q < 0) q = sp[i];
+            else if (sp[i] != q) uni = false;
+        }
+        if (q >= 0 && uni) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const bool mx = (MAXMASK >> k) & 1u;
+                double x = mx ? -__builtin_inf() : __builtin_inf();
+                for (int i = 0; i < NW; ++i)
+                    if (sp[i] >= 0) x = mx ? fmax(x, sv[i][k]) : fmin(x, sv[i][k]);
+                unsigned long long *a = addr(q, k);
+                if (mx) atomicMax(a, d2ord(x));
+                else atomicMin(a, d2ord(x));
+            }
+        } else if (q >= 0) {
+            for (int i = 0; i < NW; ++i) {
+                if (sp[i] < 0) continue;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    unsigned long long *a = addr(sp[i], k);
+                    if ((MAXMASK >> k) & 1u) atomicMax(a, d2ord(sv[i][k]));
+                    else atomicMin(a, d2ord(sv[i][k]));
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+} // namespace hd
