@@ -125,6 +125,7 @@ def main():
         "result": {"L": L, "U": U, "dA": st["dA"], "eps_abs": st["eps_abs"], "rounds": st["rounds"],
                    "subdivided": st["subdivided"], "nodes_bounded": st["nodes_bounded"],
                    "queries": st["queries"], "pt_tri_evals": st["pt_tri_evals"],
+                   "query_leaf_evals": st["query_leaf_evals"], "query_box_tests": st["query_box_tests"],
                    "discards": st["discards"], "rechecked64": st["rechecked64"],
                    "parked_final": st["parked_final"]},
         "evals_per_s": evals / ((q_ms + c_ms) * 1e-3) if q_ms + c_ms > 0 else None,

@@ -106,7 +106,10 @@ hd_status hd_build_bvh_batched(int32_t npairs, const double *const *VB, const in
                                const int32_t *const *FB, const int64_t *nB, hd_stream_t stream,
                                hd_bvh *out);
 
-/* Release a handle from hd_build_bvh or hd_build_bvh_batched (NULL is allowed). */
+/* Release a handle from hd_build_bvh or hd_build_bvh_batched (NULL is allowed).
+ * Waits for the device to go idle (work on any stream may still read the
+ * BVH). The library may keep the handle's device buffers for a later build on
+ * the same device instead of freeing them. */
 void hd_free_bvh(hd_bvh bvh);
 
 /* Certified [L, U] for h(A, B), B given by its BVH; eps is the paper's

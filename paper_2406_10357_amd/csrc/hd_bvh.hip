@@ -50,6 +50,7 @@ struct PairAcc { // per-pair accumulators, ordered-double bits
 struct BuildState {
     int bad;
     int n_upper;
+    int n_wide; // four-wide nodes
 };
 
 __global__ void k_init(PairAcc *acc, int npairs, BuildState *st) {
@@ -57,6 +58,7 @@ __global__ void k_init(PairAcc *acc, int npairs, BuildState *st) {
     if (p == 0) {
         st->bad = 0;
         st->n_upper = 0;
+        st->n_wide = 0;
     }
     if (p >= npairs) return;
     for (int k = 0; k < 3; ++k) {
@@ -340,7 +342,7 @@ __device__ double build_leaf(const PairSrc *__restrict__ src, const int64_t *__r
     fr32[4 * i] = make_float4((float)A.x, (float)A.y, (float)A.z, (float)Lb);
     fr32[4 * i + 1] = make_float4((float)ex.x, (float)ex.y, (float)ex.z, (float)cx);
     fr32[4 * i + 2] = make_float4((float)ey.x, (float)ey.y, (float)ey.z, (float)cy);
-    fr32[4 * i + 3] = make_float4((float)ibc, (float)ica, (float)Lb, 0.f);
+    fr32[4 * i + 3] = make_float4((float)ibc, (float)ica, (float)Lb, __builtin_bit_cast(float, (int32_t)lf));
     double2 *q = fr64 + 8 * i;
     q[0] = make_double2(A.x, A.y);
     q[1] = make_double2(A.z, Lb);
@@ -349,7 +351,7 @@ __device__ double build_leaf(const PairSrc *__restrict__ src, const int64_t *__r
     q[4] = make_double2(ey.x, ey.y);
     q[5] = make_double2(ey.z, cy);
     q[6] = make_double2(ibc, ica);
-    q[7] = make_double2(Lb, 0.0);
+    q[7] = make_double2(Lb, (double)lf);
     ids[i] = make_int4(iA, iB, iC, (int32_t)lf);
     return Lb;
 }
@@ -432,21 +434,92 @@ __global__ __launch_bounds__(1024) void k_refit_upper(const int32_t *__restrict_
     }
 }
 
-__global__ void k_node_records(int64_t ninternal, const int32_t *__restrict__ childL,
-                               const int32_t *__restrict__ childR, const float4 *__restrict__ nbox,
-                               const float4 *__restrict__ lbox, NodeRec *__restrict__ out) {
+// Collapse of the binary tree into four-wide nodes: a wide node stands for a
+// binary node at even depth below its pair's root, and its slots hold that
+// node's grandchildren (or a child itself when the child is a leaf).
+// flag[i] = 1 when internal node i is such a representative.
+__global__ void k_wide_flags(int64_t ninternal, const int32_t *__restrict__ parentN, const int2 *__restrict__ range,
+                             const BvhPair *__restrict__ pairs, int npairs, const unsigned long long *__restrict__ keys,
+                             int32_t *__restrict__ flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninternal) return;
-    int32_t cl = childL[i], cr = childR[i];
-    float4 l0, h0, l1, h1;
-    load_box(nbox, lbox, cl, l0, h0);
-    load_box(nbox, lbox, cr, l1, h1);
-    NodeRec r;
-    r.a = make_float4(l0.x, l0.y, l0.z, __builtin_bit_cast(float, cl));
-    r.b = make_float4(h0.x, h0.y, h0.z, __builtin_bit_cast(float, cr));
-    r.c = make_float4(l1.x, l1.y, l1.z, 0.f);
-    r.d = make_float4(h1.x, h1.y, h1.z, 0.f);
-    out[i] = r;
+    int f = 0;
+    const int2 r = range[i];
+    const int p = (int)(keys[r.x] >> 32);
+    if (p >= 0 && p < npairs) {
+        const BvhPair &P = pairs[p];
+        // inside the pair's subtree: the range lies within the pair's leaves
+        if (P.root >= 0 && r.x >= P.tri_begin && (int64_t)r.y < P.tri_end) {
+            int depth = 0;
+            int32_t x = (int32_t)i;
+            while (x != P.root && x >= 0) {
+                x = parentN[x];
+                ++depth;
+            }
+            f = (x == P.root && (depth & 1) == 0) ? 1 : 0;
+        }
+    }
+    flag[i] = f;
+}
+
+__global__ void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag, const int32_t *__restrict__ widx,
+                             const int32_t *__restrict__ childL, const int32_t *__restrict__ childR,
+                             const float4 *__restrict__ nbox, const float4 *__restrict__ lbox,
+                             WideNode *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninternal || !flag[i]) return;
+    float lo[3][4], hi[3][4];
+    int ref[4];
+    int k = 0;
+    auto put = [&](int32_t c) {
+        float4 l, h;
+        load_box(nbox, lbox, c, l, h);
+        // k is at most 3 here; the stores below use constant indices
+        const float lv[3] = {l.x, l.y, l.z}, hv[3] = {h.x, h.y, h.z};
+        const int32_t rf = c < 0 ? c : widx[c];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (s == k) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    lo[d][s] = lv[d];
+                    hi[d][s] = hv[d];
+                }
+                ref[s] = rf;
+            }
+        ++k;
+    };
+    const int32_t c2[2] = {childL[i], childR[i]};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int32_t c = c2[j];
+        if (c < 0) {
+            put(c);
+        } else {
+            put(childL[c]);
+            put(childR[c]);
+        }
+    }
+    WideNode w;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (s >= k) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                lo[d][s] = 0.f;
+                hi[d][s] = 0.f;
+            }
+            ref[s] = WIDE_EMPTY;
+        }
+    w.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+    w.loy = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+    w.loz = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+    w.hix = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+    w.hiy = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+    w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
+    w.child = make_int4(ref[0], ref[1], ref[2], ref[3]);
+    w.meta = make_int4(k, 0, 0, 0);
+    out[widx[i]] = w;
 }
 
 // root of each pair: the internal node whose leaf range is exactly the pair's
@@ -460,11 +533,14 @@ __global__ void k_pair_roots(int64_t ninternal, const int2 *__restrict__ range, 
     if (pairs[p].tri_begin == r.x && pairs[p].tri_end == (int64_t)r.y + 1) pairs[p].root = (int32_t)i;
 }
 
-__global__ void k_pair_finish(const PairAcc *acc, int npairs, BvhPair *pairs) {
+// per-pair maxima; the root becomes a wide-node index (widx null: no
+// internal nodes)
+__global__ void k_pair_finish(const PairAcc *acc, int npairs, BvhPair *pairs, const int32_t *__restrict__ widx) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
     pairs[p].coord_max = ord2d(acc[p].coord_max);
     pairs[p].edge_max = ord2d(acc[p].edge_max);
+    if (widx && pairs[p].root >= 0) pairs[p].root = widx[pairs[p].root];
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -477,7 +553,10 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 // destruction). A build that finds it busy uses a private one.
 struct BuildScratch {
     std::mutex mu;
-    DBuf mem, sort_tmp, src;
+    DBuf mem, sort_tmp, src, scan_tmp;
+    PinnedBuf host; // [0, 4) export sequence word; staged uploads; exported results
+    unsigned seq = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 std::mutex g_scratch_mu;
 BuildScratch *g_scratch[64] = {};
@@ -488,7 +567,44 @@ BuildScratch *scratch_for(int dev) {
     return b;
 }
 
+// Released BVH handles keep their device buffers for the next build on the
+// same device (a few per device), so that repeated build/free cycles do not
+// pay for hipMalloc and hipFree each time.
+constexpr int SPARE_BVHS = 2;
+std::mutex g_spare_mu;
+std::vector<Bvh *> g_spare[64];
+
+Bvh *take_bvh(int dev) {
+    std::lock_guard<std::mutex> lk(g_spare_mu);
+    std::vector<Bvh *> &v = g_spare[dev & 63];
+    if (v.empty()) return new Bvh();
+    Bvh *b = v.back();
+    v.pop_back();
+    return b;
+}
+
 } // namespace
+
+void recycle_bvh(Bvh *b) {
+    if (!b) return;
+    // work queued on any stream may still read the BVH: wait for it, as the
+    // hipFree calls of a plain delete would
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_spare_mu);
+    std::vector<Bvh *> &v = g_spare[b->device & 63];
+    if ((int)v.size() < SPARE_BVHS) {
+        b->npairs = 0;
+        b->nB = 0;
+        b->hpairs.clear();
+        v.push_back(b);
+    } else {
+        delete b;
+    }
+}
 
 Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int32_t *const *FB, const int64_t *nBp,
                hipStream_t s) {
@@ -500,9 +616,11 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
     }
     const int64_t n = foff[npairs];
     if (n >= (int64_t(1) << 30)) throw Error{HD_E_INVALID, "soups B too large (>= 2^30 faces)"};
-    Bvh *b = new Bvh();
+    int dev = 0;
+    HD_HIP(hipGetDevice(&dev));
+    Bvh *b = take_bvh(dev);
     try {
-        HD_HIP(hipGetDevice(&b->device));
+        b->device = dev;
         BuildScratch *shared = scratch_for(b->device);
         std::unique_lock<std::mutex> lk(shared->mu, std::try_to_lock);
         std::unique_ptr<BuildScratch> priv;
@@ -510,10 +628,18 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         BuildScratch &sc = lk.owns_lock() ? *shared : *priv;
         b->npairs = npairs;
         b->nB = n;
-        hipEvent_t e0, e1;
-        HD_HIP(hipEventCreate(&e0));
-        HD_HIP(hipEventCreate(&e1));
-        HD_HIP(hipEventRecord(e0, s));
+        if (!sc.e0) {
+            HD_HIP(hipEventCreate(&sc.e0));
+            HD_HIP(hipEventCreate(&sc.e1));
+        }
+        HD_HIP(hipEventRecord(sc.e0, s));
+        // pinned staging: sources and face offsets, pair records; results
+        auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+        const size_t o_src = 256, o_foff = o_src + al(npairs * sizeof(PairSrc)),
+                     o_pairs = o_foff + al((npairs + 1) * sizeof(int64_t)),
+                     o_rst = o_pairs + al(npairs * sizeof(BvhPair)), o_rpairs = o_rst + al(sizeof(BuildState)),
+                     host_bytes = o_rpairs + al(npairs * sizeof(BvhPair));
+        sc.host.reserve(host_bytes);
         const int64_t ni = n > 1 ? n - 1 : 1;
         size_t off = 0;
         auto take = [&](size_t bytes) {
@@ -536,6 +662,8 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         size_t o_cnt = take(ni * sizeof(int32_t));
         size_t o_range = take(ni * sizeof(int2));
         size_t o_upper = take(ni * sizeof(int32_t));
+        size_t o_flag = take(ni * sizeof(int32_t));
+        size_t o_widx = take(ni * sizeof(int32_t));
         size_t o_lbox = take(n * 2 * sizeof(float4));
         size_t o_nbox = take(ni * 2 * sizeof(float4));
         sc.mem.reserve(off);
@@ -555,27 +683,31 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         int32_t *cnt = (int32_t *)(base + o_cnt);
         int2 *range = (int2 *)(base + o_range);
         int32_t *upper = (int32_t *)(base + o_upper);
+        int32_t *flag = (int32_t *)(base + o_flag);
+        int32_t *widx = (int32_t *)(base + o_widx);
         float4 *lbox = (float4 *)(base + o_lbox);
         float4 *nbox = (float4 *)(base + o_nbox);
 
         // per-pair sources and face offsets
-        std::vector<PairSrc> hsrc(npairs);
+        PairSrc *hsrc = sc.host.as<PairSrc>(o_src);
         for (int p = 0; p < npairs; ++p) hsrc[p] = PairSrc{VB[p], FB[p], mB[p]};
-        sc.src.reserve(npairs * sizeof(PairSrc) + (npairs + 1) * sizeof(int64_t) + 256);
+        std::memcpy(sc.host.as<char>(o_foff), foff.data(), (npairs + 1) * sizeof(int64_t));
+        // source records and offsets share one device block with the pinned layout
+        sc.src.reserve(o_pairs - o_src);
         PairSrc *dsrc = sc.src.as<PairSrc>();
-        int64_t *dfoff = (int64_t *)(dsrc + npairs);
-        HD_HIP(hipMemcpyAsync(dsrc, hsrc.data(), npairs * sizeof(PairSrc), hipMemcpyHostToDevice, s));
-        HD_HIP(hipMemcpyAsync(dfoff, foff.data(), (npairs + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        b->hpairs.assign(npairs, BvhPair{});
+        int64_t *dfoff = (int64_t *)(sc.src.as<char>() + (o_foff - o_src));
+        HD_HIP(hipMemcpyAsync(dsrc, sc.host.as<char>(o_src), o_pairs - o_src, hipMemcpyHostToDevice, s));
+        BvhPair *hp = sc.host.as<BvhPair>(o_pairs);
         for (int p = 0; p < npairs; ++p) {
-            b->hpairs[p].tri_begin = foff[p];
-            b->hpairs[p].tri_end = foff[p + 1];
-            b->hpairs[p].nB = (int32_t)nBp[p];
-            b->hpairs[p].root = nBp[p] == 1 ? ~(int32_t)foff[p] : -1;
+            hp[p] = BvhPair{};
+            hp[p].tri_begin = foff[p];
+            hp[p].tri_end = foff[p + 1];
+            hp[p].nB = (int32_t)nBp[p];
+            hp[p].root = nBp[p] == 1 ? ~(int32_t)foff[p] : -1;
         }
         b->pairs.reserve(npairs * sizeof(BvhPair));
         BvhPair *dpairs = b->pairs.as<BvhPair>();
-        HD_HIP(hipMemcpyAsync(dpairs, b->hpairs.data(), npairs * sizeof(BvhPair), hipMemcpyHostToDevice, s));
+        HD_HIP(hipMemcpyAsync(dpairs, hp, npairs * sizeof(BvhPair), hipMemcpyHostToDevice, s));
 
         k_init<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, st);
         k_faces_check<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, acc, st);
@@ -587,7 +719,7 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         while ((1 << pair_bits) < npairs) ++pair_bits;
         radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, s);
 
-        b->nodes.reserve(ni * sizeof(NodeRec));
+        b->nodes.reserve(ni * sizeof(WideNode));
         b->frames32.reserve(n * 4 * sizeof(float4));
         b->frames64.reserve(n * 8 * sizeof(double2));
         b->ids.reserve(n * sizeof(int4));
@@ -602,25 +734,36 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
             k_refit_tiles<<<grid_for(n, TILE), TILE, 0, s>>>(n, cl, cr, pn, pl, range, lbox, nbox, cnt);
             k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(cnt, ni, 0);
             k_refit_upper<<<1, 1024, 0, s>>>(upper, st, cl, cr, pn, range, lbox, nbox, cnt);
-            k_node_records<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, cl, cr, nbox, lbox, b->nodes.as<NodeRec>());
             k_pair_roots<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, range, dpairs, npairs, keys);
+            k_wide_flags<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, pn, range, dpairs, npairs, keys, flag);
+            scan_exclusive_i32(flag, widx, ni, &st->n_wide, sc.scan_tmp, s);
+            k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, flag, widx, cl, cr, nbox, lbox,
+                                                           b->nodes.as<WideNode>());
         }
-        k_pair_finish<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs);
+        k_pair_finish<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs, n > 1 ? widx : nullptr);
         HD_LAUNCH_CHECK();
-        BuildState hs;
-        HD_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-        HD_HIP(hipMemcpyAsync(b->hpairs.data(), dpairs, npairs * sizeof(BvhPair), hipMemcpyDeviceToHost, s));
-        HD_HIP(hipEventRecord(e1, s));
-        HD_HIP(hipStreamSynchronize(s));
-        HD_HIP(hipEventElapsedTime(&b->ms_build, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        HD_HIP(hipEventRecord(sc.e1, s));
+        Export ex{};
+        ex.n = 2;
+        ex.src[0] = st;
+        ex.dst[0] = sc.host.dev_as<char>(o_rst);
+        ex.bytes[0] = sizeof(BuildState);
+        ex.src[1] = dpairs;
+        ex.dst[1] = sc.host.dev_as<char>(o_rpairs);
+        ex.bytes[1] = npairs * sizeof(BvhPair);
+        const unsigned seq = ++sc.seq;
+        export_to_host(ex, sc.host.dev_as<unsigned>(0), seq, s);
+        wait_host_seq(sc.host.as<unsigned>(0), seq, s);
+        const BuildState hs = *sc.host.as<BuildState>(o_rst);
+        b->hpairs.assign(sc.host.as<BvhPair>(o_rpairs), sc.host.as<BvhPair>(o_rpairs) + npairs);
+        HD_HIP(hipEventSynchronize(sc.e1));
+        HD_HIP(hipEventElapsedTime(&b->ms_build, sc.e0, sc.e1));
         if (hs.bad) throw Error{HD_E_INVALID, "soup B has an out-of-range index or a non-finite coordinate"};
         for (int p = 0; p < npairs; ++p)
             if (b->hpairs[p].nB > 1 && b->hpairs[p].root < 0) throw Error{HD_E_INTERNAL, "pair subtree root not found"};
         return b;
     } catch (...) {
-        delete b;
+        recycle_bvh(b);
         throw;
     }
 }

@@ -40,13 +40,17 @@ constexpr int DEEP_SLOTS = 4096; // concurrent deep traversals
 constexpr int BLK = 256;
 constexpr int NW = BLK / 64;
 
+// Device control block. The append counters, the cascade statistics and the
+// query statistics sit on separate 128-byte lines: atomics on one line do not
+// stall the others.
 struct Ctl {
-    unsigned long long queries, evals, boxes, bounded, q_leaves, q_boxes, rechecked;
-    unsigned long long discards[5];
-    unsigned long long act_next, park_next; // append counters of the current round
-    unsigned long long b_next, c_next;      // records waiting for cascade stage B / C
+    alignas(128) unsigned long long act_next, park_next; // append counters of the current round
+    unsigned long long b_next, c_next;                   // records waiting for cascade stage B / C
     int bad;        // 1 invalid input, 2 traversal deeper than the fallback stack, 3 depth exhausted
     int n_overflow; // queries whose LDS stack overflowed this round
+    alignas(128) unsigned long long evals, bounded, rechecked;
+    unsigned long long discards[5];
+    alignas(128) unsigned long long queries, boxes, q_leaves;
 };
 
 struct PairSrcA {
@@ -133,6 +137,25 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 }
 
 __global__ void k_ctl_init(Ctl *c) { memset(c, 0, sizeof(Ctl)); }
+
+// What the host needs between rounds, written by the device into pinned host
+// memory; `seq` last, after a system-scope fence, so that a host that sees
+// the new seq sees the fields too.
+struct Mailbox {
+    long long act, park, nref;
+    int bad;
+    unsigned seq;
+};
+
+__global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *mb, unsigned seq) {
+    if (threadIdx.x != 0) return;
+    mb->act = (long long)ctl->act_next;
+    mb->park = (long long)ctl->park_next;
+    mb->nref = nref ? *nref : 0;
+    mb->bad = ctl->bad;
+    __threadfence_system();
+    __hip_atomic_store(&mb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 __global__ void k_round_setup(Ctl *c, unsigned long long act_base, unsigned long long park_base) {
     c->n_overflow = 0;
@@ -307,7 +330,7 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
 }
 
 struct QueryCfg {
-    const NodeRec *nodes;
+    const WideNode *nodes;
     const int4 *ids;
     int raise_L; // fold d - mu into the lower bound and the argmax key
 };
@@ -353,7 +376,7 @@ HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResul
 }
 
 template <class T, int SD>
-__global__ __launch_bounds__(QBLOCK) __attribute__((amdgpu_waves_per_eu(5))) void k_query(QueryIn<T> in, int64_t n, QueryCfg cfg, BView<T> bv,
+__global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, int64_t n, QueryCfg cfg, BView<T> bv,
                                                   QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
                                                   Ctl *ctl, int32_t *ovf_list) {
     __shared__ int s_node[SD * QBLOCK];
@@ -366,8 +389,7 @@ __global__ __launch_bounds__(QBLOCK) __attribute__((amdgpu_waves_per_eu(5))) voi
         pair = qp.pair;
         V3<T> p = cvt<T>(qp.p);
         QueryResult<T> r = empty_result<T>();
-        if (qp.seed[0] >= 0) visit_leaf(r, bv, cfg.ids, p, qp.seed[0]);
-        if (qp.seed[1] >= 0 && qp.seed[1] != qp.seed[0]) visit_leaf(r, bv, cfg.ids, p, qp.seed[1]);
+        seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
         LdsStack<SD, QBLOCK> stk{s_node, s_dist, 0};
         r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
         nb = r.nbox;
@@ -381,17 +403,13 @@ __global__ __launch_bounds__(QBLOCK) __attribute__((amdgpu_waves_per_eu(5))) voi
         }
     }
     pair_max2(pv, pair, lord, key);
-    wave_add(&ctl->boxes, nb);
-    wave_add(&ctl->evals, nl);
-    wave_add(&ctl->q_leaves, nl);
-    wave_add(&ctl->q_boxes, nb);
-    wave_add(&ctl->queries, nq);
+    block_add<3, QBLOCK>({nb, nl, nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
 }
 
 // queries whose LDS stack overflowed, redone with a deep stack in global
 // memory (grid-stride over the overflow list; exits at once when it is empty)
 template <class T>
-__global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<T> out,
+__global__ __launch_bounds__(64) void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<T> out,
                              const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, const int32_t *ovf_list,
                              int2 *stack_mem) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -402,8 +420,7 @@ __global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<
         QPoint qp = query_point(in, i);
         V3<T> p = cvt<T>(qp.p);
         QueryResult<T> r = empty_result<T>();
-        if (qp.seed[0] >= 0) visit_leaf(r, bv, cfg.ids, p, qp.seed[0]);
-        if (qp.seed[1] >= 0 && qp.seed[1] != qp.seed[0]) visit_leaf(r, bv, cfg.ids, p, qp.seed[1]);
+        seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
         GlobalStack stk{stack_mem + tid, DEEP_SLOTS, DEEP_STACK, 0};
         r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
         nb += r.nbox;
@@ -418,14 +435,14 @@ __global__ void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<
         if (key) atomicMax(&pv[qp.pair].round_key, key);
     }
     wave_add(&ctl->boxes, nb);
-    wave_add(&ctl->evals, nl);
+    wave_add(&ctl->q_leaves, nl);
 }
 
 // after a query round: the query holding its pair's best key records its
 // exact position (keys are unique up to a tag collision of one point)
 template <class T>
 __global__ void k_argmax_finalize(QueryIn<T> in, int64_t n, const unsigned long long *__restrict__ keys,
-                                  PairVar *pv) {
+                                  const int *__restrict__ tri, PairVar *pv) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
@@ -437,6 +454,7 @@ __global__ void k_argmax_finalize(QueryIn<T> in, int64_t n, const unsigned long 
         P.argmax_pos[0] = qp.p.x;
         P.argmax_pos[1] = qp.p.y;
         P.argmax_pos[2] = qp.p.z;
+        P.argmax_tri = tri[o];
         P.argmax_dirty = 1;
     }
 }
@@ -444,7 +462,7 @@ __global__ void k_argmax_finalize(QueryIn<T> in, int64_t n, const unsigned long 
 // FP64 distance of each pair's best vertex when it changed: the lower bound
 // then carries the FP64 margin instead of the FP32 one, which the recheck
 // band needs to park triangles within eps of it
-__global__ void k_L64(const NodeRec *nodes, BView<double> bv64, const int4 *ids, const PairConst *pc, PairVar *pv,
+__global__ __launch_bounds__(64) void k_L64(const WideNode *nodes, BView<double> bv64, const int4 *ids, const PairConst *pc, PairVar *pv,
                       int npairs, int2 *stack_mem) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
@@ -456,7 +474,11 @@ __global__ void k_L64(const NodeRec *nodes, BView<double> bv64, const int4 *ids,
     P.argmax_dirty = 0;
     V3<double> x = {P.argmax_pos[0], P.argmax_pos[1], P.argmax_pos[2]};
     GlobalStack stk{stack_mem + p, npairs, DEEP_STACK, 0};
-    QueryResult<double> r = traverse<double>(nodes, bv64, ids, x, C.root, stk, empty_result<double>());
+    // the FP32 query's closest triangle bounds the FP64 distance from above,
+    // so the traversal starts with a tight pruning radius
+    QueryResult<double> r = empty_result<double>();
+    visit_leaf(r, bv64, ids, x, P.argmax_tri);
+    r = traverse<double>(nodes, bv64, ids, x, C.root, stk, r);
     if (r.overflow || r.s < 0) return;
     double d = sqrt(r.d2);
     double dlo = d - (C.m64.mu_d * d + C.m64.mu_0);
@@ -653,13 +675,15 @@ __device__ int64_t append_slot(int list, Ctl *ctl) {
     return slot;
 }
 
-HD_D void tally(Ctl *ctl, int list, int decider, int evals, int rechecked, bool valid, bool bounded) {
-    unsigned long long dis[5] = {0, 0, 0, 0, 0};
-    if (valid && list == TO_DISCARD) dis[decider] = 1;
-    for (int k = 0; k < 5; ++k) wave_add(&ctl->discards[k], dis[k]);
-    wave_add(&ctl->evals, valid ? (unsigned long long)evals : 0ull);
-    wave_add(&ctl->rechecked, valid ? (unsigned long long)rechecked : 0ull);
-    wave_add(&ctl->bounded, valid && bounded ? 1ull : 0ull);
+// block-aggregated statistics of a cascade kernel (every thread must call it)
+__device__ void tally(Ctl *ctl, int list, int decider, int evals, int rechecked, bool valid, bool bounded) {
+    const bool dis = valid && list == TO_DISCARD;
+    block_add<8, BLK>({dis && decider == 0 ? 1ull : 0ull, dis && decider == 1 ? 1ull : 0ull,
+                       dis && decider == 2 ? 1ull : 0ull, dis && decider == 3 ? 1ull : 0ull,
+                       dis && decider == 4 ? 1ull : 0ull, valid ? (unsigned long long)evals : 0ull,
+                       valid ? (unsigned long long)rechecked : 0ull, valid && bounded ? 1ull : 0ull},
+                      {&ctl->discards[0], &ctl->discards[1], &ctl->discards[2], &ctl->discards[3],
+                       &ctl->discards[4], &ctl->evals, &ctl->rechecked, &ctl->bounded});
 }
 
 template <class T> struct Dest {
@@ -883,20 +907,24 @@ template <class T>
 __global__ __launch_bounds__(BLK) void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> bv64, IdView iv, CascadeCtx c,
                           const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
     unsigned long long ev = 0;
-    if (i < n) {
-        int pair = fr.pair()[i];
+    int pair = 0;
+    double u[2] = {0, 0};
+    if (valid) {
+        pair = fr.pair()[i];
         int ba[3] = {fr.ba(0)[i], fr.ba(1)[i], fr.ba(2)[i]};
         int bb[3] = {fr.bb(0)[i], fr.bb(1)[i], fr.bb(2)[i]};
         int I[3] = {fr.I(0)[i], fr.I(1)[i], fr.I(2)[i]};
         int evals = 0;
         double u64 = rebound64(a, pair, fr.face()[i], fr.lvl()[i], ba, bb, I, bv64, iv, c, pc[pair].m64, &evals);
         double u32 = (double)fr.ub()[i];
-        atomicMax(&pv[pair].Uord, d2ord(hmin(u64, u32)));
-        atomicMax(&pv[pair].Urounds, d2ord(u32));
+        u[0] = hmin(u64, u32);
+        u[1] = u32;
         ev = evals;
     }
-    wave_add(&ctl->evals, ev);
+    block_pair_minmax<2, 3u, BLK>(pair, valid, u, [&](int p, int k) { return k == 0 ? &pv[p].Uord : &pv[p].Urounds; });
+    block_add<1, BLK>({ev}, {&ctl->evals});
 }
 
 // ---------------------------------------------------------------------------
@@ -1017,7 +1045,10 @@ template <class T> struct TypedWs {
 };
 struct Workspace {
     std::mutex mu;
-    DBuf ctl, pc, pv, src, offs, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
+    PinnedBuf host; // mailbox, staged uploads, exported results
+    unsigned mb_seq = 0;
+    std::vector<hipEvent_t> evpool; // profiling events (kept until the process ends)
+    DBuf ctl, pc, pv, params, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
     TypedWs<float> w32;
     TypedWs<double> w64;
     template <class T> TypedWs<T> &typed();
@@ -1054,14 +1085,23 @@ int parse_order(int32_t order, int out[4]) {
     return n;
 }
 
+// Kernel timing with HIP events on the engine's stream (begin/end pairs).
+// Events come from a pool kept with the workspace, so that a profiled call
+// does not create and destroy events.
 struct Profiler {
     hipStream_t s;
     bool on = false;
-    std::vector<hipEvent_t> q, c; // begin/end pairs
+    std::vector<hipEvent_t> *pool = nullptr;
+    size_t used = 0;
+    std::vector<hipEvent_t> q, c;
     void mark(std::vector<hipEvent_t> &v) {
         if (!on) return;
-        hipEvent_t e;
-        HD_HIP(hipEventCreate(&e));
+        if (used == pool->size()) {
+            hipEvent_t e;
+            HD_HIP(hipEventCreate(&e));
+            pool->push_back(e);
+        }
+        hipEvent_t e = (*pool)[used++];
         HD_HIP(hipEventRecord(e, s));
         v.push_back(e);
     }
@@ -1072,10 +1112,6 @@ struct Profiler {
             if (hipEventElapsedTime(&t, v[i], v[i + 1]) == hipSuccess) ms += t;
         }
         return ms;
-    }
-    ~Profiler() {
-        for (auto e : q) (void)hipEventDestroy(e);
-        for (auto e : c) (void)hipEventDestroy(e);
     }
 };
 
@@ -1118,25 +1154,57 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     Profiler prof;
     prof.s = s;
     prof.on = opt.profile != 0;
+    prof.pool = &ws.evpool;
 
     // ---- small tables -----------------------------------------------------
+    // Pinned host block: [0, 64) mailbox, [64, 68) export sequence word,
+    // then the packed upload (pair sources, face and vertex offsets, eps) and
+    // the result area (control block, pair tables). The upload goes to the
+    // device in one asynchronous copy; results come back through one export.
     ws.ctl.reserve(sizeof(Ctl));
     Ctl *ctl = ws.ctl.as<Ctl>();
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const int neps = in.eps_per_pair ? np : 1;
+    const size_t o_src = 0, o_foff = o_src + al(np * sizeof(PairSrcA)), o_voff = o_foff + al((np + 1) * 8),
+                 o_eps = o_voff + al((np + 1) * 8), up_bytes = o_eps + al(neps * 8);
+    const size_t o_up = 256, o_res = o_up + up_bytes;
+    const size_t o_rctl = 0, o_rpv = al(sizeof(Ctl)), o_rpc = o_rpv + al(np * sizeof(PairVar)),
+                 res_bytes = o_rpc + al(np * sizeof(PairConst));
+    ws.host.reserve(o_res + res_bytes);
+    Mailbox *mb = ws.host.as<Mailbox>(), *mb_dev = ws.host.dev_as<Mailbox>();
+    // Enqueue a report and wait for it by polling the pinned mailbox: far
+    // lower latency than a stream synchronisation plus a staged copy.
+    auto report = [&](const int32_t *nref) -> Mailbox {
+        const unsigned seq = ++ws.mb_seq;
+        k_report<<<1, 64, 0, s>>>(ctl, nref, mb_dev, seq);
+        HD_LAUNCH_CHECK();
+        wait_host_seq(&mb->seq, seq, s);
+        Mailbox m;
+        m.act = mb->act;
+        m.park = mb->park;
+        m.nref = mb->nref;
+        m.bad = mb->bad;
+        m.seq = seq;
+        return m;
+    };
     ws.pc.reserve(np * sizeof(PairConst));
     ws.pv.reserve(np * sizeof(PairVar));
     PairConst *pc = ws.pc.as<PairConst>();
     PairVar *pv = ws.pv.as<PairVar>();
-    std::vector<PairSrcA> hsrc(np);
-    for (int p = 0; p < np; ++p) hsrc[p] = PairSrcA{in.VA[p], in.FA[p], in.mA[p]};
-    ws.src.reserve(np * sizeof(PairSrcA));
-    ws.offs.reserve((2 * (np + 1) + np) * sizeof(int64_t));
-    int64_t *dfoff = ws.offs.as<int64_t>();
-    int64_t *dvoff = dfoff + (np + 1);
-    double *deps = (double *)(dvoff + (np + 1));
-    HD_HIP(hipMemcpyAsync(ws.src.p, hsrc.data(), np * sizeof(PairSrcA), hipMemcpyHostToDevice, s));
-    HD_HIP(hipMemcpyAsync(dfoff, foff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    HD_HIP(hipMemcpyAsync(dvoff, voff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    HD_HIP(hipMemcpyAsync(deps, in.eps, (in.eps_per_pair ? np : 1) * sizeof(double), hipMemcpyHostToDevice, s));
+    {
+        char *up = ws.host.as<char>(o_up);
+        PairSrcA *hs = (PairSrcA *)(up + o_src);
+        for (int p = 0; p < np; ++p) hs[p] = PairSrcA{in.VA[p], in.FA[p], in.mA[p]};
+        std::memcpy(up + o_foff, foff.data(), (np + 1) * 8);
+        std::memcpy(up + o_voff, voff.data(), (np + 1) * 8);
+        std::memcpy(up + o_eps, in.eps, neps * 8);
+    }
+    ws.params.reserve(up_bytes);
+    HD_HIP(hipMemcpyAsync(ws.params.p, ws.host.as<char>(o_up), up_bytes, hipMemcpyHostToDevice, s));
+    const PairSrcA *dsrc = (const PairSrcA *)(ws.params.as<char>() + o_src);
+    int64_t *dfoff = (int64_t *)(ws.params.as<char>() + o_foff);
+    int64_t *dvoff = (int64_t *)(ws.params.as<char>() + o_voff);
+    double *deps = (double *)(ws.params.as<char>() + o_eps);
 
     // ---- ingest A ---------------------------------------------------------
     ws.Vcat.reserve(mA * 3 * sizeof(double));
@@ -1150,19 +1218,13 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     k_ctl_init<<<1, 1, 0, s>>>(ctl);
     k_pairs_init<<<grid_for(np, 64), 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), np);
     k_fill_i32<<<grid_for(mA, BLK), BLK, 0, s>>>(ref, mA, 0);
-    k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(ws.src.as<PairSrcA>(), dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
+    k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
                                               ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pv, ctl);
     k_pairs_post<<<grid_for(np, 64), 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair);
     scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
     HD_LAUNCH_CHECK();
-    struct {
-        Ctl c;
-        int32_t nref;
-    } h0;
-    HD_HIP(hipMemcpyAsync(&h0.c, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HD_HIP(hipMemcpyAsync(&h0.nref, d_total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HD_HIP(hipStreamSynchronize(s));
-    if (h0.c.bad) throw Error{HD_E_INVALID, "soup A has an out-of-range index or a non-finite coordinate"};
+    const Mailbox h0 = report(d_total);
+    if (h0.bad) throw Error{HD_E_INVALID, "soup A has an out-of-range index or a non-finite coordinate"};
     const int64_t nref = h0.nref;
     ws.vids.reserve(nref * sizeof(int32_t));
     k_ref_scatter<<<grid_for(mA, BLK), BLK, 0, s>>>(ref, refpos, mA, ws.vids.as<int32_t>());
@@ -1174,7 +1236,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const BView<double> bv64{B->frames64.as<double2>()};
     const IdView iv{B->ids.as<int4>()};
     const AView av{ws.Vcat.as<double>(), ws.Fcat.as<int32_t>(), pc};
-    const QueryCfg qcfg{B->nodes.as<NodeRec>(), B->ids.as<int4>(), 1};
+    const QueryCfg qcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 1};
     ws.gstack.reserve((size_t)np * DEEP_STACK * sizeof(int2));
     ws.deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
     const bool small_stack = opt.stack_depth > 0 && opt.stack_depth < QSTACK;
@@ -1193,8 +1255,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         prof.mark(prof.q);
         k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                         ws.deep.as<int2>());
-        k_argmax_finalize<T><<<grid_for(n, BLK), BLK, 0, s>>>(qi, n, out.key, pv);
-        k_L64<<<grid_for(np, 64), 64, 0, s>>>(B->nodes.as<NodeRec>(), bv64, iv.ids, pc, pv, np,
+        k_argmax_finalize<T><<<grid_for(n, BLK), BLK, 0, s>>>(qi, n, out.key, out.I, pv);
+        k_L64<<<grid_for(np, 64), 64, 0, s>>>(B->nodes.as<WideNode>(), bv64, iv.ids, pc, pv, np,
                                                ws.gstack.as<int2>());
         HD_LAUNCH_CHECK();
     };
@@ -1247,10 +1309,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     HD_LAUNCH_CHECK();
     later_stages(nA, tw.act.v);
     prof.mark(prof.c);
-    Ctl hc;
-    HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HD_HIP(hipStreamSynchronize(s));
-    int64_t nAct = (int64_t)hc.act_next, nPark = (int64_t)hc.park_next;
+    Mailbox hm = report(nullptr);
+    int64_t nAct = hm.act, nPark = hm.park;
 
     const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
     double processed = (double)nA;
@@ -1258,7 +1318,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     int rounds = 0;
     S.max_frontier = nAct + nPark;
     hd_status status = HD_OK;
-    if (hc.bad == 2) status = HD_E_INTERNAL;
+    if (hm.bad == 2) status = HD_E_INTERNAL;
     while (status == HD_OK && nAct > 0) {
         if (opt.max_rounds > 0 && rounds >= opt.max_rounds) break;
         // how many to split this round, growing the lists when allowed
@@ -1322,22 +1382,20 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
         later_stages(4 * K, tw.act2.v);
         prof.mark(prof.c);
-        HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HD_HIP(hipStreamSynchronize(s));
+        hm = report(nullptr);
         swap_fb(tw.act, tw.act2);
-        nAct = (int64_t)hc.act_next;
-        nPark = (int64_t)hc.park_next;
+        nAct = hm.act;
+        nPark = hm.park;
         subdivided += K;
         processed += 4.0 * (double)K;
         ++rounds;
         S.max_frontier = std::max<int64_t>(S.max_frontier, nAct + nPark);
-        if (hc.bad == 3) status = HD_E_CAPACITY; // depth exhausted: tolerance below what the arithmetic resolves
-        else if (hc.bad) status = HD_E_INTERNAL;
+        if (hm.bad == 3) status = HD_E_CAPACITY; // depth exhausted: tolerance below what the arithmetic resolves
+        else if (hm.bad) status = HD_E_INTERNAL;
     }
 
     // ---- final FP64 step: U over every live triangle --------------------------
-    std::vector<PairConst> hc_(np);
-    std::vector<PairVar> hp(np);
+
     if (status == HD_OK) {
         prof.mark(prof.c);
         if (nPark > 0)
@@ -1347,10 +1405,25 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
         prof.mark(prof.c);
     }
-    HD_HIP(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HD_HIP(hipMemcpyAsync(hp.data(), pv, np * sizeof(PairVar), hipMemcpyDeviceToHost, s));
-    HD_HIP(hipMemcpyAsync(hc_.data(), pc, np * sizeof(PairConst), hipMemcpyDeviceToHost, s));
-    HD_HIP(hipStreamSynchronize(s));
+    {
+        Export ex{};
+        ex.n = 3;
+        ex.src[0] = ctl;
+        ex.dst[0] = ws.host.dev_as<char>(o_res + o_rctl);
+        ex.bytes[0] = sizeof(Ctl);
+        ex.src[1] = pv;
+        ex.dst[1] = ws.host.dev_as<char>(o_res + o_rpv);
+        ex.bytes[1] = np * sizeof(PairVar);
+        ex.src[2] = pc;
+        ex.dst[2] = ws.host.dev_as<char>(o_res + o_rpc);
+        ex.bytes[2] = np * sizeof(PairConst);
+        const unsigned seq = ++ws.mb_seq;
+        export_to_host(ex, ws.host.dev_as<unsigned>(64), seq, s);
+        wait_host_seq(ws.host.as<unsigned>(64), seq, s);
+    }
+    const Ctl &hc = *ws.host.as<Ctl>(o_res + o_rctl);
+    const PairVar *hp = ws.host.as<PairVar>(o_res + o_rpv);
+    const PairConst *hc_ = ws.host.as<PairConst>(o_res + o_rpc);
     if (status == HD_OK && hc.bad == 2) status = HD_E_INTERNAL;
     if (status == HD_OK) {
         for (int p = 0; p < np; ++p) {
@@ -1367,13 +1440,13 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     S.nodes_bounded = (int64_t)hc.bounded;
     S.subdivided = subdivided;
     S.queries = (int64_t)hc.queries;
-    S.pt_tri_evals = (int64_t)hc.evals;
+    S.pt_tri_evals = (int64_t)(hc.evals + hc.q_leaves);
     S.box_tests = (int64_t)hc.boxes;
     for (int k = 0; k < 5; ++k) S.discards[k] = (int64_t)hc.discards[k];
     S.rechecked64 = (int64_t)hc.rechecked;
     S.parked_final = nPark;
     S.query_leaf_evals = (int64_t)hc.q_leaves;
-    S.query_box_tests = (int64_t)hc.q_boxes;
+    S.query_box_tests = (int64_t)hc.boxes;
     S.dA = hc_[0].dA;
     S.eps_abs = hc_[0].eps_abs;
     S.mu_coef_d = margins_of<T>(hc_[0]).mu_d;
@@ -1491,7 +1564,7 @@ hd_status hd_build_bvh_batched(int32_t npairs, const double *const *VB, const in
     });
 }
 
-void hd_free_bvh(hd_bvh b) { delete reinterpret_cast<Bvh *>(b); }
+void hd_free_bvh(hd_bvh b) { recycle_bvh(reinterpret_cast<Bvh *>(b)); }
 
 hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, hd_bvh Bh, double eps,
                    const hd_options *opt, hd_stream_t stream, double LU_out[2], hd_stats *stats) {
@@ -1541,7 +1614,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
         PairVar *pv = pvb.as<PairVar>();
         k_ctl_init<<<1, 1, 0, s>>>(ctl);
         k_pairs_init<<<1, 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), 1);
-        const QueryCfg cfg{B->nodes.as<NodeRec>(), B->ids.as<int4>(), 0};
+        const QueryCfg cfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
         auto go = [&](auto tag) {
             using T = decltype(tag);
             QBuf<T> qb;

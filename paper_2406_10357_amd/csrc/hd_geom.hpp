@@ -21,9 +21,11 @@ namespace hd {
 template <class T> struct Frame {
     V3<T> A, ex, ey;
     T Lb, cx, cy, inv2bc, inv2ca, R;
+    int orig; // original face index within its pair (ties between equal distances)
 };
 
-// device layout: float -> 4 x float4 (64 B); double -> 8 x double2 (128 B)
+// device layout: float -> 4 x float4 (64 B); double -> 8 x double2 (128 B);
+// the last word holds the original face index (int bits / exact double)
 HD_D Frame<float> load_frame(const float4 *__restrict__ F, int64_t i) {
     float4 a = F[4 * i], b = F[4 * i + 1], c = F[4 * i + 2], d = F[4 * i + 3];
     Frame<float> f;
@@ -36,6 +38,7 @@ HD_D Frame<float> load_frame(const float4 *__restrict__ F, int64_t i) {
     f.inv2bc = d.x;
     f.inv2ca = d.y;
     f.R = d.z;
+    f.orig = __builtin_bit_cast(int, d.w);
     return f;
 }
 HD_D Frame<double> load_frame(const double2 *__restrict__ F, int64_t i) {
@@ -51,6 +54,7 @@ HD_D Frame<double> load_frame(const double2 *__restrict__ F, int64_t i) {
     f.inv2bc = h.x;
     f.inv2ca = h.y;
     f.R = k.x;
+    f.orig = (int)k.y;
     return f;
 }
 

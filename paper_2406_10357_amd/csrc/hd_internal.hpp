@@ -6,6 +6,7 @@
 
 #include <stdint.h>
 
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -80,7 +81,7 @@ struct Bvh {
     int device = 0;
     int npairs = 0;
     int64_t nB = 0;
-    DBuf nodes;    // internal nodes x 64 B: child boxes + child refs
+    DBuf nodes;    // four-wide nodes x 128 B (at most nB - 1 of them)
     DBuf frames32; // nB x 64 B
     DBuf frames64; // nB x 128 B
     DBuf ids;      // nB x int4: corner vertex ids (frame order), original face index in its pair
@@ -88,6 +89,48 @@ struct Bvh {
     std::vector<BvhPair> hpairs;
     float ms_build = 0;
 };
+
+// Owning pinned host buffer (hipHostMalloc, mapped and coherent), used to
+// stage small uploads and to receive results written by the device. Grows
+// only; contents are not preserved on growth.
+struct PinnedBuf {
+    void *p = nullptr;
+    void *dev = nullptr; // the same memory as seen by the device
+    size_t bytes = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void reserve(size_t n) {
+        if (n <= bytes) return;
+        if (p) (void)hipHostFree(p);
+        p = dev = nullptr;
+        bytes = 0;
+        size_t b = n < 4096 ? 4096 : n;
+        HD_HIP(hipHostMalloc(&p, b, hipHostMallocMapped | hipHostMallocCoherent));
+        HD_HIP(hipHostGetDevicePointer(&dev, p, 0));
+        bytes = b;
+        std::memset(p, 0, b);
+    }
+    template <class X> X *as(size_t off = 0) const { return (X *)((char *)p + off); }
+    template <class X> X *dev_as(size_t off = 0) const { return (X *)((char *)dev + off); }
+};
+
+// Device -> pinned host copy of up to four regions (sizes in bytes, multiples
+// of 4), followed by a store of `seq` to *seq_dev that the host can poll: one
+// kernel instead of staged copies and a stream synchronisation.
+struct Export {
+    const void *src[4];
+    void *dst[4]; // device view of pinned memory
+    int64_t bytes[4];
+    int n;
+};
+void export_to_host(const Export &e, unsigned *seq_dev, unsigned seq, hipStream_t s);
+// Wait until *seq_host == seq. Polls the pinned word; queries the stream now
+// and then so that a failed launch or a device error ends the wait.
+void wait_host_seq(const unsigned *seq_host, unsigned seq, hipStream_t s);
 
 // --- primitives (hd_prims.hip) -------------------------------------------
 // Exclusive scan of n int32 values; total in *d_total (device, may be null).
@@ -104,13 +147,20 @@ void radix_sort_u64(unsigned long long *keys, int32_t *vals, unsigned long long 
 // VB[p], FB[p]: device pointers of pair p (host arrays of npairs pointers).
 Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int32_t *const *FB,
                const int64_t *nB, hipStream_t s);
+// Release a BVH (waits for the device; its buffers may serve a later build).
+void recycle_bvh(Bvh *b);
 
-// Node record: a = (lo_L.xyz, child_L), b = (hi_L.xyz, child_R),
-// c = (lo_R.xyz, 0), d = (hi_R.xyz, 0). A child >= 0 is an internal node,
-// a child < 0 the leaf ~child (sorted triangle index).
-struct NodeRec {
-    float4 a, b, c, d;
+// Four-wide BVH node, one 128-byte line: the boxes of up to four children
+// (structure of arrays: component c of child k at lo*/hi*[k]) and their
+// references. A reference >= 0 is a wide node, WIDE_EMPTY an unused slot, any
+// other negative value the leaf ~ref (sorted triangle index).
+constexpr int32_t WIDE_EMPTY = INT32_MIN;
+struct alignas(128) WideNode {
+    float4 lox, loy, loz, hix, hiy, hiz;
+    int4 child;
+    int4 meta; // (number of used slots, 0, 0, 0)
 };
+static_assert(sizeof(WideNode) == 128, "one cache line per node");
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 

@@ -42,7 +42,7 @@ struct alignas(128) PairVar {
     unsigned long long coord_max; // ordered FP64 largest |coordinate| of A after centring
     double argmax_pos[3];         // centred FP64 position of the best vertex
     int32_t argmax_dirty;
-    int32_t pad;
+    int32_t argmax_tri;           // closest triangle (sorted index) found for it by the query
     double L64;
 };
 
@@ -206,70 +206,154 @@ template <class T> HD_D QueryResult<T> empty_result() {
     return r;
 }
 
-// fold leaf s into the running result (exact ties: smallest original index)
-template <class T>
-HD_D void visit_leaf(QueryResult<T> &r, const BView<T> &bv, const int4 *__restrict__ ids, const V3<T> &p, int s) {
-    Frame<T> f = load_frame(bv.frames, s);
+// fold leaf s (its frame f) into the running result (exact ties: smallest
+// original index)
+template <class T> HD_D void fold_leaf(QueryResult<T> &r, const Frame<T> &f, const V3<T> &p, int s) {
     T d2 = frame_dist2<T, false>(f, p, nullptr);
     ++r.nleaf;
-    if (d2 <= r.d2) {
-        int o = ids[s].w;
-        if (d2 < r.d2 || o < r.orig) {
-            r.d2 = d2;
-            r.s = s;
-            r.orig = o;
-        }
+    if (d2 < r.d2 || (d2 == r.d2 && f.orig < r.orig)) {
+        r.d2 = d2;
+        r.s = s;
+        r.orig = f.orig;
     }
+}
+
+template <class T>
+HD_D void visit_leaf(QueryResult<T> &r, const BView<T> &bv, const int4 *__restrict__ ids, const V3<T> &p, int s) {
+    fold_leaf(r, load_frame(bv.frames, s), p, s);
+}
+
+// seed a result with up to two candidate triangles (s < 0: none), both frames
+// loaded before either is evaluated
+template <class T>
+HD_D void seed_two(QueryResult<T> &r, const BView<T> &bv, const V3<T> &p, int s0, int s1) {
+    if (s1 == s0) s1 = -1;
+    Frame<T> F0, F1;
+    if (s0 >= 0) F0 = load_frame(bv.frames, s0);
+    if (s1 >= 0) F1 = load_frame(bv.frames, s1);
+    if (s0 >= 0) fold_leaf(r, F0, p, s0);
+    if (s1 >= 0) fold_leaf(r, F1, p, s1);
 }
 
 // Closest-first traversal from `root`, starting from the result `r` (empty,
 // or seeded with candidate triangles). A child box is entered only when its
 // distance is within (1 + 16u) of the best squared distance so far, which
-// keeps pruning conservative under the rounding of the box test.
+// keeps pruning conservative under the rounding of the box test. Per wide
+// node: leaf children are evaluated at once; the internal children still in
+// range are sorted by box distance, the nearest is entered and the others are
+// pushed farthest first.
+template <class T>
+HD_D void cswap(T &ea, int &fa, T &eb, int &fb) {
+    if (eb < ea) {
+        T te = ea;
+        ea = eb;
+        eb = te;
+        int tf = fa;
+        fa = fb;
+        fb = tf;
+    }
+}
+
 template <class T, class Stack>
-HD_D QueryResult<T> traverse(const NodeRec *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
+HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
                              const V3<T> &p, int root, Stack &st, QueryResult<T> r) {
     const T slack = T(1) + T(16 * Prec<T>::u);
+    const T inf = T(__builtin_inf());
     if (root < 0) {
         visit_leaf(r, bv, ids, p, ~root);
         return r;
+    }
+    // Without a bound every child is in range and every sibling would be
+    // pushed; descend greedily (nearest box first, nothing pushed) to one
+    // leaf, and start the real traversal with its distance as the bound.
+    if (!(r.d2 < T(__builtin_inf()))) {
+        int x = root;
+        for (int guard = 0; guard < 64 && x >= 0; ++guard) {
+            const WideNode *w = nodes + x;
+            const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
+            const int4 ch = w->child;
+            T best = T(__builtin_inf());
+            int pick = WIDE_EMPTY;
+            auto consider = [&](float a, float b, float c, float d, float e, float f, int ref) {
+                if (ref == WIDE_EMPTY) return;
+                T dd = box_d2<T>(make_float4(a, b, c, 0.f), make_float4(d, e, f, 0.f), p);
+                if (pick == WIDE_EMPTY || dd < best) {
+                    best = dd;
+                    pick = ref;
+                }
+            };
+            consider(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ch.x);
+            consider(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ch.y);
+            consider(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ch.z);
+            consider(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ch.w);
+            r.nbox += 4;
+            if (pick == WIDE_EMPTY) break;
+            if (pick < 0) {
+                visit_leaf(r, bv, ids, p, ~pick);
+                break;
+            }
+            x = pick;
+        }
     }
     int node = root;
     bool lost = false;
     int restarts = 0;
     while (true) {
-        const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
-        float4 a = np[0], b = np[1], c = np[2], d = np[3];
-        int cl = __builtin_bit_cast(int, a.w), cr = __builtin_bit_cast(int, b.w);
-        T dl = box_d2<T>(a, b, p), dr = box_d2<T>(c, d, p);
-        r.nbox += 2;
-        T thr = r.d2 * slack;
-        bool hl = dl <= thr, hr = dr <= thr;
-        if (hl && cl < 0) {
-            visit_leaf(r, bv, ids, p, ~cl);
-            hl = false;
+        const WideNode *w = nodes + node;
+        const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
+        const int4 ch = w->child;
+        T e0 = box_d2<T>(make_float4(lx.x, ly.x, lz.x, 0.f), make_float4(hx.x, hy.x, hz.x, 0.f), p);
+        T e1 = box_d2<T>(make_float4(lx.y, ly.y, lz.y, 0.f), make_float4(hx.y, hy.y, hz.y, 0.f), p);
+        T e2 = box_d2<T>(make_float4(lx.z, ly.z, lz.z, 0.f), make_float4(hx.z, hy.z, hz.z, 0.f), p);
+        T e3 = box_d2<T>(make_float4(lx.w, ly.w, lz.w, 0.f), make_float4(hx.w, hy.w, hz.w, 0.f), p);
+        int f0 = ch.x, f1 = ch.y, f2 = ch.z, f3 = ch.w;
+        r.nbox += (f0 != WIDE_EMPTY) + (f1 != WIDE_EMPTY) + (f2 != WIDE_EMPTY) + (f3 != WIDE_EMPTY);
+        // leaves in range: their frames are loaded together (independent
+        // loads in flight at once), then folded in slot order
+        {
+            const T thr = r.d2 * slack;
+            const bool l0 = f0 < 0 && f0 != WIDE_EMPTY && e0 <= thr, l1 = f1 < 0 && f1 != WIDE_EMPTY && e1 <= thr,
+                       l2 = f2 < 0 && f2 != WIDE_EMPTY && e2 <= thr, l3 = f3 < 0 && f3 != WIDE_EMPTY && e3 <= thr;
+            if constexpr (sizeof(T) == 8) {
+                // FP64 frames are twice the size: one at a time
+                if (l0) visit_leaf(r, bv, ids, p, ~f0);
+                if (l1 && e1 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f1);
+                if (l2 && e2 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f2);
+                if (l3 && e3 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f3);
+            } else if (l0 || l1 || l2 || l3) {
+                Frame<T> F0, F1, F2, F3;
+                if (l0) F0 = load_frame(bv.frames, ~f0);
+                if (l1) F1 = load_frame(bv.frames, ~f1);
+                if (l2) F2 = load_frame(bv.frames, ~f2);
+                if (l3) F3 = load_frame(bv.frames, ~f3);
+                if (l0) fold_leaf(r, F0, p, ~f0);
+                if (l1 && e1 <= r.d2 * slack) fold_leaf(r, F1, p, ~f1);
+                if (l2 && e2 <= r.d2 * slack) fold_leaf(r, F2, p, ~f2);
+                if (l3 && e3 <= r.d2 * slack) fold_leaf(r, F3, p, ~f3);
+            }
         }
-        if (hr && cr < 0) {
-            visit_leaf(r, bv, ids, p, ~cr);
-            hr = false;
-        }
-        thr = r.d2 * slack;
-        hl = hl && dl <= thr;
-        hr = hr && dr <= thr;
-        if (hl && hr) {
-            bool lfirst = dl <= dr;
-            int nearc = lfirst ? cl : cr, farc = lfirst ? cr : cl;
-            T fard = lfirst ? dr : dl;
-            if (!st.push(farc, to_float_down(fard))) lost = true;
-            node = nearc;
-            continue;
-        }
-        if (hl) {
-            node = cl;
-            continue;
-        }
-        if (hr) {
-            node = cr;
+        // internal children in range, nearest first
+        const T thr = r.d2 * slack;
+        auto keep = [&](T &e, int &f) {
+            if (!(f >= 0 && e <= thr)) {
+                e = inf;
+                f = -1;
+            }
+        };
+        keep(e0, f0);
+        keep(e1, f1);
+        keep(e2, f2);
+        keep(e3, f3);
+        cswap(e0, f0, e1, f1);
+        cswap(e2, f2, e3, f3);
+        cswap(e0, f0, e2, f2);
+        cswap(e1, f1, e3, f3);
+        cswap(e1, f1, e2, f2);
+        if (f0 >= 0) {
+            if (f3 >= 0 && !st.push(f3, to_float_down(e3))) lost = true;
+            if (f2 >= 0 && !st.push(f2, to_float_down(e2))) lost = true;
+            if (f1 >= 0 && !st.push(f1, to_float_down(e1))) lost = true;
+            node = f0;
             continue;
         }
         bool found = false;

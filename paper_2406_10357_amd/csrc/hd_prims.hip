@@ -190,7 +190,40 @@ void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int
     }
 }
 
+__global__ __launch_bounds__(256) void k_export(Export e, unsigned *seq_dev, unsigned seq) {
+    for (int r = 0; r < e.n; ++r) {
+        const uint32_t *src = (const uint32_t *)e.src[r];
+        uint32_t *dst = (uint32_t *)e.dst[r];
+        const int64_t w = e.bytes[r] / 4;
+        for (int64_t i = threadIdx.x; i < w; i += blockDim.x) dst[i] = src[i];
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(seq_dev, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 } // namespace
+
+void export_to_host(const Export &e, unsigned *seq_dev, unsigned seq, hipStream_t s) {
+    k_export<<<1, 256, 0, s>>>(e, seq_dev, seq);
+    HD_LAUNCH_CHECK();
+}
+
+void wait_host_seq(const unsigned *seq_host, unsigned seq, hipStream_t s) {
+    for (unsigned long it = 1;; ++it) {
+        if (__atomic_load_n(seq_host, __ATOMIC_ACQUIRE) == seq) return;
+        if ((it & 4095) == 0) {
+            hipError_t e = hipStreamQuery(s);
+            if (e != hipSuccess && e != hipErrorNotReady) throw Error{HD_E_DEVICE, hipGetErrorString(e)};
+            if (e == hipSuccess) {
+                __atomic_thread_fence(__ATOMIC_SEQ_CST);
+                if (__atomic_load_n(seq_host, __ATOMIC_ACQUIRE) == seq) return;
+                throw Error{HD_E_INTERNAL, "device report not visible after the stream drained"};
+            }
+        }
+        __builtin_ia32_pause();
+    }
+}
 
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,
                         hipStream_t s) {

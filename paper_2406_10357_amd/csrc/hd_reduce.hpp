@@ -83,4 +83,24 @@ __device__ __forceinline__ void block_pair_minmax(int p, bool valid, const doubl
     __syncthreads();
 }
 
+// Statistics counters: the block sums v[k] (wave shuffles, then LDS) and one
+// thread adds each nonzero sum to *dst[k]. Every thread of the block must call
+// this (it contains barriers).
+template <int N, int BLOCK>
+__device__ __forceinline__ void block_add(const unsigned long long (&v)[N], unsigned long long *const (&dst)[N]) {
+    __shared__ unsigned long long s[N];
+    if (threadIdx.x < N) s[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        unsigned long long x = v[k];
+        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (__lane_id() == 0 && x) atomicAdd(&s[k], x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if (threadIdx.x == k && s[k]) atomicAdd(dst[k], s[k]);
+}
+
 } // namespace hd
