@@ -24,11 +24,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time to eps-certified h(A,B) (ms), learned vs plain; point-tri dist evals/s"
 
-# Algorithmic FP32 operations per unit of work in the query kernel (counted from
-# the source of the frame evaluation and the box test; an FMA counts as 2).
+# Algorithmic work per unit in the query kernel (LBVH traversal + point-triangle
+# distances). Bytes: a four-wide node is one 128 B line, a leaf's FP32 frame
+# 64 B, a query reads its point (3 x 8 B) and writes d, I, q, p and its key
+# (40 B). FP32 operations counted from the source of the frame evaluation and
+# the box test (an FMA counts as 2).
+BYTES_PER_NODE = 128
+BYTES_PER_LEAF = 64
+BYTES_PER_QUERY = 64
+BOXES_PER_NODE = 4
 FLOP_PER_LEAF = 63       # one point-triangle distance in the triangle's frame
 FLOP_PER_BOX = 11        # one point-box squared distance
 FLOP_PER_QUERY = 70      # final closest point + square root per query
+PEAK_HBM = 8000.0         # GB/s, MI355X datasheet HBM3E
 PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X datasheet vector FP32
 
 
@@ -40,7 +48,48 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--precision", default="fp32+recheck", choices=["fp64", "fp32", "fp32+recheck"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (x4): the reference for the HBM "
+                         "byte counters (FETCH_SIZE / WRITE_SIZE) of a rocprofv3 --pmc run")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": n * 4,
+                      "bytes_written_per_launch": n * 4, "launches": 4}), flush=True)
+
+
+# HBM traffic of the query kernel from a rocprofv3 --pmc run, valid only for
+# the kernel sources it was measured on (their hash is stored beside it)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_query_traffic_c2_torus.json")
+KERNEL_SOURCES = ["hd_kernels.hpp", "hd_geom.hpp", "hd_math.hpp", "hd_engine.hip", "hd_bvh.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2406_10357_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(W, reps=3):
@@ -55,6 +104,9 @@ def cpu_baseline(W, reps=3):
 
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
@@ -101,7 +153,9 @@ def main():
     q_launch = sum(r[2]["query_launches"] for r in results)
     evals = sum(r[2]["pt_tri_evals"] for r in results)
     flops = FLOP_PER_LEAF * q_leaf + FLOP_PER_BOX * q_box + FLOP_PER_QUERY * q_n
-    achieved = flops / (q_ms * 1e-3) / 1e12 if q_ms > 0 else None
+    nbytes = BYTES_PER_NODE * q_box / BOXES_PER_NODE + BYTES_PER_LEAF * q_leaf + BYTES_PER_QUERY * q_n
+    achieved = nbytes / (q_ms * 1e-3) / 1e9 if q_ms > 0 else None
+    tflops = flops / (q_ms * 1e-3) / 1e12 if q_ms > 0 else None
 
     out = {
         "metric": METRIC,
@@ -131,16 +185,18 @@ def main():
         "evals_per_s": evals / ((q_ms + c_ms) * 1e-3) if q_ms + c_ms > 0 else None,
         "learned_ms": None,
         "roofline": {
-            "kernel": "k_query<float> (LBVH traversal + point-triangle distances)",
-            "bound": "alu",
+            "kernel": "k_query<float> (four-wide LBVH traversal + point-triangle distances)",
+            "bound": "hbm",
             "achieved": achieved,
-            "peak": PEAK_FP32_VECTOR,
-            "unit": "TFLOP/s",
-            "frac": (achieved / PEAK_FP32_VECTOR) if achieved else None,
-            "traffic": None,
+            "peak": PEAK_HBM,
+            "unit": "GB/s",
+            "frac": (achieved / PEAK_HBM) if achieved else None,
+            "traffic": measured_traffic(),
             "launches": q_launch,
             "avg_launch_ms": q_ms / q_launch if q_launch else None,
-            "flops_per_launch": flops / q_launch if q_launch else None,
+            "algorithmic_bytes_per_launch": nbytes / q_launch if q_launch else None,
+            "fp32_tflops": tflops,
+            "fp32_frac_of_157_3": (tflops / PEAK_FP32_VECTOR) if tflops else None,
         },
     }
     if not a.no_cpu_baseline:
