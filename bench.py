@@ -81,13 +81,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(config):
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != kernel_source_hash():
+    if t.get("config") != config or t.get("source_sha256") != kernel_source_hash():
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -100,6 +100,30 @@ def cpu_baseline(W, reps=3):
         res = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
         times.append((time.perf_counter() - t0) * 1e3)
     return statistics.median(times), res
+
+
+def bbox_diag(W):
+    """dA: diagonal of the bounding box of A's referenced vertices."""
+    import numpy as np
+    V = W.VA[np.unique(W.FA)]
+    return float(np.linalg.norm(V.max(0) - V.min(0)))
+
+
+def cpu_baseline_pairs(pairs, budget_s=15.0):
+    """The oracle on the first pairs of the batch until about budget_s of CPU
+    work, scaled to the whole batch by face count."""
+    import oracle
+    t_total, faces, res = 0.0, 0, []
+    for W in pairs:
+        t0 = time.perf_counter()
+        r = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+        t_total += time.perf_counter() - t0
+        faces += W.FA.shape[0]
+        res.append(r)
+        if t_total > budget_s:
+            break
+    all_faces = sum(W.FA.shape[0] for W in pairs)
+    return t_total * 1e3 * all_faces / faces, res, faces
 
 
 def main():
@@ -118,15 +142,28 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    W = wl.config(a.config)
     prec = {"fp64": hd.PREC_FP64, "fp32": hd.PREC_FP32, "fp32+recheck": hd.PREC_FP32_RECHECK}[a.precision]
-    VA = torch.from_numpy(W.VA).cuda()
-    FA = torch.from_numpy(W.FA).cuda()
-    VB = torch.from_numpy(W.VB).cuda()
-    FB = torch.from_numpy(W.FB).cuda()
+    batched = a.config == 4
+    if batched:
+        print("generating the 256 pairs ...", file=sys.stderr, flush=True)
+        pairs = wl.batched_pairs(256, workers=min(16, os.cpu_count() or 1))
+        cu = lambda x: torch.from_numpy(x).cuda()
+        soupsB = [(cu(P.VB), cu(P.FB)) for P in pairs]
+        soupsA = [(cu(P.VA), cu(P.FA)) for P in pairs]
+        eps = [P.eps_rel for P in pairs]
+        W = pairs[0]
+    else:
+        W = wl.config(a.config)
+        VA = torch.from_numpy(W.VA).cuda()
+        FA = torch.from_numpy(W.FA).cuda()
+        VB = torch.from_numpy(W.VB).cuda()
+        FB = torch.from_numpy(W.FB).cuda()
     torch.cuda.synchronize()
 
     def step(profile=0):
+        if batched:
+            bvh = hd.build_bvh_batched(soupsB)
+            return hd.bound_batched(soupsA, bvh, eps, precision=prec, profile=profile)
         bvh = hd.build_bvh(VB, FB)
         return hd.bound(VA, FA, bvh, W.eps_rel, precision=prec, profile=profile)
 
@@ -157,6 +194,26 @@ def main():
     achieved = nbytes / (q_ms * 1e-3) / 1e9 if q_ms > 0 else None
     tflops = flops / (q_ms * 1e-3) / 1e12 if q_ms > 0 else None
 
+    if batched:
+        nA_all = sum(P.FA.shape[0] for P in pairs)
+        nB_all = sum(P.FB.shape[0] for P in pairs)
+        workload = {"workload": f"C4 256 pairs (noisy spheres / tori, {nA_all} / {nB_all} F in all, "
+                                "eps 1e-4*dA per pair)", "npairs": 256, "nA": nA_all, "nB": nB_all,
+                    "eps_rel": 1e-4, "precision": a.precision, "variant": "one batched call, breadth-first rounds"}
+        result = {"rounds": st["rounds"], "subdivided": st["subdivided"], "nodes_bounded": st["nodes_bounded"],
+                  "queries": st["queries"], "pt_tri_evals": st["pt_tri_evals"],
+                  "max_width_over_eps": max((u - l) / (P.eps_rel * bbox_diag(P)) for l, u, P in zip(L, U, pairs)),
+                  "status": st["status"]}
+    else:
+        workload = {"workload": W.name, "nA": int(W.FA.shape[0]), "nB": int(W.FB.shape[0]),
+                    "eps_rel": W.eps_rel, "precision": a.precision,
+                    "variant": "plain cascade 1234, breadth-first rounds"}
+        result = {"L": L, "U": U, "dA": st["dA"], "eps_abs": st["eps_abs"], "rounds": st["rounds"],
+                  "subdivided": st["subdivided"], "nodes_bounded": st["nodes_bounded"],
+                  "queries": st["queries"], "pt_tri_evals": st["pt_tri_evals"],
+                  "query_leaf_evals": st["query_leaf_evals"], "query_box_tests": st["query_box_tests"],
+                  "discards": st["discards"], "rechecked64": st["rechecked64"],
+                  "parked_final": st["parked_final"]}
     out = {
         "metric": METRIC,
         "value": round(ms, 4),
@@ -170,18 +227,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {
-            "workload": W.name,
-            "nA": int(W.FA.shape[0]), "nB": int(W.FB.shape[0]),
-            "eps_rel": W.eps_rel, "precision": a.precision,
-            "variant": "plain cascade 1234, breadth-first rounds",
-        },
-        "result": {"L": L, "U": U, "dA": st["dA"], "eps_abs": st["eps_abs"], "rounds": st["rounds"],
-                   "subdivided": st["subdivided"], "nodes_bounded": st["nodes_bounded"],
-                   "queries": st["queries"], "pt_tri_evals": st["pt_tri_evals"],
-                   "query_leaf_evals": st["query_leaf_evals"], "query_box_tests": st["query_box_tests"],
-                   "discards": st["discards"], "rechecked64": st["rechecked64"],
-                   "parked_final": st["parked_final"]},
+        "config": workload,
+        "result": result,
         "evals_per_s": evals / ((q_ms + c_ms) * 1e-3) if q_ms + c_ms > 0 else None,
         "learned_ms": None,
         "roofline": {
@@ -191,7 +238,7 @@ def main():
             "peak": PEAK_HBM,
             "unit": "GB/s",
             "frac": (achieved / PEAK_HBM) if achieved else None,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(a.config),
             "launches": q_launch,
             "avg_launch_ms": q_ms / q_launch if q_launch else None,
             "algorithmic_bytes_per_launch": nbytes / q_launch if q_launch else None,
@@ -199,7 +246,16 @@ def main():
             "fp32_frac_of_157_3": (tflops / PEAK_FP32_VECTOR) if tflops else None,
         },
     }
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and batched:
+        print("timing the CPU oracle on a sample of the pairs ...", file=sys.stderr, flush=True)
+        cms, refs, faces = cpu_baseline_pairs(pairs)
+        out["cpu_baseline"] = {"value": round(cms, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"single-threaded FP64 oracle (own AABB tree) on the first {len(refs)} "
+                                         f"pairs ({faces} of {nA_all} A faces), scaled to the batch by face count"}
+        ok = [bool(L[i] <= r["U"] and r["L"] <= U[i]) for i, r in enumerate(refs)]
+        out["parity"] = {"pairs_checked": len(refs), "overlap_all": all(ok),
+                         "max_dL_over_eps": max(abs(L[i] - r["L"]) / r["eps_abs"] for i, r in enumerate(refs))}
+    elif not a.no_cpu_baseline:
         print("timing the CPU oracle on the same workload ...", file=sys.stderr, flush=True)
         cms, ref = cpu_baseline(W)
         out["cpu_baseline"] = {"value": round(cms, 3), "unit": "ms", "cores": 1, "kind": "oracle",

@@ -351,36 +351,43 @@ def _smooth_displacement(P, N, rng, amp=0.01, nwaves=4):
     return P + (amp / nwaves) * disp[:, None] * N
 
 
-def batched_pairs(npairs=256, nmin=1000, nmax=100000, seed=0):
+def batched_pairs(npairs=256, nmin=1000, nmax=100000, seed=0, workers=1):
     """Many independent pairs of uneven size. Pair i draws from
     default_rng([seed, i]): a noisy geodesic sphere or displaced torus A with a
     log-uniform face count in [nmin, nmax], and B a re-triangulated copy of the
     same surface moved along its normal by N(0, sigma^2) with sigma
-    log-uniform in [1e-4, 1e-2]. Tolerance 1e-4 relative per pair."""
-    out = []
-    for i in range(npairs):
-        rng = np.random.default_rng([seed, i])
-        kind = "sphere" if rng.uniform() < 0.5 else "torus"
-        nA = float(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
-        sigma = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
-        wave_seed = int(rng.integers(1 << 31))
-        if kind == "sphere":
-            freq = max(2, int(round(math.sqrt(nA / 20.0))))
-            VA, FA = geodesic_sphere(freq)
-            wr = np.random.default_rng(wave_seed)
-            VA = _smooth_displacement(VA, VA.copy(), wr)
-            VB, FB = sphere_hull(max(8, int(round(nA / 2 + 2))), rng)
-            NB = VB.copy()
-            VB = _smooth_displacement(VB, NB, np.random.default_rng(wave_seed))
-            VB = perturb_along_normals(VB, NB, sigma, rng)
-        else:
-            nv = max(4, int(round(math.sqrt(nA / 2 * TORUS_r / TORUS_R))))
-            nu = max(4, int(round(nA / 2 / nv)))
-            amp = 0.01
-            VA, FA = torus_grid(nu, nv, amp=amp, ku=3, kv=2)
-            VB, FB, uv = torus_delaunay(max(16, int(round(nA / 2))), rng.integers(1 << 31),
-                                        amp=amp, ku=3, kv=2)
-            VB = perturb_along_normals(VB, torus_normal(uv[:, 0], uv[:, 1]), sigma, rng)
-        out.append(Workload(f"pair{i}-{kind}", VA, FA, VB, FB, 1e-4, "fp32+recheck",
-                            {"sigma": sigma, "kind": kind}))
-    return out
+    log-uniform in [1e-4, 1e-2]. Tolerance 1e-4 relative per pair.
+    workers > 1 generates the pairs in that many processes (same result)."""
+    if workers > 1 and npairs > 1:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            futs = [ex.submit(_one_pair, i, nmin, nmax, seed) for i in range(npairs)]
+            return [f.result() for f in futs]
+    return [_one_pair(i, nmin, nmax, seed) for i in range(npairs)]
+
+
+def _one_pair(i, nmin, nmax, seed):
+    rng = np.random.default_rng([seed, i])
+    kind = "sphere" if rng.uniform() < 0.5 else "torus"
+    nA = float(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
+    sigma = float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2))))
+    wave_seed = int(rng.integers(1 << 31))
+    if kind == "sphere":
+        freq = max(2, int(round(math.sqrt(nA / 20.0))))
+        VA, FA = geodesic_sphere(freq)
+        wr = np.random.default_rng(wave_seed)
+        VA = _smooth_displacement(VA, VA.copy(), wr)
+        VB, FB = sphere_hull(max(8, int(round(nA / 2 + 2))), rng)
+        NB = VB.copy()
+        VB = _smooth_displacement(VB, NB, np.random.default_rng(wave_seed))
+        VB = perturb_along_normals(VB, NB, sigma, rng)
+    else:
+        nv = max(4, int(round(math.sqrt(nA / 2 * TORUS_r / TORUS_R))))
+        nu = max(4, int(round(nA / 2 / nv)))
+        amp = 0.01
+        VA, FA = torus_grid(nu, nv, amp=amp, ku=3, kv=2)
+        VB, FB, uv = torus_delaunay(max(16, int(round(nA / 2))), rng.integers(1 << 31),
+                                    amp=amp, ku=3, kv=2)
+        VB = perturb_along_normals(VB, torus_normal(uv[:, 0], uv[:, 1]), sigma, rng)
+    return Workload(f"pair{i}-{kind}", VA, FA, VB, FB, 1e-4, "fp32+recheck", {"sigma": sigma, "kind": kind})

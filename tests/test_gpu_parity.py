@@ -295,6 +295,40 @@ def test_batched_pairs_against_oracle_and_single(prec):
         assert L1 <= Us[i] + 1e-12 * dA and Ls[i] <= U1 + 1e-12 * dA
 
 
+def _dA(VA, FA):
+    V = VA[np.unique(FA)]
+    return float(np.linalg.norm(V.max(0) - V.min(0)))
+
+
+@pytest.mark.parametrize("npairs,nmax", [(24, 3000), (256, 100000)])
+def test_batched_generator_pairs(npairs, nmax):
+    """The many-pair workload in one call: every pair certified to its own
+    tolerance; sampled pairs against the oracle (the small ones, which the
+    oracle finishes in seconds)."""
+    import os
+    hd, torch = _hd()
+    pairs = wl.batched_pairs(npairs, nmax=nmax, workers=min(16, os.cpu_count() or 1))
+    nA = sum(P.FA.shape[0] for P in pairs)
+    say("batched generator", npairs, "pairs, nmax", nmax, "faces", nA)
+    bvh = hd.build_bvh_batched([(_cu(P.VB, torch), _cu(P.FB, torch)) for P in pairs])
+    Ls, Us, st = hd.bound_batched([(_cu(P.VA, torch), _cu(P.FA, torch)) for P in pairs], bvh,
+                                  [P.eps_rel for P in pairs], precision=hd.PREC_FP32_RECHECK)
+    assert st["status"] == 0
+    for i, P in enumerate(pairs):
+        dA = _dA(P.VA, P.FA)
+        assert 0 <= Ls[i] <= Us[i], i
+        assert Us[i] - Ls[i] <= P.eps_rel * dA * (1 + 1e-12), i
+    order = np.argsort([P.FA.shape[0] for P in pairs])
+    for i in list(order[:3]) + [int(order[len(order) // 2])]:
+        P = pairs[i]
+        ref = oracle.bound(P.VA, P.FA, P.VB, P.FB, P.eps_rel, backend="tree")
+        dA = ref["dA"]
+        print(f"pair {i} ({P.FA.shape[0]} F): gpu [{Ls[i]:.10g}, {Us[i]:.10g}] "
+              f"oracle [{ref['L']:.10g}, {ref['U']:.10g}]", flush=True)
+        assert Ls[i] <= ref["U"] + 1e-12 * dA and ref["L"] <= Us[i] + 1e-12 * dA
+        assert abs(Ls[i] - ref["L"]) <= P.eps_rel * dA
+
+
 def test_subbatch_selection_is_certified():
     hd, torch = _hd()
     W = wl.config(2, scale=0.05)
