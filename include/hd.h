@@ -154,6 +154,36 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh B, int32_t prec
 hd_status hd_eval_bounds(const double *v, const double *d, const int32_t *I, const double *q, int64_t n,
                          hd_bvh B, int32_t precision, double *out, int32_t *u3_case, hd_stream_t stream);
 
+/* ---- learned proposal: the network ---------------------------------------
+ * Not part of the paper's method. A 16 -> 64 -> 64 -> 1 ReLU network predicts,
+ * for a frontier triangle, (max over the triangle of d(p, B) - largest vertex
+ * distance) / longest edge from 16 features; the prediction only orders work
+ * and picks which bounds to evaluate, never a discard or a certificate.
+ * Parameters: one FP32 vector of hd_mlp_nparams() = 5313 values, W1 [16][64]
+ * (input-major), b1 [64], W2 [64][64], b2 [64], w3 [64], b3. The hidden layers
+ * run as BF16 x BF16 matrix products with FP32 accumulation, the output layer
+ * as an FP32 dot product with BF16-rounded weights. All pointers are device
+ * pointers; the calls are asynchronous on `stream`. */
+int32_t hd_mlp_nparams(void);
+
+/* y[i] = network(X[i, 0..15]) for i < n (X row-major FP32, 16-byte aligned). */
+hd_status hd_mlp_forward(const float *X, int64_t n, const float *params, float *y, hd_stream_t stream);
+
+/* Gradient of the mean squared error (1/n) sum_i (y_i - t_i)^2 with respect to
+ * the parameters, into grad[5313]; *loss (device, may be NULL) receives the
+ * loss. One workgroup; intended for checks and small batches. */
+hd_status hd_mlp_grad(const float *X, const float *t, int64_t n, const float *params, float *grad, float *loss,
+                      hd_stream_t stream);
+
+/* nsteps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * the mean squared error; step s uses rows rows[s*batch .. s*batch+batch-1] of
+ * (X, t). params, adam_m and adam_v (5313 each) are updated in place; step0 is
+ * the number of steps already taken (for the bias correction). loss (device,
+ * may be NULL) receives nsteps minibatch losses. Runs in one workgroup. */
+hd_status hd_mlp_train(const float *X, const float *t, const int32_t *rows, int64_t nsteps, int32_t batch,
+                       float *params, float *adam_m, float *adam_v, int64_t step0, float lr, float *loss,
+                       hd_stream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char *hd_status_str(hd_status s);
 

@@ -56,7 +56,8 @@ class Stats(C.Structure):
 
 
 EXPORTS = ["hd_build_bvh", "hd_build_bvh_batched", "hd_free_bvh", "hd_bound", "hd_bound_batched",
-           "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options"]
+           "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options",
+           "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train"]
 
 
 def load_library(path: str | None = None):
@@ -91,6 +92,14 @@ def load_library(path: str | None = None):
     lib.hd_status_str.argtypes = [i32]
     lib.hd_default_options.restype = None
     lib.hd_default_options.argtypes = [C.POINTER(Options)]
+    lib.hd_mlp_nparams.restype = i32
+    lib.hd_mlp_nparams.argtypes = []
+    lib.hd_mlp_forward.restype = i32
+    lib.hd_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+    lib.hd_mlp_grad.restype = i32
+    lib.hd_mlp_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    lib.hd_mlp_train.restype = i32
+    lib.hd_mlp_train.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, i64, C.c_float, vp, vp]
     _lib = lib
     return lib
 
@@ -245,3 +254,57 @@ def eval_bounds(v, d, I, q, bvh: Bvh, precision=PREC_FP64):
                             C.c_void_p(case.data_ptr()), _stream())
     _check(st, "hd_eval_bounds")
     return out, case
+
+
+# ---------------------------------------------------------------------------
+# learned proposal: the network
+# ---------------------------------------------------------------------------
+
+def mlp_nparams() -> int:
+    return int(load_library().hd_mlp_nparams())
+
+
+def _ptr(x):
+    return C.c_void_p(x.data_ptr())
+
+
+def mlp_forward(X, params):
+    """Predictions of the network for the rows of X (n x 16)."""
+    torch = _torch()
+    lib = load_library()
+    X = _dev(X, torch.float32).reshape(-1, 16)
+    params = _dev(params, torch.float32)
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(lib.hd_mlp_forward(_ptr(X), X.shape[0], _ptr(params), _ptr(y), _stream()), "hd_mlp_forward")
+    return y
+
+
+def mlp_grad(X, t, params):
+    """(gradient of the mean squared error, loss) for rows X, targets t."""
+    torch = _torch()
+    lib = load_library()
+    X = _dev(X, torch.float32).reshape(-1, 16)
+    t = _dev(t, torch.float32)
+    params = _dev(params, torch.float32)
+    g = torch.empty(mlp_nparams(), dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib.hd_mlp_grad(_ptr(X), _ptr(t), X.shape[0], _ptr(params), _ptr(g), _ptr(loss), _stream()),
+           "hd_mlp_grad")
+    return g, loss
+
+
+def mlp_train(X, t, rows, batch, params, adam_m, adam_v, step0=0, lr=1e-3):
+    """Adam steps in place on params / adam_m / adam_v (device FP32 tensors);
+    rows holds nsteps * batch row indices. Returns the minibatch losses."""
+    torch = _torch()
+    lib = load_library()
+    X = _dev(X, torch.float32).reshape(-1, 16)
+    t = _dev(t, torch.float32)
+    rows = _dev(rows, torch.int32)
+    nsteps = rows.numel() // batch
+    for a in (params, adam_m, adam_v):
+        assert a.is_cuda and a.dtype == torch.float32 and a.is_contiguous()
+    loss = torch.empty(max(nsteps, 1), dtype=torch.float32, device=X.device)
+    _check(lib.hd_mlp_train(_ptr(X), _ptr(t), _ptr(rows), nsteps, batch, _ptr(params), _ptr(adam_m),
+                            _ptr(adam_v), step0, float(lr), _ptr(loss), _stream()), "hd_mlp_train")
+    return loss[:nsteps]

@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhd.so")
-SOURCES = ["hd_prims.hip", "hd_bvh.hip", "hd_engine.hip"]
+SOURCES = ["hd_prims.hip", "hd_bvh.hip", "hd_engine.hip", "hd_mlp.hip"]
 ARCH = os.environ.get("HD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
