@@ -62,6 +62,18 @@ typedef struct {
                             upper bound first (approximates the paper's best-first queue) */
     int32_t profile;     /* 1: time the query and cascade kernels with HIP events on the
                             call's stream (fills the ms_* kernel fields of hd_stats) */
+    int32_t learned;     /* learned proposal (not in the paper): 0 off; 1 the sub-batch is
+                            taken in order of the network's predicted maximum distance
+                            instead of the upper bound; 2 also let the network skip u3 and u4
+                            for triangles it predicts to stay active. Bounds, discards and
+                            the certificate are unchanged in kind. */
+    int32_t log_frontier;      /* 1: log every subdivided parent's features and label */
+    const float *mlp_params;   /* device, hd_mlp_nparams() FP32 values; needed when learned > 0 */
+    float *log_out;            /* device, log_cap rows of 17 FP32: the 16 features (as the
+                                  network takes them) and the label (max over the resolution-4
+                                  barycentric lattice of d(p, B) - max vertex distance) /
+                                  longest edge; rows of parents deeper than level 28 are NaN */
+    int64_t log_cap;
 } hd_options;
 
 typedef struct {
@@ -87,6 +99,8 @@ typedef struct {
     int64_t query_launches, cascade_launches;
     int64_t query_leaf_evals;  /* closest-point evaluations inside the query kernels */
     int64_t query_box_tests;   /* box tests inside the query kernels */
+    int64_t logged;            /* log_frontier: rows written to log_out (<= log_cap) */
+    int64_t learned_skips;     /* learned = 2: triangles whose u3 and u4 were skipped */
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle
@@ -183,6 +197,13 @@ hd_status hd_mlp_grad(const float *X, const float *t, int64_t n, const float *pa
 hd_status hd_mlp_train(const float *X, const float *t, const int32_t *rows, int64_t nsteps, int32_t batch,
                        float *params, float *adam_m, float *adam_v, int64_t step0, float lr, float *loss,
                        hd_stream_t stream);
+
+/* Test entry: the 16 features of n triangles of a single-pair B (layout as in
+ * hd_eval_bounds: v, q n x 9, d, I n x 3 with ORIGINAL face indices), given
+ * the running lower bound L and the tolerance scale dA, in FP32 arithmetic,
+ * into X (n x 16, device). Out-of-range face indices give NaN rows. */
+hd_status hd_frontier_features(const double *v, const double *d, const int32_t *I, const double *q, int64_t n,
+                               hd_bvh B, double L, double dA, float *X, hd_stream_t stream);
 
 /* Human-readable name of a status code (static string). */
 const char *hd_status_str(hd_status s);

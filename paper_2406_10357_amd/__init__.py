@@ -34,7 +34,9 @@ class HDError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("order", C.c_int32), ("budget_m", C.c_double),
                 ("capacity", C.c_int64), ("max_rounds", C.c_int32), ("stack_depth", C.c_int32),
-                ("subbatch", C.c_int32), ("profile", C.c_int32)]
+                ("subbatch", C.c_int32), ("profile", C.c_int32), ("learned", C.c_int32),
+                ("log_frontier", C.c_int32), ("mlp_params", C.c_void_p), ("log_out", C.c_void_p),
+                ("log_cap", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -47,7 +49,8 @@ class Stats(C.Structure):
                 ("mu_coef_0", C.c_double), ("ms_total", C.c_double),
                 ("ms_query_kernels", C.c_double), ("ms_cascade_kernels", C.c_double),
                 ("query_launches", C.c_int64), ("cascade_launches", C.c_int64),
-                ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64)]
+                ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64),
+                ("logged", C.c_int64), ("learned_skips", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -57,7 +60,7 @@ class Stats(C.Structure):
 
 EXPORTS = ["hd_build_bvh", "hd_build_bvh_batched", "hd_free_bvh", "hd_bound", "hd_bound_batched",
            "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options",
-           "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train"]
+           "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train", "hd_frontier_features"]
 
 
 def load_library(path: str | None = None):
@@ -92,6 +95,8 @@ def load_library(path: str | None = None):
     lib.hd_status_str.argtypes = [i32]
     lib.hd_default_options.restype = None
     lib.hd_default_options.argtypes = [C.POINTER(Options)]
+    lib.hd_frontier_features.restype = i32
+    lib.hd_frontier_features.argtypes = [vp, vp, vp, vp, i64, vp, dbl, dbl, vp, vp]
     lib.hd_mlp_nparams.restype = i32
     lib.hd_mlp_nparams.argtypes = []
     lib.hd_mlp_forward.restype = i32
@@ -156,12 +161,22 @@ def build_bvh(VB, FB) -> Bvh:
 
 
 def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
-                 stack_depth=0, subbatch=0, profile=0) -> Options:
+                 stack_depth=0, subbatch=0, profile=0, learned=0, mlp_params=None, log_out=None) -> Options:
+    """mlp_params: device FP32 tensor of mlp_nparams() values (learned > 0);
+    log_out: device FP32 tensor (rows, 17) that receives the frontier log."""
     o = Options()
     load_library().hd_default_options(C.byref(o))
     o.precision, o.order, o.budget_m = precision, order, budget_m
     o.capacity, o.max_rounds, o.stack_depth, o.subbatch = capacity, max_rounds, stack_depth, subbatch
     o.profile = profile
+    o.learned = learned
+    if mlp_params is not None:
+        o.mlp_params = mlp_params.data_ptr()
+    if log_out is not None:
+        assert log_out.is_cuda and log_out.dtype == _torch().float32 and log_out.shape[-1] == 17
+        o.log_frontier = 1
+        o.log_out = log_out.data_ptr()
+        o.log_cap = log_out.shape[0]
     return o
 
 
@@ -308,3 +323,18 @@ def mlp_train(X, t, rows, batch, params, adam_m, adam_v, step0=0, lr=1e-3):
     _check(lib.hd_mlp_train(_ptr(X), _ptr(t), _ptr(rows), nsteps, batch, _ptr(params), _ptr(adam_m),
                             _ptr(adam_v), step0, float(lr), _ptr(loss), _stream()), "hd_mlp_train")
     return loss[:nsteps]
+
+
+def frontier_features(v, d, I, q, bvh: Bvh, L: float, dA: float):
+    """The learned proposal's 16 features of n triangles (see hd_frontier_features)."""
+    torch = _torch()
+    lib = load_library()
+    v = _dev(v, torch.float64).reshape(-1, 9)
+    n = v.shape[0]
+    d = _dev(d, torch.float64).reshape(n, 3)
+    I = _dev(I, torch.int32).reshape(n, 3)
+    q = _dev(q, torch.float64).reshape(n, 9)
+    X = torch.empty((n, 16), dtype=torch.float32, device=v.device)
+    _check(lib.hd_frontier_features(_ptr(v), _ptr(d), _ptr(I), _ptr(q), n, bvh.handle, float(L), float(dA),
+                                    _ptr(X), _stream()), "hd_frontier_features")
+    return X

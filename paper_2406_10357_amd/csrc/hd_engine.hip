@@ -26,6 +26,8 @@
 #include <mutex>
 
 #include "hd_kernels.hpp"
+#include "hd_learned.hpp"
+#include "hd_mlp.hpp"
 #include "hd_reduce.hpp"
 
 namespace hd {
@@ -51,6 +53,7 @@ struct Ctl {
     alignas(128) unsigned long long evals, bounded, rechecked;
     unsigned long long discards[5];
     alignas(128) unsigned long long queries, boxes, q_leaves;
+    unsigned long long skips; // records whose u3 / u4 the learned policy skipped
 };
 
 struct PairSrcA {
@@ -267,7 +270,15 @@ __global__ void k_ref_scatter(const int32_t *__restrict__ ref, const int32_t *__
 // ---------------------------------------------------------------------------
 // point queries
 // ---------------------------------------------------------------------------
-enum QMode { Q_POINTS = 0, Q_VERTICES = 1, Q_MIDPOINTS = 2 };
+enum QMode { Q_POINTS = 0, Q_VERTICES = 1, Q_MIDPOINTS = 2, Q_LATTICE = 3 };
+
+// The twelve non-corner points of the resolution-4 barycentric lattice of a
+// triangle (weights (4 - a1 - a2, a1, a2) / 4), two bits per weight.
+constexpr int LATTICE_PTS = 12;
+constexpr uint32_t LATTICE_A1 = (1u << 0) | (0u << 2) | (2u << 4) | (1u << 6) | (0u << 8) | (3u << 10) | (2u << 12) |
+                                (1u << 14) | (0u << 16) | (3u << 18) | (2u << 20) | (1u << 22);
+constexpr uint32_t LATTICE_A2 = (0u << 0) | (1u << 2) | (0u << 4) | (1u << 6) | (2u << 8) | (0u << 10) | (1u << 12) |
+                                (2u << 14) | (3u << 16) | (1u << 18) | (2u << 20) | (3u << 22);
 
 template <class T> struct QueryOut {
     T *d;
@@ -284,7 +295,7 @@ template <class T> struct QueryIn {
     const int32_t *vids;     // Q_VERTICES: referenced vertex ids (global)
     const int64_t *voff;     // Q_VERTICES: vertex offsets of the pairs
     AView a;                 // Q_VERTICES / Q_MIDPOINTS
-    FrontierView<T> par;     // Q_MIDPOINTS: selected parents
+    FrontierView<T> par;     // Q_MIDPOINTS / Q_LATTICE: selected parents
     const PairConst *pc;
 };
 
@@ -313,6 +324,26 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
         q.p = a_vertex(in.a, q.pair, v);
         q.out = v;
         q.tag = mix32((uint32_t)v ^ 0x5bd1e995u);
+        return q;
+    }
+    if (in.mode == Q_LATTICE) {
+        const int64_t j = i / LATTICE_PTS;
+        const int k = (int)(i - LATTICE_PTS * j);
+        const int a1 = (LATTICE_A1 >> (2 * k)) & 3, a2 = (LATTICE_A2 >> (2 * k)) & 3, a0 = 4 - a1 - a2;
+        const int face = in.par.face()[j], lvl = in.par.lvl()[j];
+        q.pair = in.par.pair()[j];
+        if (lvl + 2 <= 30) {
+            const int ba = a0 * in.par.ba(0)[j] + a1 * in.par.ba(1)[j] + a2 * in.par.ba(2)[j];
+            const int bb = a0 * in.par.bb(0)[j] + a1 * in.par.bb(1)[j] + a2 * in.par.bb(2)[j];
+            q.p = a_point(in.a, q.pair, face, lvl + 2, ba, bb);
+        } else { // not representable: the first corner (such parents are not logged)
+            q.p = a_point(in.a, q.pair, face, lvl, in.par.ba(0)[j], in.par.bb(0)[j]);
+        }
+        q.out = i;
+        q.tag = 0;
+        const int heavy = a0 >= a1 && a0 >= a2 ? 0 : (a1 >= a2 ? 1 : 2);
+        q.seed[0] = in.par.I(heavy)[j];
+        q.seed[1] = in.par.I(heavy == 2 ? 0 : heavy + 1)[j];
         return q;
     }
     int64_t j = i / 3;
@@ -858,6 +889,157 @@ __global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg
 }
 
 // ---------------------------------------------------------------------------
+// learned proposal: features, predictions, logging, bound policy
+// ---------------------------------------------------------------------------
+struct LearnCfg {
+    const PairConst *pc;
+    const PairVar *pv;
+    IdView iv;
+};
+
+template <class T> HD_D Tri<T> record_tri(const FrontierView<T> &f, int64_t j) {
+    Corner<T> cn[3];
+    load_corners(f, j, cn);
+    return make_tri(cn);
+}
+
+// features of records 0..n-1 into rows of X (row stride `stride` floats)
+template <class T>
+__global__ void k_features_list(FrontierView<T> fr, int64_t n, LearnCfg lc, BView<T> bv, float *X, int stride) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int pair = fr.pair()[j];
+    float f[16];
+    tri_features(record_tri(fr, j), ord2d(lc.pv[pair].Lord), lc.pc[pair].dA, bv, lc.iv, f);
+    float *o = X + j * (int64_t)stride;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) o[k] = f[k];
+}
+
+// predicted maximum distance of a record: largest vertex distance plus the
+// network's output times the longest edge
+template <class T> HD_D float predicted_max(const FrontierView<T> &fr, int64_t j, float y) {
+    const Tri<T> t = record_tri(fr, j);
+    const T ell = hmax(hsqrt(norm2(t.v[1] - t.v[0])), hmax(hsqrt(norm2(t.v[2] - t.v[1])), hsqrt(norm2(t.v[0] - t.v[2]))));
+    const T dmax = hmax(t.d[0], hmax(t.d[1], t.d[2]));
+    return (float)dmax + (float)ell * y;
+}
+
+// selection keys in learned order: descending predicted maximum distance,
+// ties by the same order-independent tag as the plain keys (a NaN prediction
+// falls back to the record's upper bound)
+template <class T>
+__global__ void k_sel_keys_learned(FrontierView<T> fr, int64_t n, const float *__restrict__ y,
+                                   unsigned long long *__restrict__ keys, int32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float pm = predicted_max(fr, i, y[i]);
+    if (!(pm == pm)) pm = fr.ub()[i];
+    uint32_t tag = point_tag(fr.face()[i], fr.lvl()[i], fr.ba(0)[i] ^ (fr.ba(1)[i] << 7) ^ (fr.ba(2)[i] << 14),
+                             fr.bb(0)[i] ^ (fr.bb(1)[i] << 7) ^ (fr.bb(2)[i] << 14));
+    keys[i] = ((unsigned long long)(~f2ord(pm)) << 32) | tag;
+    vals[i] = (int32_t)i;
+}
+
+// frontier log: for parents 0..n-1, their features and the label
+// (max over the resolution-4 lattice of d(p, B) - max vertex distance) / l,
+// into rows base + j of log (17 floats each; rows past cap are dropped, as
+// are parents too deep for the lattice)
+template <class T>
+__global__ void k_log_parents(FrontierView<T> fr, int64_t n, QueryOut<T> lq, LearnCfg lc, BView<T> bv, float *log,
+                              int64_t base, int64_t cap) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n || base + j >= cap) return;
+    float *o = log + (base + j) * 17;
+    const Tri<T> t = record_tri(fr, j);
+    const int pair = fr.pair()[j];
+    if (fr.lvl()[j] + 2 > 30) {
+        for (int k = 0; k < 17; ++k) o[k] = __builtin_nanf("");
+        return;
+    }
+    float f[16];
+    tri_features(t, ord2d(lc.pv[pair].Lord), lc.pc[pair].dA, bv, lc.iv, f);
+    const T dmax = hmax(t.d[0], hmax(t.d[1], t.d[2]));
+    T h = dmax;
+    for (int k = 0; k < LATTICE_PTS; ++k) h = hmax(h, lq.d[j * LATTICE_PTS + k]);
+    const T ell = hmax(hsqrt(norm2(t.v[1] - t.v[0])), hmax(hsqrt(norm2(t.v[2] - t.v[1])), hsqrt(norm2(t.v[0] - t.v[2]))));
+    for (int k = 0; k < 16; ++k) o[k] = f[k];
+    o[16] = ell > T(0) ? (float)((h - dmax) / ell) : 0.f;
+}
+
+// Stage B with the bound policy: a wave scores its 64 records with the
+// network (matrix cores); a record whose predicted maximum lies above
+// L + eps by more than 2% of its longest edge keeps stage A's bound and
+// skips u3 and u4 (its true maximum, hence any bound, almost surely keeps it
+// active); the others run stage B as usual.
+constexpr float POLICY_MARGIN = 0.02f;
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, ClassifyCfg cc, BView<T> bv, Dest<T> dst,
+                                                         Ctl *ctl, LearnCfg lc, const float *__restrict__ params) {
+    const int64_t n = (int64_t)ctl->b_next;
+    if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole block idle
+    __shared__ mlp::Weights W;
+    __shared__ alignas(16) float X[BLK * 16];
+    __shared__ alignas(16) unsigned short stage[NW][16 * 64];
+    __shared__ float yv[BLK];
+    for (int i = threadIdx.x; i < mlp::NPARAM; i += BLK) mlp::set_param(W, i, params[i]);
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = j < n;
+    int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
+    double carry = 0;
+    Corner<T> cn[3];
+    float f[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f[k] = 0.f;
+    double L = 0;
+    if (valid) {
+        load_corners(in, j, cn);
+        pair = in.pair()[j];
+        face = in.face()[j];
+        lvl = in.lvl()[j] & 0xff;
+        L = ord2d(cc.pv[pair].Lord);
+        tri_features(make_tri(cn), L, lc.pc[pair].dA, bv, lc.iv, f);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) X[threadIdx.x * 16 + k] = f[k];
+    __syncthreads();
+    {
+        const int wave = threadIdx.x >> 6, l = __lane_id(), g = l >> 4, c = l & 15;
+        for (int t = 0; t < 4; ++t) {
+            mlp::Tile tl;
+            mlp::tile_forward(X + wave * 64 * 16, nullptr, 16 * t, 64, W, stage[wave], tl);
+            if (c == 0)
+                for (int q = 0; q < 4; ++q) yv[wave * 64 + 16 * t + 4 * g + q] = tl.y[q];
+        }
+    }
+    __syncthreads();
+    int skipped = 0;
+    if (valid) {
+        const Tri<T> t = make_tri(cn);
+        const T ell = hmax(hsqrt(norm2(t.v[1] - t.v[0])), hmax(hsqrt(norm2(t.v[2] - t.v[1])), hsqrt(norm2(t.v[0] - t.v[2]))));
+        const T dmax = hmax(t.d[0], hmax(t.d[1], t.d[2]));
+        const double pm = (double)dmax + (double)ell * (double)yv[threadIdx.x];
+        const double eps = cc.pc[pair].eps_abs;
+        if (pm > L + eps + (double)POLICY_MARGIN * (double)ell) {
+            // stage A's running minimum is already a valid bound
+            const double mu = tri_margin(t, margins_of<T>(cc.pc[pair]));
+            carry = (double)in.ub()[j];
+            decider = in.lvl()[j] >> 8;
+            list = decide(carry, L, eps, mu, cc.recheck);
+            skipped = 1;
+        } else {
+            list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+        }
+    }
+    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+    if (valid)
+        write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
+    tally(ctl, list, decider, evals, 0, valid, false);
+    block_add<1, BLK>({(unsigned long long)skipped}, {&ctl->skips});
+}
+
+// ---------------------------------------------------------------------------
 // record movement and selection
 // ---------------------------------------------------------------------------
 template <class T>
@@ -961,6 +1143,33 @@ __global__ void k_eval_bounds(const double *v, const double *d, const int32_t *I
     u3case[i] = cs;
 }
 
+// test entry: the learned proposal's features of given triangles
+template <class T>
+__global__ void k_tri_features(const double *v, const double *d, const int32_t *Iorig, const double *q, int64_t n,
+                               const int32_t *inv_perm, int64_t nB, BView<T> bv, IdView iv, const PairConst *pc,
+                               double L, double dA, float *X) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < 3; ++k) {
+        int32_t f = Iorig[3 * i + k];
+        if (f < 0 || f >= nB) {
+            for (int j = 0; j < 16; ++j) X[16 * i + j] = __builtin_nanf("");
+            return;
+        }
+    }
+    Tri<T> t;
+    const double *c = pc[0].ctr;
+    for (int k = 0; k < 3; ++k) {
+        t.v[k] = {T(v[9 * i + 3 * k] - c[0]), T(v[9 * i + 3 * k + 1] - c[1]), T(v[9 * i + 3 * k + 2] - c[2])};
+        t.q[k] = {T(q[9 * i + 3 * k] - c[0]), T(q[9 * i + 3 * k + 1] - c[1]), T(q[9 * i + 3 * k + 2] - c[2])};
+        t.d[k] = T(d[3 * i + k]);
+        t.I[k] = inv_perm[Iorig[3 * i + k]];
+    }
+    float f[16];
+    tri_features(t, L, dA, bv, iv, f);
+    for (int j = 0; j < 16; ++j) X[16 * i + j] = f[j];
+}
+
 __global__ void k_inv_perm(const int4 *ids, int64_t n, int32_t *inv) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) inv[ids[i].w] = (int32_t)i;
@@ -1041,13 +1250,14 @@ template <class T> struct QBuf {
 template <class T> struct TypedWs {
     FrontierBuf<T> act, act2, park;
     FrontierBuf<T> pend_b, pend_c; // records between cascade stages (one round's worth)
-    QBuf<T> vq, mq;
+    QBuf<T> vq, mq, lq;
 };
 struct Workspace {
     std::mutex mu;
     PinnedBuf host; // mailbox, staged uploads, exported results
     unsigned mb_seq = 0;
     std::vector<hipEvent_t> evpool; // profiling events (kept until the process ends)
+    DBuf feat; // learned order: features and predictions of the active list
     DBuf ctl, pc, pv, params, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
     TypedWs<float> w32;
     TypedWs<double> w64;
@@ -1139,6 +1349,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     CascadeCtx cctx;
     cctx.norder = parse_order(opt.order, cctx.order);
     if (cctx.norder <= 0) throw Error{HD_E_INVALID, "bad cascade order"};
+    if (opt.learned < 0 || opt.learned > 2) throw Error{HD_E_INVALID, "learned must be 0, 1 or 2"};
+    if (opt.learned > 0 && !opt.mlp_params) throw Error{HD_E_INVALID, "learned mode needs the network's parameters"};
+    if (opt.log_frontier && (!opt.log_out || opt.log_cap <= 0)) throw Error{HD_E_INVALID, "frontier log needs a buffer"};
     for (int p = 0; p < (in.eps_per_pair ? np : 1); ++p)
         if (!(in.eps[p] > 0) || !std::isfinite(in.eps[p])) throw Error{HD_E_INVALID, "eps must be positive"};
     std::vector<int64_t> foff(np + 1, 0), voff(np + 1, 0);
@@ -1293,9 +1506,13 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cc.pv = pv;
 
     // stages B and C over what one round's stage A produced (at most n records)
+    const LearnCfg lc{pc, pv, iv};
     auto later_stages = [&](int64_t n, const FrontierView<T> &act_out) {
         Dest<T> d{act_out, tw.park.v, tw.pend_b.v, tw.pend_c.v};
-        k_stage_b<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
+        if (opt.learned == 2)
+            k_stage_b_learned<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params);
+        else
+            k_stage_b<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
         if (cc.recheck) k_stage_c<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl);
         HD_LAUNCH_CHECK();
     };
@@ -1314,7 +1531,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
 
     const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
     double processed = (double)nA;
-    int64_t subdivided = 0;
+    int64_t subdivided = 0, logged = 0;
     int rounds = 0;
     S.max_frontier = nAct + nPark;
     hd_status status = HD_OK;
@@ -1354,7 +1571,18 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             unsigned long long *keys2 = keys + nAct;
             int32_t *vals = (int32_t *)(keys2 + nAct);
             int32_t *vals2 = vals + nAct;
-            k_sel_keys<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, keys, vals);
+            if (opt.learned > 0) {
+                // the network's predicted maximum distance orders the frontier
+                ws.feat.reserve((size_t)nAct * 16 * sizeof(float) + (size_t)nAct * sizeof(float) + 512);
+                float *X = ws.feat.as<float>();
+                float *y = X + ((nAct * 16 + 63) & ~int64_t(63));
+                k_features_list<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, lc, bv, X, 16);
+                HD_LAUNCH_CHECK();
+                mlp_forward(X, nAct, opt.mlp_params, y, s);
+                k_sel_keys_learned<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, y, keys, vals);
+            } else {
+                k_sel_keys<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, keys, vals);
+            }
             radix_sort_u64(keys, vals, keys2, vals2, nAct, 64, ws.sort_tmp, s);
             k_gather<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, vals, 0, nAct, tw.act2.v);
             HD_LAUNCH_CHECK();
@@ -1362,6 +1590,29 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         }
         const int64_t rest = nAct - K;
         k_round_setup<<<1, 1, 0, s>>>(ctl, (unsigned long long)rest, (unsigned long long)nPark);
+        if (opt.log_frontier && logged < opt.log_cap) {
+            // the parents' features and labels: 12 lattice queries each (they do
+            // not raise L, so the logged run follows the plain one)
+            tw.lq.ensure(LATTICE_PTS * K);
+            QueryIn<T> li{};
+            li.mode = Q_LATTICE;
+            li.npairs = np;
+            li.a = av;
+            li.par = tw.act.v;
+            li.pc = pc;
+            const QueryCfg lcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
+            const int64_t nq = LATTICE_PTS * K;
+            ws.ovf.reserve((size_t)nq * sizeof(int32_t));
+            k_query<T, QSTACK><<<grid_for(nq, QBLOCK), QBLOCK, 0, s>>>(li, nq, lcfg, bv, tw.lq.o, pc, pv, ctl,
+                                                                        ws.ovf.as<int32_t>());
+            k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(li, lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
+                                                            ws.deep.as<int2>());
+            k_log_parents<T><<<grid_for(K, BLK), BLK, 0, s>>>(tw.act.v, K, tw.lq.o, lc, bv, opt.log_out, logged,
+                                                              opt.log_cap);
+            HD_LAUNCH_CHECK();
+            logged += std::min<int64_t>(K, opt.log_cap - logged);
+            k_round_setup<<<1, 1, 0, s>>>(ctl, (unsigned long long)rest, (unsigned long long)nPark);
+        }
         // midpoints of the K selected parents
         tw.mq.ensure(3 * K);
         QueryIn<T> qi{};
@@ -1447,6 +1698,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     S.parked_final = nPark;
     S.query_leaf_evals = (int64_t)hc.q_leaves;
     S.query_box_tests = (int64_t)hc.boxes;
+    S.logged = logged;
+    S.learned_skips = (int64_t)hc.skips;
     S.dA = hc_[0].dA;
     S.eps_abs = hc_[0].eps_abs;
     S.mu_coef_d = margins_of<T>(hc_[0]).mu_d;
@@ -1667,6 +1920,29 @@ hd_status hd_eval_bounds(const double *v, const double *dd, const int32_t *I, co
             k_eval_bounds<float><<<grid_for(n, BLK), BLK, 0, s>>>(v, dd, I, q, n, inv.as<int32_t>(), B->nB,
                                                                   BView<float>{B->frames32.as<float4>()}, iv, pc,
                                                                   out, u3_case);
+        HD_LAUNCH_CHECK();
+        HD_HIP(hipStreamSynchronize(s));
+        return HD_OK;
+    });
+}
+
+hd_status hd_frontier_features(const double *v, const double *dd, const int32_t *I, const double *q, int64_t n,
+                               hd_bvh Bh, double L, double dA, float *X, hd_stream_t stream) {
+    if (!Bh || n < 0 || (n > 0 && (!v || !dd || !I || !q || !X)) || !(dA > 0)) return HD_E_INVALID;
+    if (n == 0) return HD_OK;
+    const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
+    hipStream_t s = (hipStream_t)stream;
+    return guard([&] {
+        DBuf inv, pcb, pvb;
+        inv.reserve((size_t)B->nB * sizeof(int32_t));
+        pcb.reserve(sizeof(PairConst));
+        pvb.reserve(sizeof(PairVar));
+        PairConst *pc = pcb.as<PairConst>();
+        k_pairs_init<<<1, 64, 0, s>>>(pc, pvb.as<PairVar>(), B->pairs.as<BvhPair>(), 1);
+        k_inv_perm<<<grid_for(B->nB, BLK), BLK, 0, s>>>(B->ids.as<int4>(), B->nB, inv.as<int32_t>());
+        k_tri_features<float><<<grid_for(n, BLK), BLK, 0, s>>>(v, dd, I, q, n, inv.as<int32_t>(), B->nB,
+                                                               BView<float>{B->frames32.as<float4>()},
+                                                               IdView{B->ids.as<int4>()}, pc, L, dA, X);
         HD_LAUNCH_CHECK();
         HD_HIP(hipStreamSynchronize(s));
         return HD_OK;

@@ -132,6 +132,9 @@ void export_to_host(const Export &e, unsigned *seq_dev, unsigned seq, hipStream_
 // and then so that a failed launch or a device error ends the wait.
 void wait_host_seq(const unsigned *seq_host, unsigned seq, hipStream_t s);
 
+// --- learned proposal network (hd_mlp.hip) --------------------------------
+hd_status mlp_forward(const float *X, int64_t n, const float *params, float *y, hipStream_t s);
+
 // --- primitives (hd_prims.hip) -------------------------------------------
 // Exclusive scan of n int32 values; total in *d_total (device, may be null).
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,

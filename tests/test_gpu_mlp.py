@@ -140,3 +140,60 @@ def test_training_fits_a_teacher():
     # the device's trained weights evaluated by the oracle give the same loss
     y_or, _ = mlp.forward(X[ntrain:].astype(np.float64), P.cpu().numpy().astype(np.float64), emulate_bf16=True)
     assert np.mean((y_or - t[ntrain:]) ** 2) == pytest.approx(loss1, rel=1e-2)
+
+
+# ----------------------------------------------------------------------------
+# features of frontier triangles
+# ----------------------------------------------------------------------------
+
+def _oracle_feature_inputs(VB, FB, tris):
+    import oracle
+    n = tris.shape[0]
+    P = tris.reshape(-1, 3)
+    d, I = oracle.points_soup(P, VB, FB)
+    q = np.array([oracle.closest_point(x, *VB[FB[f]])[1] for x, f in zip(P, I)])
+    d, I, q = np.asarray(d).reshape(n, 3), np.asarray(I).reshape(n, 3), q.reshape(n, 3, 3)
+    e1 = VB[FB[:, 1]] - VB[FB[:, 0]]
+    e2 = VB[FB[:, 2]] - VB[FB[:, 0]]
+    nB = np.cross(e1, e2)
+    nB /= np.linalg.norm(nB, axis=1)[:, None]
+    nS = nB[I]
+    distinct = np.array([len(set(r)) for r in I])
+    shared = np.zeros(n)
+    for i, r in enumerate(I):
+        u = sorted(set(r))
+        if len(u) == 2:
+            shared[i] = 1.0 if len(set(FB[u[0]]) & set(FB[u[1]])) >= 2 else 0.0
+    return d, I, q, nS, distinct, shared
+
+
+def test_features_match_oracle():
+    hd, torch = _hd()
+    from paper_2406_10357_amd import workloads as wl
+    W = wl.config(2, scale=0.05)
+    rng = np.random.default_rng(21)
+    # small triangles around points of A's surface, several sizes
+    base = W.VA[rng.integers(0, W.VA.shape[0], 600)]
+    size = np.exp(rng.uniform(np.log(1e-3), np.log(0.1), 600))[:, None, None]
+    tris = base[:, None, :] + size * rng.normal(size=(600, 3, 3))
+    d, I, q, nS, distinct, shared = _oracle_feature_inputs(W.VB, W.FB, tris)
+    L = float(np.median(d)) * 0.8
+    dA = 3.0
+    say("features of", tris.shape[0], "triangles;", int(shared.sum()), "with a shared edge")
+    bvh = hd.build_bvh(torch.from_numpy(W.VB).cuda(), torch.from_numpy(W.FB).cuda())
+    X = hd.frontier_features(tris.reshape(-1, 9), d, I, q.reshape(-1, 9), bvh, L, dA).cpu().numpy()
+    from oracle import mlp
+    F = mlp.features(tris, d, q, nS, distinct, shared, L, dA)
+    err = np.abs(X - F)
+    # FP32 arithmetic on centred coordinates: differences of vertices of size
+    # S carry errors of u*S, so a ratio or a direction over an edge l is off by
+    # about u*S/l; 16 of those plus a few ulps of the feature itself
+    S = np.abs(tris - 0.5 * (W.VB.min(0) + W.VB.max(0))).max()
+    ell = np.max(np.linalg.norm(tris - np.roll(tris, 1, axis=1), axis=2), axis=1)
+    u = 2.0 ** -24
+    tol = (16 * u * S / ell)[:, None] * (1 + np.abs(F)) + 8 * u * (1 + np.abs(F))
+    worst = np.unravel_index(np.argmax(err / tol), err.shape)
+    print("max err/tol", float(np.max(err / tol)), "at", worst, X[worst], F[worst])
+    assert np.array_equal(X[:, 9], F[:, 9]) and np.array_equal(X[:, 10], F[:, 10])
+    assert np.all(err <= tol)
+    assert shared.sum() > 0 and distinct.min() >= 1
