@@ -665,6 +665,7 @@ HD_D void write_record(const FrontierView<T> &fo, int64_t o, const Corner<T> cn[
     fo.face()[o] = face;
     fo.lvl()[o] = lvl;
     fo.pair()[o] = pair;
+    fo.score()[o] = __builtin_nanf("");
 }
 
 // Records waiting for stage B or C carry the index of the bound that gave
@@ -903,37 +904,74 @@ template <class T> HD_D Tri<T> record_tri(const FrontierView<T> &f, int64_t j) {
     return make_tri(cn);
 }
 
-// features of records 0..n-1 into rows of X (row stride `stride` floats)
-template <class T>
-__global__ void k_features_list(FrontierView<T> fr, int64_t n, LearnCfg lc, BView<T> bv, float *X, int stride) {
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    const int pair = fr.pair()[j];
-    float f[16];
-    tri_features(record_tri(fr, j), ord2d(lc.pv[pair].Lord), lc.pc[pair].dA, bv, lc.iv, f);
-    float *o = X + j * (int64_t)stride;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) o[k] = f[k];
-}
-
 // predicted maximum distance of a record: largest vertex distance plus the
 // network's output times the longest edge
-template <class T> HD_D float predicted_max(const FrontierView<T> &fr, int64_t j, float y) {
-    const Tri<T> t = record_tri(fr, j);
+template <class T> HD_D float predicted_max(const Tri<T> &t, float y) {
     const T ell = hmax(hsqrt(norm2(t.v[1] - t.v[0])), hmax(hsqrt(norm2(t.v[2] - t.v[1])), hsqrt(norm2(t.v[0] - t.v[2]))));
     const T dmax = hmax(t.d[0], hmax(t.d[1], t.d[2]));
     return (float)dmax + (float)ell * y;
 }
 
-// selection keys in learned order: descending predicted maximum distance,
-// ties by the same order-independent tag as the plain keys (a NaN prediction
-// falls back to the record's upper bound)
+// Network scores of a block of records: each thread's 16 features go to an
+// LDS tile, each wave runs the network on its 64 rows (four 16-row tiles on
+// the matrix cores), and the thread reads back its prediction. Every thread
+// of the block must call this.
+struct ScoreLds {
+    mlp::Weights W;
+    alignas(16) float X[BLK * 16];
+    alignas(16) unsigned short stage[NW][16 * 64];
+    float y[BLK];
+};
 template <class T>
-__global__ void k_sel_keys_learned(FrontierView<T> fr, int64_t n, const float *__restrict__ y,
-                                   unsigned long long *__restrict__ keys, int32_t *__restrict__ vals) {
+__device__ float score_block(ScoreLds &S, bool valid, const Tri<T> &t, double L, double dA, const BView<T> &bv,
+                             const IdView &iv) {
+    float f[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f[k] = 0.f;
+    if (valid) tri_features(t, L, dA, bv, iv, f);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) S.X[threadIdx.x * 16 + k] = f[k];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, l = __lane_id(), g = l >> 4, c = l & 15;
+    for (int q = 0; q < 4; ++q) {
+        mlp::Tile tl;
+        mlp::tile_forward(S.X + wave * 64 * 16, nullptr, 16 * q, 64, S.W, S.stage[wave], tl);
+        if (c == 0)
+            for (int j = 0; j < 4; ++j) S.y[wave * 64 + 16 * q + 4 * g + j] = tl.y[j];
+    }
+    __syncthreads();
+    return S.y[threadIdx.x];
+}
+
+// score records from..from+n-1 of a list (those the round appended)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_score(FrontierView<T> fr, int64_t from, int64_t n, LearnCfg lc, BView<T> bv,
+                                               const float *__restrict__ params) {
+    __shared__ ScoreLds S;
+    for (int i = threadIdx.x; i < mlp::NPARAM; i += BLK) mlp::set_param(S.W, i, params[i]);
+    const int64_t j = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = j < from + n;
+    Tri<T> t{};
+    double L = 0, dA = 1;
+    if (valid) {
+        t = record_tri(fr, j);
+        const int pair = fr.pair()[j];
+        L = ord2d(lc.pv[pair].Lord);
+        dA = lc.pc[pair].dA;
+    }
+    const float y = score_block(S, valid, t, L, dA, bv, lc.iv);
+    if (valid) fr.score()[j] = predicted_max(t, y);
+}
+
+// selection keys in learned order: descending stored prediction, ties by the
+// same order-independent tag as the plain keys (an unscored record, or a NaN
+// prediction, falls back to its upper bound)
+template <class T>
+__global__ void k_sel_keys_learned(FrontierView<T> fr, int64_t n, unsigned long long *__restrict__ keys,
+                                   int32_t *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float pm = predicted_max(fr, i, y[i]);
+    float pm = fr.score()[i];
     if (!(pm == pm)) pm = fr.ub()[i];
     uint32_t tag = point_tag(fr.face()[i], fr.lvl()[i], fr.ba(0)[i] ^ (fr.ba(1)[i] << 7) ^ (fr.ba(2)[i] << 14),
                              fr.bb(0)[i] ^ (fr.bb(1)[i] << 7) ^ (fr.bb(2)[i] << 14));
@@ -979,47 +1017,28 @@ __global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, Cla
                                                          Ctl *ctl, LearnCfg lc, const float *__restrict__ params) {
     const int64_t n = (int64_t)ctl->b_next;
     if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole block idle
-    __shared__ mlp::Weights W;
-    __shared__ alignas(16) float X[BLK * 16];
-    __shared__ alignas(16) unsigned short stage[NW][16 * 64];
-    __shared__ float yv[BLK];
-    for (int i = threadIdx.x; i < mlp::NPARAM; i += BLK) mlp::set_param(W, i, params[i]);
+    __shared__ ScoreLds S;
+    for (int i = threadIdx.x; i < mlp::NPARAM; i += BLK) mlp::set_param(S.W, i, params[i]);
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = j < n;
     int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
-    double carry = 0;
+    double carry = 0, L = 0, dA = 1;
     Corner<T> cn[3];
-    float f[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) f[k] = 0.f;
-    double L = 0;
+    Tri<T> t{};
     if (valid) {
         load_corners(in, j, cn);
         pair = in.pair()[j];
         face = in.face()[j];
         lvl = in.lvl()[j] & 0xff;
         L = ord2d(cc.pv[pair].Lord);
-        tri_features(make_tri(cn), L, lc.pc[pair].dA, bv, lc.iv, f);
+        dA = lc.pc[pair].dA;
+        t = make_tri(cn);
     }
-#pragma unroll
-    for (int k = 0; k < 16; ++k) X[threadIdx.x * 16 + k] = f[k];
-    __syncthreads();
-    {
-        const int wave = threadIdx.x >> 6, l = __lane_id(), g = l >> 4, c = l & 15;
-        for (int t = 0; t < 4; ++t) {
-            mlp::Tile tl;
-            mlp::tile_forward(X + wave * 64 * 16, nullptr, 16 * t, 64, W, stage[wave], tl);
-            if (c == 0)
-                for (int q = 0; q < 4; ++q) yv[wave * 64 + 16 * t + 4 * g + q] = tl.y[q];
-        }
-    }
-    __syncthreads();
+    const float y = score_block(S, valid, t, L, dA, bv, lc.iv);
     int skipped = 0;
     if (valid) {
-        const Tri<T> t = make_tri(cn);
         const T ell = hmax(hsqrt(norm2(t.v[1] - t.v[0])), hmax(hsqrt(norm2(t.v[2] - t.v[1])), hsqrt(norm2(t.v[0] - t.v[2]))));
-        const T dmax = hmax(t.d[0], hmax(t.d[1], t.d[2]));
-        const double pm = (double)dmax + (double)ell * (double)yv[threadIdx.x];
+        const double pm = (double)predicted_max(t, y);
         const double eps = cc.pc[pair].eps_abs;
         if (pm > L + eps + (double)POLICY_MARGIN * (double)ell) {
             // stage A's running minimum is already a valid bound
@@ -1060,6 +1079,7 @@ HD_D void copy_record(const FrontierView<T> &src, int64_t i, const FrontierView<
     dst.face()[o] = src.face()[i];
     dst.lvl()[o] = src.lvl()[i];
     dst.pair()[o] = src.pair()[i];
+    dst.score()[o] = src.score()[i];
 }
 
 // dst[o] = src[perm[o]] (perm null: src[off + o])
@@ -1257,7 +1277,6 @@ struct Workspace {
     PinnedBuf host; // mailbox, staged uploads, exported results
     unsigned mb_seq = 0;
     std::vector<hipEvent_t> evpool; // profiling events (kept until the process ends)
-    DBuf feat; // learned order: features and predictions of the active list
     DBuf ctl, pc, pv, params, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
     TypedWs<float> w32;
     TypedWs<double> w64;
@@ -1528,6 +1547,15 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     prof.mark(prof.c);
     Mailbox hm = report(nullptr);
     int64_t nAct = hm.act, nPark = hm.park;
+    // learned order: every record is scored once, when it joins the active
+    // list (only needed when sub-batches are selected)
+    const bool scoring = opt.learned > 0 && opt.subbatch > 0;
+    auto score_new = [&](int64_t from, int64_t to) {
+        if (!scoring || to <= from) return;
+        k_score<T><<<grid_for(to - from, BLK), BLK, 0, s>>>(tw.act.v, from, to - from, lc, bv, opt.mlp_params);
+        HD_LAUNCH_CHECK();
+    };
+    score_new(0, nAct);
 
     const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
     double processed = (double)nA;
@@ -1572,14 +1600,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             int32_t *vals = (int32_t *)(keys2 + nAct);
             int32_t *vals2 = vals + nAct;
             if (opt.learned > 0) {
-                // the network's predicted maximum distance orders the frontier
-                ws.feat.reserve((size_t)nAct * 16 * sizeof(float) + (size_t)nAct * sizeof(float) + 512);
-                float *X = ws.feat.as<float>();
-                float *y = X + ((nAct * 16 + 63) & ~int64_t(63));
-                k_features_list<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, lc, bv, X, 16);
-                HD_LAUNCH_CHECK();
-                mlp_forward(X, nAct, opt.mlp_params, y, s);
-                k_sel_keys_learned<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, y, keys, vals);
+                // the network's predicted maximum distance (scored when each
+                // record joined the active list) orders the frontier
+                k_sel_keys_learned<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, keys, vals);
             } else {
                 k_sel_keys<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, keys, vals);
             }
@@ -1637,6 +1660,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         swap_fb(tw.act, tw.act2);
         nAct = hm.act;
         nPark = hm.park;
+        score_new(rest, nAct);
         subdivided += K;
         processed += 4.0 * (double)K;
         ++rounds;

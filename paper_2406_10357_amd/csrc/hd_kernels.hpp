@@ -54,7 +54,7 @@ struct alignas(128) PairVar {
 // face (E1 = V1 - V0, E2 = V2 - V0), so positions never accumulate rounding.
 // ---------------------------------------------------------------------------
 // One allocation of `cap` records, field by field (structure of arrays): 21
-// fields of T, then 13 fields of 4 bytes. A view is a base and a capacity, so
+// fields of T, then 14 fields of 4 bytes. A view is a base and a capacity, so
 // choosing among several lists per lane costs a few registers, not a table of
 // pointers.
 template <class T> struct FrontierView {
@@ -71,7 +71,8 @@ template <class T> struct FrontierView {
     HD_HD int *pair() const { return i32(6); }
     HD_HD int *ba(int i) const { return i32(7 + i); } // dyadic barycentric numerators of vertex i
     HD_HD int *bb(int i) const { return i32(10 + i); }
-    static constexpr size_t bytes_per_record() { return 21 * sizeof(T) + 13 * 4; }
+    HD_HD float *score() const { return (float *)i32(13); } // learned proposal: predicted max distance (NaN: none)
+    static constexpr size_t bytes_per_record() { return 21 * sizeof(T) + 14 * 4; }
 };
 
 // A's vertices and faces (all pairs concatenated; face indices are global).
