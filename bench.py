@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--precision", default="fp32+recheck", choices=["fp64", "fp32", "fp32+recheck"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain comparison on the large torus")
+    ap.add_argument("--learned-subbatch", type=int, default=8192)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x4): the reference for the HBM "
                          "byte counters (FETCH_SIZE / WRITE_SIZE) of a rocprofv3 --pmc run")
@@ -124,6 +127,55 @@ def cpu_baseline_pairs(pairs, budget_s=15.0):
             break
     all_faces = sum(W.FA.shape[0] for W in pairs)
     return t_total * 1e3 * all_faces / faces, res, faces
+
+
+def learned_comparison(a, hd, torch, wl):
+    """Train the proposal network on the GPU from frontier logs of the plain
+    method (torus, thin strip at quarter size, 32 many-pair pairs), then time
+    plain and learned on the large torus (1M vs 800k triangles) with the same
+    sub-batched scheduler. Untimed by the step loop; reported beside it."""
+    from paper_2406_10357_amd import learned
+    K = a.learned_subbatch
+    W2, W3 = wl.config(2), wl.config(3, scale=0.25)
+    pairs = wl.batched_pairs(32, nmax=20000, workers=min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    rows = learned.log_frontier([(W2.VA, W2.FA, W2.VB, W2.FB, W2.eps_rel), (W3.VA, W3.FA, W3.VB, W3.FB, W3.eps_rel),
+                                 [(P.VA, P.FA, P.VB, P.FB, P.eps_rel) for P in pairs]], subbatch=K, cap=1 << 19)
+    t_log = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, losses, (vb, va) = learned.train(rows, epochs=6)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    W5 = wl.config(5)
+    VA, FA, VB, FB = (torch.from_numpy(x).cuda() for x in (W5.VA, W5.FA, W5.VB, W5.FB))
+    bvh = hd.build_bvh(VB, FB)
+    res = {0: [], 1: []}
+    for rep in range(3):
+        for mode in (0, 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L, U, st = hd.bound(VA, FA, bvh, W5.eps_rel, subbatch=K, learned=mode,
+                                mlp_params=params if mode else None)
+            res[mode].append(((time.perf_counter() - t0) * 1e3, L, U, st))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Lb, Ub, sb = hd.bound(VA, FA, bvh, W5.eps_rel)
+    bf_ms = (time.perf_counter() - t0) * 1e3
+
+    def summary(mode):
+        ms = statistics.median(r[0] for r in res[mode])
+        _, L, U, st = res[mode][-1]
+        return {"ms": round(ms, 3), "L": L, "U": U, "nodes_bounded": st["nodes_bounded"],
+                "subdivided": st["subdivided"], "rounds": st["rounds"], "queries": st["queries"]}
+
+    return {"workload": f"C5 torus 1000x500 ({W5.FA.shape[0]} F) vs periodic Delaunay 400k ({W5.FB.shape[0]} F), "
+                        "sigma 5e-4, eps 1e-5*dA, FP32+recheck", "subbatch": K,
+            "train": {"rows": int(rows.shape[0]), "log_s": round(t_log, 2), "train_s": round(t_train, 2),
+                      "steps": int(len(losses)), "heldout_mse_before": vb, "heldout_mse_after": va,
+                      "label_variance": float(rows[:, 16].var())},
+            "plain": summary(0), "learned": summary(1),
+            "plain_breadth_first": {"ms": round(bf_ms, 3), "nodes_bounded": sb["nodes_bounded"], "rounds": sb["rounds"]},
+            "timing": "hd_bound only (BVH prebuilt), median of 3"}
 
 
 def main():
@@ -246,6 +298,11 @@ def main():
             "fp32_frac_of_157_3": (tflops / PEAK_FP32_VECTOR) if tflops else None,
         },
     }
+    if not a.no_learned and not batched:
+        print("learned vs plain on the large torus ...", file=sys.stderr, flush=True)
+        lc = learned_comparison(a, hd, torch, wl)
+        out["learned"] = lc
+        out["learned_ms"] = lc["learned"]["ms"]
     if not a.no_cpu_baseline and batched:
         print("timing the CPU oracle on a sample of the pairs ...", file=sys.stderr, flush=True)
         cms, refs, faces = cpu_baseline_pairs(pairs)
