@@ -41,6 +41,8 @@ constexpr int DEEP_STACK = 256;
 constexpr int DEEP_SLOTS = 4096; // concurrent deep traversals
 constexpr int BLK = 256;
 constexpr int NW = BLK / 64;
+constexpr unsigned GRID_MAX = 2048;  // persistent cap of grid-stride launches (8 blocks per CU)
+constexpr unsigned QGRID_MAX = 4096; // the same for the query kernel's smaller blocks
 
 // Device control block. The append counters, the cascade statistics and the
 // query statistics sit on separate 128-byte lines: atomics on one line do not
@@ -54,7 +56,24 @@ struct Ctl {
     unsigned long long discards[5];
     alignas(128) unsigned long long queries, boxes, q_leaves;
     unsigned long long skips; // records whose u3 / u4 the learned policy skipped
+    // device-planned rounds (written by k_plan, read by the round's kernels)
+    alignas(128) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
+    unsigned long long subdivided, rounds;             // totals over the planned rounds
+    double processed;                                  // faces processed (the paper's budget count)
+    int stall;                                         // 1: capacity left no room to split
+    int over_budget;                                   // 1: the next split would exceed the budget
 };
+
+// Item count of a launch: a host value, or (device-planned rounds) a count
+// the device wrote, times a multiplicity. Kernels that take one loop over it
+// with a grid stride, so their grid need not match it.
+struct DevCount {
+    const unsigned long long *p;
+    int64_t mult;
+    int64_t host_n;
+    HD_D int64_t get() const { return p ? (int64_t)(*p) * mult : host_n; }
+};
+inline DevCount host_count(int64_t n) { return DevCount{nullptr, 1, n}; }
 
 struct PairSrcA {
     const double *V;
@@ -144,20 +163,73 @@ __global__ void k_ctl_init(Ctl *c) { memset(c, 0, sizeof(Ctl)); }
 // What the host needs between rounds, written by the device into pinned host
 // memory; `seq` last, after a system-scope fence, so that a host that sees
 // the new seq sees the fields too.
-struct Mailbox {
-    long long act, park, nref;
-    int bad;
+// Reports go to a ring of MB_SLOTS slots (slot seq % MB_SLOTS), so that a
+// report may be in flight while the host reads the previous one.
+constexpr int MB_SLOTS = 4;
+struct alignas(64) Mailbox {
+    int64_t act, park, nref, rounds, subdivided;
+    int bad, stall, over_budget;
     unsigned seq;
 };
 
-__global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *mb, unsigned seq) {
+__global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *ring, unsigned seq) {
     if (threadIdx.x != 0) return;
+    Mailbox *mb = ring + seq % MB_SLOTS;
     mb->act = (long long)ctl->act_next;
     mb->park = (long long)ctl->park_next;
     mb->nref = nref ? *nref : 0;
+    mb->rounds = (long long)ctl->rounds;
+    mb->subdivided = (long long)ctl->subdivided;
     mb->bad = ctl->bad;
+    mb->stall = ctl->stall;
+    mb->over_budget = ctl->over_budget;
     __threadfence_system();
     __hip_atomic_store(&mb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Device-planned round: how many active records to split (all of them,
+// capped by the list capacities and the face budget) and the per-round
+// counters. A round planned with nothing to do leaves everything in place.
+struct PlanCaps {
+    int64_t act, park, pend, mq; // capacities (records / queries)
+    double budget;               // the paper's m * nA
+};
+__global__ void k_plan(Ctl *c, PlanCaps caps) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t nAct = (int64_t)c->act_next, nPark = (int64_t)c->park_next;
+    int64_t K = 0;
+    if (!c->bad && !c->stall && !c->over_budget && nAct > 0) {
+        K = nAct;
+        K = K < (caps.act - nAct) / 3 ? K : (caps.act - nAct) / 3;
+        K = K < (caps.park - nPark) / 4 ? K : (caps.park - nPark) / 4;
+        K = K < caps.pend / 4 ? K : caps.pend / 4;
+        K = K < caps.mq / 3 ? K : caps.mq / 3;
+        if (K <= 0) {
+            K = 0;
+            c->stall = 1;
+        } else if (c->processed + 4.0 * (double)K > caps.budget) {
+            K = 0;
+            c->over_budget = 1;
+        }
+    }
+    c->plan_K = (unsigned long long)K;
+    c->plan_rest = (unsigned long long)(nAct - K);
+    c->processed += 4.0 * (double)K;
+    c->subdivided += (unsigned long long)K;
+    if (K > 0) c->rounds += 1;
+    c->act_next = (unsigned long long)(nAct - K);
+    c->park_next = (unsigned long long)nPark;
+    c->b_next = 0;
+    c->c_next = 0;
+    c->n_overflow = 0;
+}
+
+// a planned round's carried-over records: act[K .. K + rest) -> act2[0 .. rest)
+template <class T>
+__global__ void k_gather_planned(FrontierView<T> src, FrontierView<T> dst, const Ctl *ctl);
+
+__global__ void k_clear_stall(Ctl *c) {
+    if (threadIdx.x == 0) c->stall = 0;
 }
 
 __global__ void k_round_setup(Ctl *c, unsigned long long act_base, unsigned long long park_base) {
@@ -407,33 +479,37 @@ HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResul
 }
 
 template <class T, int SD>
-__global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, int64_t n, QueryCfg cfg, BView<T> bv,
+__global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
                                                   QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
                                                   Ctl *ctl, int32_t *ovf_list) {
     __shared__ int s_node[SD * QBLOCK];
     __shared__ float s_dist[SD * QBLOCK];
-    int64_t i = (int64_t)blockIdx.x * QBLOCK + threadIdx.x;
-    unsigned long long nb = 0, nl = 0, nq = 0, lord = 0, key = 0;
-    int pair = 0;
-    if (i < n) {
-        QPoint qp = query_point(in, i);
-        pair = qp.pair;
-        V3<T> p = cvt<T>(qp.p);
-        QueryResult<T> r = empty_result<T>();
-        seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
-        LdsStack<SD, QBLOCK> stk{s_node, s_dist, 0};
-        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
-        nb = r.nbox;
-        nl = r.nleaf;
-        nq = 1;
-        if (r.overflow) {
-            int k = atomicAdd(&ctl->n_overflow, 1);
-            ovf_list[k] = (int32_t)i;
-        } else {
-            finish_query<T>(cfg, bv, r, qp, p, out, pc, &lord, &key);
+    const int64_t n = cnt.get();
+    unsigned long long nb = 0, nl = 0, nq = 0;
+    for (int64_t base = (int64_t)blockIdx.x * QBLOCK; base < n; base += (int64_t)gridDim.x * QBLOCK) {
+        const int64_t i = base + threadIdx.x;
+        unsigned long long lord = 0, key = 0;
+        int pair = 0;
+        if (i < n) {
+            QPoint qp = query_point(in, i);
+            pair = qp.pair;
+            V3<T> p = cvt<T>(qp.p);
+            QueryResult<T> r = empty_result<T>();
+            seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
+            LdsStack<SD, QBLOCK> stk{s_node, s_dist, 0};
+            r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
+            nb += r.nbox;
+            nl += r.nleaf;
+            nq += 1;
+            if (r.overflow) {
+                int k = atomicAdd(&ctl->n_overflow, 1);
+                ovf_list[k] = (int32_t)i;
+            } else {
+                finish_query<T>(cfg, bv, r, qp, p, out, pc, &lord, &key);
+            }
         }
+        pair_max2(pv, pair, lord, key);
     }
-    pair_max2(pv, pair, lord, key);
     block_add<3, QBLOCK>({nb, nl, nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
 }
 
@@ -472,21 +548,22 @@ __global__ __launch_bounds__(64) void k_query_deep(QueryIn<T> in, QueryCfg cfg, 
 // after a query round: the query holding its pair's best key records its
 // exact position (keys are unique up to a tag collision of one point)
 template <class T>
-__global__ void k_argmax_finalize(QueryIn<T> in, int64_t n, const unsigned long long *__restrict__ keys,
+__global__ void k_argmax_finalize(QueryIn<T> in, DevCount cnt, const unsigned long long *__restrict__ keys,
                                   const int *__restrict__ tri, PairVar *pv) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
-    unsigned long long key = keys[o];
-    if (key == 0) return;
-    QPoint qp = query_point(in, i);
-    PairVar &P = pv[qp.pair];
-    if (key == P.round_key && key > P.best_key) {
-        P.argmax_pos[0] = qp.p.x;
-        P.argmax_pos[1] = qp.p.y;
-        P.argmax_pos[2] = qp.p.z;
-        P.argmax_tri = tri[o];
-        P.argmax_dirty = 1;
+    const int64_t n = cnt.get();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
+        unsigned long long key = keys[o];
+        if (key == 0) continue;
+        QPoint qp = query_point(in, i);
+        PairVar &P = pv[qp.pair];
+        if (key == P.round_key && key > P.best_key) {
+            P.argmax_pos[0] = qp.p.x;
+            P.argmax_pos[1] = qp.p.y;
+            P.argmax_pos[2] = qp.p.z;
+            P.argmax_tri = tri[o];
+            P.argmax_dirty = 1;
+        }
     }
 }
 
@@ -776,9 +853,11 @@ __global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__res
 // round k: child c of selected parent c/4, from the parent's record and the
 // three midpoint query results (midpoint e joins parent vertices e and e+1)
 template <class T>
-__global__ __launch_bounds__(BLK) void k_children(int64_t nsel, FrontierView<T> par, QueryOut<T> mq,
+__global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T> par, QueryOut<T> mq,
                                                   ClassifyCfg cc, Dest<T> dst, Ctl *ctl) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nsel = nselc.get();
+    for (int64_t cbase = (int64_t)blockIdx.x * BLK; cbase < 4 * nsel; cbase += (int64_t)gridDim.x * BLK) {
+    const int64_t c = cbase + threadIdx.x;
     bool valid = c < 4 * nsel;
     int list = TO_DISCARD, decider = 0, pair = 0, face = 0, lvl = 0;
     double carry = 0;
@@ -834,59 +913,62 @@ __global__ __launch_bounds__(BLK) void k_children(int64_t nsel, FrontierView<T> 
     if (valid)
         write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
     tally(ctl, list, decider, 0, 0, valid, true);
+    }
 }
 
 // stage B over the records stage A left undecided (count in ctl->b_next;
-// the grid covers an upper bound of it)
+// grid-stride)
 template <class T>
 __global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg cc, BView<T> bv, Dest<T> dst,
                                                  Ctl *ctl) {
     const int64_t n = (int64_t)ctl->b_next;
-    if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole block idle
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = j < n;
-    int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
-    double carry = 0;
-    Corner<T> cn[3];
-    if (valid) {
-        load_corners(in, j, cn);
-        pair = in.pair()[j];
-        face = in.face()[j];
-        lvl = in.lvl()[j] & 0xff;
-        list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+    for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
+        const int64_t j = base + threadIdx.x;
+        const bool valid = j < n;
+        int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
+        double carry = 0;
+        Corner<T> cn[3];
+        if (valid) {
+            load_corners(in, j, cn);
+            pair = in.pair()[j];
+            face = in.face()[j];
+            lvl = in.lvl()[j] & 0xff;
+            list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+        }
+        int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+        if (valid)
+            write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
+        tally(ctl, list, decider, evals, 0, valid, false);
     }
-    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
-    if (valid)
-        write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
-    tally(ctl, list, decider, evals, 0, valid, false);
 }
 
 // stage C: FP64 re-bound of the recheck band (count in ctl->c_next)
 template <class T>
 __global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg cc, Dest<T> dst, Ctl *ctl) {
     const int64_t n = (int64_t)ctl->c_next;
-    if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole block idle
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = j < n;
-    int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
-    double ub = 0;
-    Corner<T> cn[3];
-    if (valid) {
-        load_corners(in, j, cn);
-        pair = in.pair()[j];
-        face = in.face()[j];
-        lvl = in.lvl()[j] & 0xff;
-        decider = in.lvl()[j] >> 8;
-        const PairConst &P = cc.pc[pair];
-        int ba[3] = {cn[0].ba, cn[1].ba, cn[2].ba}, bb[3] = {cn[0].bb, cn[1].bb, cn[2].bb};
-        int I[3] = {cn[0].I, cn[1].I, cn[2].I};
-        double u64 = rebound64(cc.a, pair, face, lvl, ba, bb, I, cc.bv64, cc.iv, cc.c, P.m64, &evals);
-        ub = hmin((double)in.ub()[j], u64);
-        list = decide(ub, ord2d(cc.pv[pair].Lord), P.eps_abs, 0.0, false);
+    for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
+        const int64_t j = base + threadIdx.x;
+        const bool valid = j < n;
+        int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
+        double ub = 0;
+        Corner<T> cn[3];
+        if (valid) {
+            load_corners(in, j, cn);
+            pair = in.pair()[j];
+            face = in.face()[j];
+            lvl = in.lvl()[j] & 0xff;
+            decider = in.lvl()[j] >> 8;
+            const PairConst &P = cc.pc[pair];
+            int ba[3] = {cn[0].ba, cn[1].ba, cn[2].ba}, bb[3] = {cn[0].bb, cn[1].bb, cn[2].bb};
+            int I[3] = {cn[0].I, cn[1].I, cn[2].I};
+            double u64 = rebound64(cc.a, pair, face, lvl, ba, bb, I, cc.bv64, cc.iv, cc.c, P.m64, &evals);
+            ub = hmin((double)in.ub()[j], u64);
+            list = decide(ub, ord2d(cc.pv[pair].Lord), P.eps_abs, 0.0, false);
+        }
+        int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+        if (valid) write_to(dst, list, slot, cn, round_up_to_float(ub), face, lvl, pair);
+        tally(ctl, list, decider, evals, 1, valid, false);
     }
-    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
-    if (valid) write_to(dst, list, slot, cn, round_up_to_float(ub), face, lvl, pair);
-    tally(ctl, list, decider, evals, 1, valid, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -1016,46 +1098,49 @@ template <class T>
 __global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, ClassifyCfg cc, BView<T> bv, Dest<T> dst,
                                                          Ctl *ctl, LearnCfg lc, const float *__restrict__ params) {
     const int64_t n = (int64_t)ctl->b_next;
-    if ((int64_t)blockIdx.x * blockDim.x >= n) return; // whole block idle
+    if ((int64_t)blockIdx.x * BLK >= n) return; // no work for this block
     __shared__ ScoreLds S;
     for (int i = threadIdx.x; i < mlp::NPARAM; i += BLK) mlp::set_param(S.W, i, params[i]);
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = j < n;
-    int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
-    double carry = 0, L = 0, dA = 1;
-    Corner<T> cn[3];
-    Tri<T> t{};
-    if (valid) {
-        load_corners(in, j, cn);
-        pair = in.pair()[j];
-        face = in.face()[j];
-        lvl = in.lvl()[j] & 0xff;
-        L = ord2d(cc.pv[pair].Lord);
-        dA = lc.pc[pair].dA;
-        t = make_tri(cn);
-    }
-    const float y = score_block(S, valid, t, L, dA, bv, lc.iv);
-    int skipped = 0;
-    if (valid) {
-        const T ell = hmax(hsqrt(norm2(t.v[1] - t.v[0])), hmax(hsqrt(norm2(t.v[2] - t.v[1])), hsqrt(norm2(t.v[0] - t.v[2]))));
-        const double pm = (double)predicted_max(t, y);
-        const double eps = cc.pc[pair].eps_abs;
-        if (pm > L + eps + (double)POLICY_MARGIN * (double)ell) {
-            // stage A's running minimum is already a valid bound
-            const double mu = tri_margin(t, margins_of<T>(cc.pc[pair]));
-            carry = (double)in.ub()[j];
-            decider = in.lvl()[j] >> 8;
-            list = decide(carry, L, eps, mu, cc.recheck);
-            skipped = 1;
-        } else {
-            list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+    for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
+        const int64_t j = base + threadIdx.x;
+        const bool valid = j < n;
+        int list = TO_DISCARD, decider = 0, evals = 0, pair = 0, face = 0, lvl = 0;
+        double carry = 0, L = 0, dA = 1;
+        Corner<T> cn[3];
+        Tri<T> t{};
+        if (valid) {
+            load_corners(in, j, cn);
+            pair = in.pair()[j];
+            face = in.face()[j];
+            lvl = in.lvl()[j] & 0xff;
+            L = ord2d(cc.pv[pair].Lord);
+            dA = lc.pc[pair].dA;
+            t = make_tri(cn);
         }
+        const float y = score_block(S, valid, t, L, dA, bv, lc.iv);
+        int skipped = 0;
+        if (valid) {
+            const T ell = hmax(hsqrt(norm2(t.v[1] - t.v[0])),
+                               hmax(hsqrt(norm2(t.v[2] - t.v[1])), hsqrt(norm2(t.v[0] - t.v[2]))));
+            const double pm = (double)predicted_max(t, y);
+            const double eps = cc.pc[pair].eps_abs;
+            if (pm > L + eps + (double)POLICY_MARGIN * (double)ell) {
+                // stage A's running minimum is already a valid bound
+                const double mu = tri_margin(t, margins_of<T>(cc.pc[pair]));
+                carry = (double)in.ub()[j];
+                decider = in.lvl()[j] >> 8;
+                list = decide(carry, L, eps, mu, cc.recheck);
+                skipped = 1;
+            } else {
+                list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+            }
+        }
+        int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
+        if (valid)
+            write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
+        tally(ctl, list, decider, evals, 0, valid, false);
+        block_add<1, BLK>({(unsigned long long)skipped}, {&ctl->skips});
     }
-    int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
-    if (valid)
-        write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
-    tally(ctl, list, decider, evals, 0, valid, false);
-    block_add<1, BLK>({(unsigned long long)skipped}, {&ctl->skips});
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,6 +1173,13 @@ __global__ void k_gather(FrontierView<T> src, const int32_t *__restrict__ perm, 
                          FrontierView<T> dst) {
     int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o < n) copy_record(src, perm ? perm[o] : off + o, dst, o);
+}
+
+template <class T>
+__global__ void k_gather_planned(FrontierView<T> src, FrontierView<T> dst, const Ctl *ctl) {
+    const int64_t off = (int64_t)ctl->plan_K, n = (int64_t)ctl->plan_rest;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x)
+        copy_record(src, off + o, dst, o);
 }
 
 // selection keys: descending upper bound, ties by an order-independent tag
@@ -1389,9 +1481,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     prof.pool = &ws.evpool;
 
     // ---- small tables -----------------------------------------------------
-    // Pinned host block: [0, 64) mailbox, [64, 68) export sequence word,
-    // then the packed upload (pair sources, face and vertex offsets, eps) and
-    // the result area (control block, pair tables). The upload goes to the
+    // Pinned host block: [0, 256) the report ring, [256, 260) the export
+    // sequence word, then the packed upload (pair sources, face and vertex
+    // offsets, eps) and the result area (control block, pair tables). The upload goes to the
     // device in one asynchronous copy; results come back through one export.
     ws.ctl.reserve(sizeof(Ctl));
     Ctl *ctl = ws.ctl.as<Ctl>();
@@ -1399,26 +1491,27 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const int neps = in.eps_per_pair ? np : 1;
     const size_t o_src = 0, o_foff = o_src + al(np * sizeof(PairSrcA)), o_voff = o_foff + al((np + 1) * 8),
                  o_eps = o_voff + al((np + 1) * 8), up_bytes = o_eps + al(neps * 8);
-    const size_t o_up = 256, o_res = o_up + up_bytes;
+    static_assert(MB_SLOTS * sizeof(Mailbox) <= 256, "report ring fits its area");
+    const size_t o_up = 512, o_res = o_up + up_bytes;
     const size_t o_rctl = 0, o_rpv = al(sizeof(Ctl)), o_rpc = o_rpv + al(np * sizeof(PairVar)),
                  res_bytes = o_rpc + al(np * sizeof(PairConst));
     ws.host.reserve(o_res + res_bytes);
     Mailbox *mb = ws.host.as<Mailbox>(), *mb_dev = ws.host.dev_as<Mailbox>();
     // Enqueue a report and wait for it by polling the pinned mailbox: far
     // lower latency than a stream synchronisation plus a staged copy.
-    auto report = [&](const int32_t *nref) -> Mailbox {
+    auto report_async = [&](const int32_t *nref) -> unsigned {
         const unsigned seq = ++ws.mb_seq;
         k_report<<<1, 64, 0, s>>>(ctl, nref, mb_dev, seq);
         HD_LAUNCH_CHECK();
-        wait_host_seq(&mb->seq, seq, s);
-        Mailbox m;
-        m.act = mb->act;
-        m.park = mb->park;
-        m.nref = mb->nref;
-        m.bad = mb->bad;
-        m.seq = seq;
+        return seq;
+    };
+    auto wait_report = [&](unsigned seq) -> Mailbox {
+        const Mailbox *slot = mb + seq % MB_SLOTS;
+        wait_host_seq(&slot->seq, seq, s);
+        Mailbox m = *slot;
         return m;
     };
+    auto report = [&](const int32_t *nref) -> Mailbox { return wait_report(report_async(nref)); };
     ws.pc.reserve(np * sizeof(PairConst));
     ws.pv.reserve(np * sizeof(PairVar));
     PairConst *pc = ws.pc.as<PairConst>();
@@ -1473,21 +1566,23 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     ws.deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
     const bool small_stack = opt.stack_depth > 0 && opt.stack_depth < QSTACK;
 
-    auto run_queries = [&](const QueryIn<T> &qi, int64_t n, const QueryOut<T> &out) {
-        if (n <= 0) return;
-        ws.ovf.reserve((size_t)n * sizeof(int32_t));
+    // queries: n_max bounds the count (host count, or the device-planned one),
+    // the grid covers it up to a persistent cap and loops beyond
+    auto run_queries = [&](const QueryIn<T> &qi, DevCount cnt, int64_t n_max, const QueryOut<T> &out) {
+        if (n_max <= 0) return;
+        ws.ovf.reserve((size_t)n_max * sizeof(int32_t));
+        const unsigned gq = std::min<unsigned>(grid_for(n_max, QBLOCK), QGRID_MAX);
         prof.mark(prof.q);
         if (small_stack)
-            k_query<T, SMALL_STACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pc, pv, ctl,
-                                                                            ws.ovf.as<int32_t>());
+            k_query<T, SMALL_STACK><<<gq, QBLOCK, 0, s>>>(qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>());
         else
-            k_query<T, QSTACK><<<grid_for(n, QBLOCK), QBLOCK, 0, s>>>(qi, n, qcfg, bv, out, pc, pv, ctl,
-                                                                       ws.ovf.as<int32_t>());
+            k_query<T, QSTACK><<<gq, QBLOCK, 0, s>>>(qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>());
         HD_LAUNCH_CHECK();
         prof.mark(prof.q);
         k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                         ws.deep.as<int2>());
-        k_argmax_finalize<T><<<grid_for(n, BLK), BLK, 0, s>>>(qi, n, out.key, out.I, pv);
+        k_argmax_finalize<T><<<std::min<unsigned>(grid_for(n_max, BLK), GRID_MAX), BLK, 0, s>>>(qi, cnt, out.key,
+                                                                                               out.I, pv);
         k_L64<<<grid_for(np, 64), 64, 0, s>>>(B->nodes.as<WideNode>(), bv64, iv.ids, pc, pv, np,
                                                ws.gstack.as<int2>());
         HD_LAUNCH_CHECK();
@@ -1504,7 +1599,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.a = av;
         qi.pc = pc;
         k_round_setup<<<1, 1, 0, s>>>(ctl, 0, 0);
-        run_queries(qi, nref, tw.vq.o);
+        run_queries(qi, host_count(nref), nref, tw.vq.o);
     }
 
     // ---- frontier buffers ---------------------------------------------------
@@ -1528,11 +1623,12 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const LearnCfg lc{pc, pv, iv};
     auto later_stages = [&](int64_t n, const FrontierView<T> &act_out) {
         Dest<T> d{act_out, tw.park.v, tw.pend_b.v, tw.pend_c.v};
+        const unsigned g = std::min<unsigned>(grid_for(n, BLK), GRID_MAX);
         if (opt.learned == 2)
-            k_stage_b_learned<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params);
+            k_stage_b_learned<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params);
         else
-            k_stage_b<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
-        if (cc.recheck) k_stage_c<T><<<grid_for(n, BLK), BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl);
+            k_stage_b<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
+        if (cc.recheck) k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl);
         HD_LAUNCH_CHECK();
     };
 
@@ -1545,8 +1641,109 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     HD_LAUNCH_CHECK();
     later_stages(nA, tw.act.v);
     prof.mark(prof.c);
-    Mailbox hm = report(nullptr);
-    int64_t nAct = hm.act, nPark = hm.park;
+    const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
+    double processed = (double)nA;
+    int64_t subdivided = 0, logged = 0, nAct = 0, nPark = 0;
+    int rounds = 0;
+    hd_status status = HD_OK;
+    Mailbox hm{};
+    // Without sub-batches or the frontier log every round splits all active
+    // triangles, so the device plans each round itself and the host enqueues
+    // one round ahead of the report it waits for: the GPU never idles between
+    // rounds. The host-driven loop below handles the other modes.
+    const bool planned = opt.subbatch <= 0 && !opt.log_frontier;
+    if (planned) {
+        auto size_round = [&]() {
+            const int64_t c = std::min(tw.act.cap, tw.act2.cap);
+            tw.mq.ensure(c);
+            tw.pend_b.ensure(c, 0, s);
+            if (cc.recheck) tw.pend_c.ensure(c, 0, s);
+        };
+        size_round();
+        auto caps = [&]() {
+            PlanCaps c;
+            c.act = std::min(tw.act.cap, tw.act2.cap);
+            c.park = tw.park.cap;
+            c.pend = cc.recheck ? std::min(tw.pend_b.cap, tw.pend_c.cap) : tw.pend_b.cap;
+            c.mq = tw.mq.cap;
+            c.budget = budget - (double)nA;
+            return c;
+        };
+        auto enqueue_round = [&]() {
+            const PlanCaps c = caps();
+            k_plan<<<1, 64, 0, s>>>(ctl, c);
+            QueryIn<T> qi{};
+            qi.mode = Q_MIDPOINTS;
+            qi.npairs = np;
+            qi.a = av;
+            qi.par = tw.act.v;
+            qi.pc = pc;
+            const int64_t kmax = std::min<int64_t>(c.mq / 3, c.act);
+            run_queries(qi, DevCount{&ctl->plan_K, 3, 0}, 3 * kmax, tw.mq.o);
+            k_gather_planned<T><<<std::min<unsigned>(grid_for(c.act, BLK), GRID_MAX), BLK, 0, s>>>(tw.act.v,
+                                                                                                   tw.act2.v, ctl);
+            prof.mark(prof.c);
+            k_children<T><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
+                DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
+                Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
+            HD_LAUNCH_CHECK();
+            later_stages(4 * kmax, tw.act2.v);
+            prof.mark(prof.c);
+            swap_fb(tw.act, tw.act2);
+        };
+        unsigned seq_prev = report_async(nullptr); // state after round 0
+        int enqueued = 0;
+        int64_t peak = 0;
+        while (true) {
+            const bool more = !(opt.max_rounds > 0 && enqueued >= opt.max_rounds);
+            unsigned seq_new = 0;
+            if (more) {
+                enqueue_round();
+                seq_new = report_async(nullptr);
+                ++enqueued;
+            }
+            hm = wait_report(seq_prev);
+            peak = std::max<int64_t>(peak, hm.act + hm.park);
+            if (!more) break;
+            const bool done = hm.act == 0 || hm.bad || hm.over_budget || hm.stall;
+            seq_prev = seq_new;
+            if (!done) continue;
+            // the round enqueued ahead found nothing to do (or stopped too)
+            hm = wait_report(seq_new);
+            peak = std::max<int64_t>(peak, hm.act + hm.park);
+            if (!(hm.stall && !hm.bad && !hm.over_budget && hm.act > 0)) break;
+            // out of list capacity: grow (the stalled rounds left the lists in
+            // place) and go on, or give up at the limit
+            const int64_t cur = std::min(tw.act.cap, tw.act2.cap);
+            if (cur >= cap_limit && tw.park.cap >= cap_limit) break;
+            const int64_t grow = std::min<int64_t>(cap_limit, std::max<int64_t>(2 * cur, 4 * hm.act));
+            try {
+                tw.act.ensure(grow, hm.act, s);
+                tw.act2.ensure(grow, 0, s);
+                tw.park.ensure(std::min<int64_t>(cap_limit, std::max<int64_t>(2 * tw.park.cap, hm.park + 4 * hm.act)), hm.park, s);
+                size_round();
+            } catch (const Error &e) {
+                if (e.st != HD_E_NOMEM) throw;
+                break;
+            }
+            k_clear_stall<<<1, 64, 0, s>>>(ctl);
+            seq_prev = report_async(nullptr);
+        }
+        nAct = hm.act;
+        nPark = hm.park;
+        rounds = (int)hm.rounds;
+        subdivided = hm.subdivided;
+        S.max_frontier = peak;
+        if (hm.bad == 3) status = HD_E_CAPACITY; // depth exhausted: tolerance below what the arithmetic resolves
+        else if (hm.bad) status = HD_E_INTERNAL;
+        else if (hm.over_budget || (hm.stall && hm.act > 0)) status = HD_E_CAPACITY;
+    } else {
+        hm = report(nullptr);
+        nAct = hm.act;
+        nPark = hm.park;
+        S.max_frontier = nAct + nPark;
+        if (hm.bad == 2) status = HD_E_INTERNAL;
+    }
     // learned order: every record is scored once, when it joins the active
     // list (only needed when sub-batches are selected)
     const bool scoring = opt.learned > 0 && opt.subbatch > 0;
@@ -1555,16 +1752,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         k_score<T><<<grid_for(to - from, BLK), BLK, 0, s>>>(tw.act.v, from, to - from, lc, bv, opt.mlp_params);
         HD_LAUNCH_CHECK();
     };
-    score_new(0, nAct);
+    if (!planned) score_new(0, nAct);
 
-    const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
-    double processed = (double)nA;
-    int64_t subdivided = 0, logged = 0;
-    int rounds = 0;
-    S.max_frontier = nAct + nPark;
-    hd_status status = HD_OK;
-    if (hm.bad == 2) status = HD_E_INTERNAL;
-    while (status == HD_OK && nAct > 0) {
+    while (!planned && status == HD_OK && nAct > 0) {
         if (opt.max_rounds > 0 && rounds >= opt.max_rounds) break;
         // how many to split this round, growing the lists when allowed
         int64_t K = nAct;
@@ -1626,7 +1816,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const QueryCfg lcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
-            k_query<T, QSTACK><<<grid_for(nq, QBLOCK), QBLOCK, 0, s>>>(li, nq, lcfg, bv, tw.lq.o, pc, pv, ctl,
+            k_query<T, QSTACK><<<std::min<unsigned>(grid_for(nq, QBLOCK), QGRID_MAX), QBLOCK, 0, s>>>(
+                li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl,
                                                                         ws.ovf.as<int32_t>());
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(li, lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                             ws.deep.as<int2>());
@@ -1644,13 +1835,14 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.a = av;
         qi.par = tw.act.v;
         qi.pc = pc;
-        run_queries(qi, 3 * K, tw.mq.o);
+        run_queries(qi, host_count(3 * K), 3 * K, tw.mq.o);
         // the unselected remainder first, then the active children
         if (rest > 0) k_gather<T><<<grid_for(rest, BLK), BLK, 0, s>>>(tw.act.v, nullptr, K, rest, tw.act2.v);
         tw.pend_b.ensure(4 * K, 0, s);
         if (cc.recheck) tw.pend_c.ensure(4 * K, 0, s);
         prof.mark(prof.c);
-        k_children<T><<<grid_for(4 * K, BLK), BLK, 0, s>>>(K, tw.act.v, tw.mq.o, cc,
+        k_children<T><<<std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX), BLK, 0, s>>>(host_count(K), tw.act.v,
+                                                                                          tw.mq.o, cc,
                                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
                                                            ctl);
         HD_LAUNCH_CHECK();
@@ -1693,8 +1885,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         ex.dst[2] = ws.host.dev_as<char>(o_res + o_rpc);
         ex.bytes[2] = np * sizeof(PairConst);
         const unsigned seq = ++ws.mb_seq;
-        export_to_host(ex, ws.host.dev_as<unsigned>(64), seq, s);
-        wait_host_seq(ws.host.as<unsigned>(64), seq, s);
+        export_to_host(ex, ws.host.dev_as<unsigned>(256), seq, s);
+        wait_host_seq(ws.host.as<unsigned>(256), seq, s);
     }
     const Ctl &hc = *ws.host.as<Ctl>(o_res + o_rctl);
     const PairVar *hp = ws.host.as<PairVar>(o_res + o_rpv);
@@ -1904,7 +2096,8 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             BView<T> bv;
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
-            k_query<T, QSTACK><<<grid_for(nP, QBLOCK), QBLOCK, 0, s>>>(qi, nP, cfg, bv, qb.o, pc, pv, ctl,
+            k_query<T, QSTACK><<<std::min<unsigned>(grid_for(nP, QBLOCK), QGRID_MAX), QBLOCK, 0, s>>>(
+                qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
                                                                         ovf.as<int32_t>());
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(),
                                                             deep.as<int2>());
