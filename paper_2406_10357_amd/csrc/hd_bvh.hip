@@ -403,6 +403,8 @@ __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *
 // tile-internal nodes); climbs start at nodes with two such children, and the
 // thread that brings a parent's counter to 2 builds it and climbs on
 // (workgroup-scope atomics: all threads share one CU).
+constexpr int UPPER_LDS = 1536; // upper nodes the LDS climb holds (about 40 B each)
+
 __global__ __launch_bounds__(1024) void k_refit_upper(const int32_t *__restrict__ upper, const BuildState *st,
                                                       const int32_t *__restrict__ childL,
                                                       const int32_t *__restrict__ childR,
@@ -415,22 +417,98 @@ __global__ __launch_bounds__(1024) void k_refit_upper(const int32_t *__restrict_
         int2 r = range[c];
         return r.x / TILE == r.y / TILE ? 1 : 0;
     };
+    if (nup > UPPER_LDS) {
+        // too many for LDS: the same climb on global counters and boxes
+        for (int k = threadIdx.x; k < nup; k += blockDim.x) {
+            int32_t u = upper[k];
+            cnt[u] = complete(childL[u]) + complete(childR[u]);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nup; k += blockDim.x) {
+            int32_t x = upper[k];
+            if (complete(childL[x]) + complete(childR[x]) != 2) continue;
+            while (true) {
+                union_box(nbox, lbox, childL[x], childR[x], nbox + 2 * (int64_t)x);
+                int32_t p = parentN[x];
+                if (p < 0) break;
+                int old = __hip_atomic_fetch_add(&cnt[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (old + 1 < 2) break;
+                x = p;
+            }
+        }
+        return;
+    }
+    // The climb in LDS: slot k holds upper node upper[k]: its box (the union of
+    // its complete children first, then of all), its parent's slot, the slots
+    // of its upper children, and an arrival counter. cnt (global) maps a node
+    // to its slot.
+    __shared__ float blo[UPPER_LDS][3], bhi[UPPER_LDS][3];
+    __shared__ int par[UPPER_LDS], cs[UPPER_LDS][2], arr[UPPER_LDS];
+    for (int k = threadIdx.x; k < nup; k += blockDim.x) cnt[upper[k]] = k;
+    __threadfence_block();
+    __syncthreads();
     for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-        int32_t u = upper[k];
-        cnt[u] = complete(childL[u]) + complete(childR[u]);
+        const int32_t u = upper[k];
+        const int32_t p = parentN[u];
+        par[k] = p >= 0 ? cnt[p] : -1;
+        float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+        float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+        int c = 0;
+        const int32_t ch[2] = {childL[u], childR[u]};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (complete(ch[j])) {
+                float4 l, h;
+                load_box(nbox, lbox, ch[j], l, h);
+                lo[0] = fminf(lo[0], l.x);
+                lo[1] = fminf(lo[1], l.y);
+                lo[2] = fminf(lo[2], l.z);
+                hi[0] = fmaxf(hi[0], h.x);
+                hi[1] = fmaxf(hi[1], h.y);
+                hi[2] = fmaxf(hi[2], h.z);
+                cs[k][j] = -1;
+                ++c;
+            } else {
+                cs[k][j] = cnt[ch[j]];
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            blo[k][d] = lo[d];
+            bhi[k][d] = hi[d];
+        }
+        arr[k] = c;
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-        int32_t x = upper[k];
-        if (complete(childL[x]) + complete(childR[x]) != 2) continue;
+        // start at nodes whose children are both complete (a static test: the
+        // counters of other nodes are being raised meanwhile)
+        if (cs[k][0] >= 0 || cs[k][1] >= 0) continue;
+        int x = k;
         while (true) {
-            union_box(nbox, lbox, childL[x], childR[x], nbox + 2 * (int64_t)x);
-            int32_t p = parentN[x];
+            const int p = par[x];
             if (p < 0) break;
-            int old = __hip_atomic_fetch_add(&cnt[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // the second child to arrive completes the parent
+            int old = __hip_atomic_fetch_add(&arr[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old + 1 < 2) break;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c = cs[p][j];
+                if (c < 0) continue;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    blo[p][d] = fminf(blo[p][d], blo[c][d]);
+                    bhi[p][d] = fmaxf(bhi[p][d], bhi[c][d]);
+                }
+            }
             x = p;
         }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nup; k += blockDim.x) {
+        float4 *o = nbox + 2 * (int64_t)upper[k];
+        o[0] = make_float4(blo[k][0], blo[k][1], blo[k][2], 0.f);
+        o[1] = make_float4(bhi[k][0], bhi[k][1], bhi[k][2], 0.f);
     }
 }
 

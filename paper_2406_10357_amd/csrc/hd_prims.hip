@@ -85,6 +85,26 @@ __global__ void k_scan_down(const int32_t *__restrict__ in, int32_t *__restrict_
 
 __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
+// Exclusive scan of a short array (n <= SMALL_SCAN_MAX) in one block: each
+// thread sums a contiguous chunk, the chunk sums are scanned in LDS, and each
+// thread writes its chunk's prefixes. One launch instead of three.
+constexpr int64_t SMALL_SCAN_MAX = 1 << 16;
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_small(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                           int64_t n, int32_t *d_total) {
+    const int64_t chunk = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const int64_t b = (int64_t)threadIdx.x * chunk, e = b + chunk < n ? b + chunk : n;
+    int sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += in[i];
+    int tot;
+    int run = block_exclusive_scan(sum, &tot);
+    for (int64_t i = b; i < e; ++i) {
+        const int v = in[i];
+        out[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0 && d_total) *d_total = tot;
+}
+
 // ---------------------------------------------------------------------------
 // radix sort: 8-bit digits, one tile of RS_BLOCK * RS_ITEMS keys per block
 // ---------------------------------------------------------------------------
@@ -176,9 +196,13 @@ void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
         k_radix_hist<K><<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, hist);
-        k_scan_reduce<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, hn, part);
-        k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, scan_parts, nullptr);
-        k_scan_down<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, offs, hn, part);
+        if (hn <= SMALL_SCAN_MAX / 4) {
+            k_scan_small<<<1, SCAN_BLOCK, 0, s>>>(hist, offs, hn, nullptr);
+        } else {
+            k_scan_reduce<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, hn, part);
+            k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, scan_parts, nullptr);
+            k_scan_down<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, offs, hn, part);
+        }
         k_radix_scatter<K><<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, offs);
         HD_LAUNCH_CHECK();
         std::swap(ka, kb);
@@ -229,6 +253,11 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_t
                         hipStream_t s) {
     if (n <= 0) {
         if (d_total) k_zero_i32<<<1, 1, 0, s>>>(d_total);
+        return;
+    }
+    if (n <= SMALL_SCAN_MAX / 4) {
+        k_scan_small<<<1, SCAN_BLOCK, 0, s>>>(in, out, n, d_total);
+        HD_LAUNCH_CHECK();
         return;
     }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
