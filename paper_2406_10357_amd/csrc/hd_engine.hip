@@ -42,7 +42,13 @@ constexpr int DEEP_SLOTS = 4096; // concurrent deep traversals
 constexpr int BLK = 256;
 constexpr int NW = BLK / 64;
 constexpr unsigned GRID_MAX = 2048;  // persistent cap of grid-stride launches (8 blocks per CU)
+constexpr unsigned XCDS = 8;         // accelerator complex dies, each with its own L2
 constexpr unsigned QGRID_MAX = 4096; // the same for the query kernel's smaller blocks
+// grid of a query launch for up to n queries: a multiple of XCDS, capped
+inline unsigned qgrid(int64_t n) {
+    const unsigned g = (unsigned)std::min<int64_t>((n + QBLOCK - 1) / QBLOCK, QGRID_MAX);
+    return std::max<unsigned>((g + XCDS - 1) / XCDS * XCDS, XCDS);
+}
 
 // Device control block. The append counters, the cascade statistics and the
 // query statistics sit on separate 128-byte lines: atomics on one line do not
@@ -486,7 +492,18 @@ __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, DevCount cnt, Q
     __shared__ float s_dist[SD * QBLOCK];
     const int64_t n = cnt.get();
     unsigned long long nb = 0, nl = 0, nq = 0;
-    for (int64_t base = (int64_t)blockIdx.x * QBLOCK; base < n; base += (int64_t)gridDim.x * QBLOCK) {
+    // XCD-aware order: the hardware deals consecutive blocks to the eight
+    // XCDs in turn; number them so that each XCD gets a contiguous run of
+    // queries (nearby points, shared BVH paths, hits in that XCD's L2)
+    // (XCD x takes tiles [x*per, (x+1)*per); a grid that is not a multiple of
+    // XCDS takes them in plain order)
+    const int64_t ntiles = (n + QBLOCK - 1) / QBLOCK;
+    const bool swz = gridDim.x % XCDS == 0;
+    const unsigned xs = swz ? XCDS : 1;
+    const int64_t per = (ntiles + xs - 1) / xs;
+    const unsigned x = blockIdx.x % xs, gx = gridDim.x / xs;
+    for (int64_t tt = blockIdx.x / xs; tt < per && x * per + tt < ntiles; tt += gx) {
+        const int64_t base = (x * per + tt) * QBLOCK;
         const int64_t i = base + threadIdx.x;
         unsigned long long lord = 0, key = 0;
         int pair = 0;
@@ -1571,7 +1588,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     auto run_queries = [&](const QueryIn<T> &qi, DevCount cnt, int64_t n_max, const QueryOut<T> &out) {
         if (n_max <= 0) return;
         ws.ovf.reserve((size_t)n_max * sizeof(int32_t));
-        const unsigned gq = std::min<unsigned>(grid_for(n_max, QBLOCK), QGRID_MAX);
+        const unsigned gq = qgrid(n_max);
         prof.mark(prof.q);
         if (small_stack)
             k_query<T, SMALL_STACK><<<gq, QBLOCK, 0, s>>>(qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>());
@@ -1816,7 +1833,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const QueryCfg lcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
-            k_query<T, QSTACK><<<std::min<unsigned>(grid_for(nq, QBLOCK), QGRID_MAX), QBLOCK, 0, s>>>(
+            k_query<T, QSTACK><<<qgrid(nq), QBLOCK, 0, s>>>(
                 li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl,
                                                                         ws.ovf.as<int32_t>());
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(li, lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
@@ -2096,7 +2113,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             BView<T> bv;
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
-            k_query<T, QSTACK><<<std::min<unsigned>(grid_for(nP, QBLOCK), QGRID_MAX), QBLOCK, 0, s>>>(
+            k_query<T, QSTACK><<<qgrid(nP), QBLOCK, 0, s>>>(
                 qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
                                                                         ovf.as<int32_t>());
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(),
