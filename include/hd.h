@@ -74,6 +74,11 @@ typedef struct {
                                   barycentric lattice of d(p, B) - max vertex distance) /
                                   longest edge; rows of parents deeper than level 28 are NaN */
     int64_t log_cap;
+    int32_t autotune;          /* 1: on the first call on a device (per arithmetic), time the
+                                  query kernel's launch shapes (block size, LDS stack depth) on
+                                  this call's vertex queries and keep the fastest for later
+                                  calls; 2: retune on this call; 0: use the kept choice */
+    int32_t pad0;
 } hd_options;
 
 typedef struct {
@@ -101,6 +106,8 @@ typedef struct {
     int64_t query_box_tests;   /* box tests inside the query kernels */
     int64_t logged;            /* log_frontier: rows written to log_out (<= log_cap) */
     int64_t learned_skips;     /* learned = 2: triangles whose u3 and u4 were skipped */
+    int32_t query_block;       /* launch shape of this call's query kernel: block size */
+    int32_t query_stack;       /* and LDS stack entries per lane */
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle

@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("capacity", C.c_int64), ("max_rounds", C.c_int32), ("stack_depth", C.c_int32),
                 ("subbatch", C.c_int32), ("profile", C.c_int32), ("learned", C.c_int32),
                 ("log_frontier", C.c_int32), ("mlp_params", C.c_void_p), ("log_out", C.c_void_p),
-                ("log_cap", C.c_int64)]
+                ("log_cap", C.c_int64), ("autotune", C.c_int32), ("pad0", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -50,7 +50,8 @@ class Stats(C.Structure):
                 ("ms_query_kernels", C.c_double), ("ms_cascade_kernels", C.c_double),
                 ("query_launches", C.c_int64), ("cascade_launches", C.c_int64),
                 ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64),
-                ("logged", C.c_int64), ("learned_skips", C.c_int64)]
+                ("logged", C.c_int64), ("learned_skips", C.c_int64), ("query_block", C.c_int32),
+                ("query_stack", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -161,7 +162,8 @@ def build_bvh(VB, FB) -> Bvh:
 
 
 def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
-                 stack_depth=0, subbatch=0, profile=0, learned=0, mlp_params=None, log_out=None) -> Options:
+                 stack_depth=0, subbatch=0, profile=0, learned=0, mlp_params=None, log_out=None,
+                 autotune=0) -> Options:
     """mlp_params: device FP32 tensor of mlp_nparams() values (learned > 0);
     log_out: device FP32 tensor (rows, 17) that receives the frontier log."""
     o = Options()
@@ -170,6 +172,7 @@ def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity
     o.capacity, o.max_rounds, o.stack_depth, o.subbatch = capacity, max_rounds, stack_depth, subbatch
     o.profile = profile
     o.learned = learned
+    o.autotune = autotune
     if mlp_params is not None:
         o.mlp_params = mlp_params.data_ptr()
     if log_out is not None:

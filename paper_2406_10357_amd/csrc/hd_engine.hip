@@ -44,11 +44,6 @@ constexpr int NW = BLK / 64;
 constexpr unsigned GRID_MAX = 2048;  // persistent cap of grid-stride launches (8 blocks per CU)
 constexpr unsigned XCDS = 8;         // accelerator complex dies, each with its own L2
 constexpr unsigned QGRID_MAX = 4096; // the same for the query kernel's smaller blocks
-// grid of a query launch for up to n queries: a multiple of XCDS, capped
-inline unsigned qgrid(int64_t n) {
-    const unsigned g = (unsigned)std::min<int64_t>((n + QBLOCK - 1) / QBLOCK, QGRID_MAX);
-    return std::max<unsigned>((g + XCDS - 1) / XCDS * XCDS, XCDS);
-}
 
 // Device control block. The append counters, the cascade statistics and the
 // query statistics sit on separate 128-byte lines: atomics on one line do not
@@ -484,12 +479,12 @@ HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResul
     }
 }
 
-template <class T, int SD>
-__global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
-                                                  QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
-                                                  Ctl *ctl, int32_t *ovf_list) {
-    __shared__ int s_node[SD * QBLOCK];
-    __shared__ float s_dist[SD * QBLOCK];
+template <class T, int SD, int QB>
+__global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
+                                              QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
+                                              Ctl *ctl, int32_t *ovf_list) {
+    __shared__ int s_node[SD * QB];
+    __shared__ float s_dist[SD * QB];
     const int64_t n = cnt.get();
     unsigned long long nb = 0, nl = 0, nq = 0;
     // XCD-aware order: the hardware deals consecutive blocks to the eight
@@ -497,13 +492,13 @@ __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, DevCount cnt, Q
     // queries (nearby points, shared BVH paths, hits in that XCD's L2)
     // (XCD x takes tiles [x*per, (x+1)*per); a grid that is not a multiple of
     // XCDS takes them in plain order)
-    const int64_t ntiles = (n + QBLOCK - 1) / QBLOCK;
+    const int64_t ntiles = (n + QB - 1) / QB;
     const bool swz = gridDim.x % XCDS == 0;
     const unsigned xs = swz ? XCDS : 1;
     const int64_t per = (ntiles + xs - 1) / xs;
     const unsigned x = blockIdx.x % xs, gx = gridDim.x / xs;
     for (int64_t tt = blockIdx.x / xs; tt < per && x * per + tt < ntiles; tt += gx) {
-        const int64_t base = (x * per + tt) * QBLOCK;
+        const int64_t base = (x * per + tt) * QB;
         const int64_t i = base + threadIdx.x;
         unsigned long long lord = 0, key = 0;
         int pair = 0;
@@ -513,7 +508,7 @@ __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, DevCount cnt, Q
             V3<T> p = cvt<T>(qp.p);
             QueryResult<T> r = empty_result<T>();
             seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
-            LdsStack<SD, QBLOCK> stk{s_node, s_dist, 0};
+            LdsStack<SD, QB> stk{s_node, s_dist, 0};
             r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
             nb += r.nbox;
             nl += r.nleaf;
@@ -527,7 +522,7 @@ __global__ __launch_bounds__(QBLOCK) void k_query(QueryIn<T> in, DevCount cnt, Q
         }
         pair_max2(pv, pair, lord, key);
     }
-    block_add<3, QBLOCK>({nb, nl, nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
+    block_add<3, QB>({nb, nl, nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
 }
 
 // queries whose LDS stack overflowed, redone with a deep stack in global
@@ -560,6 +555,45 @@ __global__ __launch_bounds__(64) void k_query_deep(QueryIn<T> in, QueryCfg cfg, 
     }
     wave_add(&ctl->boxes, nb);
     wave_add(&ctl->q_leaves, nl);
+}
+
+// Launch shapes of the query kernel (LDS stack entries per lane, block size)
+// that the autotuner chooses from; entry 0 is the default.
+struct QVariant {
+    int sd, qb;
+};
+constexpr QVariant QVARIANTS[] = {{16, 128}, {8, 64}, {16, 64}, {32, 128}, {8, 256}, {16, 256}};
+constexpr int NQVAR = sizeof(QVARIANTS) / sizeof(QVARIANTS[0]);
+
+// grid of a query launch of block size qb for up to n queries: a multiple of
+// XCDS, capped at a persistent size
+inline unsigned qgrid_b(int64_t n, int qb) {
+    const unsigned g = (unsigned)std::min<int64_t>((n + qb - 1) / qb, (int64_t)QGRID_MAX * 128 / qb);
+    return std::max<unsigned>((g + XCDS - 1) / XCDS * XCDS, XCDS);
+}
+
+// variant v (-1: the tiny-stack test hook) for up to n_max queries
+template <class T>
+void launch_query(int v, int64_t n_max, const QueryIn<T> &qi, DevCount cnt, const QueryCfg &cfg, const BView<T> &bv,
+                  const QueryOut<T> &out, const PairConst *pc, PairVar *pv, Ctl *ctl, int32_t *ovf, hipStream_t s) {
+#define HD_QLAUNCH(SD, QB) k_query<T, SD, QB><<<qgrid_b(n_max, QB), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf)
+    switch (v) {
+    case -1: HD_QLAUNCH(SMALL_STACK, 128); break;
+    case 1: HD_QLAUNCH(8, 64); break;
+    case 2: HD_QLAUNCH(16, 64); break;
+    case 3: HD_QLAUNCH(32, 128); break;
+    case 4: HD_QLAUNCH(8, 256); break;
+    case 5: HD_QLAUNCH(16, 256); break;
+    default: HD_QLAUNCH(16, 128); break;
+    }
+#undef HD_QLAUNCH
+    HD_LAUNCH_CHECK();
+}
+
+__global__ void k_zero_query_stats(Ctl *c) {
+    if (threadIdx.x != 0) return;
+    c->queries = c->boxes = c->q_leaves = 0;
+    c->n_overflow = 0;
 }
 
 // after a query round: the query holding its pair's best key records its
@@ -1386,6 +1420,9 @@ struct Workspace {
     PinnedBuf host; // mailbox, staged uploads, exported results
     unsigned mb_seq = 0;
     std::vector<hipEvent_t> evpool; // profiling events (kept until the process ends)
+    int qvar[2] = {0, 0};           // query launch shape per arithmetic (FP32, FP64)
+    bool tuned[2] = {false, false};
+    hipEvent_t tune_ev[2] = {nullptr, nullptr};
     DBuf ctl, pc, pv, params, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
     TypedWs<float> w32;
     TypedWs<double> w64;
@@ -1582,19 +1619,16 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     ws.gstack.reserve((size_t)np * DEEP_STACK * sizeof(int2));
     ws.deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
     const bool small_stack = opt.stack_depth > 0 && opt.stack_depth < QSTACK;
+    int &qvar = ws.qvar[sizeof(T) == 4 ? 0 : 1];
+    if (qvar < 0 || qvar >= NQVAR) qvar = 0;
 
     // queries: n_max bounds the count (host count, or the device-planned one),
     // the grid covers it up to a persistent cap and loops beyond
     auto run_queries = [&](const QueryIn<T> &qi, DevCount cnt, int64_t n_max, const QueryOut<T> &out) {
         if (n_max <= 0) return;
         ws.ovf.reserve((size_t)n_max * sizeof(int32_t));
-        const unsigned gq = qgrid(n_max);
         prof.mark(prof.q);
-        if (small_stack)
-            k_query<T, SMALL_STACK><<<gq, QBLOCK, 0, s>>>(qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>());
-        else
-            k_query<T, QSTACK><<<gq, QBLOCK, 0, s>>>(qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>());
-        HD_LAUNCH_CHECK();
+        launch_query<T>(small_stack ? -1 : qvar, n_max, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(), s);
         prof.mark(prof.q);
         k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                         ws.deep.as<int2>());
@@ -1605,8 +1639,51 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
     };
 
-    // ---- round 0: vertex queries ------------------------------------------
+    // ---- autotuner: the query kernel's launch shape -------------------------
+    // Times every variant on this call's vertex queries (no effect on L: the
+    // trial queries do not raise it) and keeps the fastest for this device and
+    // arithmetic; later calls reuse the choice.
     tw.vq.ensure(mA);
+    if ((opt.autotune == 1 && !ws.tuned[sizeof(T) == 4 ? 0 : 1]) || opt.autotune == 2) {
+        QueryIn<T> qi{};
+        qi.mode = Q_VERTICES;
+        qi.npairs = np;
+        qi.vids = ws.vids.as<int32_t>();
+        qi.voff = dvoff;
+        qi.a = av;
+        qi.pc = pc;
+        const QueryCfg tcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
+        ws.ovf.reserve((size_t)nref * sizeof(int32_t));
+        if (ws.tune_ev[0] == nullptr)
+            for (auto &e : ws.tune_ev) HD_HIP(hipEventCreate(&e));
+        float best = 0;
+        int pick = 0;
+        for (int v = 0; v < NQVAR; ++v) {
+            float t = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
+                HD_HIP(hipEventRecord(ws.tune_ev[0], s));
+                launch_query<T>(v, nref, qi, host_count(nref), tcfg, bv, tw.vq.o, pc, pv, ctl,
+                                ws.ovf.as<int32_t>(), s);
+                HD_HIP(hipEventRecord(ws.tune_ev[1], s));
+                HD_HIP(hipEventSynchronize(ws.tune_ev[1]));
+                float ms = 0;
+                HD_HIP(hipEventElapsedTime(&ms, ws.tune_ev[0], ws.tune_ev[1]));
+                t = std::min(t, ms);
+            }
+            if (v == 0 || t < best) {
+                best = t;
+                pick = v;
+            }
+        }
+        k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
+        qvar = pick;
+        ws.tuned[sizeof(T) == 4 ? 0 : 1] = true;
+    }
+    S.query_block = small_stack ? 128 : QVARIANTS[qvar].qb;
+    S.query_stack = small_stack ? SMALL_STACK : QVARIANTS[qvar].sd;
+
+    // ---- round 0: vertex queries ------------------------------------------
     {
         QueryIn<T> qi{};
         qi.mode = Q_VERTICES;
@@ -1833,9 +1910,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const QueryCfg lcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
-            k_query<T, QSTACK><<<qgrid(nq), QBLOCK, 0, s>>>(
-                li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl,
-                                                                        ws.ovf.as<int32_t>());
+            launch_query<T>(qvar, nq, li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(), s);
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(li, lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                             ws.deep.as<int2>());
             k_log_parents<T><<<grid_for(K, BLK), BLK, 0, s>>>(tw.act.v, K, tw.lq.o, lc, bv, opt.log_out, logged,
@@ -2113,9 +2188,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             BView<T> bv;
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
-            k_query<T, QSTACK><<<qgrid(nP), QBLOCK, 0, s>>>(
-                qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
-                                                                        ovf.as<int32_t>());
+            launch_query<T>(0, nP, qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(), s);
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(),
                                                             deep.as<int2>());
             k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q);

@@ -382,3 +382,22 @@ def test_cascade_order_invariance_on_gpu():
         key = (L, U, st["subdivided"], st["nodes_bounded"])
         ref = ref or key
         assert key == ref
+
+
+def test_autotuned_launch_shape_gives_the_same_result():
+    """The autotuner only changes the query kernel's launch shape: the result
+    and every count stay the same."""
+    hd, torch = _hd()
+    W = wl.config(2, scale=0.1)
+    say("autotune on config2 scale 0.1")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    L0, U0, s0 = hd.bound(*args)
+    L1, U1, s1 = hd.bound(*args, autotune=2)
+    L2, U2, s2 = hd.bound(*args)
+    print("tuned shape: block", s1["query_block"], "stack", s1["query_stack"])
+    assert (s1["query_block"], s1["query_stack"]) in [(128, 16), (64, 8), (64, 16), (128, 32), (256, 8), (256, 16)]
+    assert (s2["query_block"], s2["query_stack"]) == (s1["query_block"], s1["query_stack"])
+    for k in ("subdivided", "nodes_bounded", "queries", "rounds", "pt_tri_evals"):
+        assert s0[k] == s1[k] == s2[k], k
+    assert (L0, U0) == (L1, U1) == (L2, U2)
