@@ -84,15 +84,19 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(config):
+def measured_traffic(config, tuned):
+    """HBM bytes per launch of the query kernel in the launch shape the timed
+    steps used, or None when not measured for these sources and workload."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("config") != config or t.get("source_sha256") != kernel_source_hash():
+    if t.get("config") != config or t.get("source_sha256") != kernel_source_hash() or not tuned:
         return None
-    return t.get("hbm_bytes_per_launch")
+    name = f"k_query<float, {tuned['query_stack']}, {tuned['query_block']}>"
+    v = t.get("per_variant", {}).get(name)
+    return v.get("hbm_bytes_per_launch") if v else None
 
 
 def cpu_baseline(W, reps=3):
@@ -288,13 +292,14 @@ def main():
         "autotuned": tuned,
         "learned_ms": None,
         "roofline": {
-            "kernel": "k_query<float> (four-wide LBVH traversal + point-triangle distances)",
+            "kernel": (f"k_query<float, {tuned['query_stack']}, {tuned['query_block']}>" if tuned else "k_query<float>")
+                      + " (four-wide LBVH traversal + point-triangle distances)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM,
             "unit": "GB/s",
             "frac": (achieved / PEAK_HBM) if achieved else None,
-            "traffic": measured_traffic(a.config),
+            "traffic": measured_traffic(a.config, tuned),
             "launches": q_launch,
             "avg_launch_ms": q_ms / q_launch if q_launch else None,
             "algorithmic_bytes_per_launch": nbytes / q_launch if q_launch else None,
