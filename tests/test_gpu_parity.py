@@ -401,3 +401,67 @@ def test_autotuned_launch_shape_gives_the_same_result():
     for k in ("subdivided", "nodes_bounded", "queries", "rounds", "pt_tri_evals"):
         assert s0[k] == s1[k] == s2[k], k
     assert (L0, U0) == (L1, U1) == (L2, U2)
+
+
+def _random_soup(rng, n, spread=1.0):
+    V = rng.normal(size=(3 * n, 3)) * spread
+    F = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    return V, F
+
+
+@pytest.mark.parametrize("seed,nA", [(0, 1), (1, 2), (2, 17), (3, 40), (4, 50)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32+recheck"])
+def test_random_tiny_soups(seed, nA, prec):
+    """Ragged tiny soups: random triangles A, and B small random triangles
+    around each vertex of A, so that the maximum lies inside A's triangles
+    and the rounds must subdivide (the dense-sampling pin of the oracle covers
+    the same kind of input)."""
+    hd, torch = _hd()
+    rng = np.random.default_rng([77, seed])
+    VA, FA = _random_soup(rng, nA)
+    VB = np.concatenate([v + rng.normal(0, 0.08, size=(3, 3)) for v in VA])
+    FB = np.arange(VB.shape[0], dtype=np.int32).reshape(-1, 3)
+    eps = 1e-4
+    ref = oracle.bound(VA, FA, VB, FB, eps)
+    p = {"fp64": hd.PREC_FP64, "fp32+recheck": hd.PREC_FP32_RECHECK}[prec]
+    say("random soups", seed, nA, FB.shape[0], prec)
+    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+    L, U, st = hd.bound(_cu(VA, torch), _cu(FA, torch), bvh, eps, precision=p)
+    _check_against_oracle(L, U, st, ref, f"random {seed} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32+recheck"])
+def test_degenerate_triangles(prec):
+    """Zero-area triangles on both sides (repeated and collinear vertices),
+    point and segment triangles in B, unreferenced vertices in both."""
+    hd, torch = _hd()
+    rng = np.random.default_rng(5)
+    V, F = wl.icosphere(1)
+    VA = np.concatenate([V, rng.normal(size=(5, 3)) * 3])  # 5 unreferenced vertices
+    FA = np.concatenate([F, [[0, 0, 1], [2, 3, 3], [4, 4, 4]]]).astype(np.int32)
+    # a collinear triangle: midpoint of an edge
+    VA = np.concatenate([VA, [(V[5] + V[6]) / 2]])
+    FA = np.concatenate([FA, [[5, 6, VA.shape[0] - 1]]]).astype(np.int32)
+    VB = V * 1.05 + rng.normal(0, 0.01, size=V.shape)
+    VB = np.concatenate([VB, rng.normal(size=(4, 3)) * 10])  # unreferenced
+    FB = np.concatenate([F, [[0, 0, 0], [1, 1, 2], [3, 4, 3]]]).astype(np.int32)
+    eps = 1e-3
+    ref = oracle.bound(VA, FA, VB, FB, eps)
+    p = {"fp64": hd.PREC_FP64, "fp32+recheck": hd.PREC_FP32_RECHECK}[prec]
+    say("degenerate triangles", prec)
+    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+    L, U, st = hd.bound(_cu(VA, torch), _cu(FA, torch), bvh, eps, precision=p)
+    _check_against_oracle(L, U, st, ref, f"degenerate {prec}")
+
+
+def test_translation_closed_form():
+    """A planar soup against its translate along the normal: h = |t|."""
+    hd, torch = _hd()
+    rng = np.random.default_rng(6)
+    V, F = _grid_soup(10, rng, amp=0.0)
+    t = 0.123
+    say("translation closed form")
+    bvh = hd.build_bvh(_cu(V + np.array([0, 0, t]), torch), _cu(F, torch))
+    for prec in (hd.PREC_FP64, hd.PREC_FP32_RECHECK):
+        L, U, st = hd.bound(_cu(V, torch), _cu(F, torch), bvh, 1e-6, precision=prec)
+        assert L <= t + 1e-12 <= U + 2e-12 and U - L <= st["eps_abs"] * (1 + 1e-12)
