@@ -43,7 +43,6 @@ __device__ __forceinline__ float round_up_f(double x) {
 
 struct PairAcc { // per-pair accumulators, ordered-double bits
     unsigned long long bbox[6];
-    unsigned long long cbox[6];
     unsigned long long coord_max, edge_max;
 };
 
@@ -64,8 +63,6 @@ __global__ void k_init(PairAcc *acc, int npairs, BuildState *st) {
     for (int k = 0; k < 3; ++k) {
         acc[p].bbox[k] = d2ord(__builtin_inf());
         acc[p].bbox[3 + k] = d2ord(-__builtin_inf());
-        acc[p].cbox[k] = d2ord(__builtin_inf());
-        acc[p].cbox[3 + k] = d2ord(-__builtin_inf());
     }
     acc[p].coord_max = d2ord(0.0);
     acc[p].edge_max = d2ord(0.0);
@@ -153,40 +150,6 @@ __global__ void k_pair_centres(const PairAcc *acc, int npairs, BvhPair *pairs) {
     for (int k = 0; k < 3; ++k) pairs[p].ctr[k] = 0.5 * (ord2d(acc[p].bbox[k]) + ord2d(acc[p].bbox[3 + k]));
 }
 
-__global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs, int64_t n,
-                            const BvhPair *__restrict__ pairs, double *__restrict__ cen, int32_t *__restrict__ fpair,
-                            PairAcc *acc, const BuildState *st) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = f < n && !st->bad;
-    int p = pair_of(foff, npairs, f < n ? f : n - 1);
-    double c[3] = {0, 0, 0};
-    double m = 0;
-    double clo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
-    double chi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
-    if (valid) {
-        PairSrc ps = src[p];
-        int64_t lf = f - foff[p];
-        for (int j = 0; j < 3; ++j) {
-            int32_t v = ps.F[3 * lf + j];
-            for (int k = 0; k < 3; ++k) {
-                double x = ps.V[3 * (int64_t)v + k] - pairs[p].ctr[k];
-                c[k] += x;
-                m = fmax(m, fabs(x));
-            }
-        }
-        for (int k = 0; k < 3; ++k) {
-            c[k] /= 3.0;
-            cen[3 * f + k] = c[k];
-            clo[k] = chi[k] = c[k];
-        }
-    }
-    if (f < n) fpair[f] = p;
-    const double v[7] = {clo[0], clo[1], clo[2], chi[0], chi[1], chi[2], m};
-    block_pair_minmax<7, 0x78u, BLK>(p, valid, v, [&](int q, int k) {
-        return k < 6 ? &acc[q].cbox[k] : &acc[q].coord_max;
-    });
-}
-
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     x &= 0x3ffu;
     x = (x | (x << 16)) & 0x030000FFu;
@@ -196,23 +159,49 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     return x;
 }
 
-__global__ void k_morton(const double *__restrict__ cen, const int32_t *__restrict__ fpair, int64_t n,
-                         const PairAcc *acc, unsigned long long *__restrict__ keys, int32_t *__restrict__ vals) {
+// Centroid of each face (centred on its pair) and its key: the pair id above
+// a 30-bit Morton code of the centroid on a 1024^3 grid over the pair's vertex
+// box (centroids lie inside it). Also the pair's largest centred coordinate.
+// ncells: the internal-node count, whose refit counters start at zero here.
+__global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs, int64_t n,
+                            const BvhPair *__restrict__ pairs, int32_t *__restrict__ fpair, PairAcc *acc,
+                            const BuildState *st, unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
+                            int32_t *__restrict__ counters, int64_t ncells) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n) return;
-    int p = fpair[f];
-    uint32_t q[3];
-    for (int k = 0; k < 3; ++k) {
-        double lo = ord2d(acc[p].cbox[k]), hi = ord2d(acc[p].cbox[3 + k]);
-        double ext = hi - lo;
-        double t = ext > 0 ? (cen[3 * f + k] - lo) / ext : 0.5;
-        t = t == t ? t : 0.5;
-        int v = (int)(t * 1023.0);
-        q[k] = (uint32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
+    if (f < ncells) counters[f] = 0;
+    bool valid = f < n && !st->bad;
+    int p = pair_of(foff, npairs, f < n ? f : n - 1);
+    double m = 0;
+    if (valid) {
+        PairSrc ps = src[p];
+        int64_t lf = f - foff[p];
+        double c[3] = {0, 0, 0};
+        for (int j = 0; j < 3; ++j) {
+            int32_t v = ps.F[3 * lf + j];
+            for (int k = 0; k < 3; ++k) {
+                double x = ps.V[3 * (int64_t)v + k] - pairs[p].ctr[k];
+                c[k] += x;
+                m = fmax(m, fabs(x));
+            }
+        }
+        uint32_t q[3];
+        for (int k = 0; k < 3; ++k) {
+            const double lo = ord2d(acc[p].bbox[k]) - pairs[p].ctr[k], hi = ord2d(acc[p].bbox[3 + k]) - pairs[p].ctr[k];
+            const double ext = hi - lo;
+            double t = ext > 0 ? (c[k] / 3.0 - lo) / ext : 0.5;
+            t = t == t ? t : 0.5;
+            int v = (int)(t * 1023.0);
+            q[k] = (uint32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
+        }
+        keys[f] = ((unsigned long long)p << 32) | ((spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]));
+        vals[f] = (int32_t)f;
+    } else if (f < n) {
+        keys[f] = (unsigned long long)p << 32;
+        vals[f] = (int32_t)f;
     }
-    uint32_t mc = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-    keys[f] = ((unsigned long long)p << 32) | mc;
-    vals[f] = (int32_t)f;
+    if (f < n) fpair[f] = p;
+    const double v[1] = {m};
+    block_pair_minmax<1, 1u, BLK>(p, valid, v, [&](int q, int) { return &acc[q].coord_max; });
 }
 
 __device__ __forceinline__ int delta(const unsigned long long *__restrict__ keys, int64_t n, int64_t i, int64_t j) {
@@ -229,6 +218,7 @@ __global__ void k_karras(const unsigned long long *__restrict__ keys, int64_t n,
                          int2 *__restrict__ range, int32_t *__restrict__ upper, BuildState *st) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
+    if (i == 0) parentN[0] = -1; // the root (every other node is some node's child)
     int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
     int dmin = delta(keys, n, i, i - d);
     int64_t lmax = 2;
@@ -727,7 +717,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         };
         size_t o_state = take(sizeof(BuildState));
         size_t o_acc = take(npairs * sizeof(PairAcc));
-        size_t o_cen = take(n * 3 * sizeof(double));
         size_t o_fpair = take(n * sizeof(int32_t));
         size_t o_keys = take(n * sizeof(unsigned long long));
         size_t o_vals = take(n * sizeof(int32_t));
@@ -748,7 +737,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         char *base = sc.mem.as<char>();
         BuildState *st = (BuildState *)(base + o_state);
         PairAcc *acc = (PairAcc *)(base + o_acc);
-        double *cen = (double *)(base + o_cen);
         int32_t *fpair = (int32_t *)(base + o_fpair);
         unsigned long long *keys = (unsigned long long *)(base + o_keys);
         int32_t *vals = (int32_t *)(base + o_vals);
@@ -790,8 +778,8 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         k_init<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, st);
         k_faces_check<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, acc, st);
         k_pair_centres<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs);
-        k_centroids<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, dpairs, cen, fpair, acc, st);
-        k_morton<<<grid_for(n, BLK), BLK, 0, s>>>(cen, fpair, n, acc, keys, vals);
+        k_centroids<<<grid_for(std::max<int64_t>(n, ni), BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
+                                                                             acc, st, keys, vals, cnt, ni);
         HD_LAUNCH_CHECK();
         int pair_bits = 0;
         while ((1 << pair_bits) < npairs) ++pair_bits;
@@ -805,12 +793,9 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
                                                   b->frames64.as<double2>(), b->ids.as<int4>(), acc, st);
         HD_LAUNCH_CHECK();
         if (n > 1) {
-            k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(pn, ni, -1);
-            k_fill_i32<<<grid_for(n, BLK), BLK, 0, s>>>(pl, n, -1);
-            k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(cnt, ni, 0);
+
             k_karras<<<grid_for(ni, BLK), BLK, 0, s>>>(keys, n, cl, cr, pn, pl, range, upper, st);
             k_refit_tiles<<<grid_for(n, TILE), TILE, 0, s>>>(n, cl, cr, pn, pl, range, lbox, nbox, cnt);
-            k_fill_i32<<<grid_for(ni, BLK), BLK, 0, s>>>(cnt, ni, 0);
             k_refit_upper<<<1, 1024, 0, s>>>(upper, st, cl, cr, pn, range, lbox, nbox, cnt);
             k_pair_roots<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, range, dpairs, npairs, keys);
             k_wide_flags<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, pn, range, dpairs, npairs, keys, flag);
