@@ -84,6 +84,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def query_kernel_name(tuned, T="float"):
+    """The query kernel's name in rocprofv3 output for a launch shape."""
+    if not tuned:
+        return f"k_query<{T}>"
+    return f"k_query<{T}, {tuned['query_stack']}, {tuned['query_block']}>"
+
+
 def measured_traffic(config, tuned):
     """HBM bytes per launch of the query kernel in the launch shape the timed
     steps used, or None when not measured for these sources and workload."""
@@ -94,8 +101,7 @@ def measured_traffic(config, tuned):
         return None
     if t.get("config") != config or t.get("source_sha256") != kernel_source_hash() or not tuned:
         return None
-    name = f"k_query<float, {tuned['query_stack']}, {tuned['query_block']}>"
-    v = t.get("per_variant", {}).get(name)
+    v = t.get("per_variant", {}).get(query_kernel_name(tuned))
     return v.get("hbm_bytes_per_launch") if v else None
 
 
@@ -227,7 +233,7 @@ def main():
     tuned = None
     for i in range(a.warmup):
         r = step(autotune=1 if i == 0 else 0)
-        tuned = tuned or {"query_block": r[2]["query_block"], "query_stack": r[2]["query_stack"]}
+        tuned = tuned or {k: r[2][k] for k in ("query_block", "query_stack", "query_quad_max")}
         print(f"warmup {i + 1}/{a.warmup} done", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
@@ -292,8 +298,8 @@ def main():
         "autotuned": tuned,
         "learned_ms": None,
         "roofline": {
-            "kernel": (f"k_query<float, {tuned['query_stack']}, {tuned['query_block']}>" if tuned else "k_query<float>")
-                      + " (four-wide LBVH traversal + point-triangle distances)",
+            "kernel": query_kernel_name(tuned) + " (four-wide LBVH traversal + point-triangle distances; "
+                      "launches of at most query_quad_max queries run a quad of lanes per query)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM,

@@ -78,7 +78,10 @@ typedef struct {
                                   query kernel's launch shapes (block size, LDS stack depth) on
                                   this call's vertex queries and keep the fastest for later
                                   calls; 2: retune on this call; 0: use the kept choice */
-    int32_t pad0;
+    int32_t query_lanes;       /* lanes per point query: 0 automatic (a quad of four lanes per
+                                  query in query launches of at most 16384 queries, where one
+                                  lane per query leaves the GPU latency-bound; one lane above);
+                                  1 always one lane; 4 always a quad */
 } hd_options;
 
 typedef struct {
@@ -107,7 +110,10 @@ typedef struct {
     int64_t logged;            /* log_frontier: rows written to log_out (<= log_cap) */
     int64_t learned_skips;     /* learned = 2: triangles whose u3 and u4 were skipped */
     int32_t query_block;       /* launch shape of this call's query kernel: block size */
-    int32_t query_stack;       /* and LDS stack entries per lane */
+    int32_t query_stack;       /* and LDS stack entries per query */
+    int32_t query_lanes;       /* the call's query_lanes option */
+    int32_t query_quad_max;    /* launches of at most this many queries ran a quad per query
+                                  (0: none did; -1: all did) */
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle
@@ -160,9 +166,11 @@ hd_status hd_bound_batched(int32_t npairs, const double *const *VA, const int64_
  * doubles), closest face of B as its original index (device, nP int32) and
  * closest points (device, nP x 3 doubles; may be NULL). precision selects
  * FP64 or FP32 arithmetic (HD_PREC_FP32 and HD_PREC_FP32_RECHECK both mean
- * FP32 here). This is the per-vertex query of the Implementation section,
- * exposed for testing and reuse. */
-hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh B, int32_t precision,
+ * FP32 here). lanes (0 or 1: one lane per point; 4: a quad of lanes per
+ * point) selects the query kernel; the results do not depend on it. This is
+ * the per-vertex query of the Implementation section, exposed for testing
+ * and reuse. HD_E_INVALID for other values of lanes. */
+hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh B, int32_t precision, int32_t lanes,
                              double *d, int32_t *I, double *Q, hd_stream_t stream);
 
 /* All five bounds of n given triangles against B, for testing the bound

@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("capacity", C.c_int64), ("max_rounds", C.c_int32), ("stack_depth", C.c_int32),
                 ("subbatch", C.c_int32), ("profile", C.c_int32), ("learned", C.c_int32),
                 ("log_frontier", C.c_int32), ("mlp_params", C.c_void_p), ("log_out", C.c_void_p),
-                ("log_cap", C.c_int64), ("autotune", C.c_int32), ("pad0", C.c_int32)]
+                ("log_cap", C.c_int64), ("autotune", C.c_int32), ("query_lanes", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -51,7 +51,7 @@ class Stats(C.Structure):
                 ("query_launches", C.c_int64), ("cascade_launches", C.c_int64),
                 ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64),
                 ("logged", C.c_int64), ("learned_skips", C.c_int64), ("query_block", C.c_int32),
-                ("query_stack", C.c_int32)]
+                ("query_stack", C.c_int32), ("query_lanes", C.c_int32), ("query_quad_max", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,7 +89,7 @@ def load_library(path: str | None = None):
     lib.hd_bound_batched.argtypes = [i32, pp, C.POINTER(i64), pp, C.POINTER(i64), vp, C.POINTER(C.c_double),
                                      i32, C.POINTER(Options), vp, C.POINTER(C.c_double), C.POINTER(Stats)]
     lib.hd_point_distances.restype = i32
-    lib.hd_point_distances.argtypes = [vp, i64, vp, i32, vp, vp, vp, vp]
+    lib.hd_point_distances.argtypes = [vp, i64, vp, i32, i32, vp, vp, vp, vp]
     lib.hd_eval_bounds.restype = i32
     lib.hd_eval_bounds.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp]
     lib.hd_status_str.restype = C.c_char_p
@@ -163,7 +163,7 @@ def build_bvh(VB, FB) -> Bvh:
 
 def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
                  stack_depth=0, subbatch=0, profile=0, learned=0, mlp_params=None, log_out=None,
-                 autotune=0) -> Options:
+                 autotune=0, query_lanes=0) -> Options:
     """mlp_params: device FP32 tensor of mlp_nparams() values (learned > 0);
     log_out: device FP32 tensor (rows, 17) that receives the frontier log."""
     o = Options()
@@ -173,6 +173,7 @@ def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity
     o.profile = profile
     o.learned = learned
     o.autotune = autotune
+    o.query_lanes = query_lanes
     if mlp_params is not None:
         o.mlp_params = mlp_params.data_ptr()
     if log_out is not None:
@@ -241,8 +242,9 @@ def bound_batched(meshes, bvh: Bvh, eps, **opts):
     return [LU[2 * i] for i in range(n)], [LU[2 * i + 1] for i in range(n)], stats.as_dict()
 
 
-def point_distances(P, bvh: Bvh, precision=PREC_FP64):
-    """(d, I, Q) of points P against B: distance, original face index, closest point."""
+def point_distances(P, bvh: Bvh, precision=PREC_FP64, lanes=1):
+    """(d, I, Q) of points P against B: distance, original face index, closest point
+    (lanes: 1 or 4 lanes of a wave per point query)."""
     torch = _torch()
     lib = load_library()
     P = _dev(P, torch.float64)
@@ -250,7 +252,7 @@ def point_distances(P, bvh: Bvh, precision=PREC_FP64):
     d = torch.empty(n, dtype=torch.float64, device=P.device)
     I = torch.empty(n, dtype=torch.int32, device=P.device)
     Q = torch.empty((n, 3), dtype=torch.float64, device=P.device)
-    st = lib.hd_point_distances(C.c_void_p(P.data_ptr()), n, bvh.handle, precision, C.c_void_p(d.data_ptr()),
+    st = lib.hd_point_distances(C.c_void_p(P.data_ptr()), n, bvh.handle, precision, lanes, C.c_void_p(d.data_ptr()),
                                 C.c_void_p(I.data_ptr()), C.c_void_p(Q.data_ptr()), _stream())
     _check(st, "hd_point_distances")
     return d, I, Q

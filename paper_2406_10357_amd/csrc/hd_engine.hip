@@ -479,27 +479,43 @@ HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResul
     }
 }
 
-template <class T, int SD, int QB>
-__global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
-                                              QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
-                                              Ctl *ctl, int32_t *ovf_list) {
-    __shared__ int s_node[SD * QB];
-    __shared__ float s_dist[SD * QB];
-    const int64_t n = cnt.get();
+// The query kernel. A launch with many queries runs one lane per query: the
+// machine is full and each lane's traversal overlaps with the others. A
+// launch with few queries (at most quad_max) is bound by the latency of each
+// traversal's chain of dependent node loads; it runs a quad of lanes per
+// query instead (see traverse4), which shortens every step of the chain.
+// Both paths give each block a run of consecutive queries in the same
+// XCD-aware tile order and write the same results (the quad's lane 0 writes).
+struct QueryTally {
     unsigned long long nb = 0, nl = 0, nq = 0;
-    // XCD-aware order: the hardware deals consecutive blocks to the eight
-    // XCDs in turn; number them so that each XCD gets a contiguous run of
-    // queries (nearby points, shared BVH paths, hits in that XCD's L2)
-    // (XCD x takes tiles [x*per, (x+1)*per); a grid that is not a multiple of
-    // XCDS takes them in plain order)
-    const int64_t ntiles = (n + QB - 1) / QB;
-    const bool swz = gridDim.x % XCDS == 0;
-    const unsigned xs = swz ? XCDS : 1;
-    const int64_t per = (ntiles + xs - 1) / xs;
-    const unsigned x = blockIdx.x % xs, gx = gridDim.x / xs;
-    for (int64_t tt = blockIdx.x / xs; tt < per && x * per + tt < ntiles; tt += gx) {
-        const int64_t base = (x * per + tt) * QB;
-        const int64_t i = base + threadIdx.x;
+};
+
+// XCD-aware order: the hardware deals consecutive blocks to the eight XCDs in
+// turn; number the tiles so that each XCD takes a contiguous run of them
+// (nearby points, shared BVH paths, hits in that XCD's L2). A grid that is
+// not a multiple of XCDS takes them in plain order.
+struct TileOrder {
+    int64_t ntiles, per;
+    unsigned x, gx, first;
+    HD_D TileOrder(int64_t n, int tile) {
+        ntiles = (n + tile - 1) / tile;
+        const unsigned xs = gridDim.x % XCDS == 0 ? XCDS : 1;
+        per = (ntiles + xs - 1) / xs;
+        x = blockIdx.x % xs;
+        gx = gridDim.x / xs;
+        first = blockIdx.x / xs;
+    }
+    HD_D bool valid(int64_t tt) const { return tt < per && x * per + tt < ntiles; }
+    HD_D int64_t tile(int64_t tt) const { return x * per + tt; }
+};
+
+template <class T, int SD, int QB>
+__device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const QueryCfg &cfg, const BView<T> &bv,
+                             const QueryOut<T> &out, const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl,
+                             int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
+    const TileOrder to(n, QB);
+    for (int64_t tt = to.first; to.valid(tt); tt += to.gx) {
+        const int64_t i = to.tile(tt) * QB + threadIdx.x;
         unsigned long long lord = 0, key = 0;
         int pair = 0;
         if (i < n) {
@@ -510,9 +526,9 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
             seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
             LdsStack<SD, QB> stk{s_node, s_dist, 0};
             r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
-            nb += r.nbox;
-            nl += r.nleaf;
-            nq += 1;
+            t.nb += r.nbox;
+            t.nl += r.nleaf;
+            t.nq += 1;
             if (r.overflow) {
                 int k = atomicAdd(&ctl->n_overflow, 1);
                 ovf_list[k] = (int32_t)i;
@@ -522,7 +538,59 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
         }
         pair_max2(pv, pair, lord, key);
     }
-    block_add<3, QB>({nb, nl, nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
+}
+
+template <class T, int SD, int QB>
+__device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const QueryCfg &cfg, const BView<T> &bv,
+                             const QueryOut<T> &out, const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl,
+                             int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
+    constexpr int NQ = QB / 4; // queries per tile
+    const int g = threadIdx.x >> 2, k = threadIdx.x & 3;
+    const TileOrder to(n, NQ);
+    for (int64_t tt = to.first; to.valid(tt); tt += to.gx) {
+        const int64_t i = to.tile(tt) * NQ + g;
+        unsigned long long lord = 0, key = 0;
+        int pair = 0;
+        if (i < n) { // the same for the four lanes of a quad
+            QPoint qp = query_point(in, i);
+            pair = qp.pair;
+            V3<T> p = cvt<T>(qp.p);
+            QueryResult<T> r = empty_result<T>();
+            // the two candidate triangles: one lane each
+            const int seed = k == 0 ? qp.seed[0] : (k == 1 && qp.seed[1] != qp.seed[0] ? qp.seed[1] : -1);
+            if (seed >= 0) visit_leaf(r, bv, cfg.ids, p, seed);
+            quad_min(r);
+            QuadStack<SD, NQ> stk{s_node, s_dist, g};
+            r = traverse4<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r, k);
+            t.nb += r.nbox;
+            t.nl += r.nleaf;
+            if (k == 0) {
+                t.nq += 1;
+                if (r.overflow) {
+                    int slot = atomicAdd(&ctl->n_overflow, 1);
+                    ovf_list[slot] = (int32_t)i;
+                } else {
+                    finish_query<T>(cfg, bv, r, qp, p, out, pc, &lord, &key);
+                }
+            }
+        }
+        pair_max2(pv, pair, lord, key);
+    }
+}
+
+template <class T, int SD, int QB>
+__global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
+                                              QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
+                                              Ctl *ctl, int32_t *ovf_list, int64_t quad_max) {
+    __shared__ int s_node[SD * QB];
+    __shared__ float s_dist[SD * QB];
+    const int64_t n = cnt.get();
+    QueryTally t;
+    if (n <= quad_max)
+        query_lanes4<T, SD, QB>(in, n, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    else
+        query_lanes1<T, SD, QB>(in, n, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    block_add<3, QB>({t.nb, t.nl, t.nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
 }
 
 // queries whose LDS stack overflowed, redone with a deep stack in global
@@ -557,26 +625,40 @@ __global__ __launch_bounds__(64) void k_query_deep(QueryIn<T> in, QueryCfg cfg, 
     wave_add(&ctl->q_leaves, nl);
 }
 
-// Launch shapes of the query kernel (LDS stack entries per lane, block size)
-// that the autotuner chooses from; entry 0 is the default.
+// Launch shapes of the query kernel (LDS stack entries per query, block
+// size) that the autotuner chooses from; entry 0 is the default.
 struct QVariant {
     int sd, qb;
 };
 constexpr QVariant QVARIANTS[] = {{16, 128}, {8, 64}, {16, 64}, {32, 128}, {8, 256}, {16, 256}};
 constexpr int NQVAR = sizeof(QVARIANTS) / sizeof(QVARIANTS[0]);
 
+// Launches of at most this many queries run a quad of lanes per query. Below
+// it the one-lane kernel holds too few waves to hide its latency: measured
+// on MI355X, a quad per query is about 30% faster for launches of a few
+// thousand queries or fewer, even around 25k, and up to 2.5x slower for
+// launches of 10^5 queries and more (there every lane's redundant share of
+// the sort and stack work costs issue slots).
+constexpr int64_t QUAD_MAX_DEFAULT = 16384;
+
 // grid of a query launch of block size qb for up to n queries: a multiple of
-// XCDS, capped at a persistent size
-inline unsigned qgrid_b(int64_t n, int qb) {
-    const unsigned g = (unsigned)std::min<int64_t>((n + qb - 1) / qb, (int64_t)QGRID_MAX * 128 / qb);
+// XCDS, capped at a persistent size; launches that may take the quad path
+// get four lanes per query
+inline unsigned qgrid_b(int64_t n, int qb, int64_t quad_max) {
+    const int64_t lanes = n <= quad_max ? 4 : 1;
+    const unsigned g = (unsigned)std::min<int64_t>((lanes * n + qb - 1) / qb, (int64_t)QGRID_MAX * 128 / qb);
     return std::max<unsigned>((g + XCDS - 1) / XCDS * XCDS, XCDS);
 }
 
-// variant v (-1: the tiny-stack test hook) for up to n_max queries
+// variant v (-1: the tiny-stack test hook) for up to n_max queries; launches
+// of at most quad_max queries (by the count the kernel reads) take the quad
+// path
 template <class T>
-void launch_query(int v, int64_t n_max, const QueryIn<T> &qi, DevCount cnt, const QueryCfg &cfg, const BView<T> &bv,
-                  const QueryOut<T> &out, const PairConst *pc, PairVar *pv, Ctl *ctl, int32_t *ovf, hipStream_t s) {
-#define HD_QLAUNCH(SD, QB) k_query<T, SD, QB><<<qgrid_b(n_max, QB), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf)
+void launch_query(int v, int64_t n_max, int64_t quad_max, const QueryIn<T> &qi, DevCount cnt, const QueryCfg &cfg,
+                  const BView<T> &bv, const QueryOut<T> &out, const PairConst *pc, PairVar *pv, Ctl *ctl,
+                  int32_t *ovf, hipStream_t s) {
+#define HD_QLAUNCH(SD, QB)                                                                                             \
+    k_query<T, SD, QB><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf, quad_max)
     switch (v) {
     case -1: HD_QLAUNCH(SMALL_STACK, 128); break;
     case 1: HD_QLAUNCH(8, 64); break;
@@ -1515,6 +1597,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cctx.norder = parse_order(opt.order, cctx.order);
     if (cctx.norder <= 0) throw Error{HD_E_INVALID, "bad cascade order"};
     if (opt.learned < 0 || opt.learned > 2) throw Error{HD_E_INVALID, "learned must be 0, 1 or 2"};
+    if (opt.query_lanes != 0 && opt.query_lanes != 1 && opt.query_lanes != 4)
+        throw Error{HD_E_INVALID, "query_lanes must be 0, 1 or 4"};
     if (opt.learned > 0 && !opt.mlp_params) throw Error{HD_E_INVALID, "learned mode needs the network's parameters"};
     if (opt.log_frontier && (!opt.log_out || opt.log_cap <= 0)) throw Error{HD_E_INVALID, "frontier log needs a buffer"};
     for (int p = 0; p < (in.eps_per_pair ? np : 1); ++p)
@@ -1621,6 +1705,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const bool small_stack = opt.stack_depth > 0 && opt.stack_depth < QSTACK;
     int &qvar = ws.qvar[sizeof(T) == 4 ? 0 : 1];
     if (qvar < 0 || qvar >= NQVAR) qvar = 0;
+    int qsel = 0; // the launch shape this call uses (set after the autotuner)
+    // launches of at most qmax queries run a quad of lanes per query
+    const int64_t qmax = opt.query_lanes == 1 ? -1 : (opt.query_lanes == 4 ? INT64_MAX : QUAD_MAX_DEFAULT);
 
     // queries: n_max bounds the count (host count, or the device-planned one),
     // the grid covers it up to a persistent cap and loops beyond
@@ -1628,7 +1715,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         if (n_max <= 0) return;
         ws.ovf.reserve((size_t)n_max * sizeof(int32_t));
         prof.mark(prof.q);
-        launch_query<T>(small_stack ? -1 : qvar, n_max, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(), s);
+        launch_query<T>(qsel, n_max, qmax, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(), s);
         prof.mark(prof.q);
         k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                         ws.deep.as<int2>());
@@ -1663,7 +1750,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             for (int rep = 0; rep < 2; ++rep) {
                 k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
                 HD_HIP(hipEventRecord(ws.tune_ev[0], s));
-                launch_query<T>(v, nref, qi, host_count(nref), tcfg, bv, tw.vq.o, pc, pv, ctl,
+                launch_query<T>(v, nref, -1, qi, host_count(nref), tcfg, bv, tw.vq.o, pc, pv, ctl,
                                 ws.ovf.as<int32_t>(), s);
                 HD_HIP(hipEventRecord(ws.tune_ev[1], s));
                 HD_HIP(hipEventSynchronize(ws.tune_ev[1]));
@@ -1680,8 +1767,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qvar = pick;
         ws.tuned[sizeof(T) == 4 ? 0 : 1] = true;
     }
-    S.query_block = small_stack ? 128 : QVARIANTS[qvar].qb;
-    S.query_stack = small_stack ? SMALL_STACK : QVARIANTS[qvar].sd;
+    qsel = small_stack ? -1 : qvar;
+    S.query_block = qsel < 0 ? 128 : QVARIANTS[qsel].qb;
+    S.query_stack = qsel < 0 ? SMALL_STACK : QVARIANTS[qsel].sd;
+    S.query_lanes = opt.query_lanes;
+    S.query_quad_max = qmax < 0 ? 0 : (qmax == INT64_MAX ? -1 : qmax);
 
     // ---- round 0: vertex queries ------------------------------------------
     {
@@ -1798,13 +1888,14 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             }
             hm = wait_report(seq_prev);
             peak = std::max<int64_t>(peak, hm.act + hm.park);
-            if (!more) break;
-            const bool done = hm.act == 0 || hm.bad || hm.over_budget || hm.stall;
-            seq_prev = seq_new;
-            if (!done) continue;
-            // the round enqueued ahead found nothing to do (or stopped too)
-            hm = wait_report(seq_new);
-            peak = std::max<int64_t>(peak, hm.act + hm.park);
+            if (more) {
+                const bool done = hm.act == 0 || hm.bad || hm.over_budget || hm.stall;
+                seq_prev = seq_new;
+                if (!done) continue;
+                // the round enqueued ahead found nothing to do (or stopped too)
+                hm = wait_report(seq_new);
+                peak = std::max<int64_t>(peak, hm.act + hm.park);
+            }
             if (!(hm.stall && !hm.bad && !hm.over_budget && hm.act > 0)) break;
             // out of list capacity: grow (the stalled rounds left the lists in
             // place) and go on, or give up at the limit
@@ -1822,6 +1913,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             }
             k_clear_stall<<<1, 64, 0, s>>>(ctl);
             seq_prev = report_async(nullptr);
+            enqueued = (int)hm.rounds; // stalled rounds split nothing and do not count
         }
         nAct = hm.act;
         nPark = hm.park;
@@ -1910,7 +2002,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const QueryCfg lcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
-            launch_query<T>(qvar, nq, li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(), s);
+            launch_query<T>(qsel, nq, qmax, li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
+                            s);
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(li, lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
                                                             ws.deep.as<int2>());
             k_log_parents<T><<<grid_for(K, BLK), BLK, 0, s>>>(tw.act.v, K, tw.lq.o, lc, bv, opt.log_out, logged,
@@ -2157,9 +2250,10 @@ hd_status hd_bound_batched(int32_t npairs, const double *const *VA, const int64_
     return st;
 }
 
-hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, double *d, int32_t *I,
-                             double *Q, hd_stream_t stream) {
+hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, int32_t lanes, double *d,
+                             int32_t *I, double *Q, hd_stream_t stream) {
     if (!Bh || nP < 0 || (nP > 0 && (!P || !d || !I))) return HD_E_INVALID;
+    if (lanes != 0 && lanes != 1 && lanes != 4) return HD_E_INVALID;
     if (nP == 0) return HD_OK;
     const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
     hipStream_t s = (hipStream_t)stream;
@@ -2188,7 +2282,8 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             BView<T> bv;
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
-            launch_query<T>(0, nP, qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(), s);
+            launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
+                            ovf.as<int32_t>(), s);
             k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(),
                                                             deep.as<int2>());
             k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q);

@@ -383,6 +383,193 @@ HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> 
 }
 
 // ---------------------------------------------------------------------------
+// Four lanes per query. A quad (four consecutive lanes of a wave) runs one
+// traversal: lane k tests child slot k of each wide node and evaluates that
+// child when it is a triangle in range; quad permutes (DPP, no LDS) then give
+// every lane of the quad the same view of the four children, and the lanes
+// take identical decisions (next node, stack entries), so the quad stays in
+// step. Per node this spreads the box tests and the closest-point
+// evaluations over four lanes, and a launch of the same queries holds four
+// times as many waves to hide the latency of the dependent node loads.
+// Every quad-level helper below must be called by all four lanes of a quad.
+// ---------------------------------------------------------------------------
+template <int CTRL> HD_D int dpp_i32(int x) { return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, false); }
+template <int CTRL, class X> HD_D X dpp(X x) {
+    if constexpr (sizeof(X) == 4) {
+        return __builtin_bit_cast(X, dpp_i32<CTRL>(__builtin_bit_cast(int, x)));
+    } else {
+        static_assert(sizeof(X) == 8, "4- or 8-byte values");
+        const unsigned long long v = __builtin_bit_cast(unsigned long long, x);
+        const int lo = dpp_i32<CTRL>((int)(unsigned)v), hi = dpp_i32<CTRL>((int)(unsigned)(v >> 32));
+        return __builtin_bit_cast(X, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+}
+// quad_perm controls: lane j of the quad to all four lanes; xor 1; xor 2
+template <int J, class X> HD_D X quad_bcast(X x) { return dpp<J * 0x55>(x); }
+template <class X> HD_D X quad_xor1(X x) { return dpp<0xB1>(x); }
+template <class X> HD_D X quad_xor2(X x) { return dpp<0x4E>(x); }
+HD_D bool quad_any(bool b) { return ((__ballot(b) >> (__lane_id() & ~3u)) & 0xfull) != 0; }
+
+// every lane of the quad takes the quad's best (d2, triangle), exact ties to
+// the smallest original index; the counters stay per lane
+template <class T> HD_D void quad_min(QueryResult<T> &r) {
+    {
+        const T d2 = quad_xor1(r.d2);
+        const int s = quad_xor1(r.s), o = quad_xor1(r.orig);
+        if (d2 < r.d2 || (d2 == r.d2 && o < r.orig)) {
+            r.d2 = d2;
+            r.s = s;
+            r.orig = o;
+        }
+    }
+    {
+        const T d2 = quad_xor2(r.d2);
+        const int s = quad_xor2(r.s), o = quad_xor2(r.orig);
+        if (d2 < r.d2 || (d2 == r.d2 && o < r.orig)) {
+            r.d2 = d2;
+            r.s = s;
+            r.orig = o;
+        }
+    }
+}
+
+// the quad's short stack in LDS: entries [slot][quad of block]; all four
+// lanes hold the same top / count and write the same values
+template <int SD, int NQ> struct QuadStack {
+    int *node;
+    float *dist;
+    int col;
+    int top = 0, cnt = 0;
+    HD_D bool push(int n, float d) {
+        node[top * NQ + col] = n;
+        dist[top * NQ + col] = d;
+        top = top + 1 == SD ? 0 : top + 1;
+        if (cnt == SD) return false;
+        ++cnt;
+        return true;
+    }
+    HD_D bool pop(int &n, float &d) {
+        if (cnt == 0) return false;
+        top = top == 0 ? SD - 1 : top - 1;
+        --cnt;
+        n = node[top * NQ + col];
+        d = dist[top * NQ + col];
+        return true;
+    }
+    HD_D void clear() { top = cnt = 0; }
+};
+
+// lane k's child of wide node w: box distance, reference
+template <class T> HD_D T slot_box_d2(const WideNode *w, int k, const V3<T> &p, int &ref) {
+    const float *b = reinterpret_cast<const float *>(w);
+    ref = reinterpret_cast<const int *>(w)[24 + k];
+    return box_d2<T>(make_float4(b[k], b[4 + k], b[8 + k], 0.f), make_float4(b[12 + k], b[16 + k], b[20 + k], 0.f), p);
+}
+
+// The traversal of `traverse` (same pruning, same order of descent, same
+// ring stack with restarts) run by a quad; k = lane within the quad. The
+// result (d2, s, orig, overflow) is the same on all four lanes; nbox and
+// nleaf count each lane's own tests.
+template <class T, class Stack>
+HD_D QueryResult<T> traverse4(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
+                              const V3<T> &p, int root, Stack &st, QueryResult<T> r, int k) {
+    const T slack = T(1) + T(16 * Prec<T>::u);
+    const T inf = T(__builtin_inf());
+    if (root < 0) {
+        if (k == 0) visit_leaf(r, bv, ids, p, ~root);
+        quad_min(r);
+        return r;
+    }
+    if (!(r.d2 < inf)) {
+        // greedy probe: nearest box first down to one leaf, nothing pushed
+        int x = root;
+        for (int guard = 0; guard < 64 && x >= 0; ++guard) {
+            int ref;
+            const T dd = slot_box_d2<T>(nodes + x, k, p, ref);
+            r.nbox += ref != WIDE_EMPTY;
+            const T d0 = quad_bcast<0>(dd), d1 = quad_bcast<1>(dd), d2 = quad_bcast<2>(dd), d3 = quad_bcast<3>(dd);
+            const int c0 = quad_bcast<0>(ref), c1 = quad_bcast<1>(ref), c2 = quad_bcast<2>(ref),
+                      c3 = quad_bcast<3>(ref);
+            T best = inf;
+            int pick = WIDE_EMPTY, slot = -1;
+            auto consider = [&](T d, int c, int j) {
+                if (c == WIDE_EMPTY) return;
+                if (pick == WIDE_EMPTY || d < best) {
+                    best = d;
+                    pick = c;
+                    slot = j;
+                }
+            };
+            consider(d0, c0, 0);
+            consider(d1, c1, 1);
+            consider(d2, c2, 2);
+            consider(d3, c3, 3);
+            if (pick == WIDE_EMPTY) break;
+            if (pick < 0) {
+                if (k == slot) visit_leaf(r, bv, ids, p, ~pick);
+                quad_min(r);
+                break;
+            }
+            x = pick;
+        }
+    }
+    int node = root;
+    bool lost = false;
+    int restarts = 0;
+    while (true) {
+        int f;
+        const T e = slot_box_d2<T>(nodes + node, k, p, f);
+        r.nbox += f != WIDE_EMPTY;
+        // triangles in range: each lane its own, then the quad's best
+        const bool leaf = f < 0 && f != WIDE_EMPTY && e <= r.d2 * slack;
+        if (quad_any(leaf)) {
+            if (leaf) visit_leaf(r, bv, ids, p, ~f);
+            quad_min(r);
+        }
+        // internal children in range, nearest first
+        const T thr = r.d2 * slack;
+        const bool in = f >= 0 && e <= thr;
+        const T ei = in ? e : inf;
+        const int fi = in ? f : -1;
+        T e0 = quad_bcast<0>(ei), e1 = quad_bcast<1>(ei), e2 = quad_bcast<2>(ei), e3 = quad_bcast<3>(ei);
+        int f0 = quad_bcast<0>(fi), f1 = quad_bcast<1>(fi), f2 = quad_bcast<2>(fi), f3 = quad_bcast<3>(fi);
+        cswap(e0, f0, e1, f1);
+        cswap(e2, f2, e3, f3);
+        cswap(e0, f0, e2, f2);
+        cswap(e1, f1, e3, f3);
+        cswap(e1, f1, e2, f2);
+        if (f0 >= 0) {
+            if (f3 >= 0 && !st.push(f3, to_float_down(e3))) lost = true;
+            if (f2 >= 0 && !st.push(f2, to_float_down(e2))) lost = true;
+            if (f1 >= 0 && !st.push(f1, to_float_down(e1))) lost = true;
+            node = f0;
+            continue;
+        }
+        bool found = false;
+        int n;
+        float dn;
+        while (st.pop(n, dn)) {
+            if (T(dn) <= r.d2 * slack) {
+                node = n;
+                found = true;
+                break;
+            }
+        }
+        if (!found) {
+            if (!lost) break;
+            if (++restarts > MAX_RESTARTS) {
+                r.overflow = true;
+                break;
+            }
+            lost = false;
+            st.clear();
+            node = root;
+        }
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
 // The cascade ("Upper bounds" subsection and Implementation section): the
 // exact bound when all three closest triangles coincide; otherwise the
 // bounds in the requested order, stopping at the first that falls below the

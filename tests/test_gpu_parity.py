@@ -147,6 +147,9 @@ def test_eval_bounds_match_oracle(seed):
 # the whole branch and bound
 # ----------------------------------------------------------------------------
 
+PRECS = {"fp64": 0, "fp32": 1, "fp32+recheck": 2}  # HD_PREC_* of include/hd.h
+
+
 def _check_against_oracle(L, U, st, ref, name):
     eps = st["eps_abs"]
     print(f"{name}: gpu [{L:.12g}, {U:.12g}] oracle [{ref['L']:.12g}, {ref['U']:.12g}] eps {eps:.3g} "
@@ -350,15 +353,104 @@ def test_small_capacity_still_certified():
     _check_against_oracle(L, U, st, ref, "config2 small capacity")
 
 
-def test_tiny_stack_falls_back_and_agrees():
+def test_round_limit_with_list_growth():
+    """A round limit on the thin-triangle workload at full size, whose first
+    round outgrows the default frontier lists: the lists grow, the stalled
+    round does not count, and the partial intervals stay valid bounds."""
+    hd, torch = _hd()
+    W = wl.config(3)
+    say("config3 full size with max_rounds 1, 2 and unlimited")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    Lf, Uf, sf = hd.bound(*args, precision=hd.PREC_FP32)
+    assert sf["status"] == 0 and sf["rounds"] > 2
+    prev = 0
+    for r in (1, 2):
+        L, U, st = hd.bound(*args, precision=hd.PREC_FP32, max_rounds=r)
+        print(f"max_rounds {r}: rounds {st['rounds']} subdivided {st['subdivided']} [{L:.10g}, {U:.10g}]")
+        assert st["status"] == 0 and st["rounds"] == r
+        assert st["subdivided"] > prev
+        prev = st["subdivided"]
+        assert L <= Lf and L <= Uf and Lf <= U
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_tiny_stack_falls_back_and_agrees(lanes):
+    """A four-entry stack (ring restarts, then the deep-stack kernel) gives
+    the result of the default stack, with one lane or a quad per query."""
     hd, torch = _hd()
     W = wl.config(2, scale=0.05)
-    say("tiny traversal stack on config2 scale 0.05")
+    say("tiny traversal stack on config2 scale 0.05, lanes", lanes)
     bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
-    a = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
-    b = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, stack_depth=2)
+    a = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, query_lanes=lanes)
+    b = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, stack_depth=2, query_lanes=lanes)
+    assert b[2]["query_lanes"] == lanes and b[2]["query_stack"] == 4
+    print("overflows", b[2]["stack_overflows"])
     assert a[0] == b[0] and a[1] == b[1]
     assert a[2]["subdivided"] == b[2]["subdivided"]
+
+
+@pytest.mark.parametrize("which", ["config2-small", "config3-small", "grid"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_quad_query_kernel_agrees(which, prec):
+    """Four lanes per point query against one lane per query. In FP64 the
+    same closest face, distance and closest point, bit for bit (both find the
+    minimum under the same tie rule). In FP32 the computed distances are not
+    exactly monotone in the box tests, so near-ties may resolve to another
+    face, visited in another order: there both distances lie within the FP32
+    margin of the exact one."""
+    hd, torch = _hd()
+    rng = np.random.default_rng(9)
+    if which == "grid":
+        VB, FB = _grid_soup(12, rng)
+        P = rng.uniform(-1.3, 1.3, size=(3001, 3))
+    else:
+        W = wl.config(2 if which == "config2-small" else 3, scale=0.05)
+        VB, FB = W.VB, W.FB
+        lo, hi = VB.min(0), VB.max(0)
+        P = np.concatenate([rng.uniform(lo - 0.1, hi + 0.1, size=(1501, 3)), W.VA[:1500]])
+    precision = hd.PREC_FP64 if prec == "fp64" else hd.PREC_FP32
+    say("quad vs one-lane point queries", which, prec, "nP", P.shape[0])
+    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+    d1, I1, Q1 = (x.cpu().numpy() for x in hd.point_distances(_cu(P, torch), bvh, precision=precision, lanes=1))
+    d4, I4, Q4 = (x.cpu().numpy() for x in hd.point_distances(_cu(P, torch), bvh, precision=precision, lanes=4))
+    dref, _ = oracle.points_soup(P, VB, FB)
+    if prec == "fp64":
+        assert np.array_equal(I1, I4)
+        assert np.array_equal(d1, d4) and np.array_equal(Q1, Q4)
+        assert np.abs(d4 - dref).max() <= 1e-12 * np.abs(VB).max()
+        return
+    edge = max(np.linalg.norm(VB[FB[:, i]] - VB[FB[:, (i + 1) % 3]], axis=1).max() for i in range(3))
+    ctr = 0.5 * (VB[np.unique(FB)].min(0) + VB[np.unique(FB)].max(0))
+    coord = max(np.abs(VB - ctr).max(), np.abs(P - ctr).max())
+    mu = _margin(dref, 2.0 ** -24, edge, coord)
+    same = I1 == I4
+    print(f"faces differ at {int((~same).sum())} of {P.shape[0]} points", flush=True)
+    assert np.array_equal(d1[same], d4[same]) and np.array_equal(Q1[same], Q4[same])
+    assert (np.abs(d1 - dref) <= mu).all() and (np.abs(d4 - dref) <= mu).all()
+
+
+@pytest.mark.parametrize("k,scale,prec", [(1, 1.0, "fp64"), (2, 0.05, "fp32+recheck"), (3, 0.02, "fp32")])
+def test_quad_query_kernel_in_the_bound(k, scale, prec):
+    """hd_bound with the four-lane query kernel, certified against the
+    oracle. In FP64 also the same interval and counts as the one-lane kernel
+    (identical query results); in FP32 a near-tie may pick another closest
+    face, so only the certificates are compared."""
+    hd, torch = _hd()
+    W = wl.config(k, scale=scale)
+    say("bound with quad queries, config", k, "scale", scale, prec)
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    L1, U1, s1 = hd.bound(*args, precision=PRECS[prec], query_lanes=1)
+    L4, U4, s4 = hd.bound(*args, precision=PRECS[prec], query_lanes=4)
+    assert s1["query_lanes"] == 1 and s4["query_lanes"] == 4
+    if prec == "fp64":
+        assert (L1, U1) == (L4, U4)
+        for key in ("rounds", "subdivided", "nodes_bounded", "queries", "discards", "rechecked64"):
+            assert s1[key] == s4[key], key
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+    _check_against_oracle(L1, U1, s1, ref, f"config{k} one-lane queries")
+    _check_against_oracle(L4, U4, s4, ref, f"config{k} quad queries")
 
 
 def test_face_budget_exceeded():
@@ -385,8 +477,8 @@ def test_cascade_order_invariance_on_gpu():
 
 
 def test_autotuned_launch_shape_gives_the_same_result():
-    """The autotuner only changes the query kernel's launch shape: the result
-    and every count stay the same."""
+    """The autotuner only changes the query kernel's launch shape (block
+    size, stack depth): the result and every count stay the same."""
     hd, torch = _hd()
     W = wl.config(2, scale=0.1)
     say("autotune on config2 scale 0.1")
@@ -395,7 +487,7 @@ def test_autotuned_launch_shape_gives_the_same_result():
     L0, U0, s0 = hd.bound(*args)
     L1, U1, s1 = hd.bound(*args, autotune=2)
     L2, U2, s2 = hd.bound(*args)
-    print("tuned shape: block", s1["query_block"], "stack", s1["query_stack"])
+    print("tuned shape: block", s1["query_block"], "stack", s1["query_stack"], "quad below", s1["query_quad_max"])
     assert (s1["query_block"], s1["query_stack"]) in [(128, 16), (64, 8), (64, 16), (128, 32), (256, 8), (256, 16)]
     assert (s2["query_block"], s2["query_stack"]) == (s1["query_block"], s1["query_stack"])
     for k in ("subdivided", "nodes_bounded", "queries", "rounds", "pt_tri_evals"):
