@@ -61,7 +61,9 @@ typedef struct {
     int32_t subbatch;    /* > 0: subdivide at most this many triangles per round, highest
                             upper bound first (approximates the paper's best-first queue) */
     int32_t profile;     /* 1: time the query and cascade kernels with HIP events on the
-                            call's stream (fills the ms_* kernel fields of hd_stats) */
+                            call's stream (fills the ms_* kernel fields of hd_stats); 2: the
+                            query kernels only (every event record costs the stream a few
+                            microseconds) */
     int32_t learned;     /* learned proposal (not in the paper): 0 off; 1 the sub-batch is
                             taken in order of the network's predicted maximum distance
                             instead of the upper bound; 2 also let the network skip u3 and u4
@@ -102,7 +104,7 @@ typedef struct {
     double L_rounds, U_rounds; /* interval reached by the rounds, before the FP64 final step */
     double mu_coef_d, mu_coef_0; /* FP32 margin: mu(d) = mu_coef_d * d + mu_coef_0 */
     double ms_total;           /* wall time of the hd_bound call */
-    double ms_query_kernels;   /* profile = 1: summed duration of the point-query kernels */
+    double ms_query_kernels;   /* profile > 0: summed duration of the point-query kernels */
     double ms_cascade_kernels; /* profile = 1: summed duration of the bound/classify kernels */
     int64_t query_launches, cascade_launches;
     int64_t query_leaf_evals;  /* closest-point evaluations inside the query kernels */

@@ -57,7 +57,10 @@ struct Ctl {
     unsigned long long discards[5];
     alignas(128) unsigned long long queries, boxes, q_leaves;
     unsigned long long skips; // records whose u3 / u4 the learned policy skipped
-    // device-planned rounds (written by k_plan, read by the round's kernels)
+    // blocks of the current query / argmax launch that have finished (the
+    // last one does the launch's tail work and resets its counter)
+    alignas(128) unsigned q_done, f_done;
+    // device-planned rounds (written by plan_round, read by the round's kernels)
     alignas(128) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
     unsigned long long subdivided, rounds;             // totals over the planned rounds
     double processed;                                  // faces processed (the paper's budget count)
@@ -92,6 +95,26 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 __device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long long v) {
     v = wave_sum_u64(v);
     if (__lane_id() == 0 && v) atomicAdd(ctr, v);
+}
+
+// True in every thread of the one of `nactive` blocks that finishes last,
+// which then sees every write the other blocks made before finishing;
+// *counter (zero at launch) is reset for the next launch. Every thread of each
+// of those blocks must call it, once, at the end of its work; blocks that had
+// no work (a grid sized for a larger count) must not: every call is an atomic
+// on one address, and these serialise.
+__device__ bool last_block(unsigned *counter, unsigned nactive) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned ticket = atomicAdd(counter, 1u);
+        last = ticket == nactive - 1;
+        if (last) atomicExch(counter, 0u);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
 }
 
 __device__ __forceinline__ int pair_of(const int64_t *__restrict__ off, int npairs, int64_t x) {
@@ -173,8 +196,7 @@ struct alignas(64) Mailbox {
     unsigned seq;
 };
 
-__global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *ring, unsigned seq) {
-    if (threadIdx.x != 0) return;
+__device__ void report_to(const Ctl *ctl, const int32_t *nref, Mailbox *ring, unsigned seq) {
     Mailbox *mb = ring + seq % MB_SLOTS;
     mb->act = (long long)ctl->act_next;
     mb->park = (long long)ctl->park_next;
@@ -188,23 +210,35 @@ __global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *ring, uns
     __hip_atomic_store(&mb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+__global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *ring, unsigned seq) {
+    if (threadIdx.x == 0) report_to(ctl, nref, ring, seq);
+}
+
 // Device-planned round: how many active records to split (all of them,
 // capped by the list capacities and the face budget) and the per-round
 // counters. A round planned with nothing to do leaves everything in place.
 struct PlanCaps {
     int64_t act, park, pend, mq; // capacities (records / queries)
     double budget;               // the paper's m * nA
+    int grow_act, grow_park;     // 1: the host can still grow the active / parked lists
 };
-__global__ void k_plan(Ctl *c, PlanCaps caps) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     const int64_t nAct = (int64_t)c->act_next, nPark = (int64_t)c->park_next;
     int64_t K = 0;
     if (!c->bad && !c->stall && !c->over_budget && nAct > 0) {
+        // room in the active-side lists (the pending and midpoint lists are
+        // sized with the active ones) and in the parked list
+        int64_t ka = (caps.act - nAct) / 3;
+        ka = ka < caps.pend / 4 ? ka : caps.pend / 4;
+        ka = ka < caps.mq / 3 ? ka : caps.mq / 3;
+        const int64_t kp = (caps.park - nPark) / 4;
         K = nAct;
-        K = K < (caps.act - nAct) / 3 ? K : (caps.act - nAct) / 3;
-        K = K < (caps.park - nPark) / 4 ? K : (caps.park - nPark) / 4;
-        K = K < caps.pend / 4 ? K : caps.pend / 4;
-        K = K < caps.mq / 3 ? K : caps.mq / 3;
+        K = K < ka ? K : ka;
+        K = K < kp ? K : kp;
+        // split all or, while the list that lacks room can grow, none (a
+        // stall: the host grows it), so that the rounds do not depend on the
+        // capacities that earlier calls left behind
+        if ((ka < nAct && caps.grow_act) || (kp < nAct && caps.grow_park)) K = 0;
         if (K <= 0) {
             K = 0;
             c->stall = 1;
@@ -225,9 +259,15 @@ __global__ void k_plan(Ctl *c, PlanCaps caps) {
     c->n_overflow = 0;
 }
 
-// a planned round's carried-over records: act[K .. K + rest) -> act2[0 .. rest)
-template <class T>
-__global__ void k_gather_planned(FrontierView<T> src, FrontierView<T> dst, const Ctl *ctl);
+// the end of a device-planned round: report its state, then plan the next
+// round (a planned round that is never enqueued changes nothing the host
+// reads afterwards)
+__global__ void k_report_plan(Ctl *ctl, Mailbox *ring, unsigned seq, PlanCaps caps) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    report_to(ctl, nullptr, ring, seq);
+    plan_round(ctl, caps);
+}
+
 
 __global__ void k_clear_stall(Ctl *c) {
     if (threadIdx.x == 0) c->stall = 0;
@@ -496,10 +536,10 @@ struct QueryTally {
 // not a multiple of XCDS takes them in plain order.
 struct TileOrder {
     int64_t ntiles, per;
-    unsigned x, gx, first;
+    unsigned xs, x, gx, first;
     HD_D TileOrder(int64_t n, int tile) {
         ntiles = (n + tile - 1) / tile;
-        const unsigned xs = gridDim.x % XCDS == 0 ? XCDS : 1;
+        xs = gridDim.x % XCDS == 0 ? XCDS : 1;
         per = (ntiles + xs - 1) / xs;
         x = blockIdx.x % xs;
         gx = gridDim.x / xs;
@@ -507,13 +547,24 @@ struct TileOrder {
     }
     HD_D bool valid(int64_t tt) const { return tt < per && x * per + tt < ntiles; }
     HD_D int64_t tile(int64_t tt) const { return x * per + tt; }
+    // whether this block has a tile, and how many blocks have one
+    HD_D bool active() const { return valid(first); }
+    HD_D unsigned active_blocks() const {
+        int64_t a = 0;
+        for (unsigned y = 0; y < xs; ++y) {
+            int64_t k = ntiles - (int64_t)y * per;
+            k = k < per ? k : per;
+            k = k < (int64_t)gx ? k : (int64_t)gx;
+            a += k > 0 ? k : 0;
+        }
+        return (unsigned)a;
+    }
 };
 
 template <class T, int SD, int QB>
-__device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const QueryCfg &cfg, const BView<T> &bv,
-                             const QueryOut<T> &out, const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl,
-                             int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
-    const TileOrder to(n, QB);
+__device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const TileOrder &to, const QueryCfg &cfg,
+                             const BView<T> &bv, const QueryOut<T> &out, const PairConst *__restrict__ pc,
+                             PairVar *pv, Ctl *ctl, int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
     for (int64_t tt = to.first; to.valid(tt); tt += to.gx) {
         const int64_t i = to.tile(tt) * QB + threadIdx.x;
         unsigned long long lord = 0, key = 0;
@@ -541,12 +592,11 @@ __device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const QueryCfg &cf
 }
 
 template <class T, int SD, int QB>
-__device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const QueryCfg &cfg, const BView<T> &bv,
-                             const QueryOut<T> &out, const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl,
-                             int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
+__device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const TileOrder &to, const QueryCfg &cfg,
+                             const BView<T> &bv, const QueryOut<T> &out, const PairConst *__restrict__ pc,
+                             PairVar *pv, Ctl *ctl, int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
     constexpr int NQ = QB / 4; // queries per tile
     const int g = threadIdx.x >> 2, k = threadIdx.x & 3;
-    const TileOrder to(n, NQ);
     for (int64_t tt = to.first; to.valid(tt); tt += to.gx) {
         const int64_t i = to.tile(tt) * NQ + g;
         unsigned long long lord = 0, key = 0;
@@ -578,37 +628,49 @@ __device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const QueryCfg &cf
     }
 }
 
+template <class T>
+__device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BView<T> &bv, const QueryOut<T> &out,
+                             const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, const int32_t *ovf_list,
+                             int2 *stack_mem);
+
+// ... and the block that finishes last redoes the queries whose LDS stack
+// overflowed (deep_queries).
 template <class T, int SD, int QB>
 __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
                                               QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
-                                              Ctl *ctl, int32_t *ovf_list, int64_t quad_max) {
+                                              Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max) {
     __shared__ int s_node[SD * QB];
     __shared__ float s_dist[SD * QB];
     const int64_t n = cnt.get();
+    const bool quad = n <= quad_max;
+    const TileOrder to(n, quad ? QB / 4 : QB);
+    if (!to.active()) return; // the grid is sized for a larger count
     QueryTally t;
-    if (n <= quad_max)
-        query_lanes4<T, SD, QB>(in, n, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    if (quad)
+        query_lanes4<T, SD, QB>(in, n, to, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
     else
-        query_lanes1<T, SD, QB>(in, n, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+        query_lanes1<T, SD, QB>(in, n, to, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
     block_add<3, QB>({t.nb, t.nl, t.nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
+    if (last_block(&ctl->q_done, to.active_blocks()))
+        deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
 }
 
 // queries whose LDS stack overflowed, redone with a deep stack in global
-// memory (grid-stride over the overflow list; exits at once when it is empty)
+// memory by the threads of one block (thread t uses stack slot t of
+// DEEP_SLOTS); the list is empty but for unusual trees
 template <class T>
-__global__ __launch_bounds__(64) void k_query_deep(QueryIn<T> in, QueryCfg cfg, BView<T> bv, QueryOut<T> out,
+__device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BView<T> &bv, const QueryOut<T> &out,
                              const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, const int32_t *ovf_list,
                              int2 *stack_mem) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int novf = ctl->n_overflow;
     unsigned long long nb = 0, nl = 0;
-    for (int k = tid; k < novf; k += DEEP_SLOTS) {
+    for (int k = threadIdx.x; k < novf; k += blockDim.x) {
         int64_t i = ovf_list[k];
         QPoint qp = query_point(in, i);
         V3<T> p = cvt<T>(qp.p);
         QueryResult<T> r = empty_result<T>();
         seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
-        GlobalStack stk{stack_mem + tid, DEEP_SLOTS, DEEP_STACK, 0};
+        GlobalStack stk{stack_mem + threadIdx.x, DEEP_SLOTS, DEEP_STACK, 0};
         r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
         nb += r.nbox;
         nl += r.nleaf;
@@ -652,13 +714,14 @@ inline unsigned qgrid_b(int64_t n, int qb, int64_t quad_max) {
 
 // variant v (-1: the tiny-stack test hook) for up to n_max queries; launches
 // of at most quad_max queries (by the count the kernel reads) take the quad
-// path
+// path; deep: DEEP_SLOTS x DEEP_STACK entries for the overflowed queries
 template <class T>
 void launch_query(int v, int64_t n_max, int64_t quad_max, const QueryIn<T> &qi, DevCount cnt, const QueryCfg &cfg,
                   const BView<T> &bv, const QueryOut<T> &out, const PairConst *pc, PairVar *pv, Ctl *ctl,
-                  int32_t *ovf, hipStream_t s) {
+                  int32_t *ovf, int2 *deep, hipStream_t s) {
 #define HD_QLAUNCH(SD, QB)                                                                                             \
-    k_query<T, SD, QB><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf, quad_max)
+    k_query<T, SD, QB><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf, deep,    \
+                                                                    quad_max)
     switch (v) {
     case -1: HD_QLAUNCH(SMALL_STACK, 128); break;
     case 1: HD_QLAUNCH(8, 64); break;
@@ -678,35 +741,11 @@ __global__ void k_zero_query_stats(Ctl *c) {
     c->n_overflow = 0;
 }
 
-// after a query round: the query holding its pair's best key records its
-// exact position (keys are unique up to a tag collision of one point)
-template <class T>
-__global__ void k_argmax_finalize(QueryIn<T> in, DevCount cnt, const unsigned long long *__restrict__ keys,
-                                  const int *__restrict__ tri, PairVar *pv) {
-    const int64_t n = cnt.get();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
-        unsigned long long key = keys[o];
-        if (key == 0) continue;
-        QPoint qp = query_point(in, i);
-        PairVar &P = pv[qp.pair];
-        if (key == P.round_key && key > P.best_key) {
-            P.argmax_pos[0] = qp.p.x;
-            P.argmax_pos[1] = qp.p.y;
-            P.argmax_pos[2] = qp.p.z;
-            P.argmax_tri = tri[o];
-            P.argmax_dirty = 1;
-        }
-    }
-}
-
-// FP64 distance of each pair's best vertex when it changed: the lower bound
+// FP64 distance of pair p's best vertex when it changed: the lower bound
 // then carries the FP64 margin instead of the FP32 one, which the recheck
 // band needs to park triangles within eps of it
-__global__ __launch_bounds__(64) void k_L64(const WideNode *nodes, BView<double> bv64, const int4 *ids, const PairConst *pc, PairVar *pv,
-                      int npairs, int2 *stack_mem) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
+__device__ void l64_pair(const WideNode *nodes, const BView<double> &bv64, const int4 *ids, const PairConst *pc,
+                         PairVar *pv, int p, int npairs, int2 *stack_mem) {
     PairVar &P = pv[p];
     const PairConst &C = pc[p];
     if (P.round_key > P.best_key) P.best_key = P.round_key;
@@ -725,6 +764,44 @@ __global__ __launch_bounds__(64) void k_L64(const WideNode *nodes, BView<double>
     double dlo = d - (C.m64.mu_d * d + C.m64.mu_0);
     P.L64 = dlo;
     if (dlo > 0 && d2ord(dlo) > P.Lord) P.Lord = d2ord(dlo);
+}
+
+struct L64Cfg {
+    const WideNode *nodes;
+    BView<double> bv64;
+    const int4 *ids;
+    const PairConst *pc;
+    int npairs;
+    int2 *stack_mem; // npairs x DEEP_STACK entries
+};
+
+// after a query round: the query holding its pair's best key records its
+// exact position (keys are unique up to a tag collision of one point); the
+// block that finishes last then takes each pair's new best point to FP64
+template <class T>
+__global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount cnt,
+                                                         const unsigned long long *__restrict__ keys,
+                                                         const int *__restrict__ tri, PairVar *pv, L64Cfg lc, Ctl *ctl) {
+    const int64_t n = cnt.get();
+    if ((int64_t)blockIdx.x * BLK >= n) return; // the grid is sized for a larger count
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
+        unsigned long long key = keys[o];
+        if (key == 0) continue;
+        QPoint qp = query_point(in, i);
+        PairVar &P = pv[qp.pair];
+        if (key == P.round_key && key > P.best_key) {
+            P.argmax_pos[0] = qp.p.x;
+            P.argmax_pos[1] = qp.p.y;
+            P.argmax_pos[2] = qp.p.z;
+            P.argmax_tri = tri[o];
+            P.argmax_dirty = 1;
+        }
+    }
+    const int64_t need = (n + BLK - 1) / BLK;
+    if (last_block(&ctl->f_done, (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x)))
+        for (int p = threadIdx.x; p < lc.npairs; p += blockDim.x)
+            l64_pair(lc.nodes, lc.bv64, lc.ids, lc.pc, pv, p, lc.npairs, lc.stack_mem);
 }
 
 // ---------------------------------------------------------------------------
@@ -932,13 +1009,29 @@ template <class T> struct Dest {
     FrontierView<T> act, park, b, c;
 };
 
+// A wave-uniform 64-bit value passed through readfirstlane: the compiler can
+// no longer trace it to the kernel argument it was loaded from, so a per-lane
+// choice between such values stays a register select (choosing between the
+// argument fields themselves makes it copy the argument struct to scratch
+// memory and index that).
+HD_D uint64_t uniform_value(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // append a record to list `list` of d (nothing for TO_DISCARD)
 template <class T>
 HD_D void write_to(const Dest<T> &d, int list, int64_t o, const Corner<T> cn[3], float ub, int face, int lvl,
                    int pair) {
     if (list < 0) return;
-    const FrontierView<T> fo = list == TO_ACT ? d.act : (list == TO_PARK ? d.park : (list == TO_B ? d.b : d.c));
-    write_record(fo, o, cn, ub, face, lvl, pair);
+    const uint64_t b0 = uniform_value((uint64_t)d.act.base), b1 = uniform_value((uint64_t)d.park.base),
+                   b2 = uniform_value((uint64_t)d.b.base), b3 = uniform_value((uint64_t)d.c.base);
+    const uint64_t c0 = uniform_value((uint64_t)d.act.cap), c1 = uniform_value((uint64_t)d.park.cap),
+                   c2 = uniform_value((uint64_t)d.b.cap), c3 = uniform_value((uint64_t)d.c.cap);
+    const uint64_t b = list == TO_ACT ? b0 : (list == TO_PARK ? b1 : (list == TO_B ? b2 : b3));
+    const uint64_t c = list == TO_ACT ? c0 : (list == TO_PARK ? c1 : (list == TO_B ? c2 : c3));
+    write_record(FrontierView<T>{(char *)b, (int64_t)c}, o, cn, ub, face, lvl, pair);
 }
 
 // load a record's corners
@@ -983,12 +1076,22 @@ __global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__res
     tally(ctl, list, decider, 0, 0, valid, true);
 }
 
+template <class T> HD_D void copy_record(const FrontierView<T> &src, int64_t i, const FrontierView<T> &dst, int64_t o);
+
 // round k: child c of selected parent c/4, from the parent's record and the
-// three midpoint query results (midpoint e joins parent vertices e and e+1)
+// three midpoint query results (midpoint e joins parent vertices e and e+1).
+// carry (device-planned rounds): the records the round does not split,
+// par[nsel .. nsel + plan_rest), move to the head of the active output,
+// ahead of the appended children (plan_round starts the append count there).
 template <class T>
 __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T> par, QueryOut<T> mq,
-                                                  ClassifyCfg cc, Dest<T> dst, Ctl *ctl) {
+                                                  ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry) {
     const int64_t nsel = nselc.get();
+    if (carry) {
+        const int64_t rest = (int64_t)ctl->plan_rest;
+        for (int64_t o = (int64_t)blockIdx.x * BLK + threadIdx.x; o < rest; o += (int64_t)gridDim.x * BLK)
+            copy_record(par, nsel + o, dst.act, o);
+    }
     for (int64_t cbase = (int64_t)blockIdx.x * BLK; cbase < 4 * nsel; cbase += (int64_t)gridDim.x * BLK) {
     const int64_t c = cbase + threadIdx.x;
     bool valid = c < 4 * nsel;
@@ -1308,13 +1411,6 @@ __global__ void k_gather(FrontierView<T> src, const int32_t *__restrict__ perm, 
     if (o < n) copy_record(src, perm ? perm[o] : off + o, dst, o);
 }
 
-template <class T>
-__global__ void k_gather_planned(FrontierView<T> src, FrontierView<T> dst, const Ctl *ctl) {
-    const int64_t off = (int64_t)ctl->plan_K, n = (int64_t)ctl->plan_rest;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x)
-        copy_record(src, off + o, dst, o);
-}
-
 // selection keys: descending upper bound, ties by an order-independent tag
 template <class T>
 __global__ void k_sel_keys(FrontierView<T> fr, int64_t n, unsigned long long *__restrict__ keys,
@@ -1548,11 +1644,12 @@ int parse_order(int32_t order, int out[4]) {
 struct Profiler {
     hipStream_t s;
     bool on = false;
+    bool cascade = true; // also time the cascade kernels
     std::vector<hipEvent_t> *pool = nullptr;
     size_t used = 0;
     std::vector<hipEvent_t> q, c;
     void mark(std::vector<hipEvent_t> &v) {
-        if (!on) return;
+        if (!on || (&v == &c && !cascade)) return;
         if (used == pool->size()) {
             hipEvent_t e;
             HD_HIP(hipEventCreate(&e));
@@ -1616,6 +1713,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     Profiler prof;
     prof.s = s;
     prof.on = opt.profile != 0;
+    prof.cascade = opt.profile == 1;
     prof.pool = &ws.evpool;
 
     // ---- small tables -----------------------------------------------------
@@ -1715,14 +1813,12 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         if (n_max <= 0) return;
         ws.ovf.reserve((size_t)n_max * sizeof(int32_t));
         prof.mark(prof.q);
-        launch_query<T>(qsel, n_max, qmax, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(), s);
+        launch_query<T>(qsel, n_max, qmax, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
+                        ws.deep.as<int2>(), s);
         prof.mark(prof.q);
-        k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
-                                                        ws.deep.as<int2>());
+        const L64Cfg l64{B->nodes.as<WideNode>(), bv64, iv.ids, pc, np, ws.gstack.as<int2>()};
         k_argmax_finalize<T><<<std::min<unsigned>(grid_for(n_max, BLK), GRID_MAX), BLK, 0, s>>>(qi, cnt, out.key,
-                                                                                               out.I, pv);
-        k_L64<<<grid_for(np, 64), 64, 0, s>>>(B->nodes.as<WideNode>(), bv64, iv.ids, pc, pv, np,
-                                               ws.gstack.as<int2>());
+                                                                                               out.I, pv, l64, ctl);
         HD_LAUNCH_CHECK();
     };
 
@@ -1751,7 +1847,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
                 HD_HIP(hipEventRecord(ws.tune_ev[0], s));
                 launch_query<T>(v, nref, -1, qi, host_count(nref), tcfg, bv, tw.vq.o, pc, pv, ctl,
-                                ws.ovf.as<int32_t>(), s);
+                                ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
                 HD_HIP(hipEventRecord(ws.tune_ev[1], s));
                 HD_HIP(hipEventSynchronize(ws.tune_ev[1]));
                 float ms = 0;
@@ -1792,7 +1888,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     tw.act.ensure(cap0, 0, s);
     tw.act2.ensure(cap0, 0, s);
     tw.park.ensure(cap0, 0, s);
-    const int64_t cap_limit = opt.capacity > 0 ? std::max<int64_t>(opt.capacity, nA) : (int64_t(1) << 30);
+    int64_t cap_limit = opt.capacity > 0 ? std::max<int64_t>(opt.capacity, nA) : (int64_t(1) << 30);
 
     ClassifyCfg cc;
     cc.c = cctx;
@@ -1851,11 +1947,20 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             c.pend = cc.recheck ? std::min(tw.pend_b.cap, tw.pend_c.cap) : tw.pend_b.cap;
             c.mq = tw.mq.cap;
             c.budget = budget - (double)nA;
+            c.grow_act = c.act < cap_limit;
+            c.grow_park = c.park < cap_limit;
             return c;
         };
+        // report the state after a round and plan the next one
+        auto report_plan_async = [&]() -> unsigned {
+            const unsigned seq = ++ws.mb_seq;
+            k_report_plan<<<1, 64, 0, s>>>(ctl, mb_dev, seq, caps());
+            HD_LAUNCH_CHECK();
+            return seq;
+        };
+        // a round as planned by the report before it
         auto enqueue_round = [&]() {
             const PlanCaps c = caps();
-            k_plan<<<1, 64, 0, s>>>(ctl, c);
             QueryIn<T> qi{};
             qi.mode = Q_MIDPOINTS;
             qi.npairs = np;
@@ -1864,18 +1969,16 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             qi.pc = pc;
             const int64_t kmax = std::min<int64_t>(c.mq / 3, c.act);
             run_queries(qi, DevCount{&ctl->plan_K, 3, 0}, 3 * kmax, tw.mq.o);
-            k_gather_planned<T><<<std::min<unsigned>(grid_for(c.act, BLK), GRID_MAX), BLK, 0, s>>>(tw.act.v,
-                                                                                                   tw.act2.v, ctl);
             prof.mark(prof.c);
             k_children<T><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
                 DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
-                Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
+                Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1);
             HD_LAUNCH_CHECK();
             later_stages(4 * kmax, tw.act2.v);
             prof.mark(prof.c);
             swap_fb(tw.act, tw.act2);
         };
-        unsigned seq_prev = report_async(nullptr); // state after round 0
+        unsigned seq_prev = report_plan_async(); // state after round 0
         int enqueued = 0;
         int64_t peak = 0;
         while (true) {
@@ -1883,7 +1986,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             unsigned seq_new = 0;
             if (more) {
                 enqueue_round();
-                seq_new = report_async(nullptr);
+                seq_new = report_plan_async();
                 ++enqueued;
             }
             hm = wait_report(seq_prev);
@@ -1909,10 +2012,13 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 size_round();
             } catch (const Error &e) {
                 if (e.st != HD_E_NOMEM) throw;
-                break;
+                // out of device memory: the lists stay as they are and the
+                // rounds split what fits (sub-batches)
+                cap_limit = std::min(std::min(tw.act.cap, tw.act2.cap), tw.park.cap);
+                size_round();
             }
             k_clear_stall<<<1, 64, 0, s>>>(ctl);
-            seq_prev = report_async(nullptr);
+            seq_prev = report_plan_async();
             enqueued = (int)hm.rounds; // stalled rounds split nothing and do not count
         }
         nAct = hm.act;
@@ -2003,9 +2109,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
             launch_query<T>(qsel, nq, qmax, li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
-                            s);
-            k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(li, lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
-                                                            ws.deep.as<int2>());
+                            ws.deep.as<int2>(), s);
             k_log_parents<T><<<grid_for(K, BLK), BLK, 0, s>>>(tw.act.v, K, tw.lq.o, lc, bv, opt.log_out, logged,
                                                               opt.log_cap);
             HD_LAUNCH_CHECK();
@@ -2029,7 +2133,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         k_children<T><<<std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX), BLK, 0, s>>>(host_count(K), tw.act.v,
                                                                                           tw.mq.o, cc,
                                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
-                                                           ctl);
+                                                           ctl, 0);
         HD_LAUNCH_CHECK();
         later_stages(4 * K, tw.act2.v);
         prof.mark(prof.c);
@@ -2283,9 +2387,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
             launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
-                            ovf.as<int32_t>(), s);
-            k_query_deep<T><<<DEEP_SLOTS / 64, 64, 0, s>>>(qi, cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(),
-                                                            deep.as<int2>());
+                            ovf.as<int32_t>(), deep.as<int2>(), s);
             k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q);
             HD_LAUNCH_CHECK();
             HD_HIP(hipStreamSynchronize(s));

@@ -355,8 +355,9 @@ def test_small_capacity_still_certified():
 
 def test_round_limit_with_list_growth():
     """A round limit on the thin-triangle workload at full size, whose first
-    round outgrows the default frontier lists: the lists grow, the stalled
-    round does not count, and the partial intervals stay valid bounds."""
+    rounds outgrow the default frontier lists: the lists grow, the stalled
+    round does not count, the partial intervals stay valid bounds, and a
+    repeated call (now with grown lists) gives the same result."""
     hd, torch = _hd()
     W = wl.config(3)
     say("config3 full size with max_rounds 1, 2 and unlimited")
@@ -372,6 +373,10 @@ def test_round_limit_with_list_growth():
         assert st["subdivided"] > prev
         prev = st["subdivided"]
         assert L <= Lf and L <= Uf and Lf <= U
+    # the rounds split every active triangle whatever list sizes the earlier
+    # calls left: the same result again
+    L2, U2, s2 = hd.bound(*args, precision=hd.PREC_FP32)
+    assert (L2, U2, s2["subdivided"], s2["rounds"]) == (Lf, Uf, sf["subdivided"], sf["rounds"])
 
 
 @pytest.mark.parametrize("lanes", [1, 4])
