@@ -601,6 +601,30 @@ __global__ void k_pair_roots(int64_t ninternal, const int2 *__restrict__ range, 
     if (pairs[p].tri_begin == r.x && pairs[p].tri_end == (int64_t)r.y + 1) pairs[p].root = (int32_t)i;
 }
 
+// Entry t of pair 0's top-level table (see TOP_NODES), by thread t: entry
+// 0 the root, 1 + k the root's child k, 5 + 4k + m child m of that child
+// (entries of slots that are empty or leaves stay unused); references from
+// the root and its children to tabled nodes become TOP_REF + entry.
+__device__ void top_entry(const WideNode *__restrict__ nodes, int32_t root, WideNode *top, int t) {
+    if (t >= TOP_NODES) return;
+    int32_t x = root;
+    if (t >= 1) {
+        const int k = t <= 4 ? t - 1 : (t - 5) >> 2;
+        x = (&nodes[root].child.x)[k];
+        if (t >= 5 && x >= 0) x = (&nodes[x].child.x)[(t - 5) & 3];
+    }
+    if (x < 0) return;
+    WideNode w = nodes[x];
+    if (t <= 4) {
+        const int first = t == 0 ? 1 : 5 + 4 * (t - 1);
+        int32_t *ch = &w.child.x;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (ch[m] >= 0) ch[m] = TOP_REF + first + m;
+    }
+    top[t] = w;
+}
+
 // per-pair maxima; the root becomes a wide-node index (widx null: no
 // internal nodes)
 __global__ void k_pair_finish(const PairAcc *acc, int npairs, BvhPair *pairs, const int32_t *__restrict__ widx) {
@@ -609,6 +633,12 @@ __global__ void k_pair_finish(const PairAcc *acc, int npairs, BvhPair *pairs, co
     pairs[p].coord_max = ord2d(acc[p].coord_max);
     pairs[p].edge_max = ord2d(acc[p].edge_max);
     if (widx && pairs[p].root >= 0) pairs[p].root = widx[pairs[p].root];
+}
+
+// pair 0's top-level table (a single-pair BVH with an internal root)
+__global__ void k_wide_top(const WideNode *__restrict__ nodes, const BvhPair *pairs, WideNode *top) {
+    const int32_t root = pairs[0].root;
+    if (root >= 0) top_entry(nodes, root, top, threadIdx.x);
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -804,6 +834,10 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
                                                            b->nodes.as<WideNode>());
         }
         k_pair_finish<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs, n > 1 ? widx : nullptr);
+        if (npairs == 1 && n > 1) {
+            b->top.reserve((size_t)TOP_NODES * sizeof(WideNode));
+            k_wide_top<<<1, 64, 0, s>>>(b->nodes.as<WideNode>(), dpairs, b->top.as<WideNode>());
+        }
         HD_LAUNCH_CHECK();
         HD_HIP(hipEventRecord(sc.e1, s));
         Export ex{};

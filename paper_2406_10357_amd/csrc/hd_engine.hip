@@ -476,7 +476,8 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
 struct QueryCfg {
     const WideNode *nodes;
     const int4 *ids;
-    int raise_L; // fold d - mu into the lower bound and the argmax key
+    int raise_L;         // fold d - mu into the lower bound and the argmax key
+    const WideNode *top; // single-pair BVH: its top-level table (staged in LDS), else null
 };
 
 // writes the result; returns in *lord, *key what the pair's L and round key
@@ -593,8 +594,9 @@ __device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const TileOrder &t
 
 template <class T, int SD, int QB>
 __device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const TileOrder &to, const QueryCfg &cfg,
-                             const BView<T> &bv, const QueryOut<T> &out, const PairConst *__restrict__ pc,
-                             PairVar *pv, Ctl *ctl, int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
+                             const NodeSrc &ns, const BView<T> &bv, const QueryOut<T> &out,
+                             const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, int32_t *ovf_list, int *s_node,
+                             float *s_dist, QueryTally &t) {
     constexpr int NQ = QB / 4; // queries per tile
     const int g = threadIdx.x >> 2, k = threadIdx.x & 3;
     for (int64_t tt = to.first; to.valid(tt); tt += to.gx) {
@@ -611,7 +613,7 @@ __device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const TileOrder &t
             if (seed >= 0) visit_leaf(r, bv, cfg.ids, p, seed);
             quad_min(r);
             QuadStack<SD, NQ> stk{s_node, s_dist, g};
-            r = traverse4<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r, k);
+            r = traverse4<T>(ns, bv, cfg.ids, p, cfg.top ? TOP_REF : pc[qp.pair].root, stk, r, k);
             t.nb += r.nbox;
             t.nl += r.nleaf;
             if (k == 0) {
@@ -641,15 +643,26 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
                                               Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max) {
     __shared__ int s_node[SD * QB];
     __shared__ float s_dist[SD * QB];
+    __shared__ float4 s_top[TOP_NODES * 8];
     const int64_t n = cnt.get();
     const bool quad = n <= quad_max;
     const TileOrder to(n, quad ? QB / 4 : QB);
     if (!to.active()) return; // the grid is sized for a larger count
     QueryTally t;
-    if (quad)
-        query_lanes4<T, SD, QB>(in, n, to, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
-    else
+    if (quad) {
+        // few queries, each bound by its chain of dependent node reads:
+        // stage the top levels of the tree, where every traversal starts, in
+        // LDS (without a table no reference reaches the copy)
+        if (cfg.top) {
+            const float4 *src = reinterpret_cast<const float4 *>(cfg.top);
+            for (int i = threadIdx.x; i < TOP_NODES * 8; i += QB) s_top[i] = src[i];
+            __syncthreads();
+        }
+        const NodeSrc ns{cfg.nodes, (LdsFloat *)s_top};
+        query_lanes4<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    } else {
         query_lanes1<T, SD, QB>(in, n, to, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    }
     block_add<3, QB>({t.nb, t.nl, t.nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
     if (last_block(&ctl->q_done, to.active_blocks()))
         deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
@@ -1797,7 +1810,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const BView<double> bv64{B->frames64.as<double2>()};
     const IdView iv{B->ids.as<int4>()};
     const AView av{ws.Vcat.as<double>(), ws.Fcat.as<int32_t>(), pc};
-    const QueryCfg qcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 1};
+    // a single-pair BVH with an internal root has its top levels tabled
+    const WideNode *top = np == 1 && B->npairs == 1 && !B->hpairs.empty() && B->hpairs[0].root >= 0
+                              ? B->top.as<WideNode>()
+                              : nullptr;
+    const QueryCfg qcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 1, top};
     ws.gstack.reserve((size_t)np * DEEP_STACK * sizeof(int2));
     ws.deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
     const bool small_stack = opt.stack_depth > 0 && opt.stack_depth < QSTACK;
@@ -1835,7 +1852,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.voff = dvoff;
         qi.a = av;
         qi.pc = pc;
-        const QueryCfg tcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
+        const QueryCfg tcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
         ws.ovf.reserve((size_t)nref * sizeof(int32_t));
         if (ws.tune_ev[0] == nullptr)
             for (auto &e : ws.tune_ev) HD_HIP(hipEventCreate(&e));
@@ -2105,7 +2122,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             li.a = av;
             li.par = tw.act.v;
             li.pc = pc;
-            const QueryCfg lcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
+            const QueryCfg lcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
             launch_query<T>(qsel, nq, qmax, li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
@@ -2373,7 +2390,10 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
         PairVar *pv = pvb.as<PairVar>();
         k_ctl_init<<<1, 1, 0, s>>>(ctl);
         k_pairs_init<<<1, 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), 1);
-        const QueryCfg cfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0};
+        const WideNode *top = B->npairs == 1 && !B->hpairs.empty() && B->hpairs[0].root >= 0
+                                  ? B->top.as<WideNode>()
+                                  : nullptr;
+        const QueryCfg cfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
         auto go = [&](auto tag) {
             using T = decltype(tag);
             QBuf<T> qb;

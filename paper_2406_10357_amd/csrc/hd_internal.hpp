@@ -82,6 +82,7 @@ struct Bvh {
     int npairs = 0;
     int64_t nB = 0;
     DBuf nodes;    // four-wide nodes x 128 B (at most nB - 1 of them)
+    DBuf top;      // TOP_NODES x 128 B: the top levels of pair 0 (single-pair BVHs with an internal root)
     DBuf frames32; // nB x 64 B
     DBuf frames64; // nB x 128 B
     DBuf ids;      // nB x int4: corner vertex ids (frame order), original face index in its pair
@@ -164,6 +165,15 @@ struct alignas(128) WideNode {
     int4 meta; // (number of used slots, 0, 0, 0)
 };
 static_assert(sizeof(WideNode) == 128, "one cache line per node");
+
+// The top levels of a single-pair BVH (its root, the root's children and
+// their children: at most 1 + 4 + 16 nodes), copied into a table that query
+// kernels stage in LDS: entry 0 the root, 1 + k its child slot k, 5 + 4k + m
+// slot m of that child (entries for empty or leaf slots unused). Inside the
+// table a child that is itself tabled is referenced as TOP_REF + its entry;
+// other references are unchanged.
+constexpr int TOP_NODES = 21;
+constexpr int32_t TOP_REF = 1 << 30; // wide-node indices stay below it
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 

@@ -459,11 +459,29 @@ template <int SD, int NQ> struct QuadStack {
     HD_D void clear() { top = cnt = 0; }
 };
 
-// lane k's child of wide node w: box distance, reference
-template <class T> HD_D T slot_box_d2(const WideNode *w, int k, const V3<T> &p, int &ref) {
-    const float *b = reinterpret_cast<const float *>(w);
-    ref = reinterpret_cast<const int *>(w)[24 + k];
+// Where a quad's traversal reads wide nodes: references below TOP_REF from
+// global memory, TOP_REF + j from entry j of the top-level table staged in
+// LDS (typed as LDS, so that those reads are ds_read rather than flat loads).
+// Without a table no such reference occurs.
+typedef __attribute__((address_space(3))) const float LdsFloat;
+typedef __attribute__((address_space(3))) const int LdsInt;
+struct NodeSrc {
+    const WideNode *__restrict__ g;
+    LdsFloat *top; // the table as 32 words per node
+};
+
+// lane k's child of the wide node at b (32 words): box distance, reference
+template <class T, class F, class I> HD_D T slot_box_d2(F *b, I *c, int k, const V3<T> &p, int &ref) {
+    ref = c[24 + k];
     return box_d2<T>(make_float4(b[k], b[4 + k], b[8 + k], 0.f), make_float4(b[12 + k], b[16 + k], b[20 + k], 0.f), p);
+}
+template <class T> HD_D T slot_box_d2(const NodeSrc &ns, int x, int k, const V3<T> &p, int &ref) {
+    if (x >= TOP_REF) {
+        LdsFloat *b = ns.top + 32 * (x - TOP_REF);
+        return slot_box_d2<T>(b, (LdsInt *)b, k, p, ref);
+    }
+    const float *b = reinterpret_cast<const float *>(ns.g + x);
+    return slot_box_d2<T>(b, reinterpret_cast<const int *>(b), k, p, ref);
 }
 
 // The traversal of `traverse` (same pruning, same order of descent, same
@@ -471,8 +489,8 @@ template <class T> HD_D T slot_box_d2(const WideNode *w, int k, const V3<T> &p, 
 // result (d2, s, orig, overflow) is the same on all four lanes; nbox and
 // nleaf count each lane's own tests.
 template <class T, class Stack>
-HD_D QueryResult<T> traverse4(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
-                              const V3<T> &p, int root, Stack &st, QueryResult<T> r, int k) {
+HD_D QueryResult<T> traverse4(const NodeSrc &nodes, const BView<T> &bv, const int4 *__restrict__ ids, const V3<T> &p,
+                              int root, Stack &st, QueryResult<T> r, int k) {
     const T slack = T(1) + T(16 * Prec<T>::u);
     const T inf = T(__builtin_inf());
     if (root < 0) {
@@ -485,7 +503,7 @@ HD_D QueryResult<T> traverse4(const WideNode *__restrict__ nodes, const BView<T>
         int x = root;
         for (int guard = 0; guard < 64 && x >= 0; ++guard) {
             int ref;
-            const T dd = slot_box_d2<T>(nodes + x, k, p, ref);
+            const T dd = slot_box_d2<T>(nodes, x, k, p, ref);
             r.nbox += ref != WIDE_EMPTY;
             const T d0 = quad_bcast<0>(dd), d1 = quad_bcast<1>(dd), d2 = quad_bcast<2>(dd), d3 = quad_bcast<3>(dd);
             const int c0 = quad_bcast<0>(ref), c1 = quad_bcast<1>(ref), c2 = quad_bcast<2>(ref),
@@ -518,7 +536,7 @@ HD_D QueryResult<T> traverse4(const WideNode *__restrict__ nodes, const BView<T>
     int restarts = 0;
     while (true) {
         int f;
-        const T e = slot_box_d2<T>(nodes + node, k, p, f);
+        const T e = slot_box_d2<T>(nodes, node, k, p, f);
         r.nbox += f != WIDE_EMPTY;
         // triangles in range: each lane its own, then the quad's best
         const bool leaf = f < 0 && f != WIDE_EMPTY && e <= r.d2 * slack;
