@@ -52,8 +52,10 @@ def parse():
                     help="skip the learned-vs-plain comparison on the large torus")
     ap.add_argument("--learned-subbatch", type=int, default=8192)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB (x4): the reference for the HBM "
-                         "byte counters (FETCH_SIZE / WRITE_SIZE) of a rocprofv3 --pmc run")
+                    help="only run a plain device copy of MIB MiB (x4) and an FP32 elementwise product of "
+                         "as many floats (x4): the references for the HBM byte counters (FETCH_SIZE / "
+                         "WRITE_SIZE) and the FP32 FLOP counter (SQ_INSTS_VALU_FLOPS_FP32) of a rocprofv3 "
+                         "--pmc run")
     return ap.parse_args()
 
 
@@ -64,9 +66,13 @@ def calibrate_copy(mib):
     dst = torch.empty_like(src)
     for _ in range(4):
         dst.copy_(src)
+    out = torch.empty_like(src)
+    for _ in range(4):
+        torch.mul(src, dst, out=out)  # one FP32 multiply per element
     torch.cuda.synchronize()
-    print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": n * 4,
-                      "bytes_written_per_launch": n * 4, "launches": 4}), flush=True)
+    print(json.dumps({"calibration": "device copy, then elementwise FP32 product", "bytes_read_per_launch": n * 4,
+                      "bytes_written_per_launch": n * 4, "fp32_flop_per_product_launch": n, "launches": 4}),
+          flush=True)
 
 
 # HBM traffic of the query kernel from a rocprofv3 --pmc run, valid only for
@@ -102,7 +108,9 @@ def measured_traffic(config, tuned):
     if t.get("config") != config or t.get("source_sha256") != kernel_source_hash() or not tuned:
         return None
     v = t.get("per_variant", {}).get(query_kernel_name(tuned))
-    return v.get("hbm_bytes_per_launch") if v else None
+    # only a shape whose counters cover the launches of timed steps (the
+    # others were counted on the autotuner's trial launches alone)
+    return v.get("hbm_bytes_per_launch") if v and v.get("timed") else None
 
 
 def cpu_baseline(W, reps=3):
@@ -194,8 +202,8 @@ def main():
         calibrate_copy(a.calibrate_copy)
         return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build "
-              "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the library runs on one "
+              "GPU per process and has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -1840,9 +1840,10 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     };
 
     // ---- autotuner: the query kernel's launch shape -------------------------
-    // Times every variant on this call's vertex queries (no effect on L: the
-    // trial queries do not raise it) and keeps the fastest for this device and
-    // arithmetic; later calls reuse the choice.
+    // Times every variant on this call's vertex queries (best of three; no
+    // effect on L: the trial queries do not raise it) and keeps the fastest
+    // for this device and arithmetic, or the default when it is within 5% of
+    // the fastest; later calls reuse the choice.
     tw.vq.ensure(mA);
     if ((opt.autotune == 1 && !ws.tuned[sizeof(T) == 4 ? 0 : 1]) || opt.autotune == 2) {
         QueryIn<T> qi{};
@@ -1856,11 +1857,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         ws.ovf.reserve((size_t)nref * sizeof(int32_t));
         if (ws.tune_ev[0] == nullptr)
             for (auto &e : ws.tune_ev) HD_HIP(hipEventCreate(&e));
-        float best = 0;
+        float best = 0, t_default = 0;
         int pick = 0;
         for (int v = 0; v < NQVAR; ++v) {
             float t = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < 3; ++rep) {
                 k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
                 HD_HIP(hipEventRecord(ws.tune_ev[0], s));
                 launch_query<T>(v, nref, -1, qi, host_count(nref), tcfg, bv, tw.vq.o, pc, pv, ctl,
@@ -1871,11 +1872,15 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 HD_HIP(hipEventElapsedTime(&ms, ws.tune_ev[0], ws.tune_ev[1]));
                 t = std::min(t, ms);
             }
+            if (v == 0) t_default = t;
             if (v == 0 || t < best) {
                 best = t;
                 pick = v;
             }
         }
+        // keep the default unless another shape is clearly faster (timings
+        // of one launch vary by a few percent)
+        if (t_default <= 1.05f * best) pick = 0;
         k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
         qvar = pick;
         ws.tuned[sizeof(T) == 4 ? 0 : 1] = true;
