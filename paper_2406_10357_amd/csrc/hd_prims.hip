@@ -85,42 +85,90 @@ __global__ void k_scan_down(const int32_t *__restrict__ in, int32_t *__restrict_
 
 __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
-// Exclusive scan of a short array (n <= SMALL_SCAN_MAX) in one block: each
-// thread sums a contiguous chunk, the chunk sums are scanned in LDS, and each
-// thread writes its chunk's prefixes. One launch instead of three.
-constexpr int64_t SMALL_SCAN_MAX = 1 << 16;
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_small(const int32_t *__restrict__ in, int32_t *__restrict__ out,
-                                                           int64_t n, int32_t *d_total) {
-    const int64_t chunk = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    const int64_t b = (int64_t)threadIdx.x * chunk, e = b + chunk < n ? b + chunk : n;
-    int sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += in[i];
-    int tot;
-    int run = block_exclusive_scan(sum, &tot);
-    for (int64_t i = b; i < e; ++i) {
-        const int v = in[i];
-        out[i] = run;
-        run += v;
+// Exclusive scan of a short array (n <= SMALL_SCAN_MAX, 16-byte aligned) in
+// one block of SMALL_SCAN_BLOCK threads. The array is cut into tiles of
+// SMALL_SCAN_BLOCK x 4 values; thread t loads values 4t..4t+3 of every tile
+// (one coalesced 16-byte load per tile, all in flight at once), and the
+// block scans the per-thread sums of all tiles together (one LDS exchange),
+// each tile's total carried into the next. One launch instead of three.
+constexpr int SMALL_SCAN_BLOCK = 1024;
+constexpr int SMALL_SCAN_TILES = 8;
+constexpr int64_t SMALL_SCAN_TILE = (int64_t)SMALL_SCAN_BLOCK * 4;
+constexpr int64_t SMALL_SCAN_MAX = SMALL_SCAN_TILE * SMALL_SCAN_TILES;
+__global__ __launch_bounds__(SMALL_SCAN_BLOCK) void k_scan_small(const int32_t *__restrict__ in,
+                                                                 int32_t *__restrict__ out, int64_t n,
+                                                                 int32_t *d_total) {
+    constexpr int NW = SMALL_SCAN_BLOCK / 64;
+    __shared__ int wsum[SMALL_SCAN_TILES][NW];
+    const int w = threadIdx.x >> 6;
+    int4 v[SMALL_SCAN_TILES];
+    int sum[SMALL_SCAN_TILES], inc[SMALL_SCAN_TILES];
+#pragma unroll
+    for (int k = 0; k < SMALL_SCAN_TILES; ++k) {
+        const int64_t i = k * SMALL_SCAN_TILE + 4 * (int64_t)threadIdx.x;
+        if (i + 3 < n) {
+            v[k] = *reinterpret_cast<const int4 *>(in + i);
+        } else {
+            v[k].x = i < n ? in[i] : 0;
+            v[k].y = i + 1 < n ? in[i + 1] : 0;
+            v[k].z = i + 2 < n ? in[i + 2] : 0;
+            v[k].w = 0;
+        }
     }
-    if (threadIdx.x == 0 && d_total) *d_total = tot;
+#pragma unroll
+    for (int k = 0; k < SMALL_SCAN_TILES; ++k) {
+        sum[k] = v[k].x + v[k].y + v[k].z + v[k].w;
+        inc[k] = wave_inclusive_scan(sum[k]);
+        if (__lane_id() == 63) wsum[k][w] = inc[k];
+    }
+    __syncthreads();
+    int carry = 0;
+#pragma unroll
+    for (int k = 0; k < SMALL_SCAN_TILES; ++k) {
+        int off = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const int t = wsum[k][i];
+            if (i < w) off += t;
+            tot += t;
+        }
+        const int64_t i = k * SMALL_SCAN_TILE + 4 * (int64_t)threadIdx.x;
+        int4 o;
+        o.x = carry + off + inc[k] - sum[k];
+        o.y = o.x + v[k].x;
+        o.z = o.y + v[k].y;
+        o.w = o.z + v[k].z;
+        if (i + 3 < n) {
+            *reinterpret_cast<int4 *>(out + i) = o;
+        } else {
+            if (i < n) out[i] = o.x;
+            if (i + 1 < n) out[i + 1] = o.y;
+            if (i + 2 < n) out[i + 2] = o.z;
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && d_total) *d_total = carry;
 }
 
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 // ---------------------------------------------------------------------------
-// radix sort: 8-bit digits, one tile of RS_BLOCK * RS_ITEMS keys per block
+// radix sort: 8-bit digits, one tile of RS_BLOCK * items keys per block
+// (items: RS_ITEMS_MAX for long arrays; fewer for short ones, so that they
+// still spread over many blocks, each with a short serial loop)
 // ---------------------------------------------------------------------------
 constexpr int RS_BLOCK = 256;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
+constexpr int RS_ITEMS_MAX = 16;
 constexpr int RS_WAVES = RS_BLOCK / 64;
 
 template <class K>
-__global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift, int nblocks,
+__global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift, int nblocks, int items,
                              int32_t *__restrict__ hist) {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ITEMS; ++r) {
+    int64_t base = (int64_t)blockIdx.x * RS_BLOCK * items;
+    for (int r = 0; r < items; ++r) {
         int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1);
     }
@@ -133,7 +181,7 @@ __global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift, i
 // then ordered through per-digit counters in LDS.
 template <class K>
 __global__ void k_radix_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin, K *__restrict__ kout,
-                                int32_t *__restrict__ vout, int64_t n, int shift, int nblocks,
+                                int32_t *__restrict__ vout, int64_t n, int shift, int nblocks, int items,
                                 const int32_t *__restrict__ offs) {
     __shared__ int goff[256];
     __shared__ int wcnt[RS_WAVES][256];
@@ -142,8 +190,8 @@ __global__ void k_radix_scatter(const K *__restrict__ kin, const int32_t *__rest
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    for (int r = 0; r < RS_ITEMS; ++r) {
+    int64_t base = (int64_t)blockIdx.x * RS_BLOCK * items;
+    for (int r = 0; r < items; ++r) {
         for (int k = 0; k < RS_WAVES; ++k) wcnt[k][threadIdx.x] = 0;
         __syncthreads();
         int64_t i = base + (int64_t)r * RS_BLOCK + threadIdx.x;
@@ -183,7 +231,12 @@ template <class K>
 void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int64_t n, int bits, DBuf &tmp,
                      hipStream_t s) {
     if (n <= 1) return;
-    int nb = (int)((n + RS_TILE - 1) / RS_TILE);
+    // the fewest items per block that keep the digit histogram within one
+    // small scan (at most 128 blocks x 256 digits), at most RS_ITEMS_MAX
+    const int items =
+        (int)std::min<int64_t>(RS_ITEMS_MAX, std::max<int64_t>(1, (n + 128 * RS_BLOCK - 1) / (128 * RS_BLOCK)));
+    const int64_t tile = (int64_t)RS_BLOCK * items;
+    int nb = (int)((n + tile - 1) / tile);
     int64_t hn = 256LL * nb;
     int64_t scan_parts = (hn + SCAN_TILE - 1) / SCAN_TILE;
     tmp.reserve((size_t)(2 * hn + scan_parts + 64) * sizeof(int32_t));
@@ -195,15 +248,15 @@ void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int
     int passes = (bits + 7) / 8;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        k_radix_hist<K><<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, hist);
-        if (hn <= SMALL_SCAN_MAX / 4) {
-            k_scan_small<<<1, SCAN_BLOCK, 0, s>>>(hist, offs, hn, nullptr);
+        k_radix_hist<K><<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, items, hist);
+        if (hn <= SMALL_SCAN_MAX && aligned16(hist) && aligned16(offs)) {
+            k_scan_small<<<1, SMALL_SCAN_BLOCK, 0, s>>>(hist, offs, hn, nullptr);
         } else {
             k_scan_reduce<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, hn, part);
             k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, scan_parts, nullptr);
             k_scan_down<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, offs, hn, part);
         }
-        k_radix_scatter<K><<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, offs);
+        k_radix_scatter<K><<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, items, offs);
         HD_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);
@@ -255,8 +308,8 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_t
         if (d_total) k_zero_i32<<<1, 1, 0, s>>>(d_total);
         return;
     }
-    if (n <= SMALL_SCAN_MAX / 4) {
-        k_scan_small<<<1, SCAN_BLOCK, 0, s>>>(in, out, n, d_total);
+    if (n <= SMALL_SCAN_MAX && aligned16(in) && aligned16(out)) {
+        k_scan_small<<<1, SMALL_SCAN_BLOCK, 0, s>>>(in, out, n, d_total);
         HD_LAUNCH_CHECK();
         return;
     }
