@@ -141,6 +141,15 @@ hd_status hd_build_bvh_batched(int32_t npairs, const double *const *VB, const in
  * the same device instead of freeing them. */
 void hd_free_bvh(hd_bvh bvh);
 
+/* Whether hd_build_bvh / hd_build_bvh_batched run the build as a HIP graph
+ * (default 1): the build's copies and kernels depend only on the soup sizes
+ * and the buffers, so they are captured once per (sizes, buffers) and
+ * replayed by later builds, one graph launch instead of about 30 kernel
+ * launches (a few graphs are kept per device). 0 launches every kernel
+ * directly. The result is the same either way. Returns the previous
+ * setting; the setting is process-wide. */
+int32_t hd_build_graphs(int32_t enable);
+
 /* Certified [L, U] for h(A, B), B given by its BVH; eps is the paper's
  * relative tolerance (eq. output_bounds), so U - L <= eps * dA on success.
  * opt may be NULL (defaults). LU_out is a HOST array of 2 doubles; stats is a

@@ -61,7 +61,8 @@ class Stats(C.Structure):
 
 EXPORTS = ["hd_build_bvh", "hd_build_bvh_batched", "hd_free_bvh", "hd_bound", "hd_bound_batched",
            "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options",
-           "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train", "hd_frontier_features"]
+           "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train", "hd_frontier_features",
+           "hd_build_graphs"]
 
 
 def load_library(path: str | None = None):
@@ -79,6 +80,8 @@ def load_library(path: str | None = None):
     lib.hd_build_bvh.argtypes = [vp, i64, vp, i64, vp, C.POINTER(vp)]
     lib.hd_free_bvh.restype = None
     lib.hd_free_bvh.argtypes = [vp]
+    lib.hd_build_graphs.restype = i32
+    lib.hd_build_graphs.argtypes = [i32]
     lib.hd_bound.restype = i32
     lib.hd_bound.argtypes = [vp, i64, vp, i64, vp, dbl, C.POINTER(Options), vp, C.POINTER(C.c_double),
                              C.POINTER(Stats)]
@@ -240,6 +243,12 @@ def bound_batched(meshes, bvh: Bvh, eps, **opts):
                               LU, C.byref(stats))
     _check(st, "hd_bound_batched")
     return [LU[2 * i] for i in range(n)], [LU[2 * i + 1] for i in range(n)], stats.as_dict()
+
+
+def build_graphs(enable: bool) -> bool:
+    """Whether BVH builds run as captured HIP graphs (process-wide); returns
+    the previous setting."""
+    return bool(load_library().hd_build_graphs(1 if enable else 0))
 
 
 def point_distances(P, bvh: Bvh, precision=PREC_FP64, lanes=1):

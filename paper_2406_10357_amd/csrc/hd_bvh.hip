@@ -16,6 +16,7 @@
 // inside one 256-leaf tile are refit by that tile's workgroup (workgroup-scope
 // counters); the few nodes above the tiles are refit by a single workgroup,
 // in sweeps.
+#include <atomic>
 #include <memory>
 #include <mutex>
 
@@ -649,13 +650,28 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 // build scratch, reused between builds on the same device; kept until the
 // process ends (never destroyed: the HIP runtime may be gone by static
 // destruction). A build that finds it busy uses a private one.
+//
+// The build is a fixed sequence of copies and kernels whose arguments depend
+// only on the soup sizes and on the buffers (not on the data, which the
+// device reads through the staged source records). It is captured once into a
+// HIP graph per (sizes, buffers) and replayed on later builds: one graph
+// launch instead of ~30 kernel launches, so the GPU runs the short build
+// kernels back to back instead of waiting on the host for each. A few graphs
+// are kept per device (builds alternate between the pooled BVH handles).
+constexpr int BUILD_GRAPHS = 4;
+constexpr int BUILD_KEY = 14;
+struct BuildGraph {
+    uintptr_t key[BUILD_KEY];
+    hipGraphExec_t exec = nullptr;
+};
 struct BuildScratch {
     std::mutex mu;
     DBuf mem, sort_tmp, src, scan_tmp;
     PinnedBuf host; // [0, 4) export sequence word; staged uploads; exported results
-    unsigned seq = 0;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t capture = nullptr;     // stream the build is captured on (never run)
+    std::vector<BuildGraph> graphs;    // most recently used last
 };
+std::atomic<int> g_build_graphs{1};
 std::mutex g_scratch_mu;
 BuildScratch *g_scratch[64] = {};
 BuildScratch *scratch_for(int dev) {
@@ -682,6 +698,8 @@ Bvh *take_bvh(int dev) {
 }
 
 } // namespace
+
+int set_build_graphs(int enable) { return g_build_graphs.exchange(enable ? 1 : 0); }
 
 void recycle_bvh(Bvh *b) {
     if (!b) return;
@@ -726,11 +744,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         BuildScratch &sc = lk.owns_lock() ? *shared : *priv;
         b->npairs = npairs;
         b->nB = n;
-        if (!sc.e0) {
-            HD_HIP(hipEventCreate(&sc.e0));
-            HD_HIP(hipEventCreate(&sc.e1));
-        }
-        HD_HIP(hipEventRecord(sc.e0, s));
         // pinned staging: sources and face offsets, pair records; results
         auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
         const size_t o_src = 256, o_foff = o_src + al(npairs * sizeof(PairSrc)),
@@ -784,15 +797,25 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         float4 *lbox = (float4 *)(base + o_lbox);
         float4 *nbox = (float4 *)(base + o_nbox);
 
-        // per-pair sources and face offsets
+        // every buffer the build writes, reserved before any work is enqueued
+        // (the enqueued sequence allocates nothing, so that it can be captured)
+        sc.src.reserve(o_pairs - o_src);
+        b->pairs.reserve(npairs * sizeof(BvhPair));
+        b->nodes.reserve(ni * sizeof(WideNode));
+        b->frames32.reserve(n * 4 * sizeof(float4));
+        b->frames64.reserve(n * 8 * sizeof(double2));
+        b->ids.reserve(n * sizeof(int4));
+        const bool with_top = npairs == 1 && n > 1;
+        if (with_top) b->top.reserve((size_t)TOP_NODES * sizeof(WideNode));
+        sc.sort_tmp.reserve(radix_sort_tmp_bytes(n));
+        sc.scan_tmp.reserve(scan_tmp_bytes(ni));
+        int pair_bits = 0;
+        while ((1 << pair_bits) < npairs) ++pair_bits;
+
+        // per-pair sources and face offsets, pair records: staged in pinned memory
         PairSrc *hsrc = sc.host.as<PairSrc>(o_src);
         for (int p = 0; p < npairs; ++p) hsrc[p] = PairSrc{VB[p], FB[p], mB[p]};
         std::memcpy(sc.host.as<char>(o_foff), foff.data(), (npairs + 1) * sizeof(int64_t));
-        // source records and offsets share one device block with the pinned layout
-        sc.src.reserve(o_pairs - o_src);
-        PairSrc *dsrc = sc.src.as<PairSrc>();
-        int64_t *dfoff = (int64_t *)(sc.src.as<char>() + (o_foff - o_src));
-        HD_HIP(hipMemcpyAsync(dsrc, sc.host.as<char>(o_src), o_pairs - o_src, hipMemcpyHostToDevice, s));
         BvhPair *hp = sc.host.as<BvhPair>(o_pairs);
         for (int p = 0; p < npairs; ++p) {
             hp[p] = BvhPair{};
@@ -801,60 +824,107 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
             hp[p].nB = (int32_t)nBp[p];
             hp[p].root = nBp[p] == 1 ? ~(int32_t)foff[p] : -1;
         }
-        b->pairs.reserve(npairs * sizeof(BvhPair));
+        // source records and offsets share one device block with the pinned layout
+        PairSrc *dsrc = sc.src.as<PairSrc>();
+        int64_t *dfoff = (int64_t *)(sc.src.as<char>() + (o_foff - o_src));
         BvhPair *dpairs = b->pairs.as<BvhPair>();
-        HD_HIP(hipMemcpyAsync(dpairs, hp, npairs * sizeof(BvhPair), hipMemcpyHostToDevice, s));
 
-        k_init<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, st);
-        k_faces_check<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, acc, st);
-        k_pair_centres<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs);
-        k_centroids<<<grid_for(std::max<int64_t>(n, ni), BLK), BLK, 0, s>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
-                                                                             acc, st, keys, vals, cnt, ni);
-        HD_LAUNCH_CHECK();
-        int pair_bits = 0;
-        while ((1 << pair_bits) < npairs) ++pair_bits;
-        radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, s);
-
-        b->nodes.reserve(ni * sizeof(WideNode));
-        b->frames32.reserve(n * 4 * sizeof(float4));
-        b->frames64.reserve(n * 8 * sizeof(double2));
-        b->ids.reserve(n * sizeof(int4));
-        k_leaves<<<grid_for(n, BLK), BLK, 0, s>>>(dsrc, dfoff, fpair, vals, n, dpairs, lbox, b->frames32.as<float4>(),
-                                                  b->frames64.as<double2>(), b->ids.as<int4>(), acc, st);
-        HD_LAUNCH_CHECK();
-        if (n > 1) {
-
-            k_karras<<<grid_for(ni, BLK), BLK, 0, s>>>(keys, n, cl, cr, pn, pl, range, upper, st);
-            k_refit_tiles<<<grid_for(n, TILE), TILE, 0, s>>>(n, cl, cr, pn, pl, range, lbox, nbox, cnt);
-            k_refit_upper<<<1, 1024, 0, s>>>(upper, st, cl, cr, pn, range, lbox, nbox, cnt);
-            k_pair_roots<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, range, dpairs, npairs, keys);
-            k_wide_flags<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, pn, range, dpairs, npairs, keys, flag);
-            scan_exclusive_i32(flag, widx, ni, &st->n_wide, sc.scan_tmp, s);
-            k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, s>>>(ni, flag, widx, cl, cr, nbox, lbox,
-                                                           b->nodes.as<WideNode>());
+        // the build, then the export of its state and pair records with
+        // sequence word 1 (the host clears the word before each build)
+        auto enqueue = [&](hipStream_t q) {
+            HD_HIP(hipMemcpyAsync(dsrc, sc.host.as<char>(o_src), o_pairs - o_src, hipMemcpyHostToDevice, q));
+            HD_HIP(hipMemcpyAsync(dpairs, hp, npairs * sizeof(BvhPair), hipMemcpyHostToDevice, q));
+            k_init<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, st);
+            k_faces_check<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, st);
+            k_pair_centres<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, dpairs);
+            k_centroids<<<grid_for(std::max<int64_t>(n, ni), BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
+                                                                                 acc, st, keys, vals, cnt, ni);
+            HD_LAUNCH_CHECK();
+            radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, q);
+            k_leaves<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, fpair, vals, n, dpairs, lbox,
+                                                      b->frames32.as<float4>(), b->frames64.as<double2>(),
+                                                      b->ids.as<int4>(), acc, st);
+            HD_LAUNCH_CHECK();
+            if (n > 1) {
+                k_karras<<<grid_for(ni, BLK), BLK, 0, q>>>(keys, n, cl, cr, pn, pl, range, upper, st);
+                k_refit_tiles<<<grid_for(n, TILE), TILE, 0, q>>>(n, cl, cr, pn, pl, range, lbox, nbox, cnt);
+                k_refit_upper<<<1, 1024, 0, q>>>(upper, st, cl, cr, pn, range, lbox, nbox, cnt);
+                k_pair_roots<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, range, dpairs, npairs, keys);
+                k_wide_flags<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, pn, range, dpairs, npairs, keys, flag);
+                scan_exclusive_i32(flag, widx, ni, &st->n_wide, sc.scan_tmp, q);
+                k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, widx, cl, cr, nbox, lbox,
+                                                               b->nodes.as<WideNode>());
+            }
+            k_pair_finish<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, dpairs, n > 1 ? widx : nullptr);
+            if (with_top) k_wide_top<<<1, 64, 0, q>>>(b->nodes.as<WideNode>(), dpairs, b->top.as<WideNode>());
+            HD_LAUNCH_CHECK();
+            Export ex{};
+            ex.n = 2;
+            ex.src[0] = st;
+            ex.dst[0] = sc.host.dev_as<char>(o_rst);
+            ex.bytes[0] = sizeof(BuildState);
+            ex.src[1] = dpairs;
+            ex.dst[1] = sc.host.dev_as<char>(o_rpairs);
+            ex.bytes[1] = npairs * sizeof(BvhPair);
+            export_to_host(ex, sc.host.dev_as<unsigned>(0), 1u, q);
+        };
+        unsigned *seq_word = sc.host.as<unsigned>(0);
+        __atomic_store_n(seq_word, 0u, __ATOMIC_RELEASE);
+        if (lk.owns_lock() && g_build_graphs.load()) {
+            const uintptr_t key[BUILD_KEY] = {(uintptr_t)n,
+                                              (uintptr_t)npairs,
+                                              (uintptr_t)sc.mem.p,
+                                              (uintptr_t)sc.src.p,
+                                              (uintptr_t)sc.sort_tmp.p,
+                                              (uintptr_t)sc.scan_tmp.p,
+                                              (uintptr_t)sc.host.p,
+                                              (uintptr_t)b->pairs.p,
+                                              (uintptr_t)b->nodes.p,
+                                              (uintptr_t)b->frames32.p,
+                                              (uintptr_t)b->frames64.p,
+                                              (uintptr_t)b->ids.p,
+                                              (uintptr_t)(with_top ? b->top.p : nullptr),
+                                              (uintptr_t)dev};
+            hipGraphExec_t exec = nullptr;
+            for (size_t g = 0; g < sc.graphs.size(); ++g)
+                if (std::memcmp(sc.graphs[g].key, key, sizeof(key)) == 0) {
+                    BuildGraph hit = sc.graphs[g];
+                    sc.graphs.erase(sc.graphs.begin() + g);
+                    sc.graphs.push_back(hit);
+                    exec = hit.exec;
+                    break;
+                }
+            if (!exec) {
+                if (!sc.capture) HD_HIP(hipStreamCreateWithFlags(&sc.capture, hipStreamNonBlocking));
+                HD_HIP(hipStreamBeginCapture(sc.capture, hipStreamCaptureModeRelaxed));
+                hipGraph_t graph = nullptr;
+                try {
+                    enqueue(sc.capture);
+                } catch (...) {
+                    if (hipStreamEndCapture(sc.capture, &graph) == hipSuccess && graph) (void)hipGraphDestroy(graph);
+                    (void)hipGetLastError();
+                    throw;
+                }
+                HD_HIP(hipStreamEndCapture(sc.capture, &graph));
+                const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ie != hipSuccess) throw Error{HD_E_DEVICE, hipGetErrorString(ie)};
+                if ((int)sc.graphs.size() == BUILD_GRAPHS) {
+                    (void)hipGraphExecDestroy(sc.graphs.front().exec);
+                    sc.graphs.erase(sc.graphs.begin());
+                }
+                BuildGraph bg;
+                std::memcpy(bg.key, key, sizeof(key));
+                bg.exec = exec;
+                sc.graphs.push_back(bg);
+            }
+            HD_HIP(hipGraphLaunch(exec, s));
+        } else {
+            enqueue(s);
         }
-        k_pair_finish<<<grid_for(npairs, 64), 64, 0, s>>>(acc, npairs, dpairs, n > 1 ? widx : nullptr);
-        if (npairs == 1 && n > 1) {
-            b->top.reserve((size_t)TOP_NODES * sizeof(WideNode));
-            k_wide_top<<<1, 64, 0, s>>>(b->nodes.as<WideNode>(), dpairs, b->top.as<WideNode>());
-        }
-        HD_LAUNCH_CHECK();
-        HD_HIP(hipEventRecord(sc.e1, s));
-        Export ex{};
-        ex.n = 2;
-        ex.src[0] = st;
-        ex.dst[0] = sc.host.dev_as<char>(o_rst);
-        ex.bytes[0] = sizeof(BuildState);
-        ex.src[1] = dpairs;
-        ex.dst[1] = sc.host.dev_as<char>(o_rpairs);
-        ex.bytes[1] = npairs * sizeof(BvhPair);
-        const unsigned seq = ++sc.seq;
-        export_to_host(ex, sc.host.dev_as<unsigned>(0), seq, s);
-        wait_host_seq(sc.host.as<unsigned>(0), seq, s);
+        wait_host_seq(seq_word, 1u, s);
         const BuildState hs = *sc.host.as<BuildState>(o_rst);
         b->hpairs.assign(sc.host.as<BvhPair>(o_rpairs), sc.host.as<BvhPair>(o_rpairs) + npairs);
-        HD_HIP(hipEventSynchronize(sc.e1));
-        HD_HIP(hipEventElapsedTime(&b->ms_build, sc.e0, sc.e1));
         if (hs.bad) throw Error{HD_E_INVALID, "soup B has an out-of-range index or a non-finite coordinate"};
         for (int p = 0; p < npairs; ++p)
             if (b->hpairs[p].nB > 1 && b->hpairs[p].root < 0) throw Error{HD_E_INTERNAL, "pair subtree root not found"};

@@ -2346,6 +2346,8 @@ hd_status hd_build_bvh_batched(int32_t npairs, const double *const *VB, const in
 
 void hd_free_bvh(hd_bvh b) { recycle_bvh(reinterpret_cast<Bvh *>(b)); }
 
+int32_t hd_build_graphs(int32_t enable) { return set_build_graphs(enable); }
+
 hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, hd_bvh Bh, double eps,
                    const hd_options *opt, hd_stream_t stream, double LU_out[2], hd_stats *stats) {
     if (LU_out) LU_out[0] = LU_out[1] = NAN;

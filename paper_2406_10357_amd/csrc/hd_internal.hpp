@@ -88,7 +88,6 @@ struct Bvh {
     DBuf ids;      // nB x int4: corner vertex ids (frame order), original face index in its pair
     DBuf pairs;    // npairs x BvhPair
     std::vector<BvhPair> hpairs;
-    float ms_build = 0;
 };
 
 // Owning pinned host buffer (hipHostMalloc, mapped and coherent), used to
@@ -137,6 +136,10 @@ void wait_host_seq(const unsigned *seq_host, unsigned seq, hipStream_t s);
 hd_status mlp_forward(const float *X, int64_t n, const float *params, float *y, hipStream_t s);
 
 // --- primitives (hd_prims.hip) -------------------------------------------
+// Scratch bytes (the tmp buffer) the scan and the radix sort below need for
+// n values: reserved up front, they add no allocation to a call.
+size_t scan_tmp_bytes(int64_t n);
+size_t radix_sort_tmp_bytes(int64_t n);
 // Exclusive scan of n int32 values; total in *d_total (device, may be null).
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,
                         hipStream_t s);
@@ -153,6 +156,9 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
                const int64_t *nB, hipStream_t s);
 // Release a BVH (waits for the device; its buffers may serve a later build).
 void recycle_bvh(Bvh *b);
+// whether BVH builds are captured into (and replayed from) HIP graphs;
+// returns the previous setting
+int set_build_graphs(int enable);
 
 // Four-wide BVH node, one 128-byte line: the boxes of up to four children
 // (structure of arrays: component c of child k at lo*/hi*[k]) and their

@@ -227,19 +227,30 @@ __global__ void k_radix_scatter(const K *__restrict__ kin, const int32_t *__rest
     }
 }
 
+// launch plan of a radix sort of n keys: the fewest items per block that
+// keep the digit histogram within one small scan (at most 128 blocks x 256
+// digits), at most RS_ITEMS_MAX
+struct RadixPlan {
+    int items, nb;
+    int64_t hn, scan_parts;
+    explicit RadixPlan(int64_t n) {
+        items = (int)std::min<int64_t>(RS_ITEMS_MAX, std::max<int64_t>(1, (n + 128 * RS_BLOCK - 1) / (128 * RS_BLOCK)));
+        const int64_t tile = (int64_t)RS_BLOCK * items;
+        nb = (int)((n + tile - 1) / tile);
+        hn = 256LL * nb;
+        scan_parts = (hn + SCAN_TILE - 1) / SCAN_TILE;
+    }
+    size_t tmp_bytes() const { return (size_t)(2 * hn + scan_parts + 64) * sizeof(int32_t); }
+};
+
 template <class K>
 void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int64_t n, int bits, DBuf &tmp,
                      hipStream_t s) {
     if (n <= 1) return;
-    // the fewest items per block that keep the digit histogram within one
-    // small scan (at most 128 blocks x 256 digits), at most RS_ITEMS_MAX
-    const int items =
-        (int)std::min<int64_t>(RS_ITEMS_MAX, std::max<int64_t>(1, (n + 128 * RS_BLOCK - 1) / (128 * RS_BLOCK)));
-    const int64_t tile = (int64_t)RS_BLOCK * items;
-    int nb = (int)((n + tile - 1) / tile);
-    int64_t hn = 256LL * nb;
-    int64_t scan_parts = (hn + SCAN_TILE - 1) / SCAN_TILE;
-    tmp.reserve((size_t)(2 * hn + scan_parts + 64) * sizeof(int32_t));
+    const RadixPlan rp(n);
+    const int items = rp.items, nb = rp.nb;
+    const int64_t hn = rp.hn, scan_parts = rp.scan_parts;
+    tmp.reserve(rp.tmp_bytes());
     int32_t *hist = tmp.as<int32_t>();
     int32_t *offs = hist + hn;
     int32_t *part = offs + hn;
@@ -301,6 +312,9 @@ void wait_host_seq(const unsigned *seq_host, unsigned seq, hipStream_t s) {
         __builtin_ia32_pause();
     }
 }
+
+size_t radix_sort_tmp_bytes(int64_t n) { return n <= 1 ? 0 : RadixPlan(n).tmp_bytes(); }
+size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) * sizeof(int32_t); }
 
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,
                         hipStream_t s) {

@@ -562,3 +562,46 @@ def test_translation_closed_form():
     for prec in (hd.PREC_FP64, hd.PREC_FP32_RECHECK):
         L, U, st = hd.bound(_cu(V, torch), _cu(F, torch), bvh, 1e-6, precision=prec)
         assert L <= t + 1e-12 <= U + 2e-12 and U - L <= st["eps_abs"] * (1 + 1e-12)
+
+
+def test_build_graph_replays_match_eager():
+    """BVH builds replayed from captured HIP graphs give what direct launches
+    give: the same closest faces, distances and closest points, bit for bit,
+    on every replay, with builds of other sizes (other graphs), direct builds
+    and bound calls in between."""
+    hd, torch = _hd()
+    rng = np.random.default_rng(17)
+    soups = [wl.config(2, scale=0.05), wl.config(1), wl.config(3, scale=0.02)]
+    pts = []
+    for W in soups:
+        lo, hi = W.VB.min(0), W.VB.max(0)
+        pts.append(_cu(np.concatenate([rng.uniform(lo - 0.05, hi + 0.05, size=(700, 3)), W.VA[:300]]), torch))
+    dev = [(_cu(W.VB, torch), _cu(W.FB, torch)) for W in soups]
+
+    def run(k, graphs):
+        hd.build_graphs(graphs)
+        bvh = hd.build_bvh(*dev[k])
+        out = []
+        for prec in (hd.PREC_FP64, hd.PREC_FP32):
+            d, I, Q = hd.point_distances(pts[k], bvh, precision=prec)
+            out += [d.cpu().numpy(), I.cpu().numpy(), Q.cpu().numpy()]
+        W = soups[k]
+        L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+        torch.cuda.synchronize()
+        return out, (L, U, st["subdivided"], st["nodes_bounded"])
+
+    try:
+        eager = [run(k, False) for k in range(len(soups))]
+        for rep in range(4):
+            for k in (0, 1, 2, 0):
+                say("graph build, soup", k, "replay", rep)
+                got = run(k, True)
+                for a, b in zip(got[0], eager[k][0]):
+                    assert np.array_equal(a, b)
+                assert got[1] == eager[k][1]
+            k = rep % len(soups)
+            say("direct build between replays, soup", k)
+            got = run(k, False)
+            assert got[1] == eager[k][1]
+    finally:
+        hd.build_graphs(True)
