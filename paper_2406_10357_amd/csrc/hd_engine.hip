@@ -177,10 +177,6 @@ __device__ void pair_max2(PairVar *pv, int pair, unsigned long long a, unsigned 
     }
 }
 
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
 __global__ void k_ctl_init(Ctl *c) { memset(c, 0, sizeof(Ctl)); }
 
@@ -281,9 +277,7 @@ __global__ void k_round_setup(Ctl *c, unsigned long long act_base, unsigned long
     c->c_next = 0;
 }
 
-__global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int npairs) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
+__device__ void pair_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int p) {
     PairConst c;
     memset(&c, 0, sizeof(c));
     PairVar d;
@@ -300,6 +294,20 @@ __global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restri
     d.coord_max = d2ord(0.0);
     pc[p] = c;
     pv[p] = d;
+}
+
+__global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int npairs) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npairs) pair_init(pc, pv, bp, p);
+}
+
+// the start of a call: control block, pair tables, referenced-vertex marks
+__global__ void k_bound_init(Ctl *ctl, PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int npairs,
+                             int32_t *__restrict__ ref, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) memset(ctl, 0, sizeof(Ctl));
+    if (i < npairs) pair_init(pc, pv, bp, (int)i);
+    if (i < m) ref[i] = 0;
 }
 
 // Validate A's faces, gather every pair's faces into one array with global
@@ -356,10 +364,10 @@ __device__ Margins make_margins(double u, double edge_max, double coord_max) {
     return m;
 }
 
-__global__ void k_pairs_post(PairConst *pc, const PairVar *pv, const BvhPair *__restrict__ bp, int npairs,
-                             const double *__restrict__ eps, int eps_per_pair) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
+// pair p's dA, eps * dA and margins, once the ingest has its bbox and
+// coordinate range
+__device__ void pair_post(PairConst *pc, const PairVar *pv, const BvhPair *__restrict__ bp, int p,
+                          const double *__restrict__ eps, int eps_per_pair) {
     double d2 = 0;
     for (int k = 0; k < 3; ++k) {
         double e = ord2d(pv[p].bbox[3 + k]) - ord2d(pv[p].bbox[k]);
@@ -373,11 +381,22 @@ __global__ void k_pairs_post(PairConst *pc, const PairVar *pv, const BvhPair *__
     pc[p].m64 = make_margins(Prec<double>::u, bp[p].edge_max, cm);
 }
 
-// compact the referenced vertex ids (order preserving)
-__global__ void k_ref_scatter(const int32_t *__restrict__ ref, const int32_t *__restrict__ pos, int64_t m,
-                              int32_t *__restrict__ out) {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// after the ingest: compact the referenced vertex ids (order preserving),
+// finish the pair tables, and set up round 0's counters
+__global__ void k_ingest_post(const int32_t *__restrict__ ref, const int32_t *__restrict__ pos, int64_t m,
+                              int32_t *__restrict__ out, PairConst *pc, const PairVar *pv,
+                              const BvhPair *__restrict__ bp, int npairs, const double *__restrict__ eps,
+                              int eps_per_pair, Ctl *ctl) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < m && ref[v]) out[pos[v]] = (int32_t)v;
+    if (v < npairs) pair_post(pc, pv, bp, (int)v, eps, eps_per_pair);
+    if (v == 0) {
+        ctl->n_overflow = 0;
+        ctl->act_next = 0;
+        ctl->park_next = 0;
+        ctl->b_next = 0;
+        ctl->c_next = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1789,19 +1808,18 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     int32_t *refpos = ref + ((mA + 63) / 64) * 64;
     ws.small.reserve(4096);
     int32_t *d_total = ws.small.as<int32_t>();
-    k_ctl_init<<<1, 1, 0, s>>>(ctl);
-    k_pairs_init<<<grid_for(np, 64), 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), np);
-    k_fill_i32<<<grid_for(mA, BLK), BLK, 0, s>>>(ref, mA, 0);
+    k_bound_init<<<grid_for(std::max<int64_t>(mA, np), BLK), BLK, 0, s>>>(ctl, pc, pv, B->pairs.as<BvhPair>(), np,
+                                                                          ref, mA);
     k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
                                               ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pv, ctl);
-    k_pairs_post<<<grid_for(np, 64), 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair);
     scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
     HD_LAUNCH_CHECK();
     const Mailbox h0 = report(d_total);
     if (h0.bad) throw Error{HD_E_INVALID, "soup A has an out-of-range index or a non-finite coordinate"};
     const int64_t nref = h0.nref;
     ws.vids.reserve(nref * sizeof(int32_t));
-    k_ref_scatter<<<grid_for(mA, BLK), BLK, 0, s>>>(ref, refpos, mA, ws.vids.as<int32_t>());
+    k_ingest_post<<<grid_for(std::max<int64_t>(mA, np), BLK), BLK, 0, s>>>(
+        ref, refpos, mA, ws.vids.as<int32_t>(), pc, pv, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair, ctl);
 
     const BView<T> bv = [&] {
         if constexpr (sizeof(T) == 4) return BView<float>{B->frames32.as<float4>()};
@@ -1900,8 +1918,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.voff = dvoff;
         qi.a = av;
         qi.pc = pc;
-        k_round_setup<<<1, 1, 0, s>>>(ctl, 0, 0);
-        run_queries(qi, host_count(nref), nref, tw.vq.o);
+        run_queries(qi, host_count(nref), nref, tw.vq.o); // counters set by k_ingest_post
     }
 
     // ---- frontier buffers ---------------------------------------------------
