@@ -776,22 +776,30 @@ __global__ void k_zero_query_stats(Ctl *c) {
 // FP64 distance of pair p's best vertex when it changed: the lower bound
 // then carries the FP64 margin instead of the FP32 one, which the recheck
 // band needs to park triangles within eps of it
-__device__ void l64_pair(const WideNode *nodes, const BView<double> &bv64, const int4 *ids, const PairConst *pc,
-                         PairVar *pv, int p, int npairs, int2 *stack_mem) {
+__device__ void l64_pair(const NodeSrc &ns, const BView<double> &bv64, const int4 *ids, const PairConst *pc,
+                         PairVar *pv, int p, int npairs, int2 *stack_mem, int k) {
+    // run by the four lanes of a quad (k = lane in the quad): all read, lane 0 writes
     PairVar &P = pv[p];
     const PairConst &C = pc[p];
-    if (P.round_key > P.best_key) P.best_key = P.round_key;
-    P.round_key = 0;
-    if (!P.argmax_dirty) return;
-    P.argmax_dirty = 0;
-    V3<double> x = {P.argmax_pos[0], P.argmax_pos[1], P.argmax_pos[2]};
+    const unsigned long long rk = P.round_key, bk = P.best_key;
+    const int dirty = P.argmax_dirty;
+    const V3<double> x = {P.argmax_pos[0], P.argmax_pos[1], P.argmax_pos[2]};
+    const int tri = P.argmax_tri;
+    if (k == 0) {
+        if (rk > bk) P.best_key = rk;
+        P.round_key = 0;
+        P.argmax_dirty = 0;
+    }
+    if (!dirty) return;
+    // every lane of the quad sees the same stack state and writes the same entries
     GlobalStack stk{stack_mem + p, npairs, DEEP_STACK, 0};
     // the FP32 query's closest triangle bounds the FP64 distance from above,
     // so the traversal starts with a tight pruning radius
     QueryResult<double> r = empty_result<double>();
-    visit_leaf(r, bv64, ids, x, P.argmax_tri);
-    r = traverse<double>(nodes, bv64, ids, x, C.root, stk, r);
-    if (r.overflow || r.s < 0) return;
+    if (k == 0) visit_leaf(r, bv64, ids, x, tri);
+    quad_min(r);
+    r = traverse4<double>(ns, bv64, ids, x, C.root, stk, r, k);
+    if (k != 0 || r.overflow || r.s < 0) return;
     double d = sqrt(r.d2);
     double dlo = d - (C.m64.mu_d * d + C.m64.mu_0);
     P.L64 = dlo;
@@ -810,6 +818,7 @@ struct L64Cfg {
 // after a query round: the query holding its pair's best key records its
 // exact position (keys are unique up to a tag collision of one point); the
 // block that finishes last then takes each pair's new best point to FP64
+// (a quad of lanes per pair: the traversal is one latency-bound chain)
 template <class T>
 __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount cnt,
                                                          const unsigned long long *__restrict__ keys,
@@ -831,9 +840,12 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
         }
     }
     const int64_t need = (n + BLK - 1) / BLK;
-    if (last_block(&ctl->f_done, (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x)))
-        for (int p = threadIdx.x; p < lc.npairs; p += blockDim.x)
-            l64_pair(lc.nodes, lc.bv64, lc.ids, lc.pc, pv, p, lc.npairs, lc.stack_mem);
+    if (last_block(&ctl->f_done, (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x))) {
+        __shared__ float4 s_none[1]; // no top-level table here (no reference reaches it)
+        const NodeSrc ns{lc.nodes, (LdsFloat *)s_none};
+        for (int p = threadIdx.x >> 2; p < lc.npairs; p += blockDim.x >> 2)
+            l64_pair(ns, lc.bv64, lc.ids, lc.pc, pv, p, lc.npairs, lc.stack_mem, threadIdx.x & 3);
+    }
 }
 
 // ---------------------------------------------------------------------------
