@@ -605,3 +605,53 @@ def test_build_graph_replays_match_eager():
             assert got[1] == eager[k][1]
     finally:
         hd.build_graphs(True)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_full_size_queries_on_sampled_points(k):
+    """The point queries at a workload's full size (the BVH the bench builds),
+    checked on sampled points against the oracle's brute force: A's vertices
+    and points around B's surface. FP64: the exact distance, the closest face
+    or one at the same distance; FP32 (one lane and a quad per query): within
+    the stated margin."""
+    hd, torch = _hd()
+    W = wl.config(k)
+    rng = np.random.default_rng(100 + k)
+    VB, FB = W.VB, W.FB
+    lo, hi = VB.min(0), VB.max(0)
+    m = 96 if k == 3 else 48  # the oracle's brute force over 800 k faces takes ~0.1 s per point
+    P = np.concatenate([W.VA[rng.choice(W.VA.shape[0], m, replace=False)],
+                        VB[FB[rng.choice(FB.shape[0], 2 * m // 3), 0]] + rng.normal(0, 0.01, size=(2 * m // 3, 3)),
+                        rng.uniform(lo, hi, size=(m // 3, 3))])
+    say(f"config{k} full size, nB {FB.shape[0]}, {P.shape[0]} sampled points")
+    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+    dref, Iref = oracle.points_soup(P, VB, FB)
+    dref = np.asarray(dref)
+    scale = np.abs(VB).max()
+    d64, I64, _ = (x.cpu().numpy() for x in hd.point_distances(_cu(P, torch), bvh, precision=hd.PREC_FP64))
+    assert np.abs(d64 - dref).max() <= 1e-12 * scale
+    for i in np.nonzero(I64 != np.asarray(Iref))[0]:
+        a, b, c = VB[FB[I64[i]]]
+        assert abs(math.sqrt(oracle.closest_point(P[i], a, b, c)[0]) - dref[i]) <= 1e-12 * scale
+    edge = max(np.linalg.norm(VB[FB[:, i]] - VB[FB[:, (i + 1) % 3]], axis=1).max() for i in range(3))
+    ctr = 0.5 * (VB[np.unique(FB)].min(0) + VB[np.unique(FB)].max(0))
+    coord = max(np.abs(VB - ctr).max(), np.abs(P - ctr).max())
+    mu = _margin(dref, 2.0 ** -24, edge, coord)
+    for lanes in (1, 4):
+        d32 = hd.point_distances(_cu(P, torch), bvh, precision=hd.PREC_FP32, lanes=lanes)[0].cpu().numpy()
+        print(f"lanes {lanes}: max |d32 - d| / margin = {np.max(np.abs(d32 - dref) / mu):.3g}")
+        assert (np.abs(d32 - dref) <= mu).all()
+
+
+def test_config5_full_size_against_oracle():
+    """The large torus at full size (1 M vs 800 k faces), FP32 with the FP64
+    recheck, in the launch configuration the bench times: certified and
+    overlapping the oracle's interval."""
+    hd, torch = _hd()
+    W = wl.config(5)
+    say("config5 full size against the oracle's AABB-tree run")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+    assert ref["status"] == 0 and st["status"] == 0
+    _check_against_oracle(L, U, st, ref, "config5 full size")
