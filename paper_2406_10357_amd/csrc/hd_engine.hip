@@ -66,6 +66,7 @@ struct Ctl {
     double processed;                                  // faces processed (the paper's budget count)
     int stall;                                         // 1: capacity left no room to split
     int over_budget;                                   // 1: the next split would exceed the budget
+    int c_decision;                                    // stage C this round: 0 undecided, 1 run, 2 deferred
 };
 
 // Item count of a launch: a host value, or (device-planned rounds) a count
@@ -188,6 +189,7 @@ __global__ void k_ctl_init(Ctl *c) { memset(c, 0, sizeof(Ctl)); }
 constexpr int MB_SLOTS = 4;
 struct alignas(64) Mailbox {
     int64_t act, park, nref, rounds, subdivided;
+    int64_t pend_c; // records waiting for stage C (deferred)
     int bad, stall, over_budget;
     unsigned seq;
 };
@@ -199,6 +201,7 @@ __device__ void report_to(const Ctl *ctl, const int32_t *nref, Mailbox *ring, un
     mb->nref = nref ? *nref : 0;
     mb->rounds = (long long)ctl->rounds;
     mb->subdivided = (long long)ctl->subdivided;
+    mb->pend_c = (long long)ctl->c_next;
     mb->bad = ctl->bad;
     mb->stall = ctl->stall;
     mb->over_budget = ctl->over_budget;
@@ -214,7 +217,7 @@ __global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *ring, uns
 // capped by the list capacities and the face budget) and the per-round
 // counters. A round planned with nothing to do leaves everything in place.
 struct PlanCaps {
-    int64_t act, park, pend, mq; // capacities (records / queries)
+    int64_t act, park, pend, pend_c, mq; // capacities (records / queries)
     double budget;               // the paper's m * nA
     int grow_act, grow_park;     // 1: the host can still grow the active / parked lists
 };
@@ -224,10 +227,13 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     if (!c->bad && !c->stall && !c->over_budget && nAct > 0) {
         // room in the active-side lists (the pending and midpoint lists are
         // sized with the active ones) and in the parked list
-        int64_t ka = (caps.act - nAct) / 3;
+        // (records waiting for stage C may each still join either list)
+        const int64_t nc = c->c_decision == 1 ? 0 : (int64_t)c->c_next;
+        int64_t ka = (caps.act - nAct - nc) / 3;
         ka = ka < caps.pend / 4 ? ka : caps.pend / 4;
+        ka = ka < (caps.pend_c - nc) / 4 ? ka : (caps.pend_c - nc) / 4;
         ka = ka < caps.mq / 3 ? ka : caps.mq / 3;
-        const int64_t kp = (caps.park - nPark) / 4;
+        const int64_t kp = (caps.park - nPark - nc) / 4;
         K = nAct;
         K = K < ka ? K : ka;
         K = K < kp ? K : kp;
@@ -251,7 +257,9 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     c->act_next = (unsigned long long)(nAct - K);
     c->park_next = (unsigned long long)nPark;
     c->b_next = 0;
-    c->c_next = 0;
+    // stage C's list is emptied when stage C ran; deferred records stay
+    if (c->c_decision != 2) c->c_next = 0;
+    c->c_decision = 0;
     c->n_overflow = 0;
 }
 
@@ -264,6 +272,15 @@ __global__ void k_report_plan(Ctl *ctl, Mailbox *ring, unsigned seq, PlanCaps ca
     plan_round(ctl, caps);
 }
 
+
+// the list counts as the host last saw them (records waiting for stage C
+// stay), before stage C runs outside a round
+__global__ void k_set_counts(Ctl *c, unsigned long long act, unsigned long long park) {
+    if (threadIdx.x != 0) return;
+    c->act_next = act;
+    c->park_next = park;
+    c->c_decision = 0;
+}
 
 __global__ void k_clear_stall(Ctl *c) {
     if (threadIdx.x == 0) c->stall = 0;
@@ -1222,10 +1239,31 @@ __global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg
     }
 }
 
-// stage C: FP64 re-bound of the recheck band (count in ctl->c_next)
+// stage C: FP64 re-bound of the recheck band (count in ctl->c_next).
+// A few records take one wave the latency of a long FP64 chain, the same
+// as a few thousand: in device-planned rounds (defer = 1) the band is left
+// to accumulate and runs only once C_FLUSH_MIN records wait or no active
+// record is left (the rounds would end). The first block to arrive decides
+// for all (before any block appends); the plan keeps deferred records.
+constexpr int64_t C_FLUSH_MIN = 4096;
+
 template <class T>
-__global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg cc, Dest<T> dst, Ctl *ctl) {
+__global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg cc, Dest<T> dst, Ctl *ctl,
+                                                 int defer) {
     const int64_t n = (int64_t)ctl->c_next;
+    // blocks without records leave at once (the grid is sized for a larger
+    // count; a decision per block is an atomic on one address)
+    if ((int64_t)blockIdx.x * BLK >= n) return;
+    if (defer) {
+        __shared__ int run;
+        if (threadIdx.x == 0) {
+            const int mine = n >= C_FLUSH_MIN || ctl->act_next == 0 ? 1 : 2;
+            const int first = atomicCAS(&ctl->c_decision, 0, mine);
+            run = (first == 0 ? mine : first) == 1;
+        }
+        __syncthreads();
+        if (!run) return;
+    }
     for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
         const int64_t j = base + threadIdx.x;
         const bool valid = j < n;
@@ -1952,14 +1990,15 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
 
     // stages B and C over what one round's stage A produced (at most n records)
     const LearnCfg lc{pc, pv, iv};
-    auto later_stages = [&](int64_t n, const FrontierView<T> &act_out) {
+    // (defer: device-planned rounds may leave the recheck band to accumulate)
+    auto later_stages = [&](int64_t n, const FrontierView<T> &act_out, int defer) {
         Dest<T> d{act_out, tw.park.v, tw.pend_b.v, tw.pend_c.v};
         const unsigned g = std::min<unsigned>(grid_for(n, BLK), GRID_MAX);
         if (opt.learned == 2)
             k_stage_b_learned<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params);
         else
             k_stage_b<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
-        if (cc.recheck) k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl);
+        if (cc.recheck) k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl, defer);
         HD_LAUNCH_CHECK();
     };
 
@@ -1970,7 +2009,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc,
                                                   Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
     HD_LAUNCH_CHECK();
-    later_stages(nA, tw.act.v);
+    later_stages(nA, tw.act.v, 0);
     prof.mark(prof.c);
     const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
     double processed = (double)nA;
@@ -1984,18 +2023,20 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // rounds. The host-driven loop below handles the other modes.
     const bool planned = opt.subbatch <= 0 && !opt.log_frontier;
     if (planned) {
-        auto size_round = [&]() {
+        // (keep_c: records waiting for stage C, kept when its list grows)
+        auto size_round = [&](int64_t keep_c) {
             const int64_t c = std::min(tw.act.cap, tw.act2.cap);
             tw.mq.ensure(c);
             tw.pend_b.ensure(c, 0, s);
-            if (cc.recheck) tw.pend_c.ensure(c, 0, s);
+            if (cc.recheck) tw.pend_c.ensure(c, keep_c, s);
         };
-        size_round();
+        size_round(0);
         auto caps = [&]() {
             PlanCaps c;
             c.act = std::min(tw.act.cap, tw.act2.cap);
             c.park = tw.park.cap;
-            c.pend = cc.recheck ? std::min(tw.pend_b.cap, tw.pend_c.cap) : tw.pend_b.cap;
+            c.pend = tw.pend_b.cap;
+            c.pend_c = cc.recheck ? tw.pend_c.cap : c.pend;
             c.mq = tw.mq.cap;
             c.budget = budget - (double)nA;
             c.grow_act = c.act < cap_limit;
@@ -2025,7 +2066,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
                 Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1);
             HD_LAUNCH_CHECK();
-            later_stages(4 * kmax, tw.act2.v);
+            later_stages(4 * kmax, tw.act2.v, 1);
             prof.mark(prof.c);
             swap_fb(tw.act, tw.act2);
         };
@@ -2060,17 +2101,32 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 tw.act.ensure(grow, hm.act, s);
                 tw.act2.ensure(grow, 0, s);
                 tw.park.ensure(std::min<int64_t>(cap_limit, std::max<int64_t>(2 * tw.park.cap, hm.park + 4 * hm.act)), hm.park, s);
-                size_round();
+                size_round(hm.pend_c);
             } catch (const Error &e) {
                 if (e.st != HD_E_NOMEM) throw;
                 // out of device memory: the lists stay as they are and the
                 // rounds split what fits (sub-batches)
                 cap_limit = std::min(std::min(tw.act.cap, tw.act2.cap), tw.park.cap);
-                size_round();
+                size_round(hm.pend_c);
             }
             k_clear_stall<<<1, 64, 0, s>>>(ctl);
             seq_prev = report_plan_async();
             enqueued = (int)hm.rounds; // stalled rounds split nothing and do not count
+        }
+        if (cc.recheck && hm.pend_c > 0 && !hm.bad) {
+            // the rounds stopped early (round limit, budget, capacity) with
+            // records still waiting for stage C: decide them now, so that the
+            // final U covers them (the lists have room: plans reserve it)
+            tw.act.ensure(hm.act + hm.pend_c, hm.act, s);
+            tw.park.ensure(hm.park + hm.pend_c, hm.park, s);
+            k_set_counts<<<1, 64, 0, s>>>(ctl, (unsigned long long)hm.act, (unsigned long long)hm.park);
+            k_stage_c<T><<<std::min<unsigned>(grid_for(hm.pend_c, BLK), GRID_MAX), BLK, 0, s>>>(
+                tw.pend_c.v, cc, Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 0);
+            HD_LAUNCH_CHECK();
+            const Mailbox hf = report(nullptr);
+            hm.act = hf.act;
+            hm.park = hf.park;
+            hm.bad = hf.bad;
         }
         nAct = hm.act;
         nPark = hm.park;
@@ -2186,7 +2242,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
                                                            ctl, 0);
         HD_LAUNCH_CHECK();
-        later_stages(4 * K, tw.act2.v);
+        later_stages(4 * K, tw.act2.v, 0);
         prof.mark(prof.c);
         hm = report(nullptr);
         swap_fb(tw.act, tw.act2);

@@ -655,3 +655,40 @@ def test_config5_full_size_against_oracle():
     ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
     assert ref["status"] == 0 and st["status"] == 0
     _check_against_oracle(L, U, st, ref, "config5 full size")
+
+
+@pytest.mark.parametrize("k,scale", [(2, 0.1), (5, 0.01), (1, 1.0)])
+def test_deferred_recheck_band(k, scale):
+    """Device-planned rounds leave the FP64 recheck band to accumulate and
+    decide it once enough records wait or no active record is left; the
+    host-driven loop (a sub-batch as large as the frontier: every active
+    triangle split each round, in the same order) decides it every round.
+    Both are certified against the oracle and overlap."""
+    hd, torch = _hd()
+    W = wl.config(k, scale=scale)
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    say(f"config{k} scale {scale}: planned rounds vs host loop, FP32 + recheck")
+    L0, U0, s0 = hd.bound(*args, precision=hd.PREC_FP32_RECHECK)
+    L1, U1, s1 = hd.bound(*args, precision=hd.PREC_FP32_RECHECK, subbatch=1 << 30)
+    print("rechecked", s0["rechecked64"], s1["rechecked64"], "rounds", s0["rounds"], s1["rounds"])
+    _check_against_oracle(L0, U0, s0, ref, "planned (deferred band)")
+    _check_against_oracle(L1, U1, s1, ref, "host loop (band every round)")
+    assert L0 <= U1 and L1 <= U0
+
+
+def test_round_limit_decides_the_waiting_band():
+    """Rounds stopped by a round limit with recheck records still waiting:
+    those are decided before the final U, which stays a valid upper bound."""
+    hd, torch = _hd()
+    W = wl.config(2)
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    say("config2 full size, FP32 + recheck, max_rounds 1..3")
+    Lf, Uf, sf = hd.bound(*args)
+    for r in (1, 2, 3):
+        L, U, st = hd.bound(*args, max_rounds=r)
+        print(f"max_rounds {r}: [{L:.12g}, {U:.12g}] rechecked {st['rechecked64']}")
+        assert st["status"] == 0 and st["rounds"] == r
+        assert L <= Lf and Lf <= U and L <= Uf
