@@ -2002,14 +2002,23 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
     };
 
+    // Without sub-batches or the frontier log every round splits all active
+    // triangles, so the device plans each round itself and the host enqueues
+    // one round ahead of the report it waits for: the GPU never idles between
+    // rounds. The host-driven loop below handles the other modes.
+    const bool planned = opt.subbatch <= 0 && !opt.log_frontier;
+
     // ---- round 0: bound every face ------------------------------------------
-    tw.pend_b.ensure(nA, 0, s);
-    if (cc.recheck) tw.pend_c.ensure(nA, 0, s);
+    // (planned rounds: the stage lists get the active lists' size now, so that
+    // recheck records deferred from round 0 are never moved by a resize)
+    const int64_t pend0 = planned ? std::max<int64_t>(nA, std::min(tw.act.cap, tw.act2.cap)) : nA;
+    tw.pend_b.ensure(pend0, 0, s);
+    if (cc.recheck) tw.pend_c.ensure(pend0, 0, s);
     prof.mark(prof.c);
     k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc,
                                                   Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
     HD_LAUNCH_CHECK();
-    later_stages(nA, tw.act.v, 0);
+    later_stages(nA, tw.act.v, planned ? 1 : 0);
     prof.mark(prof.c);
     const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
     double processed = (double)nA;
@@ -2017,11 +2026,6 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     int rounds = 0;
     hd_status status = HD_OK;
     Mailbox hm{};
-    // Without sub-batches or the frontier log every round splits all active
-    // triangles, so the device plans each round itself and the host enqueues
-    // one round ahead of the report it waits for: the GPU never idles between
-    // rounds. The host-driven loop below handles the other modes.
-    const bool planned = opt.subbatch <= 0 && !opt.log_frontier;
     if (planned) {
         // (keep_c: records waiting for stage C, kept when its list grows)
         auto size_round = [&](int64_t keep_c) {
@@ -2030,7 +2034,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             tw.pend_b.ensure(c, 0, s);
             if (cc.recheck) tw.pend_c.ensure(c, keep_c, s);
         };
-        size_round(0);
+        size_round(0); // no resize here (round 0 sized the stage lists): deferred records stay
         auto caps = [&]() {
             PlanCaps c;
             c.act = std::min(tw.act.cap, tw.act2.cap);
