@@ -642,10 +642,6 @@ __global__ void k_wide_top(const WideNode *__restrict__ nodes, const BvhPair *pa
     if (root >= 0) top_entry(nodes, root, top, threadIdx.x);
 }
 
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
 // build scratch, reused between builds on the same device; kept until the
 // process ends (never destroyed: the HIP runtime may be gone by static

@@ -16,7 +16,10 @@
 //
 // All pairs of a batched call share the kernels: records carry their pair id
 // and every per-pair quantity (centre, BVH root, L, U, eps, margins) is read
-// from the pair table. One host read-back per round returns the list sizes.
+// from the pair table. Without sub-batches the device plans each round
+// (k_report_plan) and the host enqueues one round ahead of the small report
+// it polls; with sub-batches (or the frontier log) the host selects each
+// round's sub-batch from the report of the previous one.
 #include <math.h>
 
 #include <algorithm>
@@ -34,7 +37,6 @@ namespace hd {
 
 namespace {
 
-constexpr int QBLOCK = 128;   // query kernel block
 constexpr int QSTACK = 16;    // LDS ring-stack entries per lane (16 KB per block)
 constexpr int SMALL_STACK = 4; // test hook: tiny LDS stack, forces the deep path
 constexpr int DEEP_STACK = 256;
