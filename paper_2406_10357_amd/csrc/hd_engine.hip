@@ -795,7 +795,7 @@ __global__ void k_zero_query_stats(Ctl *c) {
 // FP64 distance of pair p's best vertex when it changed: the lower bound
 // then carries the FP64 margin instead of the FP32 one, which the recheck
 // band needs to park triangles within eps of it
-__device__ void l64_pair(const NodeSrc &ns, const BView<double> &bv64, const int4 *ids, const PairConst *pc,
+HD_D void l64_pair(const NodeSrc &ns, const BView<double> &bv64, const int4 *ids, const PairConst *pc,
                          PairVar *pv, int p, int npairs, int2 *stack_mem, int k) {
     // run by the four lanes of a quad (k = lane in the quad): all read, lane 0 writes
     PairVar &P = pv[p];

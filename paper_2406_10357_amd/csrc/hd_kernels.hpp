@@ -255,6 +255,41 @@ HD_D void cswap(T &ea, int &fa, T &eb, int &fb) {
     }
 }
 
+// Descent without a bound: nearest box first, nothing pushed, down to one
+// leaf, whose distance then bounds the real traversal (without it every
+// child would be in range and every sibling pushed).
+template <class T>
+HD_D void greedy_probe(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
+                       const V3<T> &p, int root, QueryResult<T> &r) {
+    int x = root;
+    for (int guard = 0; guard < 64 && x >= 0; ++guard) {
+        const WideNode *w = nodes + x;
+        const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
+        const int4 ch = w->child;
+        T best = T(__builtin_inf());
+        int pick = WIDE_EMPTY;
+        auto consider = [&](float a, float b, float c, float d, float e, float f, int ref) {
+            if (ref == WIDE_EMPTY) return;
+            T dd = box_d2<T>(make_float4(a, b, c, 0.f), make_float4(d, e, f, 0.f), p);
+            if (pick == WIDE_EMPTY || dd < best) {
+                best = dd;
+                pick = ref;
+            }
+        };
+        consider(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ch.x);
+        consider(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ch.y);
+        consider(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ch.z);
+        consider(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ch.w);
+        r.nbox += 4;
+        if (pick == WIDE_EMPTY) break;
+        if (pick < 0) {
+            visit_leaf(r, bv, ids, p, ~pick);
+            break;
+        }
+        x = pick;
+    }
+}
+
 template <class T, class Stack>
 HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
                              const V3<T> &p, int root, Stack &st, QueryResult<T> r) {
@@ -265,37 +300,8 @@ HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> 
         return r;
     }
     // Without a bound every child is in range and every sibling would be
-    // pushed; descend greedily (nearest box first, nothing pushed) to one
-    // leaf, and start the real traversal with its distance as the bound.
-    if (!(r.d2 < T(__builtin_inf()))) {
-        int x = root;
-        for (int guard = 0; guard < 64 && x >= 0; ++guard) {
-            const WideNode *w = nodes + x;
-            const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
-            const int4 ch = w->child;
-            T best = T(__builtin_inf());
-            int pick = WIDE_EMPTY;
-            auto consider = [&](float a, float b, float c, float d, float e, float f, int ref) {
-                if (ref == WIDE_EMPTY) return;
-                T dd = box_d2<T>(make_float4(a, b, c, 0.f), make_float4(d, e, f, 0.f), p);
-                if (pick == WIDE_EMPTY || dd < best) {
-                    best = dd;
-                    pick = ref;
-                }
-            };
-            consider(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ch.x);
-            consider(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ch.y);
-            consider(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ch.z);
-            consider(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ch.w);
-            r.nbox += 4;
-            if (pick == WIDE_EMPTY) break;
-            if (pick < 0) {
-                visit_leaf(r, bv, ids, p, ~pick);
-                break;
-            }
-            x = pick;
-        }
-    }
+    // pushed; descend greedily first (see greedy_probe).
+    if (!(r.d2 < T(__builtin_inf()))) greedy_probe(nodes, bv, ids, p, root, r);
     int node = root;
     bool lost = false;
     int restarts = 0;
