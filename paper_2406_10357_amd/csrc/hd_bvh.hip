@@ -46,6 +46,12 @@ struct PairAcc { // per-pair accumulators, ordered-double bits
     unsigned long long bbox[6];
     unsigned long long coord_max, edge_max;
 };
+// The accumulators come in ACC_COPIES copies of npairs entries each, astride
+// entries (a multiple of 256 bytes) apart; a block updates copy
+// blockIdx % ACC_COPIES, and the kernel that reads a value folds the copies.
+__device__ __forceinline__ PairAcc &acc_of(PairAcc *acc, int astride, int p) {
+    return acc[(int64_t)acc_copy() * astride + p];
+}
 
 struct BuildState {
     int bad;
@@ -53,20 +59,21 @@ struct BuildState {
     int n_wide; // four-wide nodes
 };
 
-__global__ void k_init(PairAcc *acc, int npairs, BuildState *st) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
+__global__ void k_init(PairAcc *acc, int npairs, int astride, BuildState *st) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
         st->bad = 0;
         st->n_upper = 0;
         st->n_wide = 0;
     }
-    if (p >= npairs) return;
+    if (i >= npairs * ACC_COPIES) return;
+    PairAcc &a = acc[(int64_t)(i / npairs) * astride + i % npairs];
     for (int k = 0; k < 3; ++k) {
-        acc[p].bbox[k] = d2ord(__builtin_inf());
-        acc[p].bbox[3 + k] = d2ord(-__builtin_inf());
+        a.bbox[k] = d2ord(__builtin_inf());
+        a.bbox[3 + k] = d2ord(-__builtin_inf());
     }
-    acc[p].coord_max = d2ord(0.0);
-    acc[p].edge_max = d2ord(0.0);
+    a.coord_max = d2ord(0.0);
+    a.edge_max = d2ord(0.0);
 }
 
 // pair of a global face index (faces of pair p are [foff[p], foff[p+1]))
@@ -115,7 +122,7 @@ __device__ __forceinline__ void acc_max(unsigned long long *a, double v, bool un
 // Every lane of a launched wave takes part (inactive lanes carry neutral
 // values) so that the wave-wide reductions see 64 lanes.
 __global__ void k_faces_check(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs,
-                              int64_t n, PairAcc *acc, BuildState *st) {
+                              int64_t n, PairAcc *acc, int astride, BuildState *st) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = f < n;
     int p = pair_of(foff, npairs, valid ? f : n - 1);
@@ -142,12 +149,21 @@ __global__ void k_faces_check(const PairSrc *__restrict__ src, const int64_t *__
         }
     }
     const double v[6] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]};
-    block_pair_minmax<6, 0x38u, BLK>(p, valid, v, [&](int q, int k) { return &acc[q].bbox[k]; });
+    block_pair_minmax<6, 0x38u, BLK>(p, valid, v, [&](int q, int k) { return &acc_of(acc, astride, q).bbox[k]; });
 }
 
-__global__ void k_pair_centres(const PairAcc *acc, int npairs, BvhPair *pairs) {
+// folds the box copies into copy 0 and takes the pair's centre
+__global__ void k_pair_centres(PairAcc *acc, int npairs, int astride, BvhPair *pairs) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
+    for (int k = 0; k < 6; ++k) {
+        unsigned long long b = acc[p].bbox[k];
+        for (int c = 1; c < ACC_COPIES; ++c) {
+            const unsigned long long x = acc[(int64_t)c * astride + p].bbox[k];
+            b = k < 3 ? (x < b ? x : b) : (x > b ? x : b);
+        }
+        acc[p].bbox[k] = b;
+    }
     for (int k = 0; k < 3; ++k) pairs[p].ctr[k] = 0.5 * (ord2d(acc[p].bbox[k]) + ord2d(acc[p].bbox[3 + k]));
 }
 
@@ -166,7 +182,7 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 // ncells: the internal-node count, whose refit counters start at zero here.
 __global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs, int64_t n,
                             const BvhPair *__restrict__ pairs, int32_t *__restrict__ fpair, PairAcc *acc,
-                            const BuildState *st, unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
+                            int astride, const BuildState *st, unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
                             int32_t *__restrict__ counters, int64_t ncells) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f < ncells) counters[f] = 0;
@@ -202,7 +218,7 @@ __global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__re
     }
     if (f < n) fpair[f] = p;
     const double v[1] = {m};
-    block_pair_minmax<1, 1u, BLK>(p, valid, v, [&](int q, int) { return &acc[q].coord_max; });
+    block_pair_minmax<1, 1u, BLK>(p, valid, v, [&](int q, int) { return &acc_of(acc, astride, q).coord_max; });
 }
 
 __device__ __forceinline__ int delta(const unsigned long long *__restrict__ keys, int64_t n, int64_t i, int64_t j) {
@@ -268,7 +284,8 @@ __global__ __launch_bounds__(BLK) void k_leaves(const PairSrc *__restrict__ src,
                                                 const int32_t *__restrict__ fpair, const int32_t *__restrict__ order,
                                                 int64_t n, const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox,
                                                 float4 *__restrict__ fr32, double2 *__restrict__ fr64,
-                                                int4 *__restrict__ ids, PairAcc *acc, const BuildState *st) {
+                                                int4 *__restrict__ ids, PairAcc *acc, int astride,
+                                                const BuildState *st) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < n && !st->bad;
     int p = 0;
@@ -279,7 +296,7 @@ __global__ __launch_bounds__(BLK) void k_leaves(const PairSrc *__restrict__ src,
         Lb = build_leaf(src, foff, p, f, pairs, lbox, fr32, fr64, ids, i);
     }
     const double v[1] = {Lb};
-    block_pair_minmax<1, 1u, BLK>(p, valid, v, [&](int q, int) { return &acc[q].edge_max; });
+    block_pair_minmax<1, 1u, BLK>(p, valid, v, [&](int q, int) { return &acc_of(acc, astride, q).edge_max; });
 }
 
 __device__ double build_leaf(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int p, int32_t f,
@@ -628,11 +645,18 @@ __device__ void top_entry(const WideNode *__restrict__ nodes, int32_t root, Wide
 
 // per-pair maxima; the root becomes a wide-node index (widx null: no
 // internal nodes)
-__global__ void k_pair_finish(const PairAcc *acc, int npairs, BvhPair *pairs, const int32_t *__restrict__ widx) {
+__global__ void k_pair_finish(const PairAcc *acc, int npairs, int astride, BvhPair *pairs,
+                              const int32_t *__restrict__ widx) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npairs) return;
-    pairs[p].coord_max = ord2d(acc[p].coord_max);
-    pairs[p].edge_max = ord2d(acc[p].edge_max);
+    unsigned long long cm = 0, em = 0;
+    for (int c = 0; c < ACC_COPIES; ++c) {
+        const PairAcc &a = acc[(int64_t)c * astride + p];
+        cm = a.coord_max > cm ? a.coord_max : cm;
+        em = a.edge_max > em ? a.edge_max : em;
+    }
+    pairs[p].coord_max = ord2d(cm);
+    pairs[p].edge_max = ord2d(em);
     if (widx && pairs[p].root >= 0) pairs[p].root = widx[pairs[p].root];
 }
 
@@ -755,7 +779,8 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
             return o;
         };
         size_t o_state = take(sizeof(BuildState));
-        size_t o_acc = take(npairs * sizeof(PairAcc));
+        const int astride = (int)(((npairs * sizeof(PairAcc) + 255) & ~size_t(255)) / sizeof(PairAcc));
+        size_t o_acc = take((size_t)ACC_COPIES * astride * sizeof(PairAcc));
         size_t o_fpair = take(n * sizeof(int32_t));
         size_t o_keys = take(n * sizeof(unsigned long long));
         size_t o_vals = take(n * sizeof(int32_t));
@@ -830,16 +855,17 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         auto enqueue = [&](hipStream_t q) {
             HD_HIP(hipMemcpyAsync(dsrc, sc.host.as<char>(o_src), o_pairs - o_src, hipMemcpyHostToDevice, q));
             HD_HIP(hipMemcpyAsync(dpairs, hp, npairs * sizeof(BvhPair), hipMemcpyHostToDevice, q));
-            k_init<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, st);
-            k_faces_check<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, st);
-            k_pair_centres<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, dpairs);
+            k_init<<<grid_for((int64_t)npairs * ACC_COPIES, 64), 64, 0, q>>>(acc, npairs, astride, st);
+            k_faces_check<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, astride, st);
+            k_pair_centres<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, astride, dpairs);
             k_centroids<<<grid_for(std::max<int64_t>(n, ni), BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
-                                                                                 acc, st, keys, vals, cnt, ni);
+                                                                                 acc, astride, st, keys, vals, cnt,
+                                                                                 ni);
             HD_LAUNCH_CHECK();
             radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, q);
             k_leaves<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, fpair, vals, n, dpairs, lbox,
                                                       b->frames32.as<float4>(), b->frames64.as<double2>(),
-                                                      b->ids.as<int4>(), acc, st);
+                                                      b->ids.as<int4>(), acc, astride, st);
             HD_LAUNCH_CHECK();
             if (n > 1) {
                 k_karras<<<grid_for(ni, BLK), BLK, 0, q>>>(keys, n, cl, cr, pn, pl, range, upper, st);
@@ -851,7 +877,7 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
                 k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, widx, cl, cr, nbox, lbox,
                                                                b->nodes.as<WideNode>());
             }
-            k_pair_finish<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, dpairs, n > 1 ? widx : nullptr);
+            k_pair_finish<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, astride, dpairs, n > 1 ? widx : nullptr);
             if (with_top) k_wide_top<<<1, 64, 0, q>>>(b->nodes.as<WideNode>(), dpairs, b->top.as<WideNode>());
             HD_LAUNCH_CHECK();
             Export ex{};

@@ -47,23 +47,39 @@ constexpr unsigned GRID_MAX = 2048;  // persistent cap of grid-stride launches (
 constexpr unsigned XCDS = 8;         // accelerator complex dies, each with its own L2
 constexpr unsigned QGRID_MAX = 4096; // the same for the query kernel's smaller blocks
 
-// Device control block. The append counters, the cascade statistics and the
-// query statistics sit on separate 128-byte lines: atomics on one line do not
-// stall the others.
+// Device control block. Atomics on one line serialise at the memory side
+// (about 9 ns each), and lines closer than 256 bytes still share that queue:
+// each append counter (every active block of a cascade kernel takes a
+// returning atomic on each list it appends to) sits on a 256-byte line of its
+// own, and the statistics are spread over ACC_COPIES copies (block b adds to
+// copy b % ACC_COPIES; readers sum the copies).
+enum {
+    ST_EVALS,
+    ST_BOUNDED,
+    ST_RECHECKED,
+    ST_DISCARDS, // five entries, one per deciding bound
+    ST_QUERIES = ST_DISCARDS + 5,
+    ST_BOXES,
+    ST_QLEAVES,
+    ST_SKIPS, // records whose u3 / u4 the learned policy skipped
+    ST_N
+};
+constexpr int ST_STRIDE = 32; // 256 bytes per copy
+static_assert(ST_N <= ST_STRIDE, "statistics copy overflows its line");
+
 struct Ctl {
-    alignas(128) unsigned long long act_next, park_next; // append counters of the current round
-    unsigned long long b_next, c_next;                   // records waiting for cascade stage B / C
-    int bad;        // 1 invalid input, 2 traversal deeper than the fallback stack, 3 depth exhausted
-    int n_overflow; // queries whose LDS stack overflowed this round
-    alignas(128) unsigned long long evals, bounded, rechecked;
-    unsigned long long discards[5];
-    alignas(128) unsigned long long queries, boxes, q_leaves;
-    unsigned long long skips; // records whose u3 / u4 the learned policy skipped
+    alignas(256) unsigned long long act_next; // append counters of the current round
+    alignas(256) unsigned long long park_next;
+    alignas(256) unsigned long long b_next; // records waiting for cascade stage B
+    alignas(256) unsigned long long c_next; // records waiting for cascade stage C
+    alignas(256) int bad; // 1 invalid input, 2 traversal deeper than the fallback stack, 3 depth exhausted
+    int n_overflow;       // queries whose LDS stack overflowed this round
+    alignas(256) unsigned long long stat[ACC_COPIES][ST_STRIDE];
     // blocks of the current query / argmax launch that have finished (the
     // last one does the launch's tail work and resets its counter)
-    alignas(128) unsigned q_done, f_done;
+    alignas(256) unsigned q_done, f_done;
     // device-planned rounds (written by plan_round, read by the round's kernels)
-    alignas(128) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
+    alignas(256) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
     unsigned long long subdivided, rounds;             // totals over the planned rounds
     double processed;                                  // faces processed (the paper's budget count)
     int stall;                                         // 1: capacity left no room to split
@@ -181,7 +197,15 @@ __device__ void pair_max2(PairVar *pv, int pair, unsigned long long a, unsigned 
 }
 
 
-__global__ void k_ctl_init(Ctl *c) { memset(c, 0, sizeof(Ctl)); }
+// zero the control block (by the threads of block 0)
+__device__ void ctl_zero(Ctl *c) {
+    static_assert(sizeof(Ctl) % 8 == 0, "control block size");
+    if (blockIdx.x != 0) return;
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(c);
+    for (int k = threadIdx.x; k < (int)(sizeof(Ctl) / 8); k += blockDim.x) w[k] = 0;
+}
+
+__global__ void k_ctl_init(Ctl *c) { ctl_zero(c); }
 
 // What the host needs between rounds, written by the device into pinned host
 // memory; `seq` last, after a system-scope fence, so that a host that sees
@@ -301,18 +325,33 @@ __device__ void pair_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict_
     memset(&c, 0, sizeof(c));
     PairVar d;
     memset(&d, 0, sizeof(d));
-    for (int k = 0; k < 3; ++k) {
-        c.ctr[k] = bp[p].ctr[k];
-        d.bbox[k] = d2ord(__builtin_inf());
-        d.bbox[3 + k] = d2ord(-__builtin_inf());
-    }
+    for (int k = 0; k < 3; ++k) c.ctr[k] = bp[p].ctr[k];
     c.root = bp[p].root;
     d.Lord = d2ord(0.0);
     d.Uord = d2ord(0.0);
     d.Urounds = d2ord(0.0);
-    d.coord_max = d2ord(0.0);
     pc[p] = c;
     pv[p] = d;
+}
+
+// Accumulators of the ingest (ordered FP64 bits): the box of A's referenced
+// vertices and the largest centred coordinate. ACC_COPIES copies of npairs
+// entries, astride entries (a multiple of 256 bytes) apart.
+struct PairBox {
+    unsigned long long bbox[6];
+    unsigned long long coord_max;
+    unsigned long long pad;
+};
+inline int pbox_stride(int npairs) { return (int)(((npairs * sizeof(PairBox) + 255) & ~size_t(255)) / sizeof(PairBox)); }
+
+__device__ void pbox_init(PairBox *pb, int npairs, int astride, int64_t i) {
+    if (i >= (int64_t)npairs * ACC_COPIES) return;
+    PairBox &b = pb[(i / npairs) * astride + i % npairs];
+    for (int k = 0; k < 3; ++k) {
+        b.bbox[k] = d2ord(__builtin_inf());
+        b.bbox[3 + k] = d2ord(-__builtin_inf());
+    }
+    b.coord_max = d2ord(0.0);
 }
 
 __global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int npairs) {
@@ -321,11 +360,12 @@ __global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restri
 }
 
 // the start of a call: control block, pair tables, referenced-vertex marks
-__global__ void k_bound_init(Ctl *ctl, PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int npairs,
-                             int32_t *__restrict__ ref, int64_t m) {
+__global__ void k_bound_init(Ctl *ctl, PairConst *pc, PairVar *pv, PairBox *pb, int astride,
+                             const BvhPair *__restrict__ bp, int npairs, int32_t *__restrict__ ref, int64_t m) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) memset(ctl, 0, sizeof(Ctl));
+    ctl_zero(ctl);
     if (i < npairs) pair_init(pc, pv, bp, (int)i);
+    pbox_init(pb, npairs, astride, i);
     if (i < m) ref[i] = 0;
 }
 
@@ -335,7 +375,7 @@ __global__ void k_bound_init(Ctl *ctl, PairConst *pc, PairVar *pv, const BvhPair
 __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__restrict__ foff,
                          const int64_t *__restrict__ voff, int npairs, int64_t n, int32_t *__restrict__ Fout,
                          double *__restrict__ Vout, int32_t *__restrict__ fpair, int32_t *__restrict__ ref,
-                         const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
+                         const PairConst *__restrict__ pc, PairBox *pb, int astride, Ctl *ctl) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = f < n;
     int p = pair_of(foff, npairs, valid ? f : n - 1);
@@ -371,7 +411,8 @@ __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__rest
     }
     const double v[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], cm};
     block_pair_minmax<7, 0x78u, BLK>(p, valid, v, [&](int q, int k) {
-        return k < 6 ? &pv[q].bbox[k] : &pv[q].coord_max;
+        PairBox &b = pb[(int64_t)acc_copy() * astride + q];
+        return k < 6 ? &b.bbox[k] : &b.coord_max;
     });
 }
 
@@ -385,17 +426,28 @@ __device__ Margins make_margins(double u, double edge_max, double coord_max) {
 
 // pair p's dA, eps * dA and margins, once the ingest has its bbox and
 // coordinate range
-__device__ void pair_post(PairConst *pc, const PairVar *pv, const BvhPair *__restrict__ bp, int p,
+__device__ void pair_post(PairConst *pc, const PairBox *pb, int astride, const BvhPair *__restrict__ bp, int p,
                           const double *__restrict__ eps, int eps_per_pair) {
+    // fold the copies
+    unsigned long long b[6], cmo = 0;
+    for (int k = 0; k < 6; ++k) b[k] = pb[p].bbox[k];
+    for (int c = 0; c < ACC_COPIES; ++c) {
+        const PairBox &x = pb[(int64_t)c * astride + p];
+        for (int k = 0; k < 3; ++k) {
+            b[k] = x.bbox[k] < b[k] ? x.bbox[k] : b[k];
+            b[3 + k] = x.bbox[3 + k] > b[3 + k] ? x.bbox[3 + k] : b[3 + k];
+        }
+        cmo = x.coord_max > cmo ? x.coord_max : cmo;
+    }
     double d2 = 0;
     for (int k = 0; k < 3; ++k) {
-        double e = ord2d(pv[p].bbox[3 + k]) - ord2d(pv[p].bbox[k]);
+        double e = ord2d(b[3 + k]) - ord2d(b[k]);
         d2 += e * e;
     }
     double dA = sqrt(d2);
     pc[p].dA = dA;
     pc[p].eps_abs = eps[eps_per_pair ? p : 0] * dA;
-    double cm = fmax(ord2d(pv[p].coord_max), bp[p].coord_max);
+    double cm = fmax(ord2d(cmo), bp[p].coord_max);
     pc[p].m32 = make_margins(Prec<float>::u, bp[p].edge_max, cm);
     pc[p].m64 = make_margins(Prec<double>::u, bp[p].edge_max, cm);
 }
@@ -403,12 +455,12 @@ __device__ void pair_post(PairConst *pc, const PairVar *pv, const BvhPair *__res
 // after the ingest: compact the referenced vertex ids (order preserving),
 // finish the pair tables, and set up round 0's counters
 __global__ void k_ingest_post(const int32_t *__restrict__ ref, const int32_t *__restrict__ pos, int64_t m,
-                              int32_t *__restrict__ out, PairConst *pc, const PairVar *pv,
+                              int32_t *__restrict__ out, PairConst *pc, const PairBox *pb, int astride,
                               const BvhPair *__restrict__ bp, int npairs, const double *__restrict__ eps,
                               int eps_per_pair, Ctl *ctl) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < m && ref[v]) out[pos[v]] = (int32_t)v;
-    if (v < npairs) pair_post(pc, pv, bp, (int)v, eps, eps_per_pair);
+    if (v < npairs) pair_post(pc, pb, astride, bp, (int)v, eps, eps_per_pair);
     if (v == 0) {
         ctl->n_overflow = 0;
         ctl->act_next = 0;
@@ -701,7 +753,8 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
     } else {
         query_lanes1<T, SD, QB>(in, n, to, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
     }
-    block_add<3, QB>({t.nb, t.nl, t.nq}, {&ctl->boxes, &ctl->q_leaves, &ctl->queries});
+    unsigned long long *st = ctl->stat[acc_copy()];
+    block_add<3, QB>({t.nb, t.nl, t.nq}, {st + ST_BOXES, st + ST_QLEAVES, st + ST_QUERIES});
     if (last_block(&ctl->q_done, to.active_blocks()))
         deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
 }
@@ -734,8 +787,8 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
         if (lord) atomicMax(&pv[qp.pair].Lord, lord);
         if (key) atomicMax(&pv[qp.pair].round_key, key);
     }
-    wave_add(&ctl->boxes, nb);
-    wave_add(&ctl->q_leaves, nl);
+    wave_add(&ctl->stat[acc_copy()][ST_BOXES], nb);
+    wave_add(&ctl->stat[acc_copy()][ST_QLEAVES], nl);
 }
 
 // Launch shapes of the query kernel (LDS stack entries per query, block
@@ -787,9 +840,9 @@ void launch_query(int v, int64_t n_max, int64_t quad_max, const QueryIn<T> &qi, 
 }
 
 __global__ void k_zero_query_stats(Ctl *c) {
-    if (threadIdx.x != 0) return;
-    c->queries = c->boxes = c->q_leaves = 0;
-    c->n_overflow = 0;
+    const int k = threadIdx.x;
+    if (k < ACC_COPIES) c->stat[k][ST_QUERIES] = c->stat[k][ST_BOXES] = c->stat[k][ST_QLEAVES] = 0;
+    if (k == 0) c->n_overflow = 0;
 }
 
 // FP64 distance of pair p's best vertex when it changed: the lower bound
@@ -1060,12 +1113,13 @@ __device__ int64_t append_slot(int list, Ctl *ctl) {
 // block-aggregated statistics of a cascade kernel (every thread must call it)
 __device__ void tally(Ctl *ctl, int list, int decider, int evals, int rechecked, bool valid, bool bounded) {
     const bool dis = valid && list == TO_DISCARD;
+    unsigned long long *st = ctl->stat[acc_copy()];
     block_add<8, BLK>({dis && decider == 0 ? 1ull : 0ull, dis && decider == 1 ? 1ull : 0ull,
                        dis && decider == 2 ? 1ull : 0ull, dis && decider == 3 ? 1ull : 0ull,
                        dis && decider == 4 ? 1ull : 0ull, valid ? (unsigned long long)evals : 0ull,
                        valid ? (unsigned long long)rechecked : 0ull, valid && bounded ? 1ull : 0ull},
-                      {&ctl->discards[0], &ctl->discards[1], &ctl->discards[2], &ctl->discards[3],
-                       &ctl->discards[4], &ctl->evals, &ctl->rechecked, &ctl->bounded});
+                      {st + ST_DISCARDS, st + ST_DISCARDS + 1, st + ST_DISCARDS + 2, st + ST_DISCARDS + 3,
+                       st + ST_DISCARDS + 4, st + ST_EVALS, st + ST_RECHECKED, st + ST_BOUNDED});
 }
 
 template <class T> struct Dest {
@@ -1459,7 +1513,7 @@ __global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, Cla
         if (valid)
             write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
         tally(ctl, list, decider, evals, 0, valid, false);
-        block_add<1, BLK>({(unsigned long long)skipped}, {&ctl->skips});
+        block_add<1, BLK>({(unsigned long long)skipped}, {&ctl->stat[acc_copy()][ST_SKIPS]});
     }
 }
 
@@ -1531,7 +1585,7 @@ __global__ __launch_bounds__(BLK) void k_final_U(FrontierView<T> fr, int64_t n, 
         ev = evals;
     }
     block_pair_minmax<2, 3u, BLK>(pair, valid, u, [&](int p, int k) { return k == 0 ? &pv[p].Uord : &pv[p].Urounds; });
-    block_add<1, BLK>({ev}, {&ctl->evals});
+    block_add<1, BLK>({ev}, {&ctl->stat[acc_copy()][ST_EVALS]});
 }
 
 // ---------------------------------------------------------------------------
@@ -1685,7 +1739,7 @@ struct Workspace {
     int qvar[2] = {0, 0};           // query launch shape per arithmetic (FP32, FP64)
     bool tuned[2] = {false, false};
     hipEvent_t tune_ev[2] = {nullptr, nullptr};
-    DBuf ctl, pc, pv, params, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
+    DBuf ctl, pc, pv, pbox, params, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
     TypedWs<float> w32;
     TypedWs<double> w64;
     template <class T> TypedWs<T> &typed();
@@ -1860,10 +1914,14 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     int32_t *refpos = ref + ((mA + 63) / 64) * 64;
     ws.small.reserve(4096);
     int32_t *d_total = ws.small.as<int32_t>();
-    k_bound_init<<<grid_for(std::max<int64_t>(mA, np), BLK), BLK, 0, s>>>(ctl, pc, pv, B->pairs.as<BvhPair>(), np,
-                                                                          ref, mA);
+    const int pstride = pbox_stride(np);
+    ws.pbox.reserve((size_t)ACC_COPIES * pstride * sizeof(PairBox));
+    PairBox *pbox = ws.pbox.as<PairBox>();
+    k_bound_init<<<grid_for(std::max<int64_t>(mA, (int64_t)np * ACC_COPIES), BLK), BLK, 0, s>>>(
+        ctl, pc, pv, pbox, pstride, B->pairs.as<BvhPair>(), np, ref, mA);
     k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
-                                              ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pv, ctl);
+                                              ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pbox, pstride,
+                                              ctl);
     scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
     HD_LAUNCH_CHECK();
     const Mailbox h0 = report(d_total);
@@ -1871,7 +1929,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const int64_t nref = h0.nref;
     ws.vids.reserve(nref * sizeof(int32_t));
     k_ingest_post<<<grid_for(std::max<int64_t>(mA, np), BLK), BLK, 0, s>>>(
-        ref, refpos, mA, ws.vids.as<int32_t>(), pc, pv, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair, ctl);
+        ref, refpos, mA, ws.vids.as<int32_t>(), pc, pbox, pstride, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair,
+        ctl);
 
     const BView<T> bv = [&] {
         if constexpr (sizeof(T) == 4) return BView<float>{B->frames32.as<float4>()};
@@ -2291,6 +2350,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         wait_host_seq(ws.host.as<unsigned>(256), seq, s);
     }
     const Ctl &hc = *ws.host.as<Ctl>(o_res + o_rctl);
+    auto stat = [&](int k) {
+        unsigned long long t = 0;
+        for (int c = 0; c < ACC_COPIES; ++c) t += hc.stat[c][k];
+        return t;
+    };
     const PairVar *hp = ws.host.as<PairVar>(o_res + o_rpv);
     const PairConst *hc_ = ws.host.as<PairConst>(o_res + o_rpc);
     if (status == HD_OK && hc.bad == 2) status = HD_E_INTERNAL;
@@ -2306,18 +2370,18 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     }
     S.rounds = rounds;
     S.status = status;
-    S.nodes_bounded = (int64_t)hc.bounded;
+    S.nodes_bounded = (int64_t)stat(ST_BOUNDED);
     S.subdivided = subdivided;
-    S.queries = (int64_t)hc.queries;
-    S.pt_tri_evals = (int64_t)(hc.evals + hc.q_leaves);
-    S.box_tests = (int64_t)hc.boxes;
-    for (int k = 0; k < 5; ++k) S.discards[k] = (int64_t)hc.discards[k];
-    S.rechecked64 = (int64_t)hc.rechecked;
+    S.queries = (int64_t)stat(ST_QUERIES);
+    S.pt_tri_evals = (int64_t)(stat(ST_EVALS) + stat(ST_QLEAVES));
+    S.box_tests = (int64_t)stat(ST_BOXES);
+    for (int k = 0; k < 5; ++k) S.discards[k] = (int64_t)stat(ST_DISCARDS + k);
+    S.rechecked64 = (int64_t)stat(ST_RECHECKED);
     S.parked_final = nPark;
-    S.query_leaf_evals = (int64_t)hc.q_leaves;
-    S.query_box_tests = (int64_t)hc.boxes;
+    S.query_leaf_evals = (int64_t)stat(ST_QLEAVES);
+    S.query_box_tests = (int64_t)stat(ST_BOXES);
     S.logged = logged;
-    S.learned_skips = (int64_t)hc.skips;
+    S.learned_skips = (int64_t)stat(ST_SKIPS);
     S.dA = hc_[0].dA;
     S.eps_abs = hc_[0].eps_abs;
     S.mu_coef_d = margins_of<T>(hc_[0]).mu_d;
@@ -2486,7 +2550,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
         Ctl *ctl = ctlb.as<Ctl>();
         PairConst *pc = pcb.as<PairConst>();
         PairVar *pv = pvb.as<PairVar>();
-        k_ctl_init<<<1, 1, 0, s>>>(ctl);
+        k_ctl_init<<<1, 256, 0, s>>>(ctl);
         k_pairs_init<<<1, 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), 1);
         const WideNode *top = B->npairs == 1 && !B->hpairs.empty() && B->hpairs[0].root >= 0
                                   ? B->top.as<WideNode>()

@@ -38,8 +38,6 @@ struct alignas(128) PairVar {
     unsigned long long Uord;      // ordered double: final upper bound
     unsigned long long Urounds;   // ordered double: largest live bound of the rounds
     unsigned long long best_key;  // best key so far
-    unsigned long long bbox[6];   // ordered FP64 bbox of A's referenced vertices
-    unsigned long long coord_max; // ordered FP64 largest |coordinate| of A after centring
     double argmax_pos[3];         // centred FP64 position of the best vertex
     int32_t argmax_dirty;
     int32_t argmax_tri;           // closest triangle (sorted index) found for it by the query

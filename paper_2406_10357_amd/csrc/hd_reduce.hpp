@@ -12,6 +12,13 @@
 
 namespace hd {
 
+// Accumulators that every block of a large grid updates are kept in
+// ACC_COPIES copies, 256 bytes apart, block b updating copy b % ACC_COPIES:
+// atomics on one 256-byte region serialise at the memory side, so sixteen
+// copies take sixteen times the rate. Whoever reads the value folds the copies.
+constexpr int ACC_COPIES = 16;
+__device__ __forceinline__ int acc_copy() { return (int)(blockIdx.x & (ACC_COPIES - 1)); }
+
 // v[k] is reduced with max when bit k of MAXMASK is set, else with min.
 // Threads with valid == false must pass neutral values (+inf for min, -inf
 // for max, or anything with valid == false: they are masked out). addr(p, k)
