@@ -12,10 +12,12 @@
 // as frame records (hd_geom.hpp) in FP32 and FP64.
 //
 // The refit avoids device-scope synchronisation, which on a multi-XCD part
-// costs an L2 write-back and invalidate per step: nodes whose leaf range lies
-// inside one 256-leaf tile are refit by that tile's workgroup (workgroup-scope
-// counters); the few nodes above the tiles are refit by a single workgroup,
-// in sweeps.
+// costs an L2 write-back and invalidate per step, and any serial chain over
+// the tree's height: nodes whose leaf range lies inside one 256-leaf tile are
+// refit by that tile's workgroup (a bottom-up climb in LDS); every node above
+// the tiles takes its box directly as the union of its leaf range, from
+// prefix / suffix unions within tiles and groups of tiles and a disjoint
+// sparse table over the tiles of a group (a few loads per node).
 #include <atomic>
 #include <memory>
 #include <mutex>
@@ -55,7 +57,6 @@ __device__ __forceinline__ PairAcc &acc_of(PairAcc *acc, int astride, int p) {
 
 struct BuildState {
     int bad;
-    int n_upper;
     int n_wide; // four-wide nodes
 };
 
@@ -63,7 +64,6 @@ __global__ void k_init(PairAcc *acc, int npairs, int astride, BuildState *st) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         st->bad = 0;
-        st->n_upper = 0;
         st->n_wide = 0;
     }
     if (i >= npairs * ACC_COPIES) return;
@@ -179,13 +179,11 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 // Centroid of each face (centred on its pair) and its key: the pair id above
 // a 30-bit Morton code of the centroid on a 1024^3 grid over the pair's vertex
 // box (centroids lie inside it). Also the pair's largest centred coordinate.
-// ncells: the internal-node count, whose refit counters start at zero here.
 __global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs, int64_t n,
                             const BvhPair *__restrict__ pairs, int32_t *__restrict__ fpair, PairAcc *acc,
-                            int astride, const BuildState *st, unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
-                            int32_t *__restrict__ counters, int64_t ncells) {
+                            int astride, const BuildState *st, unsigned long long *__restrict__ keys,
+                            int32_t *__restrict__ vals) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < ncells) counters[f] = 0;
     bool valid = f < n && !st->bad;
     int p = pair_of(foff, npairs, f < n ? f : n - 1);
     double m = 0;
@@ -229,10 +227,10 @@ __device__ __forceinline__ int delta(const unsigned long long *__restrict__ keys
 }
 
 // Karras 2012, one thread per internal node i in [0, n-2]; also the node's
-// leaf range, and the list of nodes whose range spans more than one tile
+// leaf range
 __global__ void k_karras(const unsigned long long *__restrict__ keys, int64_t n, int32_t *__restrict__ childL,
                          int32_t *__restrict__ childR, int32_t *__restrict__ parentN, int32_t *__restrict__ parentL,
-                         int2 *__restrict__ range, int32_t *__restrict__ upper, BuildState *st) {
+                         int2 *__restrict__ range) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
     if (i == 0) parentN[0] = -1; // the root (every other node is some node's child)
@@ -271,7 +269,6 @@ __global__ void k_karras(const unsigned long long *__restrict__ keys, int64_t n,
     childL[i] = cl;
     childR[i] = cr;
     range[i] = make_int2((int)lo, (int)hi);
-    if (lo / TILE != hi / TILE) upper[atomicAdd(&st->n_upper, 1)] = (int32_t)i;
 }
 
 // leaf data in sorted order: outward-rounded box, frame records, ids; the
@@ -384,139 +381,178 @@ __device__ __forceinline__ void union_box(const float4 *nbox, const float4 *__re
     out[1] = make_float4(fmaxf(h0.x, h1.x), fmaxf(h0.y, h1.y), fmaxf(h0.z, h1.z), 0.f);
 }
 
-// nodes inside one tile: bottom-up, the second thread of the workgroup to
-// reach a node builds it (workgroup-scope counters)
+// Float boxes as six values; union is exact (min / max), so any grouping of
+// the same leaf boxes gives the same node box.
+struct FBox {
+    float lx, ly, lz, hx, hy, hz;
+};
+__device__ __forceinline__ FBox fbox_empty() {
+    const float inf = __builtin_inff();
+    return FBox{inf, inf, inf, -inf, -inf, -inf};
+}
+__device__ __forceinline__ FBox fbox_union(const FBox &a, const FBox &b) {
+    return FBox{fminf(a.lx, b.lx), fminf(a.ly, b.ly), fminf(a.lz, b.lz),
+                fmaxf(a.hx, b.hx), fmaxf(a.hy, b.hy), fmaxf(a.hz, b.hz)};
+}
+__device__ __forceinline__ FBox fbox_load(const float4 *__restrict__ b, int64_t k) {
+    const float4 lo = b[2 * k], hi = b[2 * k + 1];
+    return FBox{lo.x, lo.y, lo.z, hi.x, hi.y, hi.z};
+}
+__device__ __forceinline__ void fbox_store(float4 *b, int64_t k, const FBox &x) {
+    b[2 * k] = make_float4(x.lx, x.ly, x.lz, 0.f);
+    b[2 * k + 1] = make_float4(x.hx, x.hy, x.hz, 0.f);
+}
+// 256 boxes in LDS, structure of arrays
+struct LdsBoxes {
+    float v[6][TILE];
+    __device__ FBox get(int k) const { return FBox{v[0][k], v[1][k], v[2][k], v[3][k], v[4][k], v[5][k]}; }
+    __device__ void set(int k, const FBox &x) {
+        v[0][k] = x.lx;
+        v[1][k] = x.ly;
+        v[2][k] = x.lz;
+        v[3][k] = x.hx;
+        v[4][k] = x.hy;
+        v[5][k] = x.hz;
+    }
+};
+
+// Prefix and suffix unions of the block's 256 boxes (thread t holds box t),
+// doubling the aligned run length h from 1 to 256: with P_h[t] the union from
+// the start of t's h-run to t and S_h[t] the union from t to the end of its
+// run, P_2h[t] adds the whole lower run when t lies in the upper half, S_2h[t]
+// the whole upper run when t lies in the lower half. visit(h, P_h[t], S_h[t])
+// sees every level h < 256 before it is doubled (the levels of a disjoint
+// sparse table); the return value is (P_256[t], S_256[t]). Every thread of
+// the block must call it.
+template <class Visit>
+__device__ void run_unions(FBox box, LdsBoxes &P, LdsBoxes &S, FBox &pre, FBox &suf, Visit visit) {
+    static_assert(TILE == 256, "one thread per box");
+    const int t = threadIdx.x;
+    pre = box;
+    suf = box;
+    for (int h = 1; h < TILE; h <<= 1) {
+        visit(h, pre, suf);
+        P.set(t, pre);
+        S.set(t, suf);
+        __syncthreads();
+        const int base = t & ~(2 * h - 1);
+        if (t & h) pre = fbox_union(P.get(base + h - 1), pre);
+        else suf = fbox_union(suf, S.get(base + h));
+        __syncthreads();
+    }
+}
+
+// Refit, bottom level: one workgroup per tile of TILE consecutive leaves.
+//  - Nodes whose leaf range lies inside the tile (their index then lies in
+//    the tile too): bottom-up climb in LDS, the second thread to reach a node
+//    builds it.
+//  - For every leaf i: lpre[i] = union of the tile's leaves up to i, lsuf[i]
+//    = union of leaves i to the tile's end; tbox = the tile's box. Nodes that
+//    span tiles take their boxes from these (k_refit_upper).
 __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *__restrict__ childL,
                                                       const int32_t *__restrict__ childR,
                                                       const int32_t *__restrict__ parentN,
                                                       const int32_t *__restrict__ parentL,
                                                       const int2 *__restrict__ range, const float4 *__restrict__ lbox,
-                                                      float4 *nbox, int32_t *counter) {
-    int64_t i = (int64_t)blockIdx.x * TILE + threadIdx.x;
-    if (i >= n) return;
+                                                      float4 *__restrict__ nbox, float4 *__restrict__ lpre,
+                                                      float4 *__restrict__ lsuf, float4 *__restrict__ tbox) {
+    __shared__ LdsBoxes leaf, node;
+    __shared__ int s_cl[TILE], s_cr[TILE], s_pn[TILE], s_cnt[TILE];
+    __shared__ bool s_in[TILE];
+    const int t = threadIdx.x;
     const int64_t t0 = (int64_t)blockIdx.x * TILE, t1 = t0 + TILE - 1;
-    int32_t p = parentL[i];
-    while (p >= 0) {
-        int2 r = range[p];
-        if (r.x < t0 || r.y > t1) return; // spans tiles: left to the upper pass
-        int old = __hip_atomic_fetch_add(&counter[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (old == 0) return;
-        union_box(nbox, lbox, childL[p], childR[p], nbox + 2 * (int64_t)p);
-        p = parentN[p];
+    const int64_t i = t0 + t;
+    const FBox lb = i < n ? fbox_load(lbox, i) : fbox_empty();
+    leaf.set(t, lb);
+    // node slot t: node t0 + t, when its range lies inside the tile
+    bool inside = false;
+    if (i < n - 1) {
+        const int2 r = range[i];
+        inside = r.x >= t0 && r.y <= t1;
+        s_cl[t] = childL[i];
+        s_cr[t] = childR[i];
+        s_pn[t] = parentN[i];
     }
+    s_in[t] = inside;
+    s_cnt[t] = 0;
+    int32_t p = i < n ? parentL[i] : -1;
+    __syncthreads();
+    while (p >= t0 && p <= t1) {
+        const int k = (int)(p - t0);
+        if (!s_in[k]) break; // spans tiles: left to k_refit_upper
+        const int old = __hip_atomic_fetch_add(&s_cnt[k], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == 0) break;
+        const int32_t a = s_cl[k], b = s_cr[k];
+        const FBox ba = a >= 0 ? node.get((int)(a - t0)) : leaf.get((int)(~a - t0));
+        const FBox bb = b >= 0 ? node.get((int)(b - t0)) : leaf.get((int)(~b - t0));
+        node.set(k, fbox_union(ba, bb));
+        p = s_pn[k];
+    }
+    __syncthreads();
+    if (inside) fbox_store(nbox, i, node.get(t));
+    __syncthreads();
+    FBox pre, suf;
+    run_unions(lb, leaf, node, pre, suf, [](int, const FBox &, const FBox &) {});
+    if (i < n) {
+        fbox_store(lpre, i, pre);
+        fbox_store(lsuf, i, suf);
+    }
+    if (t == TILE - 1) fbox_store(tbox, blockIdx.x, pre);
 }
 
-// nodes spanning tiles: one workgroup climbs bottom-up. A node's counter
-// starts at the number of its children that are already complete (leaves and
-// tile-internal nodes); climbs start at nodes with two such children, and the
-// thread that brings a parent's counter to 2 builds it and climbs on
-// (workgroup-scope atomics: all threads share one CU).
-constexpr int UPPER_LDS = 1536; // upper nodes the LDS climb holds (about 40 B each)
+// Refit, middle level: one workgroup per group of TILE consecutive tiles.
+// tpre / tsuf: unions of the group's tiles up to / from tile a; gbox: the
+// group's box; tdst[l][a] (l = 0..7, h = 2^l): the union from a to the end of
+// its h-run when bit l of a is clear, from the start of its h-run to a when it
+// is set (a disjoint sparse table: tiles a < b of one group with highest
+// differing bit l have union tdst[l][a] U tdst[l][b]).
+__global__ __launch_bounds__(TILE) void k_refit_groups(int64_t ntiles, const float4 *__restrict__ tbox,
+                                                       float4 *__restrict__ tpre, float4 *__restrict__ tsuf,
+                                                       float4 *__restrict__ gbox, float4 *__restrict__ tdst) {
+    __shared__ LdsBoxes P, S;
+    const int64_t a = (int64_t)blockIdx.x * TILE + threadIdx.x;
+    const FBox b = a < ntiles ? fbox_load(tbox, a) : fbox_empty();
+    FBox pre, suf;
+    run_unions(b, P, S, pre, suf, [&](int h, const FBox &ph, const FBox &sh) {
+        if (a < ntiles) fbox_store(tdst + 2 * (int64_t)(__builtin_ctz(h)) * ntiles, a, (a & h) ? ph : sh);
+    });
+    if (a < ntiles) {
+        fbox_store(tpre, a, pre);
+        fbox_store(tsuf, a, suf);
+    }
+    if (threadIdx.x == TILE - 1) fbox_store(gbox, blockIdx.x, pre);
+}
 
-__global__ __launch_bounds__(1024) void k_refit_upper(const int32_t *__restrict__ upper, const BuildState *st,
-                                                      const int32_t *__restrict__ childL,
-                                                      const int32_t *__restrict__ childR,
-                                                      const int32_t *__restrict__ parentN,
-                                                      const int2 *__restrict__ range, const float4 *__restrict__ lbox,
-                                                      float4 *nbox, int32_t *cnt) {
-    const int nup = st->n_upper;
-    auto complete = [&](int32_t c) {
-        if (c < 0) return 1;
-        int2 r = range[c];
-        return r.x / TILE == r.y / TILE ? 1 : 0;
-    };
-    if (nup > UPPER_LDS) {
-        // too many for LDS: the same climb on global counters and boxes
-        for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-            int32_t u = upper[k];
-            cnt[u] = complete(childL[u]) + complete(childR[u]);
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-            int32_t x = upper[k];
-            if (complete(childL[x]) + complete(childR[x]) != 2) continue;
-            while (true) {
-                union_box(nbox, lbox, childL[x], childR[x], nbox + 2 * (int64_t)x);
-                int32_t p = parentN[x];
-                if (p < 0) break;
-                int old = __hip_atomic_fetch_add(&cnt[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (old + 1 < 2) break;
-                x = p;
-            }
-        }
-        return;
-    }
-    // The climb in LDS: slot k holds upper node upper[k]: its box (the union of
-    // its complete children first, then of all), its parent's slot, the slots
-    // of its upper children, and an arrival counter. cnt (global) maps a node
-    // to its slot.
-    __shared__ float blo[UPPER_LDS][3], bhi[UPPER_LDS][3];
-    __shared__ int par[UPPER_LDS], cs[UPPER_LDS][2], arr[UPPER_LDS];
-    for (int k = threadIdx.x; k < nup; k += blockDim.x) cnt[upper[k]] = k;
-    __threadfence_block();
-    __syncthreads();
-    for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-        const int32_t u = upper[k];
-        const int32_t p = parentN[u];
-        par[k] = p >= 0 ? cnt[p] : -1;
-        float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
-        float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-        int c = 0;
-        const int32_t ch[2] = {childL[u], childR[u]};
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            if (complete(ch[j])) {
-                float4 l, h;
-                load_box(nbox, lbox, ch[j], l, h);
-                lo[0] = fminf(lo[0], l.x);
-                lo[1] = fminf(lo[1], l.y);
-                lo[2] = fminf(lo[2], l.z);
-                hi[0] = fmaxf(hi[0], h.x);
-                hi[1] = fmaxf(hi[1], h.y);
-                hi[2] = fmaxf(hi[2], h.z);
-                cs[k][j] = -1;
-                ++c;
+// Refit, top level: every node whose leaf range [lo, hi] spans tiles, on its
+// own: the union of lsuf[lo], lpre[hi] and the whole tiles between (one
+// sparse-table pair within a group, else the two partial groups and the
+// whole groups between).
+__global__ void k_refit_upper(int64_t ninternal, int64_t ntiles, const int2 *__restrict__ range,
+                              const float4 *__restrict__ lpre, const float4 *__restrict__ lsuf,
+                              const float4 *__restrict__ tbox, const float4 *__restrict__ tpre,
+                              const float4 *__restrict__ tsuf, const float4 *__restrict__ gbox,
+                              const float4 *__restrict__ tdst, float4 *__restrict__ nbox) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ninternal;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int2 r = range[i];
+        const int64_t ta = r.x / TILE, tb = r.y / TILE;
+        if (ta == tb) continue;
+        FBox x = fbox_union(fbox_load(lsuf, r.x), fbox_load(lpre, r.y));
+        const int64_t a = ta + 1, b = tb - 1;
+        if (a == b) {
+            x = fbox_union(x, fbox_load(tbox, a));
+        } else if (a < b) {
+            const int64_t ga = a / TILE, gb = b / TILE;
+            if (ga == gb) {
+                const int l = 31 - __clz((int)(a ^ b));
+                const float4 *d = tdst + 2 * (int64_t)l * ntiles;
+                x = fbox_union(x, fbox_union(fbox_load(d, a), fbox_load(d, b)));
             } else {
-                cs[k][j] = cnt[ch[j]];
+                x = fbox_union(x, fbox_union(fbox_load(tsuf, a), fbox_load(tpre, b)));
+                for (int64_t g = ga + 1; g < gb; ++g) x = fbox_union(x, fbox_load(gbox, g));
             }
         }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            blo[k][d] = lo[d];
-            bhi[k][d] = hi[d];
-        }
-        arr[k] = c;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-        // start at nodes whose children are both complete (a static test: the
-        // counters of other nodes are being raised meanwhile)
-        if (cs[k][0] >= 0 || cs[k][1] >= 0) continue;
-        int x = k;
-        while (true) {
-            const int p = par[x];
-            if (p < 0) break;
-            // the second child to arrive completes the parent
-            int old = __hip_atomic_fetch_add(&arr[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (old + 1 < 2) break;
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int c = cs[p][j];
-                if (c < 0) continue;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    blo[p][d] = fminf(blo[p][d], blo[c][d]);
-                    bhi[p][d] = fmaxf(bhi[p][d], bhi[c][d]);
-                }
-            }
-            x = p;
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nup; k += blockDim.x) {
-        float4 *o = nbox + 2 * (int64_t)upper[k];
-        o[0] = make_float4(blo[k][0], blo[k][1], blo[k][2], 0.f);
-        o[1] = make_float4(bhi[k][0], bhi[k][1], bhi[k][2], 0.f);
+        fbox_store(nbox, i, x);
     }
 }
 
@@ -790,9 +826,12 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         size_t o_cr = take(ni * sizeof(int32_t));
         size_t o_pn = take(ni * sizeof(int32_t));
         size_t o_pl = take(n * sizeof(int32_t));
-        size_t o_cnt = take(ni * sizeof(int32_t));
+        const int64_t ntiles = (n + TILE - 1) / TILE, ngroups = (ntiles + TILE - 1) / TILE;
         size_t o_range = take(ni * sizeof(int2));
-        size_t o_upper = take(ni * sizeof(int32_t));
+        size_t o_lps = take(2 * n * 2 * sizeof(float4)); // lpre, lsuf
+        size_t o_tps = take(3 * ntiles * 2 * sizeof(float4)); // tbox, tpre, tsuf
+        size_t o_tdst = take(8 * ntiles * 2 * sizeof(float4));
+        size_t o_gbox = take(ngroups * 2 * sizeof(float4));
         size_t o_flag = take(ni * sizeof(int32_t));
         size_t o_widx = take(ni * sizeof(int32_t));
         size_t o_lbox = take(n * 2 * sizeof(float4));
@@ -810,9 +849,11 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         int32_t *cr = (int32_t *)(base + o_cr);
         int32_t *pn = (int32_t *)(base + o_pn);
         int32_t *pl = (int32_t *)(base + o_pl);
-        int32_t *cnt = (int32_t *)(base + o_cnt);
         int2 *range = (int2 *)(base + o_range);
-        int32_t *upper = (int32_t *)(base + o_upper);
+        float4 *lpre = (float4 *)(base + o_lps), *lsuf = lpre + 2 * n;
+        float4 *tbox = (float4 *)(base + o_tps), *tpre = tbox + 2 * ntiles, *tsuf = tpre + 2 * ntiles;
+        float4 *tdst = (float4 *)(base + o_tdst);
+        float4 *gbox = (float4 *)(base + o_gbox);
         int32_t *flag = (int32_t *)(base + o_flag);
         int32_t *widx = (int32_t *)(base + o_widx);
         float4 *lbox = (float4 *)(base + o_lbox);
@@ -859,8 +900,7 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
             k_faces_check<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, astride, st);
             k_pair_centres<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, astride, dpairs);
             k_centroids<<<grid_for(std::max<int64_t>(n, ni), BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
-                                                                                 acc, astride, st, keys, vals, cnt,
-                                                                                 ni);
+                                                                                 acc, astride, st, keys, vals);
             HD_LAUNCH_CHECK();
             radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, q);
             k_leaves<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, fpair, vals, n, dpairs, lbox,
@@ -868,9 +908,14 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
                                                       b->ids.as<int4>(), acc, astride, st);
             HD_LAUNCH_CHECK();
             if (n > 1) {
-                k_karras<<<grid_for(ni, BLK), BLK, 0, q>>>(keys, n, cl, cr, pn, pl, range, upper, st);
-                k_refit_tiles<<<grid_for(n, TILE), TILE, 0, q>>>(n, cl, cr, pn, pl, range, lbox, nbox, cnt);
-                k_refit_upper<<<1, 1024, 0, q>>>(upper, st, cl, cr, pn, range, lbox, nbox, cnt);
+                k_karras<<<grid_for(ni, BLK), BLK, 0, q>>>(keys, n, cl, cr, pn, pl, range);
+                k_refit_tiles<<<(unsigned)ntiles, TILE, 0, q>>>(n, cl, cr, pn, pl, range, lbox, nbox, lpre, lsuf,
+                                                                 tbox);
+                if (ntiles > 1) {
+                    k_refit_groups<<<(unsigned)ngroups, TILE, 0, q>>>(ntiles, tbox, tpre, tsuf, gbox, tdst);
+                    k_refit_upper<<<grid_for(std::min<int64_t>(ni, 512 * BLK), BLK), BLK, 0, q>>>(
+                        ni, ntiles, range, lpre, lsuf, tbox, tpre, tsuf, gbox, tdst, nbox);
+                }
                 k_pair_roots<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, range, dpairs, npairs, keys);
                 k_wide_flags<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, pn, range, dpairs, npairs, keys, flag);
                 scan_exclusive_i32(flag, widx, ni, &st->n_wide, sc.scan_tmp, q);

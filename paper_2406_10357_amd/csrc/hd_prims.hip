@@ -161,9 +161,12 @@ constexpr int RS_BLOCK = 256;
 constexpr int RS_ITEMS_MAX = 16;
 constexpr int RS_WAVES = RS_BLOCK / 64;
 
+// digit counts of each block's tile: hist[d * nblocks + b] (digit-major, for
+// the device-wide scan), or hist[b * 256 + d] when block_major (for the
+// scatter that derives its own offsets)
 template <class K>
 __global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift, int nblocks, int items,
-                             int32_t *__restrict__ hist) {
+                             int block_major, int32_t *__restrict__ hist) {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -173,20 +176,58 @@ __global__ void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift, i
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    hist[block_major ? (int64_t)blockIdx.x * 256 + threadIdx.x : (int64_t)threadIdx.x * nblocks + blockIdx.x] =
+        h[threadIdx.x];
+}
+
+// Offset of digit d (= thread) for this block, from the block-major counts
+// of all nblocks blocks: the count of smaller digits in all blocks plus the
+// count of digit d in earlier blocks. Every block reads the whole table
+// (nblocks x 1 KB, coalesced), which replaces a separate scan launch when
+// the table is small.
+__device__ int radix_block_offset(const int32_t *__restrict__ hist, int nblocks) {
+    static_assert(RS_BLOCK == 256, "one thread per digit");
+    const int d = threadIdx.x;
+    // rows in batches of 32 loads in flight (the table was written by blocks
+    // on every XCD, so each load has the latency of memory beyond L2)
+    constexpr int RB = 32;
+    int total = 0, before = 0;
+    for (int b0 = 0; b0 < nblocks; b0 += RB) {
+        int hv[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) hv[k] = b0 + k < nblocks ? hist[(int64_t)(b0 + k) * 256 + d] : 0;
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            total += hv[k];
+            before += b0 + k < (int)blockIdx.x ? hv[k] : 0;
+        }
+    }
+    // exclusive scan of the totals over the 256 digits
+    __shared__ int wsum[RS_WAVES];
+    const int inc = wave_inclusive_scan(total);
+    const int w = d >> 6;
+    if (__lane_id() == 63) wsum[w] = inc;
+    __syncthreads();
+    int off = 0;
+#pragma unroll
+    for (int i = 0; i < RS_WAVES; ++i)
+        if (i < w) off += wsum[i];
+    return off + inc - total + before;
 }
 
 // Stable scatter: within a round of RS_BLOCK keys, a key's rank among equal
 // digits of its wave comes from eight ballots (one per digit bit); waves are
-// then ordered through per-digit counters in LDS.
+// then ordered through per-digit counters in LDS. The block's digit offsets
+// come from offs (digit-major, scanned), or, with offs null, from the
+// block-major counts in hist.
 template <class K>
 __global__ void k_radix_scatter(const K *__restrict__ kin, const int32_t *__restrict__ vin, K *__restrict__ kout,
                                 int32_t *__restrict__ vout, int64_t n, int shift, int nblocks, int items,
-                                const int32_t *__restrict__ offs) {
+                                const int32_t *__restrict__ offs, const int32_t *__restrict__ hist) {
     __shared__ int goff[256];
     __shared__ int wcnt[RS_WAVES][256];
     __shared__ int woff[RS_WAVES][256];
-    goff[threadIdx.x] = offs[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    goff[threadIdx.x] = offs ? offs[(int64_t)threadIdx.x * nblocks + blockIdx.x] : radix_block_offset(hist, nblocks);
     const int w = threadIdx.x >> 6;
     const int lane = __lane_id();
     const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -228,13 +269,15 @@ __global__ void k_radix_scatter(const K *__restrict__ kin, const int32_t *__rest
 }
 
 // launch plan of a radix sort of n keys: the fewest items per block that
-// keep the digit histogram within one small scan (at most 128 blocks x 256
-// digits), at most RS_ITEMS_MAX
+// keep the digit histogram small (at most RS_FUSED_MAX blocks x 256 digits:
+// then each scatter block derives its own offsets), at most RS_ITEMS_MAX
+constexpr int RS_FUSED_MAX = 128;
 struct RadixPlan {
     int items, nb;
     int64_t hn, scan_parts;
     explicit RadixPlan(int64_t n) {
-        items = (int)std::min<int64_t>(RS_ITEMS_MAX, std::max<int64_t>(1, (n + 128 * RS_BLOCK - 1) / (128 * RS_BLOCK)));
+        items = (int)std::min<int64_t>(
+            RS_ITEMS_MAX, std::max<int64_t>(1, (n + RS_FUSED_MAX * RS_BLOCK - 1) / (RS_FUSED_MAX * RS_BLOCK)));
         const int64_t tile = (int64_t)RS_BLOCK * items;
         nb = (int)((n + tile - 1) / tile);
         hn = 256LL * nb;
@@ -257,9 +300,17 @@ void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int
     K *ka = keys, *kb = keys_alt;
     int32_t *va = vals, *vb = vals_alt;
     int passes = (bits + 7) / 8;
+    const bool fused = nb <= RS_FUSED_MAX;
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
-        k_radix_hist<K><<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, items, hist);
+        k_radix_hist<K><<<nb, RS_BLOCK, 0, s>>>(ka, n, shift, nb, items, fused ? 1 : 0, hist);
+        if (fused) {
+            k_radix_scatter<K><<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, items, nullptr, hist);
+            HD_LAUNCH_CHECK();
+            std::swap(ka, kb);
+            std::swap(va, vb);
+            continue;
+        }
         if (hn <= SMALL_SCAN_MAX && aligned16(hist) && aligned16(offs)) {
             k_scan_small<<<1, SMALL_SCAN_BLOCK, 0, s>>>(hist, offs, hn, nullptr);
         } else {
@@ -267,7 +318,7 @@ void radix_sort_impl(K *keys, int32_t *vals, K *keys_alt, int32_t *vals_alt, int
             k_scan_partials<<<1, SCAN_BLOCK, 0, s>>>(part, scan_parts, nullptr);
             k_scan_down<<<(unsigned)scan_parts, SCAN_BLOCK, 0, s>>>(hist, offs, hn, part);
         }
-        k_radix_scatter<K><<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, items, offs);
+        k_radix_scatter<K><<<nb, RS_BLOCK, 0, s>>>(ka, va, kb, vb, n, shift, nb, items, offs, nullptr);
         HD_LAUNCH_CHECK();
         std::swap(ka, kb);
         std::swap(va, vb);
