@@ -57,14 +57,12 @@ __device__ __forceinline__ PairAcc &acc_of(PairAcc *acc, int astride, int p) {
 
 struct BuildState {
     int bad;
-    int n_wide; // four-wide nodes
 };
 
 __global__ void k_init(PairAcc *acc, int npairs, int astride, BuildState *st) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         st->bad = 0;
-        st->n_wide = 0;
     }
     if (i >= npairs * ACC_COPIES) return;
     PairAcc &a = acc[(int64_t)(i / npairs) * astride + i % npairs];
@@ -448,7 +446,7 @@ __device__ void run_unions(FBox box, LdsBoxes &P, LdsBoxes &S, FBox &pre, FBox &
 //    builds it.
 //  - For every leaf i: lpre[i] = union of the tile's leaves up to i, lsuf[i]
 //    = union of leaves i to the tile's end; tbox = the tile's box. Nodes that
-//    span tiles take their boxes from these (k_refit_upper).
+//    span tiles take their boxes from these (k_nodes).
 __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *__restrict__ childL,
                                                       const int32_t *__restrict__ childR,
                                                       const int32_t *__restrict__ parentN,
@@ -479,7 +477,7 @@ __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *
     __syncthreads();
     while (p >= t0 && p <= t1) {
         const int k = (int)(p - t0);
-        if (!s_in[k]) break; // spans tiles: left to k_refit_upper
+        if (!s_in[k]) break; // spans tiles: left to k_nodes
         const int old = __hip_atomic_fetch_add(&s_cnt[k], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (old == 0) break;
         const int32_t a = s_cl[k], b = s_cr[k];
@@ -523,69 +521,83 @@ __global__ __launch_bounds__(TILE) void k_refit_groups(int64_t ntiles, const flo
     if (threadIdx.x == TILE - 1) fbox_store(gbox, blockIdx.x, pre);
 }
 
-// Refit, top level: every node whose leaf range [lo, hi] spans tiles, on its
-// own: the union of lsuf[lo], lpre[hi] and the whole tiles between (one
-// sparse-table pair within a group, else the two partial groups and the
-// whole groups between).
-__global__ void k_refit_upper(int64_t ninternal, int64_t ntiles, const int2 *__restrict__ range,
-                              const float4 *__restrict__ lpre, const float4 *__restrict__ lsuf,
-                              const float4 *__restrict__ tbox, const float4 *__restrict__ tpre,
-                              const float4 *__restrict__ tsuf, const float4 *__restrict__ gbox,
-                              const float4 *__restrict__ tdst, float4 *__restrict__ nbox) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ninternal;
-         i += (int64_t)gridDim.x * blockDim.x) {
+// One pass over the internal nodes, after the tiles and groups:
+//  - refit, top level: every node whose leaf range [lo, hi] spans tiles, on
+//    its own: the union of lsuf[lo], lpre[hi] and the whole tiles between
+//    (one sparse-table pair within a group, else the two partial groups and
+//    the whole groups between);
+//  - each pair's root: the node whose leaf range is exactly the pair's leaves
+//    (an endpoint of a node's range is its index, so it is node tri_begin or
+//    node tri_end - 1);
+//  - the four-wide collapse: a wide node stands for a binary node at even
+//    depth below its pair's root, and its slots hold that node's
+//    grandchildren (or a child itself when the child is a leaf); flag[i] = 1
+//    for such a representative;
+//  - threads below npairs: the pair's maxima, folded from the copies.
+__global__ void k_nodes(int64_t ninternal, int64_t ntiles, const int2 *__restrict__ range,
+                        const float4 *__restrict__ lpre, const float4 *__restrict__ lsuf,
+                        const float4 *__restrict__ tbox, const float4 *__restrict__ tpre,
+                        const float4 *__restrict__ tsuf, const float4 *__restrict__ gbox,
+                        const float4 *__restrict__ tdst, float4 *__restrict__ nbox, const int32_t *__restrict__ parentN,
+                        const unsigned long long *__restrict__ keys, BvhPair *pairs, int npairs,
+                        int32_t *__restrict__ flag, const PairAcc *__restrict__ acc, int astride) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < npairs) {
+        unsigned long long cm = 0, em = 0;
+        for (int c = 0; c < ACC_COPIES; ++c) {
+            const PairAcc &a = acc[(int64_t)c * astride + gid];
+            cm = a.coord_max > cm ? a.coord_max : cm;
+            em = a.edge_max > em ? a.edge_max : em;
+        }
+        pairs[gid].coord_max = ord2d(cm);
+        pairs[gid].edge_max = ord2d(em);
+    }
+    for (int64_t i = gid; i < ninternal; i += (int64_t)gridDim.x * blockDim.x) {
         const int2 r = range[i];
         const int64_t ta = r.x / TILE, tb = r.y / TILE;
-        if (ta == tb) continue;
-        FBox x = fbox_union(fbox_load(lsuf, r.x), fbox_load(lpre, r.y));
-        const int64_t a = ta + 1, b = tb - 1;
-        if (a == b) {
-            x = fbox_union(x, fbox_load(tbox, a));
-        } else if (a < b) {
-            const int64_t ga = a / TILE, gb = b / TILE;
-            if (ga == gb) {
-                const int l = 31 - __clz((int)(a ^ b));
-                const float4 *d = tdst + 2 * (int64_t)l * ntiles;
-                x = fbox_union(x, fbox_union(fbox_load(d, a), fbox_load(d, b)));
-            } else {
-                x = fbox_union(x, fbox_union(fbox_load(tsuf, a), fbox_load(tpre, b)));
-                for (int64_t g = ga + 1; g < gb; ++g) x = fbox_union(x, fbox_load(gbox, g));
+        if (ta != tb) {
+            FBox x = fbox_union(fbox_load(lsuf, r.x), fbox_load(lpre, r.y));
+            const int64_t a = ta + 1, b = tb - 1;
+            if (a == b) {
+                x = fbox_union(x, fbox_load(tbox, a));
+            } else if (a < b) {
+                const int64_t ga = a / TILE, gb = b / TILE;
+                if (ga == gb) {
+                    const int l = 31 - __clz((int)(a ^ b));
+                    const float4 *d = tdst + 2 * (int64_t)l * ntiles;
+                    x = fbox_union(x, fbox_union(fbox_load(d, a), fbox_load(d, b)));
+                } else {
+                    x = fbox_union(x, fbox_union(fbox_load(tsuf, a), fbox_load(tpre, b)));
+                    for (int64_t g = ga + 1; g < gb; ++g) x = fbox_union(x, fbox_load(gbox, g));
+                }
+            }
+            fbox_store(nbox, i, x);
+        }
+        int f = 0;
+        const int p = (int)(keys[r.x] >> 32);
+        if (p >= 0 && p < npairs) {
+            const int64_t b0 = pairs[p].tri_begin, b1 = pairs[p].tri_end; // leaves [b0, b1)
+            if (r.x >= b0 && (int64_t)r.y < b1 && b1 - b0 > 1) {
+                const bool root_lo = range[b0].x == b0 && (int64_t)range[b0].y == b1 - 1;
+                const int64_t root = root_lo ? b0 : b1 - 1;
+                if (i == root) pairs[p].root = (int32_t)i;
+                int depth = 0;
+                int32_t x = (int32_t)i;
+                while (x != root && x >= 0) {
+                    x = parentN[x];
+                    ++depth;
+                }
+                f = (x == root && (depth & 1) == 0) ? 1 : 0;
             }
         }
-        fbox_store(nbox, i, x);
+        flag[i] = f;
     }
 }
 
-// Collapse of the binary tree into four-wide nodes: a wide node stands for a
-// binary node at even depth below its pair's root, and its slots hold that
-// node's grandchildren (or a child itself when the child is a leaf).
-// flag[i] = 1 when internal node i is such a representative.
-__global__ void k_wide_flags(int64_t ninternal, const int32_t *__restrict__ parentN, const int2 *__restrict__ range,
-                             const BvhPair *__restrict__ pairs, int npairs, const unsigned long long *__restrict__ keys,
-                             int32_t *__restrict__ flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ninternal) return;
-    int f = 0;
-    const int2 r = range[i];
-    const int p = (int)(keys[r.x] >> 32);
-    if (p >= 0 && p < npairs) {
-        const BvhPair &P = pairs[p];
-        // inside the pair's subtree: the range lies within the pair's leaves
-        if (P.root >= 0 && r.x >= P.tri_begin && (int64_t)r.y < P.tri_end) {
-            int depth = 0;
-            int32_t x = (int32_t)i;
-            while (x != P.root && x >= 0) {
-                x = parentN[x];
-                ++depth;
-            }
-            f = (x == P.root && (depth & 1) == 0) ? 1 : 0;
-        }
-    }
-    flag[i] = f;
-}
-
-__global__ void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag, const int32_t *__restrict__ widx,
-                             const int32_t *__restrict__ childL, const int32_t *__restrict__ childR,
+// A four-wide node per flagged binary node, stored at the binary node's own
+// index (the array is sparse: no scan to number the flagged nodes, and slot
+// references are binary node indices).
+__global__ void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag, const int32_t *__restrict__ childL, const int32_t *__restrict__ childR,
                              const float4 *__restrict__ nbox, const float4 *__restrict__ lbox,
                              WideNode *__restrict__ out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -598,7 +610,7 @@ __global__ void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag
         load_box(nbox, lbox, c, l, h);
         // k is at most 3 here; the stores below use constant indices
         const float lv[3] = {l.x, l.y, l.z}, hv[3] = {h.x, h.y, h.z};
-        const int32_t rf = c < 0 ? c : widx[c];
+        const int32_t rf = c;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             if (s == k) {
@@ -641,18 +653,7 @@ __global__ void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag
     w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
     w.child = make_int4(ref[0], ref[1], ref[2], ref[3]);
     w.meta = make_int4(k, 0, 0, 0);
-    out[widx[i]] = w;
-}
-
-// root of each pair: the internal node whose leaf range is exactly the pair's
-__global__ void k_pair_roots(int64_t ninternal, const int2 *__restrict__ range, BvhPair *pairs, int npairs,
-                             const unsigned long long *__restrict__ keys) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ninternal) return;
-    int2 r = range[i];
-    int p = (int)(keys[r.x] >> 32);
-    if (p < 0 || p >= npairs) return;
-    if (pairs[p].tri_begin == r.x && pairs[p].tri_end == (int64_t)r.y + 1) pairs[p].root = (int32_t)i;
+    out[i] = w;
 }
 
 // Entry t of pair 0's top-level table (see TOP_NODES), by thread t: entry
@@ -677,23 +678,6 @@ __device__ void top_entry(const WideNode *__restrict__ nodes, int32_t root, Wide
             if (ch[m] >= 0) ch[m] = TOP_REF + first + m;
     }
     top[t] = w;
-}
-
-// per-pair maxima; the root becomes a wide-node index (widx null: no
-// internal nodes)
-__global__ void k_pair_finish(const PairAcc *acc, int npairs, int astride, BvhPair *pairs,
-                              const int32_t *__restrict__ widx) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
-    unsigned long long cm = 0, em = 0;
-    for (int c = 0; c < ACC_COPIES; ++c) {
-        const PairAcc &a = acc[(int64_t)c * astride + p];
-        cm = a.coord_max > cm ? a.coord_max : cm;
-        em = a.edge_max > em ? a.edge_max : em;
-    }
-    pairs[p].coord_max = ord2d(cm);
-    pairs[p].edge_max = ord2d(em);
-    if (widx && pairs[p].root >= 0) pairs[p].root = widx[pairs[p].root];
 }
 
 // pair 0's top-level table (a single-pair BVH with an internal root)
@@ -833,7 +817,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         size_t o_tdst = take(8 * ntiles * 2 * sizeof(float4));
         size_t o_gbox = take(ngroups * 2 * sizeof(float4));
         size_t o_flag = take(ni * sizeof(int32_t));
-        size_t o_widx = take(ni * sizeof(int32_t));
         size_t o_lbox = take(n * 2 * sizeof(float4));
         size_t o_nbox = take(ni * 2 * sizeof(float4));
         sc.mem.reserve(off);
@@ -855,7 +838,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         float4 *tdst = (float4 *)(base + o_tdst);
         float4 *gbox = (float4 *)(base + o_gbox);
         int32_t *flag = (int32_t *)(base + o_flag);
-        int32_t *widx = (int32_t *)(base + o_widx);
         float4 *lbox = (float4 *)(base + o_lbox);
         float4 *nbox = (float4 *)(base + o_nbox);
 
@@ -870,7 +852,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         const bool with_top = npairs == 1 && n > 1;
         if (with_top) b->top.reserve((size_t)TOP_NODES * sizeof(WideNode));
         sc.sort_tmp.reserve(radix_sort_tmp_bytes(n));
-        sc.scan_tmp.reserve(scan_tmp_bytes(ni));
         int pair_bits = 0;
         while ((1 << pair_bits) < npairs) ++pair_bits;
 
@@ -911,18 +892,15 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
                 k_karras<<<grid_for(ni, BLK), BLK, 0, q>>>(keys, n, cl, cr, pn, pl, range);
                 k_refit_tiles<<<(unsigned)ntiles, TILE, 0, q>>>(n, cl, cr, pn, pl, range, lbox, nbox, lpre, lsuf,
                                                                  tbox);
-                if (ntiles > 1) {
+                if (ntiles > 1)
                     k_refit_groups<<<(unsigned)ngroups, TILE, 0, q>>>(ntiles, tbox, tpre, tsuf, gbox, tdst);
-                    k_refit_upper<<<grid_for(std::min<int64_t>(ni, 512 * BLK), BLK), BLK, 0, q>>>(
-                        ni, ntiles, range, lpre, lsuf, tbox, tpre, tsuf, gbox, tdst, nbox);
-                }
-                k_pair_roots<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, range, dpairs, npairs, keys);
-                k_wide_flags<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, pn, range, dpairs, npairs, keys, flag);
-                scan_exclusive_i32(flag, widx, ni, &st->n_wide, sc.scan_tmp, q);
-                k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, widx, cl, cr, nbox, lbox,
-                                                               b->nodes.as<WideNode>());
             }
-            k_pair_finish<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, astride, dpairs, n > 1 ? widx : nullptr);
+            const int64_t nint = n - 1; // internal nodes (none for a single triangle)
+            k_nodes<<<grid_for(std::min<int64_t>(std::max<int64_t>(nint, npairs), 512 * BLK), BLK), BLK, 0, q>>>(
+                nint, ntiles, range, lpre, lsuf, tbox, tpre, tsuf, gbox, tdst, nbox, pn, keys, dpairs, npairs, flag,
+                acc, astride);
+            if (n > 1)
+                k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, cl, cr, nbox, lbox, b->nodes.as<WideNode>());
             if (with_top) k_wide_top<<<1, 64, 0, q>>>(b->nodes.as<WideNode>(), dpairs, b->top.as<WideNode>());
             HD_LAUNCH_CHECK();
             Export ex{};

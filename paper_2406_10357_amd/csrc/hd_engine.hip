@@ -72,7 +72,8 @@ struct Ctl {
     alignas(256) unsigned long long park_next;
     alignas(256) unsigned long long b_next; // records waiting for cascade stage B
     alignas(256) unsigned long long c_next; // records waiting for cascade stage C
-    alignas(256) int bad; // 1 invalid input, 2 traversal deeper than the fallback stack, 3 depth exhausted
+    alignas(256) int bad; // 2 traversal deeper than the fallback stack, 3 depth exhausted
+    int bad_input;        // 1: soup A has an out-of-range index or a non-finite coordinate
     int n_overflow;       // queries whose LDS stack overflowed this round
     alignas(256) unsigned long long stat[ACC_COPIES][ST_STRIDE];
     // blocks of the current query / argmax launch that have finished (the
@@ -80,6 +81,7 @@ struct Ctl {
     alignas(256) unsigned q_done, f_done;
     // device-planned rounds (written by plan_round, read by the round's kernels)
     alignas(256) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
+    unsigned long long nref;                           // referenced vertices of A (round 0's queries)
     unsigned long long subdivided, rounds;             // totals over the planned rounds
     double processed;                                  // faces processed (the paper's budget count)
     int stall;                                         // 1: capacity left no room to split
@@ -214,17 +216,18 @@ __global__ void k_ctl_init(Ctl *c) { ctl_zero(c); }
 // report may be in flight while the host reads the previous one.
 constexpr int MB_SLOTS = 4;
 struct alignas(64) Mailbox {
-    int64_t act, park, nref, rounds, subdivided;
+    int64_t act, park, rounds, subdivided;
+    int32_t bad_input, pad;
     int64_t pend_c; // records waiting for stage C (deferred)
     int bad, stall, over_budget;
     unsigned seq;
 };
 
-__device__ void report_to(const Ctl *ctl, const int32_t *nref, Mailbox *ring, unsigned seq) {
+__device__ void report_to(const Ctl *ctl, Mailbox *ring, unsigned seq) {
     Mailbox *mb = ring + seq % MB_SLOTS;
     mb->act = (long long)ctl->act_next;
     mb->park = (long long)ctl->park_next;
-    mb->nref = nref ? *nref : 0;
+    mb->bad_input = ctl->bad_input;
     mb->rounds = (long long)ctl->rounds;
     mb->subdivided = (long long)ctl->subdivided;
     mb->pend_c = (long long)ctl->c_next;
@@ -235,8 +238,8 @@ __device__ void report_to(const Ctl *ctl, const int32_t *nref, Mailbox *ring, un
     __hip_atomic_store(&mb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ void k_report(const Ctl *ctl, const int32_t *nref, Mailbox *ring, unsigned seq) {
-    if (threadIdx.x == 0) report_to(ctl, nref, ring, seq);
+__global__ void k_report(const Ctl *ctl, Mailbox *ring, unsigned seq) {
+    if (threadIdx.x == 0) report_to(ctl, ring, seq);
 }
 
 // Device-planned round: how many active records to split (all of them,
@@ -294,7 +297,7 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
 // reads afterwards)
 __global__ void k_report_plan(Ctl *ctl, Mailbox *ring, unsigned seq, PlanCaps caps) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    report_to(ctl, nullptr, ring, seq);
+    report_to(ctl, ring, seq);
     plan_round(ctl, caps);
 }
 
@@ -389,7 +392,7 @@ __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__rest
         for (int j = 0; j < 3; ++j) {
             int32_t v = s.F[3 * lf + j];
             if (v < 0 || v >= s.m) {
-                ctl->bad = 1;
+                ctl->bad_input = 1;
                 Fout[3 * f + j] = (int32_t)voff[p];
                 continue;
             }
@@ -399,7 +402,7 @@ __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__rest
             for (int k = 0; k < 3; ++k) {
                 double x = s.V[3 * (int64_t)v + k];
                 if (!__builtin_isfinite(x)) {
-                    ctl->bad = 1;
+                    ctl->bad_input = 1;
                     x = 0;
                 }
                 Vout[3 * vg + k] = x;
@@ -455,13 +458,14 @@ __device__ void pair_post(PairConst *pc, const PairBox *pb, int astride, const B
 // after the ingest: compact the referenced vertex ids (order preserving),
 // finish the pair tables, and set up round 0's counters
 __global__ void k_ingest_post(const int32_t *__restrict__ ref, const int32_t *__restrict__ pos, int64_t m,
-                              int32_t *__restrict__ out, PairConst *pc, const PairBox *pb, int astride,
-                              const BvhPair *__restrict__ bp, int npairs, const double *__restrict__ eps,
-                              int eps_per_pair, Ctl *ctl) {
+                              const int32_t *__restrict__ nref, int32_t *__restrict__ out, PairConst *pc,
+                              const PairBox *pb, int astride, const BvhPair *__restrict__ bp, int npairs,
+                              const double *__restrict__ eps, int eps_per_pair, Ctl *ctl) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < m && ref[v]) out[pos[v]] = (int32_t)v;
     if (v < npairs) pair_post(pc, pb, astride, bp, (int)v, eps, eps_per_pair);
     if (v == 0) {
+        ctl->nref = (unsigned long long)*nref;
         ctl->n_overflow = 0;
         ctl->act_next = 0;
         ctl->park_next = 0;
@@ -1873,9 +1877,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     Mailbox *mb = ws.host.as<Mailbox>(), *mb_dev = ws.host.dev_as<Mailbox>();
     // Enqueue a report and wait for it by polling the pinned mailbox: far
     // lower latency than a stream synchronisation plus a staged copy.
-    auto report_async = [&](const int32_t *nref) -> unsigned {
+    auto report_async = [&]() -> unsigned {
         const unsigned seq = ++ws.mb_seq;
-        k_report<<<1, 64, 0, s>>>(ctl, nref, mb_dev, seq);
+        k_report<<<1, 64, 0, s>>>(ctl, mb_dev, seq);
         HD_LAUNCH_CHECK();
         return seq;
     };
@@ -1883,9 +1887,15 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         const Mailbox *slot = mb + seq % MB_SLOTS;
         wait_host_seq(&slot->seq, seq, s);
         Mailbox m = *slot;
+        if (m.bad_input) {
+            // the ingest made the input safe to run on (indices and values
+            // replaced), and the rounds already enqueued finish first
+            HD_HIP(hipStreamSynchronize(s));
+            throw Error{HD_E_INVALID, "soup A has an out-of-range index or a non-finite coordinate"};
+        }
         return m;
     };
-    auto report = [&](const int32_t *nref) -> Mailbox { return wait_report(report_async(nref)); };
+    auto report = [&]() -> Mailbox { return wait_report(report_async()); };
     ws.pc.reserve(np * sizeof(PairConst));
     ws.pv.reserve(np * sizeof(PairVar));
     PairConst *pc = ws.pc.as<PairConst>();
@@ -1924,13 +1934,14 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                                               ctl);
     scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
     HD_LAUNCH_CHECK();
-    const Mailbox h0 = report(d_total);
-    if (h0.bad) throw Error{HD_E_INVALID, "soup A has an out-of-range index or a non-finite coordinate"};
-    const int64_t nref = h0.nref;
-    ws.vids.reserve(nref * sizeof(int32_t));
+    // The count of referenced vertices stays on the device (round 0's
+    // launches read it; their grids are sized for all mA vertices), and an
+    // invalid input is reported with the first round's report: no wait here.
+    ws.vids.reserve(mA * sizeof(int32_t));
     k_ingest_post<<<grid_for(std::max<int64_t>(mA, np), BLK), BLK, 0, s>>>(
-        ref, refpos, mA, ws.vids.as<int32_t>(), pc, pbox, pstride, B->pairs.as<BvhPair>(), np, deps, in.eps_per_pair,
-        ctl);
+        ref, refpos, mA, d_total, ws.vids.as<int32_t>(), pc, pbox, pstride, B->pairs.as<BvhPair>(), np, deps,
+        in.eps_per_pair, ctl);
+    const DevCount nref_dev{&ctl->nref, 1, 0};
 
     const BView<T> bv = [&] {
         if constexpr (sizeof(T) == 4) return BView<float>{B->frames32.as<float4>()};
@@ -1983,7 +1994,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.a = av;
         qi.pc = pc;
         const QueryCfg tcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
-        ws.ovf.reserve((size_t)nref * sizeof(int32_t));
+        ws.ovf.reserve((size_t)mA * sizeof(int32_t));
         if (ws.tune_ev[0] == nullptr)
             for (auto &e : ws.tune_ev) HD_HIP(hipEventCreate(&e));
         float best = 0, t_default = 0;
@@ -1993,7 +2004,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             for (int rep = 0; rep < 3; ++rep) {
                 k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
                 HD_HIP(hipEventRecord(ws.tune_ev[0], s));
-                launch_query<T>(v, nref, -1, qi, host_count(nref), tcfg, bv, tw.vq.o, pc, pv, ctl,
+                launch_query<T>(v, mA, -1, qi, nref_dev, tcfg, bv, tw.vq.o, pc, pv, ctl,
                                 ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
                 HD_HIP(hipEventRecord(ws.tune_ev[1], s));
                 HD_HIP(hipEventSynchronize(ws.tune_ev[1]));
@@ -2029,7 +2040,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         qi.voff = dvoff;
         qi.a = av;
         qi.pc = pc;
-        run_queries(qi, host_count(nref), nref, tw.vq.o); // counters set by k_ingest_post
+        run_queries(qi, nref_dev, mA, tw.vq.o); // counters set by k_ingest_post
     }
 
     // ---- frontier buffers ---------------------------------------------------
@@ -2188,7 +2199,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             k_stage_c<T><<<std::min<unsigned>(grid_for(hm.pend_c, BLK), GRID_MAX), BLK, 0, s>>>(
                 tw.pend_c.v, cc, Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 0);
             HD_LAUNCH_CHECK();
-            const Mailbox hf = report(nullptr);
+            const Mailbox hf = report();
             hm.act = hf.act;
             hm.park = hf.park;
             hm.bad = hf.bad;
@@ -2202,7 +2213,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         else if (hm.bad) status = HD_E_INTERNAL;
         else if (hm.over_budget || (hm.stall && hm.act > 0)) status = HD_E_CAPACITY;
     } else {
-        hm = report(nullptr);
+        hm = report();
         nAct = hm.act;
         nPark = hm.park;
         S.max_frontier = nAct + nPark;
@@ -2309,7 +2320,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
         later_stages(4 * K, tw.act2.v, 0);
         prof.mark(prof.c);
-        hm = report(nullptr);
+        hm = report();
         swap_fb(tw.act, tw.act2);
         nAct = hm.act;
         nPark = hm.park;
