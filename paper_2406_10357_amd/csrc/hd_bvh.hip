@@ -59,8 +59,9 @@ struct BuildState {
     int bad;
 };
 
-__global__ void k_init(PairAcc *acc, int npairs, int astride, BuildState *st) {
+__global__ void k_init(PairAcc *acc, int npairs, int astride, BuildState *st, unsigned *gcount, int ngroups) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ngroups) gcount[i] = 0;
     if (i == 0) {
         st->bad = 0;
     }
@@ -150,19 +151,14 @@ __global__ void k_faces_check(const PairSrc *__restrict__ src, const int64_t *__
     block_pair_minmax<6, 0x38u, BLK>(p, valid, v, [&](int q, int k) { return &acc_of(acc, astride, q).bbox[k]; });
 }
 
-// folds the box copies into copy 0 and takes the pair's centre
-__global__ void k_pair_centres(PairAcc *acc, int npairs, int astride, BvhPair *pairs) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npairs) return;
-    for (int k = 0; k < 6; ++k) {
-        unsigned long long b = acc[p].bbox[k];
-        for (int c = 1; c < ACC_COPIES; ++c) {
-            const unsigned long long x = acc[(int64_t)c * astride + p].bbox[k];
-            b = k < 3 ? (x < b ? x : b) : (x > b ? x : b);
-        }
-        acc[p].bbox[k] = b;
+// value k of pair p's box (0..2 lower, 3..5 upper), folded over the copies
+__device__ unsigned long long fold_box(const PairAcc *acc, int astride, int p, int k) {
+    unsigned long long b = acc[p].bbox[k];
+    for (int c = 1; c < ACC_COPIES; ++c) {
+        const unsigned long long x = acc[(int64_t)c * astride + p].bbox[k];
+        b = k < 3 ? (x < b ? x : b) : (x > b ? x : b);
     }
-    for (int k = 0; k < 3; ++k) pairs[p].ctr[k] = 0.5 * (ord2d(acc[p].bbox[k]) + ord2d(acc[p].bbox[3 + k]));
+    return b;
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
@@ -176,14 +172,32 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {
 
 // Centroid of each face (centred on its pair) and its key: the pair id above
 // a 30-bit Morton code of the centroid on a 1024^3 grid over the pair's vertex
-// box (centroids lie inside it). Also the pair's largest centred coordinate.
-__global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs, int64_t n,
-                            const BvhPair *__restrict__ pairs, int32_t *__restrict__ fpair, PairAcc *acc,
-                            int astride, const BuildState *st, unsigned long long *__restrict__ keys,
-                            int32_t *__restrict__ vals) {
+// box (centroids lie inside it). Also the pair's largest centred coordinate,
+// and its centre (the box midpoint, written by the thread of its first face).
+// A block folds the box copies of its pairs in LDS (when it spans few pairs;
+// else every thread folds its own pair's).
+constexpr int CENTRE_PAIRS = 8;
+__global__ __launch_bounds__(BLK) void k_centroids(const PairSrc *__restrict__ src,
+                                                   const int64_t *__restrict__ foff, int npairs, int64_t n,
+                                                   BvhPair *__restrict__ pairs, int32_t *__restrict__ fpair,
+                                                   PairAcc *acc, int astride, const BuildState *st,
+                                                   unsigned long long *__restrict__ keys,
+                                                   int32_t *__restrict__ vals) {
+    __shared__ double s_box[CENTRE_PAIRS][6];
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = f < n && !st->bad;
     int p = pair_of(foff, npairs, f < n ? f : n - 1);
+    const int64_t f0 = (int64_t)blockIdx.x * blockDim.x, f1 = std::min<int64_t>(f0 + blockDim.x, n) - 1;
+    const int pa = pair_of(foff, npairs, f0), pb = pair_of(foff, npairs, f1);
+    const bool in_lds = pb - pa < CENTRE_PAIRS;
+    if (in_lds && (int)threadIdx.x < (pb - pa + 1) * 6)
+        s_box[threadIdx.x / 6][threadIdx.x % 6] = ord2d(fold_box(acc, astride, pa + threadIdx.x / 6, threadIdx.x % 6));
+    __syncthreads();
+    double box[6];
+    for (int k = 0; k < 6; ++k) box[k] = in_lds ? s_box[p - pa][k] : ord2d(fold_box(acc, astride, p, k));
+    const double ctr[3] = {0.5 * (box[0] + box[3]), 0.5 * (box[1] + box[4]), 0.5 * (box[2] + box[5])};
+    if (f < n && f == foff[p])
+        for (int k = 0; k < 3; ++k) pairs[p].ctr[k] = ctr[k];
     double m = 0;
     if (valid) {
         PairSrc ps = src[p];
@@ -192,14 +206,14 @@ __global__ void k_centroids(const PairSrc *__restrict__ src, const int64_t *__re
         for (int j = 0; j < 3; ++j) {
             int32_t v = ps.F[3 * lf + j];
             for (int k = 0; k < 3; ++k) {
-                double x = ps.V[3 * (int64_t)v + k] - pairs[p].ctr[k];
+                double x = ps.V[3 * (int64_t)v + k] - ctr[k];
                 c[k] += x;
                 m = fmax(m, fabs(x));
             }
         }
         uint32_t q[3];
         for (int k = 0; k < 3; ++k) {
-            const double lo = ord2d(acc[p].bbox[k]) - pairs[p].ctr[k], hi = ord2d(acc[p].bbox[3 + k]) - pairs[p].ctr[k];
+            const double lo = box[k] - ctr[k], hi = box[3 + k] - ctr[k];
             const double ext = hi - lo;
             double t = ext > 0 ? (c[k] / 3.0 - lo) / ext : 0.5;
             t = t == t ? t : 0.5;
@@ -224,13 +238,10 @@ __device__ __forceinline__ int delta(const unsigned long long *__restrict__ keys
     return __clzll(a ^ b);
 }
 
-// Karras 2012, one thread per internal node i in [0, n-2]; also the node's
-// leaf range
-__global__ void k_karras(const unsigned long long *__restrict__ keys, int64_t n, int32_t *__restrict__ childL,
-                         int32_t *__restrict__ childR, int32_t *__restrict__ parentN, int32_t *__restrict__ parentL,
-                         int2 *__restrict__ range) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
+// Karras 2012, internal node i in [0, n-2]; also the node's leaf range
+__device__ void karras_node(const unsigned long long *__restrict__ keys, int64_t n, int32_t *__restrict__ childL,
+                            int32_t *__restrict__ childR, int32_t *__restrict__ parentN,
+                            int32_t *__restrict__ parentL, int2 *__restrict__ range, int64_t i) {
     if (i == 0) parentN[0] = -1; // the root (every other node is some node's child)
     int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
     int dmin = delta(keys, n, i, i - d);
@@ -275,13 +286,19 @@ __device__ double build_leaf(const PairSrc *__restrict__ src, const int64_t *__r
                              const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox, float4 *__restrict__ fr32,
                              double2 *__restrict__ fr64, int4 *__restrict__ ids, int64_t i);
 
+// After the sort, thread i: leaf i (frames, box, ids) and internal node i
+// of the hierarchy (karras_node); both read only the sorted keys and order.
 __global__ __launch_bounds__(BLK) void k_leaves(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff,
                                                 const int32_t *__restrict__ fpair, const int32_t *__restrict__ order,
                                                 int64_t n, const BvhPair *__restrict__ pairs, float4 *__restrict__ lbox,
                                                 float4 *__restrict__ fr32, double2 *__restrict__ fr64,
                                                 int4 *__restrict__ ids, PairAcc *acc, int astride,
-                                                const BuildState *st) {
+                                                const BuildState *st, const unsigned long long *__restrict__ keys,
+                                                int32_t *__restrict__ childL, int32_t *__restrict__ childR,
+                                                int32_t *__restrict__ parentN, int32_t *__restrict__ parentL,
+                                                int2 *__restrict__ range) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n - 1) karras_node(keys, n, childL, childR, parentN, parentL, range, i);
     const bool valid = i < n && !st->bad;
     int p = 0;
     double Lb = 0;
@@ -440,6 +457,28 @@ __device__ void run_unions(FBox box, LdsBoxes &P, LdsBoxes &S, FBox &pre, FBox &
     }
 }
 
+// Refit, middle level: group g of TILE consecutive tiles, by one workgroup.
+// tpre / tsuf: unions of the group's tiles up to / from tile a; gbox: the
+// group's box; tdst[l][a] (l = 0..7, h = 2^l): the union from a to the end of
+// its h-run when bit l of a is clear, from the start of its h-run to a when it
+// is set (a disjoint sparse table: tiles a < b of one group with highest
+// differing bit l have union tdst[l][a] U tdst[l][b]).
+__device__ void group_tables(int64_t g, int64_t ntiles, const float4 *__restrict__ tbox, float4 *__restrict__ tpre,
+                             float4 *__restrict__ tsuf, float4 *__restrict__ gbox, float4 *__restrict__ tdst,
+                             LdsBoxes &P, LdsBoxes &S) {
+    const int64_t a = g * TILE + threadIdx.x;
+    const FBox b = a < ntiles ? fbox_load(tbox, a) : fbox_empty();
+    FBox pre, suf;
+    run_unions(b, P, S, pre, suf, [&](int h, const FBox &ph, const FBox &sh) {
+        if (a < ntiles) fbox_store(tdst + 2 * (int64_t)(__builtin_ctz(h)) * ntiles, a, (a & h) ? ph : sh);
+    });
+    if (a < ntiles) {
+        fbox_store(tpre, a, pre);
+        fbox_store(tsuf, a, suf);
+    }
+    if (threadIdx.x == TILE - 1) fbox_store(gbox, g, pre);
+}
+
 // Refit, bottom level: one workgroup per tile of TILE consecutive leaves.
 //  - Nodes whose leaf range lies inside the tile (their index then lies in
 //    the tile too): bottom-up climb in LDS, the second thread to reach a node
@@ -447,13 +486,18 @@ __device__ void run_unions(FBox box, LdsBoxes &P, LdsBoxes &S, FBox &pre, FBox &
 //  - For every leaf i: lpre[i] = union of the tile's leaves up to i, lsuf[i]
 //    = union of leaves i to the tile's end; tbox = the tile's box. Nodes that
 //    span tiles take their boxes from these (k_nodes).
+//  - The last tile of each group of TILE tiles to finish (gcount: one ticket
+//    per group, zero at launch) then builds that group's tables.
 __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *__restrict__ childL,
                                                       const int32_t *__restrict__ childR,
                                                       const int32_t *__restrict__ parentN,
                                                       const int32_t *__restrict__ parentL,
                                                       const int2 *__restrict__ range, const float4 *__restrict__ lbox,
                                                       float4 *__restrict__ nbox, float4 *__restrict__ lpre,
-                                                      float4 *__restrict__ lsuf, float4 *__restrict__ tbox) {
+                                                      float4 *__restrict__ lsuf, float4 *__restrict__ tbox,
+                                                      int64_t ntiles, unsigned *gcount, float4 *__restrict__ tpre,
+                                                      float4 *__restrict__ tsuf, float4 *__restrict__ gbox,
+                                                      float4 *__restrict__ tdst) {
     __shared__ LdsBoxes leaf, node;
     __shared__ int s_cl[TILE], s_cr[TILE], s_pn[TILE], s_cnt[TILE];
     __shared__ bool s_in[TILE];
@@ -496,29 +540,19 @@ __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *
         fbox_store(lsuf, i, suf);
     }
     if (t == TILE - 1) fbox_store(tbox, blockIdx.x, pre);
-}
-
-// Refit, middle level: one workgroup per group of TILE consecutive tiles.
-// tpre / tsuf: unions of the group's tiles up to / from tile a; gbox: the
-// group's box; tdst[l][a] (l = 0..7, h = 2^l): the union from a to the end of
-// its h-run when bit l of a is clear, from the start of its h-run to a when it
-// is set (a disjoint sparse table: tiles a < b of one group with highest
-// differing bit l have union tdst[l][a] U tdst[l][b]).
-__global__ __launch_bounds__(TILE) void k_refit_groups(int64_t ntiles, const float4 *__restrict__ tbox,
-                                                       float4 *__restrict__ tpre, float4 *__restrict__ tsuf,
-                                                       float4 *__restrict__ gbox, float4 *__restrict__ tdst) {
-    __shared__ LdsBoxes P, S;
-    const int64_t a = (int64_t)blockIdx.x * TILE + threadIdx.x;
-    const FBox b = a < ntiles ? fbox_load(tbox, a) : fbox_empty();
-    FBox pre, suf;
-    run_unions(b, P, S, pre, suf, [&](int h, const FBox &ph, const FBox &sh) {
-        if (a < ntiles) fbox_store(tdst + 2 * (int64_t)(__builtin_ctz(h)) * ntiles, a, (a & h) ? ph : sh);
-    });
-    if (a < ntiles) {
-        fbox_store(tpre, a, pre);
-        fbox_store(tsuf, a, suf);
+    if (ntiles <= 1) return; // no node spans tiles
+    __shared__ int s_last;
+    __syncthreads();
+    const int64_t g = blockIdx.x / TILE;
+    if (t == 0) {
+        __threadfence();
+        const unsigned in_group = (unsigned)std::min<int64_t>(TILE, ntiles - g * TILE);
+        s_last = atomicAdd(&gcount[g], 1u) == in_group - 1;
     }
-    if (threadIdx.x == TILE - 1) fbox_store(gbox, blockIdx.x, pre);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    group_tables(g, ntiles, tbox, tpre, tsuf, gbox, tdst, leaf, node);
 }
 
 // One pass over the internal nodes, after the tiles and groups:
@@ -597,11 +631,8 @@ __global__ void k_nodes(int64_t ninternal, int64_t ntiles, const int2 *__restric
 // A four-wide node per flagged binary node, stored at the binary node's own
 // index (the array is sparse: no scan to number the flagged nodes, and slot
 // references are binary node indices).
-__global__ void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag, const int32_t *__restrict__ childL, const int32_t *__restrict__ childR,
-                             const float4 *__restrict__ nbox, const float4 *__restrict__ lbox,
-                             WideNode *__restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ninternal || !flag[i]) return;
+__device__ void wide_node(int64_t i, const int32_t *__restrict__ childL, const int32_t *__restrict__ childR,
+                          const float4 *__restrict__ nbox, const float4 *__restrict__ lbox, WideNode *__restrict__ out) {
     float lo[3][4], hi[3][4];
     int ref[4];
     int k = 0;
@@ -680,10 +711,29 @@ __device__ void top_entry(const WideNode *__restrict__ nodes, int32_t root, Wide
     top[t] = w;
 }
 
-// pair 0's top-level table (a single-pair BVH with an internal root)
-__global__ void k_wide_top(const WideNode *__restrict__ nodes, const BvhPair *pairs, WideNode *top) {
+// The four-wide nodes, one thread per binary node; with top non-null, the
+// block that finishes last (done: zero at launch) then writes pair 0's
+// top-level table (a single-pair BVH with an internal root).
+__global__ __launch_bounds__(BLK) void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag,
+                                                    const int32_t *__restrict__ childL,
+                                                    const int32_t *__restrict__ childR,
+                                                    const float4 *__restrict__ nbox, const float4 *__restrict__ lbox,
+                                                    WideNode *out, const BvhPair *pairs, WideNode *top,
+                                                    unsigned *done) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ninternal && flag[i]) wide_node(i, childL, childR, nbox, lbox, out);
+    if (!top) return;
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
     const int32_t root = pairs[0].root;
-    if (root >= 0) top_entry(nodes, root, top, threadIdx.x);
+    if (root >= 0) top_entry(out, root, top, threadIdx.x);
 }
 
 
@@ -816,6 +866,7 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         size_t o_tps = take(3 * ntiles * 2 * sizeof(float4)); // tbox, tpre, tsuf
         size_t o_tdst = take(8 * ntiles * 2 * sizeof(float4));
         size_t o_gbox = take(ngroups * 2 * sizeof(float4));
+        size_t o_gcount = take((ngroups + 1) * sizeof(unsigned)); // group tickets, then the wide-node ticket
         size_t o_flag = take(ni * sizeof(int32_t));
         size_t o_lbox = take(n * 2 * sizeof(float4));
         size_t o_nbox = take(ni * 2 * sizeof(float4));
@@ -837,6 +888,7 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         float4 *tbox = (float4 *)(base + o_tps), *tpre = tbox + 2 * ntiles, *tsuf = tpre + 2 * ntiles;
         float4 *tdst = (float4 *)(base + o_tdst);
         float4 *gbox = (float4 *)(base + o_gbox);
+        unsigned *gcount = (unsigned *)(base + o_gcount);
         int32_t *flag = (int32_t *)(base + o_flag);
         float4 *lbox = (float4 *)(base + o_lbox);
         float4 *nbox = (float4 *)(base + o_nbox);
@@ -877,31 +929,30 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         auto enqueue = [&](hipStream_t q) {
             HD_HIP(hipMemcpyAsync(dsrc, sc.host.as<char>(o_src), o_pairs - o_src, hipMemcpyHostToDevice, q));
             HD_HIP(hipMemcpyAsync(dpairs, hp, npairs * sizeof(BvhPair), hipMemcpyHostToDevice, q));
-            k_init<<<grid_for((int64_t)npairs * ACC_COPIES, 64), 64, 0, q>>>(acc, npairs, astride, st);
+            k_init<<<grid_for(std::max<int64_t>((int64_t)npairs * ACC_COPIES, ngroups + 1), 64), 64, 0, q>>>(
+                acc, npairs, astride, st, gcount, (int)ngroups + 1);
             k_faces_check<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, astride, st);
-            k_pair_centres<<<grid_for(npairs, 64), 64, 0, q>>>(acc, npairs, astride, dpairs);
-            k_centroids<<<grid_for(std::max<int64_t>(n, ni), BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
+            k_centroids<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
                                                                                  acc, astride, st, keys, vals);
             HD_LAUNCH_CHECK();
             radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, q);
             k_leaves<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, fpair, vals, n, dpairs, lbox,
                                                       b->frames32.as<float4>(), b->frames64.as<double2>(),
-                                                      b->ids.as<int4>(), acc, astride, st);
+                                                      b->ids.as<int4>(), acc, astride, st, keys, cl, cr, pn, pl,
+                                                      range);
             HD_LAUNCH_CHECK();
             if (n > 1) {
-                k_karras<<<grid_for(ni, BLK), BLK, 0, q>>>(keys, n, cl, cr, pn, pl, range);
                 k_refit_tiles<<<(unsigned)ntiles, TILE, 0, q>>>(n, cl, cr, pn, pl, range, lbox, nbox, lpre, lsuf,
-                                                                 tbox);
-                if (ntiles > 1)
-                    k_refit_groups<<<(unsigned)ngroups, TILE, 0, q>>>(ntiles, tbox, tpre, tsuf, gbox, tdst);
+                                                                 tbox, ntiles, gcount, tpre, tsuf, gbox, tdst);
             }
             const int64_t nint = n - 1; // internal nodes (none for a single triangle)
             k_nodes<<<grid_for(std::min<int64_t>(std::max<int64_t>(nint, npairs), 512 * BLK), BLK), BLK, 0, q>>>(
                 nint, ntiles, range, lpre, lsuf, tbox, tpre, tsuf, gbox, tdst, nbox, pn, keys, dpairs, npairs, flag,
                 acc, astride);
             if (n > 1)
-                k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, cl, cr, nbox, lbox, b->nodes.as<WideNode>());
-            if (with_top) k_wide_top<<<1, 64, 0, q>>>(b->nodes.as<WideNode>(), dpairs, b->top.as<WideNode>());
+                k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, cl, cr, nbox, lbox, b->nodes.as<WideNode>(),
+                                                               dpairs, with_top ? b->top.as<WideNode>() : nullptr,
+                                                               gcount + ngroups);
             HD_LAUNCH_CHECK();
             Export ex{};
             ex.n = 2;
