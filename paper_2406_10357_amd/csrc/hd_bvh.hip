@@ -93,30 +93,6 @@ struct PairSrc {
     int64_t m;
 };
 
-// true when every active lane of the wave holds the same value of p
-__device__ __forceinline__ bool uniform_pair(int p) {
-    int p0 = __shfl(p, __ffsll((unsigned long long)__ballot(1)) - 1, 64);
-    return __ballot(p != p0) == 0;
-}
-
-// min/max over a wave when every active lane has the same pair, else per lane
-__device__ __forceinline__ void acc_min(unsigned long long *a, double v, bool uni) {
-    if (uni) {
-        for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-        if (__lane_id() == 0) atomicMin(a, d2ord(v));
-    } else {
-        atomicMin(a, d2ord(v));
-    }
-}
-__device__ __forceinline__ void acc_max(unsigned long long *a, double v, bool uni) {
-    if (uni) {
-        for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-        if (__lane_id() == 0) atomicMax(a, d2ord(v));
-    } else {
-        atomicMax(a, d2ord(v));
-    }
-}
-
 // validate faces and compute each pair's vertex box (through its faces).
 // Every lane of a launched wave takes part (inactive lanes carry neutral
 // values) so that the wave-wide reductions see 64 lanes.
@@ -385,15 +361,6 @@ __device__ __forceinline__ void load_box(const float4 *nbox, const float4 *__res
         lo = lbox[2 * (int64_t)(~c)];
         hi = lbox[2 * (int64_t)(~c) + 1];
     }
-}
-
-__device__ __forceinline__ void union_box(const float4 *nbox, const float4 *__restrict__ lbox, int32_t cl, int32_t cr,
-                                          float4 *out) {
-    float4 l0, h0, l1, h1;
-    load_box(nbox, lbox, cl, l0, h0);
-    load_box(nbox, lbox, cr, l1, h1);
-    out[0] = make_float4(fminf(l0.x, l1.x), fminf(l0.y, l1.y), fminf(l0.z, l1.z), 0.f);
-    out[1] = make_float4(fmaxf(h0.x, h1.x), fmaxf(h0.y, h1.y), fmaxf(h0.z, h1.z), 0.f);
 }
 
 // Float boxes as six values; union is exact (min / max), so any grouping of
@@ -749,14 +716,14 @@ __global__ __launch_bounds__(BLK) void k_wide_nodes(int64_t ninternal, const int
 // kernels back to back instead of waiting on the host for each. A few graphs
 // are kept per device (builds alternate between the pooled BVH handles).
 constexpr int BUILD_GRAPHS = 4;
-constexpr int BUILD_KEY = 14;
+constexpr int BUILD_KEY = 13;
 struct BuildGraph {
     uintptr_t key[BUILD_KEY];
     hipGraphExec_t exec = nullptr;
 };
 struct BuildScratch {
     std::mutex mu;
-    DBuf mem, sort_tmp, src, scan_tmp;
+    DBuf mem, sort_tmp, src;
     PinnedBuf host; // [0, 4) export sequence word; staged uploads; exported results
     hipStream_t capture = nullptr;     // stream the build is captured on (never run)
     std::vector<BuildGraph> graphs;    // most recently used last
@@ -972,7 +939,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
                                               (uintptr_t)sc.mem.p,
                                               (uintptr_t)sc.src.p,
                                               (uintptr_t)sc.sort_tmp.p,
-                                              (uintptr_t)sc.scan_tmp.p,
                                               (uintptr_t)sc.host.p,
                                               (uintptr_t)b->pairs.p,
                                               (uintptr_t)b->nodes.p,

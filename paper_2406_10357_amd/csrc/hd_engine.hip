@@ -148,27 +148,6 @@ __device__ __forceinline__ int pair_of(const int64_t *__restrict__ off, int npai
     return lo;
 }
 
-__device__ __forceinline__ bool wave_uniform(int p) {
-    int p0 = __shfl(p, __ffsll((unsigned long long)__ballot(1)) - 1, 64);
-    return __ballot(p != p0) == 0;
-}
-__device__ __forceinline__ void acc_min(unsigned long long *a, double v, bool uni) {
-    if (uni) {
-        for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-        if (__lane_id() == 0) atomicMin(a, d2ord(v));
-    } else {
-        atomicMin(a, d2ord(v));
-    }
-}
-__device__ __forceinline__ void acc_max(unsigned long long *a, double v, bool uni) {
-    if (uni) {
-        for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-        if (__lane_id() == 0) atomicMax(a, d2ord(v));
-    } else {
-        atomicMax(a, d2ord(v));
-    }
-}
-
 template <class T> HD_HD const Margins &margins_of(const PairConst &p);
 template <> HD_HD const Margins &margins_of<float>(const PairConst &p) { return p.m32; }
 template <> HD_HD const Margins &margins_of<double>(const PairConst &p) { return p.m64; }

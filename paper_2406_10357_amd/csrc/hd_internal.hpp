@@ -136,9 +136,8 @@ void wait_host_seq(const unsigned *seq_host, unsigned seq, hipStream_t s);
 hd_status mlp_forward(const float *X, int64_t n, const float *params, float *y, hipStream_t s);
 
 // --- primitives (hd_prims.hip) -------------------------------------------
-// Scratch bytes (the tmp buffer) the scan and the radix sort below need for
-// n values: reserved up front, they add no allocation to a call.
-size_t scan_tmp_bytes(int64_t n);
+// Scratch bytes (the tmp buffer) the radix sort below needs for n values:
+// reserved up front, it adds no allocation to a call.
 size_t radix_sort_tmp_bytes(int64_t n);
 // Exclusive scan of n int32 values; total in *d_total (device, may be null).
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,

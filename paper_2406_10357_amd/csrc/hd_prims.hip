@@ -365,7 +365,6 @@ void wait_host_seq(const unsigned *seq_host, unsigned seq, hipStream_t s) {
 }
 
 size_t radix_sort_tmp_bytes(int64_t n) { return n <= 1 ? 0 : RadixPlan(n).tmp_bytes(); }
-size_t scan_tmp_bytes(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) * sizeof(int32_t); }
 
 void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *d_total, DBuf &tmp,
                         hipStream_t s) {
