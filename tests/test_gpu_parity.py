@@ -564,6 +564,30 @@ def test_translation_closed_form():
         assert L <= t + 1e-12 <= U + 2e-12 and U - L <= st["eps_abs"] * (1 + 1e-12)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 255, 256, 257, 511, 513, 65535, 65536, 65537, 65536 + 257])
+def test_build_sizes_at_tile_and_group_boundaries(n):
+    """BVH builds whose triangle count falls on either side of a refit tile
+    (256 leaves) and of a group of tiles (65536 leaves): every node box comes
+    from the in-tile climb, the tile / group tables or the whole groups
+    between, so FP64 point distances must equal the oracle's brute force.
+    Half of the points are centroids of sampled triangles (distance 0 to
+    their own triangle: a box that missed part of its subtree would show);
+    the four-lane kernel (with the top-level table) must agree too."""
+    hd, torch = _hd()
+    rng = np.random.default_rng(1000 + n)
+    C = rng.uniform(-1, 1, size=(n, 3))
+    V = (C[:, None, :] + 0.05 * rng.normal(size=(n, 3, 3))).reshape(-1, 3)
+    F = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    pick = rng.choice(n, size=min(n, 400), replace=False)
+    P = np.concatenate([V[F[pick]].mean(1), rng.uniform(-1.2, 1.2, size=(300, 3))])
+    say("build sizes: n", n, "points", P.shape[0])
+    bvh = hd.build_bvh(_cu(V, torch), _cu(F, torch))
+    dref, _ = oracle.points_soup(P, V, F)
+    for lanes in (1, 4):
+        d = hd.point_distances(_cu(P, torch), bvh, precision=hd.PREC_FP64, lanes=lanes)[0].cpu().numpy()
+        assert np.abs(d - dref).max() <= 1e-12, (lanes, float(np.abs(d - dref).max()))
+
+
 def test_build_graph_replays_match_eager():
     """BVH builds replayed from captured HIP graphs give what direct launches
     give: the same closest faces, distances and closest points, bit for bit,
