@@ -59,9 +59,8 @@ struct BuildState {
     int bad;
 };
 
-__global__ void k_init(PairAcc *acc, int npairs, int astride, BuildState *st, unsigned *gcount, int ngroups) {
+__global__ void k_init(PairAcc *acc, int npairs, int astride, BuildState *st) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ngroups) gcount[i] = 0;
     if (i == 0) {
         st->bad = 0;
     }
@@ -453,18 +452,13 @@ __device__ void group_tables(int64_t g, int64_t ntiles, const float4 *__restrict
 //  - For every leaf i: lpre[i] = union of the tile's leaves up to i, lsuf[i]
 //    = union of leaves i to the tile's end; tbox = the tile's box. Nodes that
 //    span tiles take their boxes from these (k_nodes).
-//  - The last tile of each group of TILE tiles to finish (gcount: one ticket
-//    per group, zero at launch) then builds that group's tables.
 __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *__restrict__ childL,
                                                       const int32_t *__restrict__ childR,
                                                       const int32_t *__restrict__ parentN,
                                                       const int32_t *__restrict__ parentL,
                                                       const int2 *__restrict__ range, const float4 *__restrict__ lbox,
                                                       float4 *__restrict__ nbox, float4 *__restrict__ lpre,
-                                                      float4 *__restrict__ lsuf, float4 *__restrict__ tbox,
-                                                      int64_t ntiles, unsigned *gcount, float4 *__restrict__ tpre,
-                                                      float4 *__restrict__ tsuf, float4 *__restrict__ gbox,
-                                                      float4 *__restrict__ tdst) {
+                                                      float4 *__restrict__ lsuf, float4 *__restrict__ tbox) {
     __shared__ LdsBoxes leaf, node;
     __shared__ int s_cl[TILE], s_cr[TILE], s_pn[TILE], s_cnt[TILE];
     __shared__ bool s_in[TILE];
@@ -507,19 +501,16 @@ __global__ __launch_bounds__(TILE) void k_refit_tiles(int64_t n, const int32_t *
         fbox_store(lsuf, i, suf);
     }
     if (t == TILE - 1) fbox_store(tbox, blockIdx.x, pre);
-    if (ntiles <= 1) return; // no node spans tiles
-    __shared__ int s_last;
-    __syncthreads();
-    const int64_t g = blockIdx.x / TILE;
-    if (t == 0) {
-        __threadfence();
-        const unsigned in_group = (unsigned)std::min<int64_t>(TILE, ntiles - g * TILE);
-        s_last = atomicAdd(&gcount[g], 1u) == in_group - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    group_tables(g, ntiles, tbox, tpre, tsuf, gbox, tdst, leaf, node);
+}
+
+// one workgroup per group of tiles (group_tables); a separate launch: as the
+// tail of the tile kernel (the last tile of a group to finish) it cost more,
+// every tile block then fencing its writes device-wide
+__global__ __launch_bounds__(TILE) void k_refit_groups(int64_t ntiles, const float4 *__restrict__ tbox,
+                                                       float4 *__restrict__ tpre, float4 *__restrict__ tsuf,
+                                                       float4 *__restrict__ gbox, float4 *__restrict__ tdst) {
+    __shared__ LdsBoxes P, S;
+    group_tables(blockIdx.x, ntiles, tbox, tpre, tsuf, gbox, tdst, P, S);
 }
 
 // One pass over the internal nodes, after the tiles and groups:
@@ -678,29 +669,20 @@ __device__ void top_entry(const WideNode *__restrict__ nodes, int32_t root, Wide
     top[t] = w;
 }
 
-// The four-wide nodes, one thread per binary node; with top non-null, the
-// block that finishes last (done: zero at launch) then writes pair 0's
-// top-level table (a single-pair BVH with an internal root).
+// the four-wide nodes, one thread per binary node
 __global__ __launch_bounds__(BLK) void k_wide_nodes(int64_t ninternal, const int32_t *__restrict__ flag,
                                                     const int32_t *__restrict__ childL,
                                                     const int32_t *__restrict__ childR,
                                                     const float4 *__restrict__ nbox, const float4 *__restrict__ lbox,
-                                                    WideNode *out, const BvhPair *pairs, WideNode *top,
-                                                    unsigned *done) {
+                                                    WideNode *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ninternal && flag[i]) wide_node(i, childL, childR, nbox, lbox, out);
-    if (!top) return;
-    __shared__ int s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = atomicAdd(done, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
+
+// pair 0's top-level table (a single-pair BVH with an internal root)
+__global__ void k_wide_top(const WideNode *__restrict__ nodes, const BvhPair *pairs, WideNode *top) {
     const int32_t root = pairs[0].root;
-    if (root >= 0) top_entry(out, root, top, threadIdx.x);
+    if (root >= 0) top_entry(nodes, root, top, threadIdx.x);
 }
 
 
@@ -833,7 +815,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         size_t o_tps = take(3 * ntiles * 2 * sizeof(float4)); // tbox, tpre, tsuf
         size_t o_tdst = take(8 * ntiles * 2 * sizeof(float4));
         size_t o_gbox = take(ngroups * 2 * sizeof(float4));
-        size_t o_gcount = take((ngroups + 1) * sizeof(unsigned)); // group tickets, then the wide-node ticket
         size_t o_flag = take(ni * sizeof(int32_t));
         size_t o_lbox = take(n * 2 * sizeof(float4));
         size_t o_nbox = take(ni * 2 * sizeof(float4));
@@ -855,7 +836,6 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         float4 *tbox = (float4 *)(base + o_tps), *tpre = tbox + 2 * ntiles, *tsuf = tpre + 2 * ntiles;
         float4 *tdst = (float4 *)(base + o_tdst);
         float4 *gbox = (float4 *)(base + o_gbox);
-        unsigned *gcount = (unsigned *)(base + o_gcount);
         int32_t *flag = (int32_t *)(base + o_flag);
         float4 *lbox = (float4 *)(base + o_lbox);
         float4 *nbox = (float4 *)(base + o_nbox);
@@ -896,8 +876,7 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
         auto enqueue = [&](hipStream_t q) {
             HD_HIP(hipMemcpyAsync(dsrc, sc.host.as<char>(o_src), o_pairs - o_src, hipMemcpyHostToDevice, q));
             HD_HIP(hipMemcpyAsync(dpairs, hp, npairs * sizeof(BvhPair), hipMemcpyHostToDevice, q));
-            k_init<<<grid_for(std::max<int64_t>((int64_t)npairs * ACC_COPIES, ngroups + 1), 64), 64, 0, q>>>(
-                acc, npairs, astride, st, gcount, (int)ngroups + 1);
+            k_init<<<grid_for((int64_t)npairs * ACC_COPIES, 64), 64, 0, q>>>(acc, npairs, astride, st);
             k_faces_check<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, astride, st);
             k_centroids<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
                                                                                  acc, astride, st, keys, vals);
@@ -910,16 +889,17 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
             HD_LAUNCH_CHECK();
             if (n > 1) {
                 k_refit_tiles<<<(unsigned)ntiles, TILE, 0, q>>>(n, cl, cr, pn, pl, range, lbox, nbox, lpre, lsuf,
-                                                                 tbox, ntiles, gcount, tpre, tsuf, gbox, tdst);
+                                                                 tbox);
+                if (ntiles > 1)
+                    k_refit_groups<<<(unsigned)ngroups, TILE, 0, q>>>(ntiles, tbox, tpre, tsuf, gbox, tdst);
             }
             const int64_t nint = n - 1; // internal nodes (none for a single triangle)
             k_nodes<<<grid_for(std::min<int64_t>(std::max<int64_t>(nint, npairs), 512 * BLK), BLK), BLK, 0, q>>>(
                 nint, ntiles, range, lpre, lsuf, tbox, tpre, tsuf, gbox, tdst, nbox, pn, keys, dpairs, npairs, flag,
                 acc, astride);
             if (n > 1)
-                k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, cl, cr, nbox, lbox, b->nodes.as<WideNode>(),
-                                                               dpairs, with_top ? b->top.as<WideNode>() : nullptr,
-                                                               gcount + ngroups);
+                k_wide_nodes<<<grid_for(ni, BLK), BLK, 0, q>>>(ni, flag, cl, cr, nbox, lbox, b->nodes.as<WideNode>());
+            if (with_top) k_wide_top<<<1, 64, 0, q>>>(b->nodes.as<WideNode>(), dpairs, b->top.as<WideNode>());
             HD_LAUNCH_CHECK();
             Export ex{};
             ex.n = 2;

@@ -78,7 +78,7 @@ struct Ctl {
     alignas(256) unsigned long long stat[ACC_COPIES][ST_STRIDE];
     // blocks of the current query / argmax launch that have finished (the
     // last one does the launch's tail work and resets its counter)
-    alignas(256) unsigned q_done, f_done;
+    alignas(256) unsigned q_done, f_done, c_done;
     // device-planned rounds (written by plan_round, read by the round's kernels)
     alignas(256) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
     unsigned long long nref;                           // referenced vertices of A (round 0's queries)
@@ -119,16 +119,19 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long 
 }
 
 // True in every thread of the one of `nactive` blocks that finishes last,
-// which then sees every write the other blocks made before finishing;
-// *counter (zero at launch) is reset for the next launch. Every thread of each
-// of those blocks must call it, once, at the end of its work; blocks that had
-// no work (a grid sized for a larger count) must not: every call is an atomic
-// on one address, and these serialise.
-__device__ bool last_block(unsigned *counter, unsigned nactive) {
+// which then sees every write the other blocks made before finishing with
+// release set (a device-scope fence, which writes the XCD's L2 back: a block
+// whose plain stores the last block does not read passes false; its returning
+// atomics were performed before its ticket anyway). *counter (zero at launch)
+// is reset for the next launch. Every thread of each of those blocks must call
+// it, once, at the end of its work, with the same release; blocks that had no
+// work (a grid sized for a larger count) must not: every call is an atomic on
+// one address, and these serialise.
+__device__ bool last_block(unsigned *counter, unsigned nactive, bool release = true) {
     __shared__ int last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        if (release) __threadfence();
         const unsigned ticket = atomicAdd(counter, 1u);
         last = ticket == nactive - 1;
         if (last) atomicExch(counter, 0u);
@@ -602,6 +605,7 @@ HD_D void finish_query(const QueryCfg &cfg, const BView<T> &bv, const QueryResul
 // XCD-aware tile order and write the same results (the quad's lane 0 writes).
 struct QueryTally {
     unsigned long long nb = 0, nl = 0, nq = 0;
+    int ovf = 0; // this thread listed an overflowed query
 };
 
 // XCD-aware order: the hardware deals consecutive blocks to the eight XCDs in
@@ -657,6 +661,7 @@ __device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const TileOrder &t
             if (r.overflow) {
                 int k = atomicAdd(&ctl->n_overflow, 1);
                 ovf_list[k] = (int32_t)i;
+                t.ovf = 1;
             } else {
                 finish_query<T>(cfg, bv, r, qp, p, out, pc, &lord, &key);
             }
@@ -694,6 +699,7 @@ __device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const TileOrder &t
                 if (r.overflow) {
                     int slot = atomicAdd(&ctl->n_overflow, 1);
                     ovf_list[slot] = (int32_t)i;
+                    t.ovf = 1;
                 } else {
                     finish_query<T>(cfg, bv, r, qp, p, out, pc, &lord, &key);
                 }
@@ -738,7 +744,8 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
     }
     unsigned long long *st = ctl->stat[acc_copy()];
     block_add<3, QB>({t.nb, t.nl, t.nq}, {st + ST_BOXES, st + ST_QLEAVES, st + ST_QUERIES});
-    if (last_block(&ctl->q_done, to.active_blocks()))
+    // the last block reads only the overflow list (and its atomic count)
+    if (last_block(&ctl->q_done, to.active_blocks(), __syncthreads_or(t.ovf) != 0))
         deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
 }
 
@@ -880,6 +887,7 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
                                                          const int *__restrict__ tri, PairVar *pv, L64Cfg lc, Ctl *ctl) {
     const int64_t n = cnt.get();
     if ((int64_t)blockIdx.x * BLK >= n) return; // the grid is sized for a larger count
+    int wrote = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
         unsigned long long key = keys[o];
@@ -892,10 +900,13 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
             P.argmax_pos[2] = qp.p.z;
             P.argmax_tri = tri[o];
             P.argmax_dirty = 1;
+            wrote = 1;
         }
     }
     const int64_t need = (n + BLK - 1) / BLK;
-    if (last_block(&ctl->f_done, (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x))) {
+    // the last block reads only the argmax records (written by one block)
+    if (last_block(&ctl->f_done, (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x),
+                   __syncthreads_or(wrote) != 0)) {
         __shared__ float4 s_none[1]; // no top-level table here (no reference reaches it)
         const NodeSrc ns{lc.nodes, (LdsFloat *)s_none};
         for (int p = threadIdx.x >> 2; p < lc.npairs; p += blockDim.x >> 2)
@@ -1286,23 +1297,10 @@ __global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg
 // for all (before any block appends); the plan keeps deferred records.
 constexpr int64_t C_FLUSH_MIN = 4096;
 
+// stage C's records [0, n) in a grid-stride loop (every thread of the block)
 template <class T>
-__global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg cc, Dest<T> dst, Ctl *ctl,
-                                                 int defer) {
-    const int64_t n = (int64_t)ctl->c_next;
-    // blocks without records leave at once (the grid is sized for a larger
-    // count; a decision per block is an atomic on one address)
-    if ((int64_t)blockIdx.x * BLK >= n) return;
-    if (defer) {
-        __shared__ int run;
-        if (threadIdx.x == 0) {
-            const int mine = n >= C_FLUSH_MIN || ctl->act_next == 0 ? 1 : 2;
-            const int first = atomicCAS(&ctl->c_decision, 0, mine);
-            run = (first == 0 ? mine : first) == 1;
-        }
-        __syncthreads();
-        if (!run) return;
-    }
+__device__ void stage_c_records(const FrontierView<T> &in, const ClassifyCfg &cc, const Dest<T> &dst, Ctl *ctl,
+                                int64_t n) {
     for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
         const int64_t j = base + threadIdx.x;
         const bool valid = j < n;
@@ -1325,6 +1323,46 @@ __global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg
         int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
         if (valid) write_to(dst, list, slot, cn, round_up_to_float(ub), face, lvl, pair);
         tally(ctl, list, decider, evals, 1, valid, false);
+    }
+}
+
+// With seq != 0 the kernel also ends a device-planned round: once every
+// block with records has decided (and run), the last of them reports the
+// round (report_to) and plans the next (plan_round), the work of
+// k_report_plan without a launch of its own; with no record at all, block 0
+// does it at once.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg cc, Dest<T> dst, Ctl *ctl,
+                                                 int defer, Mailbox *ring, unsigned seq, PlanCaps caps) {
+    const int64_t n = (int64_t)ctl->c_next;
+    const int64_t need = (n + BLK - 1) / BLK;
+    const unsigned nact = (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x);
+    // blocks without records leave at once (the grid is sized for a larger
+    // count; a decision per block is an atomic on one address)
+    if (blockIdx.x >= nact) {
+        if (seq && nact == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+            report_to(ctl, ring, seq);
+            plan_round(ctl, caps);
+        }
+        return;
+    }
+    bool run = true;
+    if (defer) {
+        __shared__ int s_run;
+        if (threadIdx.x == 0) {
+            const int mine = n >= C_FLUSH_MIN || ctl->act_next == 0 ? 1 : 2;
+            const int first = atomicCAS(&ctl->c_decision, 0, mine);
+            s_run = (first == 0 ? mine : first) == 1;
+        }
+        __syncthreads();
+        run = s_run;
+    }
+    if (run) stage_c_records(in, cc, dst, ctl, n);
+    // (the plan resets the decision and the counters for the next round: it
+    // waits until every block with records has read them)
+    if (seq && last_block(&ctl->c_done, nact) && threadIdx.x == 0) {
+        report_to(ctl, ring, seq);
+        plan_round(ctl, caps);
     }
 }
 
@@ -2055,14 +2093,43 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // stages B and C over what one round's stage A produced (at most n records)
     const LearnCfg lc{pc, pv, iv};
     // (defer: device-planned rounds may leave the recheck band to accumulate)
-    auto later_stages = [&](int64_t n, const FrontierView<T> &act_out, int defer) {
+    const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
+    // device-planned rounds: the stage lists follow the active lists (keep_c:
+    // records waiting for stage C, kept when its list grows), and the
+    // capacities each plan works with
+    auto size_round = [&](int64_t keep_c) {
+        const int64_t c = std::min(tw.act.cap, tw.act2.cap);
+        tw.mq.ensure(c);
+        tw.pend_b.ensure(c, 0, s);
+        if (cc.recheck) tw.pend_c.ensure(c, keep_c, s);
+    };
+    auto caps = [&]() {
+        PlanCaps c;
+        c.act = std::min(tw.act.cap, tw.act2.cap);
+        c.park = tw.park.cap;
+        c.pend = tw.pend_b.cap;
+        c.pend_c = cc.recheck ? tw.pend_c.cap : c.pend;
+        c.mq = tw.mq.cap;
+        c.budget = budget - (double)nA;
+        c.grow_act = c.act < cap_limit;
+        c.grow_park = c.park < cap_limit;
+        return c;
+    };
+    // plan_seq != 0: the stages end a device-planned round (report under
+    // that sequence number, plan the next), in stage C's last block when
+    // there is a stage C, else in a kernel of their own
+    auto later_stages = [&](int64_t n, const FrontierView<T> &act_out, int defer, unsigned plan_seq) {
         Dest<T> d{act_out, tw.park.v, tw.pend_b.v, tw.pend_c.v};
-        const unsigned g = std::min<unsigned>(grid_for(n, BLK), GRID_MAX);
+        const unsigned g = std::max(1u, std::min<unsigned>(grid_for(n, BLK), GRID_MAX));
         if (opt.learned == 2)
             k_stage_b_learned<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params);
         else
             k_stage_b<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
-        if (cc.recheck) k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl, defer);
+        if (cc.recheck)
+            k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl, defer, mb_dev, plan_seq,
+                                           plan_seq ? caps() : PlanCaps{});
+        else if (plan_seq)
+            k_report_plan<<<1, 64, 0, s>>>(ctl, mb_dev, plan_seq, caps());
         HD_LAUNCH_CHECK();
     };
 
@@ -2078,39 +2145,24 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const int64_t pend0 = planned ? std::max<int64_t>(nA, std::min(tw.act.cap, tw.act2.cap)) : nA;
     tw.pend_b.ensure(pend0, 0, s);
     if (cc.recheck) tw.pend_c.ensure(pend0, 0, s);
+    // planned rounds: round 0's stages also report it and plan round 1
+    unsigned seq0 = 0;
+    if (planned) {
+        size_round(0); // no resize here (round 0 sized the stage lists): deferred records stay
+        seq0 = ++ws.mb_seq;
+    }
     prof.mark(prof.c);
     k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc,
                                                   Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
     HD_LAUNCH_CHECK();
-    later_stages(nA, tw.act.v, planned ? 1 : 0);
+    later_stages(nA, tw.act.v, planned ? 1 : 0, seq0);
     prof.mark(prof.c);
-    const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
     double processed = (double)nA;
     int64_t subdivided = 0, logged = 0, nAct = 0, nPark = 0;
     int rounds = 0;
     hd_status status = HD_OK;
     Mailbox hm{};
     if (planned) {
-        // (keep_c: records waiting for stage C, kept when its list grows)
-        auto size_round = [&](int64_t keep_c) {
-            const int64_t c = std::min(tw.act.cap, tw.act2.cap);
-            tw.mq.ensure(c);
-            tw.pend_b.ensure(c, 0, s);
-            if (cc.recheck) tw.pend_c.ensure(c, keep_c, s);
-        };
-        size_round(0); // no resize here (round 0 sized the stage lists): deferred records stay
-        auto caps = [&]() {
-            PlanCaps c;
-            c.act = std::min(tw.act.cap, tw.act2.cap);
-            c.park = tw.park.cap;
-            c.pend = tw.pend_b.cap;
-            c.pend_c = cc.recheck ? tw.pend_c.cap : c.pend;
-            c.mq = tw.mq.cap;
-            c.budget = budget - (double)nA;
-            c.grow_act = c.act < cap_limit;
-            c.grow_park = c.park < cap_limit;
-            return c;
-        };
         // report the state after a round and plan the next one
         auto report_plan_async = [&]() -> unsigned {
             const unsigned seq = ++ws.mb_seq;
@@ -2134,19 +2186,20 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
                 Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1);
             HD_LAUNCH_CHECK();
-            later_stages(4 * kmax, tw.act2.v, 1);
+            const unsigned seq = ++ws.mb_seq;
+            later_stages(4 * kmax, tw.act2.v, 1, seq);
             prof.mark(prof.c);
             swap_fb(tw.act, tw.act2);
+            return seq;
         };
-        unsigned seq_prev = report_plan_async(); // state after round 0
+        unsigned seq_prev = seq0; // state after round 0
         int enqueued = 0;
         int64_t peak = 0;
         while (true) {
             const bool more = !(opt.max_rounds > 0 && enqueued >= opt.max_rounds);
             unsigned seq_new = 0;
             if (more) {
-                enqueue_round();
-                seq_new = report_plan_async();
+                seq_new = enqueue_round();
                 ++enqueued;
             }
             hm = wait_report(seq_prev);
@@ -2189,7 +2242,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             tw.park.ensure(hm.park + hm.pend_c, hm.park, s);
             k_set_counts<<<1, 64, 0, s>>>(ctl, (unsigned long long)hm.act, (unsigned long long)hm.park);
             k_stage_c<T><<<std::min<unsigned>(grid_for(hm.pend_c, BLK), GRID_MAX), BLK, 0, s>>>(
-                tw.pend_c.v, cc, Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 0);
+                tw.pend_c.v, cc, Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 0, nullptr, 0u,
+                PlanCaps{});
             HD_LAUNCH_CHECK();
             const Mailbox hf = report();
             hm.act = hf.act;
@@ -2310,7 +2364,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
                                                            ctl, 0);
         HD_LAUNCH_CHECK();
-        later_stages(4 * K, tw.act2.v, 0);
+        later_stages(4 * K, tw.act2.v, 0, 0);
         prof.mark(prof.c);
         hm = report();
         swap_fb(tw.act, tw.act2);
