@@ -144,8 +144,8 @@ void hd_free_bvh(hd_bvh bvh);
 /* Whether hd_build_bvh / hd_build_bvh_batched run the build as a HIP graph
  * (default 1): the build's copies and kernels depend only on the soup sizes
  * and the buffers, so they are captured once per (sizes, buffers) and
- * replayed by later builds, one graph launch instead of about 30 kernel
- * launches (a few graphs are kept per device). 0 launches every kernel
+ * replayed by later builds, one graph launch instead of about 20 kernel
+ * launches and copies (a few graphs are kept per device). 0 launches every kernel
  * directly. The result is the same either way. Returns the previous
  * setting; the setting is process-wide. */
 int32_t hd_build_graphs(int32_t enable);
@@ -153,7 +153,12 @@ int32_t hd_build_graphs(int32_t enable);
 /* Certified [L, U] for h(A, B), B given by its BVH; eps is the paper's
  * relative tolerance (eq. output_bounds), so U - L <= eps * dA on success.
  * opt may be NULL (defaults). LU_out is a HOST array of 2 doubles; stats is a
- * host struct or NULL. The stream is synchronised before return. */
+ * host struct or NULL. The stream is synchronised before return.
+ * HD_E_INVALID for nA <= 0, mA <= 0, eps <= 0, a bad option, or an
+ * out-of-range index or non-finite coordinate in A. The device finds the
+ * latter while ingesting A, so the call returns it at its first report, after
+ * the work already enqueued has drained. That work runs on sanitised copies:
+ * indices are replaced and values zeroed. */
 hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, hd_bvh B,
                    double eps, const hd_options *opt, hd_stream_t stream, double LU_out[2],
                    hd_stats *stats);
