@@ -250,11 +250,16 @@ def test_invalid_inputs(bad):
         VA[2, 0] = np.nan
     say("invalid input", bad)
     bvh = hd.build_bvh(_cu(V, torch), _cu(F, torch))
+    ref = hd.bound(_cu(V, torch), _cu(F, torch), bvh, 1e-3)
     if bad == "emptyA":
         FA = FA[:0]
     with pytest.raises(hd.HDError) as e:
         hd.bound(_cu(VA, torch), _cu(FA, torch), bvh, eps)
     assert e.value.status == 1
+    # an input error found on the device ends the call early: the next call
+    # on the same workspace is unaffected
+    again = hd.bound(_cu(V, torch), _cu(F, torch), bvh, 1e-3)
+    assert again[:2] == ref[:2] and again[2]["subdivided"] == ref[2]["subdivided"]
     FB = F.copy()
     FB[0, 0] = -1
     with pytest.raises(hd.HDError):
