@@ -212,7 +212,9 @@ __device__ void report_to(const Ctl *ctl, Mailbox *ring, unsigned seq) {
     mb->bad_input = ctl->bad_input;
     mb->rounds = (long long)ctl->rounds;
     mb->subdivided = (long long)ctl->subdivided;
-    mb->pend_c = (long long)ctl->c_next;
+    // records still waiting for stage C: none once stage C ran this round
+    // (its count is cleared only by the next plan)
+    mb->pend_c = ctl->c_decision == 1 ? 0 : (long long)ctl->c_next;
     mb->bad = ctl->bad;
     mb->stall = ctl->stall;
     mb->over_budget = ctl->over_budget;
@@ -1297,6 +1299,10 @@ __global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg
 // for all (before any block appends); the plan keeps deferred records.
 constexpr int64_t C_FLUSH_MIN = 4096;
 
+// device-planned rounds: a pending round that splits at most this many
+// triangles is not followed by one enqueued ahead of its report
+constexpr int64_t LOOKAHEAD_MIN = 64;
+
 // stage C's records [0, n) in a grid-stride loop (every thread of the block)
 template <class T>
 __device__ void stage_c_records(const FrontierView<T> &in, const ClassifyCfg &cc, const Dest<T> &dst, Ctl *ctl,
@@ -2192,25 +2198,37 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             swap_fb(tw.act, tw.act2);
             return seq;
         };
-        unsigned seq_prev = seq0; // state after round 0
+        unsigned seq_prev = seq0; // state after round 0 (the latest report not yet read)
         int enqueued = 0;
         int64_t peak = 0;
+        int64_t last_act = -1; // active count of the last report read (-1: none yet)
         while (true) {
             const bool more = !(opt.max_rounds > 0 && enqueued >= opt.max_rounds);
+            // The next round goes in ahead of the pending report, unless the
+            // last report read left so few active triangles that the pending
+            // round is likely the last: an empty round costs its five
+            // launches, a missed look-ahead one host reaction.
+            const bool ahead = more && !(last_act >= 0 && last_act <= LOOKAHEAD_MIN);
             unsigned seq_new = 0;
-            if (more) {
+            if (ahead) {
                 seq_new = enqueue_round();
                 ++enqueued;
             }
             hm = wait_report(seq_prev);
             peak = std::max<int64_t>(peak, hm.act + hm.park);
-            if (more) {
-                const bool done = hm.act == 0 || hm.bad || hm.over_budget || hm.stall;
+            last_act = hm.act;
+            const bool done = hm.act == 0 || hm.bad || hm.over_budget || hm.stall;
+            if (ahead) {
                 seq_prev = seq_new;
                 if (!done) continue;
                 // the round enqueued ahead found nothing to do (or stopped too)
                 hm = wait_report(seq_new);
                 peak = std::max<int64_t>(peak, hm.act + hm.park);
+                last_act = hm.act;
+            } else if (more && !done) {
+                seq_prev = enqueue_round();
+                ++enqueued;
+                continue;
             }
             if (!(hm.stall && !hm.bad && !hm.over_budget && hm.act > 0)) break;
             // out of list capacity: grow (the stalled rounds left the lists in

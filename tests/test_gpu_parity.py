@@ -707,6 +707,26 @@ def test_deferred_recheck_band(k, scale):
     assert L0 <= U1 and L1 <= U0
 
 
+@pytest.mark.parametrize("k,scale,prec,subbatch", [(1, 1.0, "fp64", 0), (2, 0.1, "fp32+recheck", 0),
+                                                   (2, 0.1, "fp32+recheck", 1 << 30), (3, 0.02, "fp32", 0),
+                                                   (5, 0.02, "fp32+recheck", 0)])
+def test_every_bounded_triangle_is_decided_once(k, scale, prec, subbatch):
+    """Conservation over a converged run: every bounded triangle ends either
+    discarded (by exactly one deciding bound), parked at the end, or split, so
+    nodes_bounded = sum(discards) + parked_final + subdivided. A recheck
+    record decided twice, or lost, breaks it."""
+    hd, torch = _hd()
+    W = wl.config(k, scale=scale)
+    say("conservation, config", k, "scale", scale, prec, "subbatch", subbatch)
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, precision=PRECS[prec],
+                        subbatch=subbatch)
+    assert st["status"] == 0 and U - L <= st["eps_abs"] * (1 + 1e-12)
+    decided = sum(st["discards"]) + st["parked_final"] + st["subdivided"]
+    print("bounded", st["nodes_bounded"], "decided", decided, "rechecked", st["rechecked64"])
+    assert st["nodes_bounded"] == decided
+
+
 def test_round_limit_decides_the_waiting_band():
     """Rounds stopped by a round limit with recheck records still waiting:
     those are decided before the final U, which stays a valid upper bound."""
