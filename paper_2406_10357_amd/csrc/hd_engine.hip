@@ -1591,10 +1591,18 @@ __global__ void k_sel_keys(FrontierView<T> fr, int64_t n, unsigned long long *__
 // ---------------------------------------------------------------------------
 // final FP64 step
 // ---------------------------------------------------------------------------
+// whether the rounds left the run converged: nothing active or planned, no
+// recheck record waiting, no error
+__device__ bool run_converged(const Ctl *c) {
+    return c->plan_K == 0 && c->act_next == 0 && c->c_next == 0 && c->bad == 0 && c->bad_input == 0 &&
+           c->over_budget == 0;
+}
+
+// the records of k_final_U (every thread of the block; i >= n: no record)
 template <class T>
-__global__ __launch_bounds__(BLK) void k_final_U(FrontierView<T> fr, int64_t n, AView a, BView<double> bv64, IdView iv, CascadeCtx c,
-                          const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void final_U_records(const FrontierView<T> &fr, int64_t i, int64_t n, const AView &a,
+                                const BView<double> &bv64, const IdView &iv, const CascadeCtx &c,
+                                const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
     const bool valid = i < n;
     unsigned long long ev = 0;
     int pair = 0;
@@ -1613,6 +1621,18 @@ __global__ __launch_bounds__(BLK) void k_final_U(FrontierView<T> fr, int64_t n, 
     }
     block_pair_minmax<2, 3u, BLK>(pair, valid, u, [&](int p, int k) { return k == 0 ? &pv[p].Uord : &pv[p].Urounds; });
     block_add<1, BLK>({ev}, {&ctl->stat[acc_copy()][ST_EVALS]});
+}
+
+// U over the live records of a list (count from cnt). With gated set the
+// launch was enqueued ahead of the report of a round that is probably the
+// last, and does nothing unless the run has converged.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_final_U(FrontierView<T> fr, DevCount cnt, int gated, AView a,
+                                                 BView<double> bv64, IdView iv, CascadeCtx c,
+                                                 const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl) {
+    const int64_t n = gated && !run_converged(ctl) ? 0 : cnt.get();
+    for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK)
+        final_U_records(fr, base + threadIdx.x, n, a, bv64, iv, c, pc, pv, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -2144,6 +2164,28 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // one round ahead of the report it waits for: the GPU never idles between
     // rounds. The host-driven loop below handles the other modes.
     const bool planned = opt.subbatch <= 0 && !opt.log_frontier;
+    // the results (control block, pair tables) to pinned host memory; returns
+    // the sequence number the host waits for
+    auto enqueue_export = [&]() -> unsigned {
+        Export ex{};
+        ex.n = 3;
+        ex.src[0] = ctl;
+        ex.dst[0] = ws.host.dev_as<char>(o_res + o_rctl);
+        ex.bytes[0] = sizeof(Ctl);
+        ex.src[1] = pv;
+        ex.dst[1] = ws.host.dev_as<char>(o_res + o_rpv);
+        ex.bytes[1] = np * sizeof(PairVar);
+        ex.src[2] = pc;
+        ex.dst[2] = ws.host.dev_as<char>(o_res + o_rpc);
+        ex.bytes[2] = np * sizeof(PairConst);
+        const unsigned seq = ++ws.mb_seq;
+        export_to_host(ex, ws.host.dev_as<unsigned>(256), seq, s);
+        return seq;
+    };
+    // a final step and export enqueued ahead of the last round's report
+    // (used when that report shows the run converged)
+    bool spec = false;
+    unsigned spec_seq = 0;
 
     // ---- round 0: bound every face ------------------------------------------
     // (planned rounds: the stage lists get the active lists' size now, so that
@@ -2213,6 +2255,17 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             if (ahead) {
                 seq_new = enqueue_round();
                 ++enqueued;
+            } else if (more) {
+                // the pending round is probably the last: its final step and
+                // export go in ahead of its report, and do nothing on the
+                // device unless the run has converged
+                prof.mark(prof.c);
+                k_final_U<T><<<std::min<unsigned>(grid_for(tw.park.cap, BLK), GRID_MAX), BLK, 0, s>>>(
+                    tw.park.v, DevCount{&ctl->park_next, 1, 0}, 1, av, bv64, iv, cctx, pc, pv, ctl);
+                HD_LAUNCH_CHECK();
+                prof.mark(prof.c);
+                spec_seq = enqueue_export();
+                spec = true;
             }
             hm = wait_report(seq_prev);
             peak = std::max<int64_t>(peak, hm.act + hm.park);
@@ -2226,6 +2279,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 peak = std::max<int64_t>(peak, hm.act + hm.park);
                 last_act = hm.act;
             } else if (more && !done) {
+                spec = false;
                 seq_prev = enqueue_round();
                 ++enqueued;
                 continue;
@@ -2248,6 +2302,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 cap_limit = std::min(std::min(tw.act.cap, tw.act2.cap), tw.park.cap);
                 size_round(hm.pend_c);
             }
+            spec = false;
             k_clear_stall<<<1, 64, 0, s>>>(ctl);
             seq_prev = report_plan_async();
             enqueued = (int)hm.rounds; // stalled rounds split nothing and do not count
@@ -2263,6 +2318,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 tw.pend_c.v, cc, Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 0, nullptr, 0u,
                 PlanCaps{});
             HD_LAUNCH_CHECK();
+            spec = false;
             const Mailbox hf = report();
             hm.act = hf.act;
             hm.park = hf.park;
@@ -2399,29 +2455,22 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
 
     // ---- final FP64 step: U over every live triangle --------------------------
 
-    if (status == HD_OK) {
+    // the final step enqueued ahead stands when the rounds converged (its
+    // launch then did the work below)
+    const bool use_spec = spec && status == HD_OK && nAct == 0 && hm.pend_c == 0;
+    if (status == HD_OK && !use_spec) {
         prof.mark(prof.c);
         if (nPark > 0)
-            k_final_U<T><<<grid_for(nPark, BLK), BLK, 0, s>>>(tw.park.v, nPark, av, bv64, iv, cctx, pc, pv, ctl);
+            k_final_U<T><<<std::min<unsigned>(grid_for(nPark, BLK), GRID_MAX), BLK, 0, s>>>(
+                tw.park.v, host_count(nPark), 0, av, bv64, iv, cctx, pc, pv, ctl);
         if (nAct > 0)
-            k_final_U<T><<<grid_for(nAct, BLK), BLK, 0, s>>>(tw.act.v, nAct, av, bv64, iv, cctx, pc, pv, ctl);
+            k_final_U<T><<<std::min<unsigned>(grid_for(nAct, BLK), GRID_MAX), BLK, 0, s>>>(
+                tw.act.v, host_count(nAct), 0, av, bv64, iv, cctx, pc, pv, ctl);
         HD_LAUNCH_CHECK();
         prof.mark(prof.c);
     }
     {
-        Export ex{};
-        ex.n = 3;
-        ex.src[0] = ctl;
-        ex.dst[0] = ws.host.dev_as<char>(o_res + o_rctl);
-        ex.bytes[0] = sizeof(Ctl);
-        ex.src[1] = pv;
-        ex.dst[1] = ws.host.dev_as<char>(o_res + o_rpv);
-        ex.bytes[1] = np * sizeof(PairVar);
-        ex.src[2] = pc;
-        ex.dst[2] = ws.host.dev_as<char>(o_res + o_rpc);
-        ex.bytes[2] = np * sizeof(PairConst);
-        const unsigned seq = ++ws.mb_seq;
-        export_to_host(ex, ws.host.dev_as<unsigned>(256), seq, s);
+        const unsigned seq = use_spec ? spec_seq : enqueue_export();
         wait_host_seq(ws.host.as<unsigned>(256), seq, s);
     }
     const Ctl &hc = *ws.host.as<Ctl>(o_res + o_rctl);
