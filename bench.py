@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--precision", default="fp32+recheck", choices=["fp64", "fp32", "fp32+recheck"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="1: the first warm-up call picks the query kernel's launch shape; 0: the "
+                         "default shape (profiling runs use it, so every counter run times the same shape)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain comparison on the large torus")
     ap.add_argument("--learned-subbatch", type=int, default=8192)
@@ -240,7 +243,7 @@ def main():
     # the first warm-up call also picks the query kernel's launch shape
     tuned = None
     for i in range(a.warmup):
-        r = step(autotune=1 if i == 0 else 0)
+        r = step(autotune=1 if i == 0 and a.autotune else 0)
         tuned = tuned or {k: r[2][k] for k in ("query_block", "query_stack", "query_quad_max")}
         print(f"warmup {i + 1}/{a.warmup} done", file=sys.stderr, flush=True)
 
