@@ -81,7 +81,7 @@ typedef struct {
                                   this call's vertex queries and keep the fastest for later
                                   calls; 2: retune on this call; 0: use the kept choice */
     int32_t query_lanes;       /* lanes per point query: 0 automatic (a quad of four lanes per
-                                  query in query launches of at most 16384 queries, where one
+                                  query in query launches of at most 32768 queries, where one
                                   lane per query leaves the GPU latency-bound; one lane above);
                                   1 always one lane; 4 always a quad */
 } hd_options;

@@ -797,7 +797,7 @@ constexpr int NQVAR = sizeof(QVARIANTS) / sizeof(QVARIANTS[0]);
 // thousand queries or fewer, even around 25k, and up to 2.5x slower for
 // launches of 10^5 queries and more (there every lane's redundant share of
 // the sort and stack work costs issue slots).
-constexpr int64_t QUAD_MAX_DEFAULT = 16384;
+constexpr int64_t QUAD_MAX_DEFAULT = 32768;
 
 // grid of a query launch of block size qb for up to n queries: a multiple of
 // XCDS, capped at a persistent size; launches that may take the quad path
