@@ -184,6 +184,24 @@ def features(v, d, q, nS, distinct, shared_edge, L, dA):
     return F
 
 
+def closest_pattern(I, FB):
+    """Columns 9 and 10 of the features, from the closest B triangles I [n,3]
+    of a triangle's vertices and B's face array: the number of distinct
+    closest triangles, and 1 when exactly two distinct ones share an edge
+    (two common vertex indices: the reading of "share an edge" for soups;
+    triangles that only repeat coordinates under other indices do not)."""
+    I = np.asarray(I)
+    FB = np.asarray(FB)
+    distinct = np.zeros(I.shape[0])
+    shared = np.zeros(I.shape[0])
+    for i, r in enumerate(I):
+        u = sorted(set(int(x) for x in r))
+        distinct[i] = len(u)
+        if len(u) == 2:
+            shared[i] = 1.0 if len(set(FB[u[0]].tolist()) & set(FB[u[1]].tolist())) >= 2 else 0.0
+    return distinct, shared
+
+
 def label(hhat, d, v):
     """Training target: (sampled maximum distance - largest vertex distance)
     divided by the longest edge."""

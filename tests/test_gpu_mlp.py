@@ -158,12 +158,8 @@ def _oracle_feature_inputs(VB, FB, tris):
     nB = np.cross(e1, e2)
     nB /= np.linalg.norm(nB, axis=1)[:, None]
     nS = nB[I]
-    distinct = np.array([len(set(r)) for r in I])
-    shared = np.zeros(n)
-    for i, r in enumerate(I):
-        u = sorted(set(r))
-        if len(u) == 2:
-            shared[i] = 1.0 if len(set(FB[u[0]]) & set(FB[u[1]])) >= 2 else 0.0
+    from oracle import mlp
+    distinct, shared = mlp.closest_pattern(I, FB)
     return d, I, q, nS, distinct, shared
 
 

@@ -125,3 +125,70 @@ def test_lattice_points_and_label():
     assert got == want
     d = np.array([[0.1, 0.2, 0.3]])
     assert mlp.label(np.array([0.5]), d, v) == pytest.approx((0.5 - 0.3) / math.sqrt(32))
+
+
+# ---------------------------------------------------------------------------
+# hand-derived values of the remaining feature columns: the gaps above L of
+# the largest vertex distance and of the two cheap bounds (6-8), the closest
+# triangle pattern (9-10), the spread of the closest points (14) and the
+# level (15)
+# ---------------------------------------------------------------------------
+
+def _one(v, d, q, L, dA, distinct=1, shared=0):
+    nS = np.repeat(np.array([[[0.0, 0.0, 1.0]]]), 3, 1)
+    return mlp.features(np.array([v], float), np.array([d], float), np.array([q], float), nS,
+                        np.array([distinct]), np.array([shared]), L, dA)[0]
+
+
+def test_feature_gaps_of_a_3_4_5_triangle():
+    # right triangle: edges e12 = 3, e23 = 5, e31 = 4, longest edge l = 5
+    v = [[0, 0, 0], [3, 0, 0], [0, 4, 0]]
+    d = [0.1, 0.2, 0.3]
+    q = [[0, 0, 0], [0, 0, 0], [0, 0.6, 0.8]]
+    F = _one(v, d, q, L=0.05, dA=40.0)
+    # max d - L = 0.25
+    assert F[6] == pytest.approx(math.asinh(0.25 / 5), abs=1e-15)
+    # u1 = min(max(3,4) + 0.1, max(3,5) + 0.2, max(5,4) + 0.3) = 4.1
+    assert F[7] == pytest.approx(math.asinh((4.1 - 0.05) / 5), abs=1e-15)
+    # not acute (25 = 9 + 16): g = l / 2 = 2.5, u2 = 2.5 + 0.3
+    assert F[8] == pytest.approx(math.asinh((2.8 - 0.05) / 5), abs=1e-15)
+    # closest points: largest pairwise distance |q3 - q1| = 1
+    assert F[14] == pytest.approx(math.asinh(1.0 / 5), abs=1e-15)
+    # log2(5 / 40) / 30 = -3 / 30
+    assert F[15] == pytest.approx(-0.1, abs=1e-15)
+    # one closest triangle: no pattern
+    assert F[9] == 0 and F[10] == 0
+    # L above every vertex distance gives a negative gap
+    F = _one(v, d, q, L=0.5, dA=40.0)
+    assert F[6] == pytest.approx(math.asinh(-0.2 / 5), abs=1e-15)
+
+
+def test_feature_u2_gap_uses_the_circumradius_of_an_acute_triangle():
+    # isosceles 6-5-5 (acute: 36 < 50), area 12: R = 6*5*5 / (4*12) = 3.125,
+    # larger than l / 2 = 3 (circumcentre (0, 7/8): 4 - 7/8 = 3.125)
+    v = [[-3, 0, 0], [3, 0, 0], [0, 4, 0]]
+    d = [0.0, 0.5, 0.25]
+    F = _one(v, d, v, L=0.125, dA=6.0)
+    assert F[8] == pytest.approx(math.asinh((3.125 + 0.5 - 0.125) / 6), abs=1e-15)
+    # u1 = min(max(6,5) + 0, max(6,5) + 0.5, max(5,5) + 0.25) = 5.25
+    assert F[7] == pytest.approx(math.asinh((5.25 - 0.125) / 6), abs=1e-15)
+    # closest points are the vertices: spread = l
+    assert F[14] == pytest.approx(math.asinh(1.0), abs=1e-15)
+    assert F[15] == pytest.approx(0.0, abs=1e-15)
+
+
+def test_closest_triangle_pattern():
+    FB = np.array([[0, 1, 2], [1, 2, 3], [2, 4, 5], [6, 7, 8], [9, 10, 11]])
+    I = np.array([[4, 4, 4],   # one triangle
+                  [0, 1, 1],   # two, sharing edge (1, 2)
+                  [0, 2, 2],   # two, sharing vertex 2 only
+                  [0, 1, 2],   # three (adjacent or not: no flag)
+                  [3, 0, 3],   # two with no common index (a duplicate by coordinates would still not count)
+                  [1, 0, 0]])  # order does not matter
+    distinct, shared = mlp.closest_pattern(I, FB)
+    assert distinct.tolist() == [1, 2, 2, 3, 2, 2]
+    assert shared.tolist() == [0, 1, 0, 0, 0, 1]
+    F = mlp.features(np.zeros((6, 3, 3)) + np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]]), np.full((6, 3), 0.1),
+                     np.zeros((6, 3, 3)), np.zeros((6, 3, 3)), distinct, shared, 0.0, 1.0)
+    assert F[:, 9].tolist() == [0.0, 0.5, 0.5, 1.0, 0.5, 0.5]
+    assert F[:, 10].tolist() == [0, 1, 0, 0, 0, 1]
