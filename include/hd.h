@@ -3,9 +3,10 @@
  * on AMD Instinct MI355X (gfx950).
  *
  * The library computes an interval [L, U] with L <= h(A,B) <= U and
- * U - L <= eps * dA, where h(A,B) = max over p in A of the distance from p to
- * B, and dA is the length of the diagonal of the bounding box of A's
- * (referenced) vertices. This is the problem statement and output contract
+ * U - L <= eps, where h(A,B) = max over p in A of the distance from p to B.
+ * The paper states the tolerance relative to dA, the length of the diagonal
+ * of the bounding box of A's (referenced) vertices: eps = epsilon * dA. This
+ * is the problem statement and output contract
  * of Sacht & Jacobson, "Cascading upper bounds for triangle soup
  * Pompeiu-Hausdorff distance" (Method section: eq. hausdorff_distance and
  * eq. output_bounds). The method is that paper's branch and bound with its
@@ -84,7 +85,37 @@ typedef struct {
                                   query in query launches of at most 32768 queries, where one
                                   lane per query leaves the GPU latency-bound; one lane above);
                                   1 always one lane; 4 always a quad */
+    int32_t eps_relative;      /* 0 (default): eps is the absolute tolerance, U - L <= eps;
+                                  1: eps is the paper's relative tolerance (eq. output_bounds),
+                                  U - L <= eps * dA, dA computed on the device from A */
+    int32_t pad0;
+    const char *tuner_cache;   /* autotune != 0: path of a JSON file that keeps the autotuner's
+                                  choice per (device, arithmetic, kernel-source hash) across
+                                  processes: a kept choice is used without tuning, a new one is
+                                  added to the file; NULL: the choice lives in process memory */
+    struct hd_round_record *round_log; /* HOST array of round_log_cap records, one per round
+                                  (round 0 = the vertex round), or NULL. Logging runs the rounds
+                                  host-driven (one report and one extra reduction per round). */
+    int64_t round_log_cap;
+    double test_bound_shift;   /* test hook, 0 normally: subtracted from every upper bound of the
+                                  FP32/FP64 cascade stages. A shift that makes a bound smaller than
+                                  the largest vertex distance of its triangle (no valid bound is)
+                                  must end the call with HD_E_INTERNAL. */
 } hd_options;
+
+/* One record of hd_options.round_log: the state after a round. */
+typedef struct hd_round_record {
+    int32_t round;             /* 0: the vertex round */
+    int32_t pad;
+    int64_t split;             /* triangles split 1 -> 4 in this round */
+    int64_t active, parked;    /* list sizes after the round */
+    int64_t bounded;           /* triangles bounded so far */
+    int64_t discards[5];       /* triangles discarded so far by uexact, u1, u2, u3, u4 */
+    double L;                  /* pair 0: lower bound after the round */
+    double U;                  /* pair 0: largest upper bound (margin included) of a live
+                                  triangle after the round, or L if none is left */
+    double ms;                 /* host time from the start of the call to the round's report */
+} hd_round_record;
 
 typedef struct {
     int32_t rounds;            /* rounds after round 0 */
@@ -116,6 +147,10 @@ typedef struct {
     int32_t query_lanes;       /* the call's query_lanes option */
     int32_t query_quad_max;    /* launches of at most this many queries ran a quad per query
                                   (0: none did; -1: all did) */
+    int64_t round_records;     /* records written to hd_options.round_log */
+    int32_t tuned;             /* where the query launch shape came from: 0 kept in memory or the
+                                  default, 1 tuned by this call, 2 read from tuner_cache */
+    int32_t pad1;
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle
@@ -150,15 +185,22 @@ void hd_free_bvh(hd_bvh bvh);
  * setting; the setting is process-wide. */
 int32_t hd_build_graphs(int32_t enable);
 
-/* Certified [L, U] for h(A, B), B given by its BVH; eps is the paper's
- * relative tolerance (eq. output_bounds), so U - L <= eps * dA on success.
+/* Certified [L, U] for h(A, B), B given by its BVH: on success
+ * L <= h(A,B) <= U and U - L <= eps, eps the absolute tolerance (the paper's
+ * relative tolerance times dA, eq. output_bounds; hd_options.eps_relative = 1
+ * takes the relative form and computes dA on the device).
  * opt may be NULL (defaults). LU_out is a HOST array of 2 doubles; stats is a
  * host struct or NULL. The stream is synchronised before return.
  * HD_E_INVALID for nA <= 0, mA <= 0, eps <= 0, a bad option, or an
  * out-of-range index or non-finite coordinate in A. The device finds the
  * latter while ingesting A, so the call returns it at its first report, after
  * the work already enqueued has drained. That work runs on sanitised copies:
- * indices are replaced and values zeroed. */
+ * indices are replaced and values zeroed.
+ * With HD_PREC_FP32 (no FP64 recheck) the tolerance must exceed the FP32
+ * margin at the lower bound (mu_coef_d * L + mu_coef_0 in hd_stats): no FP32
+ * bound can then park the triangle that holds the maximum, so the call
+ * returns HD_E_INVALID after the vertex round instead of subdividing to the
+ * depth limit (use HD_PREC_FP32_RECHECK or HD_PREC_FP64 there). */
 hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, hd_bvh B,
                    double eps, const hd_options *opt, hd_stream_t stream, double LU_out[2],
                    hd_stats *stats);
@@ -168,7 +210,8 @@ hd_status hd_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, 
  * pair id; L, U, eps and the margins are per pair). A_p is given as host
  * arrays of device pointers and sizes; B is a handle from
  * hd_build_bvh_batched over the B_p in the same order. eps is a host array
- * of npairs relative tolerances when eps_per_pair != 0, else one value.
+ * of npairs tolerances when eps_per_pair != 0, else one value (absolute, or
+ * relative to each pair's dA with hd_options.eps_relative = 1).
  * LU_out is a host array of 2 * npairs doubles (L_0, U_0, L_1, U_1, ...);
  * stats (host, nullable) sums the counters over pairs and reports pair 0's
  * dA and eps_abs. A pair whose vertices are all referenced by no face is

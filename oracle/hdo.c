@@ -15,6 +15,7 @@
 
 #include <math.h>
 #include <stdlib.h>
+#include <pthread.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------------ */
@@ -690,6 +691,60 @@ static double query_point(qctx *c, const double p[3], int32_t *I, double q[3]) {
     return hdo_point_soup(p, c->VB, c->FB, c->nB, I, q);
 }
 
+/* Threads of the vertex-query phase (1 = the plain single-threaded oracle).
+ * The phase computes D_A, I_A and C_A for every referenced vertex: each
+ * query is independent, so threads take contiguous vertex ranges with their
+ * own counters; the lower bound and its argmax are then taken in vertex
+ * order, as in the single-threaded run. Results are identical. */
+static int g_threads = 1;
+void hdo_set_threads(int32_t n) { g_threads = n < 1 ? 1 : (n > 256 ? 256 : n); }
+
+typedef struct {
+    const qctx *c;
+    const double *VA;
+    const unsigned char *ref;
+    int64_t lo, hi;
+    double *DA, *CA;
+    int32_t *IA;
+    hdo_result counters;
+} vq_job;
+
+static void *vq_run(void *arg) {
+    vq_job *j = (vq_job *)arg;
+    qctx c = *j->c;
+    c.res = &j->counters;
+    for (int64_t i = j->lo; i < j->hi; ++i)
+        if (j->ref[i]) j->DA[i] = query_point(&c, j->VA + 3 * i, &j->IA[i], j->CA + 3 * i);
+    return NULL;
+}
+
+static void query_vertices(qctx *c, const double *VA, int64_t mA, const unsigned char *ref, double *DA,
+                           int32_t *IA, double *CA) {
+    int nt = g_threads;
+    if (nt > mA) nt = (int)mA;
+    vq_job jobs[256];
+    pthread_t th[256];
+    int started[256];
+    for (int t = 0; t < nt; ++t) {
+        memset(&jobs[t], 0, sizeof(jobs[t]));
+        jobs[t].c = c;
+        jobs[t].VA = VA;
+        jobs[t].ref = ref;
+        jobs[t].lo = mA * t / nt;
+        jobs[t].hi = mA * (t + 1) / nt;
+        jobs[t].DA = DA;
+        jobs[t].IA = IA;
+        jobs[t].CA = CA;
+        started[t] = nt > 1 && pthread_create(&th[t], NULL, vq_run, &jobs[t]) == 0;
+        if (!started[t]) vq_run(&jobs[t]);
+    }
+    for (int t = 0; t < nt; ++t) {
+        if (started[t]) pthread_join(th[t], NULL);
+        c->res->queries += jobs[t].counters.queries;
+        c->res->evals += jobs[t].counters.evals;
+    }
+}
+
 static int all_finite(const double *x, int64_t n) {
     for (int64_t i = 0; i < n; ++i)
         if (!isfinite(x[i])) return 0;
@@ -753,9 +808,9 @@ int32_t hdo_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA,
     double *CA = (double *)malloc((size_t)mA * 3 * sizeof(double));
     double l = 0.0;
     int have_l = 0;
+    query_vertices(&qc, VA, mA, ref, DA, IA, CA);
     for (int64_t i = 0; i < mA; ++i) {
         if (!ref[i]) continue;
-        DA[i] = query_point(&qc, VA + 3 * i, &IA[i], CA + 3 * i);
         if (!have_l || DA[i] > l) {
             l = DA[i];
             copy3(VA + 3 * i, res->argmax);

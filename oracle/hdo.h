@@ -77,6 +77,10 @@ int32_t hdo_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA,
                   double eps_rel, double budget_m, const int32_t *order, int32_t norder,
                   int32_t backend, hdo_result *res);
 
+/* Threads for the vertex-query phase of hdo_bound (default 1, the plain
+ * single-threaded oracle). Only that phase is split; results are identical. */
+void hdo_set_threads(int32_t n);
+
 #ifdef __cplusplus
 }
 #endif

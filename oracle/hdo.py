@@ -20,9 +20,9 @@ _lib = None
 def build(force: bool = True, sanitize: bool = False, out: str | None = None) -> str:
     """Compile hdo.c with gcc into a shared library and return its path."""
     out = out or _LIB
-    flags = ["-O2", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra"]
+    flags = ["-O2", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
     if sanitize:
-        flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-std=c11", "-fPIC", "-shared",
+        flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-std=c11", "-fPIC", "-shared", "-pthread",
                  "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
     if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
         tmp = out + ".tmp"
@@ -64,6 +64,8 @@ def _load():
             lib.hdo_tree_free.argtypes = [C.c_void_p]
             lib.hdo_bounds.restype = None
             lib.hdo_bounds.argtypes = [dp, dp, ip, dp, dp, ip, C.c_int64, dp, ip]
+            lib.hdo_set_threads.restype = None
+            lib.hdo_set_threads.argtypes = [C.c_int32]
             lib.hdo_bound.restype = C.c_int32
             lib.hdo_bound.argtypes = [dp, C.c_int64, ip, C.c_int64, dp, C.c_int64, ip,
                                       C.c_int64, C.c_double, C.c_double, ip, C.c_int32,
@@ -153,9 +155,12 @@ def bounds(v, d, I, q, VB, FB):
     return out, case.value
 
 
-def bound(VA, FA, VB, FB, eps_rel, m=1e7, order=(1, 2, 3, 4), backend="brute"):
-    """The branch and bound. Returns a dict with L, U, status and counters."""
+def bound(VA, FA, VB, FB, eps_rel, m=1e7, order=(1, 2, 3, 4), backend="brute", threads=1):
+    """The branch and bound. Returns a dict with L, U, status and counters.
+    threads > 1 splits only the vertex-query phase over that many threads
+    (same results)."""
     lib = _load()
+    lib.hdo_set_threads(int(threads))
     VA_, VAp = _d(VA)
     FA_, FAp = _i(FA)
     VB_, VBp = _d(VB)

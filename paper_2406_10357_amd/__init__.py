@@ -36,7 +36,21 @@ class Options(C.Structure):
                 ("capacity", C.c_int64), ("max_rounds", C.c_int32), ("stack_depth", C.c_int32),
                 ("subbatch", C.c_int32), ("profile", C.c_int32), ("learned", C.c_int32),
                 ("log_frontier", C.c_int32), ("mlp_params", C.c_void_p), ("log_out", C.c_void_p),
-                ("log_cap", C.c_int64), ("autotune", C.c_int32), ("query_lanes", C.c_int32)]
+                ("log_cap", C.c_int64), ("autotune", C.c_int32), ("query_lanes", C.c_int32),
+                ("eps_relative", C.c_int32), ("pad0", C.c_int32), ("tuner_cache", C.c_char_p),
+                ("round_log", C.c_void_p), ("round_log_cap", C.c_int64), ("test_bound_shift", C.c_double)]
+
+
+class RoundRecord(C.Structure):
+    """One record of the per-round log (hd_round_record)."""
+    _fields_ = [("round", C.c_int32), ("pad", C.c_int32), ("split", C.c_int64), ("active", C.c_int64),
+                ("parked", C.c_int64), ("bounded", C.c_int64), ("discards", C.c_int64 * 5), ("L", C.c_double),
+                ("U", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d["discards"] = list(self.discards)
+        return d
 
 
 class Stats(C.Structure):
@@ -51,10 +65,11 @@ class Stats(C.Structure):
                 ("query_launches", C.c_int64), ("cascade_launches", C.c_int64),
                 ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64),
                 ("logged", C.c_int64), ("learned_skips", C.c_int64), ("query_block", C.c_int32),
-                ("query_stack", C.c_int32), ("query_lanes", C.c_int32), ("query_quad_max", C.c_int32)]
+                ("query_stack", C.c_int32), ("query_lanes", C.c_int32), ("query_quad_max", C.c_int32),
+                ("round_records", C.c_int64), ("tuned", C.c_int32), ("pad1", C.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad1"}
         d["discards"] = list(self.discards)
         return d
 
@@ -166,9 +181,13 @@ def build_bvh(VB, FB) -> Bvh:
 
 def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
                  stack_depth=0, subbatch=0, profile=0, learned=0, mlp_params=None, log_out=None,
-                 autotune=0, query_lanes=0) -> Options:
+                 autotune=0, query_lanes=0, relative=False, tuner_cache=None, round_log=None,
+                 test_bound_shift=0.0) -> Options:
     """mlp_params: device FP32 tensor of mlp_nparams() values (learned > 0);
-    log_out: device FP32 tensor (rows, 17) that receives the frontier log."""
+    log_out: device FP32 tensor (rows, 17) that receives the frontier log;
+    relative: eps is the paper's relative tolerance (times dA) instead of an
+    absolute one; tuner_cache: path of the autotuner's JSON cache file;
+    round_log: a ctypes array of RoundRecord that receives one record per round."""
     o = Options()
     load_library().hd_default_options(C.byref(o))
     o.precision, o.order, o.budget_m = precision, order, budget_m
@@ -177,6 +196,15 @@ def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity
     o.learned = learned
     o.autotune = autotune
     o.query_lanes = query_lanes
+    o.eps_relative = 1 if relative else 0
+    o.test_bound_shift = float(test_bound_shift)
+    if tuner_cache is not None:
+        o._tuner_cache = os.fsencode(tuner_cache)  # kept alive with the options
+        o.tuner_cache = o._tuner_cache
+    if round_log is not None:
+        o._round_log = round_log
+        o.round_log = C.cast(round_log, C.c_void_p)
+        o.round_log_cap = len(round_log)
     if mlp_params is not None:
         o.mlp_params = mlp_params.data_ptr()
     if log_out is not None:
@@ -187,19 +215,32 @@ def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity
     return o
 
 
-def bound(VA, FA, bvh: Bvh, eps: float, **opts):
-    """Certified (L, U, stats) with L <= h(A,B) <= U and U - L <= eps * dA."""
+def _round_log(n):
+    return (RoundRecord * n)() if n else None
+
+
+def _with_log(d, log):
+    if log is not None:
+        d["round_log"] = [log[i].as_dict() for i in range(d["round_records"])]
+    return d
+
+
+def bound(VA, FA, bvh: Bvh, eps: float, round_log: int = 0, **opts):
+    """Certified (L, U, stats) with L <= h(A,B) <= U and U - L <= eps (eps
+    times dA with relative=True). round_log = n > 0 returns up to n per-round
+    records in stats["round_log"]."""
     torch = _torch()
     lib = load_library()
     VA = _dev(VA, torch.float64)
     FA = _dev(FA, torch.int32)
-    o = make_options(**opts)
+    log = _round_log(round_log)
+    o = make_options(round_log=log, **opts)
     LU = (C.c_double * 2)()
     stats = Stats()
     st = lib.hd_bound(C.c_void_p(VA.data_ptr()), VA.shape[0], C.c_void_p(FA.data_ptr()), FA.shape[0],
                       bvh.handle, float(eps), C.byref(o), _stream(), LU, C.byref(stats))
     _check(st, "hd_bound")
-    return LU[0], LU[1], stats.as_dict()
+    return LU[0], LU[1], _with_log(stats.as_dict(), log)
 
 
 def build_bvh_batched(soups) -> Bvh:
@@ -221,10 +262,11 @@ def build_bvh_batched(soups) -> Bvh:
     return b
 
 
-def bound_batched(meshes, bvh: Bvh, eps, **opts):
+def bound_batched(meshes, bvh: Bvh, eps, round_log: int = 0, **opts):
     """Certified [L_p, U_p] for many pairs at once; meshes is a list of
     (VA, FA) in the order of the soups given to build_bvh_batched; eps is one
-    value or one per pair. Returns (L list, U list, summed stats)."""
+    value or one per pair (absolute, or relative with relative=True).
+    Returns (L list, U list, summed stats)."""
     torch = _torch()
     lib = load_library()
     Vs = [_dev(V, torch.float64) for V, _ in meshes]
@@ -236,13 +278,14 @@ def bound_batched(meshes, bvh: Bvh, eps, **opts):
     ns = (C.c_int64 * n)(*[F.shape[0] for F in Fs])
     per = not isinstance(eps, (int, float))
     ev = (C.c_double * (n if per else 1))(*([float(e) for e in eps] if per else [float(eps)]))
-    o = make_options(**opts)
+    log = _round_log(round_log)
+    o = make_options(round_log=log, **opts)
     LU = (C.c_double * (2 * n))()
     stats = Stats()
     st = lib.hd_bound_batched(n, vptr, ms, fptr, ns, bvh.handle, ev, 1 if per else 0, C.byref(o), _stream(),
                               LU, C.byref(stats))
     _check(st, "hd_bound_batched")
-    return [LU[2 * i] for i in range(n)], [LU[2 * i + 1] for i in range(n)], stats.as_dict()
+    return [LU[2 * i] for i in range(n)], [LU[2 * i + 1] for i in range(n)], _with_log(stats.as_dict(), log)
 
 
 def build_graphs(enable: bool) -> bool:

@@ -24,9 +24,14 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <string>
+#include <unistd.h>
+#include <utility>
+#include <vector>
 
 #include "hd_kernels.hpp"
 #include "hd_learned.hpp"
@@ -72,9 +77,13 @@ struct Ctl {
     alignas(256) unsigned long long park_next;
     alignas(256) unsigned long long b_next; // records waiting for cascade stage B
     alignas(256) unsigned long long c_next; // records waiting for cascade stage C
-    alignas(256) int bad; // 2 traversal deeper than the fallback stack, 3 depth exhausted
+    // 2 traversal deeper than the fallback stack, 3 depth exhausted, 4 an upper
+    // bound below a vertex distance of its triangle (unsound), 5 plain FP32
+    // with a tolerance below its margin at the lower bound
+    alignas(256) int bad;
     int bad_input;        // 1: soup A has an out-of-range index or a non-finite coordinate
     int n_overflow;       // queries whose LDS stack overflowed this round
+    int log_rounds;       // 1: reports carry the lower bound, upper bound and statistics
     alignas(256) unsigned long long stat[ACC_COPIES][ST_STRIDE];
     // blocks of the current query / argmax launch that have finished (the
     // last one does the launch's tail work and resets its counter)
@@ -197,16 +206,33 @@ __global__ void k_ctl_init(Ctl *c) { ctl_zero(c); }
 // Reports go to a ring of MB_SLOTS slots (slot seq % MB_SLOTS), so that a
 // report may be in flight while the host reads the previous one.
 constexpr int MB_SLOTS = 4;
-struct alignas(64) Mailbox {
+struct alignas(128) Mailbox {
     int64_t act, park, rounds, subdivided;
     int32_t bad_input, pad;
     int64_t pend_c; // records waiting for stage C (deferred)
     int bad, stall, over_budget;
     unsigned seq;
+    // with Ctl::log_rounds: pair 0's bounds and the statistics so far
+    double L0, U0;
+    int64_t bounded, discards[5];
 };
+// the pinned host block: the report ring, then the export's sequence word
+constexpr size_t HOST_RING = 0, HOST_EXPORT_SEQ = MB_SLOTS * sizeof(Mailbox), HOST_UPLOAD = HOST_EXPORT_SEQ + 256;
 
-__device__ void report_to(const Ctl *ctl, Mailbox *ring, unsigned seq) {
+__device__ void report_to(const Ctl *ctl, const PairVar *pv, Mailbox *ring, unsigned seq) {
     Mailbox *mb = ring + seq % MB_SLOTS;
+    if (ctl->log_rounds) {
+        const double L = ord2d(pv[0].Lord);
+        mb->L0 = L;
+        mb->U0 = fmax(L, ord2d(pv[0].Uround));
+        unsigned long long b = 0, dc[5] = {0, 0, 0, 0, 0};
+        for (int c = 0; c < ACC_COPIES; ++c) {
+            b += ctl->stat[c][ST_BOUNDED];
+            for (int k = 0; k < 5; ++k) dc[k] += ctl->stat[c][ST_DISCARDS + k];
+        }
+        mb->bounded = (int64_t)b;
+        for (int k = 0; k < 5; ++k) mb->discards[k] = (int64_t)dc[k];
+    }
     mb->act = (long long)ctl->act_next;
     mb->park = (long long)ctl->park_next;
     mb->bad_input = ctl->bad_input;
@@ -222,8 +248,8 @@ __device__ void report_to(const Ctl *ctl, Mailbox *ring, unsigned seq) {
     __hip_atomic_store(&mb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ void k_report(const Ctl *ctl, Mailbox *ring, unsigned seq) {
-    if (threadIdx.x == 0) report_to(ctl, ring, seq);
+__global__ void k_report(const Ctl *ctl, const PairVar *pv, Mailbox *ring, unsigned seq) {
+    if (threadIdx.x == 0) report_to(ctl, pv, ring, seq);
 }
 
 // Device-planned round: how many active records to split (all of them,
@@ -279,9 +305,9 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
 // the end of a device-planned round: report its state, then plan the next
 // round (a planned round that is never enqueued changes nothing the host
 // reads afterwards)
-__global__ void k_report_plan(Ctl *ctl, Mailbox *ring, unsigned seq, PlanCaps caps) {
+__global__ void k_report_plan(Ctl *ctl, const PairVar *pv, Mailbox *ring, unsigned seq, PlanCaps caps) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    report_to(ctl, ring, seq);
+    report_to(ctl, pv, ring, seq);
     plan_round(ctl, caps);
 }
 
@@ -317,6 +343,7 @@ __device__ void pair_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict_
     d.Lord = d2ord(0.0);
     d.Uord = d2ord(0.0);
     d.Urounds = d2ord(0.0);
+    d.Uround = d2ord(0.0);
     pc[p] = c;
     pv[p] = d;
 }
@@ -348,9 +375,12 @@ __global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restri
 
 // the start of a call: control block, pair tables, referenced-vertex marks
 __global__ void k_bound_init(Ctl *ctl, PairConst *pc, PairVar *pv, PairBox *pb, int astride,
-                             const BvhPair *__restrict__ bp, int npairs, int32_t *__restrict__ ref, int64_t m) {
+                             const BvhPair *__restrict__ bp, int npairs, int32_t *__restrict__ ref, int64_t m,
+                             int log_rounds) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ctl_zero(ctl);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl->log_rounds = log_rounds;
     if (i < npairs) pair_init(pc, pv, bp, (int)i);
     pbox_init(pb, npairs, astride, i);
     if (i < m) ref[i] = 0;
@@ -414,7 +444,7 @@ __device__ Margins make_margins(double u, double edge_max, double coord_max) {
 // pair p's dA, eps * dA and margins, once the ingest has its bbox and
 // coordinate range
 __device__ void pair_post(PairConst *pc, const PairBox *pb, int astride, const BvhPair *__restrict__ bp, int p,
-                          const double *__restrict__ eps, int eps_per_pair) {
+                          const double *__restrict__ eps, int eps_per_pair, int eps_rel) {
     // fold the copies
     unsigned long long b[6], cmo = 0;
     for (int k = 0; k < 6; ++k) b[k] = pb[p].bbox[k];
@@ -433,7 +463,8 @@ __device__ void pair_post(PairConst *pc, const PairBox *pb, int astride, const B
     }
     double dA = sqrt(d2);
     pc[p].dA = dA;
-    pc[p].eps_abs = eps[eps_per_pair ? p : 0] * dA;
+    // the tolerance: absolute, or the paper's relative form (times dA)
+    pc[p].eps_abs = eps[eps_per_pair ? p : 0] * (eps_rel ? dA : 1.0);
     double cm = fmax(ord2d(cmo), bp[p].coord_max);
     pc[p].m32 = make_margins(Prec<float>::u, bp[p].edge_max, cm);
     pc[p].m64 = make_margins(Prec<double>::u, bp[p].edge_max, cm);
@@ -444,10 +475,10 @@ __device__ void pair_post(PairConst *pc, const PairBox *pb, int astride, const B
 __global__ void k_ingest_post(const int32_t *__restrict__ ref, const int32_t *__restrict__ pos, int64_t m,
                               const int32_t *__restrict__ nref, int32_t *__restrict__ out, PairConst *pc,
                               const PairBox *pb, int astride, const BvhPair *__restrict__ bp, int npairs,
-                              const double *__restrict__ eps, int eps_per_pair, Ctl *ctl) {
+                              const double *__restrict__ eps, int eps_per_pair, int eps_rel, Ctl *ctl) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < m && ref[v]) out[pos[v]] = (int32_t)v;
-    if (v < npairs) pair_post(pc, pb, astride, bp, (int)v, eps, eps_per_pair);
+    if (v < npairs) pair_post(pc, pb, astride, bp, (int)v, eps, eps_per_pair, eps_rel);
     if (v == 0) {
         ctl->nref = (unsigned long long)*nref;
         ctl->n_overflow = 0;
@@ -877,6 +908,7 @@ struct L64Cfg {
     const PairConst *pc;
     int npairs;
     int2 *stack_mem; // npairs x DEEP_STACK entries
+    int check_fp32;  // plain FP32 rounds: the tolerance must exceed the margin at L
 };
 
 // after a query round: the query holding its pair's best key records its
@@ -911,8 +943,18 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
                    __syncthreads_or(wrote) != 0)) {
         __shared__ float4 s_none[1]; // no top-level table here (no reference reaches it)
         const NodeSrc ns{lc.nodes, (LdsFloat *)s_none};
-        for (int p = threadIdx.x >> 2; p < lc.npairs; p += blockDim.x >> 2)
+        for (int p = threadIdx.x >> 2; p < lc.npairs; p += blockDim.x >> 2) {
             l64_pair(ns, lc.bv64, lc.ids, lc.pc, pv, p, lc.npairs, lc.stack_mem, threadIdx.x & 3);
+            // Plain FP32 parks a triangle only when its bound plus the FP32
+            // margin lies within the tolerance of L; near the maximum that
+            // margin tends to mu_d * h + mu_0 as the triangles shrink, so a
+            // tolerance below it cannot be reached (the rounds would split
+            // to the depth limit).
+            if (lc.check_fp32 && (threadIdx.x & 3) == 0) {
+                const PairConst &C = lc.pc[p];
+                if (C.eps_abs <= C.m32.mu_d * ord2d(pv[p].Lord) + C.m32.mu_0) ctl->bad = 5;
+            }
+        }
     }
 }
 
@@ -923,6 +965,7 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
 struct ClassifyCfg {
     CascadeCtx c;
     int recheck; // FP32 + FP64 recheck of the ambiguity band
+    double shift; // test hook: subtracted from every bound of stages A and B
     AView a;
     BView<double> bv64;
     IdView iv;
@@ -980,16 +1023,25 @@ template <class T> HD_D T bound_cheap(int k, const Tri<T> &t) {
     return k == 1 ? bound_u1(t) : (k == 2 ? bound_u2(t) : bound_u4(t));
 }
 
+// A valid upper bound over T is at least the distance at each vertex of T,
+// and a computed one plus its margin at least the computed vertex distance
+// minus that margin: a bound below is unsound (flagged in *unsound).
+template <class T> HD_D void check_sound(double u, const Tri<T> &t, double mu, int *unsound) {
+    if (u < (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) - mu) *unsound = 1;
+}
+
 // stage A; *carry receives the running minimum for stage B
 template <class T>
-HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double *carry, int *decider) {
+HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double *carry, int *decider,
+                 int *unsound) {
     const Tri<T> t = make_tri(cn);
     const PairConst &P = cc.pc[pair];
     const double L = ord2d(cc.pv[pair].Lord);
     const double mu = tri_margin(t, margins_of<T>(P));
     if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) {
         *decider = 0;
-        double ub = (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
+        double ub = (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) - cc.shift + mu;
+        check_sound(ub, t, mu, unsound);
         *carry = ub;
         return decide(ub, L, P.eps_abs, mu, cc.recheck);
     }
@@ -1001,7 +1053,8 @@ HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double 
             *carry = best;
             return TO_B;
         }
-        double u = (double)bound_cheap<T>(k, t) + mu;
+        double u = (double)bound_cheap<T>(k, t) - cc.shift + mu;
+        check_sound(u, t, mu, unsound);
         if (u < L) {
             *decider = k;
             *carry = u;
@@ -1019,7 +1072,7 @@ HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double 
 // stage B: u3 and the bounds after it, from the running minimum `best`
 template <class T>
 HD_D int stage_b(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, const BView<T> &bv, double best,
-                 int best_k, double *carry, int *decider, int *evals) {
+                 int best_k, double *carry, int *decider, int *evals, int *unsound) {
     const Tri<T> t = make_tri(cn);
     const PairConst &P = cc.pc[pair];
     const double L = ord2d(cc.pv[pair].Lord);
@@ -1029,7 +1082,8 @@ HD_D int stage_b(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, const B
     *decider = best_k;
     for (int i = i3; i < cc.c.norder; ++i) {
         int k = cc.c.order[i];
-        double u = (double)(k == 3 ? bound_u3(t, bv, cc.iv, nullptr, evals) : bound_cheap<T>(k, t)) + mu;
+        double u = (double)(k == 3 ? bound_u3(t, bv, cc.iv, nullptr, evals) : bound_cheap<T>(k, t)) - cc.shift + mu;
+        check_sound(u, t, mu, unsound);
         if (u < L) {
             *decider = k;
             *carry = u;
@@ -1181,7 +1235,9 @@ __global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__res
             cn[j].ba = (j == 1);
             cn[j].bb = (j == 2);
         }
-        list = stage_a<T>(cn, pair, cc, &carry, &decider);
+        int unsound = 0;
+        list = stage_a<T>(cn, pair, cc, &carry, &decider, &unsound);
+        if (unsound) ctl->bad = 4;
     }
     int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
     if (valid)
@@ -1256,7 +1312,9 @@ __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T
         // dyadic coordinates are int32 numerators over 2^lvl: level 30 is the
         // deepest representable one
         if (lvl > 30) ctl->bad = 3;
-        list = stage_a<T>(cn, pair, cc, &carry, &decider);
+        int unsound = 0;
+        list = stage_a<T>(cn, pair, cc, &carry, &decider, &unsound);
+        if (unsound) ctl->bad = 4;
     }
     int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
     if (valid)
@@ -1282,7 +1340,10 @@ __global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg
             pair = in.pair()[j];
             face = in.face()[j];
             lvl = in.lvl()[j] & 0xff;
-            list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+            int unsound = 0;
+            list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals,
+                              &unsound);
+            if (unsound) ctl->bad = 4;
         }
         int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
         if (valid)
@@ -1347,7 +1408,7 @@ __global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg
     // count; a decision per block is an atomic on one address)
     if (blockIdx.x >= nact) {
         if (seq && nact == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
-            report_to(ctl, ring, seq);
+            report_to(ctl, cc.pv, ring, seq);
             plan_round(ctl, caps);
         }
         return;
@@ -1367,7 +1428,7 @@ __global__ __launch_bounds__(BLK) void k_stage_c(FrontierView<T> in, ClassifyCfg
     // (the plan resets the decision and the counters for the next round: it
     // waits until every block with records has read them)
     if (seq && last_block(&ctl->c_done, nact) && threadIdx.x == 0) {
-        report_to(ctl, ring, seq);
+        report_to(ctl, cc.pv, ring, seq);
         plan_round(ctl, caps);
     }
 }
@@ -1533,7 +1594,10 @@ __global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, Cla
                 list = decide(carry, L, eps, mu, cc.recheck);
                 skipped = 1;
             } else {
-                list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals);
+                int unsound = 0;
+                list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider,
+                                  &evals, &unsound);
+                if (unsound) ctl->bad = 4;
             }
         }
         int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
@@ -1716,6 +1780,31 @@ __global__ void k_export_points(const QueryOut<T> r, int64_t n, const int4 *ids,
     }
 }
 
+// round log: every pair's largest live bound after a round
+__global__ void k_round_U_reset(PairVar *pv, int npairs) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npairs) pv[p].Uround = d2ord(0.0);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_round_U(FrontierView<T> act, FrontierView<T> park, const Ctl *ctl,
+                                                 PairVar *pv) {
+    const int64_t na = (int64_t)ctl->act_next, n = na + (int64_t)ctl->park_next;
+    for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        int pair = 0;
+        double u[1] = {0.0};
+        if (valid) {
+            const bool a = i < na;
+            const int64_t j = a ? i : i - na;
+            u[0] = (double)(a ? act.ub()[j] : park.ub()[j]);
+            pair = a ? act.pair()[j] : park.pair()[j];
+        }
+        block_pair_minmax<1, 1u, BLK>(pair, valid, u, [&](int p, int) { return &pv[p].Uround; });
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side: buffers
 // ---------------------------------------------------------------------------
@@ -1809,6 +1898,84 @@ Workspace *workspace_for(int dev) {
     return w;
 }
 
+// ---- the autotuner's cache file ----------------------------------------------
+// One JSON object whose keys name (device, arithmetic, kernel-source hash)
+// and whose values hold the chosen launch shape:
+//   {"gfx950/256CU/fp32/<hash>": {"variant": 0, "block": 128, "stack": 16}, ...}
+// A file that is missing or cannot be parsed counts as empty; it is rewritten
+// whole (through a temporary file and a rename) when a choice is added.
+#ifndef HD_SOURCE_HASH
+#define HD_SOURCE_HASH "unhashed"
+#endif
+
+std::string tuner_key(int arith64) {
+    int dev = 0;
+    HD_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t pr;
+    HD_HIP(hipGetDeviceProperties(&pr, dev));
+    std::string arch(pr.gcnArchName);
+    for (char &c : arch)
+        if (c == '"' || c == '\\') c = '_';
+    return arch + "/" + std::to_string(pr.multiProcessorCount) + "CU/" + (arith64 ? "fp64" : "fp32") + "/" +
+           HD_SOURCE_HASH;
+}
+
+std::vector<std::pair<std::string, int>> tuner_read(const char *path) {
+    std::vector<std::pair<std::string, int>> out;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return out;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, n);
+    std::fclose(f);
+    size_t i = txt.find('{');
+    while (i != std::string::npos) {
+        const size_t k0 = txt.find('"', i + 1);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = txt.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
+        const size_t body = txt.find('{', k1);
+        const size_t end = body == std::string::npos ? std::string::npos : txt.find('}', body);
+        if (end == std::string::npos) break;
+        const size_t v = txt.find("\"variant\"", body);
+        if (v != std::string::npos && v < end) {
+            const size_t c = txt.find(':', v);
+            if (c != std::string::npos && c < end) {
+                char *e = nullptr;
+                const long val = std::strtol(txt.c_str() + c + 1, &e, 10);
+                if (e != txt.c_str() + c + 1) out.emplace_back(txt.substr(k0 + 1, k1 - k0 - 1), (int)val);
+            }
+        }
+        i = end;
+    }
+    return out;
+}
+
+void tuner_write(const char *path, const std::vector<std::pair<std::string, int>> &entries) {
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return; // the cache is an optimisation: an unwritable path only loses it
+    std::fputs("{\n", f);
+    for (size_t i = 0; i < entries.size(); ++i) {
+        const int v = entries[i].second >= 0 && entries[i].second < NQVAR ? entries[i].second : 0;
+        std::fprintf(f, "  \"%s\": {\"variant\": %d, \"block\": %d, \"stack\": %d}%s\n", entries[i].first.c_str(), v,
+                     QVARIANTS[v].qb, QVARIANTS[v].sd, i + 1 < entries.size() ? "," : "");
+    }
+    std::fputs("}\n", f);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
+}
+
+// the status of a call whose device state has bad != 0 (see Ctl::bad)
+hd_status status_of_bad(int bad) {
+    switch (bad) {
+    case 3: return HD_E_CAPACITY; // depth exhausted: tolerance below what the arithmetic resolves
+    case 5: return HD_E_INVALID;  // plain FP32 with a tolerance below its margin
+    default: return HD_E_INTERNAL;
+    }
+}
+
 int parse_order(int32_t order, int out[4]) {
     if (order <= 0) order = 1234;
     int digits[8], n = 0;
@@ -1889,6 +2056,13 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     if (opt.log_frontier && (!opt.log_out || opt.log_cap <= 0)) throw Error{HD_E_INVALID, "frontier log needs a buffer"};
     for (int p = 0; p < (in.eps_per_pair ? np : 1); ++p)
         if (!(in.eps[p] > 0) || !std::isfinite(in.eps[p])) throw Error{HD_E_INVALID, "eps must be positive"};
+    if (opt.eps_relative != 0 && opt.eps_relative != 1) throw Error{HD_E_INVALID, "eps_relative must be 0 or 1"};
+    if (!std::isfinite(opt.test_bound_shift)) throw Error{HD_E_INVALID, "test_bound_shift must be finite"};
+    if (opt.round_log_cap < 0 || (opt.round_log_cap > 0 && !opt.round_log))
+        throw Error{HD_E_INVALID, "round log needs a host array"};
+    const bool logging = opt.round_log != nullptr && opt.round_log_cap > 0;
+    // plain FP32 rounds: a tolerance below the FP32 margin at L is an input error
+    const int check_fp32 = sizeof(T) == 4 && opt.precision == HD_PREC_FP32 ? 1 : 0;
     std::vector<int64_t> foff(np + 1, 0), voff(np + 1, 0);
     for (int p = 0; p < np; ++p) {
         if (in.nA[p] <= 0 || in.mA[p] <= 0 || !in.VA[p] || !in.FA[p]) throw Error{HD_E_INVALID, "empty soup A"};
@@ -1912,12 +2086,15 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // device in one asynchronous copy; results come back through one export.
     ws.ctl.reserve(sizeof(Ctl));
     Ctl *ctl = ws.ctl.as<Ctl>();
+    ws.pc.reserve(np * sizeof(PairConst));
+    ws.pv.reserve(np * sizeof(PairVar));
+    PairConst *pc = ws.pc.as<PairConst>();
+    PairVar *pv = ws.pv.as<PairVar>();
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const int neps = in.eps_per_pair ? np : 1;
     const size_t o_src = 0, o_foff = o_src + al(np * sizeof(PairSrcA)), o_voff = o_foff + al((np + 1) * 8),
                  o_eps = o_voff + al((np + 1) * 8), up_bytes = o_eps + al(neps * 8);
-    static_assert(MB_SLOTS * sizeof(Mailbox) <= 256, "report ring fits its area");
-    const size_t o_up = 512, o_res = o_up + up_bytes;
+    const size_t o_up = HOST_UPLOAD, o_res = o_up + up_bytes;
     const size_t o_rctl = 0, o_rpv = al(sizeof(Ctl)), o_rpc = o_rpv + al(np * sizeof(PairVar)),
                  res_bytes = o_rpc + al(np * sizeof(PairConst));
     ws.host.reserve(o_res + res_bytes);
@@ -1926,7 +2103,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // lower latency than a stream synchronisation plus a staged copy.
     auto report_async = [&]() -> unsigned {
         const unsigned seq = ++ws.mb_seq;
-        k_report<<<1, 64, 0, s>>>(ctl, mb_dev, seq);
+        k_report<<<1, 64, 0, s>>>(ctl, pv, mb_dev, seq);
         HD_LAUNCH_CHECK();
         return seq;
     };
@@ -1943,10 +2120,6 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         return m;
     };
     auto report = [&]() -> Mailbox { return wait_report(report_async()); };
-    ws.pc.reserve(np * sizeof(PairConst));
-    ws.pv.reserve(np * sizeof(PairVar));
-    PairConst *pc = ws.pc.as<PairConst>();
-    PairVar *pv = ws.pv.as<PairVar>();
     {
         char *up = ws.host.as<char>(o_up);
         PairSrcA *hs = (PairSrcA *)(up + o_src);
@@ -1984,7 +2157,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     ws.pbox.reserve((size_t)ACC_COPIES * pstride * sizeof(PairBox));
     PairBox *pbox = ws.pbox.as<PairBox>();
     k_bound_init<<<grid_for(std::max<int64_t>(mA, (int64_t)np * ACC_COPIES), BLK), BLK, 0, s>>>(
-        ctl, pc, pv, pbox, pstride, B->pairs.as<BvhPair>(), np, ref, mA);
+        ctl, pc, pv, pbox, pstride, B->pairs.as<BvhPair>(), np, ref, mA, logging ? 1 : 0);
     k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
                                               ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pbox, pstride,
                                               ctl);
@@ -1996,7 +2169,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     ws.vids.reserve(mA * sizeof(int32_t));
     k_ingest_post<<<grid_for(std::max<int64_t>(mA, np), BLK), BLK, 0, s>>>(
         ref, refpos, mA, d_total, ws.vids.as<int32_t>(), pc, pbox, pstride, B->pairs.as<BvhPair>(), np, deps,
-        in.eps_per_pair, ctl);
+        in.eps_per_pair, opt.eps_relative ? 1 : 0, ctl);
     const DevCount nref_dev{&ctl->nref, 1, 0};
 
     const BView<T> bv = [&] {
@@ -2029,7 +2202,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         launch_query<T>(qsel, n_max, qmax, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
                         ws.deep.as<int2>(), s);
         prof.mark(prof.q);
-        const L64Cfg l64{B->nodes.as<WideNode>(), bv64, iv.ids, pc, np, ws.gstack.as<int2>()};
+        const L64Cfg l64{B->nodes.as<WideNode>(), bv64, iv.ids, pc, np, ws.gstack.as<int2>(), check_fp32};
         k_argmax_finalize<T><<<std::min<unsigned>(grid_for(n_max, BLK), GRID_MAX), BLK, 0, s>>>(qi, cnt, out.key,
                                                                                                out.I, pv, l64, ctl);
         HD_LAUNCH_CHECK();
@@ -2039,9 +2212,22 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // Times every variant on this call's vertex queries (best of three; no
     // effect on L: the trial queries do not raise it) and keeps the fastest
     // for this device and arithmetic, or the default when it is within 5% of
-    // the fastest; later calls reuse the choice.
+    // the fastest; later calls reuse the choice. With a cache file, a choice
+    // kept there for this device, arithmetic and kernel source is taken
+    // without tuning, and a new choice is added to it.
     tw.vq.ensure(mA);
-    if ((opt.autotune == 1 && !ws.tuned[sizeof(T) == 4 ? 0 : 1]) || opt.autotune == 2) {
+    const int arith = sizeof(T) == 4 ? 0 : 1;
+    std::string tkey;
+    if (opt.autotune == 1 && !ws.tuned[arith] && opt.tuner_cache) {
+        tkey = tuner_key(arith);
+        for (const auto &e : tuner_read(opt.tuner_cache))
+            if (e.first == tkey && e.second >= 0 && e.second < NQVAR) {
+                qvar = e.second;
+                ws.tuned[arith] = true;
+                S.tuned = 2;
+            }
+    }
+    if ((opt.autotune == 1 && !ws.tuned[arith]) || opt.autotune == 2) {
         QueryIn<T> qi{};
         qi.mode = Q_VERTICES;
         qi.npairs = np;
@@ -2079,7 +2265,20 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         if (t_default <= 1.05f * best) pick = 0;
         k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
         qvar = pick;
-        ws.tuned[sizeof(T) == 4 ? 0 : 1] = true;
+        ws.tuned[arith] = true;
+        S.tuned = 1;
+        if (opt.tuner_cache) {
+            if (tkey.empty()) tkey = tuner_key(arith);
+            auto entries = tuner_read(opt.tuner_cache);
+            bool found = false;
+            for (auto &e : entries)
+                if (e.first == tkey) {
+                    e.second = pick;
+                    found = true;
+                }
+            if (!found) entries.emplace_back(tkey, pick);
+            tuner_write(opt.tuner_cache, entries);
+        }
     }
     qsel = small_stack ? -1 : qvar;
     S.query_block = qsel < 0 ? 128 : QVARIANTS[qsel].qb;
@@ -2110,6 +2309,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     ClassifyCfg cc;
     cc.c = cctx;
     cc.recheck = (opt.precision == HD_PREC_FP32_RECHECK) && sizeof(T) == 4;
+    cc.shift = opt.test_bound_shift;
     cc.a = av;
     cc.bv64 = bv64;
     cc.iv = iv;
@@ -2155,7 +2355,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl, defer, mb_dev, plan_seq,
                                            plan_seq ? caps() : PlanCaps{});
         else if (plan_seq)
-            k_report_plan<<<1, 64, 0, s>>>(ctl, mb_dev, plan_seq, caps());
+            k_report_plan<<<1, 64, 0, s>>>(ctl, pv, mb_dev, plan_seq, caps());
         HD_LAUNCH_CHECK();
     };
 
@@ -2163,7 +2363,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     // triangles, so the device plans each round itself and the host enqueues
     // one round ahead of the report it waits for: the GPU never idles between
     // rounds. The host-driven loop below handles the other modes.
-    const bool planned = opt.subbatch <= 0 && !opt.log_frontier;
+    const bool planned = opt.subbatch <= 0 && !opt.log_frontier && !logging;
     // the results (control block, pair tables) to pinned host memory; returns
     // the sequence number the host waits for
     auto enqueue_export = [&]() -> unsigned {
@@ -2179,8 +2379,33 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         ex.dst[2] = ws.host.dev_as<char>(o_res + o_rpc);
         ex.bytes[2] = np * sizeof(PairConst);
         const unsigned seq = ++ws.mb_seq;
-        export_to_host(ex, ws.host.dev_as<unsigned>(256), seq, s);
+        export_to_host(ex, ws.host.dev_as<unsigned>(HOST_EXPORT_SEQ), seq, s);
         return seq;
+    };
+    // round log: each pair's largest live bound (active and parked lists,
+    // counts on the device) into PairVar::Uround before the round's report,
+    // and one record per report
+    Mailbox hm{}; // the latest report read
+    auto round_U = [&](const FrontierView<T> &act_out) {
+        if (!logging) return;
+        k_round_U_reset<<<grid_for(np, 64), 64, 0, s>>>(pv, np);
+        k_round_U<T><<<std::min<unsigned>(grid_for(tw.act.cap + tw.park.cap, BLK), GRID_MAX), BLK, 0, s>>>(
+            act_out, tw.park.v, ctl, pv);
+        HD_LAUNCH_CHECK();
+    };
+    auto log_round = [&](int r, int64_t split) {
+        if (!logging || S.round_records >= opt.round_log_cap) return;
+        hd_round_record &R = opt.round_log[S.round_records++];
+        std::memset(&R, 0, sizeof(R));
+        R.round = r;
+        R.split = split;
+        R.active = hm.act;
+        R.parked = hm.park;
+        R.bounded = hm.bounded;
+        for (int k = 0; k < 5; ++k) R.discards[k] = hm.discards[k];
+        R.L = hm.L0;
+        R.U = hm.U0;
+        R.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     };
     // a final step and export enqueued ahead of the last round's report
     // (used when that report shows the run converged)
@@ -2209,12 +2434,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     int64_t subdivided = 0, logged = 0, nAct = 0, nPark = 0;
     int rounds = 0;
     hd_status status = HD_OK;
-    Mailbox hm{};
     if (planned) {
         // report the state after a round and plan the next one
         auto report_plan_async = [&]() -> unsigned {
             const unsigned seq = ++ws.mb_seq;
-            k_report_plan<<<1, 64, 0, s>>>(ctl, mb_dev, seq, caps());
+            k_report_plan<<<1, 64, 0, s>>>(ctl, pv, mb_dev, seq, caps());
             HD_LAUNCH_CHECK();
             return seq;
         };
@@ -2329,15 +2553,16 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         rounds = (int)hm.rounds;
         subdivided = hm.subdivided;
         S.max_frontier = peak;
-        if (hm.bad == 3) status = HD_E_CAPACITY; // depth exhausted: tolerance below what the arithmetic resolves
-        else if (hm.bad) status = HD_E_INTERNAL;
+        if (hm.bad) status = status_of_bad(hm.bad);
         else if (hm.over_budget || (hm.stall && hm.act > 0)) status = HD_E_CAPACITY;
     } else {
+        round_U(tw.act.v);
         hm = report();
         nAct = hm.act;
         nPark = hm.park;
         S.max_frontier = nAct + nPark;
-        if (hm.bad == 2) status = HD_E_INTERNAL;
+        if (hm.bad) status = status_of_bad(hm.bad);
+        log_round(0, 0);
     }
     // learned order: every record is scored once, when it joins the active
     // list (only needed when sub-batches are selected)
@@ -2440,6 +2665,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
         later_stages(4 * K, tw.act2.v, 0, 0);
         prof.mark(prof.c);
+        round_U(tw.act2.v);
         hm = report();
         swap_fb(tw.act, tw.act2);
         nAct = hm.act;
@@ -2449,8 +2675,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         processed += 4.0 * (double)K;
         ++rounds;
         S.max_frontier = std::max<int64_t>(S.max_frontier, nAct + nPark);
-        if (hm.bad == 3) status = HD_E_CAPACITY; // depth exhausted: tolerance below what the arithmetic resolves
-        else if (hm.bad) status = HD_E_INTERNAL;
+        if (hm.bad) status = status_of_bad(hm.bad);
+        log_round(rounds, K);
     }
 
     // ---- final FP64 step: U over every live triangle --------------------------
@@ -2471,7 +2697,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     }
     {
         const unsigned seq = use_spec ? spec_seq : enqueue_export();
-        wait_host_seq(ws.host.as<unsigned>(256), seq, s);
+        wait_host_seq(ws.host.as<unsigned>(HOST_EXPORT_SEQ), seq, s);
     }
     const Ctl &hc = *ws.host.as<Ctl>(o_res + o_rctl);
     auto stat = [&](int k) {
@@ -2481,7 +2707,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     };
     const PairVar *hp = ws.host.as<PairVar>(o_res + o_rpv);
     const PairConst *hc_ = ws.host.as<PairConst>(o_res + o_rpc);
-    if (status == HD_OK && hc.bad == 2) status = HD_E_INTERNAL;
+    if (status == HD_OK && hc.bad) status = status_of_bad(hc.bad);
     if (status == HD_OK) {
         for (int p = 0; p < np; ++p) {
             double L = ord2d(hp[p].Lord);

@@ -42,6 +42,7 @@ struct alignas(128) PairVar {
     int32_t argmax_dirty;
     int32_t argmax_tri;           // closest triangle (sorted index) found for it by the query
     double L64;
+    unsigned long long Uround;    // ordered double: largest live bound after a round (round log)
 };
 
 // ---------------------------------------------------------------------------

@@ -49,12 +49,12 @@ def log_frontier(workloads, subbatch: int = 0, cap: int = 1 << 20, precision=PRE
         if isinstance(W, list):
             bvh = build_bvh_batched([(_cu(VB, torch), _cu(FB, torch)) for _, _, VB, FB, _ in W])
             _, _, st = bound_batched([(_cu(VA, torch), _cu(FA, torch)) for VA, FA, _, _, _ in W], bvh,
-                                     [e for *_, e in W], precision=precision, subbatch=subbatch, log_out=log)
+                                     [e for *_, e in W], precision=precision, subbatch=subbatch, log_out=log, relative=True)
         else:
             VA, FA, VB, FB, eps = W
             bvh = build_bvh(_cu(VB, torch), _cu(FB, torch))
             _, _, st = bound(_cu(VA, torch), _cu(FA, torch), bvh, eps, precision=precision, subbatch=subbatch,
-                             log_out=log)
+                             log_out=log, relative=True)
         rows = log[:st["logged"]].cpu().numpy()
         out.append(rows[np.all(np.isfinite(rows), 1)])
     return np.concatenate(out) if out else np.zeros((0, 17), np.float32)

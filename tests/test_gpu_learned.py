@@ -40,7 +40,7 @@ def test_first_logged_parent_matches_oracle():
     log = torch.empty((4096, 17), dtype=torch.float32, device="cuda")
     say("log of one triangle")
     bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
-    L, U, st = hd.bound(_cu(VA, torch), _cu(FA, torch), bvh, 1e-4, subbatch=1, log_out=log)
+    L, U, st = hd.bound(_cu(VA, torch), _cu(FA, torch), bvh, 1e-4, subbatch=1, log_out=log, relative=True)
     assert st["logged"] >= 1
     row = log[0].cpu().numpy().astype(np.float64)
     d, I = oracle.points_soup(VA, VB, FB)
@@ -74,7 +74,7 @@ def test_learned_modes_stay_certified(mode):
     say("learned mode", mode, "untrained network, sub-batch 64")
     bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
     L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, subbatch=64, learned=mode,
-                        mlp_params=P)
+                        mlp_params=P, relative=True)
     dA = ref["dA"]
     print(f"gpu [{L:.10g}, {U:.10g}] oracle [{ref['L']:.10g}, {ref['U']:.10g}] rounds {st['rounds']} "
           f"skips {st['learned_skips']}")
@@ -89,7 +89,7 @@ def test_learned_mode_needs_parameters():
     W = wl.config(1)
     bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
     with pytest.raises(hd.HDError):
-        hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, learned=1)
+        hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, learned=1, relative=True)
 
 
 def test_trained_network_gains_over_plain_on_the_large_torus():
@@ -118,7 +118,7 @@ def test_trained_network_gains_over_plain_on_the_large_torus():
         say("config 5 (quarter size), sub-batch", K, "learned" if mode else "plain")
         bvh = hd.build_bvh(VB, FB)
         L, U, st = hd.bound(VA, FA, bvh, W5.eps_rel, subbatch=K, learned=mode, mlp_params=P if mode else None,
-                            profile=1)
+                            profile=1, relative=True)
         res[mode] = (L, U, st)
         print(f"  [{L:.10g}, {U:.10g}] nodes bounded {st['nodes_bounded']} subdivided {st['subdivided']} "
               f"rounds {st['rounds']} ms {st['ms_total']:.2f}")

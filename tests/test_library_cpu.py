@@ -46,3 +46,28 @@ def test_product_path_fails_loudly_without_library(tmp_path):
             hd.load_library(str(tmp_path / "missing.so"))
         finally:
             hd._lib = saved
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every field of hd_options, hd_stats and hd_round_record sits at the same
+    offset in the ctypes binding as in the C header (compiled here)."""
+    import ctypes as C
+    import subprocess
+    import paper_2406_10357_amd as hd
+    structs = {"hd_options": hd.Options, "hd_stats": hd.Stats, "hd_round_record": hd.RoundRecord}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    for row in filter(None, out):
+        cname, field, val = row.split()
+        py = structs[cname]
+        want = C.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(val) == want, (cname, field, int(val), want)
