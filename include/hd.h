@@ -232,6 +232,24 @@ hd_status hd_bound_batched(int32_t npairs, const double *const *VA, const int64_
 hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh B, int32_t precision, int32_t lanes,
                              double *d, int32_t *I, double *Q, hd_stream_t stream);
 
+/* hd_point_distances for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same query kernels and results, with every piece of scratch
+ * (control block, pair table, overflow list, deep stack, query results) in a
+ * static device array of about 5 MB per GPU, held until the process ends.
+ * Nothing is allocated, nothing is copied to the host and the stream is not
+ * synchronised: the call only enqueues work on `stream`. *err (a DEVICE
+ * int32) receives HD_OK, or HD_E_INTERNAL when a traversal exceeded the deep
+ * fallback stack, once the stream reaches the end of the call.
+ * At most HD_NOALLOC_MAX_POINTS points per call: more returns HD_E_CAPACITY
+ * before anything is enqueued. HD_E_INVALID for a NULL err or bad arguments.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe. */
+#define HD_NOALLOC_MAX_POINTS 65536
+hd_status hd_point_distances_noalloc(const double *P, int64_t nP, hd_bvh B, int32_t precision, int32_t lanes,
+                                     double *d, int32_t *I, double *Q, int32_t *err, hd_stream_t stream);
+
 /* All five bounds of n given triangles against B, for testing the bound
  * kernels in isolation ("Upper bounds" subsection). Device arrays: v (n x 9
  * doubles: three vertices), d (n x 3 vertex distances), I (n x 3 closest faces

@@ -77,7 +77,8 @@ class Stats(C.Structure):
 EXPORTS = ["hd_build_bvh", "hd_build_bvh_batched", "hd_free_bvh", "hd_bound", "hd_bound_batched",
            "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options",
            "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train", "hd_frontier_features",
-           "hd_build_graphs"]
+           "hd_build_graphs", "hd_point_distances_noalloc"]
+NOALLOC_MAX_POINTS = 65536  # HD_NOALLOC_MAX_POINTS
 
 
 def load_library(path: str | None = None):
@@ -108,6 +109,8 @@ def load_library(path: str | None = None):
                                      i32, C.POINTER(Options), vp, C.POINTER(C.c_double), C.POINTER(Stats)]
     lib.hd_point_distances.restype = i32
     lib.hd_point_distances.argtypes = [vp, i64, vp, i32, i32, vp, vp, vp, vp]
+    lib.hd_point_distances_noalloc.restype = i32
+    lib.hd_point_distances_noalloc.argtypes = [vp, i64, vp, i32, i32, vp, vp, vp, vp, vp]
     lib.hd_eval_bounds.restype = i32
     lib.hd_eval_bounds.argtypes = [vp, vp, vp, vp, i64, vp, i32, vp, vp, vp]
     lib.hd_status_str.restype = C.c_char_p
@@ -308,6 +311,28 @@ def point_distances(P, bvh: Bvh, precision=PREC_FP64, lanes=1):
                                 C.c_void_p(I.data_ptr()), C.c_void_p(Q.data_ptr()), _stream())
     _check(st, "hd_point_distances")
     return d, I, Q
+
+
+def point_distances_noalloc(P, bvh: Bvh, precision=PREC_FP64, lanes=1, out=None):
+    """point_distances through the entry point that allocates nothing (its
+    scratch is a static device array; at most NOALLOC_MAX_POINTS points).
+    out: optional (d, I, Q, err) device tensors to write into. Returns
+    (d, I, Q, err) with err a one-element device int32 tensor (the status the
+    device wrote). Only enqueues work: read err after the stream."""
+    torch = _torch()
+    lib = load_library()
+    P = _dev(P, torch.float64)
+    n = P.shape[0]
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float64, device=P.device), torch.empty(n, dtype=torch.int32, device=P.device),
+               torch.empty((n, 3), dtype=torch.float64, device=P.device),
+               torch.full((1,), -1, dtype=torch.int32, device=P.device))
+    d, I, Q, err = out
+    st = lib.hd_point_distances_noalloc(C.c_void_p(P.data_ptr()), n, bvh.handle, precision, lanes,
+                                        C.c_void_p(d.data_ptr()), C.c_void_p(I.data_ptr()), C.c_void_p(Q.data_ptr()),
+                                        C.c_void_p(err.data_ptr()), _stream())
+    _check(st, "hd_point_distances_noalloc")
+    return d, I, Q, err
 
 
 def eval_bounds(v, d, I, q, bvh: Bvh, precision=PREC_FP64):

@@ -45,7 +45,7 @@ namespace {
 constexpr int QSTACK = 16;    // LDS ring-stack entries per lane (16 KB per block)
 constexpr int SMALL_STACK = 4; // test hook: tiny LDS stack, forces the deep path
 constexpr int DEEP_STACK = 256;
-constexpr int DEEP_SLOTS = 4096; // concurrent deep traversals
+constexpr int DEEP_SLOTS = 256;  // deep traversals at once: one per thread of the query kernel's last block
 constexpr int BLK = 256;
 constexpr int NW = BLK / 64;
 constexpr unsigned GRID_MAX = 2048;  // persistent cap of grid-stride launches (8 blocks per CU)
@@ -753,6 +753,7 @@ template <class T, int SD, int QB>
 __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
                                               QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
                                               Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max) {
+    static_assert(QB <= DEEP_SLOTS, "every thread of the last block has a deep-stack slot");
     __shared__ int s_node[SD * QB];
     __shared__ float s_dist[SD * QB];
     __shared__ float4 s_top[TOP_NODES * 8];
@@ -1767,8 +1768,10 @@ __global__ void k_inv_perm(const int4 *ids, int64_t n, int32_t *inv) {
 
 template <class T>
 __global__ void k_export_points(const QueryOut<T> r, int64_t n, const int4 *ids, const PairConst *pc, double *d,
-                                int32_t *I, double *Q) {
+                                int32_t *I, double *Q, const Ctl *ctl, int32_t *err) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the query kernel has finished (stream order): its failure flag is final
+    if (err && i == 0) *err = ctl->bad == 2 ? (int32_t)HD_E_INTERNAL : (int32_t)HD_OK;
     if (i >= n) return;
     const double *c = pc[0].ctr;
     d[i] = (double)r.d[i];
@@ -1838,6 +1841,26 @@ template <class T> void swap_fb(FrontierBuf<T> &a, FrontierBuf<T> &b) {
     std::swap(a.v, b.v);
 }
 
+// query results for nc queries, one array per field (256-byte aligned)
+// carved from p; qout_bytes<T>(nc) bytes
+template <class T> constexpr size_t qout_bytes(int64_t nc) {
+    return (size_t)nc * (sizeof(T) * 7 + 4 + 8) + 16 * 256;
+}
+template <class T> QueryOut<T> carve_qout(char *p, int64_t nc) {
+    QueryOut<T> o{};
+    auto take = [&](size_t sz) {
+        char *r = p;
+        p += ((size_t)nc * sz + 255) & ~size_t(255);
+        return r;
+    };
+    o.d = (T *)take(sizeof(T));
+    o.I = (int *)take(4);
+    for (int k = 0; k < 3; ++k) o.q[k] = (T *)take(sizeof(T));
+    for (int k = 0; k < 3; ++k) o.p[k] = (T *)take(sizeof(T));
+    o.key = (unsigned long long *)take(8);
+    return o;
+}
+
 template <class T> struct QBuf {
     DBuf mem;
     int64_t cap = 0;
@@ -1845,18 +1868,8 @@ template <class T> struct QBuf {
     void ensure(int64_t n) {
         if (n <= cap) return;
         int64_t nc = std::max<int64_t>(n, cap + cap / 2);
-        mem.reserve((size_t)nc * (sizeof(T) * 7 + 4 + 8) + 16 * 256);
-        char *p = mem.as<char>();
-        auto take = [&](size_t sz) {
-            char *r = p;
-            p += ((size_t)nc * sz + 255) & ~size_t(255);
-            return r;
-        };
-        o.d = (T *)take(sizeof(T));
-        o.I = (int *)take(4);
-        for (int k = 0; k < 3; ++k) o.q[k] = (T *)take(sizeof(T));
-        for (int k = 0; k < 3; ++k) o.p[k] = (T *)take(sizeof(T));
-        o.key = (unsigned long long *)take(8);
+        mem.reserve(qout_bytes<T>(nc));
+        o = carve_qout<T>(mem.as<char>(), nc);
         cap = nc;
     }
 };
@@ -2758,6 +2771,51 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
 // ============================================================================
 using namespace hd;
 
+// ---- scratch of hd_point_distances_noalloc --------------------------------
+// Callers that cannot allocate get their scratch (the control block, the pair
+// tables, the overflow list, the deep stack and the query results) from one
+// static device array per GPU, held until the process ends. Host code never
+// uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_dev.
+namespace {
+constexpr size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t NA_CTL = 0;
+constexpr size_t NA_PC = NA_CTL + al256(sizeof(Ctl));
+constexpr size_t NA_PV = NA_PC + al256(sizeof(PairConst));
+constexpr size_t NA_OVF = NA_PV + al256(sizeof(PairVar));
+constexpr size_t NA_DEEP = NA_OVF + al256((size_t)HD_NOALLOC_MAX_POINTS * sizeof(int32_t));
+constexpr size_t NA_Q = NA_DEEP + al256((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
+constexpr size_t NA_BYTES = NA_Q + qout_bytes<double>(HD_NOALLOC_MAX_POINTS); // FP64 results are the larger
+static_assert(qout_bytes<double>(1) >= qout_bytes<float>(1), "FP64 query results need more room");
+} // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[64] = {};
+
+// the device address of `scratch` on the current device (looked up once per device)
+static char *scratch_on_current_device() {
+    int dev = 0;
+    HD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) throw Error{HD_E_DEVICE, "device index out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = p;
+    }
+    return static_cast<char *>(g_scratch_dev[dev]);
+}
+
+namespace hd {
+namespace {
+__global__ void k_write_status(int32_t *err, int32_t v) {
+    if (threadIdx.x == 0) *err = v;
+}
+} // namespace
+} // namespace hd
+
 static hd_status guard(const std::function<hd_status()> &fn) {
     try {
         return fn();
@@ -2920,7 +2978,8 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             else bv = BView<double>{B->frames64.as<double2>()};
             launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
                             ovf.as<int32_t>(), deep.as<int2>(), s);
-            k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q);
+            k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q, ctl,
+                                                                 nullptr);
             HD_LAUNCH_CHECK();
             HD_HIP(hipStreamSynchronize(s));
         };
@@ -2929,6 +2988,57 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
         Ctl hc;
         HD_HIP(hipMemcpy(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost));
         if (hc.bad == 2) return HD_E_INTERNAL;
+        return HD_OK;
+    });
+}
+
+hd_status hd_point_distances_noalloc(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, int32_t lanes,
+                                     double *d, int32_t *I, double *Q, int32_t *err, hd_stream_t stream) {
+    if (!Bh || !err || nP < 0 || (nP > 0 && (!P || !d || !I))) return HD_E_INVALID;
+    if (lanes != 0 && lanes != 1 && lanes != 4) return HD_E_INVALID;
+    if (precision != HD_PREC_FP64 && precision != HD_PREC_FP32 && precision != HD_PREC_FP32_RECHECK)
+        return HD_E_INVALID;
+    if (nP > HD_NOALLOC_MAX_POINTS) return HD_E_CAPACITY;
+    const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
+    hipStream_t s = (hipStream_t)stream;
+    return guard([&] {
+        char *sc = scratch_on_current_device();
+        if (nP == 0) {
+            k_write_status<<<1, 64, 0, s>>>(err, HD_OK);
+            HD_LAUNCH_CHECK();
+            return HD_OK;
+        }
+        Ctl *ctl = reinterpret_cast<Ctl *>(sc + NA_CTL);
+        PairConst *pc = reinterpret_cast<PairConst *>(sc + NA_PC);
+        PairVar *pv = reinterpret_cast<PairVar *>(sc + NA_PV);
+        int32_t *ovf = reinterpret_cast<int32_t *>(sc + NA_OVF);
+        int2 *deep = reinterpret_cast<int2 *>(sc + NA_DEEP);
+        // the previous call's contents stay in the array: zero the control
+        // block and rebuild the pair table (kernels, no memset)
+        k_ctl_init<<<1, 256, 0, s>>>(ctl);
+        k_pairs_init<<<1, 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), 1);
+        const WideNode *top = B->npairs == 1 && !B->hpairs.empty() && B->hpairs[0].root >= 0
+                                  ? B->top.as<WideNode>()
+                                  : nullptr;
+        const QueryCfg cfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            const QueryOut<T> qo = carve_qout<T>(sc + NA_Q, nP);
+            QueryIn<T> qi{};
+            qi.mode = Q_POINTS;
+            qi.npairs = 1;
+            qi.P = P;
+            qi.pc = pc;
+            BView<T> bv;
+            if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
+            else bv = BView<double>{B->frames64.as<double2>()};
+            launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qo, pc, pv, ctl, ovf,
+                            deep, s);
+            k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qo, nP, B->ids.as<int4>(), pc, d, I, Q, ctl, err);
+            HD_LAUNCH_CHECK();
+        };
+        if (precision == HD_PREC_FP64) go(double{});
+        else go(float{});
         return HD_OK;
     });
 }
