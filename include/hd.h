@@ -59,8 +59,11 @@ typedef struct {
     int64_t capacity;    /* frontier capacity in triangles; 0 = automatic */
     int32_t max_rounds;  /* 0 = unlimited */
     int32_t stack_depth; /* traversal stack entries per lane (test hook); 0 = default */
-    int32_t subbatch;    /* > 0: subdivide at most this many triangles per round, highest
-                            upper bound first (approximates the paper's best-first queue) */
+    int32_t subbatch;    /* > 0: subdivide about this many triangles per round, highest upper
+                            bound first (approximates the paper's best-first queue). The device
+                            selects them (a radix select on the key; the last key bin is taken
+                            whole, so a round may split a few more); triangles whose bound fell
+                            below L are dropped and those within eps of L parked first. */
     int32_t profile;     /* 1: time the query and cascade kernels with HIP events on the
                             call's stream (fills the ms_* kernel fields of hd_stats); 2: the
                             query kernels only (every event record costs the stream a few
@@ -151,6 +154,8 @@ typedef struct {
     int32_t tuned;             /* where the query launch shape came from: 0 kept in memory or the
                                   default, 1 tuned by this call, 2 read from tuner_cache */
     int32_t pad1;
+    int64_t stale;             /* sub-batches: active triangles dropped before being split because
+                                  L had risen above their bound (the paper's stale queue entries) */
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle

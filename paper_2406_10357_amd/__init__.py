@@ -66,7 +66,7 @@ class Stats(C.Structure):
                 ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64),
                 ("logged", C.c_int64), ("learned_skips", C.c_int64), ("query_block", C.c_int32),
                 ("query_stack", C.c_int32), ("query_lanes", C.c_int32), ("query_quad_max", C.c_int32),
-                ("round_records", C.c_int64), ("tuned", C.c_int32), ("pad1", C.c_int32)]
+                ("round_records", C.c_int64), ("tuned", C.c_int32), ("pad1", C.c_int32), ("stale", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad1"}

@@ -67,6 +67,7 @@ enum {
     ST_BOXES,
     ST_QLEAVES,
     ST_SKIPS, // records whose u3 / u4 the learned policy skipped
+    ST_STALE, // active records dropped by the sub-batch selection (bound below L)
     ST_N
 };
 constexpr int ST_STRIDE = 32; // 256 bytes per copy
@@ -87,7 +88,7 @@ struct Ctl {
     alignas(256) unsigned long long stat[ACC_COPIES][ST_STRIDE];
     // blocks of the current query / argmax launch that have finished (the
     // last one does the launch's tail work and resets its counter)
-    alignas(256) unsigned q_done, f_done, c_done;
+    alignas(256) unsigned q_done, f_done, c_done, h1_done, h2_done;
     // device-planned rounds (written by plan_round, read by the round's kernels)
     alignas(256) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
     unsigned long long nref;                           // referenced vertices of A (round 0's queries)
@@ -96,6 +97,18 @@ struct Ctl {
     int stall;                                         // 1: capacity left no room to split
     int over_budget;                                   // 1: the next split would exceed the budget
     int c_decision;                                    // stage C this round: 0 undecided, 1 run, 2 deferred
+    // device sub-batch selection (sel_round): plan_round leaves the list as it
+    // is and sets the target; the selection passes pick the records and
+    // finish the plan
+    unsigned long long plan_kcap;  // most parents the lists have room for this round
+    unsigned long long sel_n;      // active records when the selection started
+    unsigned long long sel_live;   // of those, neither below L nor within eps of it
+    unsigned long long sel_above1; // live records in first-level bins above sel_b1
+    unsigned sel_b1, sel_thr;      // boundary bin of the first pass; the ordered-key threshold
+    int sel_mode;                  // SEL_NONE, SEL_ALL or SEL_THRESHOLD
+    alignas(256) unsigned long long sel_prom;  // learned order: live records predicted above L + eps
+    alignas(256) unsigned long long sel_next;  // selected parents appended (their record indices)
+    alignas(256) unsigned long long rest_next; // unselected live records appended
 };
 
 // Item count of a launch: a host value, or (device-planned rounds) a count
@@ -259,10 +272,19 @@ struct PlanCaps {
     int64_t act, park, pend, pend_c, mq; // capacities (records / queries)
     double budget;               // the paper's m * nA
     int grow_act, grow_park;     // 1: the host can still grow the active / parked lists
+    int64_t subbatch;            // > 0: the round splits the sub-batch the device selects
+    int learned;                 // sub-batches in learned order (the selection may take all)
 };
 __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     const int64_t nAct = (int64_t)c->act_next, nPark = (int64_t)c->park_next;
-    int64_t K = 0;
+    // with sub-batches the round splits at most this many (the selection
+    // may also drop or park up to all of the others)
+    // (the learned order splits every live record once none is predicted to
+    // raise L, so its rounds are planned for all of them)
+    const int64_t want =
+        caps.subbatch > 0 && !caps.learned ? (nAct < caps.subbatch ? nAct : caps.subbatch) : nAct;
+    const int64_t reserve_park = caps.subbatch > 0 ? nAct : 0;
+    int64_t K = 0, kcap = 0;
     if (!c->bad && !c->stall && !c->over_budget && nAct > 0) {
         // room in the active-side lists (the pending and midpoint lists are
         // sized with the active ones) and in the parked list
@@ -272,21 +294,32 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
         ka = ka < caps.pend / 4 ? ka : caps.pend / 4;
         ka = ka < (caps.pend_c - nc) / 4 ? ka : (caps.pend_c - nc) / 4;
         ka = ka < caps.mq / 3 ? ka : caps.mq / 3;
-        const int64_t kp = (caps.park - nPark - nc) / 4;
-        K = nAct;
-        K = K < ka ? K : ka;
-        K = K < kp ? K : kp;
+        const int64_t kp = (caps.park - nPark - nc - reserve_park) / 4;
+        kcap = ka < kp ? ka : kp;
+        K = want < kcap ? want : kcap;
         // split all or, while the list that lacks room can grow, none (a
         // stall: the host grows it), so that the rounds do not depend on the
         // capacities that earlier calls left behind
-        if ((ka < nAct && caps.grow_act) || (kp < nAct && caps.grow_park)) K = 0;
+        if ((ka < want && caps.grow_act) || (kp < want && caps.grow_park)) K = 0;
         if (K <= 0) {
             K = 0;
             c->stall = 1;
-        } else if (c->processed + 4.0 * (double)K > caps.budget) {
+        } else if (caps.subbatch <= 0 && c->processed + 4.0 * (double)K > caps.budget) {
             K = 0;
             c->over_budget = 1;
         }
+    }
+    if (caps.subbatch > 0) {
+        // the selection passes pick about K records and finish the plan
+        // (split count, carried count, budget, totals)
+        c->plan_K = (unsigned long long)K;
+        c->plan_kcap = (unsigned long long)(kcap > 0 ? kcap : 0);
+        c->sel_prom = 0;
+        c->b_next = 0;
+        if (c->c_decision != 2) c->c_next = 0;
+        c->c_decision = 0;
+        c->n_overflow = 0;
+        return;
     }
     c->plan_K = (unsigned long long)K;
     c->plan_rest = (unsigned long long)(nAct - K);
@@ -319,6 +352,11 @@ __global__ void k_set_counts(Ctl *c, unsigned long long act, unsigned long long 
     c->act_next = act;
     c->park_next = park;
     c->c_decision = 0;
+}
+
+__global__ void k_zero_u32(unsigned *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 __global__ void k_clear_stall(Ctl *c) {
@@ -519,6 +557,7 @@ template <class T> struct QueryIn {
     AView a;                 // Q_VERTICES / Q_MIDPOINTS
     FrontierView<T> par;     // Q_MIDPOINTS / Q_LATTICE: selected parents
     const PairConst *pc;
+    const int32_t *sel;      // Q_MIDPOINTS: record index of each parent (null: the first parents)
 };
 
 struct QPoint {
@@ -568,9 +607,10 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
         q.seed[1] = in.par.I(heavy == 2 ? 0 : heavy + 1)[j];
         return q;
     }
-    int64_t j = i / 3;
-    int e = (int)(i - 3 * j);
-    int k = (e + 1) % 3;
+    const int64_t js = i / 3;
+    const int e = (int)(i - 3 * js);
+    const int k = (e + 1) % 3;
+    const int64_t j = in.sel ? (int64_t)in.sel[js] : js;
     int face = in.par.face()[j], lvl = in.par.lvl()[j] + 1;
     int ba = in.par.ba(e)[j] + in.par.ba(k)[j], bb = in.par.bb(e)[j] + in.par.bb(k)[j];
     q.pair = in.par.pair()[j];
@@ -1253,14 +1293,17 @@ template <class T> HD_D void copy_record(const FrontierView<T> &src, int64_t i, 
 // carry (device-planned rounds): the records the round does not split,
 // par[nsel .. nsel + plan_rest), move to the head of the active output,
 // ahead of the appended children (plan_round starts the append count there).
+// With sel and rest (device sub-batch selection) the parents and the carried
+// records are the ones those index lists name.
 template <class T>
 __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T> par, QueryOut<T> mq,
-                                                  ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry) {
+                                                  ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry,
+                                                  const int32_t *__restrict__ sel, const int32_t *__restrict__ rest) {
     const int64_t nsel = nselc.get();
     if (carry) {
-        const int64_t rest = (int64_t)ctl->plan_rest;
-        for (int64_t o = (int64_t)blockIdx.x * BLK + threadIdx.x; o < rest; o += (int64_t)gridDim.x * BLK)
-            copy_record(par, nsel + o, dst.act, o);
+        const int64_t nrest = (int64_t)ctl->plan_rest;
+        for (int64_t o = (int64_t)blockIdx.x * BLK + threadIdx.x; o < nrest; o += (int64_t)gridDim.x * BLK)
+            copy_record(par, rest ? (int64_t)rest[o] : nsel + o, dst.act, o);
     }
     for (int64_t cbase = (int64_t)blockIdx.x * BLK; cbase < 4 * nsel; cbase += (int64_t)gridDim.x * BLK) {
     const int64_t c = cbase + threadIdx.x;
@@ -1269,7 +1312,8 @@ __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T
     double carry = 0;
     Corner<T> cn[3];
     if (valid) {
-        const int64_t j = c >> 2;
+        const int64_t js = c >> 2;                       // the parent's position in the round
+        const int64_t j = sel ? (int64_t)sel[js] : js;   // its record
         const int kid = (int)(c & 3);
         // corner s of the parent, or the midpoint of parent edge (e, e+1);
         // every array index below is a compile-time constant, so the view's
@@ -1285,7 +1329,7 @@ __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T
         };
         auto mid = [&](Corner<T> &o, auto E) {
             constexpr int e = decltype(E)::value, e2 = (e + 1) % 3;
-            const int64_t mi = 3 * j + e;
+            const int64_t mi = 3 * js + e;
             o.v = {mq.p[0][mi], mq.p[1][mi], mq.p[2][mi]};
             o.q = {mq.q[0][mi], mq.q[1][mi], mq.q[2][mi]};
             o.d = mq.d[mi];
@@ -1654,6 +1698,339 @@ __global__ void k_sel_keys(FrontierView<T> fr, int64_t n, unsigned long long *__
 }
 
 // ---------------------------------------------------------------------------
+// device sub-batch selection
+// ---------------------------------------------------------------------------
+// Rounds with sub-batches split about K of the active records: those with the
+// largest keys (the upper bound: the paper's best-first order; or the
+// network's predicted maximum: the learned order). A two-level radix select on
+// the 32-bit ordered key finds the threshold without sorting: 4096 bins of the
+// key's top 12 bits, then 4096 bins of the next 12 bits inside the boundary
+// bin; every record at or above the threshold is selected (about K: the last
+// bin is taken whole, and it is 2^-15 of the key's magnitude wide). The
+// selected set depends only on the records, not on their order in the list.
+// The passes also re-check each record against the current L, which may have
+// risen since the record was bounded: below L it is dropped (the paper's stale
+// queue entries), within eps of L it is parked.
+constexpr int SEL_BINS = 4096;
+constexpr unsigned SEL_GRID_MAX = 512;
+// SEL_FROZEN: the plan splits nothing (no room, a failure, the budget): every
+// record is carried as it is (the park list has no room reserved for it)
+enum { SEL_NONE = 0, SEL_ALL = 1, SEL_THRESHOLD = 2, SEL_FROZEN = 3 };
+
+struct SelCfg {
+    unsigned *hist1, *hist2; // SEL_BINS counters each, zero between rounds
+    int32_t *sel, *rest;     // record indices: the selected parents, the carried records
+    int learned;             // the key: the network's prediction (1) or the upper bound (0)
+    double budget;           // the paper's face budget (m * nA), less round 0
+    int64_t subbatch;        // the sub-batch size
+};
+
+template <class T> HD_D uint32_t sel_key(const FrontierView<T> &f, int64_t j, int learned) {
+    float k = f.ub()[j];
+    if (learned) {
+        const float sc = f.score()[j];
+        if (sc == sc) k = sc; // unscored or NaN: the bound
+    }
+    return f2ord(k);
+}
+
+// what the selection does with record j: 0 keep it live, 1 drop it (its bound
+// is below L), 2 park it (its bound is within eps of L)
+template <class T> HD_D int sel_fate(const FrontierView<T> &f, int64_t j, const PairConst *pc, const PairVar *pv) {
+    const int pair = f.pair()[j];
+    const double ub = (double)f.ub()[j], L = ord2d(pv[pair].Lord);
+    if (ub < L) return 1;
+    return ub - L <= park_limit(pc[pair].eps_abs) ? 2 : 0;
+}
+
+// Run by every thread of one block: the largest bin b of hist with
+// sum(hist[b..]) >= want (-1 if the total is smaller); *above receives the sum
+// over the bins above b, *at the count of b, *total the sum of all bins. The
+// histogram is read with device-scope loads (other blocks filled it with
+// atomics) and zeroed for the next round.
+__device__ int sel_find_bin(unsigned *hist, unsigned long long want, unsigned long long *above,
+                            unsigned long long *at, unsigned long long *total) {
+    constexpr int PER = SEL_BINS / BLK;
+    static_assert(SEL_BINS % BLK == 0, "bins per thread");
+    __shared__ unsigned long long sfx[BLK];
+    __shared__ int s_bin;
+    __shared__ unsigned long long s_above, s_at;
+    const int t = threadIdx.x;
+    unsigned v[PER];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = __hip_atomic_load(&hist[t * PER + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sum += v[k];
+    }
+    sfx[t] = sum;
+    if (t == 0) {
+        s_bin = -1;
+        s_above = 0;
+        s_at = 0;
+    }
+    __syncthreads();
+    // inclusive suffix sums over the threads' chunks
+    for (int off = 1; off < BLK; off <<= 1) {
+        const unsigned long long x = t + off < BLK ? sfx[t + off] : 0ull;
+        __syncthreads();
+        sfx[t] += x;
+        __syncthreads();
+    }
+    unsigned long long run = t + 1 < BLK ? sfx[t + 1] : 0ull; // records in the chunks above
+    if (run < want && sfx[t] >= want) {
+        // the crossing lies in this thread's chunk: walk it from the top
+        for (int k = PER - 1; k >= 0; --k) {
+            if (run + v[k] >= want) {
+                s_bin = t * PER + k;
+                s_above = run;
+                s_at = v[k];
+                break;
+            }
+            run += v[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) hist[t * PER + k] = 0;
+    __syncthreads();
+    *above = s_above;
+    *at = s_at;
+    *total = sfx[0];
+    return s_bin;
+}
+
+// block histogram of the live records' keys: level 1 bins the top 12 bits of
+// every live record; level 2 the next 12 bits of those in bin b1
+template <class T, int LEVEL>
+__device__ void sel_histogram(const FrontierView<T> &act, int64_t n, int learned, unsigned b1, const PairConst *pc,
+                              const PairVar *pv, unsigned *global_hist, unsigned long long *prom_out) {
+    __shared__ unsigned h[SEL_BINS];
+    __shared__ unsigned prom;
+    for (int i = threadIdx.x; i < SEL_BINS; i += BLK) h[i] = 0;
+    if (threadIdx.x == 0) prom = 0;
+    __syncthreads();
+    for (int64_t j = (int64_t)blockIdx.x * BLK + threadIdx.x; j < n; j += (int64_t)gridDim.x * BLK) {
+        if (sel_fate(act, j, pc, pv) != 0) continue;
+        const uint32_t key = sel_key(act, j, learned);
+        if (LEVEL == 1) {
+            atomicAdd(&h[key >> 20], 1u);
+            // learned order: a live record whose predicted maximum lies above
+            // L + eps may still raise L
+            if (learned) {
+                const float sc = act.score()[j];
+                const int pair = act.pair()[j];
+                if (sc == sc && (double)sc > ord2d(pv[pair].Lord) + pc[pair].eps_abs) atomicAdd(&prom, 1u);
+            }
+        } else if ((key >> 20) == b1) {
+            atomicAdd(&h[(key >> 8) & (SEL_BINS - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < SEL_BINS; i += BLK)
+        if (h[i]) atomicAdd(&global_hist[i], h[i]);
+    if (LEVEL == 1 && threadIdx.x == 0 && prom) atomicAdd(prom_out, (unsigned long long)prom);
+}
+
+// first pass: histogram of the live records; the last block finds the
+// boundary bin of the target (ctl->plan_K, set by plan_round)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_sel_hist1(FrontierView<T> act, SelCfg sc, const PairConst *__restrict__ pc,
+                                                   const PairVar *pv, Ctl *ctl) {
+    const int64_t n = (int64_t)ctl->act_next;
+    const unsigned long long want = ctl->plan_K;
+    if (want == 0) { // frozen: nothing to count
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->sel_n = (unsigned long long)n;
+            ctl->sel_live = (unsigned long long)n;
+            ctl->sel_above1 = 0;
+            ctl->sel_b1 = 0;
+            ctl->sel_mode = SEL_FROZEN;
+        }
+        return;
+    }
+    const int64_t need = (n + BLK - 1) / BLK;
+    const unsigned nact = (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x);
+    if (blockIdx.x >= nact && !(nact == 0 && blockIdx.x == 0)) return;
+    if (nact > 0) sel_histogram<T, 1>(act, n, sc.learned, 0, pc, pv, sc.hist1, &ctl->sel_prom);
+    if (nact == 0 || last_block(&ctl->h1_done, nact)) {
+        // learned order: the top sub-batch by prediction while some record
+        // may still raise L, else every live record (breadth-first)
+        const unsigned long long target =
+            sc.learned ? (__hip_atomic_load(&ctl->sel_prom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0
+                              ? (want < (unsigned long long)sc.subbatch ? want : (unsigned long long)sc.subbatch)
+                              : want)
+                       : want;
+        unsigned long long above = 0, at = 0, total = 0;
+        const int b = sel_find_bin(sc.hist1, target, &above, &at, &total);
+        if (threadIdx.x == 0) {
+            ctl->sel_n = (unsigned long long)n;
+            ctl->sel_live = total;
+            ctl->sel_above1 = above;
+            ctl->sel_b1 = b < 0 ? 0u : (unsigned)b;
+            // every live record, or a threshold the second pass refines inside bin b
+            ctl->sel_mode = total <= target ? SEL_ALL : SEL_THRESHOLD;
+            ctl->plan_K = target;
+        }
+    }
+}
+
+// second pass: the boundary bin's records by their next 12 bits; the last
+// block fixes the threshold and finishes the round's plan
+template <class T>
+__global__ __launch_bounds__(BLK) void k_sel_hist2(FrontierView<T> act, SelCfg sc, const PairConst *__restrict__ pc,
+                                                   const PairVar *pv, Ctl *ctl) {
+    const int64_t n = (int64_t)ctl->sel_n;
+    const unsigned long long want = ctl->plan_K;
+    const bool refine = ctl->sel_mode == SEL_THRESHOLD;
+    const int64_t need = refine ? (n + BLK - 1) / BLK : 0;
+    const unsigned nact = (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x);
+    if (blockIdx.x >= nact && !(nact == 0 && blockIdx.x == 0)) return;
+    if (nact > 0) sel_histogram<T, 2>(act, n, sc.learned, ctl->sel_b1, pc, pv, sc.hist2, nullptr);
+    if (!(nact == 0 || last_block(&ctl->h2_done, nact))) return;
+    unsigned long long above = 0, at = 0, total = 0;
+    int b2 = -1;
+    if (refine) b2 = sel_find_bin(sc.hist2, want - ctl->sel_above1, &above, &at, &total);
+    if (threadIdx.x != 0) return;
+    const unsigned long long live = ctl->sel_live;
+    unsigned long long K = 0;
+    int mode = SEL_NONE;
+    unsigned thr = 0xffffffffu;
+    if (ctl->sel_mode == SEL_ALL) {
+        K = live;
+        mode = SEL_ALL;
+    } else if (refine && b2 >= 0) {
+        const unsigned b1 = ctl->sel_b1;
+        K = ctl->sel_above1 + above + at;
+        thr = (b1 << 20) | ((unsigned)b2 << 8);
+        mode = SEL_THRESHOLD;
+        if (K > ctl->plan_kcap) {
+            // the boundary bin does not fit: leave it out (what is above it
+            // is fewer than the target, which fits)
+            K = ctl->sel_above1 + above;
+            thr = b2 + 1 < SEL_BINS ? ((b1 << 20) | ((unsigned)(b2 + 1) << 8)) : ((b1 + 1) << 20);
+            if (K == 0) {
+                ctl->stall = 1;
+                mode = SEL_NONE;
+            }
+        }
+    }
+    if (K > 0 && ctl->processed + 4.0 * (double)K > sc.budget) {
+        K = 0;
+        mode = SEL_NONE;
+        ctl->over_budget = 1;
+    }
+    if (mode == SEL_NONE) K = 0;
+    if (ctl->sel_mode == SEL_FROZEN) mode = SEL_FROZEN;
+    ctl->sel_mode = mode;
+    ctl->sel_thr = mode == SEL_THRESHOLD ? thr : (mode == SEL_ALL ? 0u : 0xffffffffu);
+    ctl->plan_K = K;
+    ctl->plan_rest = live - K;
+    ctl->act_next = live - K; // the carried records lead the round's output list
+    ctl->processed += 4.0 * (double)K;
+    ctl->subdivided += K;
+    if (K > 0) ctl->rounds += 1;
+    ctl->sel_next = 0;
+    ctl->rest_next = 0;
+}
+
+// block-aggregated append to one of three counters (list 0..2; -1: none);
+// every thread of the block must call it
+__device__ int64_t append3(int list, unsigned long long *c0, unsigned long long *c1, unsigned long long *c2) {
+    __shared__ int wc[3][NW];
+    __shared__ unsigned long long base[3];
+    const int w = threadIdx.x >> 6, lane = __lane_id();
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long m[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        m[k] = __ballot(list == k);
+        if (lane == 0) wc[k][w] = __popcll(m[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        int tot = 0;
+        for (int j = 0; j < NW; ++j) {
+            const int c = wc[k][j];
+            wc[k][j] = tot;
+            tot += c;
+        }
+        unsigned long long *ctr = k == 0 ? c0 : (k == 1 ? c1 : c2);
+        base[k] = tot ? atomicAdd(ctr, (unsigned long long)tot) : 0;
+    }
+    __syncthreads();
+    int64_t slot = -1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        if (list == k) slot = (int64_t)(base[k] + wc[k][w] + __popcll(m[k] & lt));
+    __syncthreads();
+    return slot;
+}
+
+// third pass: drop the records below L, park those within eps of it, and list
+// the selected parents and the carried records (record indices)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_sel_compact(FrontierView<T> act, FrontierView<T> park, SelCfg sc,
+                                                     const PairConst *__restrict__ pc, const PairVar *pv, Ctl *ctl) {
+    const int64_t n = (int64_t)ctl->sel_n;
+    const int mode = ctl->sel_mode;
+    const unsigned thr = ctl->sel_thr;
+    unsigned long long stale = 0;
+    for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
+        const int64_t j = base + threadIdx.x;
+        int list = -1; // 0 park, 1 selected, 2 carried
+        if (j < n && mode == SEL_FROZEN) {
+            list = 2;
+        } else if (j < n) {
+            const int fate = sel_fate(act, j, pc, pv);
+            if (fate == 1) ++stale;
+            else if (fate == 2) list = 0;
+            else list = (mode == SEL_ALL || (mode == SEL_THRESHOLD && sel_key(act, j, sc.learned) >= thr)) ? 1 : 2;
+        }
+        const int64_t slot = append3(list, &ctl->park_next, &ctl->sel_next, &ctl->rest_next);
+        if (list == 0) copy_record(act, j, park, slot);
+        else if (list == 1) sc.sel[slot] = (int32_t)j;
+        else if (list == 2) sc.rest[slot] = (int32_t)j;
+    }
+    block_add<1, BLK>({stale}, {&ctl->stat[acc_copy()][ST_STALE]});
+}
+
+// learned order in device-planned rounds: the network scores every active
+// record that has no score yet (those the previous round appended)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_score_new(FrontierView<T> fr, const Ctl *ctl, LearnCfg lc, BView<T> bv,
+                                                   const float *__restrict__ params) {
+    const int64_t n = (int64_t)ctl->act_next;
+    if ((int64_t)blockIdx.x * BLK >= n) return;
+    __shared__ ScoreLds S;
+    bool loaded = false;
+    for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
+        const int64_t j = base + threadIdx.x;
+        bool valid = false;
+        if (j < n) {
+            const float sc = fr.score()[j];
+            valid = !(sc == sc);
+        }
+        if (!__syncthreads_or(valid)) continue;
+        if (!loaded) {
+            for (int i = threadIdx.x; i < mlp::NPARAM; i += BLK) mlp::set_param(S.W, i, params[i]);
+            loaded = true;
+            __syncthreads();
+        }
+        Tri<T> t{};
+        double L = 0, dA = 1;
+        if (valid) {
+            t = record_tri(fr, j);
+            const int pair = fr.pair()[j];
+            L = ord2d(lc.pv[pair].Lord);
+            dA = lc.pc[pair].dA;
+        }
+        const float y = score_block(S, valid, t, L, dA, bv, lc.iv);
+        if (valid) fr.score()[j] = predicted_max(t, y);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // final FP64 step
 // ---------------------------------------------------------------------------
 // whether the rounds left the run converged: nothing active or planned, no
@@ -1889,6 +2266,7 @@ struct Workspace {
     bool tuned[2] = {false, false};
     hipEvent_t tune_ev[2] = {nullptr, nullptr};
     DBuf ctl, pc, pv, pbox, params, Vcat, Fcat, fpair, ref, vids, ovf, deep, gstack, scan_tmp, sort_tmp, sortbuf, small;
+    DBuf selidx, selhist; // device sub-batch selection: index lists, two histograms
     // what the device copy of the upload holds (the copy is skipped when a
     // call uploads the same bytes to the same buffer)
     std::vector<char> uploaded;
@@ -2333,6 +2711,14 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     const LearnCfg lc{pc, pv, iv};
     // (defer: device-planned rounds may leave the recheck band to accumulate)
     const double budget = (opt.budget_m > 0 ? opt.budget_m : 1e7) * (double)nA;
+    // The device plans each round itself (the sub-batch too, when there is
+    // one) and the host enqueues one round ahead of the report it waits for:
+    // the GPU never idles between rounds. The host-driven loop below handles
+    // the frontier log and the round log.
+    const bool planned = !opt.log_frontier && !logging;
+    // device-planned rounds with sub-batches: the device selects each round's
+    // sub-batch (k_sel_hist1, k_sel_hist2, k_sel_compact)
+    const bool sel_round = planned && opt.subbatch > 0;
     // device-planned rounds: the stage lists follow the active lists (keep_c:
     // records waiting for stage C, kept when its list grows), and the
     // capacities each plan works with
@@ -2341,6 +2727,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         tw.mq.ensure(c);
         tw.pend_b.ensure(c, 0, s);
         if (cc.recheck) tw.pend_c.ensure(c, keep_c, s);
+        if (sel_round) ws.selidx.reserve(2 * (size_t)std::max(tw.act.cap, tw.act2.cap) * sizeof(int32_t));
     };
     auto caps = [&]() {
         PlanCaps c;
@@ -2352,6 +2739,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         c.budget = budget - (double)nA;
         c.grow_act = c.act < cap_limit;
         c.grow_park = c.park < cap_limit;
+        c.subbatch = sel_round ? opt.subbatch : 0;
+        c.learned = sel_round && opt.learned > 0 ? 1 : 0;
         return c;
     };
     // plan_seq != 0: the stages end a device-planned round (report under
@@ -2372,11 +2761,6 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
     };
 
-    // Without sub-batches or the frontier log every round splits all active
-    // triangles, so the device plans each round itself and the host enqueues
-    // one round ahead of the report it waits for: the GPU never idles between
-    // rounds. The host-driven loop below handles the other modes.
-    const bool planned = opt.subbatch <= 0 && !opt.log_frontier && !logging;
     // the results (control block, pair tables) to pinned host memory; returns
     // the sequence number the host waits for
     auto enqueue_export = [&]() -> unsigned {
@@ -2437,6 +2821,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         size_round(0); // no resize here (round 0 sized the stage lists): deferred records stay
         seq0 = ++ws.mb_seq;
     }
+    if (sel_round) {
+        ws.selhist.reserve(2 * SEL_BINS * sizeof(unsigned));
+        k_zero_u32<<<grid_for(2 * SEL_BINS, BLK), BLK, 0, s>>>(ws.selhist.as<unsigned>(), 2 * SEL_BINS);
+        HD_LAUNCH_CHECK();
+    }
     prof.mark(prof.c);
     k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc,
                                                   Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
@@ -2458,18 +2847,40 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         // a round as planned by the report before it
         auto enqueue_round = [&]() {
             const PlanCaps c = caps();
+            const int64_t kmax = std::min<int64_t>(c.mq / 3, c.act);
+            const int32_t *selp = nullptr, *restp = nullptr;
+            if (sel_round) {
+                // the sub-batch: score the new records (learned order), then
+                // select by key, dropping and parking what the current L
+                // decides (the counts are on the device)
+                const int64_t cap_act = tw.act.cap;
+                SelCfg sc{ws.selhist.as<unsigned>(), ws.selhist.as<unsigned>() + SEL_BINS,
+                          ws.selidx.as<int32_t>(), ws.selidx.as<int32_t>() + std::max(tw.act.cap, tw.act2.cap),
+                          opt.learned > 0 ? 1 : 0, c.budget, (int64_t)opt.subbatch};
+                const unsigned gs = std::max(1u, std::min<unsigned>(grid_for(cap_act, BLK), SEL_GRID_MAX));
+                if (opt.learned > 0)
+                    k_score_new<T><<<std::min<unsigned>(grid_for(cap_act, BLK), GRID_MAX), BLK, 0, s>>>(
+                        tw.act.v, ctl, lc, bv, opt.mlp_params);
+                k_sel_hist1<T><<<gs, BLK, 0, s>>>(tw.act.v, sc, pc, pv, ctl);
+                k_sel_hist2<T><<<gs, BLK, 0, s>>>(tw.act.v, sc, pc, pv, ctl);
+                k_sel_compact<T><<<std::min<unsigned>(grid_for(cap_act, BLK), GRID_MAX), BLK, 0, s>>>(
+                    tw.act.v, tw.park.v, sc, pc, pv, ctl);
+                HD_LAUNCH_CHECK();
+                selp = sc.sel;
+                restp = sc.rest;
+            }
             QueryIn<T> qi{};
             qi.mode = Q_MIDPOINTS;
             qi.npairs = np;
             qi.a = av;
             qi.par = tw.act.v;
             qi.pc = pc;
-            const int64_t kmax = std::min<int64_t>(c.mq / 3, c.act);
+            qi.sel = selp;
             run_queries(qi, DevCount{&ctl->plan_K, 3, 0}, 3 * kmax, tw.mq.o);
             prof.mark(prof.c);
             k_children<T><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
                 DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
-                Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1);
+                Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp, restp);
             HD_LAUNCH_CHECK();
             const unsigned seq = ++ws.mb_seq;
             later_stages(4 * kmax, tw.act2.v, 1, seq);
@@ -2674,7 +3085,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         k_children<T><<<std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX), BLK, 0, s>>>(host_count(K), tw.act.v,
                                                                                           tw.mq.o, cc,
                                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
-                                                           ctl, 0);
+                                                           ctl, 0, nullptr, nullptr);
         HD_LAUNCH_CHECK();
         later_stages(4 * K, tw.act2.v, 0, 0);
         prof.mark(prof.c);
@@ -2745,6 +3156,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     S.query_box_tests = (int64_t)stat(ST_BOXES);
     S.logged = logged;
     S.learned_skips = (int64_t)stat(ST_SKIPS);
+    S.stale = (int64_t)stat(ST_STALE);
     S.dA = hc_[0].dA;
     S.eps_abs = hc_[0].eps_abs;
     S.mu_coef_d = margins_of<T>(hc_[0]).mu_d;

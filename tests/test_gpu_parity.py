@@ -356,6 +356,33 @@ def test_subbatch_selection_is_certified():
     assert st["rounds"] > 5
 
 
+@pytest.mark.parametrize("k,scale,prec,K", [(2, 0.05, 2, 64), (2, 0.1, 2, 1000), (3, 0.05, 1, 500),
+                                           (3, 0.05, 0, 500), (1, 1.0, 0, 16), (5, 0.01, 2, 3000)])
+def test_device_subbatch_selection(k, scale, prec, K):
+    """Sub-batches selected on the device (radix select on the upper bound):
+    certified against the oracle, deterministic, every round splits about K
+    (at least K while enough live records remain: the last key bin is taken
+    whole), and against the host-driven loop's exact top-K sort (the round
+    log selects it) the same interval up to eps."""
+    hd, torch = _hd()
+    W = wl.config(k, scale=scale)
+    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+    say(f"device sub-batch {K} on config{k} scale {scale} precision {prec}")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    L, U, st = hd.bound(*args, subbatch=K, precision=prec, relative=True)
+    _check_against_oracle(L, U, st, ref, f"config{k}@{scale} device subbatch {K}")
+    again = hd.bound(*args, subbatch=K, precision=prec, relative=True)
+    assert again[:2] == (L, U)
+    for key in ("subdivided", "nodes_bounded", "rounds", "stale"):
+        assert again[2][key] == st[key], key
+    # about K per round: never fewer rounds than the exact top-K would need
+    assert st["rounds"] >= -(-st["subdivided"] // (4 * K)) and st["subdivided"] > 0
+    Lh, Uh, sh = hd.bound(*args, subbatch=K, precision=prec, relative=True, round_log=1 << 14)
+    _check_against_oracle(Lh, Uh, sh, ref, f"config{k}@{scale} host-sorted subbatch {K}")
+    assert all(r["split"] <= K for r in sh["round_log"])
+
+
 def test_small_capacity_still_certified():
     hd, torch = _hd()
     W = wl.config(2, scale=0.05)
@@ -714,9 +741,9 @@ def test_config3_full_size_against_oracle():
 def test_deferred_recheck_band(k, scale):
     """Device-planned rounds leave the FP64 recheck band to accumulate and
     decide it once enough records wait or no active record is left; the
-    host-driven loop (a sub-batch as large as the frontier: every active
-    triangle split each round, in the same order) decides it every round.
-    Both are certified against the oracle and overlap."""
+    host-driven loop (which the round log selects: every active triangle
+    split each round, in the same order) decides it every round. Both are
+    certified against the oracle and overlap."""
     hd, torch = _hd()
     W = wl.config(k, scale=scale)
     ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
@@ -724,7 +751,7 @@ def test_deferred_recheck_band(k, scale):
     args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
     say(f"config{k} scale {scale}: planned rounds vs host loop, FP32 + recheck")
     L0, U0, s0 = hd.bound(*args, precision=hd.PREC_FP32_RECHECK, relative=True)
-    L1, U1, s1 = hd.bound(*args, precision=hd.PREC_FP32_RECHECK, subbatch=1 << 30, relative=True)
+    L1, U1, s1 = hd.bound(*args, precision=hd.PREC_FP32_RECHECK, round_log=4096, relative=True)
     print("rechecked", s0["rechecked64"], s1["rechecked64"], "rounds", s0["rounds"], s1["rounds"])
     _check_against_oracle(L0, U0, s0, ref, "planned (deferred band)")
     _check_against_oracle(L1, U1, s1, ref, "host loop (band every round)")
@@ -732,13 +759,16 @@ def test_deferred_recheck_band(k, scale):
 
 
 @pytest.mark.parametrize("k,scale,prec,subbatch", [(1, 1.0, "fp64", 0), (2, 0.1, "fp32+recheck", 0),
-                                                   (2, 0.1, "fp32+recheck", 1 << 30), (3, 0.02, "fp32", 0),
-                                                   (5, 0.02, "fp32+recheck", 0)])
+                                                   (2, 0.1, "fp32+recheck", 1 << 30), (2, 0.1, "fp32+recheck", 300),
+                                                   (3, 0.02, "fp32", 0), (3, 0.05, "fp32", 2000),
+                                                   (5, 0.02, "fp32+recheck", 0), (5, 0.02, "fp32+recheck", 4096)])
 def test_every_bounded_triangle_is_decided_once(k, scale, prec, subbatch):
     """Conservation over a converged run: every bounded triangle ends either
-    discarded (by exactly one deciding bound), parked at the end, or split, so
-    nodes_bounded = sum(discards) + parked_final + subdivided. A recheck
-    record decided twice, or lost, breaks it."""
+    discarded (by exactly one deciding bound), dropped by the sub-batch
+    selection (its bound fell below L before it was split), parked at the end,
+    or split, so nodes_bounded = sum(discards) + stale + parked_final +
+    subdivided. A recheck record decided twice, or lost, breaks it; so does a
+    record the selection loses or duplicates."""
     hd, torch = _hd()
     W = wl.config(k, scale=scale)
     say("conservation, config", k, "scale", scale, prec, "subbatch", subbatch)
@@ -746,8 +776,9 @@ def test_every_bounded_triangle_is_decided_once(k, scale, prec, subbatch):
     L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, precision=PRECS[prec],
                         subbatch=subbatch, relative=True)
     assert st["status"] == 0 and U - L <= st["eps_abs"] * (1 + 1e-12)
-    decided = sum(st["discards"]) + st["parked_final"] + st["subdivided"]
-    print("bounded", st["nodes_bounded"], "decided", decided, "rechecked", st["rechecked64"])
+    decided = sum(st["discards"]) + st["stale"] + st["parked_final"] + st["subdivided"]
+    print("bounded", st["nodes_bounded"], "decided", decided, "rechecked", st["rechecked64"], "stale", st["stale"],
+          "rounds", st["rounds"])
     assert st["nodes_bounded"] == decided
 
 
