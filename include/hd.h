@@ -226,6 +226,23 @@ hd_status hd_bound_batched(int32_t npairs, const double *const *VA, const int64_
                            int32_t eps_per_pair, const hd_options *opt, hd_stream_t stream,
                            double *LU_out, hd_stats *stats);
 
+/* Certified [L, U] for the two-sided distance H(A,B) = max{h(A,B), h(B,A)}
+ * (Conclusion and future work: the symmetric distance, with the lower bound of
+ * one direction reused by the other). Both directions run as one two-pair
+ * call over one BVH of both soups (built inside the call), and their
+ * decisions share one lower bound, the larger of the two: a triangle of
+ * either direction bounded below it cannot raise H. On success
+ * L <= H(A,B) <= U and U - L <= eps (absolute; with hd_options.eps_relative = 1
+ * relative to the larger of the two soups' bounding-box diagonals).
+ * LU_out: HOST array of 2 doubles. LU_dir (host, 4 doubles, nullable):
+ * [L, U] of h(A,B), then of h(B,A); each contains its distance but may be
+ * wider than eps (the direction whose distance is the smaller one stops as
+ * soon as it cannot exceed the other). Soups are device arrays as for
+ * hd_bound; stats (nullable) sums both directions. Errors as for hd_bound. */
+hd_status hd_hausdorff(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, const double *VB, int64_t mB,
+                       const int32_t *FB, int64_t nB, double eps, const hd_options *opt, hd_stream_t stream,
+                       double LU_out[2], double LU_dir[4], hd_stats *stats);
+
 /* Distances from nP points P (device, nP x 3 doubles) to B: d (device, nP
  * doubles), closest face of B as its original index (device, nP int32) and
  * closest points (device, nP x 3 doubles; may be NULL). precision selects

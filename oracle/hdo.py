@@ -175,3 +175,22 @@ def bound(VA, FA, VB, FB, eps_rel, m=1e7, order=(1, 2, 3, 4), backend="brute", t
     out["argmax"] = list(r.argmax)
     out["status"] = st
     return out
+
+
+def _diag(V, F):
+    """Diagonal of the bounding box of the vertices the faces reference."""
+    P = np.asarray(V, np.float64)[np.unique(np.asarray(F))]
+    return float(np.linalg.norm(P.max(0) - P.min(0)))
+
+
+def hausdorff(VA, FA, VB, FB, eps_abs, backend="brute", **kw):
+    """The two-sided distance H(A,B) = max{h(A,B), h(B,A)} (Conclusion and
+    future work): the branch and bound run in each direction to the same
+    absolute tolerance; H lies in [max of the lower bounds, max of the upper
+    bounds], an interval no wider than the tolerance. Returns a dict with L, U,
+    status and the two one-sided results (ab, ba)."""
+    ab = bound(VA, FA, VB, FB, eps_abs / _diag(VA, FA), backend=backend, **kw)
+    ba = bound(VB, FB, VA, FA, eps_abs / _diag(VB, FB), backend=backend, **kw)
+    status = ab["status"] or ba["status"]
+    return {"L": max(ab["L"], ba["L"]), "U": max(ab["U"], ba["U"]), "status": status, "ab": ab, "ba": ba,
+            "eps_abs": eps_abs}

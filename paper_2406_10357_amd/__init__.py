@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-__all__ = ["HDError", "Bvh", "Options", "build_bvh", "bound", "build_bvh_batched", "bound_batched",
+__all__ = ["HDError", "Bvh", "Options", "build_bvh", "bound", "build_bvh_batched", "bound_batched", "hausdorff",
            "point_distances", "eval_bounds",
            "load_library", "PREC_FP64", "PREC_FP32", "PREC_FP32_RECHECK"]
 
@@ -77,7 +77,7 @@ class Stats(C.Structure):
 EXPORTS = ["hd_build_bvh", "hd_build_bvh_batched", "hd_free_bvh", "hd_bound", "hd_bound_batched",
            "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options",
            "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train", "hd_frontier_features",
-           "hd_build_graphs", "hd_point_distances_noalloc"]
+           "hd_build_graphs", "hd_point_distances_noalloc", "hd_hausdorff"]
 NOALLOC_MAX_POINTS = 65536  # HD_NOALLOC_MAX_POINTS
 
 
@@ -109,6 +109,9 @@ def load_library(path: str | None = None):
                                      i32, C.POINTER(Options), vp, C.POINTER(C.c_double), C.POINTER(Stats)]
     lib.hd_point_distances.restype = i32
     lib.hd_point_distances.argtypes = [vp, i64, vp, i32, i32, vp, vp, vp, vp]
+    lib.hd_hausdorff.restype = i32
+    lib.hd_hausdorff.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64, dbl, C.POINTER(Options), vp,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(Stats)]
     lib.hd_point_distances_noalloc.restype = i32
     lib.hd_point_distances_noalloc.argtypes = [vp, i64, vp, i32, i32, vp, vp, vp, vp, vp]
     lib.hd_eval_bounds.restype = i32
@@ -244,6 +247,27 @@ def bound(VA, FA, bvh: Bvh, eps: float, round_log: int = 0, **opts):
                       bvh.handle, float(eps), C.byref(o), _stream(), LU, C.byref(stats))
     _check(st, "hd_bound")
     return LU[0], LU[1], _with_log(stats.as_dict(), log)
+
+
+def hausdorff(VA, FA, VB, FB, eps: float, round_log: int = 0, **opts):
+    """Certified (L, U, ((L_AB, U_AB), (L_BA, U_BA)), stats) for the two-sided
+    distance H(A,B) = max{h(A,B), h(B,A)}: L <= H <= U, U - L <= eps (eps
+    times the larger bounding-box diagonal with relative=True). The two
+    one-sided intervals contain their distances but may be wider than eps."""
+    torch = _torch()
+    lib = load_library()
+    VA, VB = _dev(VA, torch.float64), _dev(VB, torch.float64)
+    FA, FB = _dev(FA, torch.int32), _dev(FB, torch.int32)
+    log = _round_log(round_log)
+    o = make_options(round_log=log, **opts)
+    LU = (C.c_double * 2)()
+    LUd = (C.c_double * 4)()
+    stats = Stats()
+    st = lib.hd_hausdorff(C.c_void_p(VA.data_ptr()), VA.shape[0], C.c_void_p(FA.data_ptr()), FA.shape[0],
+                          C.c_void_p(VB.data_ptr()), VB.shape[0], C.c_void_p(FB.data_ptr()), FB.shape[0], float(eps),
+                          C.byref(o), _stream(), LU, LUd, C.byref(stats))
+    _check(st, "hd_hausdorff")
+    return LU[0], LU[1], ((LUd[0], LUd[1]), (LUd[2], LUd[3])), _with_log(stats.as_dict(), log)
 
 
 def build_bvh_batched(soups) -> Bvh:

@@ -371,13 +371,15 @@ __global__ void k_round_setup(Ctl *c, unsigned long long act_base, unsigned long
     c->c_next = 0;
 }
 
-__device__ void pair_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int p) {
+// linked: pairs 2k and 2k + 1 share their lower bound (two-sided distance)
+__device__ void pair_init(PairConst *pc, PairVar *pv, const BvhPair *__restrict__ bp, int p, int linked = 0) {
     PairConst c;
     memset(&c, 0, sizeof(c));
     PairVar d;
     memset(&d, 0, sizeof(d));
     for (int k = 0; k < 3; ++k) c.ctr[k] = bp[p].ctr[k];
     c.root = bp[p].root;
+    c.link = linked ? (p ^ 1) : p;
     d.Lord = d2ord(0.0);
     d.Uord = d2ord(0.0);
     d.Urounds = d2ord(0.0);
@@ -414,12 +416,12 @@ __global__ void k_pairs_init(PairConst *pc, PairVar *pv, const BvhPair *__restri
 // the start of a call: control block, pair tables, referenced-vertex marks
 __global__ void k_bound_init(Ctl *ctl, PairConst *pc, PairVar *pv, PairBox *pb, int astride,
                              const BvhPair *__restrict__ bp, int npairs, int32_t *__restrict__ ref, int64_t m,
-                             int log_rounds) {
+                             int log_rounds, int linked) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ctl_zero(ctl);
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x == 0) ctl->log_rounds = log_rounds;
-    if (i < npairs) pair_init(pc, pv, bp, (int)i);
+    if (i < npairs) pair_init(pc, pv, bp, (int)i, linked);
     pbox_init(pb, npairs, astride, i);
     if (i < m) ref[i] = 0;
 }
@@ -479,30 +481,42 @@ __device__ Margins make_margins(double u, double edge_max, double coord_max) {
     return m;
 }
 
-// pair p's dA, eps * dA and margins, once the ingest has its bbox and
-// coordinate range
-__device__ void pair_post(PairConst *pc, const PairBox *pb, int astride, const BvhPair *__restrict__ bp, int p,
-                          const double *__restrict__ eps, int eps_per_pair, int eps_rel) {
-    // fold the copies
-    unsigned long long b[6], cmo = 0;
+// diagonal of the box of pair p's referenced A vertices (folding the copies)
+__device__ double pair_diag(const PairBox *pb, int astride, int p) {
+    unsigned long long b[6];
     for (int k = 0; k < 6; ++k) b[k] = pb[p].bbox[k];
-    for (int c = 0; c < ACC_COPIES; ++c) {
+    for (int c = 1; c < ACC_COPIES; ++c) {
         const PairBox &x = pb[(int64_t)c * astride + p];
         for (int k = 0; k < 3; ++k) {
             b[k] = x.bbox[k] < b[k] ? x.bbox[k] : b[k];
             b[3 + k] = x.bbox[3 + k] > b[3 + k] ? x.bbox[3 + k] : b[3 + k];
         }
-        cmo = x.coord_max > cmo ? x.coord_max : cmo;
     }
     double d2 = 0;
     for (int k = 0; k < 3; ++k) {
-        double e = ord2d(b[3 + k]) - ord2d(b[k]);
+        const double e = ord2d(b[3 + k]) - ord2d(b[k]);
         d2 += e * e;
     }
-    double dA = sqrt(d2);
+    return sqrt(d2);
+}
+
+// pair p's dA, eps * dA and margins, once the ingest has its bbox and
+// coordinate range
+__device__ void pair_post(PairConst *pc, const PairBox *pb, int astride, const BvhPair *__restrict__ bp, int p,
+                          const double *__restrict__ eps, int eps_per_pair, int eps_rel) {
+    // fold the copies of the coordinate range
+    unsigned long long cmo = 0;
+    for (int c = 0; c < ACC_COPIES; ++c) {
+        const unsigned long long x = pb[(int64_t)c * astride + p].coord_max;
+        cmo = x > cmo ? x : cmo;
+    }
+    const double dA = pair_diag(pb, astride, p);
     pc[p].dA = dA;
-    // the tolerance: absolute, or the paper's relative form (times dA)
-    pc[p].eps_abs = eps[eps_per_pair ? p : 0] * (eps_rel ? dA : 1.0);
+    // the tolerance: absolute, or the paper's relative form (times dA; two
+    // linked pairs take the larger diagonal, so that both use one tolerance)
+    const int q = pc[p].link;
+    const double scale = q == p ? dA : fmax(dA, pair_diag(pb, astride, q));
+    pc[p].eps_abs = eps[eps_per_pair ? p : 0] * (eps_rel ? scale : 1.0);
     double cm = fmax(ord2d(cmo), bp[p].coord_max);
     pc[p].m32 = make_margins(Prec<float>::u, bp[p].edge_max, cm);
     pc[p].m64 = make_margins(Prec<double>::u, bp[p].edge_max, cm);
@@ -993,7 +1007,7 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
             // to the depth limit).
             if (lc.check_fp32 && (threadIdx.x & 3) == 0) {
                 const PairConst &C = lc.pc[p];
-                if (C.eps_abs <= C.m32.mu_d * ord2d(pv[p].Lord) + C.m32.mu_0) ctl->bad = 5;
+                if (C.eps_abs <= C.m32.mu_d * pair_L(lc.pc, pv, p) + C.m32.mu_0) ctl->bad = 5;
             }
         }
     }
@@ -1077,7 +1091,7 @@ HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double 
                  int *unsound) {
     const Tri<T> t = make_tri(cn);
     const PairConst &P = cc.pc[pair];
-    const double L = ord2d(cc.pv[pair].Lord);
+    const double L = pair_L(cc.pc, cc.pv, pair);
     const double mu = tri_margin(t, margins_of<T>(P));
     if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) {
         *decider = 0;
@@ -1116,7 +1130,7 @@ HD_D int stage_b(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, const B
                  int best_k, double *carry, int *decider, int *evals, int *unsound) {
     const Tri<T> t = make_tri(cn);
     const PairConst &P = cc.pc[pair];
-    const double L = ord2d(cc.pv[pair].Lord);
+    const double L = pair_L(cc.pc, cc.pv, pair);
     const double mu = tri_margin(t, margins_of<T>(P));
     int i3 = 0;
     while (cc.c.order[i3] != 3) ++i3;
@@ -1430,7 +1444,7 @@ __device__ void stage_c_records(const FrontierView<T> &in, const ClassifyCfg &cc
             int I[3] = {cn[0].I, cn[1].I, cn[2].I};
             double u64 = rebound64(cc.a, pair, face, lvl, ba, bb, I, cc.bv64, cc.iv, cc.c, P.m64, &evals);
             ub = hmin((double)in.ub()[j], u64);
-            list = decide(ub, ord2d(cc.pv[pair].Lord), P.eps_abs, 0.0, false);
+            list = decide(ub, pair_L(cc.pc, cc.pv, pair), P.eps_abs, 0.0, false);
         }
         int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
         if (valid) write_to(dst, list, slot, cn, round_up_to_float(ub), face, lvl, pair);
@@ -1545,7 +1559,7 @@ __global__ __launch_bounds__(BLK) void k_score(FrontierView<T> fr, int64_t from,
     if (valid) {
         t = record_tri(fr, j);
         const int pair = fr.pair()[j];
-        L = ord2d(lc.pv[pair].Lord);
+        L = pair_L(lc.pc, lc.pv, pair);
         dA = lc.pc[pair].dA;
     }
     const float y = score_block(S, valid, t, L, dA, bv, lc.iv);
@@ -1585,7 +1599,7 @@ __global__ void k_log_parents(FrontierView<T> fr, int64_t n, QueryOut<T> lq, Lea
         return;
     }
     float f[16];
-    tri_features(t, ord2d(lc.pv[pair].Lord), lc.pc[pair].dA, bv, lc.iv, f);
+    tri_features(t, pair_L(lc.pc, lc.pv, pair), lc.pc[pair].dA, bv, lc.iv, f);
     const T dmax = hmax(t.d[0], hmax(t.d[1], t.d[2]));
     T h = dmax;
     for (int k = 0; k < LATTICE_PTS; ++k) h = hmax(h, lq.d[j * LATTICE_PTS + k]);
@@ -1620,7 +1634,7 @@ __global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, Cla
             pair = in.pair()[j];
             face = in.face()[j];
             lvl = in.lvl()[j] & 0xff;
-            L = ord2d(cc.pv[pair].Lord);
+            L = pair_L(cc.pc, cc.pv, pair);
             dA = lc.pc[pair].dA;
             t = make_tri(cn);
         }
@@ -1738,7 +1752,7 @@ template <class T> HD_D uint32_t sel_key(const FrontierView<T> &f, int64_t j, in
 // is below L), 2 park it (its bound is within eps of L)
 template <class T> HD_D int sel_fate(const FrontierView<T> &f, int64_t j, const PairConst *pc, const PairVar *pv) {
     const int pair = f.pair()[j];
-    const double ub = (double)f.ub()[j], L = ord2d(pv[pair].Lord);
+    const double ub = (double)f.ub()[j], L = pair_L(pc, pv, pair);
     if (ub < L) return 1;
     return ub - L <= park_limit(pc[pair].eps_abs) ? 2 : 0;
 }
@@ -1819,7 +1833,7 @@ __device__ void sel_histogram(const FrontierView<T> &act, int64_t n, int learned
             if (learned) {
                 const float sc = act.score()[j];
                 const int pair = act.pair()[j];
-                if (sc == sc && (double)sc > ord2d(pv[pair].Lord) + pc[pair].eps_abs) atomicAdd(&prom, 1u);
+                if (sc == sc && (double)sc > pair_L(pc, pv, pair) + pc[pair].eps_abs) atomicAdd(&prom, 1u);
             }
         } else if ((key >> 20) == b1) {
             atomicAdd(&h[(key >> 8) & (SEL_BINS - 1)], 1u);
@@ -2022,7 +2036,7 @@ __global__ __launch_bounds__(BLK) void k_score_new(FrontierView<T> fr, const Ctl
         if (valid) {
             t = record_tri(fr, j);
             const int pair = fr.pair()[j];
-            L = ord2d(lc.pv[pair].Lord);
+            L = pair_L(lc.pc, lc.pv, pair);
             dA = lc.pc[pair].dA;
         }
         const float y = score_block(S, valid, t, L, dA, bv, lc.iv);
@@ -2424,6 +2438,7 @@ struct Input {
     const int64_t *nA;
     const double *eps; // host: one value, or npairs values
     int eps_per_pair;
+    int linked; // pairs 2k and 2k + 1 share their lower bound (the two directions of H)
 };
 
 // ---------------------------------------------------------------------------
@@ -2435,6 +2450,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     auto t0 = std::chrono::steady_clock::now();
     const int np = in.npairs;
     if (np != B->npairs) throw Error{HD_E_INVALID, "pair count differs from the BVH's"};
+    if (in.linked && (np % 2) != 0) throw Error{HD_E_INVALID, "linked pairs come in twos"};
     hd_stats S;
     std::memset(&S, 0, sizeof(S));
     CascadeCtx cctx;
@@ -2548,7 +2564,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     ws.pbox.reserve((size_t)ACC_COPIES * pstride * sizeof(PairBox));
     PairBox *pbox = ws.pbox.as<PairBox>();
     k_bound_init<<<grid_for(std::max<int64_t>(mA, (int64_t)np * ACC_COPIES), BLK), BLK, 0, s>>>(
-        ctl, pc, pv, pbox, pstride, B->pairs.as<BvhPair>(), np, ref, mA, logging ? 1 : 0);
+        ctl, pc, pv, pbox, pstride, B->pairs.as<BvhPair>(), np, ref, mA, logging ? 1 : 0, in.linked);
     k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
                                               ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pbox, pstride,
                                               ctl);
@@ -3134,11 +3150,13 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     if (status == HD_OK && hc.bad) status = status_of_bad(hc.bad);
     if (status == HD_OK) {
         for (int p = 0; p < np; ++p) {
-            double L = ord2d(hp[p].Lord);
-            double U = std::max(L, ord2d(hp[p].Uord));
+            // a pair's own lower bound, and the (shared) one its decisions used
+            const double L = ord2d(hp[p].Lord);
+            const double Ld = std::max(L, ord2d(hp[hc_[p].link].Lord));
+            const double U = std::max(Ld, ord2d(hp[p].Uord));
             LU[2 * p] = L;
             LU[2 * p + 1] = U;
-            if (nAct == 0 && U - L > hc_[p].eps_abs) status = HD_E_INTERNAL;
+            if (nAct == 0 && U - Ld > hc_[p].eps_abs) status = HD_E_INTERNAL;
         }
         if (nAct > 0 && opt.max_rounds <= 0) status = HD_E_INTERNAL;
     }
@@ -3349,6 +3367,46 @@ hd_status hd_bound_batched(int32_t npairs, const double *const *VA, const int64_
     if (npairs <= 0 || !LU_out || !Bh || !VA || !mA || !FA || !nA || !eps) return HD_E_INVALID;
     Input in{npairs, VA, mA, FA, nA, eps, eps_per_pair ? 1 : 0};
     hd_status st = bound_any(in, Bh, opt, stream, LU_out, stats);
+    if (stats) stats->status = st;
+    return st;
+}
+
+hd_status hd_hausdorff(const double *VA, int64_t mA, const int32_t *FA, int64_t nA, const double *VB, int64_t mB,
+                       const int32_t *FB, int64_t nB, double eps, const hd_options *opt, hd_stream_t stream,
+                       double LU_out[2], double LU_dir[4], hd_stats *stats) {
+    if (LU_out) LU_out[0] = LU_out[1] = NAN;
+    if (LU_dir)
+        for (int k = 0; k < 4; ++k) LU_dir[k] = NAN;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->status = HD_E_INVALID;
+    }
+    if (!LU_out || !VA || !FA || !VB || !FB || mA <= 0 || nA <= 0 || mB <= 0 || nB <= 0) return HD_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    hd_status st = guard([&] {
+        // one BVH over both soups: pair 0 queries B (for h(A,B)), pair 1 queries A (for h(B,A))
+        const double *Vt[2] = {VB, VA};
+        const int32_t *Ft[2] = {FB, FA};
+        const int64_t mt[2] = {mB, mA}, nt[2] = {nB, nA};
+        Bvh *b = build_bvh(2, Vt, mt, Ft, nt, s);
+        struct Release {
+            Bvh *b;
+            ~Release() { recycle_bvh(b); }
+        } release{b};
+        const double *Vs[2] = {VA, VB};
+        const int32_t *Fs[2] = {FA, FB};
+        const int64_t ms[2] = {mA, mB}, ns[2] = {nA, nB};
+        Input in{2, Vs, ms, Fs, ns, &eps, 0, 1};
+        double lu[4];
+        const hd_status r = bound_any(in, reinterpret_cast<hd_bvh>(b), opt, stream, lu, stats);
+        if (r != HD_OK) return r;
+        // H = max(h(A,B), h(B,A)): the larger lower bound, the larger upper bound
+        LU_out[0] = std::max(lu[0], lu[2]);
+        LU_out[1] = std::max(lu[1], lu[3]);
+        if (LU_dir)
+            for (int k = 0; k < 4; ++k) LU_dir[k] = lu[k];
+        return HD_OK;
+    });
     if (stats) stats->status = st;
     return st;
 }

@@ -28,7 +28,7 @@ struct Margins {
 struct PairConst {
     double ctr[3];  // centre subtracted from every coordinate of the pair
     int32_t root;   // BVH subtree root (>= 0 node, < 0 leaf ~root)
-    int32_t pad;
+    int32_t link;   // the pair whose lower bound this pair shares (itself unless linked)
     double eps_abs, dA;
     Margins m32, m64;
 };
@@ -44,6 +44,14 @@ struct alignas(128) PairVar {
     double L64;
     unsigned long long Uround;    // ordered double: largest live bound after a round (round log)
 };
+
+// The lower bound pair p's decisions use: its own, or, for two linked pairs
+// (the two directions of a two-sided distance), the larger of the two. A
+// triangle bounded below it cannot raise the maximum of the two distances.
+HD_D double pair_L(const PairConst *pc, const PairVar *pv, int p) {
+    const unsigned long long a = pv[p].Lord, b = pv[pc[p].link].Lord;
+    return ord2d(a > b ? a : b);
+}
 
 // ---------------------------------------------------------------------------
 // Frontier records (structure of arrays; one slot per triangle).

@@ -520,3 +520,55 @@ def test_invalid_inputs(bad):
         FA = FA[:0]
     r = oracle.bound(VA, FA, V, F, eps)
     assert r["status"] == oracle.HDO_E_INVALID
+
+
+# ----------------------------------------------------------------------------
+# the two-sided distance H(A,B) = max{h(A,B), h(B,A)} (Conclusion and future
+# work): the oracle takes the larger of two one-sided runs
+# ----------------------------------------------------------------------------
+
+def test_two_sided_closed_form_and_symmetry():
+    """A = T, B = T and a copy of T moved by t: h(A,B) = 0 (A lies in B); the
+    far copy's points are at most max over its vertices from T (the distance
+    to a convex set is convex, so its maximum over a triangle is at a vertex),
+    and exactly |t| when t is along T's normal. H is symmetric."""
+    rng = np.random.default_rng(41)
+    for along_normal in (True, False):
+        v = rng.normal(size=(3, 3))
+        t = _tri_normal(v) * 0.8 if along_normal else rng.normal(size=3)
+        VA, FA = v, np.array([[0, 1, 2]], np.int32)
+        VB = np.concatenate([v, v + t])
+        FB = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+        if along_normal:
+            H = 0.8
+        else:
+            H = max(math.sqrt(oracle.closest_point(x, *v)[0]) for x in v + t)
+        for a, b in (((VA, FA), (VB, FB)), ((VB, FB), (VA, FA))):
+            r = oracle.hausdorff(*a, *b, 1e-7)
+            assert r["status"] == 0
+            assert r["L"] - 1e-12 <= H <= r["U"] + 1e-12 and r["U"] - r["L"] <= 1e-7
+        r = oracle.hausdorff(VA, FA, VB, FB, 1e-7)
+        assert r["ab"]["U"] <= 1e-7 and r["ab"]["L"] <= 1e-12  # A lies in B
+
+
+def test_two_sided_brackets_dense_sampling():
+    """Tiny random soups: the larger of the two sampled one-sided maxima lies
+    in [L - r_cov, U] (r_cov: the sampling's covering radius)."""
+    rng = np.random.default_rng(42)
+    for _ in range(3):
+        VA = rng.normal(size=(6, 3))
+        FA = np.array([[0, 1, 2], [3, 4, 5], [0, 3, 5]], np.int32)
+        VB = rng.normal(size=(6, 3)) + 0.3
+        FB = np.array([[0, 1, 2], [1, 2, 3], [3, 4, 5]], np.int32)
+        r = oracle.hausdorff(VA, FA, VB, FB, 1e-4)
+        n = 40
+        best, rcov = 0.0, 0.0
+        for (V, F), (W, G) in (((VA, FA), (VB, FB)), ((VB, FB), (VA, FA))):
+            for f in F:
+                P = tri_points(V[f], n)
+                d = np.min([[math.sqrt(oracle.closest_point(p, *W[g])[0]) for g in G] for p in P], 1)
+                best = max(best, d.max())
+                e = max(np.linalg.norm(V[f[i]] - V[f[(i + 1) % 3]]) for i in range(3))
+                rcov = max(rcov, e / n)
+        assert best <= r["U"] + 1e-12
+        assert r["L"] <= best + rcov
