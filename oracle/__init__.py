@@ -7,5 +7,5 @@ single-threaded); this module compiles it with gcc and marshals arguments.
 `oracle.mlp` is the FP64 numpy oracle of the learned proposal's network and
 features (forward, backward, Adam).
 """
-from .hdo import (build, closest_point, point_soup, points_soup, Tree, bounds, bound, hausdorff,  # noqa: F401
+from .hdo import (build, closest_point, point_soup, points_soup, Tree, bounds, bound, bound_u5, hausdorff,  # noqa: F401
                   HDO_OK, HDO_E_INVALID, HDO_E_CAPACITY, HDO_E_NOMEM, HDO_E_INTERNAL)

@@ -329,6 +329,8 @@ typedef struct {
     const int32_t *FB;
     int64_t nB;
     int64_t *evals;
+    hdo_tree tree;     /* for the point queries a bound makes (NULL: brute force) */
+    int64_t *queries;  /* counter of those queries (may be NULL) */
 } soupref;
 
 /* distance from x to one triangle S of B */
@@ -555,12 +557,46 @@ static double bound_u4(const otri *T) {
     return min2(h_tri_two_points(T, q1, q2), h_tri_two_points(T, q1, q3));
 }
 
+/* The bound of Zheng et al. that the paper quotes in its fourth-bound
+ * subsection: min over S in {S1, S2, S3, S_b} of h(T, S), where S_b is the
+ * triangle of B closest to the barycenter b of T (one more point query), and
+ * h(T, S), the distance from the triangle T to the triangle S, is the largest
+ * distance of a vertex of T to S (the distance to a convex set is a convex
+ * function, so its maximum over T is reached at a vertex). *Sb_out (may be
+ * NULL) receives S_b. */
+static double bound_u5(const otri *T, const soupref *B, int32_t *Sb_out) {
+    double b[3], qb[3];
+    for (int k = 0; k < 3; ++k) b[k] = (T->v[0][k] + T->v[1][k] + T->v[2][k]) / 3.0;
+    int32_t Sb = -1;
+    if (B->queries) (*B->queries)++;
+    if (B->tree) {
+        hdo_tree_query(B->tree, b, &Sb, qb, B->evals);
+    } else {
+        *B->evals += B->nB;
+        hdo_point_soup(b, B->VB, B->FB, B->nB, &Sb, qb);
+    }
+    if (Sb_out) *Sb_out = Sb;
+    const int32_t S[4] = {T->I[0], T->I[1], T->I[2], Sb};
+    double best = INFINITY;
+    for (int i = 0; i < 4; ++i) {
+        double h = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            /* vertex i's distance to its own closest triangle is known */
+            const double dj = (i < 3 && j == i) ? T->d[i] : dist_to_face(B, T->v[j], S[i]);
+            h = max2(h, dj);
+        }
+        best = min2(best, h);
+    }
+    return best;
+}
+
 static double bound_k(int k, const otri *T, const soupref *B) {
     switch (k) {
     case 1: return bound_u1(T);
     case 2: return bound_u2(T);
     case 3: return bound_u3(T, B, NULL);
     case 4: return bound_u4(T);
+    case 5: return bound_u5(T, B, NULL);
     }
     return INFINITY;
 }
@@ -578,12 +614,28 @@ void hdo_bounds(const double v[9], const double d[3], const int32_t I[3], const 
         T.I[i] = I[i];
     }
     int64_t evals = 0;
-    soupref B = {VB, FB, nB, &evals};
+    soupref B = {VB, FB, nB, &evals, NULL, NULL};
     out[0] = (I[0] == I[1] && I[1] == I[2]) ? bound_uexact(&T) : NAN;
     out[1] = bound_u1(&T);
     out[2] = bound_u2(&T);
     out[3] = bound_u3(&T, &B, u3_case);
     out[4] = bound_u4(&T);
+}
+
+double hdo_bound_u5(const double v[9], const double d[3], const int32_t I[3], const double *VB,
+                    const int32_t *FB, int64_t nB, int32_t *Sb) {
+    otri T;
+    for (int i = 0; i < 3; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            T.v[i][k] = v[3 * i + k];
+            T.q[i][k] = 0.0;
+        }
+        T.d[i] = d[i];
+        T.I[i] = I[i];
+    }
+    int64_t evals = 0;
+    soupref B = {VB, FB, nB, &evals, NULL, NULL};
+    return bound_u5(&T, &B, Sb);
 }
 
 /* UpperBound: the exact bound when all closest points share a triangle of B;
@@ -763,12 +815,12 @@ int32_t hdo_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA,
         norder = 4;
     }
     /* validation */
-    if (!(eps_rel > 0.0) || nA <= 0 || nB <= 0 || mA <= 0 || mB <= 0 || norder > 4) {
+    if (!(eps_rel > 0.0) || nA <= 0 || nB <= 0 || mA <= 0 || mB <= 0 || norder > 5) {
         res->status = HDO_E_INVALID;
         return res->status;
     }
     for (int i = 0; i < norder; ++i)
-        if (order[i] < 1 || order[i] > 4) { res->status = HDO_E_INVALID; return res->status; }
+        if (order[i] < 1 || order[i] > 5) { res->status = HDO_E_INVALID; return res->status; }
     for (int64_t i = 0; i < 3 * nA; ++i)
         if (FA[i] < 0 || FA[i] >= mA) { res->status = HDO_E_INVALID; return res->status; }
     for (int64_t i = 0; i < 3 * nB; ++i)
@@ -800,7 +852,7 @@ int32_t hdo_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA,
 
     qctx qc = {VB, FB, nB, NULL, res};
     if (backend == 1) qc.tree = hdo_tree_build(VB, mB, FB, nB);
-    soupref B = {VB, FB, nB, &res->evals};
+    soupref B = {VB, FB, nB, &res->evals, qc.tree, &res->queries};
 
     /* distances of all referenced vertices; the initial lower bound */
     double *DA = (double *)malloc((size_t)mA * sizeof(double));

@@ -21,7 +21,7 @@ extern "C" {
 enum { HDO_OK = 0, HDO_E_INVALID = 1, HDO_E_CAPACITY = 2, HDO_E_NOMEM = 3, HDO_E_INTERNAL = 5 };
 
 /* Bound identifiers used in the order array and the discard counters. */
-enum { HDO_UEXACT = 0, HDO_U1 = 1, HDO_U2 = 2, HDO_U3 = 3, HDO_U4 = 4 };
+enum { HDO_UEXACT = 0, HDO_U1 = 1, HDO_U2 = 2, HDO_U3 = 3, HDO_U4 = 4, HDO_U5 = 5 /* Zheng et al. */ };
 
 typedef struct {
     double L, U;             /* certified interval, L <= h(A,B) <= U */
@@ -33,7 +33,7 @@ typedef struct {
     int64_t evals;           /* point-triangle closest-point evaluations */
     int64_t pushes;          /* triangles pushed into the priority queue */
     int64_t stale;           /* popped triangles already below the lower bound */
-    int64_t discards[5];     /* triangles discarded by uexact, u1, u2, u3, u4 */
+    int64_t discards[6];     /* triangles discarded by uexact, u1, u2, u3, u4, u5 */
     int64_t max_queue;       /* peak priority-queue length */
     int32_t status;          /* HDO_* */
     int32_t empty_queue;     /* 1 if the queue emptied before the tolerance held */
@@ -68,10 +68,19 @@ void hdo_bounds(const double v[9], const double d[3], const int32_t I[3], const 
                 const double *VB, const int32_t *FB, int64_t nB, double out[5],
                 int32_t *u3_case);
 
+/* The bound of Zheng et al. quoted in the paper's fourth-bound subsection,
+ * min over S in {S1, S2, S3, S_b} of the largest vertex distance of T to S,
+ * S_b the triangle of B closest to T's barycenter (found by brute force here;
+ * written to *Sb). */
+double hdo_bound_u5(const double v[9], const double d[3], const int32_t I[3], const double *VB,
+                    const int32_t *FB, int64_t nB, int32_t *Sb);
+
 /* The branch-and-bound. eps_rel is the paper's epsilon (relative to dA);
  * budget_m is the paper's m (the queue may process at most m * nA faces);
- * order lists the bounds to try (values 1..4), norder of them; backend 0 =
- * brute force, 1 = AABB tree. Returns the status, also stored in res. */
+ * order lists the bounds to try (values 1..4, and 5 for the bound of Zheng
+ * et al., which makes one point query per evaluation), norder of them;
+ * backend 0 = brute force, 1 = AABB tree. Returns the status, also stored in
+ * res. */
 int32_t hdo_bound(const double *VA, int64_t mA, const int32_t *FA, int64_t nA,
                   const double *VB, int64_t mB, const int32_t *FB, int64_t nB,
                   double eps_rel, double budget_m, const int32_t *order, int32_t norder,

@@ -36,7 +36,7 @@ class _Result(C.Structure):
         ("L", C.c_double), ("U", C.c_double), ("dA", C.c_double), ("eps_abs", C.c_double),
         ("subdivided", C.c_int64), ("bounded", C.c_int64), ("queries", C.c_int64),
         ("evals", C.c_int64), ("pushes", C.c_int64), ("stale", C.c_int64),
-        ("discards", C.c_int64 * 5), ("max_queue", C.c_int64), ("status", C.c_int32),
+        ("discards", C.c_int64 * 6), ("max_queue", C.c_int64), ("status", C.c_int32),
         ("empty_queue", C.c_int32), ("argmax", C.c_double * 3),
     ]
 
@@ -62,6 +62,8 @@ def _load():
             lib.hdo_tree_query.argtypes = [C.c_void_p, dp, ip, dp, C.POINTER(C.c_int64)]
             lib.hdo_tree_free.restype = None
             lib.hdo_tree_free.argtypes = [C.c_void_p]
+            lib.hdo_bound_u5.restype = C.c_double
+            lib.hdo_bound_u5.argtypes = [dp, dp, ip, dp, ip, C.c_int64, ip]
             lib.hdo_bounds.restype = None
             lib.hdo_bounds.argtypes = [dp, dp, ip, dp, dp, ip, C.c_int64, dp, ip]
             lib.hdo_set_threads.restype = None
@@ -153,6 +155,20 @@ def bounds(v, d, I, q, VB, FB):
     case = C.c_int32(0)
     lib.hdo_bounds(vp, dp, Ip, qp, Vp, Fp, F_.shape[0], op, C.byref(case))
     return out, case.value
+
+
+def bound_u5(v, d, I, VB, FB):
+    """The bound of Zheng et al. (quoted in the paper's fourth-bound
+    subsection) of one triangle, and the closest B triangle of its barycenter."""
+    lib = _load()
+    v_, vp = _d(np.asarray(v).reshape(9))
+    d_, dp = _d(d)
+    I_, Ip = _i(I)
+    V_, Vp = _d(VB)
+    F_, Fp = _i(FB)
+    Sb = C.c_int32(-1)
+    u = lib.hdo_bound_u5(vp, dp, Ip, Vp, Fp, F_.shape[0], C.byref(Sb))
+    return u, Sb.value
 
 
 def bound(VA, FA, VB, FB, eps_rel, m=1e7, order=(1, 2, 3, 4), backend="brute", threads=1):

@@ -572,3 +572,103 @@ def test_two_sided_brackets_dense_sampling():
                 rcov = max(rcov, e / n)
         assert best <= r["U"] + 1e-12
         assert r["L"] <= best + rcov
+
+
+# ----------------------------------------------------------------------------
+# the bound of Zheng et al. quoted in the fourth-bound subsection (order
+# digit 5): min over S in {S1, S2, S3, S_b} of the largest vertex distance to S
+# ----------------------------------------------------------------------------
+
+def _zheng_scene():
+    """T at height 1 over three tiny triangles 0.1 below its vertices and a
+    large triangle 0.5 below covering all of it: each vertex's closest
+    triangle is its tiny one (0.1), the barycenter's is the large one (0.5,
+    against about 1.7 to the tiny ones), and every vertex is 0.5 above the
+    large one, so the bound is exactly 0.5 (the three tiny triangles give
+    about 3.9: each is far from the other two vertices)."""
+    v = np.array([[0, 0, 1], [4, 0, 1], [0, 4, 1]], float)
+    tiny = np.array([[-0.1, -0.1, 0], [0.1, -0.1, 0], [0.0, 0.1, 0]])
+    VB = np.concatenate([tiny + [0, 0, 0.9], tiny + [4, 0, 0.9], tiny + [0, 4, 0.9],
+                         [[-1, -1, 0.5], [7, -1, 0.5], [-1, 7, 0.5]]])
+    FB = np.arange(12, dtype=np.int32).reshape(4, 3)
+    return v, VB, FB
+
+
+def test_zheng_bound_worked_example():
+    v, VB, FB = _zheng_scene()
+    res = [oracle.point_soup(x, VB, FB) for x in v]
+    assert [r[1] for r in res] == [0, 1, 2] and all(abs(r[0] - 0.1) < 1e-12 for r in res)
+    u5, Sb = oracle.bound_u5(v, [r[0] for r in res], np.array([r[1] for r in res], np.int32), VB, FB)
+    assert Sb == 3
+    assert u5 == pytest.approx(0.5, abs=1e-12)
+    # the other bounds are far looser here (u4 uses the three footpoints)
+    out, _ = oracle.bounds(v, [r[0] for r in res], np.array([r[1] for r in res], np.int32),
+                           np.array([r[2] for r in res]), VB, FB)
+    assert min(out[1:]) > 1.0
+    # and the branch and bound with it alone finishes at once: h = 0.5 at b
+    VA, FA = v, np.array([[0, 1, 2]], np.int32)
+    r = oracle.bound(VA, FA, VB, FB, 1e-3, order=(5,))
+    assert r["status"] == 0 and r["L"] <= 0.5 + 1e-12 and r["U"] - r["L"] <= r["eps_abs"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_zheng_bound_is_valid_and_below_its_own_terms(seed):
+    """For random triangles against random soups: the bound is at least the
+    densely sampled maximum of d(p, B) over T, and at most the largest vertex
+    distance to each of S1, S2, S3 and S_b (computed here from the closest
+    point routine, with S_b found by brute force over B)."""
+    rng = np.random.default_rng(500 + seed)
+    VB = rng.normal(size=(30, 3))
+    FB = rng.integers(0, 30, size=(12, 3)).astype(np.int32)
+    for _ in range(40):
+        v = np.array(random_triangle(rng, scale=rng.choice([0.2, 1.0])))
+        res = [oracle.point_soup(x, VB, FB) for x in v]
+        d = np.array([r[0] for r in res])
+        I = np.array([r[1] for r in res], np.int32)
+        u5, Sb = oracle.bound_u5(v, d, I, VB, FB)
+        b = v.mean(0)
+        db = [math.sqrt(oracle.closest_point(b, *VB[f])[0]) for f in FB]
+        assert db[Sb] == pytest.approx(min(db), abs=1e-12)
+        terms = [max(math.sqrt(oracle.closest_point(x, *VB[FB[S]])[0]) for x in v) for S in (*I, Sb)]
+        assert u5 == pytest.approx(min(terms), rel=1e-12, abs=1e-12)
+        P = tri_points(v, 24)
+        sampled = max(min(math.sqrt(oracle.closest_point(p, *VB[f])[0]) for f in FB) for p in P)
+        assert sampled <= u5 + 1e-12
+
+
+def test_cascade_order_invariance_with_the_fifth_bound():
+    """With L fixed during a bound pass the decision is min(bounds) < L, so
+    every order of the same set of bounds gives the same run."""
+    W = wl.config(2, scale=0.05)
+    base = None
+    for order in [(1, 2, 3, 4, 5), (5, 4, 3, 2, 1), (2, 5, 1, 4, 3), (3, 1, 5, 2, 4)]:
+        r = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, order=order, backend="tree")
+        assert r["status"] == 0
+        key = (r["L"], r["U"], r["subdivided"], r["bounded"], sum(r["discards"]))
+        base = base or key
+        assert key == base, order
+    r4 = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, order=(1, 2, 3, 4), backend="tree")
+    # a fifth bound can only discard more: never more subdivisions
+    assert base[2] <= r4["subdivided"] and abs(base[0] - r4["L"]) <= r4["eps_abs"]
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_single_bound_orders_are_certified(seed):
+    """Each bound alone (the single-bound variant the paper's conclusion
+    suggests for a GPU) still brackets the densely sampled maximum."""
+    rng = np.random.default_rng(600 + seed)
+    VA = rng.normal(size=(8, 3))
+    FA = np.array([[0, 1, 2], [2, 3, 4], [4, 5, 6], [1, 6, 7]], np.int32)
+    VB = rng.normal(size=(9, 3)) * 1.2
+    FB = np.array([[0, 1, 2], [3, 4, 5], [6, 7, 8], [0, 4, 8]], np.int32)
+    n = 40
+    best, rcov = 0.0, 0.0
+    for f in FA:
+        P = tri_points(VA[f], n)
+        d = max(min(math.sqrt(oracle.closest_point(p, *VB[g])[0]) for g in FB) for p in P)
+        best = max(best, d)
+        rcov = max(rcov, max(np.linalg.norm(VA[f[i]] - VA[f[(i + 1) % 3]]) for i in range(3)) / n)
+    for order in [(1,), (2,), (3,), (4,), (5,)]:
+        r = oracle.bound(VA, FA, VB, FB, 1e-4, order=order)
+        assert r["status"] == 0, order
+        assert best <= r["U"] + 1e-12 and r["L"] <= best + rcov, order
