@@ -507,11 +507,13 @@ def eps_curve_main(a, hd, torch, wl):
 def order_study_main(a, hd, torch, wl):
     """Every cascade order: the 24 orders of the four bounds and all 40
     ordered proper subsets (64 in all), on C2, C3 and C4 (the paper's bound
-    order benchmark, and its question whether fewer bounds suit a GPU)."""
+    order benchmark, and its question whether fewer bounds suit a GPU), plus
+    the bound of Zheng et al. (5) alone, before and after the four."""
     import itertools
     orders = []
     for r in (1, 2, 3, 4):
         orders += [int("".join(map(str, p))) for p in itertools.permutations((1, 2, 3, 4), r)]
+    orders += [5, 12345, 51234, 1245]
     rows = []
     for cfg in (2, 3, 4):
         if cfg == 4:

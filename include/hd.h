@@ -53,7 +53,11 @@ typedef struct hd_bvh_s *hd_bvh; /* opaque; owns library-allocated device memory
 typedef struct {
     int32_t precision;   /* HD_PREC_*; default HD_PREC_FP32_RECHECK */
     int32_t order;       /* cascade order as decimal digits, e.g. 1234 (default) or 2314;
-                            any non-empty subset of {1,2,3,4} without repeats */
+                            any non-empty subset of {1,2,3,4,5} without repeats. 5 is the bound
+                            of Zheng et al. that the paper quotes in its fourth-bound subsection
+                            (min over the vertices' and the barycenter's closest B triangles of
+                            the largest vertex distance to it); it costs one point query per
+                            triangle that reaches it. A single digit is a single-bound cascade. */
     double budget_m;     /* the paper's m: at most m * nA faces may be processed (Implementation
                             section); <= 0 means 1e7 */
     int64_t capacity;    /* frontier capacity in triangles; 0 = automatic */
@@ -156,6 +160,7 @@ typedef struct {
     int32_t pad1;
     int64_t stale;             /* sub-batches: active triangles dropped before being split because
                                   L had risen above their bound (the paper's stale queue entries) */
+    int64_t discards_u5;       /* triangles discarded by the fifth bound (order digit 5) */
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle
@@ -281,6 +286,15 @@ hd_status hd_point_distances_noalloc(const double *P, int64_t nP, hd_bvh B, int3
  * precision is HD_PREC_FP64 or HD_PREC_FP32. */
 hd_status hd_eval_bounds(const double *v, const double *d, const int32_t *I, const double *q, int64_t n,
                          hd_bvh B, int32_t precision, double *out, int32_t *u3_case, hd_stream_t stream);
+
+/* The fifth bound (order digit 5) of n given triangles, for testing it in
+ * isolation: v (device, n x 9 doubles), d (n x 3 vertex distances), I (n x 3
+ * closest faces of B, original indices); the closest face of each
+ * triangle's barycenter comes from a point query and is written to Sb
+ * (device, n int32, original index), the bound (no margin) to out (device, n
+ * doubles). precision is HD_PREC_FP64 or HD_PREC_FP32. */
+hd_status hd_eval_bound_u5(const double *v, const double *d, const int32_t *I, int64_t n, hd_bvh B,
+                           int32_t precision, double *out, int32_t *Sb, hd_stream_t stream);
 
 /* ---- learned proposal: the network ---------------------------------------
  * Not part of the paper's method. A 16 -> 64 -> 64 -> 1 ReLU network predicts,

@@ -66,7 +66,8 @@ class Stats(C.Structure):
                 ("query_leaf_evals", C.c_int64), ("query_box_tests", C.c_int64),
                 ("logged", C.c_int64), ("learned_skips", C.c_int64), ("query_block", C.c_int32),
                 ("query_stack", C.c_int32), ("query_lanes", C.c_int32), ("query_quad_max", C.c_int32),
-                ("round_records", C.c_int64), ("tuned", C.c_int32), ("pad1", C.c_int32), ("stale", C.c_int64)]
+                ("round_records", C.c_int64), ("tuned", C.c_int32), ("pad1", C.c_int32), ("stale", C.c_int64),
+                ("discards_u5", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad1"}
@@ -77,7 +78,8 @@ class Stats(C.Structure):
 EXPORTS = ["hd_build_bvh", "hd_build_bvh_batched", "hd_free_bvh", "hd_bound", "hd_bound_batched",
            "hd_point_distances", "hd_eval_bounds", "hd_status_str", "hd_default_options",
            "hd_mlp_nparams", "hd_mlp_forward", "hd_mlp_grad", "hd_mlp_train", "hd_frontier_features",
-           "hd_build_graphs", "hd_point_distances_noalloc", "hd_hausdorff"]
+           "hd_build_graphs", "hd_point_distances_noalloc", "hd_hausdorff",
+           "hd_eval_bound_u5"]
 NOALLOC_MAX_POINTS = 65536  # HD_NOALLOC_MAX_POINTS
 
 
@@ -109,6 +111,8 @@ def load_library(path: str | None = None):
                                      i32, C.POINTER(Options), vp, C.POINTER(C.c_double), C.POINTER(Stats)]
     lib.hd_point_distances.restype = i32
     lib.hd_point_distances.argtypes = [vp, i64, vp, i32, i32, vp, vp, vp, vp]
+    lib.hd_eval_bound_u5.restype = i32
+    lib.hd_eval_bound_u5.argtypes = [vp, vp, vp, i64, vp, i32, vp, vp, vp]
     lib.hd_hausdorff.restype = i32
     lib.hd_hausdorff.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64, dbl, C.POINTER(Options), vp,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(Stats)]
@@ -375,6 +379,22 @@ def eval_bounds(v, d, I, q, bvh: Bvh, precision=PREC_FP64):
                             C.c_void_p(case.data_ptr()), _stream())
     _check(st, "hd_eval_bounds")
     return out, case
+
+
+def eval_bound_u5(v, d, I, bvh: Bvh, precision=PREC_FP64):
+    """The fifth bound (Zheng et al.) of n triangles and their barycenters'
+    closest faces of B (original indices)."""
+    torch = _torch()
+    lib = load_library()
+    v = _dev(v, torch.float64).reshape(-1, 9)
+    n = v.shape[0]
+    d = _dev(d, torch.float64).reshape(n, 3)
+    I = _dev(I, torch.int32).reshape(n, 3)
+    out = torch.empty(n, dtype=torch.float64, device=v.device)
+    Sb = torch.empty(n, dtype=torch.int32, device=v.device)
+    _check(lib.hd_eval_bound_u5(_ptr(v), _ptr(d), _ptr(I), n, bvh.handle, precision, _ptr(out), _ptr(Sb), _stream()),
+           "hd_eval_bound_u5")
+    return out, Sb
 
 
 # ---------------------------------------------------------------------------

@@ -62,8 +62,8 @@ enum {
     ST_EVALS,
     ST_BOUNDED,
     ST_RECHECKED,
-    ST_DISCARDS, // five entries, one per deciding bound
-    ST_QUERIES = ST_DISCARDS + 5,
+    ST_DISCARDS, // six entries, one per deciding bound (uexact, u1..u5)
+    ST_QUERIES = ST_DISCARDS + 6,
     ST_BOXES,
     ST_QLEAVES,
     ST_SKIPS, // records whose u3 / u4 the learned policy skipped
@@ -544,7 +544,7 @@ __global__ void k_ingest_post(const int32_t *__restrict__ ref, const int32_t *__
 // ---------------------------------------------------------------------------
 // point queries
 // ---------------------------------------------------------------------------
-enum QMode { Q_POINTS = 0, Q_VERTICES = 1, Q_MIDPOINTS = 2, Q_LATTICE = 3 };
+enum QMode { Q_POINTS = 0, Q_VERTICES = 1, Q_MIDPOINTS = 2, Q_LATTICE = 3, Q_BARYCENTERS = 4 };
 
 // The twelve non-corner points of the resolution-4 barycentric lattice of a
 // triangle (weights (4 - a1 - a2, a1, a2) / 4), two bits per weight.
@@ -599,6 +599,23 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
         q.p = a_vertex(in.a, q.pair, v);
         q.out = v;
         q.tag = mix32((uint32_t)v ^ 0x5bd1e995u);
+        return q;
+    }
+    if (in.mode == Q_BARYCENTERS) {
+        // the barycenter of record i of the list (the fifth bound's S_b):
+        // the mean of its exact corners; seeded with two corners' closest
+        // triangles (records waiting for stage B keep a decider in the
+        // level field's upper bits)
+        const int face = in.par.face()[i], lvl = in.par.lvl()[i] & 0xff;
+        q.pair = in.par.pair()[i];
+        const V3<double> c0 = a_point(in.a, q.pair, face, lvl, in.par.ba(0)[i], in.par.bb(0)[i]);
+        const V3<double> c1 = a_point(in.a, q.pair, face, lvl, in.par.ba(1)[i], in.par.bb(1)[i]);
+        const V3<double> c2 = a_point(in.a, q.pair, face, lvl, in.par.ba(2)[i], in.par.bb(2)[i]);
+        q.p = (1.0 / 3.0) * (c0 + c1 + c2);
+        q.out = i;
+        q.tag = 0;
+        q.seed[0] = in.par.I(0)[i];
+        q.seed[1] = in.par.I(1)[i];
         return q;
     }
     if (in.mode == Q_LATTICE) {
@@ -867,6 +884,9 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
     }
     wave_add(&ctl->stat[acc_copy()][ST_BOXES], nb);
     wave_add(&ctl->stat[acc_copy()][ST_QLEAVES], nl);
+    // the list is done: a later query launch of the same round starts empty
+    __syncthreads();
+    if (threadIdx.x == 0) ctl->n_overflow = 0;
 }
 
 // Launch shapes of the query kernel (LDS stack entries per query, block
@@ -1104,7 +1124,7 @@ HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double 
     *decider = cc.c.order[cc.c.norder - 1];
     for (int i = 0; i < cc.c.norder; ++i) {
         int k = cc.c.order[i];
-        if (k == 3) {
+        if (k == 3 || k == 5) { // the bounds that evaluate at fixed B triangles: stage B
             *carry = best;
             return TO_B;
         }
@@ -1127,17 +1147,19 @@ HD_D int stage_a(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, double 
 // stage B: u3 and the bounds after it, from the running minimum `best`
 template <class T>
 HD_D int stage_b(const Corner<T> cn[3], int pair, const ClassifyCfg &cc, const BView<T> &bv, double best,
-                 int best_k, double *carry, int *decider, int *evals, int *unsound) {
+                 int best_k, double *carry, int *decider, int *evals, int *unsound, int Sb) {
     const Tri<T> t = make_tri(cn);
     const PairConst &P = cc.pc[pair];
     const double L = pair_L(cc.pc, cc.pv, pair);
     const double mu = tri_margin(t, margins_of<T>(P));
     int i3 = 0;
-    while (cc.c.order[i3] != 3) ++i3;
+    while (cc.c.order[i3] != 3 && cc.c.order[i3] != 5) ++i3;
     *decider = best_k;
     for (int i = i3; i < cc.c.norder; ++i) {
         int k = cc.c.order[i];
-        double u = (double)(k == 3 ? bound_u3(t, bv, cc.iv, nullptr, evals) : bound_cheap<T>(k, t)) - cc.shift + mu;
+        const T b = k == 3 ? bound_u3(t, bv, cc.iv, nullptr, evals)
+                           : (k == 5 ? bound_u5(t, bv, Sb, evals) : bound_cheap<T>(k, t));
+        double u = (double)b - cc.shift + mu;
         check_sound(u, t, mu, unsound);
         if (u < L) {
             *decider = k;
@@ -1219,12 +1241,14 @@ __device__ int64_t append_slot(int list, Ctl *ctl) {
 __device__ void tally(Ctl *ctl, int list, int decider, int evals, int rechecked, bool valid, bool bounded) {
     const bool dis = valid && list == TO_DISCARD;
     unsigned long long *st = ctl->stat[acc_copy()];
-    block_add<8, BLK>({dis && decider == 0 ? 1ull : 0ull, dis && decider == 1 ? 1ull : 0ull,
+    block_add<9, BLK>({dis && decider == 0 ? 1ull : 0ull, dis && decider == 1 ? 1ull : 0ull,
                        dis && decider == 2 ? 1ull : 0ull, dis && decider == 3 ? 1ull : 0ull,
-                       dis && decider == 4 ? 1ull : 0ull, valid ? (unsigned long long)evals : 0ull,
-                       valid ? (unsigned long long)rechecked : 0ull, valid && bounded ? 1ull : 0ull},
+                       dis && decider == 4 ? 1ull : 0ull, dis && decider == 5 ? 1ull : 0ull,
+                       valid ? (unsigned long long)evals : 0ull, valid ? (unsigned long long)rechecked : 0ull,
+                       valid && bounded ? 1ull : 0ull},
                       {st + ST_DISCARDS, st + ST_DISCARDS + 1, st + ST_DISCARDS + 2, st + ST_DISCARDS + 3,
-                       st + ST_DISCARDS + 4, st + ST_EVALS, st + ST_RECHECKED, st + ST_BOUNDED});
+                       st + ST_DISCARDS + 4, st + ST_DISCARDS + 5, st + ST_EVALS, st + ST_RECHECKED,
+                       st + ST_BOUNDED});
 }
 
 template <class T> struct Dest {
@@ -1383,10 +1407,11 @@ __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T
 }
 
 // stage B over the records stage A left undecided (count in ctl->b_next;
-// grid-stride)
+// grid-stride); Sb (when the order has the fifth bound): the closest B
+// triangle (sorted index) of each record's barycenter
 template <class T>
 __global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg cc, BView<T> bv, Dest<T> dst,
-                                                 Ctl *ctl) {
+                                                 Ctl *ctl, const int *__restrict__ Sb) {
     const int64_t n = (int64_t)ctl->b_next;
     for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
         const int64_t j = base + threadIdx.x;
@@ -1401,7 +1426,7 @@ __global__ __launch_bounds__(BLK) void k_stage_b(FrontierView<T> in, ClassifyCfg
             lvl = in.lvl()[j] & 0xff;
             int unsound = 0;
             list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider, &evals,
-                              &unsound);
+                              &unsound, Sb ? Sb[j] : -1);
             if (unsound) ctl->bad = 4;
         }
         int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
@@ -1617,7 +1642,8 @@ constexpr float POLICY_MARGIN = 0.02f;
 
 template <class T>
 __global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, ClassifyCfg cc, BView<T> bv, Dest<T> dst,
-                                                         Ctl *ctl, LearnCfg lc, const float *__restrict__ params) {
+                                                         Ctl *ctl, LearnCfg lc, const float *__restrict__ params,
+                                                         const int *__restrict__ Sb) {
     const int64_t n = (int64_t)ctl->b_next;
     if ((int64_t)blockIdx.x * BLK >= n) return; // no work for this block
     __shared__ ScoreLds S;
@@ -1655,7 +1681,7 @@ __global__ __launch_bounds__(BLK) void k_stage_b_learned(FrontierView<T> in, Cla
             } else {
                 int unsound = 0;
                 list = stage_b<T>(cn, pair, cc, bv, (double)in.ub()[j], in.lvl()[j] >> 8, &carry, &decider,
-                                  &evals, &unsound);
+                                  &evals, &unsound, Sb ? Sb[j] : -1);
                 if (unsound) ctl->bad = 4;
             }
         }
@@ -2125,6 +2151,40 @@ __global__ void k_eval_bounds(const double *v, const double *d, const int32_t *I
     u3case[i] = cs;
 }
 
+// test entry: the fifth bound of given triangles (uncentred FP64 input),
+// their barycenters' closest triangles from a point query (Sb, sorted)
+__global__ void k_barycenters(const double *v, int64_t n, double *P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < 3; ++k) P[3 * i + k] = (v[9 * i + k] + v[9 * i + 3 + k] + v[9 * i + 6 + k]) / 3.0;
+}
+
+template <class T>
+__global__ void k_eval_u5(const double *v, const double *d, const int32_t *Iorig, int64_t n, const int32_t *inv_perm,
+                          int64_t nB, const int *Sb, BView<T> bv, const int4 *ids, const PairConst *pc, double *out,
+                          int32_t *Sb_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < 3; ++k) {
+        const int32_t f = Iorig[3 * i + k];
+        if (f < 0 || f >= nB) {
+            out[i] = __builtin_nan("");
+            Sb_out[i] = -1;
+            return;
+        }
+    }
+    Tri<T> t;
+    const double *c = pc[0].ctr;
+    for (int k = 0; k < 3; ++k) {
+        t.v[k] = {T(v[9 * i + 3 * k] - c[0]), T(v[9 * i + 3 * k + 1] - c[1]), T(v[9 * i + 3 * k + 2] - c[2])};
+        t.q[k] = t.v[k];
+        t.d[k] = T(d[3 * i + k]);
+        t.I[k] = inv_perm[Iorig[3 * i + k]];
+    }
+    out[i] = (double)bound_u5(t, bv, Sb[i], nullptr);
+    Sb_out[i] = ids[Sb[i]].w;
+}
+
 // test entry: the learned proposal's features of given triangles
 template <class T>
 __global__ void k_tri_features(const double *v, const double *d, const int32_t *Iorig, const double *q, int64_t n,
@@ -2269,7 +2329,7 @@ template <class T> struct QBuf {
 template <class T> struct TypedWs {
     FrontierBuf<T> act, act2, park;
     FrontierBuf<T> pend_b, pend_c; // records between cascade stages (one round's worth)
-    QBuf<T> vq, mq, lq;
+    QBuf<T> vq, mq, lq, bq; // vertex, midpoint, lattice and barycenter query results
 };
 struct Workspace {
     std::mutex mu;
@@ -2381,18 +2441,18 @@ hd_status status_of_bad(int bad) {
     }
 }
 
-int parse_order(int32_t order, int out[4]) {
+int parse_order(int32_t order, int out[5]) {
     if (order <= 0) order = 1234;
-    int digits[8], n = 0;
-    while (order > 0 && n < 8) {
+    int digits[10], n = 0;
+    while (order > 0 && n < 10) {
         digits[n++] = order % 10;
         order /= 10;
     }
-    if (order > 0 || n > 4) return -1;
+    if (order > 0 || n > 5) return -1;
     int used = 0;
     for (int i = 0; i < n; ++i) {
         int k = digits[n - 1 - i];
-        if (k < 1 || k > 4 || (used >> k) & 1) return -1;
+        if (k < 1 || k > 5 || (used >> k) & 1) return -1;
         used |= 1 << k;
         out[i] = k;
     }
@@ -2717,6 +2777,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cc.c = cctx;
     cc.recheck = (opt.precision == HD_PREC_FP32_RECHECK) && sizeof(T) == 4;
     cc.shift = opt.test_bound_shift;
+    bool has_u5 = false; // the order has the fifth bound (barycenter queries before stage B)
+    for (int i = 0; i < cctx.norder; ++i) has_u5 = has_u5 || cctx.order[i] == 5;
     cc.a = av;
     cc.bv64 = bv64;
     cc.iv = iv;
@@ -2765,10 +2827,27 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     auto later_stages = [&](int64_t n, const FrontierView<T> &act_out, int defer, unsigned plan_seq) {
         Dest<T> d{act_out, tw.park.v, tw.pend_b.v, tw.pend_c.v};
         const unsigned g = std::max(1u, std::min<unsigned>(grid_for(n, BLK), GRID_MAX));
+        const int *Sb = nullptr;
+        if (has_u5) {
+            // the fifth bound: the closest B triangle of each waiting record's
+            // barycenter (one point query each; they do not raise L)
+            tw.bq.ensure(tw.pend_b.cap);
+            QueryIn<T> qi{};
+            qi.mode = Q_BARYCENTERS;
+            qi.npairs = np;
+            qi.a = av;
+            qi.par = tw.pend_b.v;
+            qi.pc = pc;
+            const QueryCfg bcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
+            ws.ovf.reserve((size_t)n * sizeof(int32_t));
+            launch_query<T>(qsel, n, qmax, qi, DevCount{&ctl->b_next, 1, 0}, bcfg, bv, tw.bq.o, pc, pv, ctl,
+                            ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
+            Sb = tw.bq.o.I;
+        }
         if (opt.learned == 2)
-            k_stage_b_learned<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params);
+            k_stage_b_learned<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params, Sb);
         else
-            k_stage_b<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl);
+            k_stage_b<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, Sb);
         if (cc.recheck)
             k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl, defer, mb_dev, plan_seq,
                                            plan_seq ? caps() : PlanCaps{});
@@ -3168,6 +3247,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     S.pt_tri_evals = (int64_t)(stat(ST_EVALS) + stat(ST_QLEAVES));
     S.box_tests = (int64_t)stat(ST_BOXES);
     for (int k = 0; k < 5; ++k) S.discards[k] = (int64_t)stat(ST_DISCARDS + k);
+    S.discards_u5 = (int64_t)stat(ST_DISCARDS + 5);
     S.rechecked64 = (int64_t)stat(ST_RECHECKED);
     S.parked_final = nPark;
     S.query_leaf_evals = (int64_t)stat(ST_QLEAVES);
@@ -3538,6 +3618,54 @@ hd_status hd_eval_bounds(const double *v, const double *dd, const int32_t *I, co
                                                                   out, u3_case);
         HD_LAUNCH_CHECK();
         HD_HIP(hipStreamSynchronize(s));
+        return HD_OK;
+    });
+}
+
+hd_status hd_eval_bound_u5(const double *v, const double *dd, const int32_t *I, int64_t n, hd_bvh Bh,
+                           int32_t precision, double *out, int32_t *Sb_out, hd_stream_t stream) {
+    if (!Bh || n < 0 || (n > 0 && (!v || !dd || !I || !out || !Sb_out))) return HD_E_INVALID;
+    if (n == 0) return HD_OK;
+    const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
+    hipStream_t s = (hipStream_t)stream;
+    return guard([&] {
+        DBuf inv, ctlb, pcb, pvb, ovf, deep, P;
+        inv.reserve((size_t)B->nB * sizeof(int32_t));
+        ctlb.reserve(sizeof(Ctl));
+        pcb.reserve(sizeof(PairConst));
+        pvb.reserve(sizeof(PairVar));
+        ovf.reserve((size_t)n * sizeof(int32_t));
+        deep.reserve((size_t)DEEP_SLOTS * DEEP_STACK * sizeof(int2));
+        P.reserve((size_t)n * 3 * sizeof(double));
+        Ctl *ctl = ctlb.as<Ctl>();
+        PairConst *pc = pcb.as<PairConst>();
+        PairVar *pv = pvb.as<PairVar>();
+        k_ctl_init<<<1, 256, 0, s>>>(ctl);
+        k_pairs_init<<<1, 64, 0, s>>>(pc, pv, B->pairs.as<BvhPair>(), 1);
+        k_inv_perm<<<grid_for(B->nB, BLK), BLK, 0, s>>>(B->ids.as<int4>(), B->nB, inv.as<int32_t>());
+        k_barycenters<<<grid_for(n, BLK), BLK, 0, s>>>(v, n, P.as<double>());
+        const QueryCfg cfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, nullptr};
+        auto go = [&](auto tag) {
+            using T = decltype(tag);
+            QBuf<T> qb;
+            qb.ensure(n);
+            QueryIn<T> qi{};
+            qi.mode = Q_POINTS;
+            qi.npairs = 1;
+            qi.P = P.as<double>();
+            qi.pc = pc;
+            BView<T> bv;
+            if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
+            else bv = BView<double>{B->frames64.as<double2>()};
+            launch_query<T>(0, n, -1, qi, host_count(n), cfg, bv, qb.o, pc, pv, ctl, ovf.as<int32_t>(),
+                            deep.as<int2>(), s);
+            k_eval_u5<T><<<grid_for(n, BLK), BLK, 0, s>>>(v, dd, I, n, inv.as<int32_t>(), B->nB, qb.o.I, bv,
+                                                          B->ids.as<int4>(), pc, out, Sb_out);
+            HD_LAUNCH_CHECK();
+            HD_HIP(hipStreamSynchronize(s));
+        };
+        if (precision == HD_PREC_FP64) go(double{});
+        else go(float{});
         return HD_OK;
     });
 }

@@ -340,4 +340,37 @@ template <class T> HD_D T bound_u4(const Tri<T> &t) {
     return hmin(h_two_points(t, qc, qa), h_two_points(t, qc, qb));
 }
 
+// The bound of Zheng et al. that the paper quotes in its fourth-bound
+// subsection: min over S in {S1, S2, S3, S_b} of the largest distance of a
+// vertex of T to S (the distance to a triangle is convex, so over T it peaks
+// at a vertex); S_b is the triangle of B closest to T's barycenter (sorted
+// index, found by a point query). Vertex i's distance to its own S_i is known.
+// One frame is live at a time; *evals counts closest-point evaluations.
+template <class T> HD_D T bound_u5(const Tri<T> &t, const BView<T> &bv, int Sb, int *evals) {
+    T best = __builtin_inf();
+    int ev = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int S = i < 3 ? pick3(t.I[0], t.I[1], t.I[2], i) : Sb;
+        // a triangle already tried gives the same term
+        if (i >= 1 && S == t.I[0]) continue;
+        if (i >= 2 && S == t.I[1]) continue;
+        if (i == 3 && S == t.I[2]) continue;
+        const Frame<T> f = load_frame(bv.frames, S);
+        T h = T(0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if (i < 3 && j == i) {
+                h = hmax(h, pick3(t.d[0], t.d[1], t.d[2], j));
+            } else {
+                h = hmax(h, hsqrt(frame_dist2<T, false>(f, pick3(t.v[0], t.v[1], t.v[2], j), nullptr)));
+                ++ev;
+            }
+        }
+        best = hmin(best, h);
+    }
+    if (evals) *evals += ev;
+    return best;
+}
+
 } // namespace hd

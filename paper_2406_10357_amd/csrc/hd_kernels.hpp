@@ -607,50 +607,14 @@ HD_D QueryResult<T> traverse4(const NodeSrc &nodes, const BView<T> &bv, const in
 // lower bound L (discard), else the minimum of all of them.
 // ---------------------------------------------------------------------------
 struct CascadeCtx {
-    int order[4];
+    int order[5]; // bounds 1..4, and 5 (the bound of Zheng et al., which needs the barycenter's query)
     int norder;
 };
-
-template <class T>
-HD_D T bound_k(int k, const Tri<T> &t, const BView<T> &bv, const IdView &iv, int *evals) {
-    switch (k) {
-    case 1: return bound_u1(t);
-    case 2: return bound_u2(t);
-    case 3: return bound_u3(t, bv, iv, nullptr, evals);
-    default: return bound_u4(t);
-    }
-}
 
 template <class T> HD_D double tri_margin(const Tri<T> &t, const Margins &m) {
     double dmax = (double)hmax(t.d[0], hmax(t.d[1], t.d[2]));
     double e = (double)hmax(norm2(t.v[0] - t.v[1]), hmax(norm2(t.v[1] - t.v[2]), norm2(t.v[2] - t.v[0])));
     return m.mu_d * dmax + m.mu_e * sqrt(e) + m.mu_0;
-}
-
-// upper bound with margin; *decider = 0 (exact), 1..4
-template <class T>
-HD_D double cascade(const Tri<T> &t, double L, const CascadeCtx &c, const Margins &m, const BView<T> &bv,
-                    const IdView &iv, int *decider, int *evals) {
-    double mu = tri_margin(t, m);
-    if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) {
-        *decider = 0;
-        return (double)hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
-    }
-    double best = __builtin_inf();
-    *decider = c.order[c.norder - 1];
-    for (int i = 0; i < c.norder; ++i) {
-        int k = c.order[i];
-        double u = (double)bound_k<T>(k, t, bv, iv, evals) + mu;
-        if (u < L) {
-            *decider = k;
-            return u;
-        }
-        if (u < best) {
-            best = u;
-            *decider = k;
-        }
-    }
-    return best;
 }
 
 // FP64 recomputation of a frontier triangle: exact vertex positions, FP64
@@ -673,8 +637,13 @@ HD_D double rebound64(const AView &a, int pair, int32_t face, int lvl, const int
     double mu = tri_margin(t, m64);
     if (t.I[0] == t.I[1] && t.I[1] == t.I[2]) return hmax(t.d[0], hmax(t.d[1], t.d[2])) + mu;
     // the minimum over the bounds in the set does not depend on their order
+    // (the fifth bound needs a point query of the barycenter, which this
+    // re-bound does not make: the minimum of the others is still a bound, and
+    // u2 stands in when the fifth is the only one)
     unsigned used = 0;
     for (int i = 0; i < c.norder; ++i) used |= 1u << c.order[i];
+    used &= 0x1eu;
+    if (!used) used = 4u;
     double best = __builtin_inf();
     if (used & 2u) best = hmin(best, bound_u1(t));
     if (used & 4u) best = hmin(best, bound_u2(t));
