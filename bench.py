@@ -74,6 +74,7 @@ def parse():
                          "as many floats (x4): the references for the HBM byte counters (FETCH_SIZE / "
                          "WRITE_SIZE) and the FP32 FLOP counter (SQ_INSTS_VALU_FLOPS_FP32) of a rocprofv3 "
                          "--pmc run")
+    ap.add_argument("--study-configs", default="2,3,4", help="order-study / eps-curve: the workloads")
     ap.add_argument("--out", default=None, help="also write the JSON line (or the study) to this file")
     return ap.parse_args()
 
@@ -489,7 +490,7 @@ def eps_curve_main(a, hd, torch, wl):
     """Time to a certified interval as eps shrinks (the paper's runtime versus
     tolerance comparison), on the torus, the thin strip and the large torus."""
     rows = []
-    for cfg in (2, 3, 5):
+    for cfg in [int(c) for c in (a.study_configs if a.study_configs != "2,3,4" else "2,3,5").split(",")]:
         W = wl.config(cfg)
         prec_name = "fp32" if cfg == 3 else "fp32+recheck"
         run = Single(hd, torch, W, PRECISIONS[prec_name])
@@ -515,7 +516,7 @@ def order_study_main(a, hd, torch, wl):
         orders += [int("".join(map(str, p))) for p in itertools.permutations((1, 2, 3, 4), r)]
     orders += [5, 12345, 51234, 1245]
     rows = []
-    for cfg in (2, 3, 4):
+    for cfg in [int(c) for c in a.study_configs.split(",")]:
         if cfg == 4:
             pairs = wl.batched_pairs(256, workers=min(16, os.cpu_count() or 1))
             run = Batch(hd, torch, pairs, PRECISIONS["fp32+recheck"])

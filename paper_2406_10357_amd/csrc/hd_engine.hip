@@ -2286,6 +2286,12 @@ template <class T> struct FrontierBuf {
     }
 };
 
+template <class T> void release_fb(FrontierBuf<T> &a) {
+    a.mem.release();
+    a.cap = 0;
+    a.v = FrontierView<T>{};
+}
+
 template <class T> void swap_fb(FrontierBuf<T> &a, FrontierBuf<T> &b) {
     a.mem.swap(b.mem);
     std::swap(a.cap, b.cap);
@@ -2316,12 +2322,21 @@ template <class T> struct QBuf {
     DBuf mem;
     int64_t cap = 0;
     QueryOut<T> o{};
+    // grow to at least n queries (contents are not preserved); on a failed
+    // allocation the old buffer stays as it was
     void ensure(int64_t n) {
         if (n <= cap) return;
         int64_t nc = std::max<int64_t>(n, cap + cap / 2);
-        mem.reserve(qout_bytes<T>(nc));
+        DBuf nm;
+        nm.reserve(qout_bytes<T>(nc));
+        mem.swap(nm);
         o = carve_qout<T>(mem.as<char>(), nc);
         cap = nc;
+    }
+    void release() {
+        mem.release();
+        cap = 0;
+        o = QueryOut<T>{};
     }
 };
 
@@ -2330,6 +2345,10 @@ template <class T> struct TypedWs {
     FrontierBuf<T> act, act2, park;
     FrontierBuf<T> pend_b, pend_c; // records between cascade stages (one round's worth)
     QBuf<T> vq, mq, lq, bq; // vertex, midpoint, lattice and barycenter query results
+    void release() {
+        for (FrontierBuf<T> *f : {&act, &act2, &park, &pend_b, &pend_c}) release_fb(*f);
+        for (QBuf<T> *q : {&vq, &mq, &lq, &bq}) q->release();
+    }
 };
 struct Workspace {
     std::mutex mu;
@@ -2348,6 +2367,15 @@ struct Workspace {
     TypedWs<float> w32;
     TypedWs<double> w64;
     template <class T> TypedWs<T> &typed();
+    // The buffers only grow: after a call that ran out of memory or of
+    // capacity (frontier lists sized near the device's memory), they are
+    // given back, so that the next call starts from what it needs.
+    void trim() {
+        w32.release();
+        w64.release();
+        for (DBuf *b : {&Vcat, &Fcat, &fpair, &ref, &vids, &ovf, &sortbuf, &selidx, &scan_tmp, &sort_tmp})
+            b->release();
+    }
 };
 template <> TypedWs<float> &Workspace::typed<float>() { return w32; }
 template <> TypedWs<double> &Workspace::typed<double>() { return w64; }
@@ -3366,13 +3394,25 @@ static hd_status bound_any(const Input &in, hd_bvh Bh, const hd_options *opt, hd
     return guard([&] {
         WsLease lease;
         std::vector<double> lu(2 * (size_t)in.npairs, NAN);
-        hd_status r;
-        if (o.precision == HD_PREC_FP64)
-            r = run<double>(in, B, o, (hipStream_t)stream, *lease.ws, lu.data(), stats);
-        else if (o.precision == HD_PREC_FP32 || o.precision == HD_PREC_FP32_RECHECK)
-            r = run<float>(in, B, o, (hipStream_t)stream, *lease.ws, lu.data(), stats);
-        else
-            return HD_E_INVALID;
+        hd_status r = HD_E_INVALID;
+        auto trim = [&] {
+            // the work already enqueued may still use the buffers
+            (void)hipStreamSynchronize((hipStream_t)stream);
+            (void)hipGetLastError();
+            lease.ws->trim();
+        };
+        try {
+            if (o.precision == HD_PREC_FP64)
+                r = run<double>(in, B, o, (hipStream_t)stream, *lease.ws, lu.data(), stats);
+            else if (o.precision == HD_PREC_FP32 || o.precision == HD_PREC_FP32_RECHECK)
+                r = run<float>(in, B, o, (hipStream_t)stream, *lease.ws, lu.data(), stats);
+            else
+                return HD_E_INVALID;
+        } catch (const Error &e) {
+            if (e.st == HD_E_NOMEM) trim();
+            throw;
+        }
+        if (r == HD_E_NOMEM || r == HD_E_CAPACITY) trim();
         if (r == HD_OK) std::copy(lu.begin(), lu.end(), LU);
         return r;
     });

@@ -503,9 +503,15 @@ def test_face_budget_exceeded():
     W = wl.config(1)
     say("budget m = 1.5 on config1")
     bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
-    with pytest.raises(hd.HDError) as e:
-        hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, budget_m=1.5, relative=True)
-    assert e.value.status == 2
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    ref = hd.bound(*args, relative=True)
+    for sub in (0, 64):
+        with pytest.raises(hd.HDError) as e:
+            hd.bound(*args, budget_m=1.5, relative=True, subbatch=sub)
+        assert e.value.status == 2
+        # the failed call gave its buffers back; the next call is unaffected
+        again = hd.bound(*args, relative=True)
+        assert again[:2] == ref[:2] and again[2]["subdivided"] == ref[2]["subdivided"]
 
 
 def test_cascade_order_invariance_on_gpu():
