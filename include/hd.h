@@ -90,8 +90,11 @@ typedef struct {
                                   calls; 2: retune on this call; 0: use the kept choice */
     int32_t query_lanes;       /* lanes per point query: 0 automatic (a quad of four lanes per
                                   query in query launches of at most 32768 queries, where one
-                                  lane per query leaves the GPU latency-bound; one lane above);
-                                  1 always one lane; 4 always a quad */
+                                  lane per query leaves the GPU latency-bound; above, one static
+                                  query per lane); 1 always one static query per lane; 2 one lane
+                                  per query with refills (a lane whose query ends takes the next
+                                  one; slower than static lanes on the paper's workloads, kept as
+                                  an option); 4 always a quad. Results do not depend on it. */
     int32_t eps_relative;      /* 0 (default): eps is the absolute tolerance, U - L <= eps;
                                   1: eps is the paper's relative tolerance (eq. output_bounds),
                                   U - L <= eps * dA, dA computed on the device from A */
@@ -161,6 +164,11 @@ typedef struct {
     int64_t stale;             /* sub-batches: active triangles dropped before being split because
                                   L had risen above their bound (the paper's stale queue entries) */
     int64_t discards_u5;       /* triangles discarded by the fifth bound (order digit 5) */
+    int32_t device_flag;       /* what the device found wrong (0 nothing): 2 a traversal deeper than the
+                                  fallback stack, 3 the subdivision depth limit, 4 an upper bound below a
+                                  vertex distance of its triangle, 5 plain FP32 with a tolerance below
+                                  its margin */
+    int32_t pad2;
 } hd_stats;
 
 /* Build the LBVH over soup B (device-built: Morton codes of triangle
@@ -252,12 +260,15 @@ hd_status hd_hausdorff(const double *VA, int64_t mA, const int32_t *FA, int64_t 
  * doubles), closest face of B as its original index (device, nP int32) and
  * closest points (device, nP x 3 doubles; may be NULL). precision selects
  * FP64 or FP32 arithmetic (HD_PREC_FP32 and HD_PREC_FP32_RECHECK both mean
- * FP32 here). lanes (0 or 1: one lane per point; 4: a quad of lanes per
+ * FP32 here). lanes (0 or 1: one lane per point; 2: one lane per point with
+ * refills; 4: a quad of lanes per
  * point) selects the query kernel; the results do not depend on it. This is
  * the per-vertex query of the Implementation section, exposed for testing
  * and reuse. HD_E_INVALID for other values of lanes. */
 hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh B, int32_t precision, int32_t lanes,
                              double *d, int32_t *I, double *Q, hd_stream_t stream);
+/* (lanes: 0 or 1 one lane per point, 2 one lane per point with refills, 4 a
+ * quad of lanes per point) */
 
 /* hd_point_distances for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

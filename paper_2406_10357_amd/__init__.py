@@ -26,9 +26,14 @@ STATUS = {0: "HD_OK", 1: "HD_E_INVALID", 2: "HD_E_CAPACITY", 3: "HD_E_NOMEM", 4:
 
 
 class HDError(RuntimeError):
-    def __init__(self, status: int, where: str):
+    """A nonzero hd_status; `stats` holds the call's statistics when it has any
+    (device_flag names what the device found wrong)."""
+
+    def __init__(self, status: int, where: str, stats=None):
         self.status = status
-        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.stats = stats
+        flag = f" (device flag {stats['device_flag']})" if stats and stats.get("device_flag") else ""
+        super().__init__(f"{where}: {STATUS.get(status, status)}{flag}")
 
 
 class Options(C.Structure):
@@ -67,10 +72,10 @@ class Stats(C.Structure):
                 ("logged", C.c_int64), ("learned_skips", C.c_int64), ("query_block", C.c_int32),
                 ("query_stack", C.c_int32), ("query_lanes", C.c_int32), ("query_quad_max", C.c_int32),
                 ("round_records", C.c_int64), ("tuned", C.c_int32), ("pad1", C.c_int32), ("stale", C.c_int64),
-                ("discards_u5", C.c_int64)]
+                ("discards_u5", C.c_int64), ("device_flag", C.c_int32), ("pad2", C.c_int32)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "pad1"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad1", "pad2")}
         d["discards"] = list(self.discards)
         return d
 
@@ -158,9 +163,9 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _check(st, where):
+def _check(st, where, stats=None):
     if st != 0:
-        raise HDError(st, where)
+        raise HDError(st, where, stats.as_dict() if stats is not None else None)
 
 
 class Bvh:
@@ -249,7 +254,7 @@ def bound(VA, FA, bvh: Bvh, eps: float, round_log: int = 0, **opts):
     stats = Stats()
     st = lib.hd_bound(C.c_void_p(VA.data_ptr()), VA.shape[0], C.c_void_p(FA.data_ptr()), FA.shape[0],
                       bvh.handle, float(eps), C.byref(o), _stream(), LU, C.byref(stats))
-    _check(st, "hd_bound")
+    _check(st, "hd_bound", stats)
     return LU[0], LU[1], _with_log(stats.as_dict(), log)
 
 
@@ -270,7 +275,7 @@ def hausdorff(VA, FA, VB, FB, eps: float, round_log: int = 0, **opts):
     st = lib.hd_hausdorff(C.c_void_p(VA.data_ptr()), VA.shape[0], C.c_void_p(FA.data_ptr()), FA.shape[0],
                           C.c_void_p(VB.data_ptr()), VB.shape[0], C.c_void_p(FB.data_ptr()), FB.shape[0], float(eps),
                           C.byref(o), _stream(), LU, LUd, C.byref(stats))
-    _check(st, "hd_hausdorff")
+    _check(st, "hd_hausdorff", stats)
     return LU[0], LU[1], ((LUd[0], LUd[1]), (LUd[2], LUd[3])), _with_log(stats.as_dict(), log)
 
 
@@ -315,7 +320,7 @@ def bound_batched(meshes, bvh: Bvh, eps, round_log: int = 0, **opts):
     stats = Stats()
     st = lib.hd_bound_batched(n, vptr, ms, fptr, ns, bvh.handle, ev, 1 if per else 0, C.byref(o), _stream(),
                               LU, C.byref(stats))
-    _check(st, "hd_bound_batched")
+    _check(st, "hd_bound_batched", stats)
     return [LU[2 * i] for i in range(n)], [LU[2 * i + 1] for i in range(n)], _with_log(stats.as_dict(), log)
 
 

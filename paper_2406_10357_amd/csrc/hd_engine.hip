@@ -106,6 +106,11 @@ struct Ctl {
     unsigned long long sel_above1; // live records in first-level bins above sel_b1
     unsigned sel_b1, sel_thr;      // boundary bin of the first pass; the ordered-key threshold
     int sel_mode;                  // SEL_NONE, SEL_ALL or SEL_THRESHOLD
+    int learn_off;                 // learned order: a round found no record predicted to raise L, so
+                                   // every later round splits all live records (no more scoring)
+    // the query kernel's refilling form: next query of each XCD's part (zero
+    // between launches), one 256-byte line each
+    alignas(256) unsigned long long qfetch[8 * 32];
     alignas(256) unsigned long long sel_prom;  // learned order: live records predicted above L + eps
     alignas(256) unsigned long long sel_next;  // selected parents appended (their record indices)
     alignas(256) unsigned long long rest_next; // unselected live records appended
@@ -813,6 +818,85 @@ __device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const TileOrder &t
     }
 }
 
+// The refilling form for large launches: each lane runs one query at a time
+// and, when it finishes, takes the next one from its XCD's part of the
+// launch (one atomic per wave and refill), instead of waiting for the
+// slowest lane of its wave (with one static query per lane, about 40% of a
+// wave's lanes were active per instruction on the large torus). The lanes
+// of a wave then traverse different queries one node per step.
+constexpr int QFETCH_STRIDE = 32; // u64 per fetch counter (256 bytes)
+template <class T, int SD, int QB>
+__device__ void query_refill(const QueryIn<T> &in, int64_t n, const QueryCfg &cfg, const BView<T> &bv,
+                             const QueryOut<T> &out, const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl,
+                             int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
+    // this block's XCD takes the queries of its own contiguous part (nearby
+    // points, shared tree paths in that XCD's L2)
+    const unsigned xs = gridDim.x % XCDS == 0 ? XCDS : 1;
+    const unsigned x = blockIdx.x % xs;
+    const int64_t per = (n + xs - 1) / xs;
+    const int64_t lo = (int64_t)x * per, hi = lo + per < n ? lo + per : n;
+    unsigned long long *ctr = &ctl->qfetch[x * QFETCH_STRIDE];
+    const int lane = __lane_id();
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    LdsStack<SD, QB> stk{s_node, s_dist, 0};
+    TravState<T> ts;
+    QPoint qp;
+    int64_t i = -1;
+    bool more = lo < hi;
+    // what this lane raises its pair's L and round key to (flushed when the
+    // pair changes, and at the end)
+    unsigned long long lord = 0, key = 0;
+    int cur_pair = 0;
+    while (true) {
+        const bool need = i < 0 && more;
+        const unsigned long long m = __ballot(need);
+        if (m) {
+            const int leader = __ffsll(m) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
+            base = __shfl(base, leader, 64);
+            if (need) {
+                const int64_t k = lo + (int64_t)base + __popcll(m & below);
+                if (k < hi) {
+                    i = k;
+                    qp = query_point(in, i);
+                    if (qp.pair != cur_pair) {
+                        if (lord) atomicMax(&pv[cur_pair].Lord, lord);
+                        if (key) atomicMax(&pv[cur_pair].round_key, key);
+                        lord = key = 0;
+                        cur_pair = qp.pair;
+                    }
+                    ts.p = cvt<T>(qp.p);
+                    ts.r = empty_result<T>();
+                    seed_two(ts.r, bv, ts.p, qp.seed[0], qp.seed[1]);
+                    stk.clear();
+                    trav_begin(ts, pc[qp.pair].root);
+                } else {
+                    more = false;
+                }
+            }
+        }
+        if (__ballot(i >= 0) == 0) break;
+        if (i >= 0 && trav_step<T>(cfg.nodes, bv, cfg.ids, ts, stk)) {
+            t.nb += ts.r.nbox;
+            t.nl += ts.r.nleaf;
+            t.nq += 1;
+            if (ts.r.overflow) {
+                const int k = atomicAdd(&ctl->n_overflow, 1);
+                ovf_list[k] = (int32_t)i;
+                t.ovf = 1;
+            } else {
+                unsigned long long a, b;
+                finish_query<T>(cfg, bv, ts.r, qp, ts.p, out, pc, &a, &b);
+                lord = a > lord ? a : lord;
+                key = b > key ? b : key;
+            }
+            i = -1;
+        }
+    }
+    pair_max2(pv, cur_pair, lord, key);
+}
+
 template <class T>
 __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BView<T> &bv, const QueryOut<T> &out,
                              const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, const int32_t *ovf_list,
@@ -823,7 +907,8 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
 template <class T, int SD, int QB>
 __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
                                               QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
-                                              Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max) {
+                                              Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max,
+                                              int refill) {
     static_assert(QB <= DEEP_SLOTS, "every thread of the last block has a deep-stack slot");
     __shared__ int s_node[SD * QB];
     __shared__ float s_dist[SD * QB];
@@ -831,9 +916,15 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
     const int64_t n = cnt.get();
     const bool quad = n <= quad_max;
     const TileOrder to(n, quad ? QB / 4 : QB);
-    if (!to.active()) return; // the grid is sized for a larger count
+    // (the refilling form runs every block of the grid, each taking queries
+    // while its XCD's part has any)
+    const bool dyn = !quad && refill;
+    if (!dyn && !to.active()) return; // the grid is sized for a larger count
+    if (dyn && n == 0) return;
     QueryTally t;
-    if (quad) {
+    if (dyn) {
+        query_refill<T, SD, QB>(in, n, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    } else if (quad) {
         // few queries, each bound by its chain of dependent node reads:
         // stage the top levels of the tree, where every traversal starts, in
         // LDS (without a table no reference reaches the copy)
@@ -850,8 +941,10 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
     unsigned long long *st = ctl->stat[acc_copy()];
     block_add<3, QB>({t.nb, t.nl, t.nq}, {st + ST_BOXES, st + ST_QLEAVES, st + ST_QUERIES});
     // the last block reads only the overflow list (and its atomic count)
-    if (last_block(&ctl->q_done, to.active_blocks(), __syncthreads_or(t.ovf) != 0))
+    if (last_block(&ctl->q_done, dyn ? gridDim.x : to.active_blocks(), __syncthreads_or(t.ovf) != 0)) {
         deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
+        if (threadIdx.x < XCDS) ctl->qfetch[threadIdx.x * QFETCH_STRIDE] = 0; // for the next launch
+    }
 }
 
 // queries whose LDS stack overflowed, redone with a deep stack in global
@@ -920,10 +1013,10 @@ inline unsigned qgrid_b(int64_t n, int qb, int64_t quad_max) {
 template <class T>
 void launch_query(int v, int64_t n_max, int64_t quad_max, const QueryIn<T> &qi, DevCount cnt, const QueryCfg &cfg,
                   const BView<T> &bv, const QueryOut<T> &out, const PairConst *pc, PairVar *pv, Ctl *ctl,
-                  int32_t *ovf, int2 *deep, hipStream_t s) {
+                  int32_t *ovf, int2 *deep, hipStream_t s, int refill = 1) {
 #define HD_QLAUNCH(SD, QB)                                                                                             \
     k_query<T, SD, QB><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf, deep,    \
-                                                                    quad_max)
+                                                                    quad_max, refill)
     switch (v) {
     case -1: HD_QLAUNCH(SMALL_STACK, 128); break;
     case 1: HD_QLAUNCH(8, 64); break;
@@ -1077,21 +1170,25 @@ template <class T> HD_D Tri<T> make_tri(const Corner<T> cn[3]) {
 
 HD_D double park_limit(double eps) { return eps * (1.0 - 1.0 / 1024.0 / 1024.0 / 1024.0); }
 
-// list for a final bound ub (margin mu included)
-HD_D int decide(double ub, double L, double eps, double mu, bool recheck) {
-    const double lim = park_limit(eps);
-    if (recheck) {
-        bool maybe_discard = ub >= L && ub - 2 * mu < L;
-        bool maybe_park = ub - L > lim && ub - 2 * mu - L <= lim;
-        if (maybe_discard || maybe_park) return TO_C;
-    }
-    return ub < L ? TO_DISCARD : (ub - L <= lim ? TO_PARK : TO_ACT);
-}
-
 HD_D float round_up_to_float(double x) {
     float f = (float)x;
     if ((double)f < x) f = next_up(f);
     return f;
+}
+
+// list for a final bound ub (margin mu included). Records keep their bound
+// rounded up to FP32, and the final U is taken over those stored values (or
+// the FP64 re-bound when smaller): a triangle is parked only when its stored
+// bound lies within eps of L.
+HD_D int decide(double ub, double L, double eps, double mu, bool recheck) {
+    const double lim = park_limit(eps);
+    const double stored = (double)round_up_to_float(ub);
+    if (recheck) {
+        bool maybe_discard = ub >= L && ub - 2 * mu < L;
+        bool maybe_park = stored - L > lim && ub - 2 * mu - L <= lim;
+        if (maybe_discard || maybe_park) return TO_C;
+    }
+    return ub < L ? TO_DISCARD : (stored - L <= lim ? TO_PARK : TO_ACT);
 }
 
 template <class T> HD_D T bound_cheap(int k, const Tri<T> &t) {
@@ -1842,8 +1939,9 @@ __device__ int sel_find_bin(unsigned *hist, unsigned long long want, unsigned lo
 // block histogram of the live records' keys: level 1 bins the top 12 bits of
 // every live record; level 2 the next 12 bits of those in bin b1
 template <class T, int LEVEL>
-__device__ void sel_histogram(const FrontierView<T> &act, int64_t n, int learned, unsigned b1, const PairConst *pc,
-                              const PairVar *pv, unsigned *global_hist, unsigned long long *prom_out) {
+__device__ void sel_histogram(const FrontierView<T> &act, int64_t n, int learned, int learn_off, unsigned b1,
+                              const PairConst *pc, const PairVar *pv, unsigned *global_hist,
+                              unsigned long long *prom_out) {
     __shared__ unsigned h[SEL_BINS];
     __shared__ unsigned prom;
     for (int i = threadIdx.x; i < SEL_BINS; i += BLK) h[i] = 0;
@@ -1856,7 +1954,7 @@ __device__ void sel_histogram(const FrontierView<T> &act, int64_t n, int learned
             atomicAdd(&h[key >> 20], 1u);
             // learned order: a live record whose predicted maximum lies above
             // L + eps may still raise L
-            if (learned) {
+            if (learned && !learn_off) {
                 const float sc = act.score()[j];
                 const int pair = act.pair()[j];
                 if (sc == sc && (double)sc > pair_L(pc, pv, pair) + pc[pair].eps_abs) atomicAdd(&prom, 1u);
@@ -1891,15 +1989,17 @@ __global__ __launch_bounds__(BLK) void k_sel_hist1(FrontierView<T> act, SelCfg s
     const int64_t need = (n + BLK - 1) / BLK;
     const unsigned nact = (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x);
     if (blockIdx.x >= nact && !(nact == 0 && blockIdx.x == 0)) return;
-    if (nact > 0) sel_histogram<T, 1>(act, n, sc.learned, 0, pc, pv, sc.hist1, &ctl->sel_prom);
+    const int learn_off = ctl->learn_off;
+    if (nact > 0) sel_histogram<T, 1>(act, n, sc.learned, learn_off, 0, pc, pv, sc.hist1, &ctl->sel_prom);
     if (nact == 0 || last_block(&ctl->h1_done, nact)) {
         // learned order: the top sub-batch by prediction while some record
-        // may still raise L, else every live record (breadth-first)
+        // may still raise L, else every live record (breadth-first), from
+        // then on without scoring
+        const bool prom = sc.learned && !learn_off &&
+                          __hip_atomic_load(&ctl->sel_prom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0;
         const unsigned long long target =
-            sc.learned ? (__hip_atomic_load(&ctl->sel_prom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0
-                              ? (want < (unsigned long long)sc.subbatch ? want : (unsigned long long)sc.subbatch)
-                              : want)
-                       : want;
+            prom ? (want < (unsigned long long)sc.subbatch ? want : (unsigned long long)sc.subbatch) : want;
+        if (sc.learned && !prom && threadIdx.x == 0) ctl->learn_off = 1;
         unsigned long long above = 0, at = 0, total = 0;
         const int b = sel_find_bin(sc.hist1, target, &above, &at, &total);
         if (threadIdx.x == 0) {
@@ -1925,7 +2025,7 @@ __global__ __launch_bounds__(BLK) void k_sel_hist2(FrontierView<T> act, SelCfg s
     const int64_t need = refine ? (n + BLK - 1) / BLK : 0;
     const unsigned nact = (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x);
     if (blockIdx.x >= nact && !(nact == 0 && blockIdx.x == 0)) return;
-    if (nact > 0) sel_histogram<T, 2>(act, n, sc.learned, ctl->sel_b1, pc, pv, sc.hist2, nullptr);
+    if (nact > 0) sel_histogram<T, 2>(act, n, sc.learned, 1, ctl->sel_b1, pc, pv, sc.hist2, nullptr);
     if (!(nact == 0 || last_block(&ctl->h2_done, nact))) return;
     unsigned long long above = 0, at = 0, total = 0;
     int b2 = -1;
@@ -2041,7 +2141,7 @@ template <class T>
 __global__ __launch_bounds__(BLK) void k_score_new(FrontierView<T> fr, const Ctl *ctl, LearnCfg lc, BView<T> bv,
                                                    const float *__restrict__ params) {
     const int64_t n = (int64_t)ctl->act_next;
-    if ((int64_t)blockIdx.x * BLK >= n) return;
+    if ((int64_t)blockIdx.x * BLK >= n || ctl->learn_off) return;
     __shared__ ScoreLds S;
     bool loaded = false;
     for (int64_t base = (int64_t)blockIdx.x * BLK; base < n; base += (int64_t)gridDim.x * BLK) {
@@ -2545,8 +2645,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cctx.norder = parse_order(opt.order, cctx.order);
     if (cctx.norder <= 0) throw Error{HD_E_INVALID, "bad cascade order"};
     if (opt.learned < 0 || opt.learned > 2) throw Error{HD_E_INVALID, "learned must be 0, 1 or 2"};
-    if (opt.query_lanes != 0 && opt.query_lanes != 1 && opt.query_lanes != 4)
-        throw Error{HD_E_INVALID, "query_lanes must be 0, 1 or 4"};
+    if (opt.query_lanes != 0 && opt.query_lanes != 1 && opt.query_lanes != 2 && opt.query_lanes != 4)
+        throw Error{HD_E_INVALID, "query_lanes must be 0, 1, 2 or 4"};
     if (opt.learned > 0 && !opt.mlp_params) throw Error{HD_E_INVALID, "learned mode needs the network's parameters"};
     if (opt.log_frontier && (!opt.log_out || opt.log_cap <= 0)) throw Error{HD_E_INVALID, "frontier log needs a buffer"};
     for (int p = 0; p < (in.eps_per_pair ? np : 1); ++p)
@@ -2686,7 +2786,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     if (qvar < 0 || qvar >= NQVAR) qvar = 0;
     int qsel = 0; // the launch shape this call uses (set after the autotuner)
     // launches of at most qmax queries run a quad of lanes per query
-    const int64_t qmax = opt.query_lanes == 1 ? -1 : (opt.query_lanes == 4 ? INT64_MAX : QUAD_MAX_DEFAULT);
+    const int64_t qmax =
+        opt.query_lanes == 1 || opt.query_lanes == 2 ? -1 : (opt.query_lanes == 4 ? INT64_MAX : QUAD_MAX_DEFAULT);
+    // one lane per query: one static query per lane, except with
+    // query_lanes = 2 (lanes refill with new queries as theirs finish)
+    const int qrefill = opt.query_lanes == 2 ? 1 : 0;
 
     // queries: n_max bounds the count (host count, or the device-planned one),
     // the grid covers it up to a persistent cap and loops beyond
@@ -2695,7 +2799,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         ws.ovf.reserve((size_t)n_max * sizeof(int32_t));
         prof.mark(prof.q);
         launch_query<T>(qsel, n_max, qmax, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
-                        ws.deep.as<int2>(), s);
+                        ws.deep.as<int2>(), s, qrefill);
         prof.mark(prof.q);
         const L64Cfg l64{B->nodes.as<WideNode>(), bv64, iv.ids, pc, np, ws.gstack.as<int2>(), check_fp32};
         k_argmax_finalize<T><<<std::min<unsigned>(grid_for(n_max, BLK), GRID_MAX), BLK, 0, s>>>(qi, cnt, out.key,
@@ -2742,7 +2846,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
                 HD_HIP(hipEventRecord(ws.tune_ev[0], s));
                 launch_query<T>(v, mA, -1, qi, nref_dev, tcfg, bv, tw.vq.o, pc, pv, ctl,
-                                ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
+                                ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s, qrefill);
                 HD_HIP(hipEventRecord(ws.tune_ev[1], s));
                 HD_HIP(hipEventSynchronize(ws.tune_ev[1]));
                 float ms = 0;
@@ -2869,7 +2973,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const QueryCfg bcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
             ws.ovf.reserve((size_t)n * sizeof(int32_t));
             launch_query<T>(qsel, n, qmax, qi, DevCount{&ctl->b_next, 1, 0}, bcfg, bv, tw.bq.o, pc, pv, ctl,
-                            ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
+                            ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s, qrefill);
             Sb = tw.bq.o.I;
         }
         if (opt.learned == 2)
@@ -3184,7 +3288,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
             launch_query<T>(qsel, nq, qmax, li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
-                            ws.deep.as<int2>(), s);
+                            ws.deep.as<int2>(), s, qrefill);
             k_log_parents<T><<<grid_for(K, BLK), BLK, 0, s>>>(tw.act.v, K, tw.lq.o, lc, bv, opt.log_out, logged,
                                                               opt.log_cap);
             HD_LAUNCH_CHECK();
@@ -3276,6 +3380,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     S.box_tests = (int64_t)stat(ST_BOXES);
     for (int k = 0; k < 5; ++k) S.discards[k] = (int64_t)stat(ST_DISCARDS + k);
     S.discards_u5 = (int64_t)stat(ST_DISCARDS + 5);
+    S.device_flag = hc.bad;
     S.rechecked64 = (int64_t)stat(ST_RECHECKED);
     S.parked_final = nPark;
     S.query_leaf_evals = (int64_t)stat(ST_QLEAVES);
@@ -3534,7 +3639,7 @@ hd_status hd_hausdorff(const double *VA, int64_t mA, const int32_t *FA, int64_t 
 hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, int32_t lanes, double *d,
                              int32_t *I, double *Q, hd_stream_t stream) {
     if (!Bh || nP < 0 || (nP > 0 && (!P || !d || !I))) return HD_E_INVALID;
-    if (lanes != 0 && lanes != 1 && lanes != 4) return HD_E_INVALID;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return HD_E_INVALID;
     if (nP == 0) return HD_OK;
     const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
     hipStream_t s = (hipStream_t)stream;
@@ -3567,7 +3672,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
             launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
-                            ovf.as<int32_t>(), deep.as<int2>(), s);
+                            ovf.as<int32_t>(), deep.as<int2>(), s, lanes == 2 ? 1 : 0);
             k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q, ctl,
                                                                  nullptr);
             HD_LAUNCH_CHECK();
@@ -3585,7 +3690,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
 hd_status hd_point_distances_noalloc(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, int32_t lanes,
                                      double *d, int32_t *I, double *Q, int32_t *err, hd_stream_t stream) {
     if (!Bh || !err || nP < 0 || (nP > 0 && (!P || !d || !I))) return HD_E_INVALID;
-    if (lanes != 0 && lanes != 1 && lanes != 4) return HD_E_INVALID;
+    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return HD_E_INVALID;
     if (precision != HD_PREC_FP64 && precision != HD_PREC_FP32 && precision != HD_PREC_FP32_RECHECK)
         return HD_E_INVALID;
     if (nP > HD_NOALLOC_MAX_POINTS) return HD_E_CAPACITY;
@@ -3623,7 +3728,7 @@ hd_status hd_point_distances_noalloc(const double *P, int64_t nP, hd_bvh Bh, int
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
             launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qo, pc, pv, ctl, ovf,
-                            deep, s);
+                            deep, s, lanes == 2 ? 1 : 0);
             k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qo, nP, B->ids.as<int4>(), pc, d, I, Q, ctl, err);
             HD_LAUNCH_CHECK();
         };

@@ -396,6 +396,147 @@ HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> 
 }
 
 // ---------------------------------------------------------------------------
+// The traversal of `traverse` as a state machine, advanced one wide node per
+// call (the greedy probe one level per call). A lane that runs several
+// queries one after the other (k_query's refilling form) keeps its state
+// here between calls; every query still visits the same nodes in the same
+// order as with `traverse`, so the results are identical.
+// ---------------------------------------------------------------------------
+template <class T> struct TravState {
+    QueryResult<T> r;
+    V3<T> p;
+    int root;
+    int node;     // next node to visit (the root first)
+    int probing;  // 1: greedy descent without a bound (greedy_probe), 2..: its depth + 1
+    int lost;     // a stack entry was dropped since the last (re)start
+    int restarts;
+};
+
+// after seeding s.r: what the first step does
+template <class T> HD_D void trav_begin(TravState<T> &s, int root) {
+    s.root = root;
+    s.node = root;
+    s.lost = 0;
+    s.restarts = 0;
+    s.probing = root >= 0 && !(s.r.d2 < T(__builtin_inf())) ? 1 : 0;
+}
+
+// One step; returns true when the query is finished (s.r holds its result).
+template <class T, class Stack>
+HD_D bool trav_step(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
+                    TravState<T> &s, Stack &st) {
+    QueryResult<T> &r = s.r;
+    const V3<T> &p = s.p;
+    if (s.root < 0) { // a single-leaf tree
+        visit_leaf(r, bv, ids, p, ~s.root);
+        return true;
+    }
+    if (s.probing) {
+        // one level of the greedy descent: nearest box, nothing pushed
+        const WideNode *w = nodes + s.node;
+        const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
+        const int4 ch = w->child;
+        T best = T(__builtin_inf());
+        int pick = WIDE_EMPTY;
+        auto consider = [&](float a, float b, float c, float d, float e, float f, int ref) {
+            if (ref == WIDE_EMPTY) return;
+            T dd = box_d2<T>(make_float4(a, b, c, 0.f), make_float4(d, e, f, 0.f), p);
+            if (pick == WIDE_EMPTY || dd < best) {
+                best = dd;
+                pick = ref;
+            }
+        };
+        consider(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ch.x);
+        consider(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ch.y);
+        consider(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ch.z);
+        consider(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ch.w);
+        r.nbox += 4;
+        if (pick >= 0 && s.probing < 64) {
+            s.node = pick;
+            ++s.probing;
+            return false;
+        }
+        if (pick != WIDE_EMPTY && pick < 0) visit_leaf(r, bv, ids, p, ~pick);
+        s.probing = 0;
+        s.node = s.root;
+        return false;
+    }
+    const T slack = T(1) + T(16 * Prec<T>::u);
+    const T inf = T(__builtin_inf());
+    const WideNode *w = nodes + s.node;
+    const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
+    const int4 ch = w->child;
+    T e0 = box_d2<T>(make_float4(lx.x, ly.x, lz.x, 0.f), make_float4(hx.x, hy.x, hz.x, 0.f), p);
+    T e1 = box_d2<T>(make_float4(lx.y, ly.y, lz.y, 0.f), make_float4(hx.y, hy.y, hz.y, 0.f), p);
+    T e2 = box_d2<T>(make_float4(lx.z, ly.z, lz.z, 0.f), make_float4(hx.z, hy.z, hz.z, 0.f), p);
+    T e3 = box_d2<T>(make_float4(lx.w, ly.w, lz.w, 0.f), make_float4(hx.w, hy.w, hz.w, 0.f), p);
+    int f0 = ch.x, f1 = ch.y, f2 = ch.z, f3 = ch.w;
+    r.nbox += (f0 != WIDE_EMPTY) + (f1 != WIDE_EMPTY) + (f2 != WIDE_EMPTY) + (f3 != WIDE_EMPTY);
+    {
+        const T thr = r.d2 * slack;
+        const bool l0 = f0 < 0 && f0 != WIDE_EMPTY && e0 <= thr, l1 = f1 < 0 && f1 != WIDE_EMPTY && e1 <= thr,
+                   l2 = f2 < 0 && f2 != WIDE_EMPTY && e2 <= thr, l3 = f3 < 0 && f3 != WIDE_EMPTY && e3 <= thr;
+        if constexpr (sizeof(T) == 8) {
+            if (l0) visit_leaf(r, bv, ids, p, ~f0);
+            if (l1 && e1 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f1);
+            if (l2 && e2 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f2);
+            if (l3 && e3 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f3);
+        } else if (l0 || l1 || l2 || l3) {
+            Frame<T> F0, F1, F2, F3;
+            if (l0) F0 = load_frame(bv.frames, ~f0);
+            if (l1) F1 = load_frame(bv.frames, ~f1);
+            if (l2) F2 = load_frame(bv.frames, ~f2);
+            if (l3) F3 = load_frame(bv.frames, ~f3);
+            if (l0) fold_leaf(r, F0, p, ~f0);
+            if (l1 && e1 <= r.d2 * slack) fold_leaf(r, F1, p, ~f1);
+            if (l2 && e2 <= r.d2 * slack) fold_leaf(r, F2, p, ~f2);
+            if (l3 && e3 <= r.d2 * slack) fold_leaf(r, F3, p, ~f3);
+        }
+    }
+    const T thr = r.d2 * slack;
+    auto keep = [&](T &e, int &f) {
+        if (!(f >= 0 && e <= thr)) {
+            e = inf;
+            f = -1;
+        }
+    };
+    keep(e0, f0);
+    keep(e1, f1);
+    keep(e2, f2);
+    keep(e3, f3);
+    cswap(e0, f0, e1, f1);
+    cswap(e2, f2, e3, f3);
+    cswap(e0, f0, e2, f2);
+    cswap(e1, f1, e3, f3);
+    cswap(e1, f1, e2, f2);
+    if (f0 >= 0) {
+        if (f3 >= 0 && !st.push(f3, to_float_down(e3))) s.lost = 1;
+        if (f2 >= 0 && !st.push(f2, to_float_down(e2))) s.lost = 1;
+        if (f1 >= 0 && !st.push(f1, to_float_down(e1))) s.lost = 1;
+        s.node = f0;
+        return false;
+    }
+    int n;
+    float dn;
+    while (st.pop(n, dn)) {
+        if (T(dn) <= r.d2 * slack) {
+            s.node = n;
+            return false;
+        }
+    }
+    if (!s.lost) return true;
+    // entries were dropped: visit the tree again with the bound found
+    if (++s.restarts > MAX_RESTARTS) {
+        r.overflow = true;
+        return true;
+    }
+    s.lost = 0;
+    st.clear();
+    s.node = s.root;
+    return false;
+}
+
+// ---------------------------------------------------------------------------
 // Four lanes per query. A quad (four consecutive lanes of a wave) runs one
 // traversal: lane k tests child slot k of each wide node and evaluates that
 // child when it is a triangle in range; quad permutes (DPP, no LDS) then give

@@ -802,3 +802,75 @@ def test_round_limit_decides_the_waiting_band():
         print(f"max_rounds {r}: [{L:.12g}, {U:.12g}] rechecked {st['rechecked64']}")
         assert st["status"] == 0 and st["rounds"] == r
         assert L <= Lf and Lf <= U and L <= Uf
+
+
+@pytest.mark.parametrize("order", [5, 1245])
+def test_batched_pairs_with_orders_without_the_third_bound(order):
+    """The 256-pair workload with cascades whose FP64 re-bound is loose (no
+    u3: the final U then rests on the stored FP32 bounds of millions of
+    parked triangles): every pair certified to its tolerance, sampled pairs
+    against the oracle with the same order."""
+    import os
+    hd, torch = _hd()
+    pairs = wl.batched_pairs(256, workers=min(16, os.cpu_count() or 1))
+    say("256 pairs, order", order)
+    bvh = hd.build_bvh_batched([(_cu(P.VB, torch), _cu(P.FB, torch)) for P in pairs])
+    Ls, Us, st = hd.bound_batched([(_cu(P.VA, torch), _cu(P.FA, torch)) for P in pairs], bvh,
+                                  [P.eps_rel for P in pairs], order=order, relative=True)
+    assert st["status"] == 0
+    for i, P in enumerate(pairs):
+        assert Us[i] - Ls[i] <= P.eps_rel * _dA(P.VA, P.FA) * (1 + 1e-12), i
+    digits = tuple(int(c) for c in str(order))
+    for i in (0, 1, 2, 100):
+        P = pairs[i]
+        ref = oracle.bound(P.VA, P.FA, P.VB, P.FB, P.eps_rel, order=digits, backend="tree")
+        assert Ls[i] <= ref["U"] + 1e-12 * ref["dA"] and ref["L"] <= Us[i] + 1e-12 * ref["dA"]
+        assert abs(Ls[i] - ref["L"]) <= ref["eps_abs"]
+
+
+@pytest.mark.parametrize("which", ["config2-small", "config5-tenth", "grid"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_refill_query_kernel_is_bit_identical(which, prec):
+    """One lane per query with refills (a lane whose query ends takes the
+    next one) against one static query per lane: every query runs the same
+    traversal in the same arithmetic, so the results are identical bit for
+    bit, in FP32 too; and certified against the oracle's brute force."""
+    hd, torch = _hd()
+    rng = np.random.default_rng(19)
+    if which == "grid":
+        VB, FB = _grid_soup(12, rng)
+        P = rng.uniform(-1.3, 1.3, size=(40001, 3))
+    else:
+        W = wl.config(2, scale=0.05) if which == "config2-small" else wl.config(5, scale=0.1)
+        VB, FB = W.VB, W.FB
+        lo, hi = VB.min(0), VB.max(0)
+        P = np.concatenate([rng.uniform(lo - 0.1, hi + 0.1, size=(20001, 3)), W.VA[:30000]])
+    precision = hd.PREC_FP64 if prec == "fp64" else hd.PREC_FP32
+    say("refill vs static one-lane point queries", which, prec, "nP", P.shape[0])
+    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
+    a = [x.cpu().numpy() for x in hd.point_distances(_cu(P, torch), bvh, precision=precision, lanes=1)]
+    b = [x.cpu().numpy() for x in hd.point_distances(_cu(P, torch), bvh, precision=precision, lanes=2)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    sample = rng.choice(P.shape[0], 600, replace=False)
+    dref, _ = oracle.points_soup(P[sample], VB, FB)
+    if prec == "fp64":
+        assert np.abs(b[0][sample] - dref).max() <= 1e-12 * np.abs(VB).max()
+
+
+@pytest.mark.parametrize("k,scale,prec", [(2, 0.1, "fp32+recheck"), (3, 0.05, "fp32"), (5, 0.05, "fp32+recheck"),
+                                          (1, 1.0, "fp64")])
+def test_refill_query_kernel_in_the_bound(k, scale, prec):
+    """hd_bound with refilling query launches gives the interval and every
+    counter of the static one-lane launches."""
+    hd, torch = _hd()
+    W = wl.config(k, scale=scale)
+    say("bound with refilling queries, config", k, "scale", scale, prec)
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    L1, U1, s1 = hd.bound(*args, precision=PRECS[prec], query_lanes=1, relative=True)
+    L2, U2, s2 = hd.bound(*args, precision=PRECS[prec], query_lanes=2, relative=True)
+    assert (L1, U1) == (L2, U2)
+    for key in ("rounds", "subdivided", "nodes_bounded", "queries", "discards", "rechecked64", "query_box_tests",
+                "query_leaf_evals"):
+        assert s1[key] == s2[key], key
