@@ -33,7 +33,9 @@
 extern "C" {
 #endif
 
-typedef struct ihipStream_t *hd_stream_t; /* hipStream_t; NULL = default stream */
+typedef struct ihipStream_t *hd_stream_t;
+
+#define HD_QUERY_SHAPES 9 /* launch shapes of the query kernel (hd_options.query_shape) */ /* hipStream_t; NULL = default stream */
 
 typedef enum {
     HD_OK = 0,
@@ -98,7 +100,11 @@ typedef struct {
     int32_t eps_relative;      /* 0 (default): eps is the absolute tolerance, U - L <= eps;
                                   1: eps is the paper's relative tolerance (eq. output_bounds),
                                   U - L <= eps * dA, dA computed on the device from A */
-    int32_t pad0;
+    int32_t query_shape;       /* 0: the query kernel's kept launch shape (the autotuner's
+                                  choice, else the default); k in 1..HD_QUERY_SHAPES: shape k-1
+                                  of the kernel's list (block size, LDS stack entries per lane)
+                                  for this call only, reported in hd_stats query_block and
+                                  query_stack. Results do not depend on it. */
     const char *tuner_cache;   /* autotune != 0: path of a JSON file that keeps the autotuner's
                                   choice per (device, arithmetic, kernel-source hash) across
                                   processes: a kept choice is used without tuning, a new one is

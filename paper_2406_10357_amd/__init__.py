@@ -42,7 +42,7 @@ class Options(C.Structure):
                 ("subbatch", C.c_int32), ("profile", C.c_int32), ("learned", C.c_int32),
                 ("log_frontier", C.c_int32), ("mlp_params", C.c_void_p), ("log_out", C.c_void_p),
                 ("log_cap", C.c_int64), ("autotune", C.c_int32), ("query_lanes", C.c_int32),
-                ("eps_relative", C.c_int32), ("pad0", C.c_int32), ("tuner_cache", C.c_char_p),
+                ("eps_relative", C.c_int32), ("query_shape", C.c_int32), ("tuner_cache", C.c_char_p),
                 ("round_log", C.c_void_p), ("round_log_cap", C.c_int64), ("test_bound_shift", C.c_double)]
 
 
@@ -197,7 +197,7 @@ def build_bvh(VB, FB) -> Bvh:
 def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
                  stack_depth=0, subbatch=0, profile=0, learned=0, mlp_params=None, log_out=None,
                  autotune=0, query_lanes=0, relative=False, tuner_cache=None, round_log=None,
-                 test_bound_shift=0.0) -> Options:
+                 test_bound_shift=0.0, query_shape=0) -> Options:
     """mlp_params: device FP32 tensor of mlp_nparams() values (learned > 0);
     log_out: device FP32 tensor (rows, 17) that receives the frontier log;
     relative: eps is the paper's relative tolerance (times dA) instead of an
@@ -211,6 +211,7 @@ def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity
     o.learned = learned
     o.autotune = autotune
     o.query_lanes = query_lanes
+    o.query_shape = query_shape
     o.eps_relative = 1 if relative else 0
     o.test_bound_shift = float(test_bound_shift)
     if tuner_cache is not None:

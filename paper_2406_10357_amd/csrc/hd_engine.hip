@@ -750,8 +750,9 @@ struct TileOrder {
 
 template <class T, int SD, int QB>
 __device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const TileOrder &to, const QueryCfg &cfg,
-                             const BView<T> &bv, const QueryOut<T> &out, const PairConst *__restrict__ pc,
-                             PairVar *pv, Ctl *ctl, int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
+                             const NodeSrc &ns, const BView<T> &bv, const QueryOut<T> &out,
+                             const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, int32_t *ovf_list, int *s_node,
+                             float *s_dist, QueryTally &t) {
     for (int64_t tt = to.first; to.valid(tt); tt += to.gx) {
         const int64_t i = to.tile(tt) * QB + threadIdx.x;
         unsigned long long lord = 0, key = 0;
@@ -763,7 +764,7 @@ __device__ void query_lanes1(const QueryIn<T> &in, int64_t n, const TileOrder &t
             QueryResult<T> r = empty_result<T>();
             seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
             LdsStack<SD, QB> stk{s_node, s_dist, 0};
-            r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
+            r = traverse<T>(ns, bv, cfg.ids, p, cfg.top ? TOP_REF : pc[qp.pair].root, stk, r);
             t.nb += r.nbox;
             t.nl += r.nleaf;
             t.nq += 1;
@@ -904,39 +905,41 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
 
 // ... and the block that finishes last redoes the queries whose LDS stack
 // overflowed (deep_queries).
-template <class T, int SD, int QB>
+// REFILL: the refilling one-lane form (its own instantiation: its lane state
+// would raise the register count, and so lower the occupancy, of the others)
+template <class T, int SD, int QB, bool REFILL>
 __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
                                               QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
-                                              Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max,
-                                              int refill) {
+                                              Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max) {
     static_assert(QB <= DEEP_SLOTS, "every thread of the last block has a deep-stack slot");
     __shared__ int s_node[SD * QB];
     __shared__ float s_dist[SD * QB];
-    __shared__ float4 s_top[TOP_NODES * 8];
+    __shared__ float4 s_top[TOP_NODES * sizeof(WideNode) / 16];
     const int64_t n = cnt.get();
     const bool quad = n <= quad_max;
     const TileOrder to(n, quad ? QB / 4 : QB);
     // (the refilling form runs every block of the grid, each taking queries
     // while its XCD's part has any)
-    const bool dyn = !quad && refill;
+    const bool dyn = REFILL && !quad;
     if (!dyn && !to.active()) return; // the grid is sized for a larger count
     if (dyn && n == 0) return;
     QueryTally t;
     if (dyn) {
         query_refill<T, SD, QB>(in, n, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
-    } else if (quad) {
-        // few queries, each bound by its chain of dependent node reads:
-        // stage the top levels of the tree, where every traversal starts, in
-        // LDS (without a table no reference reaches the copy)
+    } else {
+        // stage the top levels of the tree, where every traversal starts
+        // (and every greedy descent passes), in LDS: their reads leave the
+        // vector memory path (without a table no reference reaches the copy)
         if (cfg.top) {
             const float4 *src = reinterpret_cast<const float4 *>(cfg.top);
-            for (int i = threadIdx.x; i < TOP_NODES * 8; i += QB) s_top[i] = src[i];
+            for (int i = threadIdx.x; i < TOP_NODES * (int)(sizeof(WideNode) / 16); i += QB) s_top[i] = src[i];
             __syncthreads();
         }
         const NodeSrc ns{cfg.nodes, (LdsFloat *)s_top};
-        query_lanes4<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
-    } else {
-        query_lanes1<T, SD, QB>(in, n, to, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+        if (quad)
+            query_lanes4<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+        else
+            query_lanes1<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
     }
     unsigned long long *st = ctl->stat[acc_copy()];
     block_add<3, QB>({t.nb, t.nl, t.nq}, {st + ST_BOXES, st + ST_QLEAVES, st + ST_QUERIES});
@@ -963,7 +966,7 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
         QueryResult<T> r = empty_result<T>();
         seed_two(r, bv, p, qp.seed[0], qp.seed[1]);
         GlobalStack stk{stack_mem + threadIdx.x, DEEP_SLOTS, DEEP_STACK, 0};
-        r = traverse<T>(cfg.nodes, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
+        r = traverse<T>(NodeSrc{cfg.nodes, nullptr}, bv, cfg.ids, p, pc[qp.pair].root, stk, r);
         nb += r.nbox;
         nl += r.nleaf;
         // a traversal deeper than the fallback stack fails the call; its
@@ -987,8 +990,10 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
 struct QVariant {
     int sd, qb;
 };
-constexpr QVariant QVARIANTS[] = {{16, 128}, {8, 64}, {16, 64}, {32, 128}, {8, 256}, {16, 256}};
+constexpr QVariant QVARIANTS[] = {{16, 128}, {8, 64}, {16, 64}, {32, 128}, {8, 256},
+                                   {16, 256}, {12, 128}, {12, 256}, {24, 128}};
 constexpr int NQVAR = sizeof(QVARIANTS) / sizeof(QVARIANTS[0]);
+static_assert(NQVAR == HD_QUERY_SHAPES, "the header counts the launch shapes");
 
 // Launches of at most this many queries run a quad of lanes per query. Below
 // it the one-lane kernel holds too few waves to hide its latency: measured
@@ -1013,17 +1018,26 @@ inline unsigned qgrid_b(int64_t n, int qb, int64_t quad_max) {
 template <class T>
 void launch_query(int v, int64_t n_max, int64_t quad_max, const QueryIn<T> &qi, DevCount cnt, const QueryCfg &cfg,
                   const BView<T> &bv, const QueryOut<T> &out, const PairConst *pc, PairVar *pv, Ctl *ctl,
-                  int32_t *ovf, int2 *deep, hipStream_t s, int refill = 1) {
+                  int32_t *ovf, int2 *deep, hipStream_t s, int refill = 0) {
 #define HD_QLAUNCH(SD, QB)                                                                                             \
-    k_query<T, SD, QB><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf, deep,    \
-                                                                    quad_max, refill)
+    k_query<T, SD, QB, false><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf,   \
+                                                                           deep, quad_max)
+    // the refilling form has one launch shape (the default's)
+    if (refill && v >= 0) v = 100;
     switch (v) {
+    case 100:
+        k_query<T, 16, 128, true><<<qgrid_b(n_max, 128, quad_max), 128, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf,
+                                                                                deep, quad_max);
+        break;
     case -1: HD_QLAUNCH(SMALL_STACK, 128); break;
     case 1: HD_QLAUNCH(8, 64); break;
     case 2: HD_QLAUNCH(16, 64); break;
     case 3: HD_QLAUNCH(32, 128); break;
     case 4: HD_QLAUNCH(8, 256); break;
     case 5: HD_QLAUNCH(16, 256); break;
+    case 6: HD_QLAUNCH(12, 128); break;
+    case 7: HD_QLAUNCH(12, 256); break;
+    case 8: HD_QLAUNCH(24, 128); break;
     default: HD_QLAUNCH(16, 128); break;
     }
 #undef HD_QLAUNCH
@@ -2645,6 +2659,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cctx.norder = parse_order(opt.order, cctx.order);
     if (cctx.norder <= 0) throw Error{HD_E_INVALID, "bad cascade order"};
     if (opt.learned < 0 || opt.learned > 2) throw Error{HD_E_INVALID, "learned must be 0, 1 or 2"};
+    if (opt.query_shape < 0 || opt.query_shape > NQVAR) throw Error{HD_E_INVALID, "query_shape out of range"};
     if (opt.query_lanes != 0 && opt.query_lanes != 1 && opt.query_lanes != 2 && opt.query_lanes != 4)
         throw Error{HD_E_INVALID, "query_lanes must be 0, 1, 2 or 4"};
     if (opt.learned > 0 && !opt.mlp_params) throw Error{HD_E_INVALID, "learned mode needs the network's parameters"};
@@ -2846,7 +2861,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
                 HD_HIP(hipEventRecord(ws.tune_ev[0], s));
                 launch_query<T>(v, mA, -1, qi, nref_dev, tcfg, bv, tw.vq.o, pc, pv, ctl,
-                                ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s, qrefill);
+                                ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s, 0);
                 HD_HIP(hipEventRecord(ws.tune_ev[1], s));
                 HD_HIP(hipEventSynchronize(ws.tune_ev[1]));
                 float ms = 0;
@@ -2879,9 +2894,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             tuner_write(opt.tuner_cache, entries);
         }
     }
-    qsel = small_stack ? -1 : qvar;
-    S.query_block = qsel < 0 ? 128 : QVARIANTS[qsel].qb;
-    S.query_stack = qsel < 0 ? SMALL_STACK : QVARIANTS[qsel].sd;
+    qsel = small_stack ? -1 : (opt.query_shape > 0 ? opt.query_shape - 1 : qvar);
+    S.query_block = qsel < 0 || qrefill ? 128 : QVARIANTS[qsel].qb;
+    S.query_stack = qsel < 0 ? SMALL_STACK : (qrefill ? 16 : QVARIANTS[qsel].sd);
     S.query_lanes = opt.query_lanes;
     S.query_quad_max = qmax < 0 ? 0 : (qmax == INT64_MAX ? -1 : qmax);
 

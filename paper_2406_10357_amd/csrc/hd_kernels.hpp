@@ -243,6 +243,61 @@ HD_D void seed_two(QueryResult<T> &r, const BView<T> &bv, const V3<T> &p, int s0
     if (s1 >= 0) fold_leaf(r, F1, p, s1);
 }
 
+// Where a traversal reads wide nodes: references below TOP_REF from global
+// memory, TOP_REF + j from entry j of the top-level table staged in LDS
+// (typed as LDS, so that those reads are ds_read rather than flat loads).
+// Without a table no such reference occurs.
+typedef __attribute__((address_space(3))) const float LdsFloat;
+typedef __attribute__((address_space(3))) const int LdsInt;
+struct NodeSrc {
+    const WideNode *__restrict__ g;
+    LdsFloat *top; // the table as 16 words per node
+};
+
+// the four child boxes and references of wide node x, decoded
+struct WideView {
+    float4 lx, ly, lz, hx, hy, hz;
+    int4 ch;
+};
+HD_D WideView decode_wide(const uint4 &a, const int4 &ch, const uint4 &q0, const uint4 &q1) {
+    const float sx = wide_step(a.w, 0), sy = wide_step(a.w, 1), sz = wide_step(a.w, 2);
+    const float ox = __uint_as_float(a.x), oy = __uint_as_float(a.y), oz = __uint_as_float(a.z);
+    auto row = [](uint32_t w, float st, float o) {
+        return make_float4(wide_decode(w, 0, st, o), wide_decode(w, 1, st, o), wide_decode(w, 2, st, o),
+                           wide_decode(w, 3, st, o));
+    };
+    WideView v;
+    v.lx = row(q0.x, sx, ox);
+    v.ly = row(q0.y, sy, oy);
+    v.lz = row(q0.z, sz, oz);
+    v.hx = row(q0.w, sx, ox);
+    v.hy = row(q1.x, sy, oy);
+    v.hz = row(q1.y, sz, oz);
+    v.ch = ch;
+    return v;
+}
+HD_D WideView load_wide(const NodeSrc &ns, int x) {
+    if (x >= TOP_REF) {
+        LdsInt *t = (LdsInt *)ns.top + 16 * (x - TOP_REF);
+        auto u4 = [&](int o) {
+            return make_uint4((uint32_t)t[o], (uint32_t)t[o + 1], (uint32_t)t[o + 2], (uint32_t)t[o + 3]);
+        };
+        const uint4 c = u4(4);
+        return decode_wide(u4(0), make_int4((int)c.x, (int)c.y, (int)c.z, (int)c.w), u4(8), u4(12));
+    }
+    const uint4 *g = reinterpret_cast<const uint4 *>(ns.g + x);
+    const uint4 a = g[0], c = g[1], q0 = g[2], q1 = g[3];
+    return decode_wide(a, make_int4((int)c.x, (int)c.y, (int)c.z, (int)c.w), q0, q1);
+}
+
+// FP32 leaf frames in flight at once per lane in `traverse` (1, 2 or 4):
+// more loads in flight per lane against more registers, so fewer waves
+#ifndef HD_LEAF_BATCH
+#define HD_LEAF_BATCH 4
+#endif
+constexpr int LEAF_BATCH = HD_LEAF_BATCH;
+static_assert(LEAF_BATCH == 1 || LEAF_BATCH == 2 || LEAF_BATCH == 4, "leaf batch of 1, 2 or 4 frames");
+
 // Closest-first traversal from `root`, starting from the result `r` (empty,
 // or seeded with candidate triangles). A child box is entered only when its
 // distance is within (1 + 16u) of the best squared distance so far, which
@@ -266,13 +321,13 @@ HD_D void cswap(T &ea, int &fa, T &eb, int &fb) {
 // leaf, whose distance then bounds the real traversal (without it every
 // child would be in range and every sibling pushed).
 template <class T>
-HD_D void greedy_probe(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
-                       const V3<T> &p, int root, QueryResult<T> &r) {
+HD_D void greedy_probe(const NodeSrc &nodes, const BView<T> &bv, const int4 *__restrict__ ids, const V3<T> &p,
+                       int root, QueryResult<T> &r) {
     int x = root;
     for (int guard = 0; guard < 64 && x >= 0; ++guard) {
-        const WideNode *w = nodes + x;
-        const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
-        const int4 ch = w->child;
+        const WideView w = load_wide(nodes, x);
+        const float4 lx = w.lx, ly = w.ly, lz = w.lz, hx = w.hx, hy = w.hy, hz = w.hz;
+        const int4 ch = w.ch;
         T best = T(__builtin_inf());
         int pick = WIDE_EMPTY;
         auto consider = [&](float a, float b, float c, float d, float e, float f, int ref) {
@@ -298,8 +353,8 @@ HD_D void greedy_probe(const WideNode *__restrict__ nodes, const BView<T> &bv, c
 }
 
 template <class T, class Stack>
-HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
-                             const V3<T> &p, int root, Stack &st, QueryResult<T> r) {
+HD_D QueryResult<T> traverse(const NodeSrc &nodes, const BView<T> &bv, const int4 *__restrict__ ids, const V3<T> &p,
+                             int root, Stack &st, QueryResult<T> r) {
     const T slack = T(1) + T(16 * Prec<T>::u);
     const T inf = T(__builtin_inf());
     if (root < 0) {
@@ -313,9 +368,9 @@ HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> 
     bool lost = false;
     int restarts = 0;
     while (true) {
-        const WideNode *w = nodes + node;
-        const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
-        const int4 ch = w->child;
+        const WideView w = load_wide(nodes, node);
+        const float4 lx = w.lx, ly = w.ly, lz = w.lz, hx = w.hx, hy = w.hy, hz = w.hz;
+        const int4 ch = w.ch;
         T e0 = box_d2<T>(make_float4(lx.x, ly.x, lz.x, 0.f), make_float4(hx.x, hy.x, hz.x, 0.f), p);
         T e1 = box_d2<T>(make_float4(lx.y, ly.y, lz.y, 0.f), make_float4(hx.y, hy.y, hz.y, 0.f), p);
         T e2 = box_d2<T>(make_float4(lx.z, ly.z, lz.z, 0.f), make_float4(hx.z, hy.z, hz.z, 0.f), p);
@@ -328,12 +383,28 @@ HD_D QueryResult<T> traverse(const WideNode *__restrict__ nodes, const BView<T> 
             const T thr = r.d2 * slack;
             const bool l0 = f0 < 0 && f0 != WIDE_EMPTY && e0 <= thr, l1 = f1 < 0 && f1 != WIDE_EMPTY && e1 <= thr,
                        l2 = f2 < 0 && f2 != WIDE_EMPTY && e2 <= thr, l3 = f3 < 0 && f3 != WIDE_EMPTY && e3 <= thr;
-            if constexpr (sizeof(T) == 8) {
-                // FP64 frames are twice the size: one at a time
+            if constexpr (sizeof(T) == 8 || LEAF_BATCH == 1) {
+                // (FP64 frames are twice the size: one at a time)
                 if (l0) visit_leaf(r, bv, ids, p, ~f0);
                 if (l1 && e1 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f1);
                 if (l2 && e2 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f2);
                 if (l3 && e3 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f3);
+            } else if constexpr (LEAF_BATCH == 2) {
+                if (l0 || l1) {
+                    Frame<T> F0, F1;
+                    if (l0) F0 = load_frame(bv.frames, ~f0);
+                    if (l1) F1 = load_frame(bv.frames, ~f1);
+                    if (l0) fold_leaf(r, F0, p, ~f0);
+                    if (l1 && e1 <= r.d2 * slack) fold_leaf(r, F1, p, ~f1);
+                }
+                const bool m2 = l2 && e2 <= r.d2 * slack, m3 = l3 && e3 <= r.d2 * slack;
+                if (m2 || m3) {
+                    Frame<T> F2, F3;
+                    if (m2) F2 = load_frame(bv.frames, ~f2);
+                    if (m3) F3 = load_frame(bv.frames, ~f3);
+                    if (m2) fold_leaf(r, F2, p, ~f2);
+                    if (m3 && e3 <= r.d2 * slack) fold_leaf(r, F3, p, ~f3);
+                }
             } else if (l0 || l1 || l2 || l3) {
                 Frame<T> F0, F1, F2, F3;
                 if (l0) F0 = load_frame(bv.frames, ~f0);
@@ -433,9 +504,9 @@ HD_D bool trav_step(const WideNode *__restrict__ nodes, const BView<T> &bv, cons
     }
     if (s.probing) {
         // one level of the greedy descent: nearest box, nothing pushed
-        const WideNode *w = nodes + s.node;
-        const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
-        const int4 ch = w->child;
+        const WideView w = load_wide(NodeSrc{nodes, nullptr}, s.node);
+        const float4 lx = w.lx, ly = w.ly, lz = w.lz, hx = w.hx, hy = w.hy, hz = w.hz;
+        const int4 ch = w.ch;
         T best = T(__builtin_inf());
         int pick = WIDE_EMPTY;
         auto consider = [&](float a, float b, float c, float d, float e, float f, int ref) {
@@ -463,9 +534,9 @@ HD_D bool trav_step(const WideNode *__restrict__ nodes, const BView<T> &bv, cons
     }
     const T slack = T(1) + T(16 * Prec<T>::u);
     const T inf = T(__builtin_inf());
-    const WideNode *w = nodes + s.node;
-    const float4 lx = w->lox, ly = w->loy, lz = w->loz, hx = w->hix, hy = w->hiy, hz = w->hiz;
-    const int4 ch = w->child;
+    const WideView w = load_wide(NodeSrc{nodes, nullptr}, s.node);
+    const float4 lx = w.lx, ly = w.ly, lz = w.lz, hx = w.hx, hy = w.hy, hz = w.hz;
+    const int4 ch = w.ch;
     T e0 = box_d2<T>(make_float4(lx.x, ly.x, lz.x, 0.f), make_float4(hx.x, hy.x, hz.x, 0.f), p);
     T e1 = box_d2<T>(make_float4(lx.y, ly.y, lz.y, 0.f), make_float4(hx.y, hy.y, hz.y, 0.f), p);
     T e2 = box_d2<T>(make_float4(lx.z, ly.z, lz.z, 0.f), make_float4(hx.z, hy.z, hz.z, 0.f), p);
@@ -613,29 +684,31 @@ template <int SD, int NQ> struct QuadStack {
     HD_D void clear() { top = cnt = 0; }
 };
 
-// Where a quad's traversal reads wide nodes: references below TOP_REF from
-// global memory, TOP_REF + j from entry j of the top-level table staged in
-// LDS (typed as LDS, so that those reads are ds_read rather than flat loads).
-// Without a table no such reference occurs.
-typedef __attribute__((address_space(3))) const float LdsFloat;
-typedef __attribute__((address_space(3))) const int LdsInt;
-struct NodeSrc {
-    const WideNode *__restrict__ g;
-    LdsFloat *top; // the table as 32 words per node
-};
 
-// lane k's child of the wide node at b (32 words): box distance, reference
-template <class T, class F, class I> HD_D T slot_box_d2(F *b, I *c, int k, const V3<T> &p, int &ref) {
-    ref = c[24 + k];
-    return box_d2<T>(make_float4(b[k], b[4 + k], b[8 + k], 0.f), make_float4(b[12 + k], b[16 + k], b[20 + k], 0.f), p);
-}
+// lane k's child of wide node x: box distance, reference (the words of the
+// node that slot k needs, from the LDS table or global memory)
 template <class T> HD_D T slot_box_d2(const NodeSrc &ns, int x, int k, const V3<T> &p, int &ref) {
+    uint4 a;
+    uint32_t l0, l1, l2, h0, h1, h2;
     if (x >= TOP_REF) {
-        LdsFloat *b = ns.top + 32 * (x - TOP_REF);
-        return slot_box_d2<T>(b, (LdsInt *)b, k, p, ref);
+        LdsInt *t = (LdsInt *)ns.top + 16 * (x - TOP_REF);
+        a = make_uint4((uint32_t)t[0], (uint32_t)t[1], (uint32_t)t[2], (uint32_t)t[3]);
+        ref = t[4 + k];
+        l0 = (uint32_t)t[8], l1 = (uint32_t)t[9], l2 = (uint32_t)t[10], h0 = (uint32_t)t[11];
+        h1 = (uint32_t)t[12], h2 = (uint32_t)t[13];
+    } else {
+        const uint4 *g = reinterpret_cast<const uint4 *>(ns.g + x);
+        a = g[0];
+        ref = reinterpret_cast<const int *>(g)[4 + k];
+        const uint4 q0 = g[2];
+        const uint2 q1 = reinterpret_cast<const uint2 *>(g)[6];
+        l0 = q0.x, l1 = q0.y, l2 = q0.z, h0 = q0.w, h1 = q1.x, h2 = q1.y;
     }
-    const float *b = reinterpret_cast<const float *>(ns.g + x);
-    return slot_box_d2<T>(b, reinterpret_cast<const int *>(b), k, p, ref);
+    const float sx = wide_step(a.w, 0), sy = wide_step(a.w, 1), sz = wide_step(a.w, 2);
+    const float ox = __uint_as_float(a.x), oy = __uint_as_float(a.y), oz = __uint_as_float(a.z);
+    return box_d2<T>(make_float4(wide_decode(l0, k, sx, ox), wide_decode(l1, k, sy, oy), wide_decode(l2, k, sz, oz), 0.f),
+                     make_float4(wide_decode(h0, k, sx, ox), wide_decode(h1, k, sy, oy), wide_decode(h2, k, sz, oz), 0.f),
+                     p);
 }
 
 // The traversal of `traverse` (same pruning, same order of descent, same
