@@ -37,12 +37,11 @@ sys.path.insert(0, ROOT)
 METRIC = "time to eps-certified h(A,B) (ms), learned vs plain; point-tri dist evals/s"
 
 # Algorithmic work per unit in the query kernel (LBVH traversal + point-triangle
-# distances). Bytes: a four-wide node is 64 B (16 B per box test: four child
-# boxes on an 8-bit grid and their references), a leaf's FP32 frame 64 B, a
-# query reads its point (3 x 8 B) and writes d, I, q, p and its key (40 B).
-# FP32 operations counted from the source of the frame evaluation and the box
-# test (an FMA counts as 2; the grid decode of a box is not counted).
-BYTES_PER_NODE = 64
+# distances). Bytes: a four-wide node is one 128 B line (32 B per box test), a
+# leaf's FP32 frame 64 B, a query reads its point (3 x 8 B) and writes d, I,
+# q, p and its key (40 B). FP32 operations counted from the source of the
+# frame evaluation and the box test (an FMA counts as 2).
+BYTES_PER_NODE = 128
 BYTES_PER_LEAF = 64
 BYTES_PER_QUERY = 64
 BOXES_PER_NODE = 4
@@ -249,7 +248,7 @@ def roofline(results, tuned, traffic):
         "unit": "GB/s",
         "frac": achieved / PEAK_HBM,
         "traffic": traffic,
-        "achieved_note": "algorithmic bytes (64 B per wide node visited, 64 B per leaf frame, 64 B per query) "
+        "achieved_note": "algorithmic bytes (128 B per wide node visited, 64 B per leaf frame, 64 B per query) "
                          "over the launch time; most of them are served by the L2 and the Infinity Cache",
         "launches": q_launch,
         "avg_launch_ms": avg_ms,

@@ -92,11 +92,9 @@ typedef struct {
                                   calls; 2: retune on this call; 0: use the kept choice */
     int32_t query_lanes;       /* lanes per point query: 0 automatic (a quad of four lanes per
                                   query in query launches of at most 32768 queries, where one
-                                  lane per query leaves the GPU latency-bound; above, one static
-                                  query per lane); 1 always one static query per lane; 2 one lane
-                                  per query with refills (a lane whose query ends takes the next
-                                  one; slower than static lanes on the paper's workloads, kept as
-                                  an option); 4 always a quad. Results do not depend on it. */
+                                  lane per query leaves the GPU latency-bound; above, one query
+                                  per lane); 1 always one lane per query; 4 always a quad.
+                                  Results do not depend on it. */
     int32_t eps_relative;      /* 0 (default): eps is the absolute tolerance, U - L <= eps;
                                   1: eps is the paper's relative tolerance (eq. output_bounds),
                                   U - L <= eps * dA, dA computed on the device from A */
@@ -266,15 +264,12 @@ hd_status hd_hausdorff(const double *VA, int64_t mA, const int32_t *FA, int64_t 
  * doubles), closest face of B as its original index (device, nP int32) and
  * closest points (device, nP x 3 doubles; may be NULL). precision selects
  * FP64 or FP32 arithmetic (HD_PREC_FP32 and HD_PREC_FP32_RECHECK both mean
- * FP32 here). lanes (0 or 1: one lane per point; 2: one lane per point with
- * refills; 4: a quad of lanes per
+ * FP32 here). lanes (0 or 1: one lane per point; 4: a quad of lanes per
  * point) selects the query kernel; the results do not depend on it. This is
  * the per-vertex query of the Implementation section, exposed for testing
  * and reuse. HD_E_INVALID for other values of lanes. */
 hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh B, int32_t precision, int32_t lanes,
                              double *d, int32_t *I, double *Q, hd_stream_t stream);
-/* (lanes: 0 or 1 one lane per point, 2 one lane per point with refills, 4 a
- * quad of lanes per point) */
 
 /* hd_point_distances for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

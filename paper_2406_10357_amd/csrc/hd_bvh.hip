@@ -623,60 +623,25 @@ __device__ void wide_node(int64_t i, const int32_t *__restrict__ childL, const i
             put(childR[c]);
         }
     }
+    WideNode w;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-        if (s >= k) ref[s] = WIDE_EMPTY;
-    // the grid: per axis the origin is the least lower corner of the used
-    // slots, and the step the smallest power of two whose 255th point
-    // reaches their largest upper corner
-    float o[3];
-    uint32_t eb[3];
-    uint32_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+        if (s >= k) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        float a = lo[d][0], b = hi[d][0];
-#pragma unroll
-        for (int s = 1; s < 4; ++s)
-            if (s < k) {
-                a = fminf(a, lo[d][s]);
-                b = fmaxf(b, hi[d][s]);
+            for (int d = 0; d < 3; ++d) {
+                lo[d][s] = 0.f;
+                hi[d][s] = 0.f;
             }
-        o[d] = a;
-        int e = -126;
-        const float ext = b - a;
-        if (ext > 0) {
-            frexpf(ext / 255.f, &e); // ext / 255 < 2^e
-            e = e < -126 ? -126 : (e > 127 ? 127 : e);
+            ref[s] = WIDE_EMPTY;
         }
-        while (e < 127 && __builtin_fmaf(255.f, __uint_as_float((uint32_t)(e + 127) << 23), a) < b) ++e;
-        eb[d] = (uint32_t)(e + 127);
-        const float step = __uint_as_float(eb[d] << 23);
-        // lower code: the largest whose grid point lies at or below the
-        // corner; upper code: the smallest at or above (both exist: code 0
-        // is the origin, code 255 reaches the largest upper corner)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (s >= k) continue;
-            int ql = (int)floorf((lo[d][s] - a) / step);
-            ql = ql < 0 ? 0 : (ql > 255 ? 255 : ql);
-            while (ql < 255 && __builtin_fmaf((float)(ql + 1), step, a) <= lo[d][s]) ++ql;
-            while (ql > 0 && __builtin_fmaf((float)ql, step, a) > lo[d][s]) --ql;
-            int qh = (int)ceilf((hi[d][s] - a) / step);
-            qh = qh < 0 ? 0 : (qh > 255 ? 255 : qh);
-            while (qh > 0 && __builtin_fmaf((float)(qh - 1), step, a) >= hi[d][s]) --qh;
-            while (qh < 255 && __builtin_fmaf((float)qh, step, a) < hi[d][s]) ++qh;
-            qlo[d] |= (uint32_t)ql << (8 * s);
-            qhi[d] |= (uint32_t)qh << (8 * s);
-        }
-    }
-    WideNode w;
-    w.ox = o[0];
-    w.oy = o[1];
-    w.oz = o[2];
-    w.exps = eb[0] | (eb[1] << 8) | (eb[2] << 16) | ((uint32_t)k << 24);
+    w.lox = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+    w.loy = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+    w.loz = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+    w.hix = make_float4(hi[0][0], hi[0][1], hi[0][2], hi[0][3]);
+    w.hiy = make_float4(hi[1][0], hi[1][1], hi[1][2], hi[1][3]);
+    w.hiz = make_float4(hi[2][0], hi[2][1], hi[2][2], hi[2][3]);
     w.child = make_int4(ref[0], ref[1], ref[2], ref[3]);
-    w.q0 = make_uint4(qlo[0], qlo[1], qlo[2], qhi[0]);
-    w.q1 = make_uint4(qhi[1], qhi[2], 0u, 0u);
+    w.meta = make_int4(k, 0, 0, 0);
     out[i] = w;
 }
 

@@ -108,9 +108,6 @@ struct Ctl {
     int sel_mode;                  // SEL_NONE, SEL_ALL or SEL_THRESHOLD
     int learn_off;                 // learned order: a round found no record predicted to raise L, so
                                    // every later round splits all live records (no more scoring)
-    // the query kernel's refilling form: next query of each XCD's part (zero
-    // between launches), one 256-byte line each
-    alignas(256) unsigned long long qfetch[8 * 32];
     alignas(256) unsigned long long sel_prom;  // learned order: live records predicted above L + eps
     alignas(256) unsigned long long sel_next;  // selected parents appended (their record indices)
     alignas(256) unsigned long long rest_next; // unselected live records appended
@@ -819,85 +816,6 @@ __device__ void query_lanes4(const QueryIn<T> &in, int64_t n, const TileOrder &t
     }
 }
 
-// The refilling form for large launches: each lane runs one query at a time
-// and, when it finishes, takes the next one from its XCD's part of the
-// launch (one atomic per wave and refill), instead of waiting for the
-// slowest lane of its wave (with one static query per lane, about 40% of a
-// wave's lanes were active per instruction on the large torus). The lanes
-// of a wave then traverse different queries one node per step.
-constexpr int QFETCH_STRIDE = 32; // u64 per fetch counter (256 bytes)
-template <class T, int SD, int QB>
-__device__ void query_refill(const QueryIn<T> &in, int64_t n, const QueryCfg &cfg, const BView<T> &bv,
-                             const QueryOut<T> &out, const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl,
-                             int32_t *ovf_list, int *s_node, float *s_dist, QueryTally &t) {
-    // this block's XCD takes the queries of its own contiguous part (nearby
-    // points, shared tree paths in that XCD's L2)
-    const unsigned xs = gridDim.x % XCDS == 0 ? XCDS : 1;
-    const unsigned x = blockIdx.x % xs;
-    const int64_t per = (n + xs - 1) / xs;
-    const int64_t lo = (int64_t)x * per, hi = lo + per < n ? lo + per : n;
-    unsigned long long *ctr = &ctl->qfetch[x * QFETCH_STRIDE];
-    const int lane = __lane_id();
-    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    LdsStack<SD, QB> stk{s_node, s_dist, 0};
-    TravState<T> ts;
-    QPoint qp;
-    int64_t i = -1;
-    bool more = lo < hi;
-    // what this lane raises its pair's L and round key to (flushed when the
-    // pair changes, and at the end)
-    unsigned long long lord = 0, key = 0;
-    int cur_pair = 0;
-    while (true) {
-        const bool need = i < 0 && more;
-        const unsigned long long m = __ballot(need);
-        if (m) {
-            const int leader = __ffsll(m) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
-            base = __shfl(base, leader, 64);
-            if (need) {
-                const int64_t k = lo + (int64_t)base + __popcll(m & below);
-                if (k < hi) {
-                    i = k;
-                    qp = query_point(in, i);
-                    if (qp.pair != cur_pair) {
-                        if (lord) atomicMax(&pv[cur_pair].Lord, lord);
-                        if (key) atomicMax(&pv[cur_pair].round_key, key);
-                        lord = key = 0;
-                        cur_pair = qp.pair;
-                    }
-                    ts.p = cvt<T>(qp.p);
-                    ts.r = empty_result<T>();
-                    seed_two(ts.r, bv, ts.p, qp.seed[0], qp.seed[1]);
-                    stk.clear();
-                    trav_begin(ts, pc[qp.pair].root);
-                } else {
-                    more = false;
-                }
-            }
-        }
-        if (__ballot(i >= 0) == 0) break;
-        if (i >= 0 && trav_step<T>(cfg.nodes, bv, cfg.ids, ts, stk)) {
-            t.nb += ts.r.nbox;
-            t.nl += ts.r.nleaf;
-            t.nq += 1;
-            if (ts.r.overflow) {
-                const int k = atomicAdd(&ctl->n_overflow, 1);
-                ovf_list[k] = (int32_t)i;
-                t.ovf = 1;
-            } else {
-                unsigned long long a, b;
-                finish_query<T>(cfg, bv, ts.r, qp, ts.p, out, pc, &a, &b);
-                lord = a > lord ? a : lord;
-                key = b > key ? b : key;
-            }
-            i = -1;
-        }
-    }
-    pair_max2(pv, cur_pair, lord, key);
-}
-
 template <class T>
 __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BView<T> &bv, const QueryOut<T> &out,
                              const PairConst *__restrict__ pc, PairVar *pv, Ctl *ctl, const int32_t *ovf_list,
@@ -905,49 +823,39 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
 
 // ... and the block that finishes last redoes the queries whose LDS stack
 // overflowed (deep_queries).
-// REFILL: the refilling one-lane form (its own instantiation: its lane state
-// would raise the register count, and so lower the occupancy, of the others)
-template <class T, int SD, int QB, bool REFILL>
+template <class T, int SD, int QB>
 __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, QueryCfg cfg, BView<T> bv,
                                               QueryOut<T> out, const PairConst *__restrict__ pc, PairVar *pv,
                                               Ctl *ctl, int32_t *ovf_list, int2 *deep_stack, int64_t quad_max) {
     static_assert(QB <= DEEP_SLOTS, "every thread of the last block has a deep-stack slot");
     __shared__ int s_node[SD * QB];
     __shared__ float s_dist[SD * QB];
-    __shared__ float4 s_top[TOP_NODES * sizeof(WideNode) / 16];
+    constexpr int TOP_F4 = WIDE_WORDS / 4; // float4 per table entry
+    __shared__ float4 s_top[TOP_NODES * TOP_F4];
     const int64_t n = cnt.get();
     const bool quad = n <= quad_max;
     const TileOrder to(n, quad ? QB / 4 : QB);
-    // (the refilling form runs every block of the grid, each taking queries
-    // while its XCD's part has any)
-    const bool dyn = REFILL && !quad;
-    if (!dyn && !to.active()) return; // the grid is sized for a larger count
-    if (dyn && n == 0) return;
+    if (!to.active()) return; // the grid is sized for a larger count
     QueryTally t;
-    if (dyn) {
-        query_refill<T, SD, QB>(in, n, cfg, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
-    } else {
-        // stage the top levels of the tree, where every traversal starts
-        // (and every greedy descent passes), in LDS: their reads leave the
-        // vector memory path (without a table no reference reaches the copy)
-        if (cfg.top) {
-            const float4 *src = reinterpret_cast<const float4 *>(cfg.top);
-            for (int i = threadIdx.x; i < TOP_NODES * (int)(sizeof(WideNode) / 16); i += QB) s_top[i] = src[i];
-            __syncthreads();
-        }
-        const NodeSrc ns{cfg.nodes, (LdsFloat *)s_top};
-        if (quad)
-            query_lanes4<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
-        else
-            query_lanes1<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    // stage the top levels of the tree, where every traversal starts (and
+    // every greedy descent passes), in LDS: the words a traversal reads of
+    // each entry (without a table no reference reaches the copy)
+    if (cfg.top) {
+        const float4 *src = reinterpret_cast<const float4 *>(cfg.top);
+        constexpr int NODE_F4 = (int)(sizeof(WideNode) / 16);
+        for (int i = threadIdx.x; i < TOP_NODES * TOP_F4; i += QB) s_top[i] = src[(i / TOP_F4) * NODE_F4 + i % TOP_F4];
+        __syncthreads();
     }
+    const NodeSrc ns{cfg.nodes, (LdsFloat *)s_top};
+    if (quad)
+        query_lanes4<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
+    else
+        query_lanes1<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
     unsigned long long *st = ctl->stat[acc_copy()];
     block_add<3, QB>({t.nb, t.nl, t.nq}, {st + ST_BOXES, st + ST_QLEAVES, st + ST_QUERIES});
     // the last block reads only the overflow list (and its atomic count)
-    if (last_block(&ctl->q_done, dyn ? gridDim.x : to.active_blocks(), __syncthreads_or(t.ovf) != 0)) {
+    if (last_block(&ctl->q_done, to.active_blocks(), __syncthreads_or(t.ovf) != 0))
         deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
-        if (threadIdx.x < XCDS) ctl->qfetch[threadIdx.x * QFETCH_STRIDE] = 0; // for the next launch
-    }
 }
 
 // queries whose LDS stack overflowed, redone with a deep stack in global
@@ -1018,17 +926,11 @@ inline unsigned qgrid_b(int64_t n, int qb, int64_t quad_max) {
 template <class T>
 void launch_query(int v, int64_t n_max, int64_t quad_max, const QueryIn<T> &qi, DevCount cnt, const QueryCfg &cfg,
                   const BView<T> &bv, const QueryOut<T> &out, const PairConst *pc, PairVar *pv, Ctl *ctl,
-                  int32_t *ovf, int2 *deep, hipStream_t s, int refill = 0) {
+                  int32_t *ovf, int2 *deep, hipStream_t s) {
 #define HD_QLAUNCH(SD, QB)                                                                                             \
-    k_query<T, SD, QB, false><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf,   \
-                                                                           deep, quad_max)
-    // the refilling form has one launch shape (the default's)
-    if (refill && v >= 0) v = 100;
+    k_query<T, SD, QB><<<qgrid_b(n_max, QB, quad_max), QB, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf, deep,    \
+                                                                    quad_max)
     switch (v) {
-    case 100:
-        k_query<T, 16, 128, true><<<qgrid_b(n_max, 128, quad_max), 128, 0, s>>>(qi, cnt, cfg, bv, out, pc, pv, ctl, ovf,
-                                                                                deep, quad_max);
-        break;
     case -1: HD_QLAUNCH(SMALL_STACK, 128); break;
     case 1: HD_QLAUNCH(8, 64); break;
     case 2: HD_QLAUNCH(16, 64); break;
@@ -2660,8 +2562,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     if (cctx.norder <= 0) throw Error{HD_E_INVALID, "bad cascade order"};
     if (opt.learned < 0 || opt.learned > 2) throw Error{HD_E_INVALID, "learned must be 0, 1 or 2"};
     if (opt.query_shape < 0 || opt.query_shape > NQVAR) throw Error{HD_E_INVALID, "query_shape out of range"};
-    if (opt.query_lanes != 0 && opt.query_lanes != 1 && opt.query_lanes != 2 && opt.query_lanes != 4)
-        throw Error{HD_E_INVALID, "query_lanes must be 0, 1, 2 or 4"};
+    if (opt.query_lanes != 0 && opt.query_lanes != 1 && opt.query_lanes != 4)
+        throw Error{HD_E_INVALID, "query_lanes must be 0, 1 or 4"};
     if (opt.learned > 0 && !opt.mlp_params) throw Error{HD_E_INVALID, "learned mode needs the network's parameters"};
     if (opt.log_frontier && (!opt.log_out || opt.log_cap <= 0)) throw Error{HD_E_INVALID, "frontier log needs a buffer"};
     for (int p = 0; p < (in.eps_per_pair ? np : 1); ++p)
@@ -2802,10 +2704,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     int qsel = 0; // the launch shape this call uses (set after the autotuner)
     // launches of at most qmax queries run a quad of lanes per query
     const int64_t qmax =
-        opt.query_lanes == 1 || opt.query_lanes == 2 ? -1 : (opt.query_lanes == 4 ? INT64_MAX : QUAD_MAX_DEFAULT);
-    // one lane per query: one static query per lane, except with
-    // query_lanes = 2 (lanes refill with new queries as theirs finish)
-    const int qrefill = opt.query_lanes == 2 ? 1 : 0;
+        opt.query_lanes == 1 ? -1 : (opt.query_lanes == 4 ? INT64_MAX : QUAD_MAX_DEFAULT);
 
     // queries: n_max bounds the count (host count, or the device-planned one),
     // the grid covers it up to a persistent cap and loops beyond
@@ -2814,7 +2713,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         ws.ovf.reserve((size_t)n_max * sizeof(int32_t));
         prof.mark(prof.q);
         launch_query<T>(qsel, n_max, qmax, qi, cnt, qcfg, bv, out, pc, pv, ctl, ws.ovf.as<int32_t>(),
-                        ws.deep.as<int2>(), s, qrefill);
+                        ws.deep.as<int2>(), s);
         prof.mark(prof.q);
         const L64Cfg l64{B->nodes.as<WideNode>(), bv64, iv.ids, pc, np, ws.gstack.as<int2>(), check_fp32};
         k_argmax_finalize<T><<<std::min<unsigned>(grid_for(n_max, BLK), GRID_MAX), BLK, 0, s>>>(qi, cnt, out.key,
@@ -2861,7 +2760,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 k_zero_query_stats<<<1, 64, 0, s>>>(ctl);
                 HD_HIP(hipEventRecord(ws.tune_ev[0], s));
                 launch_query<T>(v, mA, -1, qi, nref_dev, tcfg, bv, tw.vq.o, pc, pv, ctl,
-                                ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s, 0);
+                                ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
                 HD_HIP(hipEventRecord(ws.tune_ev[1], s));
                 HD_HIP(hipEventSynchronize(ws.tune_ev[1]));
                 float ms = 0;
@@ -2895,8 +2794,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         }
     }
     qsel = small_stack ? -1 : (opt.query_shape > 0 ? opt.query_shape - 1 : qvar);
-    S.query_block = qsel < 0 || qrefill ? 128 : QVARIANTS[qsel].qb;
-    S.query_stack = qsel < 0 ? SMALL_STACK : (qrefill ? 16 : QVARIANTS[qsel].sd);
+    S.query_block = qsel < 0 ? 128 : QVARIANTS[qsel].qb;
+    S.query_stack = qsel < 0 ? SMALL_STACK : QVARIANTS[qsel].sd;
     S.query_lanes = opt.query_lanes;
     S.query_quad_max = qmax < 0 ? 0 : (qmax == INT64_MAX ? -1 : qmax);
 
@@ -2988,7 +2887,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const QueryCfg bcfg{B->nodes.as<WideNode>(), B->ids.as<int4>(), 0, top};
             ws.ovf.reserve((size_t)n * sizeof(int32_t));
             launch_query<T>(qsel, n, qmax, qi, DevCount{&ctl->b_next, 1, 0}, bcfg, bv, tw.bq.o, pc, pv, ctl,
-                            ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s, qrefill);
+                            ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
             Sb = tw.bq.o.I;
         }
         if (opt.learned == 2)
@@ -3303,7 +3202,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             const int64_t nq = LATTICE_PTS * K;
             ws.ovf.reserve((size_t)nq * sizeof(int32_t));
             launch_query<T>(qsel, nq, qmax, li, host_count(nq), lcfg, bv, tw.lq.o, pc, pv, ctl, ws.ovf.as<int32_t>(),
-                            ws.deep.as<int2>(), s, qrefill);
+                            ws.deep.as<int2>(), s);
             k_log_parents<T><<<grid_for(K, BLK), BLK, 0, s>>>(tw.act.v, K, tw.lq.o, lc, bv, opt.log_out, logged,
                                                               opt.log_cap);
             HD_LAUNCH_CHECK();
@@ -3654,7 +3553,7 @@ hd_status hd_hausdorff(const double *VA, int64_t mA, const int32_t *FA, int64_t 
 hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, int32_t lanes, double *d,
                              int32_t *I, double *Q, hd_stream_t stream) {
     if (!Bh || nP < 0 || (nP > 0 && (!P || !d || !I))) return HD_E_INVALID;
-    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return HD_E_INVALID;
+    if (lanes != 0 && lanes != 1 && lanes != 4) return HD_E_INVALID;
     if (nP == 0) return HD_OK;
     const Bvh *B = reinterpret_cast<const Bvh *>(Bh);
     hipStream_t s = (hipStream_t)stream;
@@ -3687,7 +3586,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
             launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qb.o, pc, pv, ctl,
-                            ovf.as<int32_t>(), deep.as<int2>(), s, lanes == 2 ? 1 : 0);
+                            ovf.as<int32_t>(), deep.as<int2>(), s);
             k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qb.o, nP, B->ids.as<int4>(), pc, d, I, Q, ctl,
                                                                  nullptr);
             HD_LAUNCH_CHECK();
@@ -3705,7 +3604,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
 hd_status hd_point_distances_noalloc(const double *P, int64_t nP, hd_bvh Bh, int32_t precision, int32_t lanes,
                                      double *d, int32_t *I, double *Q, int32_t *err, hd_stream_t stream) {
     if (!Bh || !err || nP < 0 || (nP > 0 && (!P || !d || !I))) return HD_E_INVALID;
-    if (lanes != 0 && lanes != 1 && lanes != 2 && lanes != 4) return HD_E_INVALID;
+    if (lanes != 0 && lanes != 1 && lanes != 4) return HD_E_INVALID;
     if (precision != HD_PREC_FP64 && precision != HD_PREC_FP32 && precision != HD_PREC_FP32_RECHECK)
         return HD_E_INVALID;
     if (nP > HD_NOALLOC_MAX_POINTS) return HD_E_CAPACITY;
@@ -3743,7 +3642,7 @@ hd_status hd_point_distances_noalloc(const double *P, int64_t nP, hd_bvh Bh, int
             if constexpr (sizeof(T) == 4) bv = BView<float>{B->frames32.as<float4>()};
             else bv = BView<double>{B->frames64.as<double2>()};
             launch_query<T>(0, nP, lanes == 4 ? INT64_MAX : -1, qi, host_count(nP), cfg, bv, qo, pc, pv, ctl, ovf,
-                            deep, s, lanes == 2 ? 1 : 0);
+                            deep, s);
             k_export_points<T><<<grid_for(nP, BLK), BLK, 0, s>>>(qo, nP, B->ids.as<int4>(), pc, d, I, Q, ctl, err);
             HD_LAUNCH_CHECK();
         };

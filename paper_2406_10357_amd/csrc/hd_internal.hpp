@@ -81,8 +81,8 @@ struct Bvh {
     int device = 0;
     int npairs = 0;
     int64_t nB = 0;
-    DBuf nodes;    // four-wide nodes x 64 B (at most nB - 1 of them)
-    DBuf top;      // TOP_NODES x 64 B: the top levels of pair 0 (single-pair BVHs with an internal root)
+    DBuf nodes;    // four-wide nodes x 128 B (at most nB - 1 of them)
+    DBuf top;      // TOP_NODES x 128 B: the top levels of pair 0 (single-pair BVHs with an internal root)
     DBuf frames32; // nB x 64 B
     DBuf frames64; // nB x 128 B
     DBuf ids;      // nB x int4: corner vertex ids (frame order), original face index in its pair
@@ -159,37 +159,22 @@ void recycle_bvh(Bvh *b);
 // returns the previous setting
 int set_build_graphs(int enable);
 
-// Four-wide BVH node in 64 bytes: the boxes of up to four children on an
-// 8-bit grid per axis over the node (origin o_d, step 2^e_d), and their
-// references. Component d of child k decodes as
-//     lo = fma(q_lo, 2^e_d, o_d),   hi = fma(q_hi, 2^e_d, o_d)
-// (one rounding, computed the same way wherever a node is read), and the
-// builder picks the codes so that the decoded box contains the child's float
-// box: a traversal prunes conservatively, with four 16-byte loads per node.
-// A reference >= 0 is a wide node, WIDE_EMPTY an unused slot, any other
-// negative value the leaf ~ref (sorted triangle index).
+// Four-wide BVH node, one 128-byte line: the boxes of up to four children
+// (structure of arrays: component c of child k at lo*/hi*[k]) and their
+// references. A reference >= 0 is a wide node, WIDE_EMPTY an unused slot, any
+// other negative value the leaf ~ref (sorted triangle index).
 constexpr int32_t WIDE_EMPTY = INT32_MIN;
-struct alignas(64) WideNode {
-    float ox, oy, oz; // grid origin
-    uint32_t exps;    // byte d < 3: e_d + 127; byte 3: number of used slots
+struct alignas(128) WideNode {
+    float4 lox, loy, loz, hix, hiy, hiz;
     int4 child;
-    uint4 q0; // byte k of .x, .y, .z, .w: lo x, lo y, lo z, hi x of child k
-    uint4 q1; // byte k of .x, .y: hi y, hi z of child k; .z, .w zero
+    int4 meta; // (number of used slots, 0, 0, 0)
 };
-static_assert(sizeof(WideNode) == 64, "four 16-byte loads per node");
-
-// grid step of axis d (biased exponent byte d of exps, a normal float)
-__device__ __forceinline__ float wide_step(uint32_t exps, int d) {
-    return __uint_as_float(((exps >> (8 * d)) & 0xffu) << 23);
-}
-// code k (byte k of word w) on the grid
-__device__ __forceinline__ float wide_decode(uint32_t w, int k, float step, float o) {
-    return __builtin_fmaf((float)((w >> (8 * k)) & 0xffu), step, o);
-}
+static_assert(sizeof(WideNode) == 128, "one cache line per node");
+constexpr int WIDE_WORDS = 28; // the words a traversal reads (boxes and references)
 
 // The top levels of a single-pair BVH (its root, the root's children and
 // their children: at most 1 + 4 + 16 nodes), copied into a table that query
-// kernels stage in LDS: entry 0 the root, 1 + k its child slot k, 5 + 4k + m
+// kernels stage in LDS (the first WIDE_WORDS words of each): entry 0 the root, 1 + k its child slot k, 5 + 4k + m
 // slot m of that child (entries for empty or leaf slots unused). Inside the
 // table a child that is itself tabled is referenced as TOP_REF + its entry;
 // other references are unchanged.

@@ -251,43 +251,38 @@ typedef __attribute__((address_space(3))) const float LdsFloat;
 typedef __attribute__((address_space(3))) const int LdsInt;
 struct NodeSrc {
     const WideNode *__restrict__ g;
-    LdsFloat *top; // the table as 16 words per node
+    LdsFloat *top; // the table as WIDE_WORDS words per node
 };
 
-// the four child boxes and references of wide node x, decoded
+// the four child boxes and references of wide node x
 struct WideView {
     float4 lx, ly, lz, hx, hy, hz;
     int4 ch;
 };
-HD_D WideView decode_wide(const uint4 &a, const int4 &ch, const uint4 &q0, const uint4 &q1) {
-    const float sx = wide_step(a.w, 0), sy = wide_step(a.w, 1), sz = wide_step(a.w, 2);
-    const float ox = __uint_as_float(a.x), oy = __uint_as_float(a.y), oz = __uint_as_float(a.z);
-    auto row = [](uint32_t w, float st, float o) {
-        return make_float4(wide_decode(w, 0, st, o), wide_decode(w, 1, st, o), wide_decode(w, 2, st, o),
-                           wide_decode(w, 3, st, o));
-    };
-    WideView v;
-    v.lx = row(q0.x, sx, ox);
-    v.ly = row(q0.y, sy, oy);
-    v.lz = row(q0.z, sz, oz);
-    v.hx = row(q0.w, sx, ox);
-    v.hy = row(q1.x, sy, oy);
-    v.hz = row(q1.y, sz, oz);
-    v.ch = ch;
-    return v;
-}
 HD_D WideView load_wide(const NodeSrc &ns, int x) {
+    WideView v;
     if (x >= TOP_REF) {
-        LdsInt *t = (LdsInt *)ns.top + 16 * (x - TOP_REF);
-        auto u4 = [&](int o) {
-            return make_uint4((uint32_t)t[o], (uint32_t)t[o + 1], (uint32_t)t[o + 2], (uint32_t)t[o + 3]);
-        };
-        const uint4 c = u4(4);
-        return decode_wide(u4(0), make_int4((int)c.x, (int)c.y, (int)c.z, (int)c.w), u4(8), u4(12));
+        LdsFloat *t = ns.top + WIDE_WORDS * (x - TOP_REF);
+        auto f4 = [&](int o) { return make_float4(t[o], t[o + 1], t[o + 2], t[o + 3]); };
+        v.lx = f4(0);
+        v.ly = f4(4);
+        v.lz = f4(8);
+        v.hx = f4(12);
+        v.hy = f4(16);
+        v.hz = f4(20);
+        LdsInt *c = (LdsInt *)t + 24;
+        v.ch = make_int4(c[0], c[1], c[2], c[3]);
+        return v;
     }
-    const uint4 *g = reinterpret_cast<const uint4 *>(ns.g + x);
-    const uint4 a = g[0], c = g[1], q0 = g[2], q1 = g[3];
-    return decode_wide(a, make_int4((int)c.x, (int)c.y, (int)c.z, (int)c.w), q0, q1);
+    const WideNode *w = ns.g + x;
+    v.lx = w->lox;
+    v.ly = w->loy;
+    v.lz = w->loz;
+    v.hx = w->hix;
+    v.hy = w->hiy;
+    v.hz = w->hiz;
+    v.ch = w->child;
+    return v;
 }
 
 // FP32 leaf frames in flight at once per lane in `traverse` (1, 2 or 4):
@@ -467,147 +462,6 @@ HD_D QueryResult<T> traverse(const NodeSrc &nodes, const BView<T> &bv, const int
 }
 
 // ---------------------------------------------------------------------------
-// The traversal of `traverse` as a state machine, advanced one wide node per
-// call (the greedy probe one level per call). A lane that runs several
-// queries one after the other (k_query's refilling form) keeps its state
-// here between calls; every query still visits the same nodes in the same
-// order as with `traverse`, so the results are identical.
-// ---------------------------------------------------------------------------
-template <class T> struct TravState {
-    QueryResult<T> r;
-    V3<T> p;
-    int root;
-    int node;     // next node to visit (the root first)
-    int probing;  // 1: greedy descent without a bound (greedy_probe), 2..: its depth + 1
-    int lost;     // a stack entry was dropped since the last (re)start
-    int restarts;
-};
-
-// after seeding s.r: what the first step does
-template <class T> HD_D void trav_begin(TravState<T> &s, int root) {
-    s.root = root;
-    s.node = root;
-    s.lost = 0;
-    s.restarts = 0;
-    s.probing = root >= 0 && !(s.r.d2 < T(__builtin_inf())) ? 1 : 0;
-}
-
-// One step; returns true when the query is finished (s.r holds its result).
-template <class T, class Stack>
-HD_D bool trav_step(const WideNode *__restrict__ nodes, const BView<T> &bv, const int4 *__restrict__ ids,
-                    TravState<T> &s, Stack &st) {
-    QueryResult<T> &r = s.r;
-    const V3<T> &p = s.p;
-    if (s.root < 0) { // a single-leaf tree
-        visit_leaf(r, bv, ids, p, ~s.root);
-        return true;
-    }
-    if (s.probing) {
-        // one level of the greedy descent: nearest box, nothing pushed
-        const WideView w = load_wide(NodeSrc{nodes, nullptr}, s.node);
-        const float4 lx = w.lx, ly = w.ly, lz = w.lz, hx = w.hx, hy = w.hy, hz = w.hz;
-        const int4 ch = w.ch;
-        T best = T(__builtin_inf());
-        int pick = WIDE_EMPTY;
-        auto consider = [&](float a, float b, float c, float d, float e, float f, int ref) {
-            if (ref == WIDE_EMPTY) return;
-            T dd = box_d2<T>(make_float4(a, b, c, 0.f), make_float4(d, e, f, 0.f), p);
-            if (pick == WIDE_EMPTY || dd < best) {
-                best = dd;
-                pick = ref;
-            }
-        };
-        consider(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, ch.x);
-        consider(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, ch.y);
-        consider(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, ch.z);
-        consider(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, ch.w);
-        r.nbox += 4;
-        if (pick >= 0 && s.probing < 64) {
-            s.node = pick;
-            ++s.probing;
-            return false;
-        }
-        if (pick != WIDE_EMPTY && pick < 0) visit_leaf(r, bv, ids, p, ~pick);
-        s.probing = 0;
-        s.node = s.root;
-        return false;
-    }
-    const T slack = T(1) + T(16 * Prec<T>::u);
-    const T inf = T(__builtin_inf());
-    const WideView w = load_wide(NodeSrc{nodes, nullptr}, s.node);
-    const float4 lx = w.lx, ly = w.ly, lz = w.lz, hx = w.hx, hy = w.hy, hz = w.hz;
-    const int4 ch = w.ch;
-    T e0 = box_d2<T>(make_float4(lx.x, ly.x, lz.x, 0.f), make_float4(hx.x, hy.x, hz.x, 0.f), p);
-    T e1 = box_d2<T>(make_float4(lx.y, ly.y, lz.y, 0.f), make_float4(hx.y, hy.y, hz.y, 0.f), p);
-    T e2 = box_d2<T>(make_float4(lx.z, ly.z, lz.z, 0.f), make_float4(hx.z, hy.z, hz.z, 0.f), p);
-    T e3 = box_d2<T>(make_float4(lx.w, ly.w, lz.w, 0.f), make_float4(hx.w, hy.w, hz.w, 0.f), p);
-    int f0 = ch.x, f1 = ch.y, f2 = ch.z, f3 = ch.w;
-    r.nbox += (f0 != WIDE_EMPTY) + (f1 != WIDE_EMPTY) + (f2 != WIDE_EMPTY) + (f3 != WIDE_EMPTY);
-    {
-        const T thr = r.d2 * slack;
-        const bool l0 = f0 < 0 && f0 != WIDE_EMPTY && e0 <= thr, l1 = f1 < 0 && f1 != WIDE_EMPTY && e1 <= thr,
-                   l2 = f2 < 0 && f2 != WIDE_EMPTY && e2 <= thr, l3 = f3 < 0 && f3 != WIDE_EMPTY && e3 <= thr;
-        if constexpr (sizeof(T) == 8) {
-            if (l0) visit_leaf(r, bv, ids, p, ~f0);
-            if (l1 && e1 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f1);
-            if (l2 && e2 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f2);
-            if (l3 && e3 <= r.d2 * slack) visit_leaf(r, bv, ids, p, ~f3);
-        } else if (l0 || l1 || l2 || l3) {
-            Frame<T> F0, F1, F2, F3;
-            if (l0) F0 = load_frame(bv.frames, ~f0);
-            if (l1) F1 = load_frame(bv.frames, ~f1);
-            if (l2) F2 = load_frame(bv.frames, ~f2);
-            if (l3) F3 = load_frame(bv.frames, ~f3);
-            if (l0) fold_leaf(r, F0, p, ~f0);
-            if (l1 && e1 <= r.d2 * slack) fold_leaf(r, F1, p, ~f1);
-            if (l2 && e2 <= r.d2 * slack) fold_leaf(r, F2, p, ~f2);
-            if (l3 && e3 <= r.d2 * slack) fold_leaf(r, F3, p, ~f3);
-        }
-    }
-    const T thr = r.d2 * slack;
-    auto keep = [&](T &e, int &f) {
-        if (!(f >= 0 && e <= thr)) {
-            e = inf;
-            f = -1;
-        }
-    };
-    keep(e0, f0);
-    keep(e1, f1);
-    keep(e2, f2);
-    keep(e3, f3);
-    cswap(e0, f0, e1, f1);
-    cswap(e2, f2, e3, f3);
-    cswap(e0, f0, e2, f2);
-    cswap(e1, f1, e3, f3);
-    cswap(e1, f1, e2, f2);
-    if (f0 >= 0) {
-        if (f3 >= 0 && !st.push(f3, to_float_down(e3))) s.lost = 1;
-        if (f2 >= 0 && !st.push(f2, to_float_down(e2))) s.lost = 1;
-        if (f1 >= 0 && !st.push(f1, to_float_down(e1))) s.lost = 1;
-        s.node = f0;
-        return false;
-    }
-    int n;
-    float dn;
-    while (st.pop(n, dn)) {
-        if (T(dn) <= r.d2 * slack) {
-            s.node = n;
-            return false;
-        }
-    }
-    if (!s.lost) return true;
-    // entries were dropped: visit the tree again with the bound found
-    if (++s.restarts > MAX_RESTARTS) {
-        r.overflow = true;
-        return true;
-    }
-    s.lost = 0;
-    st.clear();
-    s.node = s.root;
-    return false;
-}
-
-// ---------------------------------------------------------------------------
 // Four lanes per query. A quad (four consecutive lanes of a wave) runs one
 // traversal: lane k tests child slot k of each wide node and evaluates that
 // child when it is a triangle in range; quad permutes (DPP, no LDS) then give
@@ -685,30 +539,18 @@ template <int SD, int NQ> struct QuadStack {
 };
 
 
-// lane k's child of wide node x: box distance, reference (the words of the
-// node that slot k needs, from the LDS table or global memory)
+// lane k's child of wide node x: box distance, reference
+template <class T, class F, class I> HD_D T slot_box_d2(F *b, I *c, int k, const V3<T> &p, int &ref) {
+    ref = c[24 + k];
+    return box_d2<T>(make_float4(b[k], b[4 + k], b[8 + k], 0.f), make_float4(b[12 + k], b[16 + k], b[20 + k], 0.f), p);
+}
 template <class T> HD_D T slot_box_d2(const NodeSrc &ns, int x, int k, const V3<T> &p, int &ref) {
-    uint4 a;
-    uint32_t l0, l1, l2, h0, h1, h2;
     if (x >= TOP_REF) {
-        LdsInt *t = (LdsInt *)ns.top + 16 * (x - TOP_REF);
-        a = make_uint4((uint32_t)t[0], (uint32_t)t[1], (uint32_t)t[2], (uint32_t)t[3]);
-        ref = t[4 + k];
-        l0 = (uint32_t)t[8], l1 = (uint32_t)t[9], l2 = (uint32_t)t[10], h0 = (uint32_t)t[11];
-        h1 = (uint32_t)t[12], h2 = (uint32_t)t[13];
-    } else {
-        const uint4 *g = reinterpret_cast<const uint4 *>(ns.g + x);
-        a = g[0];
-        ref = reinterpret_cast<const int *>(g)[4 + k];
-        const uint4 q0 = g[2];
-        const uint2 q1 = reinterpret_cast<const uint2 *>(g)[6];
-        l0 = q0.x, l1 = q0.y, l2 = q0.z, h0 = q0.w, h1 = q1.x, h2 = q1.y;
+        LdsFloat *b = ns.top + WIDE_WORDS * (x - TOP_REF);
+        return slot_box_d2<T>(b, (LdsInt *)b, k, p, ref);
     }
-    const float sx = wide_step(a.w, 0), sy = wide_step(a.w, 1), sz = wide_step(a.w, 2);
-    const float ox = __uint_as_float(a.x), oy = __uint_as_float(a.y), oz = __uint_as_float(a.z);
-    return box_d2<T>(make_float4(wide_decode(l0, k, sx, ox), wide_decode(l1, k, sy, oy), wide_decode(l2, k, sz, oz), 0.f),
-                     make_float4(wide_decode(h0, k, sx, ox), wide_decode(h1, k, sy, oy), wide_decode(h2, k, sz, oz), 0.f),
-                     p);
+    const float *b = reinterpret_cast<const float *>(ns.g + x);
+    return slot_box_d2<T>(b, reinterpret_cast<const int *>(b), k, p, ref);
 }
 
 // The traversal of `traverse` (same pruning, same order of descent, same

@@ -154,3 +154,22 @@ def test_tuner_cache_across_processes(tmp_path):
     c = _child(path)
     assert c["tuned"] == 1
     assert len(json.loads(path.read_text())) == 1
+
+
+def test_query_options_out_of_range():
+    """query_lanes other than 0, 1, 4 and query_shape outside 0..HD_QUERY_SHAPES
+    are rejected as HD_E_INVALID; every shape in range gives a certified
+    interval (FP64: the same one)."""
+    hd, torch = _hd()
+    W = wl.config(1)
+    say("query option range on config1")
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
+    for kw in (dict(query_lanes=2), dict(query_lanes=3), dict(query_shape=-1), dict(query_shape=10)):
+        with pytest.raises(hd.HDError) as e:
+            hd.bound(*args, relative=True, **kw)
+        assert e.value.status == 1, kw
+    ref = hd.bound(*args, relative=True, precision=0)
+    for shape in range(1, 10):
+        L, U, st = hd.bound(*args, relative=True, precision=0, query_shape=shape)
+        assert (L, U) == ref[:2], shape

@@ -826,75 +826,3 @@ def test_batched_pairs_with_orders_without_the_third_bound(order):
         ref = oracle.bound(P.VA, P.FA, P.VB, P.FB, P.eps_rel, order=digits, backend="tree")
         assert Ls[i] <= ref["U"] + 1e-12 * ref["dA"] and ref["L"] <= Us[i] + 1e-12 * ref["dA"]
         assert abs(Ls[i] - ref["L"]) <= ref["eps_abs"]
-
-
-@pytest.mark.parametrize("which", ["config2-small", "config5-tenth", "grid"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_refill_query_kernel_agrees(which, prec):
-    """One lane per query with refills (a lane whose query ends takes the
-    next one) against one static query per lane. In FP64 the same closest
-    face, distance and closest point, bit for bit. In FP32 the two forms are
-    compiled separately (the static one also reads the top levels from LDS),
-    so a near-tie may resolve to another face: there both distances lie
-    within the FP32 margin of the exact one."""
-    hd, torch = _hd()
-    rng = np.random.default_rng(19)
-    if which == "grid":
-        VB, FB = _grid_soup(12, rng)
-        P = rng.uniform(-1.3, 1.3, size=(40001, 3))
-    else:
-        W = wl.config(2, scale=0.05) if which == "config2-small" else wl.config(5, scale=0.1)
-        VB, FB = W.VB, W.FB
-        lo, hi = VB.min(0), VB.max(0)
-        P = np.concatenate([rng.uniform(lo - 0.1, hi + 0.1, size=(20001, 3)), W.VA[:30000]])
-    precision = hd.PREC_FP64 if prec == "fp64" else hd.PREC_FP32
-    say("refill vs static one-lane point queries", which, prec, "nP", P.shape[0])
-    bvh = hd.build_bvh(_cu(VB, torch), _cu(FB, torch))
-    d1, I1, Q1 = (x.cpu().numpy() for x in hd.point_distances(_cu(P, torch), bvh, precision=precision, lanes=1))
-    d2, I2, Q2 = (x.cpu().numpy() for x in hd.point_distances(_cu(P, torch), bvh, precision=precision, lanes=2))
-    sample = rng.choice(P.shape[0], 600, replace=False)
-    dref, _ = oracle.points_soup(P[sample], VB, FB)
-    if prec == "fp64":
-        assert np.array_equal(I1, I2) and np.array_equal(d1, d2) and np.array_equal(Q1, Q2)
-        assert np.abs(d2[sample] - dref).max() <= 1e-12 * np.abs(VB).max()
-        return
-    edge = max(np.linalg.norm(VB[FB[:, i]] - VB[FB[:, (i + 1) % 3]], axis=1).max() for i in range(3))
-    ctr = 0.5 * (VB[np.unique(FB)].min(0) + VB[np.unique(FB)].max(0))
-    coord = max(np.abs(VB - ctr).max(), np.abs(P - ctr).max())
-    mu = _margin(dref, 2.0 ** -24, edge, coord)
-    same = I1 == I2
-    print(f"faces differ at {int((~same).sum())} of {P.shape[0]} points", flush=True)
-    assert (~same).sum() <= P.shape[0] // 1000
-    assert np.array_equal(d1[same], d2[same]) and np.array_equal(Q1[same], Q2[same])
-    assert (np.abs(d1[sample] - dref) <= mu).all() and (np.abs(d2[sample] - dref) <= mu).all()
-    # a differing face is a near-tie: its distance is within the margin of the other's
-    diff = np.flatnonzero(~same)
-    if diff.size:
-        assert np.all(np.abs(d1[diff] - d2[diff]) <= 2 * _margin(d1[diff], 2.0 ** -24, edge, coord))
-
-
-@pytest.mark.parametrize("k,scale,prec", [(2, 0.1, "fp32+recheck"), (3, 0.05, "fp32"), (5, 0.05, "fp32+recheck"),
-                                          (1, 1.0, "fp64")])
-def test_refill_query_kernel_in_the_bound(k, scale, prec):
-    """hd_bound with refilling query launches, certified against the oracle.
-    In FP64 also the interval and every counter of the static one-lane
-    launches; in FP32 a near-tie may pick another closest face, so there the
-    two certificates must overlap."""
-    hd, torch = _hd()
-    W = wl.config(k, scale=scale)
-    say("bound with refilling queries, config", k, "scale", scale, prec)
-    ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
-    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
-    args = (_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel)
-    L1, U1, s1 = hd.bound(*args, precision=PRECS[prec], query_lanes=1, relative=True)
-    L2, U2, s2 = hd.bound(*args, precision=PRECS[prec], query_lanes=2, relative=True)
-    dA = ref["dA"]
-    for L, U in ((L1, U1), (L2, U2)):
-        assert U - L <= W.eps_rel * dA * (1 + 1e-12)
-        assert L <= ref["U"] + 1e-12 * dA and ref["L"] <= U + 1e-12 * dA
-    assert L1 <= U2 and L2 <= U1
-    if prec == "fp64":
-        assert (L1, U1) == (L2, U2)
-        for key in ("rounds", "subdivided", "nodes_bounded", "queries", "discards", "query_box_tests",
-                    "query_leaf_evals"):
-            assert s1[key] == s2[key], key
