@@ -51,6 +51,7 @@ constexpr int NW = BLK / 64;
 constexpr unsigned GRID_MAX = 2048;  // persistent cap of grid-stride launches (8 blocks per CU)
 constexpr unsigned XCDS = 8;         // accelerator complex dies, each with its own L2
 constexpr unsigned QGRID_MAX = 4096; // the same for the query kernel's smaller blocks
+constexpr unsigned C_GRID_MAX = 256;  // stage C (FP64 re-bounds of the few records in the recheck band)
 
 // Device control block. Atomics on one line serialise at the memory side
 // (about 9 ns each), and lines closer than 256 bytes still share that queue:
@@ -89,6 +90,9 @@ struct Ctl {
     // blocks of the current query / argmax launch that have finished (the
     // last one does the launch's tail work and resets its counter)
     alignas(256) unsigned q_done, f_done, c_done, h1_done, h2_done;
+    // after a query launch that raises L: some pair has a round key above its
+    // best key (the argmax step then has a new point to take to FP64)
+    alignas(256) int argmax_new;
     // device-planned rounds (written by plan_round, read by the round's kernels)
     alignas(256) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
     unsigned long long nref;                           // referenced vertices of A (round 0's queries)
@@ -655,6 +659,16 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
     return q;
 }
 
+// the pair of query i (what query_point gives, without the point)
+template <class T> HD_D int query_pair(const QueryIn<T> &in, int64_t i) {
+    if (in.npairs == 1 || in.mode == Q_POINTS) return 0;
+    if (in.mode == Q_VERTICES) return pair_of(in.voff, in.npairs, in.vids[i]);
+    if (in.mode == Q_BARYCENTERS) return in.par.pair()[i];
+    if (in.mode == Q_LATTICE) return in.par.pair()[i / LATTICE_PTS];
+    const int64_t js = i / 3;
+    return in.par.pair()[in.sel ? (int64_t)in.sel[js] : js];
+}
+
 struct QueryCfg {
     const WideNode *nodes;
     const int4 *ids;
@@ -853,9 +867,35 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
         query_lanes1<T, SD, QB>(in, n, to, cfg, ns, bv, out, pc, pv, ctl, ovf_list, s_node, s_dist, t);
     unsigned long long *st = ctl->stat[acc_copy()];
     block_add<3, QB>({t.nb, t.nl, t.nq}, {st + ST_BOXES, st + ST_QLEAVES, st + ST_QUERIES});
-    // the last block reads only the overflow list (and its atomic count)
-    if (last_block(&ctl->q_done, to.active_blocks(), __syncthreads_or(t.ovf) != 0))
+    // the last block reads only the overflow list (and its atomic count);
+    // then, the round keys being final, whether the argmax step has work:
+    // some pair's best point of the round beats its best so far and, taken
+    // to FP64, could raise L. (The computed distance is within the margin of
+    // the exact one, so the FP64 lower bound of that point is at most its
+    // key's lower bound plus twice the margin.)
+    if (last_block(&ctl->q_done, to.active_blocks(), __syncthreads_or(t.ovf) != 0)) {
         deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
+        if (cfg.raise_L) {
+            __syncthreads();
+            int fresh = 0;
+            for (int p = threadIdx.x; p < in.npairs; p += QB) {
+                const unsigned long long rk =
+                    __hip_atomic_load(&pv[p].round_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (rk <= pv[p].best_key) continue;
+                const Margins &m = margins_of<T>(pc[p]);
+                const double lo = (double)next_up(ord2f((uint32_t)(rk >> 32))); // above the key's d - mu
+                const double d = (lo + m.mu_0) / (1.0 - m.mu_d);                 // above the computed d
+                const double reach = (lo + 2.0 * (m.mu_d * d + m.mu_0)) * (1.0 + 1e-9);
+                const unsigned long long a =
+                    __hip_atomic_load(&pv[p].Lord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long b =
+                    __hip_atomic_load(&pv[pc[p].link].Lord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fresh |= reach > ord2d(a > b ? a : b);
+            }
+            fresh = __syncthreads_or(fresh);
+            if (threadIdx.x == 0) ctl->argmax_new = fresh;
+        }
+    }
 }
 
 // queries whose LDS stack overflowed, redone with a deep stack in global
@@ -1005,11 +1045,24 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
                                                          const int *__restrict__ tri, PairVar *pv, L64Cfg lc, Ctl *ctl) {
     const int64_t n = cnt.get();
     if ((int64_t)blockIdx.x * BLK >= n) return; // the grid is sized for a larger count
+    if (!ctl->argmax_new) {
+        // no key above its pair's best: no new point, L stands; only the
+        // plain-FP32 tolerance check (L may still have risen within the
+        // rounding of a key)
+        if (blockIdx.x == 0 && lc.check_fp32)
+            for (int p = threadIdx.x; p < lc.npairs; p += blockDim.x) {
+                const PairConst &C = lc.pc[p];
+                if (C.eps_abs <= C.m32.mu_d * pair_L(lc.pc, pv, p) + C.m32.mu_0) ctl->bad = 5;
+            }
+        return;
+    }
     int wrote = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int64_t o = in.mode == Q_VERTICES ? in.vids[i] : i;
         unsigned long long key = keys[o];
         if (key == 0) continue;
+        const PairVar &Pq = pv[query_pair(in, i)];
+        if (key != Pq.round_key || key <= Pq.best_key) continue;
         QPoint qp = query_point(in, i);
         PairVar &P = pv[qp.pair];
         if (key == P.round_key && key > P.best_key) {
@@ -2894,9 +2947,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             k_stage_b_learned<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params, Sb);
         else
             k_stage_b<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, Sb);
+        // (stage C's records are the few within the FP32 margin of a
+        // decision: a grid of one block per CU, striding, suffices)
         if (cc.recheck)
-            k_stage_c<T><<<g, BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl, defer, mb_dev, plan_seq,
-                                           plan_seq ? caps() : PlanCaps{});
+            k_stage_c<T><<<std::min(g, C_GRID_MAX), BLK, 0, s>>>(tw.pend_c.v, cc, d, ctl, defer, mb_dev, plan_seq,
+                                                                 plan_seq ? caps() : PlanCaps{});
         else if (plan_seq)
             k_report_plan<<<1, 64, 0, s>>>(ctl, pv, mb_dev, plan_seq, caps());
         HD_LAUNCH_CHECK();

@@ -217,28 +217,50 @@ struct IdView {
     const int4 *ids; // per sorted triangle: vertex ids of frame corners A, B, C; original face id
 };
 
+// Which case of Kang's bound applies to closest triangles I[0..2]: the
+// first (eq. Kang2018_case1) when exactly two coincide and the odd vertex's
+// triangle S1 shares an edge (vertex ids c0, c1) with the others' S2, else
+// the second (eq. Kang2018_case2).
+struct U3Case {
+    int odd;        // the vertex whose closest triangle differs (-1: none)
+    int S1, S2;     // its closest triangle and the other vertices'
+    int a1[3], a2[3]; // vertex ids of S1 and S2 (frame order)
+    int c0, c1;     // the first two distinct ids of S1 that S2 shares (-1: none)
+    HD_D bool first() const { return odd >= 0 && c1 >= 0; }
+};
+HD_D U3Case u3_case(int I0, int I1, int I2, const IdView &iv) {
+    U3Case u;
+    u.odd = -1;
+    if (I0 != I1 && I1 == I2) u.odd = 0;
+    else if (I1 != I0 && I0 == I2) u.odd = 1;
+    else if (I2 != I0 && I0 == I1) u.odd = 2;
+    u.c0 = u.c1 = -1;
+    if (u.odd < 0) return u;
+    u.S1 = pick3(I0, I1, I2, u.odd);
+    u.S2 = pick3(I0, I1, I2, (u.odd + 1) % 3);
+    const int4 i1 = iv.ids[u.S1], i2 = iv.ids[u.S2];
+    u.a1[0] = i1.x, u.a1[1] = i1.y, u.a1[2] = i1.z;
+    u.a2[0] = i2.x, u.a2[1] = i2.y, u.a2[2] = i2.z;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const bool shared = u.a1[i] == u.a2[0] || u.a1[i] == u.a2[1] || u.a1[i] == u.a2[2];
+        if (shared && u.c0 < 0) u.c0 = u.a1[i];
+        else if (shared && u.c1 < 0 && u.a1[i] != u.c0) u.c1 = u.a1[i];
+    }
+    return u;
+}
+
 // eq. Kang2018_case1 / eq. Kang2018_case2. *evals counts closest-point
 // evaluations.
 template <class T>
 HD_D T bound_u3(const Tri<T> &t, const BView<T> &bv, const IdView &iv, int *which_case, int *evals) {
-    int odd = -1;
-    if (t.I[0] != t.I[1] && t.I[1] == t.I[2]) odd = 0;
-    else if (t.I[1] != t.I[0] && t.I[0] == t.I[2]) odd = 1;
-    else if (t.I[2] != t.I[0] && t.I[0] == t.I[1]) odd = 2;
-    if (odd >= 0) {
+    const U3Case u = u3_case(t.I[0], t.I[1], t.I[2], iv);
+    if (u.odd >= 0) {
         // rotate so that the odd vertex comes first (selects, not indexing)
-        const int r1 = (odd + 1) % 3, r2 = (odd + 2) % 3;
-        const int S1 = pick3(t.I[0], t.I[1], t.I[2], odd), S2 = pick3(t.I[0], t.I[1], t.I[2], r1);
-        int4 i1 = iv.ids[S1], i2 = iv.ids[S2];
-        int a1[3] = {i1.x, i1.y, i1.z}, a2[3] = {i2.x, i2.y, i2.z};
-        // the first two distinct vertex ids of S1 that S2 shares, in S1's order
-        int c0 = -1, c1 = -1;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const bool shared = a1[i] == a2[0] || a1[i] == a2[1] || a1[i] == a2[2];
-            if (shared && c0 < 0) c0 = a1[i];
-            else if (shared && c1 < 0 && a1[i] != c0) c1 = a1[i];
-        }
+        const int odd = u.odd, r1 = (odd + 1) % 3, r2 = (odd + 2) % 3;
+        const int S1 = u.S1, S2 = u.S2;
+        const int a1[3] = {u.a1[0], u.a1[1], u.a1[2]}, a2[3] = {u.a2[0], u.a2[1], u.a2[2]};
+        const int c0 = u.c0, c1 = u.c1;
         if (c1 >= 0) {
             if (which_case) *which_case = 1;
             Frame<T> f1 = load_frame(bv.frames, S1), f2 = load_frame(bv.frames, S2);
