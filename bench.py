@@ -277,11 +277,49 @@ def summary(ms, res):
 # CPU oracle on the host (the reported baseline)
 # ---------------------------------------------------------------------------
 
+def oracle_bound_tree(W):
+    import oracle
+    return oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree")
+
+
 def cpu_oracle(W, threads=1):
     import oracle
     t0 = time.perf_counter()
     res = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="tree", threads=threads)
     return (time.perf_counter() - t0) * 1e3, res
+
+
+def tree_check(W, ref, hd, torch, bvh, npts=10000, threads=16):
+    """The oracle's AABB tree (the backend of the CPU baseline on the large
+    workloads) against its brute force at npts random points around B plus
+    the vertex that attains the oracle's L; and the GPU's FP64 point query at
+    the same points. Brute force runs over threads (each a C call)."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(2406)
+    lo, hi = W.VB.min(0), W.VB.max(0)
+    pad = 0.05 * (hi - lo)
+    P = np.concatenate([rng.uniform(lo - pad, hi + pad, size=(npts, 3)), np.asarray(ref["argmax"])[None]])
+    t0 = time.perf_counter()
+    chunks = np.array_split(np.arange(P.shape[0]), threads)
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda c: oracle.points_soup(P[c], W.VB, W.FB), chunks))
+    dB = np.concatenate([p[0] for p in parts])
+    IB = np.concatenate([p[1] for p in parts])
+    t_brute = time.perf_counter() - t0
+    tree = oracle.Tree(W.VB, W.FB)
+    dT = np.empty(P.shape[0])
+    IT = np.empty(P.shape[0], np.int64)
+    for i, x in enumerate(P):
+        dT[i], IT[i], _, _ = tree.query(x)
+    dG = hd.point_distances(torch.from_numpy(P).cuda(), bvh, precision=hd.PREC_FP64)[0].cpu().numpy()
+    scale = float(np.abs(W.VB).max())
+    return {"points": int(P.shape[0]), "includes_argmax_vertex": True,
+            "tree_equals_brute": bool(np.array_equal(dT, dB) and np.array_equal(IT, IB)),
+            "tree_max_abs_diff": float(np.abs(dT - dB).max()),
+            "gpu_fp64_max_abs_diff_over_scale": float(np.abs(dG - dB).max() / scale),
+            "argmax_vertex_d_brute": float(dB[-1]), "brute_s": round(t_brute, 2), "brute_threads": threads}
 
 
 def parity_of(L, U, st, ref):
@@ -443,6 +481,12 @@ def bench_main(a, hd, torch, wl):
                                             "what": "the same with the vertex-query phase split over the cores"},
                                "host": cpu}
         out["parity"] = parity_of(L, U, st, ref)
+        log("oracle tree and GPU FP64 queries against brute force at 10^4 points ...")
+        # (brute force over the 800 k triangles of the large torus costs about
+        # 0.15 core-seconds per point: 2000 points here, 10^4 on the 51 k torus)
+        out["parity"]["tree_check"] = tree_check(W, ref, hd, torch, hd.build_bvh(run.VB, run.FB),
+                                                 npts=2000 if W.FB.shape[0] > 200000 else 10000,
+                                                 threads=min(16, cpu["usable_cores"]))
     elif not a.no_cpu_baseline and batched:
         log("CPU oracle on a stratified sample of the pairs ...")
         checks, t_s, faces = pairs_parity(pairs, L, U)
@@ -463,6 +507,15 @@ def bench_main(a, hd, torch, wl):
         out["c2"] = {"config": workload_info(W2, "fp32+recheck", "plain cascade 1234, breadth-first rounds"),
                      **summary(ms2, res2), "roofline": roofline(res2, tuned2, measured_traffic(2, tuned2))}
         log(f"  {ms2:.3f} ms/step")
+        if not a.no_cpu_baseline:
+            log("  oracle, and its tree and GPU FP64 queries against brute force at 10^4 points ...")
+            L2, U2, st2 = res2[-1]
+            t0 = time.perf_counter()
+            ref2 = oracle_bound_tree(W2)
+            out["c2"]["parity"] = parity_of(L2, U2, st2, ref2)
+            out["c2"]["parity"]["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+            out["c2"]["parity"]["tree_check"] = tree_check(W2, ref2, hd, torch, hd.build_bvh(r2.VB, r2.FB),
+                                                           npts=10000, threads=min(16, cpu["usable_cores"]))
         log("extra: C4 256 pairs ...")
         pairs = wl.batched_pairs(256, workers=min(16, os.cpu_count() or 1))
         r4 = Batch(hd, torch, pairs, PRECISIONS["fp32+recheck"])
