@@ -74,6 +74,27 @@ enum {
 constexpr int ST_STRIDE = 32; // 256 bytes per copy
 static_assert(ST_N <= ST_STRIDE, "statistics copy overflows its line");
 
+// Counts of the blocks of a launch that have finished, to find the last
+// one (last_block). Atomics on one address serialise at the memory side (tens
+// of nanoseconds each when thousands of blocks end together), so blocks count
+// on LB_WAYS separate lines, and the block that completes a line counts on
+// the top line: the block that completes the top line is the last.
+constexpr int LB_WAYS = 16;
+// launches of at most this many blocks count on one line (the second level
+// would only lengthen the last block's path)
+constexpr unsigned LB_SPLIT_MIN = 256;
+struct BlockCounter {
+    struct alignas(256) Line {
+        unsigned n;
+    };
+    Line way[LB_WAYS];
+    Line top;
+};
+// way w's share of nactive blocks dealt to the ways in turn
+HD_D unsigned way_share(unsigned nactive, unsigned w) {
+    return nactive / LB_WAYS + (w < nactive % LB_WAYS ? 1u : 0u);
+}
+
 struct Ctl {
     alignas(256) unsigned long long act_next; // append counters of the current round
     alignas(256) unsigned long long park_next;
@@ -87,9 +108,6 @@ struct Ctl {
     int n_overflow;       // queries whose LDS stack overflowed this round
     int log_rounds;       // 1: reports carry the lower bound, upper bound and statistics
     alignas(256) unsigned long long stat[ACC_COPIES][ST_STRIDE];
-    // blocks of the current query / argmax launch that have finished (the
-    // last one does the launch's tail work and resets its counter)
-    alignas(256) unsigned q_done, f_done, c_done, h1_done, h2_done;
     // after a query launch that raises L: some pair has a round key above its
     // best key (the argmax step then has a new point to take to FP64)
     alignas(256) int argmax_new;
@@ -115,7 +133,14 @@ struct Ctl {
     alignas(256) unsigned long long sel_prom;  // learned order: live records predicted above L + eps
     alignas(256) unsigned long long sel_next;  // selected parents appended (their record indices)
     alignas(256) unsigned long long rest_next; // unselected live records appended
+    // blocks of the current query / argmax / stage C / selection launch that
+    // have finished (the last one does the launch's tail work; every count
+    // is back at zero after it). Last in the block: the host never reads them.
+    BlockCounter q_done, f_done, c_done, h1_done, h2_done;
 };
+// the part of the control block the host reads
+constexpr size_t CTL_HOST_BYTES = offsetof(Ctl, q_done);
+static_assert(CTL_HOST_BYTES % 8 == 0, "exported control block size");
 
 // Item count of a launch: a host value, or (device-planned rounds) a count
 // the device wrote, times a multiplicity. Kernels that take one loop over it
@@ -155,18 +180,37 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, unsigned long 
 // it, once, at the end of its work, with the same release; blocks that had no
 // work (a grid sized for a larger count) must not: every call is an atomic on
 // one address, and these serialise.
-__device__ bool last_block(unsigned *counter, unsigned nactive, bool release = true) {
+__device__ bool last_block(BlockCounter *c, unsigned way, unsigned way_blocks, unsigned ways, bool release = true) {
     __shared__ int last;
     __syncthreads();
     if (threadIdx.x == 0) {
         if (release) __threadfence();
-        const unsigned ticket = atomicAdd(counter, 1u);
-        last = ticket == nactive - 1;
-        if (last) atomicExch(counter, 0u);
+        int l = 0;
+        if (atomicAdd(&c->way[way].n, 1u) == way_blocks - 1) {
+            atomicExch(&c->way[way].n, 0u);
+            if (ways == 1) {
+                l = 1;
+            } else {
+                __threadfence(); // the way's blocks, ahead of the top count
+                if (atomicAdd(&c->top.n, 1u) == ways - 1) {
+                    atomicExch(&c->top.n, 0u);
+                    l = 1;
+                }
+            }
+        }
+        last = l;
     }
     __syncthreads();
     if (last) __threadfence();
     return last;
+}
+
+// the same when the blocks with work are blocks 0 .. nactive - 1 (way: the
+// block index modulo LB_WAYS; one way for small grids)
+__device__ bool last_block(BlockCounter *c, unsigned nactive, bool release = true) {
+    if (nactive <= LB_SPLIT_MIN) return last_block(c, 0, nactive, 1, release);
+    const unsigned w = blockIdx.x % LB_WAYS;
+    return last_block(c, w, way_share(nactive, w), LB_WAYS, release);
 }
 
 __device__ __forceinline__ int pair_of(const int64_t *__restrict__ off, int npairs, int64_t x) {
@@ -747,15 +791,25 @@ struct TileOrder {
     HD_D int64_t tile(int64_t tt) const { return x * per + tt; }
     // whether this block has a tile, and how many blocks have one
     HD_D bool active() const { return valid(first); }
-    HD_D unsigned active_blocks() const {
-        int64_t a = 0;
-        for (unsigned y = 0; y < xs; ++y) {
-            int64_t k = ntiles - (int64_t)y * per;
-            k = k < per ? k : per;
-            k = k < (int64_t)gx ? k : (int64_t)gx;
-            a += k > 0 ? k : 0;
-        }
-        return (unsigned)a;
+    // the blocks of XCD slot y with a tile: first = 0 .. lim(y) - 1
+    HD_D int64_t lim(unsigned y) const {
+        int64_t k = ntiles - (int64_t)y * per;
+        k = k < per ? k : per;
+        k = k < (int64_t)gx ? k : (int64_t)gx;
+        return k > 0 ? k : 0;
+    }
+    // last_block over the blocks with a tile: way first % LB_WAYS, its share
+    // summed over the XCD slots, and the ways that have blocks (slot 0 has
+    // the most); one way for small grids
+    HD_D bool last(BlockCounter *c, bool release) const {
+        unsigned total = 0;
+        for (unsigned y = 0; y < xs; ++y) total += (unsigned)lim(y);
+        if (total <= LB_SPLIT_MIN) return last_block(c, 0, total, 1, release);
+        const unsigned w = first % LB_WAYS;
+        unsigned share = 0;
+        for (unsigned y = 0; y < xs; ++y) share += way_share((unsigned)lim(y), w);
+        const int64_t l0 = lim(0);
+        return last_block(c, w, share, (unsigned)(l0 < LB_WAYS ? l0 : LB_WAYS), release);
     }
 };
 
@@ -873,7 +927,7 @@ __global__ __launch_bounds__(QB) void k_query(QueryIn<T> in, DevCount cnt, Query
     // to FP64, could raise L. (The computed distance is within the margin of
     // the exact one, so the FP64 lower bound of that point is at most its
     // key's lower bound plus twice the margin.)
-    if (last_block(&ctl->q_done, to.active_blocks(), __syncthreads_or(t.ovf) != 0)) {
+    if (to.last(&ctl->q_done, __syncthreads_or(t.ovf) != 0)) {
         deep_queries<T>(in, cfg, bv, out, pc, pv, ctl, ovf_list, deep_stack);
         if (cfg.raise_L) {
             __syncthreads();
@@ -2966,7 +3020,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         ex.n = 3;
         ex.src[0] = ctl;
         ex.dst[0] = ws.host.dev_as<char>(o_res + o_rctl);
-        ex.bytes[0] = sizeof(Ctl);
+        ex.bytes[0] = CTL_HOST_BYTES;
         ex.src[1] = pv;
         ex.dst[1] = ws.host.dev_as<char>(o_res + o_rpv);
         ex.bytes[1] = np * sizeof(PairVar);
@@ -3652,7 +3706,7 @@ hd_status hd_point_distances(const double *P, int64_t nP, hd_bvh Bh, int32_t pre
         if (precision == HD_PREC_FP64) go(double{});
         else go(float{});
         Ctl hc;
-        HD_HIP(hipMemcpy(&hc, ctl, sizeof(hc), hipMemcpyDeviceToHost));
+        HD_HIP(hipMemcpy(&hc, ctl, CTL_HOST_BYTES, hipMemcpyDeviceToHost));
         if (hc.bad == 2) return HD_E_INTERNAL;
         return HD_OK;
     });
