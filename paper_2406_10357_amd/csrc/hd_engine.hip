@@ -230,6 +230,14 @@ template <> HD_HD const Margins &margins_of<double>(const PairConst &p) { return
 // atomicMax of (a, b) into pair `pair`'s L and round key: one atomic per wave
 // when every contributing lane has the same pair, else one per lane. All
 // lanes of the wave must call it; lanes with nothing to add pass zeros.
+// Both values only grow while a launch runs, so an atomic that cannot raise
+// the value is skipped: a plain read of it (possibly an older copy in this
+// XCD's L2, which is never above the current value) decides. Without that
+// test every wave of a query launch queues one atomic on the same line,
+// and those serialise at the memory side.
+HD_D bool may_raise(const unsigned long long *x, unsigned long long v) {
+    return v && v > __hip_atomic_load(x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ void pair_max2(PairVar *pv, int pair, unsigned long long a, unsigned long long b) {
     unsigned long long has = __ballot(a != 0 || b != 0);
     if (!has) return;
@@ -243,12 +251,12 @@ __device__ void pair_max2(PairVar *pv, int pair, unsigned long long a, unsigned 
             b = tb > b ? tb : b;
         }
         if (__lane_id() == 0) {
-            if (a) atomicMax(&pv[p0].Lord, a);
-            if (b) atomicMax(&pv[p0].round_key, b);
+            if (may_raise(&pv[p0].Lord, a)) atomicMax(&pv[p0].Lord, a);
+            if (may_raise(&pv[p0].round_key, b)) atomicMax(&pv[p0].round_key, b);
         }
     } else {
-        if (a) atomicMax(&pv[pair].Lord, a);
-        if (b) atomicMax(&pv[pair].round_key, b);
+        if (may_raise(&pv[pair].Lord, a)) atomicMax(&pv[pair].Lord, a);
+        if (may_raise(&pv[pair].round_key, b)) atomicMax(&pv[pair].round_key, b);
     }
 }
 
