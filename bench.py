@@ -68,6 +68,8 @@ def parse():
                     help="1: the first warm-up call picks the query kernel's launch shape; 0: the "
                          "default shape (profiling runs use it, so every counter run times the same shape)")
     ap.add_argument("--no-learned", action="store_true", help="skip the best-first and learned variants")
+    ap.add_argument("--query-shape", type=int, default=0, choices=range(0, 10),
+                    help="headline steps: force launch shape k of the query kernel (1..9; 0: tuned or default)")
     ap.add_argument("--learned-subbatch", type=int, default=8192)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x4) and an FP32 elementwise product of "
@@ -404,7 +406,7 @@ def bench_main(a, hd, torch, wl):
         run = Single(hd, torch, W, prec)
 
     log("plain cascade, breadth-first rounds: warm-up and timed steps ...")
-    ms, res, tuned = timed(run.step, a.steps, a.warmup, autotune=a.autotune)
+    ms, res, tuned = timed(run.step, a.steps, a.warmup, autotune=a.autotune, query_shape=a.query_shape)
     log(f"  {ms:.3f} ms/step")
     L, U, st = res[-1]
     evals = sum(r[2]["pt_tri_evals"] for r in res)
