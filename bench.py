@@ -105,7 +105,8 @@ def calibrate_copy(mib):
 # the kernel sources it was measured on (their hash is stored beside it)
 TRAFFIC_FILES = {2: os.path.join(ROOT, "profiles", "k_query_traffic_c2_torus.json"),
                  5: os.path.join(ROOT, "profiles", "k_query_traffic_c5_torus.json")}
-KERNEL_SOURCES = ["hd_kernels.hpp", "hd_geom.hpp", "hd_math.hpp", "hd_engine.hip", "hd_bvh.hip"]
+KERNEL_SOURCES = ["hd_kernels.hpp", "hd_geom.hpp", "hd_math.hpp", "hd_reduce.hpp", "hd_internal.hpp", "hd_engine.hip",
+                  "hd_bvh.hip"]
 
 
 def kernel_source_hash():
