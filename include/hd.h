@@ -64,7 +64,8 @@ typedef struct {
                             section); <= 0 means 1e7 */
     int64_t capacity;    /* frontier capacity in triangles; 0 = automatic */
     int32_t max_rounds;  /* 0 = unlimited */
-    int32_t stack_depth; /* traversal stack entries per lane (test hook); 0 = default */
+    int32_t stack_depth; /* test hook: 1..15 runs the query kernel with a one-entry LDS
+                            stack per lane (restarts, then the deep-stack fallback); 0 = default */
     int32_t subbatch;    /* > 0: subdivide about this many triangles per round, highest upper
                             bound first (approximates the paper's best-first queue). The device
                             selects them (a radix select on the key; the last key bin is taken

@@ -43,7 +43,7 @@ namespace hd {
 namespace {
 
 constexpr int QSTACK = 16;    // LDS ring-stack entries per lane (16 KB per block)
-constexpr int SMALL_STACK = 4; // test hook: tiny LDS stack, forces the deep path
+constexpr int SMALL_STACK = 1; // test hook: a one-entry LDS stack, forces the deep path
 constexpr int DEEP_STACK = 256;
 constexpr int DEEP_SLOTS = 256;  // deep traversals at once: one per thread of the query kernel's last block
 constexpr int BLK = 256;
@@ -69,6 +69,7 @@ enum {
     ST_QLEAVES,
     ST_SKIPS, // records whose u3 / u4 the learned policy skipped
     ST_STALE, // active records dropped by the sub-batch selection (bound below L)
+    ST_OVERFLOWS, // queries redone with the deep stack (their LDS stack overflowed)
     ST_N
 };
 constexpr int ST_STRIDE = 32; // 256 bytes per copy
@@ -992,7 +993,10 @@ __device__ void deep_queries(const QueryIn<T> &in, const QueryCfg &cfg, const BV
     wave_add(&ctl->stat[acc_copy()][ST_QLEAVES], nl);
     // the list is done: a later query launch of the same round starts empty
     __syncthreads();
-    if (threadIdx.x == 0) ctl->n_overflow = 0;
+    if (threadIdx.x == 0) {
+        if (novf) atomicAdd(&ctl->stat[acc_copy()][ST_OVERFLOWS], (unsigned long long)novf);
+        ctl->n_overflow = 0;
+    }
 }
 
 // Launch shapes of the query kernel (LDS stack entries per query, block
@@ -1050,7 +1054,8 @@ void launch_query(int v, int64_t n_max, int64_t quad_max, const QueryIn<T> &qi, 
 
 __global__ void k_zero_query_stats(Ctl *c) {
     const int k = threadIdx.x;
-    if (k < ACC_COPIES) c->stat[k][ST_QUERIES] = c->stat[k][ST_BOXES] = c->stat[k][ST_QLEAVES] = 0;
+    if (k < ACC_COPIES)
+        c->stat[k][ST_QUERIES] = c->stat[k][ST_BOXES] = c->stat[k][ST_QLEAVES] = c->stat[k][ST_OVERFLOWS] = 0;
     if (k == 0) c->n_overflow = 0;
 }
 
@@ -3421,6 +3426,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     S.logged = logged;
     S.learned_skips = (int64_t)stat(ST_SKIPS);
     S.stale = (int64_t)stat(ST_STALE);
+    S.stack_overflows = (int64_t)stat(ST_OVERFLOWS);
     S.dA = hc_[0].dA;
     S.eps_abs = hc_[0].eps_abs;
     S.mu_coef_d = margins_of<T>(hc_[0]).mu_d;

@@ -421,18 +421,41 @@ def test_round_limit_with_list_growth():
 
 @pytest.mark.parametrize("lanes", [1, 4])
 def test_tiny_stack_falls_back_and_agrees(lanes):
-    """A four-entry stack (ring restarts, then the deep-stack kernel) gives
-    the result of the default stack, with one lane or a quad per query."""
+    """A one-entry stack (ring restarts, then the deep stack of the query
+    launch's last block) gives the result of the default stack, with one
+    lane or a quad per query."""
     hd, torch = _hd()
     W = wl.config(2, scale=0.05)
     say("tiny traversal stack on config2 scale 0.05, lanes", lanes)
     bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
     a = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, query_lanes=lanes, relative=True)
     b = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, stack_depth=2, query_lanes=lanes, relative=True)
-    assert b[2]["query_lanes"] == lanes and b[2]["query_stack"] == 4
+    assert b[2]["query_lanes"] == lanes and b[2]["query_stack"] == 1
     print("overflows", b[2]["stack_overflows"])
+    assert b[2]["stack_overflows"] > 0
     assert a[0] == b[0] and a[1] == b[1]
     assert a[2]["subdivided"] == b[2]["subdivided"]
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_tiny_stack_in_launches_of_many_blocks(lanes):
+    """The overflowed traversals are redone by the last block of the query
+    launch; launches of more than 256 blocks find that block in two levels
+    (sixteen counting lines, then a top line). Full-size C2 with a one-entry
+    stack: its first split round launches about 800 blocks with one lane per
+    query and about 3,100 with a quad per query, and the interval must still
+    be the default stack's."""
+    hd, torch = _hd()
+    W = wl.config(2)
+    say("tiny traversal stack on config2 full size, lanes", lanes)
+    bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
+    a = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, query_lanes=lanes, relative=True)
+    b = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, stack_depth=2, query_lanes=lanes, relative=True)
+    print("overflows", b[2]["stack_overflows"], "queries", b[2]["queries"])
+    assert b[2]["query_lanes"] == lanes and b[2]["query_stack"] == 1
+    assert b[2]["stack_overflows"] > 0
+    assert a[0] == b[0] and a[1] == b[1]
+    assert a[2]["subdivided"] == b[2]["subdivided"] and a[2]["queries"] == b[2]["queries"]
 
 
 @pytest.mark.parametrize("which", ["config2-small", "config3-small", "grid"])
