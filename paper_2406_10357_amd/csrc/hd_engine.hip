@@ -798,7 +798,7 @@ struct TileOrder {
     }
     HD_D bool valid(int64_t tt) const { return tt < per && x * per + tt < ntiles; }
     HD_D int64_t tile(int64_t tt) const { return x * per + tt; }
-    // whether this block has a tile, and how many blocks have one
+    // whether this block has a tile
     HD_D bool active() const { return valid(first); }
     // the blocks of XCD slot y with a tile: first = 0 .. lim(y) - 1
     HD_D int64_t lim(unsigned y) const {
