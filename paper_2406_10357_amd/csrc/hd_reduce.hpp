@@ -19,6 +19,22 @@ namespace hd {
 constexpr int ACC_COPIES = 16;
 __device__ __forceinline__ int acc_copy() { return (int)(blockIdx.x & (ACC_COPIES - 1)); }
 
+// Fold ordered bits x into *a with max (mx) or min, for the paths where
+// several pairs share a wave or a block: there every lane or wave has an
+// atomic of its own, and a batch of pairs can queue thousands of them on one
+// pair's line. The slot only moves one way while a launch runs, so an atomic
+// that cannot change it is skipped: a plain read (possibly an older copy in
+// this XCD's L2, never past the current value) decides. (The one atomic of a
+// block that holds a single pair is left as it is: there the read only
+// lengthens the path.)
+__device__ __forceinline__ void fold_ord(unsigned long long *a, unsigned long long x, bool mx) {
+    const unsigned long long cur = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (mx ? x > cur : x < cur) {
+        if (mx) atomicMax(a, x);
+        else atomicMin(a, x);
+    }
+}
+
 // v[k] is reduced with max when bit k of MAXMASK is set, else with min.
 // Threads with valid == false must pass neutral values (+inf for min, -inf
 // for max, or anything with valid == false: they are masked out). addr(p, k)
@@ -44,9 +60,7 @@ __device__ __forceinline__ void block_pair_minmax(int p, bool valid, const doubl
                 x = mx ? fmax(x, y) : fmin(x, y);
             }
         } else if (valid) {
-            unsigned long long *a = addr(p, k);
-            if (mx) atomicMax(a, d2ord(x));
-            else atomicMin(a, d2ord(x));
+            fold_ord(addr(p, k), d2ord(x), mx);
         }
         r[k] = x;
     }
@@ -79,11 +93,7 @@ __device__ __forceinline__ void block_pair_minmax(int p, bool valid, const doubl
             for (int i = 0; i < NW; ++i) {
                 if (sp[i] < 0) continue;
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    unsigned long long *a = addr(sp[i], k);
-                    if ((MAXMASK >> k) & 1u) atomicMax(a, d2ord(sv[i][k]));
-                    else atomicMin(a, d2ord(sv[i][k]));
-                }
+                for (int k = 0; k < K; ++k) fold_ord(addr(sp[i], k), d2ord(sv[i][k]), (MAXMASK >> k) & 1u);
             }
         }
     }
