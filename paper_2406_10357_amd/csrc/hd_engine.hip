@@ -1102,6 +1102,23 @@ struct L64Cfg {
     int check_fp32;  // plain FP32 rounds: the tolerance must exceed the margin at L
 };
 
+// pair p's FP64 argmax step (l64_pair) by the four lanes of a quad, then
+// the plain-FP32 tolerance check. Plain FP32 parks a triangle only when its
+// bound plus the FP32 margin lies within the tolerance of L; near the
+// maximum that margin tends to mu_d * h + mu_0 as the triangles shrink, so a
+// tolerance below it cannot be reached (the rounds would split to the depth
+// limit).
+constexpr int ARGMAX_LAST_BLOCK_PAIRS = BLK / 4;
+__device__ void argmax_step(const L64Cfg &lc, PairVar *pv, int p, Ctl *ctl) {
+    __shared__ float4 s_none[1]; // no top-level table here (no reference reaches it)
+    const NodeSrc ns{lc.nodes, (LdsFloat *)s_none};
+    l64_pair(ns, lc.bv64, lc.ids, lc.pc, pv, p, lc.npairs, lc.stack_mem, threadIdx.x & 3);
+    if (lc.check_fp32 && (threadIdx.x & 3) == 0) {
+        const PairConst &C = lc.pc[p];
+        if (C.eps_abs <= C.m32.mu_d * pair_L(lc.pc, pv, p) + C.m32.mu_0) ctl->bad = 5;
+    }
+}
+
 // after a query round: the query holding its pair's best key records its
 // exact position (keys are unique up to a tag collision of one point); the
 // block that finishes last then takes each pair's new best point to FP64
@@ -1141,25 +1158,23 @@ __global__ __launch_bounds__(BLK) void k_argmax_finalize(QueryIn<T> in, DevCount
             wrote = 1;
         }
     }
+    // many pairs: their FP64 steps run in k_argmax_pairs, a quad per pair
+    // over as many blocks as needed, instead of in turns in one block
+    if (lc.npairs > ARGMAX_LAST_BLOCK_PAIRS) return;
     const int64_t need = (n + BLK - 1) / BLK;
     // the last block reads only the argmax records (written by one block)
     if (last_block(&ctl->f_done, (unsigned)(need < (int64_t)gridDim.x ? need : (int64_t)gridDim.x),
                    __syncthreads_or(wrote) != 0)) {
-        __shared__ float4 s_none[1]; // no top-level table here (no reference reaches it)
-        const NodeSrc ns{lc.nodes, (LdsFloat *)s_none};
-        for (int p = threadIdx.x >> 2; p < lc.npairs; p += blockDim.x >> 2) {
-            l64_pair(ns, lc.bv64, lc.ids, lc.pc, pv, p, lc.npairs, lc.stack_mem, threadIdx.x & 3);
-            // Plain FP32 parks a triangle only when its bound plus the FP32
-            // margin lies within the tolerance of L; near the maximum that
-            // margin tends to mu_d * h + mu_0 as the triangles shrink, so a
-            // tolerance below it cannot be reached (the rounds would split
-            // to the depth limit).
-            if (lc.check_fp32 && (threadIdx.x & 3) == 0) {
-                const PairConst &C = lc.pc[p];
-                if (C.eps_abs <= C.m32.mu_d * pair_L(lc.pc, pv, p) + C.m32.mu_0) ctl->bad = 5;
-            }
-        }
+        for (int p = threadIdx.x >> 2; p < lc.npairs; p += blockDim.x >> 2) argmax_step(lc, pv, p, ctl);
     }
+}
+
+// the FP64 argmax steps of more than ARGMAX_LAST_BLOCK_PAIRS pairs, after
+// k_argmax_finalize (which wrote the argmax records): a quad per pair
+__global__ __launch_bounds__(BLK) void k_argmax_pairs(PairVar *pv, L64Cfg lc, Ctl *ctl) {
+    if (!ctl->argmax_new) return; // (k_argmax_finalize made the plain-FP32 check)
+    const int p = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2);
+    if (p < lc.npairs) argmax_step(lc, pv, p, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -2840,6 +2855,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         const L64Cfg l64{B->nodes.as<WideNode>(), bv64, iv.ids, pc, np, ws.gstack.as<int2>(), check_fp32};
         k_argmax_finalize<T><<<std::min<unsigned>(grid_for(n_max, BLK), GRID_MAX), BLK, 0, s>>>(qi, cnt, out.key,
                                                                                                out.I, pv, l64, ctl);
+        if (np > ARGMAX_LAST_BLOCK_PAIRS) k_argmax_pairs<<<grid_for((int64_t)np * 4, BLK), BLK, 0, s>>>(pv, l64, ctl);
         HD_LAUNCH_CHECK();
     };
 
