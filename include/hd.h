@@ -116,6 +116,13 @@ typedef struct {
                                   FP32/FP64 cascade stages. A shift that makes a bound smaller than
                                   the largest vertex distance of its triangle (no valid bound is)
                                   must end the call with HD_E_INTERNAL. */
+    int32_t split_levels;      /* 0 (default): a breadth-first round that splits at most 8192
+                                  triangles splits each of them two levels deep at once (its 16
+                                  grandchildren, every one bounded), so that the few last rounds,
+                                  bound by kernel latency rather than work, take half as many
+                                  launches; 1: every round splits one level (1 -> 4). Sub-batched
+                                  and host-driven rounds always split one level. */
+    int32_t pad_opt;
 } hd_options;
 
 /* One record of hd_options.round_log: the state after a round. */

@@ -43,7 +43,8 @@ class Options(C.Structure):
                 ("log_frontier", C.c_int32), ("mlp_params", C.c_void_p), ("log_out", C.c_void_p),
                 ("log_cap", C.c_int64), ("autotune", C.c_int32), ("query_lanes", C.c_int32),
                 ("eps_relative", C.c_int32), ("query_shape", C.c_int32), ("tuner_cache", C.c_char_p),
-                ("round_log", C.c_void_p), ("round_log_cap", C.c_int64), ("test_bound_shift", C.c_double)]
+                ("round_log", C.c_void_p), ("round_log_cap", C.c_int64), ("test_bound_shift", C.c_double),
+                ("split_levels", C.c_int32), ("pad_opt", C.c_int32)]
 
 
 class RoundRecord(C.Structure):
@@ -197,12 +198,14 @@ def build_bvh(VB, FB) -> Bvh:
 def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity=0, max_rounds=0,
                  stack_depth=0, subbatch=0, profile=0, learned=0, mlp_params=None, log_out=None,
                  autotune=0, query_lanes=0, relative=False, tuner_cache=None, round_log=None,
-                 test_bound_shift=0.0, query_shape=0) -> Options:
+                 test_bound_shift=0.0, query_shape=0, split_levels=0) -> Options:
     """mlp_params: device FP32 tensor of mlp_nparams() values (learned > 0);
     log_out: device FP32 tensor (rows, 17) that receives the frontier log;
     relative: eps is the paper's relative tolerance (times dA) instead of an
     absolute one; tuner_cache: path of the autotuner's JSON cache file;
-    round_log: a ctypes array of RoundRecord that receives one record per round."""
+    round_log: a ctypes array of RoundRecord that receives one record per round;
+    split_levels: 1 keeps every round to one level of subdivision (0: small
+    breadth-first rounds split two levels deep)."""
     o = Options()
     load_library().hd_default_options(C.byref(o))
     o.precision, o.order, o.budget_m = precision, order, budget_m
@@ -214,6 +217,7 @@ def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity
     o.query_shape = query_shape
     o.eps_relative = 1 if relative else 0
     o.test_bound_shift = float(test_bound_shift)
+    o.split_levels = split_levels
     if tuner_cache is not None:
         o._tuner_cache = os.fsencode(tuner_cache)  # kept alive with the options
         o.tuner_cache = o._tuner_cache

@@ -114,6 +114,9 @@ struct Ctl {
     alignas(256) int argmax_new;
     // device-planned rounds (written by plan_round, read by the round's kernels)
     alignas(256) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
+    unsigned long long plan_Q;                         // the round's point queries (3 or 12 per parent)
+    int plan_two;                                      // 1: the round splits each parent two levels deep
+    int lvl_bound;                                     // no record is deeper than this subdivision level
     unsigned long long nref;                           // referenced vertices of A (round 0's queries)
     unsigned long long subdivided, rounds;             // totals over the planned rounds
     double processed;                                  // faces processed (the paper's budget count)
@@ -333,6 +336,8 @@ struct PlanCaps {
     int grow_act, grow_park;     // 1: the host can still grow the active / parked lists
     int64_t subbatch;            // > 0: the round splits the sub-batch the device selects
     int learned;                 // sub-batches in learned order (the selection may take all)
+    int64_t two_max;             // breadth-first rounds of at most this many parents split two
+                                 // levels deep (0: never)
 };
 __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     const int64_t nAct = (int64_t)c->act_next, nPark = (int64_t)c->park_next;
@@ -343,12 +348,12 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     const int64_t want =
         caps.subbatch > 0 && !caps.learned ? (nAct < caps.subbatch ? nAct : caps.subbatch) : nAct;
     const int64_t reserve_park = caps.subbatch > 0 ? nAct : 0;
+    // records waiting for stage C may each still join either list
+    const int64_t nc = c->c_decision == 1 ? 0 : (int64_t)c->c_next;
     int64_t K = 0, kcap = 0;
     if (!c->bad && !c->stall && !c->over_budget && nAct > 0) {
         // room in the active-side lists (the pending and midpoint lists are
         // sized with the active ones) and in the parked list
-        // (records waiting for stage C may each still join either list)
-        const int64_t nc = c->c_decision == 1 ? 0 : (int64_t)c->c_next;
         int64_t ka = (caps.act - nAct - nc) / 3;
         ka = ka < caps.pend / 4 ? ka : caps.pend / 4;
         ka = ka < (caps.pend_c - nc) / 4 ? ka : (caps.pend_c - nc) / 4;
@@ -371,6 +376,8 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     if (caps.subbatch > 0) {
         // the selection passes pick about K records and finish the plan
         // (split count, carried count, budget, totals)
+        c->plan_two = 0;
+        c->plan_Q = 0;
         c->plan_K = (unsigned long long)K;
         c->plan_kcap = (unsigned long long)(kcap > 0 ? kcap : 0);
         c->sel_prom = 0;
@@ -380,11 +387,34 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
         c->n_overflow = 0;
         return;
     }
+    // A round with few parents is bound by the latency of its kernels, not
+    // by their work: splitting each parent two levels deep at once (its 16
+    // grandchildren, from the 12 non-corner points of its resolution-4
+    // lattice) does the next round's splits of its children in the same
+    // launches. Every grandchild is bounded as usual; a child that a
+    // one-level round would have discarded just has its four children
+    // bounded (and discarded) instead. Only while every record is at least
+    // two levels above the depth limit, and when the lists and the budget
+    // have room for 16 children per parent.
+    int two = 0;
+    if (K > 0 && K <= caps.two_max && c->lvl_bound + 2 <= 30) {
+        int64_t kd = (caps.act - nAct - nc) / 15;
+        kd = kd < caps.pend / 16 ? kd : caps.pend / 16;
+        kd = kd < (caps.pend_c - nc) / 16 ? kd : (caps.pend_c - nc) / 16;
+        kd = kd < caps.mq / 12 ? kd : caps.mq / 12;
+        const int64_t kpd = (caps.park - nPark - nc) / 16;
+        two = K <= kd && K <= kpd && c->processed + 16.0 * (double)K <= caps.budget;
+    }
     c->plan_K = (unsigned long long)K;
+    c->plan_Q = (unsigned long long)K * (two ? 12u : 3u);
+    c->plan_two = two;
     c->plan_rest = (unsigned long long)(nAct - K);
-    c->processed += 4.0 * (double)K;
+    c->processed += (two ? 16.0 : 4.0) * (double)K;
     c->subdivided += (unsigned long long)K;
-    if (K > 0) c->rounds += 1;
+    if (K > 0) {
+        c->rounds += 1;
+        c->lvl_bound += two ? 2 : 1;
+    }
     c->act_next = (unsigned long long)(nAct - K);
     c->park_next = (unsigned long long)nPark;
     c->b_next = 0;
@@ -631,7 +661,13 @@ template <class T> struct QueryIn {
     FrontierView<T> par;     // Q_MIDPOINTS / Q_LATTICE: selected parents
     const PairConst *pc;
     const int32_t *sel;      // Q_MIDPOINTS: record index of each parent (null: the first parents)
+    const int *two;          // Q_MIDPOINTS: with *two set, the round splits each parent two levels
+                             // deep and queries its 12 lattice points instead of its 3 midpoints
 };
+
+// Q_MIDPOINTS in a two-level round: lattice point k (0..11) of the parent's
+// resolution-4 lattice, at the parent's level + 2
+HD_D int two_level(const int *two) { return two ? *two : 0; }
 
 struct QPoint {
     V3<double> p;
@@ -697,6 +733,24 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
         q.seed[1] = in.par.I(heavy == 2 ? 0 : heavy + 1)[j];
         return q;
     }
+    if (two_level(in.two)) {
+        const int64_t js = i / LATTICE_PTS;
+        const int k = (int)(i - LATTICE_PTS * js);
+        const int a1 = (LATTICE_A1 >> (2 * k)) & 3, a2 = (LATTICE_A2 >> (2 * k)) & 3, a0 = 4 - a1 - a2;
+        const int64_t j = in.sel ? (int64_t)in.sel[js] : js;
+        // (the plan keeps every parent at least two levels above the limit)
+        const int face = in.par.face()[j], lvl = in.par.lvl()[j] + 2;
+        const int ba = a0 * in.par.ba(0)[j] + a1 * in.par.ba(1)[j] + a2 * in.par.ba(2)[j];
+        const int bb = a0 * in.par.bb(0)[j] + a1 * in.par.bb(1)[j] + a2 * in.par.bb(2)[j];
+        q.pair = in.par.pair()[j];
+        q.p = a_point(in.a, q.pair, face, lvl, ba, bb);
+        q.out = i;
+        q.tag = point_tag(face, lvl, ba, bb);
+        const int heavy = a0 >= a1 && a0 >= a2 ? 0 : (a1 >= a2 ? 1 : 2);
+        q.seed[0] = in.par.I(heavy)[j];
+        q.seed[1] = in.par.I(heavy == 2 ? 0 : heavy + 1)[j];
+        return q;
+    }
     const int64_t js = i / 3;
     const int e = (int)(i - 3 * js);
     const int k = (e + 1) % 3;
@@ -718,7 +772,7 @@ template <class T> HD_D int query_pair(const QueryIn<T> &in, int64_t i) {
     if (in.mode == Q_VERTICES) return pair_of(in.voff, in.npairs, in.vids[i]);
     if (in.mode == Q_BARYCENTERS) return in.par.pair()[i];
     if (in.mode == Q_LATTICE) return in.par.pair()[i / LATTICE_PTS];
-    const int64_t js = i / 3;
+    const int64_t js = i / (two_level(in.two) ? LATTICE_PTS : 3);
     return in.par.pair()[in.sel ? (int64_t)in.sel[js] : js];
 }
 
@@ -1481,23 +1535,76 @@ template <class T> HD_D void copy_record(const FrontierView<T> &src, int64_t i, 
 // ahead of the appended children (plan_round starts the append count there).
 // With sel and rest (device sub-batch selection) the parents and the carried
 // records are the ones those index lists name.
-template <class T>
+//
+// A two-level round (ctl->plan_two, planned rounds only) gives every parent
+// its 16 grandchildren instead: the unit triangles of its resolution-4
+// lattice, (i,j) (i+1,j) (i,j+1) for i + j <= 3 and (i+1,j) (i+1,j+1)
+// (i,j+1) for i + j <= 2, with (i,j) the weights of parent corners 1 and 2
+// over 4 (so each keeps the parent's orientation). TWO_CORNER[c] holds, four
+// bits per grandchild, where its corner c comes from: 0..11 the parent's
+// lattice query of that index, 12..14 the parent's corner 0..2.
+// (The two forms are separate instantiations, both enqueued in planned
+// breadth-first rounds, the one that does not match the plan returning at
+// once: in one kernel the two-level form's registers would cost the large
+// one-level rounds occupancy.)
+constexpr uint64_t TWO_CORNER[3] = {0x567230567823401cull, 0x9ab673d9ab567230ull, 0x6783419abe678341ull};
+template <class T, int TWO>
 __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T> par, QueryOut<T> mq,
                                                   ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry,
                                                   const int32_t *__restrict__ sel, const int32_t *__restrict__ rest) {
+    if (carry && ctl->plan_two != TWO) return;
     const int64_t nsel = nselc.get();
     if (carry) {
         const int64_t nrest = (int64_t)ctl->plan_rest;
         for (int64_t o = (int64_t)blockIdx.x * BLK + threadIdx.x; o < nrest; o += (int64_t)gridDim.x * BLK)
             copy_record(par, rest ? (int64_t)rest[o] : nsel + o, dst.act, o);
     }
-    for (int64_t cbase = (int64_t)blockIdx.x * BLK; cbase < 4 * nsel; cbase += (int64_t)gridDim.x * BLK) {
+    constexpr bool two = TWO != 0;
+    const int64_t nkids = (two ? 16 : 4) * nsel;
+    for (int64_t cbase = (int64_t)blockIdx.x * BLK; cbase < nkids; cbase += (int64_t)gridDim.x * BLK) {
     const int64_t c = cbase + threadIdx.x;
-    bool valid = c < 4 * nsel;
+    bool valid = c < nkids;
     int list = TO_DISCARD, decider = 0, pair = 0, face = 0, lvl = 0;
     double carry = 0;
     Corner<T> cn[3];
-    if (valid) {
+    if (valid && two) {
+        const int64_t js = c >> 4;
+        const int64_t j = sel ? (int64_t)sel[js] : js;
+        const int g = (int)(c & 15);
+        const int pba[3] = {par.ba(0)[j], par.ba(1)[j], par.ba(2)[j]};
+        const int pbb[3] = {par.bb(0)[j], par.bb(1)[j], par.bb(2)[j]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Corner<T> &o = cn[k];
+            const int src = (int)((TWO_CORNER[k] >> (4 * g)) & 15u);
+            int a1, a2;
+            if (src >= LATTICE_PTS) {
+                const int pk = src - LATTICE_PTS; // a parent corner
+                o.v = {par.v(3 * pk)[j], par.v(3 * pk + 1)[j], par.v(3 * pk + 2)[j]};
+                o.q = {par.q(3 * pk)[j], par.q(3 * pk + 1)[j], par.q(3 * pk + 2)[j]};
+                o.d = par.d(pk)[j];
+                o.I = par.I(pk)[j];
+                a1 = pk == 1 ? 4 : 0;
+                a2 = pk == 2 ? 4 : 0;
+            } else {
+                const int64_t mi = LATTICE_PTS * js + src;
+                o.v = {mq.p[0][mi], mq.p[1][mi], mq.p[2][mi]};
+                o.q = {mq.q[0][mi], mq.q[1][mi], mq.q[2][mi]};
+                o.d = mq.d[mi];
+                o.I = mq.I[mi];
+                a1 = (LATTICE_A1 >> (2 * src)) & 3;
+                a2 = (LATTICE_A2 >> (2 * src)) & 3;
+            }
+            // the point's dyadic numerators at the parent's level + 2 (the
+            // lattice query used the same ones)
+            const int a0 = 4 - a1 - a2;
+            o.ba = a0 * pba[0] + a1 * pba[1] + a2 * pba[2];
+            o.bb = a0 * pbb[0] + a1 * pbb[1] + a2 * pbb[2];
+        }
+        pair = par.pair()[j];
+        face = par.face()[j];
+        lvl = par.lvl()[j] + 2;
+    } else if (valid) {
         const int64_t js = c >> 2;                       // the parent's position in the round
         const int64_t j = sel ? (int64_t)sel[js] : js;   // its record
         const int kid = (int)(c & 3);
@@ -1539,6 +1646,8 @@ __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T
         pair = par.pair()[j];
         face = par.face()[j];
         lvl = par.lvl()[j] + 1;
+    }
+    if (valid) {
         // dyadic coordinates are int32 numerators over 2^lvl: level 30 is the
         // deepest representable one
         if (lvl > 30) ctl->bad = 3;
@@ -1597,6 +1706,10 @@ constexpr int64_t C_FLUSH_MIN = 4096;
 // device-planned rounds: a pending round that splits at most this many
 // triangles is not followed by one enqueued ahead of its report
 constexpr int64_t LOOKAHEAD_MIN = 64;
+
+// device-planned breadth-first rounds of at most this many parents split each
+// of them two levels deep (hd_options.split_levels)
+constexpr int64_t TWO_LEVEL_MAX = 8192;
 
 // stage C's records [0, n) in a grid-stride loop (every thread of the block)
 template <class T>
@@ -2117,11 +2230,15 @@ __global__ __launch_bounds__(BLK) void k_sel_hist2(FrontierView<T> act, SelCfg s
     ctl->sel_mode = mode;
     ctl->sel_thr = mode == SEL_THRESHOLD ? thr : (mode == SEL_ALL ? 0u : 0xffffffffu);
     ctl->plan_K = K;
+    ctl->plan_Q = 3 * K;
     ctl->plan_rest = live - K;
     ctl->act_next = live - K; // the carried records lead the round's output list
     ctl->processed += 4.0 * (double)K;
     ctl->subdivided += K;
-    if (K > 0) ctl->rounds += 1;
+    if (K > 0) {
+        ctl->rounds += 1;
+        ctl->lvl_bound += 1;
+    }
     ctl->sel_next = 0;
     ctl->rest_next = 0;
 }
@@ -2707,6 +2824,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         if (!(in.eps[p] > 0) || !std::isfinite(in.eps[p])) throw Error{HD_E_INVALID, "eps must be positive"};
     if (opt.eps_relative != 0 && opt.eps_relative != 1) throw Error{HD_E_INVALID, "eps_relative must be 0 or 1"};
     if (!std::isfinite(opt.test_bound_shift)) throw Error{HD_E_INVALID, "test_bound_shift must be finite"};
+    if (opt.split_levels != 0 && opt.split_levels != 1) throw Error{HD_E_INVALID, "split_levels must be 0 or 1"};
     if (opt.round_log_cap < 0 || (opt.round_log_cap > 0 && !opt.round_log))
         throw Error{HD_E_INVALID, "round log needs a host array"};
     const bool logging = opt.round_log != nullptr && opt.round_log_cap > 0;
@@ -3003,6 +3121,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         c.grow_park = c.park < cap_limit;
         c.subbatch = sel_round ? opt.subbatch : 0;
         c.learned = sel_round && opt.learned > 0 ? 1 : 0;
+        c.two_max = !sel_round && opt.split_levels != 1 ? TWO_LEVEL_MAX : 0;
         return c;
     };
     // plan_seq != 0: the stages end a device-planned round (report under
@@ -3157,11 +3276,19 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             qi.par = tw.act.v;
             qi.pc = pc;
             qi.sel = selp;
-            run_queries(qi, DevCount{&ctl->plan_K, 3, 0}, 3 * kmax, tw.mq.o);
+            qi.two = &ctl->plan_two;
+            // (the plan keeps the round's queries, 3 or 12 per parent, within
+            // 3 * kmax: two-level rounds need room for 16 children per parent)
+            run_queries(qi, DevCount{&ctl->plan_Q, 1, 0}, 3 * kmax, tw.mq.o);
             prof.mark(prof.c);
-            k_children<T><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
+            k_children<T, 0><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
                 DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
                 Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp, restp);
+            if (c.two_max > 0)
+                k_children<T, 1><<<std::min<unsigned>(grid_for(16 * std::min(kmax, c.two_max), BLK), GRID_MAX), BLK,
+                                   0, s>>>(DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
+                                           Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp,
+                                           restp);
             HD_LAUNCH_CHECK();
             const unsigned seq = ++ws.mb_seq;
             later_stages(4 * kmax, tw.act2.v, 1, seq);
@@ -3363,7 +3490,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         tw.pend_b.ensure(4 * K, 0, s);
         if (cc.recheck) tw.pend_c.ensure(4 * K, 0, s);
         prof.mark(prof.c);
-        k_children<T><<<std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX), BLK, 0, s>>>(host_count(K), tw.act.v,
+        k_children<T, 0><<<std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX), BLK, 0, s>>>(host_count(K), tw.act.v,
                                                                                           tw.mq.o, cc,
                                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
                                                            ctl, 0, nullptr, nullptr);

@@ -88,38 +88,42 @@ __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 // Exclusive scan of a short array (n <= SMALL_SCAN_MAX, 16-byte aligned) in
 // one block of SMALL_SCAN_BLOCK threads. The array is cut into tiles of
 // SMALL_SCAN_BLOCK x 4 values; thread t loads values 4t..4t+3 of every tile
-// (one coalesced 16-byte load per tile, all in flight at once), and the
-// block scans the per-thread sums of all tiles together (one LDS exchange),
-// each tile's total carried into the next. One launch instead of three.
+// (one coalesced 16-byte load per tile, all in flight at once) and keeps only
+// their sums; the block scans the per-thread sums of all tiles together (one
+// LDS exchange), each tile's total carried into the next, and every thread
+// then reads its four values again (from the L2) to write their offsets.
+// One launch instead of three, up to 64 Ki values (the digit table of a
+// radix sort of 800 k keys).
 constexpr int SMALL_SCAN_BLOCK = 1024;
-constexpr int SMALL_SCAN_TILES = 8;
+constexpr int SMALL_SCAN_TILES = 16;
 constexpr int64_t SMALL_SCAN_TILE = (int64_t)SMALL_SCAN_BLOCK * 4;
 constexpr int64_t SMALL_SCAN_MAX = SMALL_SCAN_TILE * SMALL_SCAN_TILES;
-__global__ __launch_bounds__(SMALL_SCAN_BLOCK) void k_scan_small(const int32_t *__restrict__ in,
-                                                                 int32_t *__restrict__ out, int64_t n,
+__device__ __forceinline__ int4 load4_tail(const int32_t *__restrict__ in, int i, int n) {
+    if (i + 3 < n) return *reinterpret_cast<const int4 *>(in + i);
+    int4 v;
+    v.x = i < n ? in[i] : 0;
+    v.y = i + 1 < n ? in[i + 1] : 0;
+    v.z = i + 2 < n ? in[i + 2] : 0;
+    v.w = 0;
+    return v;
+}
+__global__ __launch_bounds__(SMALL_SCAN_BLOCK) void k_scan_small(const int32_t *in, int32_t *out, int64_t n,
                                                                  int32_t *d_total) {
     constexpr int NW = SMALL_SCAN_BLOCK / 64;
     __shared__ int wsum[SMALL_SCAN_TILES][NW];
     const int w = threadIdx.x >> 6;
-    int4 v[SMALL_SCAN_TILES];
-    int sum[SMALL_SCAN_TILES], inc[SMALL_SCAN_TILES];
+    const int m = (int)n; // n <= SMALL_SCAN_MAX
+    int exc[SMALL_SCAN_TILES]; // the thread's exclusive offset inside its wave, per tile
 #pragma unroll
     for (int k = 0; k < SMALL_SCAN_TILES; ++k) {
-        const int64_t i = k * SMALL_SCAN_TILE + 4 * (int64_t)threadIdx.x;
-        if (i + 3 < n) {
-            v[k] = *reinterpret_cast<const int4 *>(in + i);
-        } else {
-            v[k].x = i < n ? in[i] : 0;
-            v[k].y = i + 1 < n ? in[i + 1] : 0;
-            v[k].z = i + 2 < n ? in[i + 2] : 0;
-            v[k].w = 0;
-        }
+        const int4 v = load4_tail(in, k * (int)SMALL_SCAN_TILE + 4 * (int)threadIdx.x, m);
+        exc[k] = v.x + v.y + v.z + v.w;
     }
 #pragma unroll
     for (int k = 0; k < SMALL_SCAN_TILES; ++k) {
-        sum[k] = v[k].x + v[k].y + v[k].z + v[k].w;
-        inc[k] = wave_inclusive_scan(sum[k]);
-        if (__lane_id() == 63) wsum[k][w] = inc[k];
+        const int inc = wave_inclusive_scan(exc[k]);
+        if (__lane_id() == 63) wsum[k][w] = inc;
+        exc[k] = inc - exc[k];
     }
     __syncthreads();
     int carry = 0;
@@ -132,18 +136,19 @@ __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void k_scan_small(const int32_t *
             if (i < w) off += t;
             tot += t;
         }
-        const int64_t i = k * SMALL_SCAN_TILE + 4 * (int64_t)threadIdx.x;
+        const int i = k * (int)SMALL_SCAN_TILE + 4 * (int)threadIdx.x;
+        const int4 v = load4_tail(in, i, m);
         int4 o;
-        o.x = carry + off + inc[k] - sum[k];
-        o.y = o.x + v[k].x;
-        o.z = o.y + v[k].y;
-        o.w = o.z + v[k].z;
-        if (i + 3 < n) {
+        o.x = carry + off + exc[k];
+        o.y = o.x + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        if (i + 3 < m) {
             *reinterpret_cast<int4 *>(out + i) = o;
         } else {
-            if (i < n) out[i] = o.x;
-            if (i + 1 < n) out[i + 1] = o.y;
-            if (i + 2 < n) out[i + 2] = o.z;
+            if (i < m) out[i] = o.x;
+            if (i + 1 < m) out[i + 1] = o.y;
+            if (i + 2 < m) out[i + 2] = o.z;
         }
         carry += tot;
     }
