@@ -2824,7 +2824,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         if (!(in.eps[p] > 0) || !std::isfinite(in.eps[p])) throw Error{HD_E_INVALID, "eps must be positive"};
     if (opt.eps_relative != 0 && opt.eps_relative != 1) throw Error{HD_E_INVALID, "eps_relative must be 0 or 1"};
     if (!std::isfinite(opt.test_bound_shift)) throw Error{HD_E_INVALID, "test_bound_shift must be finite"};
-    if (opt.split_levels != 0 && opt.split_levels != 1) throw Error{HD_E_INVALID, "split_levels must be 0 or 1"};
+    if (opt.split_levels < 0) throw Error{HD_E_INVALID, "split_levels must not be negative"};
     if (opt.round_log_cap < 0 || (opt.round_log_cap > 0 && !opt.round_log))
         throw Error{HD_E_INVALID, "round log needs a host array"};
     const bool logging = opt.round_log != nullptr && opt.round_log_cap > 0;
@@ -3121,7 +3121,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         c.grow_park = c.park < cap_limit;
         c.subbatch = sel_round ? opt.subbatch : 0;
         c.learned = sel_round && opt.learned > 0 ? 1 : 0;
-        c.two_max = !sel_round && opt.split_levels != 1 ? TWO_LEVEL_MAX : 0;
+        c.two_max = sel_round || opt.split_levels == 1 ? 0 : (opt.split_levels == 0 ? TWO_LEVEL_MAX : opt.split_levels);
         return c;
     };
     // plan_seq != 0: the stages end a device-planned round (report under

@@ -855,9 +855,9 @@ def test_split_levels_out_of_range():
     hd, torch = _hd()
     W = wl.config(1)
     bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
-    say("split_levels 2 is rejected")
+    say("split_levels -1 is rejected")
     with pytest.raises(hd.HDError):
-        hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, relative=True, split_levels=2)
+        hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, relative=True, split_levels=-1)
 
 
 def test_round_limit_decides_the_waiting_band():
