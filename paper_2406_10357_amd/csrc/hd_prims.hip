@@ -89,11 +89,12 @@ __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 // one block of SMALL_SCAN_BLOCK threads. The array is cut into tiles of
 // SMALL_SCAN_BLOCK x 4 values; thread t loads values 4t..4t+3 of every tile
 // (one coalesced 16-byte load per tile, all in flight at once) and keeps only
-// their sums; the block scans the per-thread sums of all tiles together (one
-// LDS exchange), each tile's total carried into the next, and every thread
-// then reads its four values again (from the L2) to write their offsets.
-// One launch instead of three, up to 64 Ki values (the digit table of a
-// radix sort of 800 k keys).
+// their sums. Each wave scans its sums per tile; one wave then scans the
+// 16 x 16 wave totals in (tile, wave) order, which is the order of the values,
+// so every thread finds its offset in one LDS read per tile; it then reads
+// its four values again (from the L2) to write their offsets. One launch
+// instead of three, up to 64 Ki values (the digit table of a radix sort of
+// 800 k keys).
 constexpr int SMALL_SCAN_BLOCK = 1024;
 constexpr int SMALL_SCAN_TILES = 16;
 constexpr int64_t SMALL_SCAN_TILE = (int64_t)SMALL_SCAN_BLOCK * 4;
@@ -110,7 +111,9 @@ __device__ __forceinline__ int4 load4_tail(const int32_t *__restrict__ in, int i
 __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void k_scan_small(const int32_t *in, int32_t *out, int64_t n,
                                                                  int32_t *d_total) {
     constexpr int NW = SMALL_SCAN_BLOCK / 64;
-    __shared__ int wsum[SMALL_SCAN_TILES][NW];
+    static_assert(SMALL_SCAN_TILES * NW == 4 * 64, "one wave scans the wave totals, four per lane");
+    __shared__ int wsum[SMALL_SCAN_TILES][NW]; // wave totals, then their exclusive prefix
+    __shared__ int s_total;
     const int w = threadIdx.x >> 6;
     const int m = (int)n; // n <= SMALL_SCAN_MAX
     int exc[SMALL_SCAN_TILES]; // the thread's exclusive offset inside its wave, per tile
@@ -126,20 +129,26 @@ __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void k_scan_small(const int32_t *
         exc[k] = inc - exc[k];
     }
     __syncthreads();
-    int carry = 0;
+    if (threadIdx.x < 64) {
+        int *flat = &wsum[0][0];
+        const int l = threadIdx.x;
+        const int t0 = flat[4 * l], t1 = flat[4 * l + 1], t2 = flat[4 * l + 2], t3 = flat[4 * l + 3];
+        const int tot = t0 + t1 + t2 + t3;
+        const int inc = wave_inclusive_scan(tot);
+        const int ex = inc - tot;
+        flat[4 * l] = ex;
+        flat[4 * l + 1] = ex + t0;
+        flat[4 * l + 2] = ex + t0 + t1;
+        flat[4 * l + 3] = ex + t0 + t1 + t2;
+        if (l == 63) s_total = inc;
+    }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < SMALL_SCAN_TILES; ++k) {
-        int off = 0, tot = 0;
-#pragma unroll
-        for (int i = 0; i < NW; ++i) {
-            const int t = wsum[k][i];
-            if (i < w) off += t;
-            tot += t;
-        }
         const int i = k * (int)SMALL_SCAN_TILE + 4 * (int)threadIdx.x;
         const int4 v = load4_tail(in, i, m);
         int4 o;
-        o.x = carry + off + exc[k];
+        o.x = wsum[k][w] + exc[k];
         o.y = o.x + v.x;
         o.z = o.y + v.y;
         o.w = o.z + v.z;
@@ -150,9 +159,8 @@ __global__ __launch_bounds__(SMALL_SCAN_BLOCK) void k_scan_small(const int32_t *
             if (i + 1 < m) out[i + 1] = o.y;
             if (i + 2 < m) out[i + 2] = o.z;
         }
-        carry += tot;
     }
-    if (threadIdx.x == 0 && d_total) *d_total = carry;
+    if (threadIdx.x == 0 && d_total) *d_total = s_total;
 }
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
