@@ -118,10 +118,12 @@ typedef struct {
                                   must end the call with HD_E_INTERNAL. */
     int32_t split_levels;      /* 0 (default): a breadth-first round that splits at most 8192
                                   triangles splits each of them two levels deep at once (its 16
-                                  grandchildren, every one bounded), so that the few last rounds,
-                                  bound by kernel latency rather than work, take fewer launches;
-                                  1: every round splits one level (1 -> 4); k >= 2: rounds of at
-                                  most k triangles split two levels. Sub-batched and host-driven
+                                  grandchildren, every one bounded), and one of at most 64
+                                  triangles four levels deep (256 descendants), so that the few
+                                  last rounds, bound by kernel latency rather than work, take
+                                  fewer launches; 1: every round splits one level (1 -> 4); 2: at
+                                  most two levels; k >= 3: rounds of at most k triangles split two
+                                  levels (and of at most 64, four). Sub-batched and host-driven
                                   rounds always split one level. Negative: HD_E_INVALID. */
     int32_t pad_opt;
 } hd_options;

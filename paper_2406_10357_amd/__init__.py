@@ -205,8 +205,8 @@ def make_options(precision=PREC_FP32_RECHECK, order=1234, budget_m=1e7, capacity
     absolute one; tuner_cache: path of the autotuner's JSON cache file;
     round_log: a ctypes array of RoundRecord that receives one record per round;
     split_levels: 1 keeps every round to one level of subdivision (0: small
-    breadth-first rounds split two levels deep; k >= 2: rounds of at most k
-    triangles do)."""
+    breadth-first rounds split two levels deep, the smallest four; 2: at most
+    two; k >= 3: rounds of at most k triangles split two levels)."""
     o = Options()
     load_library().hd_default_options(C.byref(o))
     o.precision, o.order, o.budget_m = precision, order, budget_m

@@ -115,7 +115,8 @@ struct Ctl {
     // device-planned rounds (written by plan_round, read by the round's kernels)
     alignas(256) unsigned long long plan_K, plan_rest; // parents split this round, records carried over
     unsigned long long plan_Q;                         // the round's point queries (3 or 12 per parent)
-    int plan_two;                                      // 1: the round splits each parent two levels deep
+    int plan_two;                                      // levels each parent is split this round, less
+                                                       // one: 0 (1 -> 4), 2 (1 -> 16) or 4 (1 -> 256)
     int lvl_bound;                                     // no record is deeper than this subdivision level
     unsigned long long nref;                           // referenced vertices of A (round 0's queries)
     unsigned long long subdivided, rounds;             // totals over the planned rounds
@@ -330,6 +331,11 @@ __global__ void k_report(const Ctl *ctl, const PairVar *pv, Mailbox *ring, unsig
 // Device-planned round: how many active records to split (all of them,
 // capped by the list capacities and the face budget) and the per-round
 // counters. A round planned with nothing to do leaves everything in place.
+// the points of a resolution-16 barycentric lattice (corners included), the
+// query set of a four-level round; such rounds take at most this many parents
+constexpr int LAT16_N = 16;
+constexpr int LAT16_PTS = (LAT16_N + 1) * (LAT16_N + 2) / 2;
+constexpr int64_t FOUR_LEVEL_MAX = 64;
 struct PlanCaps {
     int64_t act, park, pend, pend_c, mq; // capacities (records / queries)
     double budget;               // the paper's m * nA
@@ -338,6 +344,7 @@ struct PlanCaps {
     int learned;                 // sub-batches in learned order (the selection may take all)
     int64_t two_max;             // breadth-first rounds of at most this many parents split two
                                  // levels deep (0: never)
+    int64_t four_max;            // and of at most this many, four (0: never)
 };
 __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     const int64_t nAct = (int64_t)c->act_next, nPark = (int64_t)c->park_next;
@@ -396,24 +403,32 @@ __device__ void plan_round(Ctl *c, const PlanCaps &caps) {
     // bounded (and discarded) instead. Only while every record is at least
     // two levels above the depth limit, and when the lists and the budget
     // have room for 16 children per parent.
-    int two = 0;
-    if (K > 0 && K <= caps.two_max && c->lvl_bound + 2 <= 30) {
-        int64_t kd = (caps.act - nAct - nc) / 15;
-        kd = kd < caps.pend / 16 ? kd : caps.pend / 16;
-        kd = kd < (caps.pend_c - nc) / 16 ? kd : (caps.pend_c - nc) / 16;
-        kd = kd < caps.mq / 12 ? kd : caps.mq / 12;
-        const int64_t kpd = (caps.park - nPark - nc) / 16;
-        two = K <= kd && K <= kpd && c->processed + 16.0 * (double)K <= caps.budget;
+    // A round of at most FOUR_LEVEL_MAX parents (the very last ones) goes
+    // four levels deep: the 153 points of each parent's resolution-16
+    // lattice and its 256 descendants at that level.
+    auto room = [&](int64_t kids, int64_t queries) {
+        int64_t kd = (caps.act - nAct - nc) / (kids - 1);
+        kd = kd < caps.pend / kids ? kd : caps.pend / kids;
+        kd = kd < (caps.pend_c - nc) / kids ? kd : (caps.pend_c - nc) / kids;
+        kd = kd < caps.mq / queries ? kd : caps.mq / queries;
+        const int64_t kpd = (caps.park - nPark - nc) / kids;
+        return K <= kd && K <= kpd && c->processed + (double)kids * (double)K <= caps.budget;
+    };
+    int dep = 0; // extra levels
+    if (K > 0 && K <= caps.two_max) {
+        if (K <= caps.four_max && c->lvl_bound + 4 <= 30 && room(256, LAT16_PTS)) dep = 4;
+        else if (c->lvl_bound + 2 <= 30 && room(16, 12)) dep = 2;
     }
+    const int kids = dep == 4 ? 256 : (dep == 2 ? 16 : 4);
     c->plan_K = (unsigned long long)K;
-    c->plan_Q = (unsigned long long)K * (two ? 12u : 3u);
-    c->plan_two = two;
+    c->plan_Q = (unsigned long long)K * (dep == 4 ? (unsigned)LAT16_PTS : (dep == 2 ? 12u : 3u));
+    c->plan_two = dep;
     c->plan_rest = (unsigned long long)(nAct - K);
-    c->processed += (two ? 16.0 : 4.0) * (double)K;
+    c->processed += (double)kids * (double)K;
     c->subdivided += (unsigned long long)K;
     if (K > 0) {
         c->rounds += 1;
-        c->lvl_bound += two ? 2 : 1;
+        c->lvl_bound += dep ? dep : 1;
     }
     c->act_next = (unsigned long long)(nAct - K);
     c->park_next = (unsigned long long)nPark;
@@ -669,6 +684,19 @@ template <class T> struct QueryIn {
 // resolution-4 lattice, at the parent's level + 2
 HD_D int two_level(const int *two) { return two ? *two : 0; }
 
+// point t of the resolution-N lattice, rows of constant a2 in order (row r
+// holds a1 = 0 .. N - r): its weights a1, a2 of parent corners 1 and 2 (over N)
+HD_D void lattice_point(int N, int t, int &a1, int &a2) {
+    int r = 0;
+    while (t > N - r) {
+        t -= N - r + 1;
+        ++r;
+    }
+    a1 = t;
+    a2 = r;
+}
+HD_D int lattice_index(int N, int a1, int a2) { return a2 * (N + 1) - (a2 * (a2 - 1)) / 2 + a1; }
+
 struct QPoint {
     V3<double> p;
     int pair;
@@ -733,6 +761,26 @@ template <class T> HD_D QPoint query_point(const QueryIn<T> &in, int64_t i) {
         q.seed[1] = in.par.I(heavy == 2 ? 0 : heavy + 1)[j];
         return q;
     }
+    if (two_level(in.two) == 4) {
+        // four-level round: every point of the parent's resolution-16 lattice
+        // (corners included), at the parent's level + 4
+        const int64_t js = i / LAT16_PTS;
+        int a1, a2;
+        lattice_point(LAT16_N, (int)(i - LAT16_PTS * js), a1, a2);
+        const int a0 = LAT16_N - a1 - a2;
+        const int64_t j = in.sel ? (int64_t)in.sel[js] : js;
+        const int face = in.par.face()[j], lvl = in.par.lvl()[j] + 4;
+        const int ba = a0 * in.par.ba(0)[j] + a1 * in.par.ba(1)[j] + a2 * in.par.ba(2)[j];
+        const int bb = a0 * in.par.bb(0)[j] + a1 * in.par.bb(1)[j] + a2 * in.par.bb(2)[j];
+        q.pair = in.par.pair()[j];
+        q.p = a_point(in.a, q.pair, face, lvl, ba, bb);
+        q.out = i;
+        q.tag = point_tag(face, lvl, ba, bb);
+        const int heavy = a0 >= a1 && a0 >= a2 ? 0 : (a1 >= a2 ? 1 : 2);
+        q.seed[0] = in.par.I(heavy)[j];
+        q.seed[1] = in.par.I(heavy == 2 ? 0 : heavy + 1)[j];
+        return q;
+    }
     if (two_level(in.two)) {
         const int64_t js = i / LATTICE_PTS;
         const int k = (int)(i - LATTICE_PTS * js);
@@ -772,7 +820,8 @@ template <class T> HD_D int query_pair(const QueryIn<T> &in, int64_t i) {
     if (in.mode == Q_VERTICES) return pair_of(in.voff, in.npairs, in.vids[i]);
     if (in.mode == Q_BARYCENTERS) return in.par.pair()[i];
     if (in.mode == Q_LATTICE) return in.par.pair()[i / LATTICE_PTS];
-    const int64_t js = i / (two_level(in.two) ? LATTICE_PTS : 3);
+    const int dep = two_level(in.two);
+    const int64_t js = i / (dep == 4 ? LAT16_PTS : (dep ? LATTICE_PTS : 3));
     return in.par.pair()[in.sel ? (int64_t)in.sel[js] : js];
 }
 
@@ -1552,7 +1601,7 @@ template <class T, int TWO>
 __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T> par, QueryOut<T> mq,
                                                   ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry,
                                                   const int32_t *__restrict__ sel, const int32_t *__restrict__ rest) {
-    if (carry && ctl->plan_two != TWO) return;
+    if (carry && (ctl->plan_two != 0) != (TWO != 0)) return;
     const int64_t nsel = nselc.get();
     if (carry) {
         const int64_t nrest = (int64_t)ctl->plan_rest;
@@ -1560,14 +1609,49 @@ __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T
             copy_record(par, rest ? (int64_t)rest[o] : nsel + o, dst.act, o);
     }
     constexpr bool two = TWO != 0;
-    const int64_t nkids = (two ? 16 : 4) * nsel;
+    const int dep = two ? ctl->plan_two : 0; // 2: 16 grandchildren; 4: 256 descendants
+    const int64_t nkids = (dep == 4 ? 256 : (two ? 16 : 4)) * nsel;
     for (int64_t cbase = (int64_t)blockIdx.x * BLK; cbase < nkids; cbase += (int64_t)gridDim.x * BLK) {
     const int64_t c = cbase + threadIdx.x;
     bool valid = c < nkids;
     int list = TO_DISCARD, decider = 0, pair = 0, face = 0, lvl = 0;
     double carry = 0;
     Corner<T> cn[3];
-    if (valid && two) {
+    if (valid && two && dep == 4) {
+        // four-level round: unit triangle g of the parent's resolution-16
+        // lattice; its strip r (between rows a2 = r and r + 1) holds 2(N - r) - 1
+        // triangles, up (i,r) (i+1,r) (i,r+1) and down (i+1,r) (i+1,r+1) (i,r+1)
+        // alternating; every lattice point, corners included, was queried
+        constexpr int N = LAT16_N;
+        const int64_t js = c >> 8;
+        const int64_t j = sel ? (int64_t)sel[js] : js;
+        int g = (int)(c & 255), r = 0;
+        while (g >= 2 * (N - r) - 1) {
+            g -= 2 * (N - r) - 1;
+            ++r;
+        }
+        const int i0 = g >> 1;
+        const bool up = (g & 1) == 0;
+        const int ca1[3] = {up ? i0 : i0 + 1, i0 + 1, i0};
+        const int ca2[3] = {r, up ? r : r + 1, r + 1};
+        const int pba[3] = {par.ba(0)[j], par.ba(1)[j], par.ba(2)[j]};
+        const int pbb[3] = {par.bb(0)[j], par.bb(1)[j], par.bb(2)[j]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            Corner<T> &o = cn[k];
+            const int64_t mi = LAT16_PTS * js + lattice_index(N, ca1[k], ca2[k]);
+            o.v = {mq.p[0][mi], mq.p[1][mi], mq.p[2][mi]};
+            o.q = {mq.q[0][mi], mq.q[1][mi], mq.q[2][mi]};
+            o.d = mq.d[mi];
+            o.I = mq.I[mi];
+            const int a0 = N - ca1[k] - ca2[k];
+            o.ba = a0 * pba[0] + ca1[k] * pba[1] + ca2[k] * pba[2];
+            o.bb = a0 * pbb[0] + ca1[k] * pbb[1] + ca2[k] * pbb[2];
+        }
+        pair = par.pair()[j];
+        face = par.face()[j];
+        lvl = par.lvl()[j] + 4;
+    } else if (valid && two) {
         const int64_t js = c >> 4;
         const int64_t j = sel ? (int64_t)sel[js] : js;
         const int g = (int)(c & 15);
@@ -3121,7 +3205,10 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         c.grow_park = c.park < cap_limit;
         c.subbatch = sel_round ? opt.subbatch : 0;
         c.learned = sel_round && opt.learned > 0 ? 1 : 0;
-        c.two_max = sel_round || opt.split_levels == 1 ? 0 : (opt.split_levels == 0 ? TWO_LEVEL_MAX : opt.split_levels);
+        c.two_max = sel_round || opt.split_levels == 1
+                        ? 0
+                        : (opt.split_levels == 0 || opt.split_levels == 2 ? TWO_LEVEL_MAX : opt.split_levels);
+        c.four_max = c.two_max > 0 && opt.split_levels != 2 ? FOUR_LEVEL_MAX : 0;
         return c;
     };
     // plan_seq != 0: the stages end a device-planned round (report under

@@ -825,18 +825,20 @@ def test_every_bounded_triangle_is_decided_once(k, scale, prec, subbatch):
                                           (3, 0.02, "fp32"), (5, 0.02, "fp32+recheck"), (5, 0.02, "fp64")])
 def test_two_level_rounds_against_one_level_and_oracle(k, scale, prec):
     """Small breadth-first rounds split each parent two levels deep (its 16
-    grandchildren, from the 12 non-corner points of its resolution-4 lattice);
-    split_levels = 1 keeps every round to one level. Both forms certify an
-    interval that overlaps the oracle's within eps, both keep the conservation
-    identity (a parent split two levels deep counts once as subdivided, its
-    grandchildren as bounded), and the two-level form needs no more rounds."""
+    grandchildren, from the 12 non-corner points of its resolution-4 lattice),
+    the smallest ones four levels deep (256 descendants from its resolution-16
+    lattice); split_levels = 1 keeps every round to one level, 2 to at most two.
+    Every form certifies an interval that overlaps the oracle's within eps,
+    keeps the conservation identity (a parent split several levels deep counts
+    once as subdivided, its descendants as bounded), and the deeper forms need
+    no more rounds than one level per round."""
     hd, torch = _hd()
     W = wl.config(k, scale=scale)
     ref = oracle.bound(W.VA, W.FA, W.VB, W.FB, W.eps_rel, backend="brute" if k == 1 else "tree")
     assert ref["status"] == 0
     bvh = hd.build_bvh(_cu(W.VB, torch), _cu(W.FB, torch))
     res = {}
-    for lv in (1, 0):
+    for lv in (1, 2, 0):
         say(f"config{k} scale {scale}", prec, "split_levels", lv)
         L, U, st = hd.bound(_cu(W.VA, torch), _cu(W.FA, torch), bvh, W.eps_rel, precision=PRECS[prec],
                             relative=True, split_levels=lv)
@@ -844,9 +846,9 @@ def test_two_level_rounds_against_one_level_and_oracle(k, scale, prec):
         decided = sum(st["discards"]) + st["stale"] + st["parked_final"] + st["subdivided"]
         assert st["nodes_bounded"] == decided
         res[lv] = st
-    print("rounds one-level", res[1]["rounds"], "two-level", res[0]["rounds"], "bounded", res[1]["nodes_bounded"],
-          res[0]["nodes_bounded"])
-    assert res[0]["rounds"] <= res[1]["rounds"]
+    print("rounds one-level", res[1]["rounds"], "two-level", res[2]["rounds"], "default", res[0]["rounds"],
+          "bounded", res[1]["nodes_bounded"], res[2]["nodes_bounded"], res[0]["nodes_bounded"])
+    assert res[0]["rounds"] <= res[1]["rounds"] and res[2]["rounds"] <= res[1]["rounds"]
     # the vertex round and the first (large) rounds are the same in both forms
     assert res[0]["nodes_bounded"] >= W.FA.shape[0]
 
