@@ -94,15 +94,23 @@ struct PairSrc {
 
 // validate faces and compute each pair's vertex box (through its faces).
 // Every lane of a launched wave takes part (inactive lanes carry neutral
-// values) so that the wave-wide reductions see 64 lanes.
+// values) so that the wave-wide reductions see 64 lanes. With several pairs
+// the grid covers the faces (one each); with one pair it is capped
+// (ONE_PAIR_GRID blocks) and every thread folds a grid-stride run of faces, so
+// that fewer blocks end in the per-pair atomics.
+constexpr unsigned ONE_PAIR_GRID = 1024;
+inline unsigned face_grid(int64_t n, int npairs) {
+    const unsigned g = grid_for(n, BLK);
+    return npairs == 1 ? std::min(g, ONE_PAIR_GRID) : g;
+}
 __global__ void k_faces_check(const PairSrc *__restrict__ src, const int64_t *__restrict__ foff, int npairs,
                               int64_t n, PairAcc *acc, int astride, BuildState *st) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = f < n;
-    int p = pair_of(foff, npairs, valid ? f : n - 1);
+    const int64_t f0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = f0 < n;
+    const int p = pair_of(foff, npairs, valid ? f0 : n - 1); // every face of the thread's run (one pair)
     double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
     double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
-    if (valid) {
+    for (int64_t f = f0; f < n; f += (int64_t)gridDim.x * blockDim.x) {
         PairSrc ps = src[p];
         int64_t lf = f - foff[p];
         for (int j = 0; j < 3; ++j) {
@@ -159,9 +167,12 @@ __global__ __launch_bounds__(BLK) void k_centroids(const PairSrc *__restrict__ s
                                                    unsigned long long *__restrict__ keys,
                                                    int32_t *__restrict__ vals) {
     __shared__ double s_box[CENTRE_PAIRS][6];
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = f < n && !st->bad;
-    int p = pair_of(foff, npairs, f < n ? f : n - 1);
+    const int64_t fs = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = st->bad != 0;
+    const bool valid = fs < n && !bad;
+    // the pair of every face of the thread's run (one face per thread with
+    // several pairs; a grid-stride run with one)
+    const int p = pair_of(foff, npairs, fs < n ? fs : n - 1);
     const int64_t f0 = (int64_t)blockIdx.x * blockDim.x, f1 = std::min<int64_t>(f0 + blockDim.x, n) - 1;
     const int pa = pair_of(foff, npairs, f0), pb = pair_of(foff, npairs, f1);
     const bool in_lds = pb - pa < CENTRE_PAIRS;
@@ -171,10 +182,11 @@ __global__ __launch_bounds__(BLK) void k_centroids(const PairSrc *__restrict__ s
     double box[6];
     for (int k = 0; k < 6; ++k) box[k] = in_lds ? s_box[p - pa][k] : ord2d(fold_box(acc, astride, p, k));
     const double ctr[3] = {0.5 * (box[0] + box[3]), 0.5 * (box[1] + box[4]), 0.5 * (box[2] + box[5])};
-    if (f < n && f == foff[p])
-        for (int k = 0; k < 3; ++k) pairs[p].ctr[k] = ctr[k];
     double m = 0;
-    if (valid) {
+    for (int64_t f = fs; f < n; f += (int64_t)gridDim.x * blockDim.x) {
+    if (f == foff[p])
+        for (int k = 0; k < 3; ++k) pairs[p].ctr[k] = ctr[k];
+    if (!bad) {
         PairSrc ps = src[p];
         int64_t lf = f - foff[p];
         double c[3] = {0, 0, 0};
@@ -197,11 +209,12 @@ __global__ __launch_bounds__(BLK) void k_centroids(const PairSrc *__restrict__ s
         }
         keys[f] = ((unsigned long long)p << 32) | ((spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]));
         vals[f] = (int32_t)f;
-    } else if (f < n) {
+    } else {
         keys[f] = (unsigned long long)p << 32;
         vals[f] = (int32_t)f;
     }
-    if (f < n) fpair[f] = p;
+    fpair[f] = p;
+    }
     const double v[1] = {m};
     block_pair_minmax<1, 1u, BLK>(p, valid, v, [&](int q, int) { return &acc_of(acc, astride, q).coord_max; });
 }
@@ -877,8 +890,8 @@ Bvh *build_bvh(int npairs, const double *const *VB, const int64_t *mB, const int
             HD_HIP(hipMemcpyAsync(dsrc, sc.host.as<char>(o_src), o_pairs - o_src, hipMemcpyHostToDevice, q));
             HD_HIP(hipMemcpyAsync(dpairs, hp, npairs * sizeof(BvhPair), hipMemcpyHostToDevice, q));
             k_init<<<grid_for((int64_t)npairs * ACC_COPIES, 64), 64, 0, q>>>(acc, npairs, astride, st);
-            k_faces_check<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, astride, st);
-            k_centroids<<<grid_for(n, BLK), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
+            k_faces_check<<<face_grid(n, npairs), BLK, 0, q>>>(dsrc, dfoff, npairs, n, acc, astride, st);
+            k_centroids<<<face_grid(n, npairs), BLK, 0, q>>>(dsrc, dfoff, npairs, n, dpairs, fpair,
                                                                                  acc, astride, st, keys, vals);
             HD_LAUNCH_CHECK();
             radix_sort_u64(keys, vals, keys2, vals2, n, pair_bits ? 32 + pair_bits : 30, sc.sort_tmp, q);

@@ -537,13 +537,15 @@ __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__rest
                          const int64_t *__restrict__ voff, int npairs, int64_t n, int32_t *__restrict__ Fout,
                          double *__restrict__ Vout, int32_t *__restrict__ fpair, int32_t *__restrict__ ref,
                          const PairConst *__restrict__ pc, PairBox *pb, int astride, Ctl *ctl) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = f < n;
-    int p = pair_of(foff, npairs, valid ? f : n - 1);
+    // one face per thread with several pairs; with one, a grid-stride run of
+    // faces per thread (a capped grid: fewer blocks end in the atomics)
+    const int64_t f0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = f0 < n;
+    const int p = pair_of(foff, npairs, valid ? f0 : n - 1);
     double lo[3] = {__builtin_inf(), __builtin_inf(), __builtin_inf()};
     double hi[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
     double cm = 0;
-    if (valid) {
+    for (int64_t f = f0; f < n; f += (int64_t)gridDim.x * blockDim.x) {
         PairSrcA s = src[p];
         int64_t lf = f - foff[p];
         fpair[f] = p;
@@ -576,6 +578,8 @@ __global__ void k_ingest(const PairSrcA *__restrict__ src, const int64_t *__rest
         return k < 6 ? &b.bbox[k] : &b.coord_max;
     });
 }
+
+constexpr unsigned INGEST_ONE_PAIR_GRID = 1024;
 
 __device__ Margins make_margins(double u, double edge_max, double coord_max) {
     Margins m;
@@ -3009,7 +3013,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     PairBox *pbox = ws.pbox.as<PairBox>();
     k_bound_init<<<grid_for(std::max<int64_t>(mA, (int64_t)np * ACC_COPIES), BLK), BLK, 0, s>>>(
         ctl, pc, pv, pbox, pstride, B->pairs.as<BvhPair>(), np, ref, mA, logging ? 1 : 0, in.linked);
-    k_ingest<<<grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
+    k_ingest<<<np == 1 ? std::min(grid_for(nA, BLK), INGEST_ONE_PAIR_GRID) : grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
                                               ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pbox, pstride,
                                               ctl);
     scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
