@@ -680,12 +680,12 @@ template <class T> struct QueryIn {
     FrontierView<T> par;     // Q_MIDPOINTS / Q_LATTICE: selected parents
     const PairConst *pc;
     const int32_t *sel;      // Q_MIDPOINTS: record index of each parent (null: the first parents)
-    const int *two;          // Q_MIDPOINTS: with *two set, the round splits each parent two levels
-                             // deep and queries its 12 lattice points instead of its 3 midpoints
+    const int *two;          // Q_MIDPOINTS: the round's extra levels (Ctl::plan_two; null: none).
+                             // 2: each parent's 12 non-corner resolution-4 lattice points instead
+                             // of its 3 midpoints; 4: all 153 points of its resolution-16 lattice
 };
 
-// Q_MIDPOINTS in a two-level round: lattice point k (0..11) of the parent's
-// resolution-4 lattice, at the parent's level + 2
+// the extra subdivision levels of a Q_MIDPOINTS round (0, 2 or 4)
 HD_D int two_level(const int *two) { return two ? *two : 0; }
 
 // point t of the resolution-N lattice, rows of constant a2 in order (row r
@@ -1589,9 +1589,9 @@ template <class T> HD_D void copy_record(const FrontierView<T> &src, int64_t i, 
 // With sel and rest (device sub-batch selection) the parents and the carried
 // records are the ones those index lists name.
 //
-// A two-level round (ctl->plan_two, planned rounds only) gives every parent
-// its 16 grandchildren instead: the unit triangles of its resolution-4
-// lattice, (i,j) (i+1,j) (i,j+1) for i + j <= 3 and (i+1,j) (i+1,j+1)
+// A two-level round (ctl->plan_two == 2, planned rounds only) gives every
+// parent its 16 grandchildren instead (a four-level round, below, its 256
+// descendants): the unit triangles of its resolution-4 lattice, (i,j) (i+1,j) (i,j+1) for i + j <= 3 and (i+1,j) (i+1,j+1)
 // (i,j+1) for i + j <= 2, with (i,j) the weights of parent corners 1 and 2
 // over 4 (so each keeps the parent's orientation). TWO_CORNER[c] holds, four
 // bits per grandchild, where its corner c comes from: 0..11 the parent's
@@ -3013,9 +3013,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     PairBox *pbox = ws.pbox.as<PairBox>();
     k_bound_init<<<grid_for(std::max<int64_t>(mA, (int64_t)np * ACC_COPIES), BLK), BLK, 0, s>>>(
         ctl, pc, pv, pbox, pstride, B->pairs.as<BvhPair>(), np, ref, mA, logging ? 1 : 0, in.linked);
-    k_ingest<<<np == 1 ? std::min(grid_for(nA, BLK), INGEST_ONE_PAIR_GRID) : grid_for(nA, BLK), BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(),
-                                              ws.Vcat.as<double>(), ws.fpair.as<int32_t>(), ref, pc, pbox, pstride,
-                                              ctl);
+    const unsigned ingest_grid = np == 1 ? std::min(grid_for(nA, BLK), INGEST_ONE_PAIR_GRID) : grid_for(nA, BLK);
+    k_ingest<<<ingest_grid, BLK, 0, s>>>(dsrc, dfoff, dvoff, np, nA, ws.Fcat.as<int32_t>(), ws.Vcat.as<double>(),
+                                         ws.fpair.as<int32_t>(), ref, pc, pbox, pstride, ctl);
     scan_exclusive_i32(ref, refpos, mA, d_total, ws.scan_tmp, s);
     HD_LAUNCH_CHECK();
     // The count of referenced vertices stays on the device (round 0's
