@@ -2114,6 +2114,8 @@ struct SelCfg {
     int learned;             // the key: the network's prediction (1) or the upper bound (0)
     double budget;           // the paper's face budget (m * nA), less round 0
     int64_t subbatch;        // the sub-batch size
+    int64_t two_max, four_max; // a round that splits every live record (SEL_ALL) of at most this many
+                               // parents splits two (four) levels deep, as breadth-first rounds do
 };
 
 template <class T> HD_D uint32_t sel_key(const FrontierView<T> &f, int64_t j, int learned) {
@@ -2314,18 +2316,33 @@ __global__ __launch_bounds__(BLK) void k_sel_hist2(FrontierView<T> act, SelCfg s
         ctl->over_budget = 1;
     }
     if (mode == SEL_NONE) K = 0;
+    // a round that splits every live record is a breadth-first round: when it
+    // is small it goes two or four levels deep (plan_round). plan_kcap counts
+    // parents with room for 4 children each; 16 need 5x that room in the
+    // active list (15 more records per parent instead of 3) and 4x in the
+    // others, 256 need 85x
+    int dep = 0;
+    const unsigned long long kc = ctl->plan_kcap;
+    if (mode == SEL_ALL && K > 0 && K <= (unsigned long long)sc.two_max) {
+        if (K <= (unsigned long long)sc.four_max && 85 * K <= kc && ctl->lvl_bound + 4 <= 30 &&
+            ctl->processed + 256.0 * (double)K <= sc.budget)
+            dep = 4;
+        else if (5 * K <= kc && ctl->lvl_bound + 2 <= 30 && ctl->processed + 16.0 * (double)K <= sc.budget)
+            dep = 2;
+    }
     if (ctl->sel_mode == SEL_FROZEN) mode = SEL_FROZEN;
     ctl->sel_mode = mode;
     ctl->sel_thr = mode == SEL_THRESHOLD ? thr : (mode == SEL_ALL ? 0u : 0xffffffffu);
     ctl->plan_K = K;
-    ctl->plan_Q = 3 * K;
+    ctl->plan_Q = K * (dep == 4 ? (unsigned long long)LAT16_PTS : (dep == 2 ? 12ull : 3ull));
+    ctl->plan_two = dep;
     ctl->plan_rest = live - K;
     ctl->act_next = live - K; // the carried records lead the round's output list
-    ctl->processed += 4.0 * (double)K;
+    ctl->processed += (dep == 4 ? 256.0 : (dep == 2 ? 16.0 : 4.0)) * (double)K;
     ctl->subdivided += K;
     if (K > 0) {
         ctl->rounds += 1;
-        ctl->lvl_bound += 1;
+        ctl->lvl_bound += dep ? dep : 1;
     }
     ctl->sel_next = 0;
     ctl->rest_next = 0;
@@ -3209,7 +3226,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         c.grow_park = c.park < cap_limit;
         c.subbatch = sel_round ? opt.subbatch : 0;
         c.learned = sel_round && opt.learned > 0 ? 1 : 0;
-        c.two_max = sel_round || opt.split_levels == 1
+        // (sub-batched rounds: only a round that splits every live record,
+        // a breadth-first round, goes deeper; the selection decides)
+        c.two_max = opt.split_levels == 1
                         ? 0
                         : (opt.split_levels == 0 || opt.split_levels == 2 ? TWO_LEVEL_MAX : opt.split_levels);
         c.four_max = c.two_max > 0 && opt.split_levels != 2 ? FOUR_LEVEL_MAX : 0;
@@ -3347,7 +3366,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 const int64_t cap_act = tw.act.cap;
                 SelCfg sc{ws.selhist.as<unsigned>(), ws.selhist.as<unsigned>() + SEL_BINS,
                           ws.selidx.as<int32_t>(), ws.selidx.as<int32_t>() + std::max(tw.act.cap, tw.act2.cap),
-                          opt.learned > 0 ? 1 : 0, c.budget, (int64_t)opt.subbatch};
+                          opt.learned > 0 ? 1 : 0, c.budget, (int64_t)opt.subbatch, c.two_max, c.four_max};
                 const unsigned gs = std::max(1u, std::min<unsigned>(grid_for(cap_act, BLK), SEL_GRID_MAX));
                 if (opt.learned > 0)
                     k_score_new<T><<<std::min<unsigned>(grid_for(cap_act, BLK), GRID_MAX), BLK, 0, s>>>(
