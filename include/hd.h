@@ -123,7 +123,8 @@ typedef struct {
                                   last rounds, bound by kernel latency rather than work, take
                                   fewer launches; 1: every round splits one level (1 -> 4); 2: at
                                   most two levels; k >= 3: rounds of at most k triangles split two
-                                  levels (and of at most 64, four). Sub-batched and host-driven
+                                  levels (and of at most 64, four). A sub-batched round goes
+                                  deeper only when it splits every live record; host-driven
                                   rounds always split one level. Negative: HD_E_INVALID. */
     int32_t pad_opt;
 } hd_options;
