@@ -1600,11 +1600,17 @@ template <class T> HD_D void copy_record(const FrontierView<T> &src, int64_t i, 
 // breadth-first rounds, the one that does not match the plan returning at
 // once: in one kernel the two-level form's registers would cost the large
 // one-level rounds occupancy.)
+//
+// FUSE (one-level, FP32, orders without the fifth bound, no learned bound
+// policy): a child that stage A leaves undecided goes through stage B at once,
+// in registers, instead of being written to stage B's list and read back by
+// k_stage_b (which then finds that list empty for these rounds); compiled, as
+// k_stage_b is, for three waves per SIMD.
 constexpr uint64_t TWO_CORNER[3] = {0x567230567823401cull, 0x9ab673d9ab567230ull, 0x6783419abe678341ull};
-template <class T, int TWO>
-__global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T> par, QueryOut<T> mq,
-                                                  ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry,
-                                                  const int32_t *__restrict__ sel, const int32_t *__restrict__ rest) {
+template <class T, int TWO, int FUSE = 0>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(FUSE ? 3 : 1))) void k_children(
+    DevCount nselc, FrontierView<T> par, QueryOut<T> mq, ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry,
+    const int32_t *__restrict__ sel, const int32_t *__restrict__ rest, BView<T> bv) {
     if (carry && (ctl->plan_two != 0) != (TWO != 0)) return;
     const int64_t nsel = nselc.get();
     if (carry) {
@@ -1735,18 +1741,23 @@ __global__ __launch_bounds__(BLK) void k_children(DevCount nselc, FrontierView<T
         face = par.face()[j];
         lvl = par.lvl()[j] + 1;
     }
+    int evals = 0;
     if (valid) {
         // dyadic coordinates are int32 numerators over 2^lvl: level 30 is the
         // deepest representable one
         if (lvl > 30) ctl->bad = 3;
         int unsound = 0;
         list = stage_a<T>(cn, pair, cc, &carry, &decider, &unsound);
+        if (FUSE && list == TO_B)
+            // stage B on the stored (rounded up) stage-A bound, as k_stage_b would
+            list = stage_b<T>(cn, pair, cc, bv, (double)round_up_to_float(carry), decider, &carry, &decider, &evals,
+                              &unsound, -1);
         if (unsound) ctl->bad = 4;
     }
     int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
     if (valid)
         write_to(dst, list, slot, cn, round_up_to_float(carry), face, lvl_field(list, lvl, decider), pair);
-    tally(ctl, list, decider, 0, 0, valid, true);
+    tally(ctl, list, decider, evals, 0, valid, true);
     }
 }
 
@@ -1798,6 +1809,9 @@ constexpr int64_t LOOKAHEAD_MIN = 64;
 // device-planned breadth-first rounds of at most this many parents split each
 // of them two levels deep (hd_options.split_levels)
 constexpr int64_t TWO_LEVEL_MAX = 8192;
+
+// one-level planned FP32 rounds run stage B in the children kernel (k_children FUSE)
+constexpr bool FUSE_STAGE_B = true;
 
 // stage C's records [0, n) in a grid-stride loop (every thread of the block)
 template <class T>
@@ -3186,6 +3200,9 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cc.shift = opt.test_bound_shift;
     bool has_u5 = false; // the order has the fifth bound (barycenter queries before stage B)
     for (int i = 0; i < cctx.norder; ++i) has_u5 = has_u5 || cctx.order[i] == 5;
+    // one-level planned rounds run stage B inside the children kernel (FP32,
+    // no barycenter queries, no learned bound policy)
+    const bool fuse_b = sizeof(T) == 4 && !has_u5 && opt.learned != 2 && FUSE_STAGE_B;
     cc.a = av;
     cc.bv64 = bv64;
     cc.iv = iv;
@@ -3391,14 +3408,24 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
             // 3 * kmax: two-level rounds need room for 16 children per parent)
             run_queries(qi, DevCount{&ctl->plan_Q, 1, 0}, 3 * kmax, tw.mq.o);
             prof.mark(prof.c);
-            k_children<T, 0><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
-                DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
-                Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp, restp);
+            bool fused = false;
+            if constexpr (sizeof(T) == 4) {
+                if (fuse_b) {
+                    k_children<T, 0, 1><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
+                        DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
+                        Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp, restp, bv);
+                    fused = true;
+                }
+            }
+            if (!fused)
+                k_children<T, 0><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
+                    DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
+                    Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp, restp, bv);
             if (c.two_max > 0)
                 k_children<T, 1><<<std::min<unsigned>(grid_for(16 * std::min(kmax, c.two_max), BLK), GRID_MAX), BLK,
                                    0, s>>>(DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp,
-                                           restp);
+                                           restp, bv);
             HD_LAUNCH_CHECK();
             const unsigned seq = ++ws.mb_seq;
             later_stages(4 * kmax, tw.act2.v, 1, seq);
@@ -3603,7 +3630,7 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         k_children<T, 0><<<std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX), BLK, 0, s>>>(host_count(K), tw.act.v,
                                                                                           tw.mq.o, cc,
                                                            Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
-                                                           ctl, 0, nullptr, nullptr);
+                                                           ctl, 0, nullptr, nullptr, bv);
         HD_LAUNCH_CHECK();
         later_stages(4 * K, tw.act2.v, 0, 0);
         prof.mark(prof.c);
