@@ -1549,13 +1549,14 @@ template <class T> HD_D void load_corners(const FrontierView<T> &f, int64_t j, C
 }
 
 // round 0: every face of A from the per-vertex query results (stage A)
-template <class T>
-__global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__restrict__ F,
-                                                const int32_t *__restrict__ fpair, QueryOut<T> vq, ClassifyCfg cc,
-                                                Dest<T> dst, Ctl *ctl) {
+// (FUSE: as in k_children, stage B for an undecided triangle at once)
+template <class T, int FUSE = 0>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(FUSE ? 3 : 1))) void k_round0(
+    int64_t nA, const int32_t *__restrict__ F, const int32_t *__restrict__ fpair, QueryOut<T> vq, ClassifyCfg cc,
+    Dest<T> dst, Ctl *ctl, BView<T> bv) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = f < nA;
-    int list = TO_DISCARD, decider = 0, pair = 0;
+    int list = TO_DISCARD, decider = 0, pair = 0, evals = 0;
     double carry = 0;
     Corner<T> cn[3];
     if (valid) {
@@ -1571,12 +1572,15 @@ __global__ __launch_bounds__(BLK) void k_round0(int64_t nA, const int32_t *__res
         }
         int unsound = 0;
         list = stage_a<T>(cn, pair, cc, &carry, &decider, &unsound);
+        if (FUSE && list == TO_B)
+            list = stage_b<T>(cn, pair, cc, bv, (double)round_up_to_float(carry), decider, &carry, &decider, &evals,
+                              &unsound, -1);
         if (unsound) ctl->bad = 4;
     }
     int64_t slot = append_slot(valid ? list : TO_DISCARD, ctl);
     if (valid)
         write_to(dst, list, slot, cn, round_up_to_float(carry), (int)f, lvl_field(list, 0, decider), pair);
-    tally(ctl, list, decider, 0, 0, valid, true);
+    tally(ctl, list, decider, evals, 0, valid, true);
 }
 
 template <class T> HD_D void copy_record(const FrontierView<T> &src, int64_t i, const FrontierView<T> &dst, int64_t o);
@@ -1810,7 +1814,8 @@ constexpr int64_t LOOKAHEAD_MIN = 64;
 // of them two levels deep (hd_options.split_levels)
 constexpr int64_t TWO_LEVEL_MAX = 8192;
 
-// one-level planned FP32 rounds run stage B in the children kernel (k_children FUSE)
+// FP32 runs take stage B inside the kernel that bounds the new triangles
+// (k_round0 and the one-level k_children, FUSE)
 constexpr bool FUSE_STAGE_B = true;
 
 // stage C's records [0, n) in a grid-stride loop (every thread of the block)
@@ -3200,8 +3205,8 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
     cc.shift = opt.test_bound_shift;
     bool has_u5 = false; // the order has the fifth bound (barycenter queries before stage B)
     for (int i = 0; i < cctx.norder; ++i) has_u5 = has_u5 || cctx.order[i] == 5;
-    // one-level planned rounds run stage B inside the children kernel (FP32,
-    // no barycenter queries, no learned bound policy)
+    // stage B inside the vertex round's and the one-level planned rounds'
+    // kernels (FP32, no barycenter queries, no learned bound policy)
     const bool fuse_b = sizeof(T) == 4 && !has_u5 && opt.learned != 2 && FUSE_STAGE_B;
     cc.a = av;
     cc.bv64 = bv64;
@@ -3354,8 +3359,20 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         HD_LAUNCH_CHECK();
     }
     prof.mark(prof.c);
-    k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o, cc,
-                                                  Dest<T>{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl);
+    {
+        const Dest<T> d0{tw.act.v, tw.park.v, tw.pend_b.v, tw.pend_c.v};
+        bool fused = false;
+        if constexpr (sizeof(T) == 4) {
+            if (fuse_b) {
+                k_round0<T, 1><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(),
+                                                                 tw.vq.o, cc, d0, ctl, bv);
+                fused = true;
+            }
+        }
+        if (!fused)
+            k_round0<T><<<grid_for(nA, BLK), BLK, 0, s>>>(nA, ws.Fcat.as<int32_t>(), ws.fpair.as<int32_t>(), tw.vq.o,
+                                                          cc, d0, ctl, bv);
+    }
     HD_LAUNCH_CHECK();
     later_stages(nA, tw.act.v, planned ? 1 : 0, seq0);
     prof.mark(prof.c);
