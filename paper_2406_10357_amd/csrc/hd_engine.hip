@@ -1605,14 +1605,14 @@ template <class T> HD_D void copy_record(const FrontierView<T> &src, int64_t i, 
 // once: in one kernel the two-level form's registers would cost the large
 // one-level rounds occupancy.)
 //
-// FUSE (one-level, FP32, orders without the fifth bound, no learned bound
-// policy): a child that stage A leaves undecided goes through stage B at once,
-// in registers, instead of being written to stage B's list and read back by
-// k_stage_b (which then finds that list empty for these rounds); compiled, as
-// k_stage_b is, for three waves per SIMD.
+// FUSE (FP32, orders without the fifth bound, no learned bound policy): a
+// child that stage A leaves undecided goes through stage B at once, in
+// registers, instead of being written to stage B's list and read back by
+// k_stage_b (which then finds that list empty); the one-level form is
+// compiled, as k_stage_b is, for three waves per SIMD.
 constexpr uint64_t TWO_CORNER[3] = {0x567230567823401cull, 0x9ab673d9ab567230ull, 0x6783419abe678341ull};
 template <class T, int TWO, int FUSE = 0>
-__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(FUSE ? 3 : 1))) void k_children(
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(FUSE && !TWO ? 3 : 1))) void k_children(
     DevCount nselc, FrontierView<T> par, QueryOut<T> mq, ClassifyCfg cc, Dest<T> dst, Ctl *ctl, int carry,
     const int32_t *__restrict__ sel, const int32_t *__restrict__ rest, BView<T> bv) {
     if (carry && (ctl->plan_two != 0) != (TWO != 0)) return;
@@ -3438,11 +3438,21 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                 k_children<T, 0><<<std::min<unsigned>(grid_for(4 * kmax, BLK), GRID_MAX), BLK, 0, s>>>(
                     DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
                     Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp, restp, bv);
-            if (c.two_max > 0)
-                k_children<T, 1><<<std::min<unsigned>(grid_for(16 * std::min(kmax, c.two_max), BLK), GRID_MAX), BLK,
-                                   0, s>>>(DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
-                                           Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v}, ctl, 1, selp,
-                                           restp, bv);
+            if (c.two_max > 0) {
+                const unsigned g2 = std::min<unsigned>(grid_for(16 * std::min(kmax, c.two_max), BLK), GRID_MAX);
+                const Dest<T> d2{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v};
+                bool fused2 = false;
+                if constexpr (sizeof(T) == 4) {
+                    if (fused) {
+                        k_children<T, 1, 1><<<g2, BLK, 0, s>>>(DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc,
+                                                               d2, ctl, 1, selp, restp, bv);
+                        fused2 = true;
+                    }
+                }
+                if (!fused2)
+                    k_children<T, 1><<<g2, BLK, 0, s>>>(DevCount{&ctl->plan_K, 1, 0}, tw.act.v, tw.mq.o, cc, d2, ctl,
+                                                        1, selp, restp, bv);
+            }
             HD_LAUNCH_CHECK();
             const unsigned seq = ++ws.mb_seq;
             later_stages(4 * kmax, tw.act2.v, 1, seq);
