@@ -3279,9 +3279,11 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
                             ws.ovf.as<int32_t>(), ws.deep.as<int2>(), s);
             Sb = tw.bq.o.I;
         }
+        // (with stage B in the kernels that create the triangles, nothing
+        // is left for it: every such kernel of this run is the FUSE form)
         if (opt.learned == 2)
             k_stage_b_learned<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, lc, opt.mlp_params, Sb);
-        else
+        else if (!(fuse_b && sizeof(T) == 4))
             k_stage_b<T><<<g, BLK, 0, s>>>(tw.pend_b.v, cc, bv, d, ctl, Sb);
         // (stage C's records are the few within the FP32 margin of a
         // decision: a grid of one block per CU, striding, suffices)
@@ -3654,10 +3656,21 @@ hd_status run(const Input &in, const Bvh *B, const hd_options &opt, hipStream_t 
         tw.pend_b.ensure(4 * K, 0, s);
         if (cc.recheck) tw.pend_c.ensure(4 * K, 0, s);
         prof.mark(prof.c);
-        k_children<T, 0><<<std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX), BLK, 0, s>>>(host_count(K), tw.act.v,
-                                                                                          tw.mq.o, cc,
-                                                           Dest<T>{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v},
-                                                           ctl, 0, nullptr, nullptr, bv);
+        {
+            const unsigned gk = std::min<unsigned>(grid_for(4 * K, BLK), GRID_MAX);
+            const Dest<T> dk{tw.act2.v, tw.park.v, tw.pend_b.v, tw.pend_c.v};
+            bool fusedk = false;
+            if constexpr (sizeof(T) == 4) {
+                if (fuse_b) {
+                    k_children<T, 0, 1><<<gk, BLK, 0, s>>>(host_count(K), tw.act.v, tw.mq.o, cc, dk, ctl, 0, nullptr,
+                                                           nullptr, bv);
+                    fusedk = true;
+                }
+            }
+            if (!fusedk)
+                k_children<T, 0><<<gk, BLK, 0, s>>>(host_count(K), tw.act.v, tw.mq.o, cc, dk, ctl, 0, nullptr, nullptr,
+                                                    bv);
+        }
         HD_LAUNCH_CHECK();
         later_stages(4 * K, tw.act2.v, 0, 0);
         prof.mark(prof.c);
