@@ -71,3 +71,25 @@ def test_binding_structs_match_the_header(tmp_path):
         py = structs[cname]
         want = C.sizeof(py) if field == "size" else getattr(py, field).offset
         assert int(val) == want, (cname, field, int(val), want)
+
+
+def test_default_options_and_binding_defaults_agree():
+    """hd_default_options sets the documented defaults (FP32 with the FP64
+    recheck, cascade order 1234, a budget of 1e7, every other field zero),
+    and make_options() with no arguments reproduces them field by field."""
+    import ctypes as C
+    import paper_2406_10357_amd as hd
+    lib = hd.load_library()
+    o = hd.Options()
+    C.memset(C.byref(o), 0xAB, C.sizeof(o))  # garbage first: every field must be set
+    lib.hd_default_options(C.byref(o))
+    want = {"precision": hd.PREC_FP32_RECHECK, "order": 1234, "budget_m": 1e7}
+    for f, _ in hd.Options._fields_:
+        v = getattr(o, f)
+        if f in want:
+            assert v == want[f], (f, v)
+        else:
+            assert not v, (f, v)
+    m = hd.make_options()
+    for f, _ in hd.Options._fields_:
+        assert getattr(m, f) == getattr(o, f), f
